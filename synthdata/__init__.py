@@ -1,0 +1,203 @@
+"""Seeded synthetic inputs for the TaCo query stage.
+
+This module only draws random inputs: base vectors, queries, per-query
+budgets and the k-means seeding choices that the index build consumes. It
+holds none of the method's arithmetic, so both the CPU oracle and the GPU
+path can take their inputs from here without sharing any computation.
+
+Every workload is a named, seeded recipe. The five recipes stand in for the
+paper's evaluation datasets (Section 5.1: DEEP1M 256-d, GIST1M 960-d,
+SIFT10M 128-d, Yandex DEEP10M 96-d), whose records are not used: only their
+scales and dimensionalities are imitated.
+
+Random streams come from numpy's PCG64 seeded through SeedSequence; big
+arrays are drawn in fixed chunks of ``CHUNK`` rows, each chunk from its own
+spawned stream, so a recipe is reproducible bit for bit whatever the memory
+available.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+CHUNK = 1 << 18
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    """One synthetic workload: data recipe plus the index/query parameters.
+
+    ``n, d`` base size; ``Ns`` subspaces of ``s`` dims each (``Ns*s <= d``);
+    ``l`` centroids per half-subspace (so ``K = l*l`` cells per subspace);
+    ``nq`` queries; ``k`` results; ``alphas`` the collision ratios swept;
+    ``beta`` the re-rank ratio; ``iters`` k-means iterations; ``n_train``
+    the k-means training sample size (``None`` = all points).
+    """
+
+    name: str
+    recipe: str
+    n: int
+    d: int
+    Ns: int
+    s: int
+    l: int
+    nq: int
+    k: int
+    alphas: Tuple[float, ...]
+    beta: float
+    seed: int
+    iters: int = 20
+    n_train: Optional[int] = None
+
+    @property
+    def M(self) -> int:
+        return self.Ns * self.s
+
+    def scaled(self, name: str, n: int, nq: int, **kw) -> "Workload":
+        """Same recipe and index shape at another size (parity-test sizes)."""
+        return dataclasses.replace(self, name=name, n=n, nq=nq, **kw)
+
+
+# The five workloads. Sizes, dimensionalities, mixtures and index shapes are
+# those of the benchmark definition; where it leaves a value open the
+# proposed reading is recorded in the recipe's docstring below.
+WORKLOADS: Dict[str, Workload] = {
+    "tiny-gmm-20k-d128": Workload(
+        name="tiny-gmm-20k-d128", recipe="gmm_iso", n=20_000, d=128, Ns=8, s=16,
+        l=16, nq=100, k=10, alphas=(0.05,), beta=0.005, seed=0x7AC0_0001),
+    "gmm-int-1m-d128": Workload(
+        name="gmm-int-1m-d128", recipe="gmm_int", n=1_000_000, d=128, Ns=8, s=16,
+        l=50, nq=10_000, k=10, alphas=(0.01, 0.03, 0.05), beta=0.005,
+        seed=0x7AC0_0002),
+    "aniso-1m-d960": Workload(
+        name="aniso-1m-d960", recipe="aniso", n=1_000_000, d=960, Ns=16, s=60,
+        l=32, nq=1_000, k=10, alphas=(0.01, 0.03, 0.05), beta=0.005,
+        seed=0x7AC0_0003),
+    "sphere-10m-d96": Workload(
+        name="sphere-10m-d96", recipe="sphere", n=10_000_000, d=96, Ns=8, s=12,
+        l=64, nq=10_000, k=10, alphas=(0.01, 0.03, 0.05), beta=0.005,
+        seed=0x7AC0_0004, n_train=1_000_000),
+    "zipf-1m-d256": Workload(
+        name="zipf-1m-d256", recipe="zipf", n=1_000_000, d=256, Ns=16, s=16,
+        l=40, nq=100_000, k=10, alphas=(0.005, 0.10), beta=0.005,
+        seed=0x7AC0_0005),
+}
+
+
+def _streams(seed: int, n: int):
+    return [np.random.Generator(np.random.PCG64(s))
+            for s in np.random.SeedSequence(seed).spawn(n)]
+
+
+def _mixture_params(rng, recipe: str, d: int):
+    """Component parameters of a recipe (drawn once from the parameter stream)."""
+    if recipe == "gmm_iso":
+        # 64 equal-weight isotropic components, means U[0,100]^d, sigma 10.
+        c = 64
+        return dict(means=rng.uniform(0.0, 100.0, (c, d)),
+                    sigma=np.full(c, 10.0), weights=np.full(c, 1.0 / c))
+    if recipe == "gmm_int":
+        # 1024 equal-weight components, means U[0,255]^d (proposed),
+        # per-component sigma U[5,25]; values rounded and clipped to [0,255].
+        c = 1024
+        return dict(means=rng.uniform(0.0, 255.0, (c, d)),
+                    sigma=rng.uniform(5.0, 25.0, c), weights=np.full(c, 1.0 / c))
+    if recipe == "aniso":
+        # One Gaussian with covariance Q diag(i^-1.2) Q^T, Q Haar-random
+        # (QR of a Gaussian matrix, columns sign-fixed by diag(R)); offset
+        # 4*sigma_t per coordinate (proposed), clipped at 0.
+        g = rng.standard_normal((d, d))
+        q, r = np.linalg.qr(g)
+        q = q * np.sign(np.diag(r))[None, :]
+        lam = np.arange(1, d + 1, dtype=np.float64) ** -1.2
+        sig_t = np.sqrt((q * q) @ lam)
+        return dict(rot=q, sqrt_lam=np.sqrt(lam), offset=4.0 * sig_t)
+    if recipe == "sphere":
+        # 4096 unit mean directions; a point is normalize(mu + sigma*g) with
+        # sigma = tan(0.3)/sqrt(d-1), i.e. about 0.3 rad angular spread.
+        c = 4096
+        mu = rng.standard_normal((c, d))
+        mu /= np.linalg.norm(mu, axis=1, keepdims=True)
+        return dict(means=mu, sigma=np.full(c, math.tan(0.3) / math.sqrt(d - 1)),
+                    weights=np.full(c, 1.0 / c))
+    if recipe == "zipf":
+        # 2048 components with Zipf(1.1) weights, means U[0,100]^d and
+        # sigma U[5,25] (proposed).
+        c = 2048
+        w = np.arange(1, c + 1, dtype=np.float64) ** -1.1
+        return dict(means=rng.uniform(0.0, 100.0, (c, d)),
+                    sigma=rng.uniform(5.0, 25.0, c), weights=w / w.sum())
+    raise ValueError(f"unknown recipe {recipe!r}")
+
+
+def _draw_rows(rng, recipe: str, p, m: int, d: int) -> np.ndarray:
+    if recipe == "aniso":
+        z = rng.standard_normal((m, d)) * p["sqrt_lam"][None, :]
+        x = z @ p["rot"].T + p["offset"][None, :]
+        return np.maximum(x, 0.0).astype(np.float32)
+    comp = rng.choice(len(p["weights"]), size=m, p=p["weights"])
+    x = p["means"][comp] + rng.standard_normal((m, d)) * p["sigma"][comp][:, None]
+    if recipe == "gmm_iso" or recipe == "zipf":
+        x = np.maximum(x, 0.0)
+    elif recipe == "gmm_int":
+        x = np.clip(np.rint(x), 0.0, 255.0)
+    elif recipe == "sphere":
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+    return x.astype(np.float32)
+
+
+def _draw(seed: int, recipe: str, p, m: int, d: int) -> np.ndarray:
+    out = np.empty((m, d), dtype=np.float32)
+    nchunk = (m + CHUNK - 1) // CHUNK
+    for ci, rng in enumerate(_streams(seed, max(nchunk, 1))):
+        lo, hi = ci * CHUNK, min(m, (ci + 1) * CHUNK)
+        if lo < hi:
+            out[lo:hi] = _draw_rows(rng, recipe, p, hi - lo, d)
+    return out
+
+
+def base_and_queries(w: Workload, nq: Optional[int] = None):
+    """Base ``(n, d)`` and query ``(nq, d)`` float32 arrays of a workload.
+
+    Queries are fresh draws from the same distribution, not members of the
+    base (the paper removes its queries from the base set).
+    """
+    nq = w.nq if nq is None else nq
+    s_par, s_base, s_q = np.random.SeedSequence(w.seed).spawn(3)
+    p = _mixture_params(np.random.Generator(np.random.PCG64(s_par)), w.recipe, w.d)
+    base = _draw(int(s_base.generate_state(1, np.uint64)[0]), w.recipe, p, w.n, w.d)
+    qs = _draw(int(s_q.generate_state(1, np.uint64)[0]), w.recipe, p, nq, w.d)
+    return base, qs
+
+
+def kmeans_seeding(w: Workload):
+    """Random choices the index build draws, passed to it as inputs.
+
+    Returns ``(train_idx, init)``: ``train_idx`` the sorted k-means training
+    sample (``None`` = every point), and ``init`` of shape ``(Ns, 2, l)``,
+    Forgy seeds as positions into the training sample, ``l`` distinct ones
+    per half-subspace.
+    """
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(w.seed ^ 0x5EED).spawn(1)[0]))
+    n_train = w.n if w.n_train is None or w.n_train >= w.n else w.n_train
+    train_idx = None
+    if n_train < w.n:
+        train_idx = np.sort(rng.choice(w.n, size=n_train, replace=False)).astype(np.int64)
+    init = np.empty((w.Ns, 2, w.l), dtype=np.int64)
+    for j in range(w.Ns):
+        for h in range(2):
+            init[j, h] = rng.choice(n_train, size=w.l, replace=False)
+    return train_idx, init
+
+
+def query_budgets(nq: int, seed: int, lo: float = 0.005, hi: float = 0.10,
+                  ks=(1, 10, 100)):
+    """Per-query collision ratios, log-uniform in ``[lo, hi]``, and per-query
+    ``k`` drawn uniformly from ``ks`` (query-aware budgets)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed ^ 0xA1FA).spawn(1)[0]))
+    alpha = np.exp(rng.uniform(math.log(lo), math.log(hi), nq))
+    k = rng.choice(np.asarray(ks, dtype=np.int32), size=nq)
+    return alpha.astype(np.float64), k.astype(np.int32)
