@@ -1,0 +1,171 @@
+/*
+ * taco.h -- C-ABI of the MI355X (gfx950) query stage of TaCo, the
+ * data-adaptive, query-aware subspace-collision method for approximate
+ * k-nearest-neighbour search.
+ *
+ * The library answers k-ANNS queries (Alg 6, Section 4.4) against an index
+ * built offline by Alg 1-3 (Sections 3.2 and 4.1) and serialized to a file.
+ * For each query it transforms the query, computes the distances of each
+ * subspace's two halves to their centroids, probes inverted-multi-index cells
+ * in ascending distance until the collision budget is met (Alg 4, Section
+ * 4.2), counts one collision per point per probed cell, selects candidates
+ * from the histogram of those counts (Alg 5, Section 4.3), re-ranks them by
+ * exact squared L2 distance and returns the k nearest.  Every step runs in
+ * hand-written HIP kernels on one GPU.
+ *
+ * Conventions shared by every entry point:
+ *  - Status: every int-returning call returns TC_OK (0) or a negative
+ *    tc_status; tc_last_error() then describes the failure (thread-local).
+ *    Arguments are validated on the host before anything is enqueued; a
+ *    failing call enqueues nothing.
+ *  - Pointers documented "device" must be device memory of the index's GPU
+ *    (e.g. from hipMalloc or a torch CUDA tensor); "host" pointers are
+ *    ordinary host memory.  The caller owns every pointer it passes; the
+ *    index owns its own device copies and scratch until tc_free_index.
+ *  - Stream ordering: search calls enqueue work on `stream` (a hipStream_t;
+ *    NULL is the default stream) and return without waiting; the caller
+ *    synchronizes before reading outputs.  Calls on one index must not
+ *    overlap (one host thread and one stream at a time per index): they
+ *    share the index's scratch.
+ *  - Distances are squared L2 distances in FP32.
+ */
+#ifndef TACO_H
+#define TACO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tc_index tc_index; /* opaque; owned by the library */
+
+enum tc_status {
+    TC_OK = 0,
+    TC_EINVAL = -1,  /* invalid argument (nothing enqueued)                  */
+    TC_EIO = -2,     /* index file cannot be opened or read                   */
+    TC_EFORMAT = -3, /* bad magic/version/shape, checksum or index contents   */
+    TC_ENOMEM = -4,  /* device or host allocation failed                      */
+    TC_EDEVICE = -5  /* HIP runtime error                                     */
+};
+
+/* Readings of Alg 5's stopping test (Section 4.3).  Scanning SC levels from
+ * Ns down with a running total `cum` that includes the current level's count
+ * c_j, a level "passes" and lowers last_collision by one when
+ *   TC_RULE_PRINTED: c_j <= beta*n - cum   (as the algorithm prints it), or
+ *   TC_RULE_PROSE:   cum <= beta*n         (as the text describes it);
+ * the first failing level ends the scan.  Candidates are the points whose
+ * SC-score is >= last_collision (every point when it drops to -1). */
+enum tc_select_rule { TC_RULE_PRINTED = 0, TC_RULE_PROSE = 1 };
+
+/* Options for tc_set_option. */
+enum tc_option {
+    TC_OPT_SELECT_RULE = 1, /* tc_select_rule; default TC_RULE_PRINTED                 */
+    TC_OPT_MAX_BATCH = 2,   /* max queries per internal batch (>= 1); scratch is
+                               re-sized to fit; default: what 16 GiB of candidate
+                               scratch allows, at most 4096                          */
+    TC_OPT_TILE_IDS = 3,    /* ids per LDS counting tile, a multiple of 1024 that
+                               fits the GPU's LDS per workgroup; default 65536       */
+    TC_OPT_PROFILE = 4,     /* 1: time every kernel launch with HIP events on the
+                               search stream (read with tc_kernel_time); 0: off      */
+    TC_OPT_SCRATCH_BYTES = 5 /* candidate-scratch budget in bytes used to pick the
+                               batch size (>= 8*n); default 16 GiB                   */
+};
+
+/*
+ * Load an index file onto GPU `device` and build its derived device tables.
+ *   path   host, NUL-terminated file name of an index written by the index
+ *          builder (layout: 128-byte header "TACOIDX1" v1 with n, d, Ns, s,
+ *          h1=s/2, h2=s-h1, l; mean f32[d]; B f32[d][Ns*s]; half centroids
+ *          C1 f32[Ns][l][h1], C2 f32[Ns][l][h2]; cell offsets u64[Ns][l*l+1]
+ *          for cell a*l+b; point ids u32[Ns][n] ascending inside each cell;
+ *          base vectors f32[n][d]; FNV-1a-64 checksum of all preceding bytes).
+ *          This is the output of Alg 3 (centroid list and one IMI per
+ *          subspace) plus Alg 1's mean and eigenvector buckets.
+ *   device HIP device ordinal.
+ *   out    host; receives the new index (NULL on failure).
+ * Returns TC_EIO (unreadable), TC_EFORMAT (bad header, checksum, offsets not
+ * partitioning [0,n), ids out of range or not ascending in a cell, Ns > 16,
+ * l > 64, n >= 2^31), TC_ENOMEM or TC_EDEVICE.  Synchronous.
+ */
+int tc_load_index(const char *path, int device, tc_index **out);
+
+/* Release the index and all its device memory.  NULL is a no-op.  The caller
+ * must have synchronized any stream still using it. */
+void tc_free_index(tc_index *index);
+
+/* Shape of a loaded index; any output pointer (host) may be NULL. */
+int tc_index_info(const tc_index *index, int64_t *n, int32_t *d, int32_t *Ns, int32_t *s,
+                  int32_t *l);
+
+/* Set an option (enum tc_option).  Synchronizes the index's device before
+ * re-sizing scratch.  TC_EINVAL for an unknown option or bad value. */
+int tc_set_option(tc_index *index, int option, int64_t value);
+
+/*
+ * k-ANNS for a batch of queries (Alg 6, Section 4.4).
+ *   queries  device, f32 [nq][d] row-major.
+ *   nq       number of queries (0: no-op, TC_OK).
+ *   k        results per query, 1 <= k <= min(n, 1024).
+ *   alpha    collision ratio, 0 < alpha <= 1: each subspace probes cells until
+ *            at least A = ceil(alpha*n) points are retrieved (IEEE double,
+ *            A clamped to [1, n]).
+ *   beta     re-rank ratio, 0 <= beta <= 1: Alg 5's budget R = floor(beta*n).
+ *   ids      device, i64 [nq][k]: base row indices ascending by (distance,
+ *            id); -1 where fewer than k candidates exist.
+ *   dists    device, f32 [nq][k]: their squared L2 distances in the original
+ *            d-dim space; +inf in padded slots.
+ *   stream   hipStream_t to enqueue on (NULL: default stream).
+ */
+int tc_search(tc_index *index, const float *queries, int64_t nq, int32_t k, double alpha,
+              double beta, int64_t *ids, float *dists, void *stream);
+
+/*
+ * Per-stage outputs of tc_search, for parity checks.  Every member is a
+ * device pointer sized for the call's nq and may be NULL (stage not dumped).
+ * K = l*l.
+ */
+typedef struct tc_stage_dump {
+    float *qt;          /* [nq][Ns*s]       transformed queries                      */
+    float *cdist;       /* [nq][Ns][2][l]   half-centroid squared distances          */
+    int32_t *corder;    /* [nq][Ns][2][l]   ascending order of each half's centroids */
+    int32_t *cells;     /* [nq][Ns][K]      probed cells in retrieval order          */
+    int32_t *ncells;    /* [nq][Ns]         number of probed cells                   */
+    int64_t *retrieved; /* [nq][Ns]         points in the probed cells               */
+    uint8_t *sc;        /* [nq][n]          SC-scores (collision counts)             */
+    int64_t *hist;      /* [nq][Ns+1]       number of points per SC level            */
+    int32_t *last;      /* [nq]             last_collision threshold                 */
+    int64_t *ncand;     /* [nq]             number of candidates |C|                 */
+    int32_t *cand;      /* [nq][n]          candidate ids (first ncand, any order)   */
+    float *cand_dist;   /* [nq][n]          their distances, aligned with cand       */
+} tc_stage_dump;
+
+/* tc_search that also writes the stages requested in `dump` (host pointer to
+ * the struct; NULL behaves as tc_search).  Same kernels and launch shapes. */
+int tc_search_debug(tc_index *index, const float *queries, int64_t nq, int32_t k, double alpha,
+                    double beta, int64_t *ids, float *dists, void *stream,
+                    const tc_stage_dump *dump);
+
+/*
+ * Kernel timing, recorded while TC_OPT_PROFILE is 1.  Waits for the recorded
+ * events, then reports for `kernel` -- one of "transform", "probe", "count",
+ * "select", "rerank", "topk" -- the summed duration in milliseconds and the
+ * number of launches since the last tc_profile_reset.  Host outputs.
+ */
+int tc_kernel_time(tc_index *index, const char *kernel, double *total_ms, int64_t *launches);
+
+/* Forget recorded kernel timings. */
+int tc_profile_reset(tc_index *index);
+
+/* Queries processed per internal batch with the current options (host out). */
+int tc_batch_capacity(const tc_index *index, int64_t *queries_per_batch);
+
+/* Message for the calling thread's last failed call ("" if none). */
+const char *tc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TACO_H */

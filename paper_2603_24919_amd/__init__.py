@@ -1,0 +1,250 @@
+"""Python binding of ``libtaco_hip.so``, the gfx950 query stage of TaCo.
+
+Argument marshalling only: every step of a search runs in the library's HIP
+kernels.  Functions carry the C-ABI's names (``include/taco.h``); tensors
+are torch CUDA tensors used as device memory, and the default stream is
+torch's current stream on the index's device.  Importing the package does
+not touch the GPU; the first call loads the library and raises
+``TacoLibraryMissing`` if it has not been built (there is no fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Tuple
+
+__all__ = [
+    "TC_OK", "TC_EINVAL", "TC_EIO", "TC_EFORMAT", "TC_ENOMEM", "TC_EDEVICE",
+    "TC_RULE_PRINTED", "TC_RULE_PROSE", "TC_OPT_SELECT_RULE", "TC_OPT_MAX_BATCH",
+    "TC_OPT_TILE_IDS", "TC_OPT_PROFILE", "TC_OPT_SCRATCH_BYTES", "KERNELS",
+    "TacoError", "TacoLibraryMissing", "lib_path", "load_library",
+    "tc_load_index", "tc_free_index", "tc_index_info", "tc_set_option", "tc_search",
+    "tc_search_debug", "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity",
+    "tc_last_error", "Index", "DUMP_FIELDS",
+]
+
+TC_OK, TC_EINVAL, TC_EIO, TC_EFORMAT, TC_ENOMEM, TC_EDEVICE = 0, -1, -2, -3, -4, -5
+TC_RULE_PRINTED, TC_RULE_PROSE = 0, 1
+TC_OPT_SELECT_RULE, TC_OPT_MAX_BATCH, TC_OPT_TILE_IDS, TC_OPT_PROFILE, TC_OPT_SCRATCH_BYTES = 1, 2, 3, 4, 5
+KERNELS = ("transform", "probe", "count", "select", "rerank", "topk")
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libtaco_hip.so"
+
+
+class TacoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"taco error {code}: {msg}")
+        self.code = code
+
+
+class TacoLibraryMissing(ImportError):
+    pass
+
+
+class _StageDump(C.Structure):
+    _fields_ = [(f, C.c_void_p) for f in (
+        "qt", "cdist", "corder", "cells", "ncells", "retrieved", "sc", "hist", "last",
+        "ncand", "cand", "cand_dist")]
+
+
+DUMP_FIELDS = tuple(f for f, _ in _StageDump._fields_)
+
+_lib = None
+
+
+def lib_path() -> str:
+    return os.path.join(_HERE, _LIB_NAME)
+
+
+def load_library():
+    """Load the built library (once).  No fallback: a missing library is an
+    error, whether or not a GPU is present."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise TacoLibraryMissing(
+            f"{path} is not built; run paper_2603_24919_amd/build.py (or __graft_entry__.build())")
+    L = C.CDLL(path)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    L.tc_load_index.argtypes = [C.c_char_p, C.c_int, C.POINTER(vp)]
+    L.tc_free_index.argtypes = [vp]
+    L.tc_free_index.restype = None
+    L.tc_index_info.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32),
+                                C.POINTER(i32), C.POINTER(i32)]
+    L.tc_set_option.argtypes = [vp, C.c_int, i64]
+    L.tc_search.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, vp]
+    L.tc_search_debug.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, vp, C.POINTER(_StageDump)]
+    L.tc_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
+    L.tc_profile_reset.argtypes = [vp]
+    L.tc_batch_capacity.argtypes = [vp, C.POINTER(i64)]
+    L.tc_last_error.restype = C.c_char_p
+    L.tc_last_error.argtypes = []
+    for f in ("tc_load_index", "tc_index_info", "tc_set_option", "tc_search", "tc_search_debug",
+              "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity"):
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def tc_last_error() -> str:
+    return load_library().tc_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != TC_OK:
+        raise TacoError(rc, tc_last_error())
+
+
+def tc_load_index(path: str, device: int = 0) -> C.c_void_p:
+    h = C.c_void_p()
+    _check(load_library().tc_load_index(os.fsencode(path), int(device), C.byref(h)))
+    return h
+
+
+def tc_free_index(index) -> None:
+    if index:
+        load_library().tc_free_index(index)
+
+
+def tc_index_info(index) -> Dict[str, int]:
+    n, d, Ns, s, l = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(load_library().tc_index_info(index, C.byref(n), C.byref(d), C.byref(Ns), C.byref(s),
+                                        C.byref(l)))
+    return dict(n=n.value, d=d.value, Ns=Ns.value, s=s.value, l=l.value)
+
+
+def tc_set_option(index, option: int, value: int) -> None:
+    _check(load_library().tc_set_option(index, int(option), int(value)))
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check_tensor(t, dtype, shape, device, name):
+    import torch
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape {tuple(shape)}")
+    if device is not None and t.device != torch.device(device):
+        raise ValueError(f"{name} must live on {device}")
+
+
+def tc_search(index, queries, k: int, alpha: float, beta: float, ids=None, dists=None,
+              stream=None) -> Tuple["object", "object"]:
+    """Enqueue a search of ``queries`` (CUDA float32 [nq, d]); returns
+    ``(ids int64 [nq, k], dists float32 [nq, k])`` (allocated if not given)."""
+    return tc_search_debug(index, queries, k, alpha, beta, None, ids, dists, stream)
+
+
+def tc_search_debug(index, queries, k: int, alpha: float, beta: float, dump=None, ids=None,
+                    dists=None, stream=None):
+    """tc_search plus per-stage outputs into the CUDA tensors of the ``dump``
+    dict (keys from ``DUMP_FIELDS``; shapes as in include/taco.h)."""
+    import torch
+    nq = int(queries.shape[0])
+    dev = queries.device
+    if ids is None:
+        ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    if dists is None:
+        dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    if queries.dtype != torch.float32 or not queries.is_cuda or not queries.is_contiguous():
+        raise ValueError("queries must be a contiguous float32 CUDA tensor")
+    _check_tensor(ids, torch.int64, (nq, k), dev, "ids")
+    _check_tensor(dists, torch.float32, (nq, k), dev, "dists")
+    st = _stream_handle(stream, dev)
+    L = load_library()
+    if dump is None:
+        rc = L.tc_search(index, queries.data_ptr(), nq, int(k), float(alpha), float(beta),
+                         ids.data_ptr(), dists.data_ptr(), st)
+    else:
+        unknown = set(dump) - set(DUMP_FIELDS)
+        if unknown:
+            raise ValueError(f"unknown dump fields {sorted(unknown)}")
+        for t in dump.values():
+            if not (t.is_cuda and t.is_contiguous()):
+                raise ValueError("dump tensors must be contiguous CUDA tensors")
+        sd = _StageDump(*[_ptr(dump.get(f)) for f in DUMP_FIELDS])
+        rc = L.tc_search_debug(index, queries.data_ptr(), nq, int(k), float(alpha), float(beta),
+                               ids.data_ptr(), dists.data_ptr(), st, C.byref(sd))
+    _check(rc)
+    return ids, dists
+
+
+def tc_kernel_time(index, kernel: str) -> Tuple[float, int]:
+    ms, n = C.c_double(), C.c_int64()
+    _check(load_library().tc_kernel_time(index, kernel.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def tc_profile_reset(index) -> None:
+    _check(load_library().tc_profile_reset(index))
+
+
+def tc_batch_capacity(index) -> int:
+    v = C.c_int64()
+    _check(load_library().tc_batch_capacity(index, C.byref(v)))
+    return v.value
+
+
+class Index:
+    """Owning wrapper of a loaded index."""
+
+    def __init__(self, path: str, device: int = 0):
+        self.device = int(device)
+        self.handle = tc_load_index(path, self.device)
+        info = tc_index_info(self.handle)
+        self.n, self.d, self.Ns, self.s, self.l = (info[x] for x in ("n", "d", "Ns", "s", "l"))
+        self.M, self.K = self.Ns * self.s, self.l * self.l
+
+    def close(self):
+        if self.handle:
+            tc_free_index(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, option: int, value: int):
+        tc_set_option(self.handle, option, value)
+
+    def search(self, queries, k: int, alpha: float, beta: float, **kw):
+        return tc_search(self.handle, queries, k, alpha, beta, **kw)
+
+    def search_debug(self, queries, k: int, alpha: float, beta: float, dump, **kw):
+        return tc_search_debug(self.handle, queries, k, alpha, beta, dump, **kw)
+
+    def dump_buffers(self, nq: int, fields=DUMP_FIELDS):
+        """Allocate stage-dump tensors for ``nq`` queries on the index's GPU."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        shapes = dict(
+            qt=((nq, self.M), torch.float32), cdist=((nq, self.Ns, 2, self.l), torch.float32),
+            corder=((nq, self.Ns, 2, self.l), torch.int32),
+            cells=((nq, self.Ns, self.K), torch.int32), ncells=((nq, self.Ns), torch.int32),
+            retrieved=((nq, self.Ns), torch.int64), sc=((nq, self.n), torch.uint8),
+            hist=((nq, self.Ns + 1), torch.int64), last=((nq,), torch.int32),
+            ncand=((nq,), torch.int64), cand=((nq, self.n), torch.int32),
+            cand_dist=((nq, self.n), torch.float32))
+        return {f: torch.empty(shapes[f][0], dtype=shapes[f][1], device=dev) for f in fields}
+
+    def kernel_time(self, kernel: str):
+        return tc_kernel_time(self.handle, kernel)
+
+    def profile_reset(self):
+        tc_profile_reset(self.handle)
+
+    def batch_capacity(self) -> int:
+        return tc_batch_capacity(self.handle)

@@ -1,0 +1,50 @@
+// kernels.h -- launchers of the gfx950 kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace taco {
+
+struct CountLaunch {
+    int nq, Ns, K, T, W;
+    int64_t n;
+    const uint32_t *ids;    // [Ns][n] point ids of every cell, cell after cell
+    const uint32_t *off2d;  // [Ns][K][T+1] start of each tile's slice of each cell
+    const int32_t *cells;   // [nq][Ns][K] probed cells
+    const int32_t *ncells;  // [nq][Ns]
+};
+
+struct SelectLaunch {
+    const uint32_t *hist;   // [nq][Ns+1] level counts (levels >= 1)
+    int64_t R;
+    int rule;
+    int64_t cap;
+    int32_t *cand;
+    uint32_t *cand_count;
+    uint8_t *dump_sc;
+    int32_t *dump_last;
+    int64_t *dump_hist;
+};
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t st);
+hipError_t launch_u32_to_i64(const uint32_t *src, int64_t *dst, int64_t count, hipStream_t st);
+hipError_t launch_build_off2d(const uint32_t *ids, const uint32_t *offs, int Ns, int K, int64_t n,
+                              int T, int W, uint32_t *off2d, hipStream_t st);
+hipError_t launch_transform(const float *Q, int nq, int d, const float *mean, const float *B,
+                            int M, float *qt, hipStream_t st);
+hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, int h2, int l,
+                        int K, const float *C1, const float *C2, const uint32_t *offs, int64_t A,
+                        int32_t *cells, int32_t *ncells, int64_t *retrieved, float *dump_cdist,
+                        int32_t *dump_corder, hipStream_t st);
+hipError_t prepare_count_kernels(int W);
+size_t count_lds_bytes(int W);
+hipError_t launch_count(const CountLaunch &c, uint32_t *hist, hipStream_t st);
+hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, hipStream_t st);
+int rerank_lanes_per_row(int d);
+hipError_t launch_rerank(const float *Q, int nq, int d, const float *base, const int32_t *cand,
+                         const uint32_t *cand_count, int64_t cap, float *cand_dist, int blocks_per_q,
+                         hipStream_t st);
+hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32_t *cand_count,
+                       int64_t cap, int nq, int k, int64_t *ids, float *dists, hipStream_t st);
+
+}  // namespace taco

@@ -1,0 +1,719 @@
+// kernels.hip -- gfx950 kernels of the TaCo query stage (Alg 4-6).
+//
+// One launch per pipeline step, all stream-ordered on the caller's stream:
+//   k_transform   q' = B^T (q - mean)                 (Alg 6 transform step)
+//   k_probe       half distances, their order, and the cell probe of Alg 4
+//                 for one (query, subspace) per wavefront
+//   k_count       per-point collision counts of a tile of ids, held in LDS,
+//                 reduced to the SC level histogram (Alg 6 count step,
+//                 Alg 5 histogram)
+//   k_select      the same counts rebuilt, Alg 5 threshold, candidate
+//                 compaction
+//   k_rerank      exact FP32 squared distances of the candidates
+//   k_topk        k smallest (distance, id) pairs by radix select
+//
+// Integer-deciding arithmetic (transform, half distances, cell keys) uses
+// the canonical FP32 chain: one fused multiply-add per term, terms in
+// ascending index order, starting from +0; the library is built with
+// -ffp-contract=off so no other operation is fused.  That makes probed
+// cells, counts and candidates reproducible bit for bit on any CPU that
+// evaluates the same chain.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace taco {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+constexpr int WAVES = BLOCK / WAVE;
+
+// ---------------------------------------------------------------------------
+// wavefront helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
+    uint32_t lo = __shfl_xor(static_cast<uint32_t>(v), mask, WAVE);
+    uint32_t hi = __shfl_xor(static_cast<uint32_t>(v >> 32), mask, WAVE);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Minimum over the wavefront; every lane receives it.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int m = WAVE / 2; m > 0; m >>= 1) {
+        uint64_t o = shfl_xor_u64(v, m);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int m = WAVE / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, WAVE);
+    return v;
+}
+
+// Inclusive prefix sum over the wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        uint32_t t = __shfl_up(v, o, WAVE);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Number of bytes of w equal to b (exact; bytes are < 0x80 here).
+__device__ __forceinline__ uint32_t bytes_equal(uint32_t w, uint32_t b) {
+    uint32_t x = w ^ (b * 0x01010101u);
+    uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
+    return __popc(z);
+}
+
+// ---------------------------------------------------------------------------
+// small utility kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t v) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (; i < count; i += stride) p[i] = v;
+}
+
+__global__ void k_u32_to_i64(const uint32_t *src, int64_t *dst, int64_t count) {
+    int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) dst[i] = static_cast<int64_t>(src[i]);
+}
+
+// off2d[(j*K + c)*(T+1) + t] = position in ids[j] of the first id >= t*W among
+// cell c's ids (which are ascending).  One thread per (subspace, cell).
+__global__ void k_build_off2d(const uint32_t *ids, const uint32_t *offs, int Ns, int K,
+                              int64_t n, int T, int W, uint32_t *off2d) {
+    int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (g >= static_cast<int64_t>(Ns) * K) return;
+    int j = static_cast<int>(g / K), c = static_cast<int>(g % K);
+    const uint32_t *idj = ids + static_cast<int64_t>(j) * n;
+    uint32_t lo0 = offs[static_cast<int64_t>(j) * (K + 1) + c];
+    uint32_t hi0 = offs[static_cast<int64_t>(j) * (K + 1) + c + 1];
+    uint32_t *out = off2d + g * (T + 1);
+    for (int t = 0; t <= T; t++) {
+        uint64_t key = static_cast<uint64_t>(t) * static_cast<uint64_t>(W);
+        uint32_t lo = lo0, hi = hi0;
+        while (lo < hi) {
+            uint32_t mid = lo + (hi - lo) / 2;
+            if (static_cast<uint64_t>(idj[mid]) < key) lo = mid + 1;
+            else hi = mid;
+        }
+        out[t] = lo;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// transform: qt[q][m] = chain over t of fma(B[t][m], fl32(Q[q][t] - mean[t]))
+// block (64, 4): x = output column, y = group of QPT queries.
+// ---------------------------------------------------------------------------
+
+constexpr int TR_QPT = 4;
+constexpr int TR_Q = 4 * TR_QPT;  // queries per block
+constexpr int TR_T = 64;          // t per LDS stage
+
+__global__ __launch_bounds__(256) void k_transform(const float *__restrict__ Q, int nq, int d,
+                                                   const float *__restrict__ mean,
+                                                   const float *__restrict__ B, int M,
+                                                   float *__restrict__ qt) {
+    __shared__ float e[TR_Q][TR_T + 1];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int col = blockIdx.x * 64 + tx;
+    const int q0 = blockIdx.y * TR_Q;
+    float acc[TR_QPT];
+#pragma unroll
+    for (int r = 0; r < TR_QPT; r++) acc[r] = 0.0f;
+    for (int t0 = 0; t0 < d; t0 += TR_T) {
+#pragma unroll
+        for (int r = 0; r < TR_QPT; r++) {
+            int qi = ty * TR_QPT + r, t = t0 + tx;
+            float v = 0.0f;
+            if (q0 + qi < nq && t < d) v = Q[static_cast<int64_t>(q0 + qi) * d + t] - mean[t];
+            e[qi][tx] = v;
+        }
+        __syncthreads();
+        const int tn = min(TR_T, d - t0);
+        if (col < M) {
+            for (int tt = 0; tt < tn; tt++) {
+                float b = B[static_cast<int64_t>(t0 + tt) * M + col];
+#pragma unroll
+                for (int r = 0; r < TR_QPT; r++) acc[r] = fmaf(b, e[ty * TR_QPT + r][tt], acc[r]);
+            }
+        }
+        __syncthreads();
+    }
+    if (col < M) {
+#pragma unroll
+        for (int r = 0; r < TR_QPT; r++) {
+            int q = q0 + ty * TR_QPT + r;
+            if (q < nq) qt[static_cast<int64_t>(q) * M + col] = acc[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// probe: one wavefront per (query, subspace).  Lane c computes the squared
+// distance of each half of q' to centroid c, ranks them (stable: ties keep
+// the lower centroid id first), then runs a tournament over the l rows of
+// the cell grid: lane r holds row r's next unprobed column and its key
+// fl32(D1s[r] + D2s[col]); each step takes the lexicographic minimum of
+// (key, row) across the wavefront.  Rows are non-decreasing along columns,
+// so this visits cells in exactly the order of Alg 4's heap (distance, row)
+// and stops at the same cell: the first one that brings the retrieved count
+// to at least A.
+// grid (ceil(nq/4), Ns), block 256; dynamic LDS: K cell sizes of subspace j.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_probe(
+    const float *__restrict__ qt, int nq, int M, int s, int h1, int h2, int l, int K,
+    const float *__restrict__ C1, const float *__restrict__ C2,
+    const uint32_t *__restrict__ offs, int64_t A, int32_t *__restrict__ cells,
+    int32_t *__restrict__ ncells, int64_t *__restrict__ retrieved,
+    float *__restrict__ dump_cdist, int32_t *__restrict__ dump_corder) {
+    extern __shared__ uint32_t sizes[];  // [K]
+    __shared__ float rawD[WAVES][2][WAVE];
+    __shared__ float sortD[WAVES][2][WAVE];
+    __shared__ int32_t order[WAVES][2][WAVE];
+
+    const int j = blockIdx.y, Ns = gridDim.y;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int q = blockIdx.x * WAVES + wave;
+    const uint32_t *off = offs + static_cast<int64_t>(j) * (K + 1);
+    for (int c = threadIdx.x; c < K; c += BLOCK) sizes[c] = off[c + 1] - off[c];
+    __syncthreads();
+    if (q >= nq) return;  // no block-wide barrier below this point
+
+    const float *x = qt + static_cast<int64_t>(q) * M + static_cast<int64_t>(j) * s;
+    float d1 = 0.0f, d2 = 0.0f;
+    if (lane < l) {
+        const float *c1 = C1 + (static_cast<int64_t>(j) * l + lane) * h1;
+        const float *c2 = C2 + (static_cast<int64_t>(j) * l + lane) * h2;
+        for (int t = 0; t < h1; t++) {
+            float u = x[t] - c1[t];
+            d1 = fmaf(u, u, d1);
+        }
+        for (int t = 0; t < h2; t++) {
+            float u = x[h1 + t] - c2[t];
+            d2 = fmaf(u, u, d2);
+        }
+        rawD[wave][0][lane] = d1;
+        rawD[wave][1][lane] = d2;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane < l) {
+        int r1 = 0, r2 = 0;
+        for (int c = 0; c < l; c++) {
+            float a = rawD[wave][0][c], b = rawD[wave][1][c];
+            r1 += (a < d1) || (a == d1 && c < lane);
+            r2 += (b < d2) || (b == d2 && c < lane);
+        }
+        order[wave][0][r1] = lane;
+        order[wave][1][r2] = lane;
+        sortD[wave][0][r1] = d1;
+        sortD[wave][1][r2] = d2;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    const int64_t qj = static_cast<int64_t>(q) * Ns + j;
+    if (dump_cdist && lane < l) {
+        dump_cdist[(qj * 2 + 0) * l + lane] = d1;
+        dump_cdist[(qj * 2 + 1) * l + lane] = d2;
+    }
+    if (dump_corder && lane < l) {
+        dump_corder[(qj * 2 + 0) * l + lane] = order[wave][0][lane];
+        dump_corder[(qj * 2 + 1) * l + lane] = order[wave][1][lane];
+    }
+
+    const float *D1s = sortD[wave][0], *D2s = sortD[wave][1];
+    const int32_t *o1 = order[wave][0], *o2 = order[wave][1];
+    int col = 0;
+    uint64_t key = ~0ull;
+    if (lane < l) key = (static_cast<uint64_t>(__float_as_uint(D1s[lane] + D2s[0])) << 32) | lane;
+    int32_t *out = cells + qj * K;
+    int64_t got = 0;
+    int nc = 0;
+    while (nc < K) {
+        uint64_t m = wave_min_u64(key);
+        if (m == ~0ull) break;
+        int w = static_cast<int>(m & 0xffffffffu);
+        int cw = __shfl(col, w, WAVE);
+        int cell = o1[w] * l + o2[cw];
+        if (lane == 0) out[nc] = cell;
+        nc++;
+        got += sizes[cell];
+        if (got >= A) break;
+        if (lane == w) {
+            col++;
+            key = col < l ? (static_cast<uint64_t>(__float_as_uint(D1s[w] + D2s[col])) << 32) | w
+                          : ~0ull;
+        }
+    }
+    if (lane == 0) {
+        ncells[qj] = nc;
+        retrieved[qj] = got;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// count / select: workgroup (tile t, query q) owns ids [t*W, t*W + W) and
+// keeps their collision counts as packed bytes in LDS (4 per 32-bit word;
+// counts <= Ns <= 16 so adding 1 << 8*(id&3) never carries).  Each wavefront
+// takes 64 probed cells at a time, looks up the slice of each cell's id list
+// that falls in the tile (index-time table off2d), and walks the 64 slices
+// as one flattened range so that every lane loads one id per step.
+// ---------------------------------------------------------------------------
+
+struct CountArgs {
+    int Ns, K, T, W;
+    int64_t n;
+    const uint32_t *ids;     // [Ns][n]
+    const uint32_t *off2d;   // [Ns][K][T+1]
+    const int32_t *cells;    // [nq][Ns][K]
+    const int32_t *ncells;   // [nq][Ns]
+};
+
+__device__ void count_tile(const CountArgs &a, int q, int t, uint32_t *cnt, uint32_t *wpre,
+                           uint32_t *wst) {
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int words = a.W / 4;
+    for (int i = threadIdx.x; i < words; i += BLOCK) cnt[i] = 0u;
+    __syncthreads();
+    const uint32_t tile_lo = static_cast<uint32_t>(t) * static_cast<uint32_t>(a.W);
+    uint32_t *pre = wpre + wave * WAVE, *st = wst + wave * WAVE;
+    for (int j = 0; j < a.Ns; j++) {
+        const int64_t qj = static_cast<int64_t>(q) * a.Ns + j;
+        const int P = a.ncells[qj];
+        const int32_t *cl = a.cells + qj * a.K;
+        const uint32_t *idj = a.ids + static_cast<int64_t>(j) * a.n;
+        for (int c0 = wave * WAVE; c0 < P; c0 += BLOCK) {
+            const int c = c0 + lane;
+            uint32_t s0 = 0, len = 0;
+            if (c < P) {
+                const int64_t b = (static_cast<int64_t>(j) * a.K + cl[c]) * (a.T + 1) + t;
+                s0 = a.off2d[b];
+                len = a.off2d[b + 1] - s0;
+            }
+            const uint32_t incl = wave_incl_scan_u32(len, lane);
+            const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
+            pre[lane] = incl - len;
+            st[lane] = s0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (uint32_t e0 = 0; e0 < total; e0 += WAVE) {
+                const uint32_t e = e0 + lane;
+                if (e < total) {
+                    int sidx = 0;
+#pragma unroll
+                    for (int step = 32; step > 0; step >>= 1)
+                        if (pre[sidx + step] <= e) sidx += step;
+                    const uint32_t id = idj[st[sidx] + (e - pre[sidx])];
+                    const uint32_t loc = id - tile_lo;
+                    atomicAdd(&cnt[loc >> 2], 1u << ((loc & 3u) * 8u));
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();
+}
+
+// grid (T, nq), block 256, dynamic LDS W + 2*BLOCK*4 bytes.
+__global__ __launch_bounds__(256) void k_count(CountArgs a, uint32_t *__restrict__ hist) {
+    extern __shared__ uint32_t lds[];
+    uint32_t *cnt = lds, *wpre = lds + a.W / 4, *wst = wpre + BLOCK;
+    __shared__ uint32_t hsum[17];
+    const int t = blockIdx.x, q = blockIdx.y;
+    if (threadIdx.x < 17) hsum[threadIdx.x] = 0u;
+    count_tile(a, q, t, cnt, wpre, wst);
+
+    const int64_t tile_lo = static_cast<int64_t>(t) * a.W;
+    const int tile_n = static_cast<int>(min<int64_t>(a.W, a.n - tile_lo));
+    const int words = (tile_n + 3) / 4;
+    uint32_t h[17];
+#pragma unroll
+    for (int v = 0; v < 17; v++) h[v] = 0u;
+    for (int i = threadIdx.x; i < words; i += BLOCK) {
+        const uint32_t w = cnt[i];
+        if (w == 0u) continue;
+#pragma unroll
+        for (int v = 1; v <= 16; v++) h[v] += bytes_equal(w, static_cast<uint32_t>(v));
+    }
+    const int lane = threadIdx.x % WAVE;
+#pragma unroll
+    for (int v = 1; v <= 16; v++) {
+        uint32_t sv = wave_sum_u32(h[v]);
+        if (lane == 0 && sv) atomicAdd(&hsum[v], sv);
+    }
+    __syncthreads();
+    if (threadIdx.x >= 1 && threadIdx.x <= a.Ns && hsum[threadIdx.x])
+        atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], hsum[threadIdx.x]);
+}
+
+struct SelectArgs {
+    const uint32_t *hist;    // [nq][Ns+1], levels >= 1 filled by k_count
+    int64_t R;               // floor(beta*n)
+    int rule;                // 0 printed, 1 prose
+    int64_t cap;             // candidate slots per query (= n)
+    int32_t *cand;           // [nq][cap]
+    uint32_t *cand_count;    // [nq]
+    uint8_t *dump_sc;        // [nq][n] or null
+    int32_t *dump_last;      // [nq] or null
+    int64_t *dump_hist;      // [nq][Ns+1] or null
+};
+
+// Alg 5 scan from the level histogram (level 0 = n minus the others).
+__device__ int select_threshold(const uint32_t *h, int Ns, int64_t n, int64_t R, int rule) {
+    int64_t above0 = 0;
+    for (int v = 1; v <= Ns; v++) above0 += h[v];
+    int last = Ns;
+    int64_t cum = 0;
+    for (int v = Ns; v >= 0; v--) {
+        const int64_t hv = v == 0 ? n - above0 : static_cast<int64_t>(h[v]);
+        cum += hv;
+        const bool pass = rule == 1 ? (cum <= R) : (hv + cum <= R);
+        if (!pass) break;
+        last--;
+    }
+    return last;
+}
+
+// grid (T, nq), block 256, same dynamic LDS as k_count.
+__global__ __launch_bounds__(256) void k_select(CountArgs a, SelectArgs sa) {
+    extern __shared__ uint32_t lds[];
+    uint32_t *cnt = lds, *wpre = lds + a.W / 4, *wst = wpre + BLOCK;
+    const int t = blockIdx.x, q = blockIdx.y;
+    count_tile(a, q, t, cnt, wpre, wst);
+
+    const uint32_t *h = sa.hist + static_cast<int64_t>(q) * (a.Ns + 1);
+    const int last = select_threshold(h, a.Ns, a.n, sa.R, sa.rule);
+    if (t == 0 && threadIdx.x == 0) {
+        if (sa.dump_last) sa.dump_last[q] = last;
+        if (sa.dump_hist) {
+            int64_t above0 = 0;
+            for (int v = 1; v <= a.Ns; v++) above0 += h[v];
+            sa.dump_hist[static_cast<int64_t>(q) * (a.Ns + 1)] = a.n - above0;
+            for (int v = 1; v <= a.Ns; v++)
+                sa.dump_hist[static_cast<int64_t>(q) * (a.Ns + 1) + v] = h[v];
+        }
+    }
+    const int64_t tile_lo = static_cast<int64_t>(t) * a.W;
+    const int tile_n = static_cast<int>(min<int64_t>(a.W, a.n - tile_lo));
+    const int words = (tile_n + 3) / 4;
+    const int lane = threadIdx.x % WAVE;
+    int32_t *cq = sa.cand + static_cast<int64_t>(q) * sa.cap;
+    for (int w0 = 0; w0 < words; w0 += BLOCK) {
+        const int wi = w0 + threadIdx.x;
+        const uint32_t w = wi < words ? cnt[wi] : 0u;
+        if (sa.dump_sc && wi < words) {
+            for (int b = 0; b < 4; b++) {
+                const int loc = wi * 4 + b;
+                if (loc < tile_n)
+                    sa.dump_sc[static_cast<int64_t>(q) * a.n + tile_lo + loc] =
+                        static_cast<uint8_t>((w >> (8 * b)) & 0xffu);
+            }
+        }
+        // a wavefront with nothing at or above the threshold skips the ballots
+        const bool any_here = last <= 0 ? (wi < words) : (w != 0u);
+        if (!__any(any_here)) continue;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const int loc = wi * 4 + b;
+            const int c = static_cast<int>((w >> (8 * b)) & 0xffu);
+            const bool flag = wi < words && loc < tile_n && c >= last;
+            const uint64_t mask = __ballot(flag);
+            if (mask == 0ull) continue;
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&sa.cand_count[q], static_cast<uint32_t>(__popcll(mask)));
+            base = __shfl(base, 0, WAVE);
+            if (flag)
+                cq[base + __popcll(mask & lanes_below(lane))] =
+                    static_cast<int32_t>(tile_lo + loc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// re-rank: squared L2 distance of each candidate row to its query, FP32.
+// LPR lanes cooperate on a row with 16-byte loads; the query sits in LDS.
+// grid (G, nq), block 256, dynamic LDS d floats.
+// ---------------------------------------------------------------------------
+
+template <int LPR, bool VEC4>
+__global__ __launch_bounds__(256) void k_rerank(const float *__restrict__ Q, int d,
+                                                const float *__restrict__ base,
+                                                const int32_t *__restrict__ cand,
+                                                const uint32_t *__restrict__ cand_count,
+                                                int64_t cap, float *__restrict__ cand_dist) {
+    extern __shared__ float qs[];
+    const int q = blockIdx.y;
+    for (int t = threadIdx.x; t < d; t += BLOCK) qs[t] = Q[static_cast<int64_t>(q) * d + t];
+    __syncthreads();
+    const int64_t nc = cand_count[q];
+    constexpr int RPW = WAVE / LPR;  // rows per wavefront per step
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int sub = lane / LPR, li = lane % LPR;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVES * RPW;
+    const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
+    float *dq = cand_dist + static_cast<int64_t>(q) * cap;
+    for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * RPW; i0 < nc;
+         i0 += stride) {
+        const int64_t i = i0 + sub;
+        float acc = 0.0f;
+        if (i < nc) {
+            const int64_t id = cq[i];
+            const float *row = base + id * d;
+            if (VEC4) {
+                const float4 *r4 = reinterpret_cast<const float4 *>(row);
+                const float4 *q4 = reinterpret_cast<const float4 *>(qs);
+                for (int f = li; f < d / 4; f += LPR) {
+                    const float4 xv = r4[f], qv = q4[f];
+                    float u = qv.x - xv.x;
+                    acc = fmaf(u, u, acc);
+                    u = qv.y - xv.y;
+                    acc = fmaf(u, u, acc);
+                    u = qv.z - xv.z;
+                    acc = fmaf(u, u, acc);
+                    u = qv.w - xv.w;
+                    acc = fmaf(u, u, acc);
+                }
+            } else {
+                for (int f = li; f < d; f += LPR) {
+                    const float u = qs[f] - row[f];
+                    acc = fmaf(u, u, acc);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = LPR / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, WAVE);
+        if (li == 0 && i < nc) dq[i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// top-k: one workgroup per query.  Keys (distance bits << 32 | id) are unique
+// and order like (distance, id) because distances are >= +0.  An MSB-first
+// radix select over 8-bit digits finds the smallest prefix whose bucket is
+// taken whole; exactly k keys fall at or below it.  They are gathered to LDS
+// and bitonic-sorted.
+// ---------------------------------------------------------------------------
+
+constexpr int TOPK_MAX = 1024;
+
+__global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
+                                              const float *__restrict__ cand_dist,
+                                              const uint32_t *__restrict__ cand_count,
+                                              int64_t cap, int k, int64_t *__restrict__ ids_out,
+                                              float *__restrict__ d_out) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint64_t sel[TOPK_MAX];
+    __shared__ uint32_t nsel;
+    __shared__ uint32_t s_digit, s_need, s_full;
+    const int q = blockIdx.x;
+    const int64_t nc = cand_count[q];
+    const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
+    const float *dq = cand_dist + static_cast<int64_t>(q) * cap;
+    auto key_of = [&](int64_t i) -> uint64_t {
+        return (static_cast<uint64_t>(__float_as_uint(dq[i])) << 32) | static_cast<uint32_t>(cq[i]);
+    };
+    if (threadIdx.x == 0) nsel = 0u;
+    __syncthreads();
+    int shift = 64;
+    uint64_t prefix = 0;
+    if (nc > k) {
+        uint32_t need = static_cast<uint32_t>(k);
+        bool done = false;
+        while (!done && shift > 0) {
+            shift -= 8;
+            hist[threadIdx.x] = 0u;
+            __syncthreads();
+            for (int64_t i = threadIdx.x; i < nc; i += BLOCK) {
+                const uint64_t kk = key_of(i);
+                const bool match = shift == 56 || (kk >> (shift + 8)) == prefix;
+                if (match) atomicAdd(&hist[(kk >> shift) & 255u], 1u);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                uint32_t cum = 0, dg = 0;
+                for (dg = 0; dg < 255; dg++) {
+                    if (cum + hist[dg] >= need) break;
+                    cum += hist[dg];
+                }
+                s_digit = dg;
+                s_need = need - cum;
+                s_full = hist[dg] == need - cum;
+            }
+            __syncthreads();
+            prefix = (prefix << 8) | s_digit;
+            need = s_need;
+            done = s_full != 0u;
+            __syncthreads();
+        }
+    }
+    // gather: every key (nc <= k) or the keys whose top (64-shift) bits <= prefix
+    for (int64_t i = threadIdx.x; i < nc; i += BLOCK) {
+        const uint64_t kk = key_of(i);
+        const bool take = nc <= k || (kk >> shift) <= prefix;
+        if (take) {
+            const uint32_t p = atomicAdd(&nsel, 1u);
+            if (p < TOPK_MAX) sel[p] = kk;
+        }
+    }
+    __syncthreads();
+    const int m = static_cast<int>(min<uint32_t>(nsel, static_cast<uint32_t>(k)));
+    int P = 1;
+    while (P < m) P <<= 1;
+    for (int i = m + threadIdx.x; i < P; i += BLOCK) sel[i] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P; i += BLOCK) {
+                const int pj = i ^ stride;
+                if (pj > i) {
+                    const bool up = (i & size) == 0;
+                    const uint64_t a = sel[i], b = sel[pj];
+                    if ((a > b) == up) {
+                        sel[i] = b;
+                        sel[pj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < k; i += BLOCK) {
+        const int64_t o = static_cast<int64_t>(q) * k + i;
+        if (i < m) {
+            ids_out[o] = static_cast<int64_t>(static_cast<uint32_t>(sel[i] & 0xffffffffu));
+            d_out[o] = __uint_as_float(static_cast<uint32_t>(sel[i] >> 32));
+        } else {
+            ids_out[o] = -1;
+            d_out[o] = __uint_as_float(0x7f800000u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    k_fill_u32<<<static_cast<unsigned>(blocks), 256, 0, st>>>(p, count, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_u32_to_i64(const uint32_t *src, int64_t *dst, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    k_u32_to_i64<<<static_cast<unsigned>((count + 255) / 256), 256, 0, st>>>(src, dst, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_off2d(const uint32_t *ids, const uint32_t *offs, int Ns, int K, int64_t n,
+                              int T, int W, uint32_t *off2d, hipStream_t st) {
+    int64_t work = static_cast<int64_t>(Ns) * K;
+    k_build_off2d<<<static_cast<unsigned>((work + 255) / 256), 256, 0, st>>>(ids, offs, Ns, K, n,
+                                                                             T, W, off2d);
+    return hipGetLastError();
+}
+
+hipError_t launch_transform(const float *Q, int nq, int d, const float *mean, const float *B,
+                            int M, float *qt, hipStream_t st) {
+    dim3 grid((M + 63) / 64, (nq + TR_Q - 1) / TR_Q), block(64, 4);
+    k_transform<<<grid, block, 0, st>>>(Q, nq, d, mean, B, M, qt);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, int h2, int l,
+                        int K, const float *C1, const float *C2, const uint32_t *offs, int64_t A,
+                        int32_t *cells, int32_t *ncells, int64_t *retrieved, float *dump_cdist,
+                        int32_t *dump_corder, hipStream_t st) {
+    dim3 grid((nq + WAVES - 1) / WAVES, Ns);
+    size_t lds = sizeof(uint32_t) * static_cast<size_t>(K);
+    k_probe<<<grid, BLOCK, lds, st>>>(qt, nq, M, s, h1, h2, l, K, C1, C2, offs, A, cells, ncells,
+                                      retrieved, dump_cdist, dump_corder);
+    return hipGetLastError();
+}
+
+static size_t count_lds(int W) { return static_cast<size_t>(W) + 2u * BLOCK * sizeof(uint32_t); }
+
+size_t count_lds_bytes(int W) { return count_lds(W) + 17 * sizeof(uint32_t); }
+
+hipError_t prepare_count_kernels(int W) {
+    const int bytes = static_cast<int>(count_lds(W));
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_count),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_select),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_count(const CountLaunch &c, uint32_t *hist, hipStream_t st) {
+    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
+    dim3 grid(c.T, c.nq);
+    k_count<<<grid, BLOCK, count_lds(c.W), st>>>(a, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, hipStream_t st) {
+    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
+    SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
+                  s.dump_hist};
+    dim3 grid(c.T, c.nq);
+    k_select<<<grid, BLOCK, count_lds(c.W), st>>>(a, sa);
+    return hipGetLastError();
+}
+
+int rerank_lanes_per_row(int d) {
+    if (d % 4 != 0) return 64;
+    int chunks = d / 4, lpr = 4;
+    while (lpr < 64 && lpr * 4 <= chunks) lpr <<= 1;
+    return lpr;
+}
+
+hipError_t launch_rerank(const float *Q, int nq, int d, const float *base, const int32_t *cand,
+                         const uint32_t *cand_count, int64_t cap, float *cand_dist, int blocks_per_q,
+                         hipStream_t st) {
+    dim3 grid(blocks_per_q, nq);
+    size_t lds = sizeof(float) * static_cast<size_t>(d);
+    const int lpr = rerank_lanes_per_row(d);
+    if (d % 4 != 0) {
+        k_rerank<64, false><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist);
+    } else {
+        switch (lpr) {
+        case 4: k_rerank<4, true><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist); break;
+        case 8: k_rerank<8, true><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist); break;
+        case 16: k_rerank<16, true><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist); break;
+        case 32: k_rerank<32, true><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist); break;
+        default: k_rerank<64, true><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist); break;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32_t *cand_count,
+                       int64_t cap, int nq, int k, int64_t *ids, float *dists, hipStream_t st) {
+    k_topk<<<nq, BLOCK, 0, st>>>(cand, cand_dist, cand_count, cap, k, ids, dists);
+    return hipGetLastError();
+}
+
+}  // namespace taco

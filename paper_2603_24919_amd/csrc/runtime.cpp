@@ -1,0 +1,538 @@
+// runtime.cpp -- host side of the C-ABI in include/taco.h: index loading,
+// device tables, scratch sizing and the stream-ordered launch sequence of a
+// search.  No host synchronization happens inside a search: every size the
+// kernels need is either known on the host (budgets, shapes) or kept on the
+// device (probe lengths, histogram, candidate counts), and scratch is sized
+// for the worst case of a batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "taco.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(TC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define TC_HIP(call, what)                         \
+    do {                                           \
+        hipError_t e_ = (call);                    \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// FNV-1a, 64-bit (offset basis 14695981039346656037, prime 1099511628211).
+struct Fnv {
+    uint64_t h = 14695981039346656037ULL;
+    void add(const void *p, size_t nb) {
+        const unsigned char *c = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < nb; i++) {
+            h ^= c[i];
+            h *= 1099511628211ULL;
+        }
+    }
+};
+
+struct Reader {
+    FILE *f = nullptr;
+    Fnv sum;
+    ~Reader() {
+        if (f) fclose(f);
+    }
+    bool read(void *dst, size_t nb) {
+        if (fread(dst, 1, nb, f) != nb) return false;
+        sum.add(dst, nb);
+        return true;
+    }
+};
+
+const char *kKernelNames[] = {"transform", "probe", "count", "select", "rerank", "topk"};
+enum Kern { K_TRANSFORM = 0, K_PROBE, K_COUNT, K_SELECT, K_RERANK, K_TOPK, K_COUNT_ };
+
+struct Timing {
+    int kernel;
+    hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct tc_index {
+    int device = 0;
+    int64_t n = 0;
+    int d = 0, Ns = 0, s = 0, h1 = 0, h2 = 0, l = 0, M = 0, K = 0;
+    // index on the device
+    float *mean = nullptr, *B = nullptr, *C1 = nullptr, *C2 = nullptr, *base = nullptr;
+    uint32_t *offs = nullptr, *ids = nullptr, *off2d = nullptr;
+    int W = 65536, T = 1;
+    int max_lds = 65536;
+    // options
+    int rule = TC_RULE_PRINTED;
+    int64_t max_batch = 0;  // 0: automatic
+    int64_t scratch_budget = int64_t(16) << 30;
+    bool profile = false;
+    // scratch for one batch of Qb queries
+    int64_t Qb = 0;
+    float *qt = nullptr;
+    int32_t *cells = nullptr, *ncells = nullptr;
+    int64_t *retrieved = nullptr;
+    uint32_t *hist = nullptr, *cand_count = nullptr;
+    int32_t *cand = nullptr;
+    float *cand_dist = nullptr;
+    // profiling
+    std::vector<Timing> pending;
+    double total_ms[K_COUNT_] = {0};
+    int64_t launches[K_COUNT_] = {0};
+};
+
+namespace {
+
+void free_scratch(tc_index *x) {
+    (void)hipFree(x->qt);
+    (void)hipFree(x->cells);
+    (void)hipFree(x->ncells);
+    (void)hipFree(x->retrieved);
+    (void)hipFree(x->hist);
+    (void)hipFree(x->cand_count);
+    (void)hipFree(x->cand);
+    (void)hipFree(x->cand_dist);
+    x->qt = nullptr;
+    x->cells = x->ncells = nullptr;
+    x->retrieved = nullptr;
+    x->hist = x->cand_count = nullptr;
+    x->cand = nullptr;
+    x->cand_dist = nullptr;
+    x->Qb = 0;
+}
+
+template <typename T>
+int dmalloc(T **p, size_t count, const char *what) {
+    *p = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * (count ? count : 1));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(TC_ENOMEM, std::string("hipMalloc failed for ") + what);
+    }
+    return TC_OK;
+}
+
+// Candidate slots are n per query (|C| can reach n); the batch size follows
+// from the candidate-scratch budget.
+int64_t batch_for(const tc_index *x) {
+    const int64_t per_q = 8 * x->n;
+    int64_t qb = x->scratch_budget / per_q;
+    int64_t cap = x->max_batch > 0 ? x->max_batch : 4096;
+    if (qb > cap) qb = cap;
+    if (qb < 1) qb = 1;
+    return qb;
+}
+
+int alloc_scratch(tc_index *x) {
+    free_scratch(x);
+    const int64_t qb = batch_for(x);
+    int rc;
+    if ((rc = dmalloc(&x->qt, size_t(qb) * x->M, "transformed queries"))) return rc;
+    if ((rc = dmalloc(&x->cells, size_t(qb) * x->Ns * x->K, "probed cells"))) return rc;
+    if ((rc = dmalloc(&x->ncells, size_t(qb) * x->Ns, "probe lengths"))) return rc;
+    if ((rc = dmalloc(&x->retrieved, size_t(qb) * x->Ns, "retrieved counts"))) return rc;
+    if ((rc = dmalloc(&x->hist, size_t(qb) * (x->Ns + 1), "level histograms"))) return rc;
+    if ((rc = dmalloc(&x->cand_count, size_t(qb), "candidate counts"))) return rc;
+    if ((rc = dmalloc(&x->cand, size_t(qb) * x->n, "candidates"))) return rc;
+    if ((rc = dmalloc(&x->cand_dist, size_t(qb) * x->n, "candidate distances"))) return rc;
+    x->Qb = qb;
+    return TC_OK;
+}
+
+int build_tiles(tc_index *x) {
+    x->T = static_cast<int>((x->n + x->W - 1) / x->W);
+    (void)hipFree(x->off2d);
+    x->off2d = nullptr;
+    int rc = dmalloc(&x->off2d, size_t(x->Ns) * x->K * (x->T + 1), "tile offsets");
+    if (rc) return rc;
+    TC_HIP(taco::launch_build_off2d(x->ids, x->offs, x->Ns, x->K, x->n, x->T, x->W, x->off2d,
+                                    nullptr),
+           "building tile offsets");
+    TC_HIP(taco::prepare_count_kernels(x->W), "setting LDS size of the count kernels");
+    TC_HIP(hipDeviceSynchronize(), "building tile offsets");
+    return TC_OK;
+}
+
+void free_all(tc_index *x) {
+    free_scratch(x);
+    (void)hipFree(x->mean);
+    (void)hipFree(x->B);
+    (void)hipFree(x->C1);
+    (void)hipFree(x->C2);
+    (void)hipFree(x->base);
+    (void)hipFree(x->offs);
+    (void)hipFree(x->ids);
+    (void)hipFree(x->off2d);
+    for (auto &t : x->pending) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    x->pending.clear();
+}
+
+template <typename T>
+int upload(T **dst, const std::vector<T> &src, const char *what) {
+    int rc = dmalloc(dst, src.size(), what);
+    if (rc) return rc;
+    TC_HIP(hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice), what);
+    return TC_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int load(const char *path, int device, tc_index *x) {
+    Reader r;
+    r.f = fopen(path, "rb");
+    if (!r.f) return fail(TC_EIO, std::string("cannot open index file ") + path);
+    unsigned char hdr[128];
+    if (!r.read(hdr, sizeof hdr)) return fail(TC_EFORMAT, "index file shorter than its header");
+    uint32_t ver, hb;
+    int32_t dims[6];
+    memcpy(&ver, hdr + 8, 4);
+    memcpy(&hb, hdr + 12, 4);
+    memcpy(&x->n, hdr + 16, 8);
+    memcpy(dims, hdr + 24, 24);
+    if (memcmp(hdr, "TACOIDX1", 8) != 0 || ver != 1u || hb != 128u)
+        return fail(TC_EFORMAT, "not a version-1 TACOIDX1 index file");
+    x->d = dims[0];
+    x->Ns = dims[1];
+    x->s = dims[2];
+    x->h1 = dims[3];
+    x->h2 = dims[4];
+    x->l = dims[5];
+    x->M = x->Ns * x->s;
+    x->K = x->l * x->l;
+    if (x->n <= 0 || x->n >= (int64_t(1) << 31) || x->d <= 0 || x->Ns <= 0 || x->Ns > 16 ||
+        x->s < 2 || x->M > x->d || x->l <= 0 || x->l > 64 || x->h1 != x->s / 2 ||
+        x->h2 != x->s - x->s / 2)
+        return fail(TC_EFORMAT, "index shape out of range (need n < 2^31, Ns <= 16, l <= 64, "
+                                "Ns*s <= d, halves s/2 and s - s/2)");
+    const size_t n = size_t(x->n), d = size_t(x->d), Ns = size_t(x->Ns), l = size_t(x->l),
+                 K = size_t(x->K), M = size_t(x->M);
+    std::vector<float> mean(d), B(d * M), C1(Ns * l * x->h1), C2(Ns * l * x->h2);
+    std::vector<uint64_t> off64(Ns * (K + 1));
+    std::vector<uint32_t> ids(Ns * n);
+    std::vector<float> base(n * d);
+    if (!r.read(mean.data(), 4 * mean.size()) || !r.read(B.data(), 4 * B.size()) ||
+        !r.read(C1.data(), 4 * C1.size()) || !r.read(C2.data(), 4 * C2.size()) ||
+        !r.read(off64.data(), 8 * off64.size()) || !r.read(ids.data(), 4 * ids.size()) ||
+        !r.read(base.data(), 4 * base.size()))
+        return fail(TC_EFORMAT, "index file truncated");
+    uint64_t want = 0;
+    const uint64_t got = r.sum.h;
+    if (fread(&want, 1, 8, r.f) != 8 || want != got)
+        return fail(TC_EFORMAT, "index checksum mismatch");
+    // The kernels rely on these: offsets partition [0, n), ids are in range
+    // and ascending inside each cell, every point appears once per subspace.
+    std::vector<uint32_t> offs(Ns * (K + 1));
+    std::vector<unsigned char> seen(n);
+    for (size_t j = 0; j < Ns; j++) {
+        const uint64_t *o = off64.data() + j * (K + 1);
+        if (o[0] != 0 || o[K] != n) return fail(TC_EFORMAT, "cell offsets do not span [0, n)");
+        std::fill(seen.begin(), seen.end(), 0);
+        for (size_t c = 0; c < K; c++) {
+            if (o[c + 1] < o[c]) return fail(TC_EFORMAT, "cell offsets decrease");
+            for (uint64_t p = o[c]; p < o[c + 1]; p++) {
+                const uint32_t id = ids[j * n + p];
+                if (id >= n || seen[id]) return fail(TC_EFORMAT, "point id out of range or repeated");
+                if (p > o[c] && ids[j * n + p - 1] >= id)
+                    return fail(TC_EFORMAT, "ids not ascending inside a cell");
+                seen[id] = 1;
+            }
+        }
+        for (size_t c = 0; c <= K; c++) offs[j * (K + 1) + c] = static_cast<uint32_t>(o[c]);
+    }
+    int ndev = 0;
+    TC_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(TC_EINVAL, "no such HIP device");
+    x->device = device;
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    TC_HIP(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+    x->max_lds = static_cast<int>(prop.sharedMemPerBlock);
+    int rc;
+    if ((rc = upload(&x->mean, mean, "mean"))) return rc;
+    if ((rc = upload(&x->B, B, "transform"))) return rc;
+    if ((rc = upload(&x->C1, C1, "half-1 centroids"))) return rc;
+    if ((rc = upload(&x->C2, C2, "half-2 centroids"))) return rc;
+    if ((rc = upload(&x->offs, offs, "cell offsets"))) return rc;
+    if ((rc = upload(&x->ids, ids, "cell ids"))) return rc;
+    if ((rc = upload(&x->base, base, "base vectors"))) return rc;
+    // Default tile: 64 Ki ids, or what the workgroup LDS limit allows.
+    int W = 65536;
+    while (W > 1024 && taco::count_lds_bytes(W) > size_t(x->max_lds)) W -= 1024;
+    x->W = W;
+    if ((rc = build_tiles(x))) return rc;
+    if ((rc = alloc_scratch(x))) return rc;
+    return TC_OK;
+}
+
+void record(tc_index *x, int kern, hipStream_t st, bool begin) {
+    if (!x->profile) return;
+    if (begin) {
+        Timing t{kern, nullptr, nullptr};
+        if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return;
+        (void)hipEventRecord(t.start, st);
+        x->pending.push_back(t);
+    } else if (!x->pending.empty() && x->pending.back().kernel == kern) {
+        (void)hipEventRecord(x->pending.back().stop, st);
+    }
+}
+
+int resolve_timings(tc_index *x) {
+    for (auto &t : x->pending) {
+        TC_HIP(hipEventSynchronize(t.stop), "waiting for profiled kernels");
+        float ms = 0.0f;
+        TC_HIP(hipEventElapsedTime(&ms, t.start, t.stop), "hipEventElapsedTime");
+        x->total_ms[t.kernel] += ms;
+        x->launches[t.kernel] += 1;
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    x->pending.clear();
+    return TC_OK;
+}
+
+int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, double beta,
+           int64_t *ids, float *dists, void *stream, const tc_stage_dump *dump) {
+    if (!x) return fail(TC_EINVAL, "index is NULL");
+    if (nq < 0) return fail(TC_EINVAL, "nq < 0");
+    if (nq == 0) return TC_OK;
+    if (!Q || !ids || !dists) return fail(TC_EINVAL, "queries, ids and dists must be non-NULL");
+    if (k < 1 || int64_t(k) > x->n || k > 1024) return fail(TC_EINVAL, "k must be in [1, min(n, 1024)]");
+    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(TC_EINVAL, "alpha must be in (0, 1]");
+    if (!(beta >= 0.0 && beta <= 1.0)) return fail(TC_EINVAL, "beta must be in [0, 1]");
+    DeviceGuard g(x->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // budgets in IEEE double (Alg 4 stop test, Alg 5 budget)
+    double a = std::ceil(alpha * double(x->n));
+    if (a < 1.0) a = 1.0;
+    if (a > double(x->n)) a = double(x->n);
+    double r = std::floor(beta * double(x->n));
+    if (r < 0.0) r = 0.0;
+    if (r > double(x->n)) r = double(x->n);
+    const int64_t A = static_cast<int64_t>(a), R = static_cast<int64_t>(r);
+    const int64_t cap = x->n;
+    const int rr_blocks = 32;
+    for (int64_t b0 = 0; b0 < nq; b0 += x->Qb) {
+        const int nb = static_cast<int>(std::min<int64_t>(x->Qb, nq - b0));
+        const float *Qb = Q + b0 * x->d;
+        TC_HIP(taco::launch_fill_u32(x->hist, int64_t(nb) * (x->Ns + 1), 0u, st), "clearing histograms");
+        TC_HIP(taco::launch_fill_u32(x->cand_count, nb, 0u, st), "clearing candidate counts");
+
+        record(x, K_TRANSFORM, st, true);
+        TC_HIP(taco::launch_transform(Qb, nb, x->d, x->mean, x->B, x->M, x->qt, st), "transform kernel");
+        record(x, K_TRANSFORM, st, false);
+
+        float *dcd = dump && dump->cdist ? dump->cdist + b0 * x->Ns * 2 * x->l : nullptr;
+        int32_t *dco = dump && dump->corder ? dump->corder + b0 * x->Ns * 2 * x->l : nullptr;
+        record(x, K_PROBE, st, true);
+        TC_HIP(taco::launch_probe(x->qt, nb, x->Ns, x->M, x->s, x->h1, x->h2, x->l, x->K, x->C1,
+                                  x->C2, x->offs, A, x->cells, x->ncells, x->retrieved, dcd, dco, st),
+               "probe kernel");
+        record(x, K_PROBE, st, false);
+
+        taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->n, x->ids, x->off2d, x->cells, x->ncells};
+        record(x, K_COUNT, st, true);
+        TC_HIP(taco::launch_count(cl, x->hist, st), "count kernel");
+        record(x, K_COUNT, st, false);
+
+        taco::SelectLaunch sl{x->hist, R, x->rule, cap, x->cand, x->cand_count,
+                              dump && dump->sc ? dump->sc + b0 * x->n : nullptr,
+                              dump && dump->last ? dump->last + b0 : nullptr,
+                              dump && dump->hist ? dump->hist + b0 * (x->Ns + 1) : nullptr};
+        record(x, K_SELECT, st, true);
+        TC_HIP(taco::launch_select(cl, sl, st), "select kernel");
+        record(x, K_SELECT, st, false);
+
+        record(x, K_RERANK, st, true);
+        TC_HIP(taco::launch_rerank(Qb, nb, x->d, x->base, x->cand, x->cand_count, cap, x->cand_dist,
+                                   rr_blocks, st),
+               "rerank kernel");
+        record(x, K_RERANK, st, false);
+
+        record(x, K_TOPK, st, true);
+        TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, ids + b0 * k,
+                                 dists + b0 * k, st),
+               "top-k kernel");
+        record(x, K_TOPK, st, false);
+
+        if (dump) {
+            const hipMemcpyKind dd = hipMemcpyDeviceToDevice;
+            if (dump->qt)
+                TC_HIP(hipMemcpyAsync(dump->qt + b0 * x->M, x->qt, sizeof(float) * nb * x->M, dd, st), "dump qt");
+            if (dump->cells)
+                TC_HIP(hipMemcpyAsync(dump->cells + b0 * x->Ns * x->K, x->cells,
+                                      sizeof(int32_t) * size_t(nb) * x->Ns * x->K, dd, st), "dump cells");
+            if (dump->ncells)
+                TC_HIP(hipMemcpyAsync(dump->ncells + b0 * x->Ns, x->ncells, sizeof(int32_t) * nb * x->Ns, dd, st),
+                       "dump ncells");
+            if (dump->retrieved)
+                TC_HIP(hipMemcpyAsync(dump->retrieved + b0 * x->Ns, x->retrieved,
+                                      sizeof(int64_t) * nb * x->Ns, dd, st), "dump retrieved");
+            if (dump->ncand)
+                TC_HIP(taco::launch_u32_to_i64(x->cand_count, dump->ncand + b0, nb, st), "dump ncand");
+            if (dump->cand)
+                TC_HIP(hipMemcpyAsync(dump->cand + b0 * x->n, x->cand, sizeof(int32_t) * size_t(nb) * x->n, dd, st),
+                       "dump cand");
+            if (dump->cand_dist)
+                TC_HIP(hipMemcpyAsync(dump->cand_dist + b0 * x->n, x->cand_dist,
+                                      sizeof(float) * size_t(nb) * x->n, dd, st), "dump cand_dist");
+        }
+    }
+    return TC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tc_load_index(const char *path, int device, tc_index **out) {
+    if (!out) return fail(TC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!path) return fail(TC_EINVAL, "path is NULL");
+    tc_index *x = new (std::nothrow) tc_index();
+    if (!x) return fail(TC_ENOMEM, "host allocation failed");
+    int rc;
+    try {
+        rc = load(path, device, x);
+    } catch (const std::bad_alloc &) {
+        rc = fail(TC_ENOMEM, "host allocation failed while reading the index");
+    }
+    if (rc != TC_OK) {
+        DeviceGuard g(x->device);
+        free_all(x);
+        delete x;
+        return rc;
+    }
+    *out = x;
+    g_err.clear();
+    return TC_OK;
+}
+
+void tc_free_index(tc_index *x) {
+    if (!x) return;
+    DeviceGuard g(x->device);
+    free_all(x);
+    delete x;
+}
+
+int tc_index_info(const tc_index *x, int64_t *n, int32_t *d, int32_t *Ns, int32_t *s, int32_t *l) {
+    if (!x) return fail(TC_EINVAL, "index is NULL");
+    if (n) *n = x->n;
+    if (d) *d = x->d;
+    if (Ns) *Ns = x->Ns;
+    if (s) *s = x->s;
+    if (l) *l = x->l;
+    return TC_OK;
+}
+
+int tc_set_option(tc_index *x, int option, int64_t value) {
+    if (!x) return fail(TC_EINVAL, "index is NULL");
+    DeviceGuard g(x->device);
+    switch (option) {
+    case TC_OPT_SELECT_RULE:
+        if (value != TC_RULE_PRINTED && value != TC_RULE_PROSE) return fail(TC_EINVAL, "unknown rule");
+        x->rule = static_cast<int>(value);
+        return TC_OK;
+    case TC_OPT_MAX_BATCH:
+        if (value < 1) return fail(TC_EINVAL, "max batch must be >= 1");
+        TC_HIP(hipDeviceSynchronize(), "synchronizing before re-sizing scratch");
+        x->max_batch = value;
+        return alloc_scratch(x);
+    case TC_OPT_SCRATCH_BYTES:
+        if (value < 8 * x->n) return fail(TC_EINVAL, "scratch budget below one query (8*n bytes)");
+        TC_HIP(hipDeviceSynchronize(), "synchronizing before re-sizing scratch");
+        x->scratch_budget = value;
+        return alloc_scratch(x);
+    case TC_OPT_TILE_IDS:
+        if (value < 1024 || value % 1024 != 0 || value > (int64_t(1) << 20) ||
+            taco::count_lds_bytes(static_cast<int>(value)) > size_t(x->max_lds))
+            return fail(TC_EINVAL, "tile must be a multiple of 1024 ids that fits the LDS");
+        TC_HIP(hipDeviceSynchronize(), "synchronizing before rebuilding tiles");
+        x->W = static_cast<int>(value);
+        return build_tiles(x);
+    case TC_OPT_PROFILE:
+        if (value != 0 && value != 1) return fail(TC_EINVAL, "profile must be 0 or 1");
+        x->profile = value != 0;
+        return TC_OK;
+    default:
+        return fail(TC_EINVAL, "unknown option");
+    }
+}
+
+int tc_search(tc_index *x, const float *queries, int64_t nq, int32_t k, double alpha, double beta,
+              int64_t *ids, float *dists, void *stream) {
+    return search(x, queries, nq, k, alpha, beta, ids, dists, stream, nullptr);
+}
+
+int tc_search_debug(tc_index *x, const float *queries, int64_t nq, int32_t k, double alpha,
+                    double beta, int64_t *ids, float *dists, void *stream, const tc_stage_dump *dump) {
+    return search(x, queries, nq, k, alpha, beta, ids, dists, stream, dump);
+}
+
+int tc_kernel_time(tc_index *x, const char *kernel, double *total_ms, int64_t *launches) {
+    if (!x || !kernel) return fail(TC_EINVAL, "index and kernel name must be non-NULL");
+    DeviceGuard g(x->device);
+    int rc = resolve_timings(x);
+    if (rc) return rc;
+    for (int i = 0; i < K_COUNT_; i++) {
+        if (strcmp(kernel, kKernelNames[i]) == 0) {
+            if (total_ms) *total_ms = x->total_ms[i];
+            if (launches) *launches = x->launches[i];
+            return TC_OK;
+        }
+    }
+    return fail(TC_EINVAL, std::string("unknown kernel name ") + kernel);
+}
+
+int tc_profile_reset(tc_index *x) {
+    if (!x) return fail(TC_EINVAL, "index is NULL");
+    DeviceGuard g(x->device);
+    int rc = resolve_timings(x);
+    for (int i = 0; i < K_COUNT_; i++) {
+        x->total_ms[i] = 0.0;
+        x->launches[i] = 0;
+    }
+    return rc;
+}
+
+int tc_batch_capacity(const tc_index *x, int64_t *qpb) {
+    if (!x || !qpb) return fail(TC_EINVAL, "index and output must be non-NULL");
+    *qpb = x->Qb;
+    return TC_OK;
+}
+
+const char *tc_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,134 @@
+"""GPU path vs the CPU oracle, through the C-ABI.
+
+Bit-exact: transformed queries, half-centroid distances, their order, probed
+cells, retrieved counts, collision counts, level histograms, thresholds and
+candidate sets.  Within 1e-5 relative: re-rank distances.  Result ids equal
+except at distance ties inside that tolerance.
+"""
+import numpy as np
+import pytest
+
+import synthdata
+from oracle import oracle as O
+
+from gpu_parity import ALL_STAGES, compare_query, gpu_search, scaled_workloads, workload_index
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def taco_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_24919_amd as taco
+    taco.load_library()
+    return taco
+
+
+@pytest.fixture(scope="module")
+def tiny(taco_mod):
+    w = synthdata.WORKLOADS["tiny-gmm-20k-d128"]
+    X, Q = synthdata.base_and_queries(w)
+    path = workload_index(w, X)
+    print(f"[tiny] index {path}", flush=True)
+    return dict(w=w, X=X, Q=Q, path=path, oidx=O.OracleIndex(path))
+
+
+def _run_all(taco, path, oidx, Q, k, alpha, beta, rule, label, options=()):
+    idx = taco.Index(path, 0)
+    try:
+        idx.set_option(taco.TC_OPT_SELECT_RULE, rule)
+        for opt, val in options:
+            idx.set_option(opt, val)
+        g = gpu_search(idx, Q, k, alpha, beta, ALL_STAGES)
+    finally:
+        idx.close()
+    for qi in range(Q.shape[0]):
+        r = oidx.query(Q[qi], alpha, beta, k, rule=rule)
+        compare_query(g, qi, r, oidx.Ns, k, label)
+    return g
+
+
+@pytest.mark.parametrize("alpha,beta,rule", [
+    (0.05, 0.005, 0), (0.05, 0.005, 1), (0.01, 0.02, 0), (0.2, 0.001, 0), (0.003, 0.05, 1)])
+def test_tiny_all_stages(taco_mod, tiny, alpha, beta, rule):
+    print(f"[tiny] alpha={alpha} beta={beta} rule={rule}", flush=True)
+    _run_all(taco_mod, tiny["path"], tiny["oidx"], tiny["Q"], 10, alpha, beta, rule,
+             f"tiny a={alpha} b={beta} r={rule}")
+
+
+def test_tiny_multi_tile_and_multi_batch(taco_mod, tiny):
+    # 4096-id tiles: 20000 ids = 4 full tiles + a ragged tail of 3616; batches
+    # of 7 queries: 14 full batches + a ragged batch of 2.
+    print("[tiny] tile=4096 batch=7", flush=True)
+    t = taco_mod
+    _run_all(t, tiny["path"], tiny["oidx"], tiny["Q"], 10, 0.05, 0.005, 0, "tiny tiles",
+             options=((t.TC_OPT_TILE_IDS, 4096), (t.TC_OPT_MAX_BATCH, 7)))
+
+
+def test_tiny_alpha_beta_one_is_exact_knn(taco_mod, tiny):
+    print("[tiny] alpha=beta=1", flush=True)
+    idx = taco_mod.Index(tiny["path"], 0)
+    g = gpu_search(idx, tiny["Q"][:16], 25, 1.0, 1.0, ("sc", "ncand", "last"))
+    idx.close()
+    gi, gd = O.bruteforce(tiny["X"], tiny["Q"][:16], 25)
+    assert np.all(g["sc"] == 8) and np.all(g["ncand"] == tiny["w"].n)
+    assert np.array_equal(g["ids"], gi)
+    np.testing.assert_allclose(g["dists"], gd, rtol=1e-5)
+
+
+def test_tiny_k_edges_and_padding(taco_mod, tiny):
+    print("[tiny] k edges", flush=True)
+    Q, oidx = tiny["Q"][:6], tiny["oidx"]
+    for k, alpha, beta in ((1, 0.05, 0.005), (1024, 0.0001, 0.0), (100, 0.02, 0.002)):
+        idx = taco_mod.Index(tiny["path"], 0)
+        g = gpu_search(idx, Q, k, alpha, beta, ALL_STAGES)
+        idx.close()
+        for qi in range(Q.shape[0]):
+            compare_query(g, qi, oidx.query(Q[qi], alpha, beta, k), oidx.Ns, k, f"k={k}")
+
+
+def test_empty_batch_and_argument_errors(taco_mod, tiny):
+    import torch
+    t = taco_mod
+    idx = t.Index(tiny["path"], 0)
+    q0 = torch.empty((0, tiny["w"].d), dtype=torch.float32, device="cuda:0")
+    ids, dists = idx.search(q0, 10, 0.05, 0.005)
+    assert ids.shape == (0, 10)
+    q = torch.from_numpy(tiny["Q"][:2]).cuda()
+    for k, a, b in ((0, 0.05, 0.005), (1025, 0.05, 0.005), (10, 0.0, 0.005), (10, 1.5, 0.005),
+                    (10, 0.05, -0.1), (10, 0.05, 1.01), (tiny["w"].n + 1, 0.05, 0.005)):
+        with pytest.raises(t.TacoError) as e:
+            idx.search(q, k, a, b)
+        assert e.value.code == t.TC_EINVAL
+    with pytest.raises(t.TacoError):
+        idx.set_option(t.TC_OPT_TILE_IDS, 1000)
+    idx.close()
+
+
+def test_deterministic_across_tiles_and_batches(taco_mod, tiny):
+    t = taco_mod
+    outs = []
+    for tile, batch in ((65536, 4096), (8192, 33), (2048, 1)):
+        idx = t.Index(tiny["path"], 0)
+        idx.set_option(t.TC_OPT_TILE_IDS, tile)
+        idx.set_option(t.TC_OPT_MAX_BATCH, batch)
+        outs.append(gpu_search(idx, tiny["Q"][:40], 10, 0.05, 0.005, ("sc", "hist", "ncand")))
+        idx.close()
+    for o in outs[1:]:
+        for f in ("sc", "hist", "ncand", "ids"):
+            assert np.array_equal(o[f], outs[0][f]), f
+        assert np.array_equal(o["dists"].view(np.uint32), outs[0]["dists"].view(np.uint32))
+
+
+@pytest.mark.parametrize("w", scaled_workloads(), ids=lambda w: w.name)
+def test_workload_shapes_all_stages(taco_mod, w):
+    X, Q = synthdata.base_and_queries(w)
+    print(f"[{w.name}] building index", flush=True)
+    path = workload_index(w, X)
+    oidx = O.OracleIndex(path)
+    t = taco_mod
+    for alpha, beta, rule, opts in ((0.05, 0.005, 0, ()), (0.02, 0.01, 1, ((t.TC_OPT_TILE_IDS, 8192),))):
+        print(f"[{w.name}] alpha={alpha} beta={beta} rule={rule}", flush=True)
+        _run_all(t, path, oidx, Q, 10, alpha, beta, rule, w.name, options=opts)
