@@ -132,3 +132,39 @@ def test_workload_shapes_all_stages(taco_mod, w):
     for alpha, beta, rule, opts in ((0.05, 0.005, 0, ()), (0.02, 0.01, 1, ((t.TC_OPT_TILE_IDS, 8192),))):
         print(f"[{w.name}] alpha={alpha} beta={beta} rule={rule}", flush=True)
         _run_all(t, path, oidx, Q, 10, alpha, beta, rule, w.name, options=opts)
+
+
+def test_bench_workload_full_size_sampled(taco_mod):
+    """The 1M x 128 workload at its full size, in the launch configuration
+    the benchmark times (default options, all 10,000 queries in one call):
+    invariants on every query, the oracle on a sample of queries."""
+    w = synthdata.WORKLOADS["gmm-int-1m-d128"]
+    print(f"[{w.name}] generating", flush=True)
+    X, Q = synthdata.base_and_queries(w)
+    print(f"[{w.name}] index (oracle build if not cached)", flush=True)
+    path = workload_index(w, X)
+    oidx = O.OracleIndex(path)
+    idx = taco_mod.Index(path, 0)
+    rng = np.random.default_rng(2024)
+    sample = np.sort(rng.choice(w.nq, 12, replace=False))
+    small = ("retrieved", "ncells", "hist", "last", "ncand")
+    for alpha in w.alphas:
+        print(f"[{w.name}] alpha={alpha}: full batch", flush=True)
+        g = gpu_search(idx, Q, w.k, alpha, w.beta, small)
+        A = O.budget_A(alpha, w.n)
+        levels = np.arange(w.Ns + 1)
+        assert np.all(g["hist"].sum(axis=1) == w.n)
+        assert np.array_equal((g["hist"] * levels).sum(axis=1), g["retrieved"].sum(axis=1))
+        assert np.all(g["retrieved"] >= A)
+        lastc = np.maximum(g["last"], 0)
+        want_nc = np.array([g["hist"][i, lastc[i]:].sum() for i in range(w.nq)])
+        assert np.array_equal(g["ncand"], want_nc)
+        assert np.all(g["dists"][:, 1:] >= g["dists"][:, :-1])
+        for qi in sample:
+            r = oidx.query(Q[qi], alpha, w.beta, w.k)
+            compare_query(g, qi, r, w.Ns, w.k, f"{w.name} a={alpha}")
+        print(f"[{w.name}] alpha={alpha}: all stages on the sample", flush=True)
+        gs = gpu_search(idx, Q[sample[:4]], w.k, alpha, w.beta, ALL_STAGES)
+        for i, qi in enumerate(sample[:4]):
+            compare_query(gs, i, oidx.query(Q[qi], alpha, w.beta, w.k), w.Ns, w.k, f"{w.name} a={alpha}")
+    idx.close()
