@@ -38,8 +38,9 @@ hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, i
                         int32_t *dump_corder, hipStream_t st);
 hipError_t prepare_count_kernels(int W);
 size_t count_lds_bytes(int W);
-hipError_t launch_count(const CountLaunch &c, uint32_t *hist, hipStream_t st);
-hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, hipStream_t st);
+hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, hipStream_t st);
+hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
+                         hipStream_t st);
 int rerank_lanes_per_row(int d);
 hipError_t launch_rerank(const float *Q, int nq, int d, const float *base, const int32_t *cand,
                          const uint32_t *cand_count, int64_t cap, float *cand_dist, int blocks_per_q,

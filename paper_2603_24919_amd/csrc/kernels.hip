@@ -69,13 +69,6 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Number of bytes of w equal to b (exact; bytes are < 0x80 here).
-__device__ __forceinline__ uint32_t bytes_equal(uint32_t w, uint32_t b) {
-    uint32_t x = w ^ (b * 0x01010101u);
-    uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);
-    return __popc(z);
-}
-
 // ---------------------------------------------------------------------------
 // small utility kernels
 // ---------------------------------------------------------------------------
@@ -272,11 +265,29 @@ __global__ __launch_bounds__(256) void k_probe(
 // ---------------------------------------------------------------------------
 // count / select: workgroup (tile t, query q) owns ids [t*W, t*W + W) and
 // keeps their collision counts as packed bytes in LDS (4 per 32-bit word;
-// counts <= Ns <= 16 so adding 1 << 8*(id&3) never carries).  Each wavefront
-// takes 64 probed cells at a time, looks up the slice of each cell's id list
-// that falls in the tile (index-time table off2d), and walks the 64 slices
-// as one flattened range so that every lane loads one id per step.
+// counts <= Ns <= 16 so adding 1 << 8*(id&3) never carries).  The probed
+// cells of all Ns subspaces form one list.  For a chunk of CT_CHUNK of them,
+// every thread first looks up (in parallel) the slice of a cell's id list
+// that falls in the tile (index-time table off2d) into LDS; then groups of
+// CT_LPS lanes walk whole slices, reading consecutive ids, CT_UNROLL slices
+// in flight per group.
 // ---------------------------------------------------------------------------
+
+#ifndef TACO_CT_BLOCK
+#define TACO_CT_BLOCK 1024
+#endif
+#ifndef TACO_CT_UNROLL
+#define TACO_CT_UNROLL 8
+#endif
+#ifndef TACO_CT_LPS
+#define TACO_CT_LPS 32
+#endif
+constexpr int CT_BLOCK = TACO_CT_BLOCK;
+constexpr int CT_UNROLL = TACO_CT_UNROLL;
+constexpr int CT_LPS = TACO_CT_LPS;             // lanes per slice
+constexpr int CT_GROUPS = CT_BLOCK / CT_LPS;    // slice walkers per workgroup
+constexpr int CT_CHUNK = 1024;                  // slices staged in LDS at a time
+constexpr int CT_STAGE = 256;                   // per-wavefront candidate staging slots
 
 struct CountArgs {
     int Ns, K, T, W;
@@ -287,84 +298,141 @@ struct CountArgs {
     const int32_t *ncells;   // [nq][Ns]
 };
 
-__device__ void count_tile(const CountArgs &a, int q, int t, uint32_t *cnt, uint32_t *wpre,
-                           uint32_t *wst) {
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+// LDS carve-up of k_count (dynamic part).
+struct CountLds {
+    uint64_t *st;     // [CT_CHUNK] slice start in ids
+    uint32_t *len;    // [CT_CHUNK] slice length
+    uint32_t *cnt;    // W/4 words of packed counts
+    int32_t *pP;      // [17] prefix of probed cells over subspaces
+};
+
+__host__ __device__ constexpr size_t count_lds_size(int W) {
+    return static_cast<size_t>(CT_CHUNK) * 12 + static_cast<size_t>(W) + 17 * 4;
+}
+
+__device__ __forceinline__ CountLds carve(unsigned char *lds, int W) {
+    CountLds c;
+    c.st = reinterpret_cast<uint64_t *>(lds);
+    c.len = reinterpret_cast<uint32_t *>(lds + CT_CHUNK * 8);
+    c.cnt = c.len + CT_CHUNK;
+    c.pP = reinterpret_cast<int32_t *>(c.cnt + W / 4);
+    return c;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L) {
     const int words = a.W / 4;
-    for (int i = threadIdx.x; i < words; i += BLOCK) cnt[i] = 0u;
-    __syncthreads();
-    const uint32_t tile_lo = static_cast<uint32_t>(t) * static_cast<uint32_t>(a.W);
-    uint32_t *pre = wpre + wave * WAVE, *st = wst + wave * WAVE;
-    for (int j = 0; j < a.Ns; j++) {
-        const int64_t qj = static_cast<int64_t>(q) * a.Ns + j;
-        const int P = a.ncells[qj];
-        const int32_t *cl = a.cells + qj * a.K;
-        const uint32_t *idj = a.ids + static_cast<int64_t>(j) * a.n;
-        for (int c0 = wave * WAVE; c0 < P; c0 += BLOCK) {
-            const int c = c0 + lane;
-            uint32_t s0 = 0, len = 0;
-            if (c < P) {
-                const int64_t b = (static_cast<int64_t>(j) * a.K + cl[c]) * (a.T + 1) + t;
-                s0 = a.off2d[b];
-                len = a.off2d[b + 1] - s0;
-            }
-            const uint32_t incl = wave_incl_scan_u32(len, lane);
-            const uint32_t total = __shfl(incl, WAVE - 1, WAVE);
-            pre[lane] = incl - len;
-            st[lane] = s0;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (uint32_t e0 = 0; e0 < total; e0 += WAVE) {
-                const uint32_t e = e0 + lane;
-                if (e < total) {
-                    int sidx = 0;
-#pragma unroll
-                    for (int step = 32; step > 0; step >>= 1)
-                        if (pre[sidx + step] <= e) sidx += step;
-                    const uint32_t id = idj[st[sidx] + (e - pre[sidx])];
-                    const uint32_t loc = id - tile_lo;
-                    atomicAdd(&cnt[loc >> 2], 1u << ((loc & 3u) * 8u));
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i = threadIdx.x; i < words; i += CT_BLOCK) L.cnt[i] = 0u;
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        L.pP[0] = 0;
+        for (int j = 0; j < a.Ns; j++) {
+            acc += a.ncells[static_cast<int64_t>(q) * a.Ns + j];
+            L.pP[j + 1] = acc;
         }
     }
     __syncthreads();
+    const int totalP = L.pP[a.Ns];
+    const uint32_t tile_lo = static_cast<uint32_t>(t) * static_cast<uint32_t>(a.W);
+    const int32_t *cq = a.cells + static_cast<int64_t>(q) * a.Ns * a.K;
+    const int grp = threadIdx.x / CT_LPS, lig = threadIdx.x % CT_LPS;
+    for (int c0 = 0; c0 < totalP; c0 += CT_CHUNK) {
+        const int nsl = min(CT_CHUNK, totalP - c0);
+        for (int i = threadIdx.x; i < nsl; i += CT_BLOCK) {
+            const int g = c0 + i;
+            int j = 0;
+            while (L.pP[j + 1] <= g) j++;
+            const int cell = cq[static_cast<int64_t>(j) * a.K + (g - L.pP[j])];
+            const int64_t b = (static_cast<int64_t>(j) * a.K + cell) * (a.T + 1) + t;
+            const uint32_t lo = a.off2d[b];
+            L.len[i] = a.off2d[b + 1] - lo;
+            L.st[i] = static_cast<uint64_t>(j) * static_cast<uint64_t>(a.n) + lo;
+        }
+        __syncthreads();
+        for (int s0 = grp; s0 < nsl; s0 += CT_GROUPS * CT_UNROLL) {
+            uint32_t id[CT_UNROLL];
+#pragma unroll
+            for (int u = 0; u < CT_UNROLL; u++) {
+                const int s = s0 + u * CT_GROUPS;
+                id[u] = 0xffffffffu;
+                if (s < nsl && static_cast<uint32_t>(lig) < L.len[s]) id[u] = a.ids[L.st[s] + lig];
+            }
+#pragma unroll
+            for (int u = 0; u < CT_UNROLL; u++) {
+                if (id[u] != 0xffffffffu) {
+                    const uint32_t loc = id[u] - tile_lo;
+                    atomicAdd(&L.cnt[loc >> 2], 1u << ((loc & 3u) * 8u));
+                }
+            }
+            // the rest of slices longer than one pass
+#pragma unroll 1
+            for (int u = 0; u < CT_UNROLL; u++) {
+                const int s = s0 + u * CT_GROUPS;
+                if (s >= nsl) break;
+                const uint32_t n_s = L.len[s];
+                const uint64_t b_s = L.st[s];
+                for (uint32_t i = CT_LPS + lig; i < n_s; i += CT_LPS) {
+                    const uint32_t loc = a.ids[b_s + i] - tile_lo;
+                    atomicAdd(&L.cnt[loc >> 2], 1u << ((loc & 3u) * 8u));
+                }
+            }
+        }
+        __syncthreads();
+    }
 }
 
-// grid (T, nq), block 256, dynamic LDS W + 2*BLOCK*4 bytes.
-__global__ __launch_bounds__(256) void k_count(CountArgs a, uint32_t *__restrict__ hist) {
-    extern __shared__ uint32_t lds[];
-    uint32_t *cnt = lds, *wpre = lds + a.W / 4, *wst = wpre + BLOCK;
+// grid (T, nq), block 512, dynamic LDS count_lds_size(W).  Adds the tile's
+// level counts to hist[q] and stores the packed counts to sc[q][t] (W bytes).
+__global__ __launch_bounds__(CT_BLOCK) void k_count(CountArgs a, uint32_t *__restrict__ hist,
+                                                   uint4 *__restrict__ sc) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const CountLds L = carve(lds_raw, a.W);
     __shared__ uint32_t hsum[17];
     const int t = blockIdx.x, q = blockIdx.y;
     if (threadIdx.x < 17) hsum[threadIdx.x] = 0u;
-    count_tile(a, q, t, cnt, wpre, wst);
+    count_tile(a, q, t, L);
 
+    // Level histogram of the tile: ge[v] counts bytes >= v, so level v holds
+    // ge[v] - ge[v+1] points.  A byte b >= v exactly when bit 7 of
+    // (b | 0x80) - v is set (no borrow between bytes since b, v <= 16).  The
+    // per-word loop stops at the first level no lane reaches.
     const int64_t tile_lo = static_cast<int64_t>(t) * a.W;
     const int tile_n = static_cast<int>(min<int64_t>(a.W, a.n - tile_lo));
     const int words = (tile_n + 3) / 4;
-    uint32_t h[17];
+    uint32_t ge[18];
 #pragma unroll
-    for (int v = 0; v < 17; v++) h[v] = 0u;
-    for (int i = threadIdx.x; i < words; i += BLOCK) {
-        const uint32_t w = cnt[i];
-        if (w == 0u) continue;
+    for (int v = 0; v < 18; v++) ge[v] = 0u;
+    for (int i0 = 0; i0 < words; i0 += CT_BLOCK) {
+        const int i = i0 + threadIdx.x;
+        const uint32_t w = (i < words ? L.cnt[i] : 0u) | 0x80808080u;
 #pragma unroll
-        for (int v = 1; v <= 16; v++) h[v] += bytes_equal(w, static_cast<uint32_t>(v));
+        for (int v = 1; v <= 16; v++) {
+            const uint32_t m = (w - static_cast<uint32_t>(v) * 0x01010101u) & 0x80808080u;
+            if (!__any(m != 0u)) break;
+            ge[v] += __popc(m);
+        }
     }
     const int lane = threadIdx.x % WAVE;
 #pragma unroll
     for (int v = 1; v <= 16; v++) {
-        uint32_t sv = wave_sum_u32(h[v]);
+        const uint32_t sv = wave_sum_u32(ge[v]);
         if (lane == 0 && sv) atomicAdd(&hsum[v], sv);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < 16; v++) hsum[v] -= hsum[v + 1];
     }
     __syncthreads();
     if (threadIdx.x >= 1 && threadIdx.x <= a.Ns && hsum[threadIdx.x])
         atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], hsum[threadIdx.x]);
+    const uint4 *c4 = reinterpret_cast<const uint4 *>(L.cnt);
+    uint4 *dst = sc + (static_cast<int64_t>(q) * a.T + t) * (a.W / 16);
+    for (int i = threadIdx.x; i < a.W / 16; i += CT_BLOCK) dst[i] = c4[i];
 }
 
 struct SelectArgs {
@@ -395,59 +463,91 @@ __device__ int select_threshold(const uint32_t *h, int Ns, int64_t n, int64_t R,
     return last;
 }
 
-// grid (T, nq), block 256, same dynamic LDS as k_count.
-__global__ __launch_bounds__(256) void k_select(CountArgs a, SelectArgs sa) {
-    extern __shared__ uint32_t lds[];
-    uint32_t *cnt = lds, *wpre = lds + a.W / 4, *wst = wpre + BLOCK;
-    const int t = blockIdx.x, q = blockIdx.y;
-    count_tile(a, q, t, cnt, wpre, wst);
+// Move a wavefront's staged candidates to the query's list: one atomic to
+// reserve the range, then coalesced stores.
+__device__ __forceinline__ void flush_stage(uint32_t *stage, uint32_t &scount, uint32_t *counter,
+                                            int32_t *out, int lane) {
+    wave_sync_lds();
+    uint32_t base = 0;
+    if (lane == 0) base = atomicAdd(counter, scount);
+    base = __shfl(base, 0, WAVE);
+    for (uint32_t i = lane; i < scount; i += WAVE) out[base + i] = static_cast<int32_t>(stage[i]);
+    wave_sync_lds();
+    scount = 0;
+}
 
-    const uint32_t *h = sa.hist + static_cast<int64_t>(q) * (a.Ns + 1);
-    const int last = select_threshold(h, a.Ns, a.n, sa.R, sa.rule);
-    if (t == 0 && threadIdx.x == 0) {
+// Streaming pass over the packed counts of one query: Alg 5's threshold from
+// the level histogram, then compaction of C = {id : SC[id] >= last} through
+// per-wavefront LDS staging.  grid (SEL_BLOCKS_PER_Q, nq), block 512; each
+// thread reads SEL_UNROLL 16-byte words (16 ids each) per step.
+constexpr int SEL_BLOCK = 512;
+constexpr int SEL_WAVES = SEL_BLOCK / WAVE;
+constexpr int SEL_UNROLL = 4;
+
+__global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int64_t n,
+                                                     int64_t words4, const uint4 *__restrict__ sc) {
+    __shared__ uint32_t stage_all[SEL_WAVES * CT_STAGE];
+    const int q = blockIdx.y;
+    const uint32_t *h = sa.hist + static_cast<int64_t>(q) * (Ns + 1);
+    const int last = select_threshold(h, Ns, n, sa.R, sa.rule);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         if (sa.dump_last) sa.dump_last[q] = last;
         if (sa.dump_hist) {
             int64_t above0 = 0;
-            for (int v = 1; v <= a.Ns; v++) above0 += h[v];
-            sa.dump_hist[static_cast<int64_t>(q) * (a.Ns + 1)] = a.n - above0;
-            for (int v = 1; v <= a.Ns; v++)
-                sa.dump_hist[static_cast<int64_t>(q) * (a.Ns + 1) + v] = h[v];
+            for (int v = 1; v <= Ns; v++) above0 += h[v];
+            sa.dump_hist[static_cast<int64_t>(q) * (Ns + 1)] = n - above0;
+            for (int v = 1; v <= Ns; v++) sa.dump_hist[static_cast<int64_t>(q) * (Ns + 1) + v] = h[v];
         }
     }
-    const int64_t tile_lo = static_cast<int64_t>(t) * a.W;
-    const int tile_n = static_cast<int>(min<int64_t>(a.W, a.n - tile_lo));
-    const int words = (tile_n + 3) / 4;
-    const int lane = threadIdx.x % WAVE;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     int32_t *cq = sa.cand + static_cast<int64_t>(q) * sa.cap;
-    for (int w0 = 0; w0 < words; w0 += BLOCK) {
-        const int wi = w0 + threadIdx.x;
-        const uint32_t w = wi < words ? cnt[wi] : 0u;
-        if (sa.dump_sc && wi < words) {
-            for (int b = 0; b < 4; b++) {
-                const int loc = wi * 4 + b;
-                if (loc < tile_n)
-                    sa.dump_sc[static_cast<int64_t>(q) * a.n + tile_lo + loc] =
-                        static_cast<uint8_t>((w >> (8 * b)) & 0xffu);
+    uint32_t *stage = stage_all + wave * CT_STAGE;
+    uint32_t *counter = sa.cand_count + q;
+    uint32_t scount = 0;
+    const uint32_t lastw = static_cast<uint32_t>(last > 0 ? last : 0) * 0x01010101u;
+    const uint4 *src = sc + static_cast<int64_t>(q) * words4;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * SEL_BLOCK;
+    for (int64_t i0 = static_cast<int64_t>(blockIdx.x) * SEL_BLOCK; i0 < words4; i0 += stride * SEL_UNROLL) {
+        uint4 v[SEL_UNROLL];
+#pragma unroll
+        for (int u = 0; u < SEL_UNROLL; u++) {
+            const int64_t i = i0 + u * stride + threadIdx.x;
+            v[u] = i < words4 ? src[i] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < SEL_UNROLL; u++) {
+            const int64_t i = i0 + u * stride + threadIdx.x;
+            const int64_t id0 = i * 16;  // first id held by this 16-byte word
+            const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+            if (sa.dump_sc && i < words4) {
+                for (int b = 0; b < 16; b++) {
+                    if (id0 + b < n)
+                        sa.dump_sc[static_cast<int64_t>(q) * n + id0 + b] =
+                            static_cast<uint8_t>((wv[b >> 2] >> (8 * (b & 3))) & 0xffu);
+                }
+            }
+            uint32_t ge[4];
+            bool anyv = false;
+#pragma unroll
+            for (int c = 0; c < 4; c++) {
+                ge[c] = last <= 0 ? (i < words4 ? 0x80808080u : 0u)
+                                  : (((wv[c] | 0x80808080u) - lastw) & 0x80808080u);
+                anyv |= ge[c] != 0u;
+            }
+            if (!__any(anyv)) continue;
+#pragma unroll
+            for (int b = 0; b < 16; b++) {
+                const int64_t id = id0 + b;
+                const bool flag = ((ge[b >> 2] >> (8 * (b & 3) + 7)) & 1u) && id < n;
+                const uint64_t mask = __ballot(flag);
+                if (mask == 0ull) continue;
+                if (scount > CT_STAGE - WAVE) flush_stage(stage, scount, counter, cq, lane);
+                if (flag) stage[scount + __popcll(mask & lanes_below(lane))] = static_cast<uint32_t>(id);
+                scount += static_cast<uint32_t>(__popcll(mask));
             }
         }
-        // a wavefront with nothing at or above the threshold skips the ballots
-        const bool any_here = last <= 0 ? (wi < words) : (w != 0u);
-        if (!__any(any_here)) continue;
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            const int loc = wi * 4 + b;
-            const int c = static_cast<int>((w >> (8 * b)) & 0xffu);
-            const bool flag = wi < words && loc < tile_n && c >= last;
-            const uint64_t mask = __ballot(flag);
-            if (mask == 0ull) continue;
-            uint32_t base = 0;
-            if (lane == 0) base = atomicAdd(&sa.cand_count[q], static_cast<uint32_t>(__popcll(mask)));
-            base = __shfl(base, 0, WAVE);
-            if (flag)
-                cq[base + __popcll(mask & lanes_below(lane))] =
-                    static_cast<int32_t>(tile_lo + loc);
-        }
     }
+    if (__any(scount != 0u)) flush_stage(stage, scount, counter, cq, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,7 +754,7 @@ hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, i
     return hipGetLastError();
 }
 
-static size_t count_lds(int W) { return static_cast<size_t>(W) + 2u * BLOCK * sizeof(uint32_t); }
+static size_t count_lds(int W) { return count_lds_size(W); }
 
 size_t count_lds_bytes(int W) { return count_lds(W) + 17 * sizeof(uint32_t); }
 
@@ -663,23 +763,27 @@ hipError_t prepare_count_kernels(int W) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_count),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_select),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return hipSuccess;
 }
 
-hipError_t launch_count(const CountLaunch &c, uint32_t *hist, hipStream_t st) {
+hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, hipStream_t st) {
     CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
     dim3 grid(c.T, c.nq);
-    k_count<<<grid, BLOCK, count_lds(c.W), st>>>(a, hist);
+    k_count<<<grid, CT_BLOCK, count_lds(c.W), st>>>(a, hist, reinterpret_cast<uint4 *>(sc));
     return hipGetLastError();
 }
 
-hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, hipStream_t st) {
-    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
+hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
+                         hipStream_t st) {
     SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
                   s.dump_hist};
-    dim3 grid(c.T, c.nq);
-    k_select<<<grid, BLOCK, count_lds(c.W), st>>>(a, sa);
+    const int64_t words4 = static_cast<int64_t>(c.T) * c.W / 16;
+    // about 16 sixteen-byte words per thread
+    int64_t blocks = (words4 + SEL_BLOCK * 16 - 1) / (SEL_BLOCK * 16);
+    if (blocks > 64) blocks = 64;
+    if (blocks < 1) blocks = 1;
+    dim3 grid(static_cast<unsigned>(blocks), c.nq);
+    k_select<<<grid, SEL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words4, reinterpret_cast<const uint4 *>(sc));
     return hipGetLastError();
 }
 

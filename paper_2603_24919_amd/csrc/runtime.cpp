@@ -94,6 +94,7 @@ struct tc_index {
     uint32_t *hist = nullptr, *cand_count = nullptr;
     int32_t *cand = nullptr;
     float *cand_dist = nullptr;
+    uint32_t *sc = nullptr;  // packed collision counts, [Qb][T*W bytes]
     // profiling
     std::vector<Timing> pending;
     double total_ms[K_COUNT_] = {0};
@@ -111,6 +112,8 @@ void free_scratch(tc_index *x) {
     (void)hipFree(x->cand_count);
     (void)hipFree(x->cand);
     (void)hipFree(x->cand_dist);
+    (void)hipFree(x->sc);
+    x->sc = nullptr;
     x->qt = nullptr;
     x->cells = x->ncells = nullptr;
     x->retrieved = nullptr;
@@ -132,10 +135,10 @@ int dmalloc(T **p, size_t count, const char *what) {
     return TC_OK;
 }
 
-// Candidate slots are n per query (|C| can reach n); the batch size follows
-// from the candidate-scratch budget.
+// Candidate slots are n per query (|C| can reach n), plus one byte of packed
+// count per id; the batch size follows from the scratch budget.
 int64_t batch_for(const tc_index *x) {
-    const int64_t per_q = 8 * x->n;
+    const int64_t per_q = 8 * x->n + int64_t(x->T) * x->W;
     int64_t qb = x->scratch_budget / per_q;
     int64_t cap = x->max_batch > 0 ? x->max_batch : 4096;
     if (qb > cap) qb = cap;
@@ -155,6 +158,7 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->cand_count, size_t(qb), "candidate counts"))) return rc;
     if ((rc = dmalloc(&x->cand, size_t(qb) * x->n, "candidates"))) return rc;
     if ((rc = dmalloc(&x->cand_dist, size_t(qb) * x->n, "candidate distances"))) return rc;
+    if ((rc = dmalloc(&x->sc, size_t(qb) * x->T * (x->W / 4), "packed counts"))) return rc;
     x->Qb = qb;
     return TC_OK;
 }
@@ -364,7 +368,7 @@ int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, dou
 
         taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->n, x->ids, x->off2d, x->cells, x->ncells};
         record(x, K_COUNT, st, true);
-        TC_HIP(taco::launch_count(cl, x->hist, st), "count kernel");
+        TC_HIP(taco::launch_count(cl, x->hist, x->sc, st), "count kernel");
         record(x, K_COUNT, st, false);
 
         taco::SelectLaunch sl{x->hist, R, x->rule, cap, x->cand, x->cand_count,
@@ -372,7 +376,7 @@ int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, dou
                               dump && dump->last ? dump->last + b0 : nullptr,
                               dump && dump->hist ? dump->hist + b0 * (x->Ns + 1) : nullptr};
         record(x, K_SELECT, st, true);
-        TC_HIP(taco::launch_select(cl, sl, st), "select kernel");
+        TC_HIP(taco::launch_select(cl, sl, x->sc, st), "select kernel");
         record(x, K_SELECT, st, false);
 
         record(x, K_RERANK, st, true);
@@ -481,7 +485,8 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
             return fail(TC_EINVAL, "tile must be a multiple of 1024 ids that fits the LDS");
         TC_HIP(hipDeviceSynchronize(), "synchronizing before rebuilding tiles");
         x->W = static_cast<int>(value);
-        return build_tiles(x);
+        if (int rc = build_tiles(x)) return rc;
+        return alloc_scratch(x);
     case TC_OPT_PROFILE:
         if (value != 0 && value != 1) return fail(TC_EINVAL, "profile must be 0 or 1");
         x->profile = value != 0;
