@@ -65,8 +65,10 @@ enum tc_option {
     TC_OPT_MAX_BATCH = 2,   /* max queries per internal batch (>= 1); scratch is
                                re-sized to fit; default: what 16 GiB of candidate
                                scratch allows, at most 4096                          */
-    TC_OPT_TILE_IDS = 3,    /* ids per LDS counting tile, a multiple of 1024 that
-                               fits the GPU's LDS per workgroup; default 65536       */
+    TC_OPT_TILE_IDS = 3,    /* ids per LDS counting tile: a multiple of 1024 whose
+                               packed counts (4 bits per id when Ns <= 15, else 8)
+                               fit the GPU's LDS per workgroup; default 64 KB of
+                               counts (131072 ids as nibbles, 65536 as bytes)        */
     TC_OPT_PROFILE = 4,     /* 1: time every kernel launch with HIP events on the
                                search stream (read with tc_kernel_time); 0: off      */
     TC_OPT_SCRATCH_BYTES = 5 /* candidate-scratch budget in bytes used to pick the

@@ -7,6 +7,7 @@ namespace taco {
 
 struct CountLaunch {
     int nq, Ns, K, T, W;
+    int bits;               // 4 (nibbles, Ns <= 15) or 8 (bytes) per packed count
     int64_t n;
     const uint32_t *ids;    // [Ns][n] point ids of every cell, cell after cell
     const uint32_t *off2d;  // [Ns][K][T+1] start of each tile's slice of each cell
@@ -36,8 +37,8 @@ hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, i
                         int K, const float *C1, const float *C2, const uint32_t *offs, int64_t A,
                         int32_t *cells, int32_t *ncells, int64_t *retrieved, float *dump_cdist,
                         int32_t *dump_corder, hipStream_t st);
-hipError_t prepare_count_kernels(int W);
-size_t count_lds_bytes(int W);
+hipError_t prepare_count_kernels(int W, int bits);
+size_t count_lds_bytes(int W, int bits);
 hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, hipStream_t st);
 hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
                          hipStream_t st);

@@ -264,13 +264,15 @@ __global__ __launch_bounds__(256) void k_probe(
 
 // ---------------------------------------------------------------------------
 // count / select: workgroup (tile t, query q) owns ids [t*W, t*W + W) and
-// keeps their collision counts as packed bytes in LDS (4 per 32-bit word;
-// counts <= Ns <= 16 so adding 1 << 8*(id&3) never carries).  The probed
-// cells of all Ns subspaces form one list.  For a chunk of CT_CHUNK of them,
-// every thread first looks up (in parallel) the slice of a cell's id list
-// that falls in the tile (index-time table off2d) into LDS; then groups of
-// CT_LPS lanes walk whole slices, reading consecutive ids, CT_UNROLL slices
-// in flight per group.
+// keeps their collision counts packed in LDS, BITS bits per id: 4-bit
+// nibbles when Ns <= 15, bytes when Ns = 16 (adding 1 << BITS*(id%slot)
+// never carries because counts never exceed Ns).  The probed cells of all Ns
+// subspaces form one list.  For a chunk of CT_CHUNK of them, every thread
+// first looks up (in parallel) the slice of a cell's id list that falls in
+// the tile (index-time table off2d) into LDS; then groups of CT_LPS lanes
+// walk whole slices, reading consecutive ids, CT_UNROLL slices in flight per
+// group.  The tile's level histogram and its packed counts go to HBM; the
+// select kernel streams the packed counts back.
 // ---------------------------------------------------------------------------
 
 #ifndef TACO_CT_BLOCK
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(256) void k_probe(
 #define TACO_CT_UNROLL 8
 #endif
 #ifndef TACO_CT_LPS
-#define TACO_CT_LPS 32
+#define TACO_CT_LPS 64
 #endif
 constexpr int CT_BLOCK = TACO_CT_BLOCK;
 constexpr int CT_UNROLL = TACO_CT_UNROLL;
@@ -302,20 +304,21 @@ struct CountArgs {
 struct CountLds {
     uint64_t *st;     // [CT_CHUNK] slice start in ids
     uint32_t *len;    // [CT_CHUNK] slice length
-    uint32_t *cnt;    // W/4 words of packed counts
+    uint32_t *cnt;    // W*BITS/32 words of packed counts
     int32_t *pP;      // [17] prefix of probed cells over subspaces
 };
 
-__host__ __device__ constexpr size_t count_lds_size(int W) {
-    return static_cast<size_t>(CT_CHUNK) * 12 + static_cast<size_t>(W) + 17 * 4;
+__host__ __device__ constexpr size_t count_lds_size(int W, int bits) {
+    return static_cast<size_t>(CT_CHUNK) * 12 + static_cast<size_t>(W) * bits / 8 + 17 * 4;
 }
 
+template <int BITS>
 __device__ __forceinline__ CountLds carve(unsigned char *lds, int W) {
     CountLds c;
     c.st = reinterpret_cast<uint64_t *>(lds);
     c.len = reinterpret_cast<uint32_t *>(lds + CT_CHUNK * 8);
     c.cnt = c.len + CT_CHUNK;
-    c.pP = reinterpret_cast<int32_t *>(c.cnt + W / 4);
+    c.pP = reinterpret_cast<int32_t *>(c.cnt + W / (32 / BITS));
     return c;
 }
 
@@ -325,8 +328,33 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+template <int BITS>
+__device__ __forceinline__ void bump(uint32_t *cnt, uint32_t loc) {
+    constexpr uint32_t PER = 32 / BITS;
+    atomicAdd(&cnt[loc / PER], 1u << ((loc % PER) * BITS));
+}
+
+// Byte masks of the counts >= v held in a packed word: bit 7 of byte b of
+// m0 (and, for nibbles, of m1) is set when that count is >= v.  For bytes
+// b, b >= v exactly when bit 7 of (b | 0x80) - v is set (no borrow: b, v <=
+// 16).  Nibbles are first spread into bytes: m0 covers the even nibbles
+// (nibble 2b in byte b), m1 the odd ones (nibble 2b+1 in byte b).
+template <int BITS>
+__device__ __forceinline__ void ge_masks(uint32_t w, uint32_t v, uint32_t &m0, uint32_t &m1) {
+    const uint32_t vv = v * 0x01010101u;
+    if (BITS == 8) {
+        m0 = ((w | 0x80808080u) - vv) & 0x80808080u;
+        m1 = 0u;
+    } else {
+        m0 = (((w & 0x0F0F0F0Fu) | 0x80808080u) - vv) & 0x80808080u;
+        m1 = ((((w >> 4) & 0x0F0F0F0Fu) | 0x80808080u) - vv) & 0x80808080u;
+    }
+}
+
+// Counts the collisions of tile t of query q into L.cnt.
+template <int BITS>
 __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L) {
-    const int words = a.W / 4;
+    const int words = a.W / (32 / BITS);
     for (int i = threadIdx.x; i < words; i += CT_BLOCK) L.cnt[i] = 0u;
     if (threadIdx.x == 0) {
         int acc = 0;
@@ -363,12 +391,8 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L) 
                 if (s < nsl && static_cast<uint32_t>(lig) < L.len[s]) id[u] = a.ids[L.st[s] + lig];
             }
 #pragma unroll
-            for (int u = 0; u < CT_UNROLL; u++) {
-                if (id[u] != 0xffffffffu) {
-                    const uint32_t loc = id[u] - tile_lo;
-                    atomicAdd(&L.cnt[loc >> 2], 1u << ((loc & 3u) * 8u));
-                }
-            }
+            for (int u = 0; u < CT_UNROLL; u++)
+                if (id[u] != 0xffffffffu) bump<BITS>(L.cnt, id[u] - tile_lo);
             // the rest of slices longer than one pass
 #pragma unroll 1
             for (int u = 0; u < CT_UNROLL; u++) {
@@ -376,45 +400,43 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L) 
                 if (s >= nsl) break;
                 const uint32_t n_s = L.len[s];
                 const uint64_t b_s = L.st[s];
-                for (uint32_t i = CT_LPS + lig; i < n_s; i += CT_LPS) {
-                    const uint32_t loc = a.ids[b_s + i] - tile_lo;
-                    atomicAdd(&L.cnt[loc >> 2], 1u << ((loc & 3u) * 8u));
-                }
+                for (uint32_t i = CT_LPS + lig; i < n_s; i += CT_LPS)
+                    bump<BITS>(L.cnt, a.ids[b_s + i] - tile_lo);
             }
         }
         __syncthreads();
     }
 }
 
-// grid (T, nq), block 512, dynamic LDS count_lds_size(W).  Adds the tile's
-// level counts to hist[q] and stores the packed counts to sc[q][t] (W bytes).
+// grid (T, nq), block CT_BLOCK, dynamic LDS count_lds_size(W, BITS).  Adds
+// the tile's level counts to hist[q] and stores the packed counts to
+// sc[q][t] (W*BITS/8 bytes).
+template <int BITS>
 __global__ __launch_bounds__(CT_BLOCK) void k_count(CountArgs a, uint32_t *__restrict__ hist,
                                                    uint4 *__restrict__ sc) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const CountLds L = carve(lds_raw, a.W);
-    __shared__ uint32_t hsum[17];
+    const CountLds L = carve<BITS>(lds_raw, a.W);
+    __shared__ uint32_t hsum[18];
     const int t = blockIdx.x, q = blockIdx.y;
-    if (threadIdx.x < 17) hsum[threadIdx.x] = 0u;
-    count_tile(a, q, t, L);
+    if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
+    count_tile<BITS>(a, q, t, L);
 
-    // Level histogram of the tile: ge[v] counts bytes >= v, so level v holds
-    // ge[v] - ge[v+1] points.  A byte b >= v exactly when bit 7 of
-    // (b | 0x80) - v is set (no borrow between bytes since b, v <= 16).  The
-    // per-word loop stops at the first level no lane reaches.
-    const int64_t tile_lo = static_cast<int64_t>(t) * a.W;
-    const int tile_n = static_cast<int>(min<int64_t>(a.W, a.n - tile_lo));
-    const int words = (tile_n + 3) / 4;
-    uint32_t ge[18];
+    // Level histogram of the tile: ge[v] counts the ids with count >= v, so
+    // level v holds ge[v] - ge[v+1].  Ids past n hold 0 and count nowhere.
+    // The per-word loop stops at the first level no lane reaches.
+    const int words = a.W / (32 / BITS);
+    uint32_t ge[17];
 #pragma unroll
-    for (int v = 0; v < 18; v++) ge[v] = 0u;
+    for (int v = 0; v < 17; v++) ge[v] = 0u;
     for (int i0 = 0; i0 < words; i0 += CT_BLOCK) {
         const int i = i0 + threadIdx.x;
-        const uint32_t w = (i < words ? L.cnt[i] : 0u) | 0x80808080u;
+        const uint32_t w = i < words ? L.cnt[i] : 0u;
 #pragma unroll
         for (int v = 1; v <= 16; v++) {
-            const uint32_t m = (w - static_cast<uint32_t>(v) * 0x01010101u) & 0x80808080u;
-            if (!__any(m != 0u)) break;
-            ge[v] += __popc(m);
+            uint32_t m0, m1;
+            ge_masks<BITS>(w, static_cast<uint32_t>(v), m0, m1);
+            if (!__any((m0 | m1) != 0u)) break;
+            ge[v] += __popc(m0) + __popc(m1);
         }
     }
     const int lane = threadIdx.x % WAVE;
@@ -424,15 +446,14 @@ __global__ __launch_bounds__(CT_BLOCK) void k_count(CountArgs a, uint32_t *__res
         if (lane == 0 && sv) atomicAdd(&hsum[v], sv);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int v = 1; v < 16; v++) hsum[v] -= hsum[v + 1];
+    if (threadIdx.x >= 1 && threadIdx.x <= a.Ns) {
+        const uint32_t hv = hsum[threadIdx.x] - hsum[threadIdx.x + 1];
+        if (hv) atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], hv);
     }
-    __syncthreads();
-    if (threadIdx.x >= 1 && threadIdx.x <= a.Ns && hsum[threadIdx.x])
-        atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], hsum[threadIdx.x]);
+    const int vec = a.W * BITS / 128;  // 16-byte words per tile
     const uint4 *c4 = reinterpret_cast<const uint4 *>(L.cnt);
-    uint4 *dst = sc + (static_cast<int64_t>(q) * a.T + t) * (a.W / 16);
-    for (int i = threadIdx.x; i < a.W / 16; i += CT_BLOCK) dst[i] = c4[i];
+    uint4 *dst = sc + (static_cast<int64_t>(q) * a.T + t) * vec;
+    for (int i = threadIdx.x; i < vec; i += CT_BLOCK) dst[i] = c4[i];
 }
 
 struct SelectArgs {
@@ -478,14 +499,17 @@ __device__ __forceinline__ void flush_stage(uint32_t *stage, uint32_t &scount, u
 
 // Streaming pass over the packed counts of one query: Alg 5's threshold from
 // the level histogram, then compaction of C = {id : SC[id] >= last} through
-// per-wavefront LDS staging.  grid (SEL_BLOCKS_PER_Q, nq), block 512; each
-// thread reads SEL_UNROLL 16-byte words (16 ids each) per step.
+// per-wavefront LDS staging.  grid (blocks per query, nq), block SEL_BLOCK;
+// each thread reads SEL_UNROLL 16-byte words (128/BITS ids each) per step.
 constexpr int SEL_BLOCK = 512;
 constexpr int SEL_WAVES = SEL_BLOCK / WAVE;
 constexpr int SEL_UNROLL = 4;
 
+template <int BITS>
 __global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int64_t n,
                                                      int64_t words4, const uint4 *__restrict__ sc) {
+    constexpr int PER_WORD = 32 / BITS;   // ids per 32-bit word
+    constexpr int PER_VEC = 128 / BITS;   // ids per 16-byte word
     __shared__ uint32_t stage_all[SEL_WAVES * CT_STAGE];
     const int q = blockIdx.y;
     const uint32_t *h = sa.hist + static_cast<int64_t>(q) * (Ns + 1);
@@ -504,10 +528,12 @@ __global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int
     uint32_t *stage = stage_all + wave * CT_STAGE;
     uint32_t *counter = sa.cand_count + q;
     uint32_t scount = 0;
-    const uint32_t lastw = static_cast<uint32_t>(last > 0 ? last : 0) * 0x01010101u;
+    // with last <= 0 every id below n is a candidate: compare against 0
+    const uint32_t lv = static_cast<uint32_t>(last > 0 ? last : 0);
     const uint4 *src = sc + static_cast<int64_t>(q) * words4;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * SEL_BLOCK;
-    for (int64_t i0 = static_cast<int64_t>(blockIdx.x) * SEL_BLOCK; i0 < words4; i0 += stride * SEL_UNROLL) {
+    for (int64_t i0 = static_cast<int64_t>(blockIdx.x) * SEL_BLOCK; i0 < words4;
+         i0 += stride * SEL_UNROLL) {
         uint4 v[SEL_UNROLL];
 #pragma unroll
         for (int u = 0; u < SEL_UNROLL; u++) {
@@ -517,33 +543,42 @@ __global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int
 #pragma unroll
         for (int u = 0; u < SEL_UNROLL; u++) {
             const int64_t i = i0 + u * stride + threadIdx.x;
-            const int64_t id0 = i * 16;  // first id held by this 16-byte word
+            const bool in = i < words4;
+            const int64_t id0 = i * PER_VEC;  // first id held by this 16-byte word
             const uint32_t wv[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-            if (sa.dump_sc && i < words4) {
-                for (int b = 0; b < 16; b++) {
+            if (sa.dump_sc && in) {
+                for (int b = 0; b < PER_VEC; b++) {
                     if (id0 + b < n)
-                        sa.dump_sc[static_cast<int64_t>(q) * n + id0 + b] =
-                            static_cast<uint8_t>((wv[b >> 2] >> (8 * (b & 3))) & 0xffu);
+                        sa.dump_sc[static_cast<int64_t>(q) * n + id0 + b] = static_cast<uint8_t>(
+                            (wv[b / PER_WORD] >> (BITS * (b % PER_WORD))) & ((1u << BITS) - 1u));
                 }
             }
-            uint32_t ge[4];
+            uint32_t m[4][2];
             bool anyv = false;
 #pragma unroll
             for (int c = 0; c < 4; c++) {
-                ge[c] = last <= 0 ? (i < words4 ? 0x80808080u : 0u)
-                                  : (((wv[c] | 0x80808080u) - lastw) & 0x80808080u);
-                anyv |= ge[c] != 0u;
+                ge_masks<BITS>(wv[c], lv, m[c][0], m[c][1]);
+                if (!in) m[c][0] = m[c][1] = 0u;
+                anyv |= (m[c][0] | m[c][1]) != 0u;
             }
             if (!__any(anyv)) continue;
 #pragma unroll
-            for (int b = 0; b < 16; b++) {
-                const int64_t id = id0 + b;
-                const bool flag = ((ge[b >> 2] >> (8 * (b & 3) + 7)) & 1u) && id < n;
-                const uint64_t mask = __ballot(flag);
-                if (mask == 0ull) continue;
-                if (scount > CT_STAGE - WAVE) flush_stage(stage, scount, counter, cq, lane);
-                if (flag) stage[scount + __popcll(mask & lanes_below(lane))] = static_cast<uint32_t>(id);
-                scount += static_cast<uint32_t>(__popcll(mask));
+            for (int c = 0; c < 4; c++) {
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+#pragma unroll
+                    for (int hh = 0; hh < (BITS == 4 ? 2 : 1); hh++) {
+                        const int slot = BITS == 8 ? b : 2 * b + hh;
+                        const int64_t id = id0 + c * PER_WORD + slot;
+                        const bool flag = ((m[c][hh] >> (8 * b + 7)) & 1u) && id < n;
+                        const uint64_t mask = __ballot(flag);
+                        if (mask == 0ull) continue;
+                        if (scount > CT_STAGE - WAVE) flush_stage(stage, scount, counter, cq, lane);
+                        if (flag)
+                            stage[scount + __popcll(mask & lanes_below(lane))] = static_cast<uint32_t>(id);
+                        scount += static_cast<uint32_t>(__popcll(mask));
+                    }
+                }
             }
         }
     }
@@ -754,22 +789,23 @@ hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, i
     return hipGetLastError();
 }
 
-static size_t count_lds(int W) { return count_lds_size(W); }
+size_t count_lds_bytes(int W, int bits) { return count_lds_size(W, bits) + 18 * sizeof(uint32_t); }
 
-size_t count_lds_bytes(int W) { return count_lds(W) + 17 * sizeof(uint32_t); }
-
-hipError_t prepare_count_kernels(int W) {
-    const int bytes = static_cast<int>(count_lds(W));
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_count),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    return hipSuccess;
+hipError_t prepare_count_kernels(int W, int bits) {
+    const int bytes = static_cast<int>(count_lds_size(W, bits));
+    const void *k = bits == 4 ? reinterpret_cast<const void *>(k_count<4>)
+                              : reinterpret_cast<const void *>(k_count<8>);
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, hipStream_t st) {
     CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
     dim3 grid(c.T, c.nq);
-    k_count<<<grid, CT_BLOCK, count_lds(c.W), st>>>(a, hist, reinterpret_cast<uint4 *>(sc));
+    uint4 *s4 = reinterpret_cast<uint4 *>(sc);
+    if (c.bits == 4)
+        k_count<4><<<grid, CT_BLOCK, count_lds_size(c.W, 4), st>>>(a, hist, s4);
+    else
+        k_count<8><<<grid, CT_BLOCK, count_lds_size(c.W, 8), st>>>(a, hist, s4);
     return hipGetLastError();
 }
 
@@ -777,13 +813,17 @@ hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint
                          hipStream_t st) {
     SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
                   s.dump_hist};
-    const int64_t words4 = static_cast<int64_t>(c.T) * c.W / 16;
+    const int64_t words4 = static_cast<int64_t>(c.T) * c.W * c.bits / 128;
     // about 16 sixteen-byte words per thread
     int64_t blocks = (words4 + SEL_BLOCK * 16 - 1) / (SEL_BLOCK * 16);
     if (blocks > 64) blocks = 64;
     if (blocks < 1) blocks = 1;
     dim3 grid(static_cast<unsigned>(blocks), c.nq);
-    k_select<<<grid, SEL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words4, reinterpret_cast<const uint4 *>(sc));
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(sc);
+    if (c.bits == 4)
+        k_select<4><<<grid, SEL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words4, s4);
+    else
+        k_select<8><<<grid, SEL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words4, s4);
     return hipGetLastError();
 }
 

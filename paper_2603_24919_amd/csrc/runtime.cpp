@@ -80,6 +80,7 @@ struct tc_index {
     float *mean = nullptr, *B = nullptr, *C1 = nullptr, *C2 = nullptr, *base = nullptr;
     uint32_t *offs = nullptr, *ids = nullptr, *off2d = nullptr;
     int W = 65536, T = 1;
+    int bits = 8;  // packed-count width: 4 when Ns <= 15, else 8
     int max_lds = 65536;
     // options
     int rule = TC_RULE_PRINTED;
@@ -138,7 +139,7 @@ int dmalloc(T **p, size_t count, const char *what) {
 // Candidate slots are n per query (|C| can reach n), plus one byte of packed
 // count per id; the batch size follows from the scratch budget.
 int64_t batch_for(const tc_index *x) {
-    const int64_t per_q = 8 * x->n + int64_t(x->T) * x->W;
+    const int64_t per_q = 8 * x->n + int64_t(x->T) * x->W * x->bits / 8;
     int64_t qb = x->scratch_budget / per_q;
     int64_t cap = x->max_batch > 0 ? x->max_batch : 4096;
     if (qb > cap) qb = cap;
@@ -158,7 +159,8 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->cand_count, size_t(qb), "candidate counts"))) return rc;
     if ((rc = dmalloc(&x->cand, size_t(qb) * x->n, "candidates"))) return rc;
     if ((rc = dmalloc(&x->cand_dist, size_t(qb) * x->n, "candidate distances"))) return rc;
-    if ((rc = dmalloc(&x->sc, size_t(qb) * x->T * (x->W / 4), "packed counts"))) return rc;
+    if ((rc = dmalloc(&x->sc, size_t(qb) * x->T * (size_t(x->W) * x->bits / 32), "packed counts")))
+        return rc;
     x->Qb = qb;
     return TC_OK;
 }
@@ -172,7 +174,7 @@ int build_tiles(tc_index *x) {
     TC_HIP(taco::launch_build_off2d(x->ids, x->offs, x->Ns, x->K, x->n, x->T, x->W, x->off2d,
                                     nullptr),
            "building tile offsets");
-    TC_HIP(taco::prepare_count_kernels(x->W), "setting LDS size of the count kernels");
+    TC_HIP(taco::prepare_count_kernels(x->W, x->bits), "setting LDS size of the count kernels");
     TC_HIP(hipDeviceSynchronize(), "building tile offsets");
     return TC_OK;
 }
@@ -292,9 +294,12 @@ int load(const char *path, int device, tc_index *x) {
     if ((rc = upload(&x->offs, offs, "cell offsets"))) return rc;
     if ((rc = upload(&x->ids, ids, "cell ids"))) return rc;
     if ((rc = upload(&x->base, base, "base vectors"))) return rc;
-    // Default tile: 64 Ki ids, or what the workgroup LDS limit allows.
-    int W = 65536;
-    while (W > 1024 && taco::count_lds_bytes(W) > size_t(x->max_lds)) W -= 1024;
+    // Counts are 4-bit when they cannot exceed 15.  Default tile: 64 KB of
+    // packed counts (128 Ki ids as nibbles, 64 Ki as bytes), or what the
+    // workgroup LDS limit allows.
+    x->bits = x->Ns <= 15 ? 4 : 8;
+    int W = x->bits == 4 ? 131072 : 65536;
+    while (W > 1024 && taco::count_lds_bytes(W, x->bits) > size_t(x->max_lds)) W -= 1024;
     x->W = W;
     if ((rc = build_tiles(x))) return rc;
     if ((rc = alloc_scratch(x))) return rc;
@@ -366,7 +371,8 @@ int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, dou
                "probe kernel");
         record(x, K_PROBE, st, false);
 
-        taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->n, x->ids, x->off2d, x->cells, x->ncells};
+        taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids, x->off2d, x->cells,
+                             x->ncells};
         record(x, K_COUNT, st, true);
         TC_HIP(taco::launch_count(cl, x->hist, x->sc, st), "count kernel");
         record(x, K_COUNT, st, false);
@@ -481,8 +487,8 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
         return alloc_scratch(x);
     case TC_OPT_TILE_IDS:
         if (value < 1024 || value % 1024 != 0 || value > (int64_t(1) << 20) ||
-            taco::count_lds_bytes(static_cast<int>(value)) > size_t(x->max_lds))
-            return fail(TC_EINVAL, "tile must be a multiple of 1024 ids that fits the LDS");
+            taco::count_lds_bytes(static_cast<int>(value), x->bits) > size_t(x->max_lds))
+            return fail(TC_EINVAL, "tile must be a multiple of 1024 ids whose packed counts fit the LDS");
         TC_HIP(hipDeviceSynchronize(), "synchronizing before rebuilding tiles");
         x->W = static_cast<int>(value);
         if (int rc = build_tiles(x)) return rc;
