@@ -33,20 +33,24 @@ constexpr int WAVES = BLOCK / WAVE;
 // wavefront helpers
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int mask) {
-    uint32_t lo = __shfl_xor(static_cast<uint32_t>(v), mask, WAVE);
-    uint32_t hi = __shfl_xor(static_cast<uint32_t>(v >> 32), mask, WAVE);
-    return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
-// Minimum over the wavefront; every lane receives it.
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-    for (int m = WAVE / 2; m > 0; m >>= 1) {
-        uint64_t o = shfl_xor_u64(v, m);
-        v = o < v ? o : v;
-    }
-    return v;
+// Unsigned minimum over the wavefront with DPP moves (gfx9 row operations):
+// quad swaps, half-row and row mirrors leave every lane holding its row's
+// minimum; two row broadcasts fold the four rows into lane 63, which is read
+// back as a uniform value.
+__device__ __forceinline__ uint32_t wave_min_u32_dpp(uint32_t v) {
+    int x = static_cast<int>(v);
+#define TACO_DPP_MIN(ctrl, rows)                                                           \
+    x = static_cast<int>(min(static_cast<uint32_t>(x),                                     \
+                             static_cast<uint32_t>(__builtin_amdgcn_update_dpp(            \
+                                 x, x, ctrl, rows, 0xf, false))))
+    TACO_DPP_MIN(0xb1, 0xf);   // quad_perm [1,0,3,2]
+    TACO_DPP_MIN(0x4e, 0xf);   // quad_perm [2,3,0,1]
+    TACO_DPP_MIN(0x141, 0xf);  // row_half_mirror
+    TACO_DPP_MIN(0x140, 0xf);  // row_mirror
+    TACO_DPP_MIN(0x142, 0xa);  // row_bcast:15 into rows 1 and 3
+    TACO_DPP_MIN(0x143, 0xc);  // row_bcast:31 into rows 2 and 3
+#undef TACO_DPP_MIN
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(x, 63));
 }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
@@ -232,28 +236,31 @@ __global__ __launch_bounds__(256) void k_probe(
         dump_corder[(qj * 2 + 1) * l + lane] = order[wave][1][lane];
     }
 
-    const float *D1s = sortD[wave][0], *D2s = sortD[wave][1];
-    const int32_t *o1 = order[wave][0], *o2 = order[wave][1];
+    // Tournament: lane r holds row r (half-1 rank r) with its next column and
+    // key bits (keys are >= +0, so their bit patterns order like the floats).
+    // Each step finds the smallest key, then the lowest row holding it.
+    const float *D2s = sortD[wave][1];
+    const float my_d1 = lane < l ? sortD[wave][0][lane] : 0.0f;
+    const int my_o1 = lane < l ? order[wave][0][lane] : 0;
+    const int my_o2 = lane < l ? order[wave][1][lane] : 0;
     int col = 0;
-    uint64_t key = ~0ull;
-    if (lane < l) key = (static_cast<uint64_t>(__float_as_uint(D1s[lane] + D2s[0])) << 32) | lane;
+    uint32_t kb = lane < l ? __float_as_uint(my_d1 + D2s[0]) : 0xffffffffu;
     int32_t *out = cells + qj * K;
     int64_t got = 0;
     int nc = 0;
     while (nc < K) {
-        uint64_t m = wave_min_u64(key);
-        if (m == ~0ull) break;
-        int w = static_cast<int>(m & 0xffffffffu);
-        int cw = __shfl(col, w, WAVE);
-        int cell = o1[w] * l + o2[cw];
+        const uint32_t kmin = wave_min_u32_dpp(kb);
+        if (kmin == 0xffffffffu) break;
+        const int w = static_cast<int>(__builtin_ctzll(__ballot(kb == kmin)));
+        const int cw = __builtin_amdgcn_readlane(col, w);
+        const int cell = __builtin_amdgcn_readlane(my_o1, w) * l + __builtin_amdgcn_readlane(my_o2, cw);
         if (lane == 0) out[nc] = cell;
         nc++;
         got += sizes[cell];
         if (got >= A) break;
         if (lane == w) {
             col++;
-            key = col < l ? (static_cast<uint64_t>(__float_as_uint(D1s[w] + D2s[col])) << 32) | w
-                          : ~0ull;
+            kb = col < l ? __float_as_uint(my_d1 + D2s[col]) : 0xffffffffu;
         }
     }
     if (lane == 0) {
