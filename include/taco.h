@@ -63,7 +63,7 @@ enum tc_select_rule { TC_RULE_PRINTED = 0, TC_RULE_PROSE = 1 };
 enum tc_option {
     TC_OPT_SELECT_RULE = 1, /* tc_select_rule; default TC_RULE_PRINTED                 */
     TC_OPT_MAX_BATCH = 2,   /* max queries per internal batch (>= 1); scratch is
-                               re-sized to fit; default: what 16 GiB of candidate
+                               re-sized to fit; default: what 32 GiB of candidate
                                scratch allows, at most 4096                          */
     TC_OPT_TILE_IDS = 3,    /* ids per LDS counting tile: a multiple of 1024 whose
                                packed counts (4 bits per id when Ns <= 15, else 8)
@@ -71,9 +71,21 @@ enum tc_option {
                                counts (131072 ids as nibbles, 65536 as bytes)        */
     TC_OPT_PROFILE = 4,     /* 1: time every kernel launch with HIP events on the
                                search stream (read with tc_kernel_time); 0: off      */
-    TC_OPT_SCRATCH_BYTES = 5 /* candidate-scratch budget in bytes used to pick the
-                               batch size (>= 8*n); default 16 GiB                   */
+    TC_OPT_SCRATCH_BYTES = 5, /* candidate-scratch budget in bytes used to pick the
+                               batch size (>= 8*n); default 32 GiB                   */
+    TC_OPT_PRECISION = 6    /* tc_precision of the re-rank; default TC_FP32         */
 };
+
+/* Arithmetic of the re-rank step.
+ *   TC_FP32: FP32 squared distances from the FP32 base rows.
+ *   TC_BF16: the rows are read as BF16 copies centred at the mean rounded to
+ *            BF16 (built on first use), giving each candidate an interval
+ *            that provably contains its TC_FP32 distance; the candidates
+ *            whose interval reaches the k-th smallest upper bound are then
+ *            recomputed with the TC_FP32 arithmetic.  Results (ids and
+ *            distances) are identical to TC_FP32; fewer bytes are read.
+ *            Not a precision form of the paper, which states none. */
+enum tc_precision { TC_FP32 = 0, TC_BF16 = 1 };
 
 /*
  * Load an index file onto GPU `device` and build its derived device tables.
@@ -140,7 +152,9 @@ typedef struct tc_stage_dump {
     int32_t *last;      /* [nq]             last_collision threshold                 */
     int64_t *ncand;     /* [nq]             number of candidates |C|                 */
     int32_t *cand;      /* [nq][n]          candidate ids (first ncand, any order)   */
-    float *cand_dist;   /* [nq][n]          their distances, aligned with cand       */
+    float *cand_dist;   /* [nq][n]          their distances, aligned with cand
+                                            (TC_FP32 re-rank only)                  */
+    int64_t *nrecheck;  /* [nq]             rows re-checked in FP32 (TC_BF16 only)   */
 } tc_stage_dump;
 
 /* tc_search that also writes the stages requested in `dump` (host pointer to
@@ -152,7 +166,7 @@ int tc_search_debug(tc_index *index, const float *queries, int64_t nq, int32_t k
 /*
  * Kernel timing, recorded while TC_OPT_PROFILE is 1.  Waits for the recorded
  * events, then reports for `kernel` -- one of "transform", "probe", "count",
- * "select", "rerank", "topk" -- the summed duration in milliseconds and the
+ * "select", "rerank", "topk", "recheck" -- the summed duration in milliseconds and the
  * number of launches since the last tc_profile_reset.  Host outputs.
  */
 int tc_kernel_time(tc_index *index, const char *kernel, double *total_ms, int64_t *launches);

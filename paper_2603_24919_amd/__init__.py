@@ -16,7 +16,8 @@ from typing import Dict, Optional, Tuple
 __all__ = [
     "TC_OK", "TC_EINVAL", "TC_EIO", "TC_EFORMAT", "TC_ENOMEM", "TC_EDEVICE",
     "TC_RULE_PRINTED", "TC_RULE_PROSE", "TC_OPT_SELECT_RULE", "TC_OPT_MAX_BATCH",
-    "TC_OPT_TILE_IDS", "TC_OPT_PROFILE", "TC_OPT_SCRATCH_BYTES", "KERNELS",
+    "TC_OPT_TILE_IDS", "TC_OPT_PROFILE", "TC_OPT_SCRATCH_BYTES", "TC_OPT_PRECISION",
+    "TC_FP32", "TC_BF16", "KERNELS",
     "TacoError", "TacoLibraryMissing", "lib_path", "load_library",
     "tc_load_index", "tc_free_index", "tc_index_info", "tc_set_option", "tc_search",
     "tc_search_debug", "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity",
@@ -26,7 +27,9 @@ __all__ = [
 TC_OK, TC_EINVAL, TC_EIO, TC_EFORMAT, TC_ENOMEM, TC_EDEVICE = 0, -1, -2, -3, -4, -5
 TC_RULE_PRINTED, TC_RULE_PROSE = 0, 1
 TC_OPT_SELECT_RULE, TC_OPT_MAX_BATCH, TC_OPT_TILE_IDS, TC_OPT_PROFILE, TC_OPT_SCRATCH_BYTES = 1, 2, 3, 4, 5
-KERNELS = ("transform", "probe", "count", "select", "rerank", "topk")
+TC_OPT_PRECISION = 6
+TC_FP32, TC_BF16 = 0, 1
+KERNELS = ("transform", "probe", "count", "select", "rerank", "topk", "recheck")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libtaco_hip.so"
@@ -45,7 +48,7 @@ class TacoLibraryMissing(ImportError):
 class _StageDump(C.Structure):
     _fields_ = [(f, C.c_void_p) for f in (
         "qt", "cdist", "corder", "cells", "ncells", "retrieved", "sc", "hist", "last",
-        "ncand", "cand", "cand_dist")]
+        "ncand", "cand", "cand_dist", "nrecheck")]
 
 
 DUMP_FIELDS = tuple(f for f, _ in _StageDump._fields_)
@@ -237,7 +240,7 @@ class Index:
             retrieved=((nq, self.Ns), torch.int64), sc=((nq, self.n), torch.uint8),
             hist=((nq, self.Ns + 1), torch.int64), last=((nq,), torch.int32),
             ncand=((nq,), torch.int64), cand=((nq, self.n), torch.int32),
-            cand_dist=((nq, self.n), torch.float32))
+            cand_dist=((nq, self.n), torch.float32), nrecheck=((nq,), torch.int64))
         return {f: torch.empty(shapes[f][0], dtype=shapes[f][1], device=dev) for f in fields}
 
     def kernel_time(self, kernel: str):

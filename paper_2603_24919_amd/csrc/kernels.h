@@ -46,6 +46,15 @@ int rerank_lanes_per_row(int d);
 hipError_t launch_rerank(const float *Q, int nq, int d, const float *base, const int32_t *cand,
                          const uint32_t *cand_count, int64_t cap, float *cand_dist, int blocks_per_q,
                          hipStream_t st);
+hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const uint16_t *base16,
+                           const float *rowerr, const int32_t *cand, const uint32_t *cand_count,
+                           int64_t cap, float *ub, float *lb, int blocks_per_q, hipStream_t st);
+hipError_t launch_recheck(const float *Q, int nq, int d, const float *base, const int32_t *cand,
+                          const uint32_t *cand_count, const float *lb, int64_t cap,
+                          const float *tau_d, int k, int32_t *rk_ids, float *rk_dist,
+                          uint32_t *rk_count, int blocks_per_q, hipStream_t st);
+hipError_t launch_prep_bf16(const float *base, int64_t n, int d, const float *mu, uint16_t *base16,
+                            float *rowerr, hipStream_t st);
 hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32_t *cand_count,
                        int64_t cap, int nq, int k, int64_t *ids, float *dists, hipStream_t st);
 

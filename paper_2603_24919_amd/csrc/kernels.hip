@@ -595,8 +595,44 @@ __global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int
 // ---------------------------------------------------------------------------
 // re-rank: squared L2 distance of each candidate row to its query, FP32.
 // LPR lanes cooperate on a row with 16-byte loads; the query sits in LDS.
-// grid (G, nq), block 256, dynamic LDS d floats.
+// The per-lane partial sums and the xor tree inside each LPR-lane group are
+// shared with k_recheck, so a row's FP32 distance is the same bits wherever
+// it is computed.  grid (G, nq), block 256, dynamic LDS d floats.
 // ---------------------------------------------------------------------------
+
+template <int LPR, bool VEC4>
+__device__ __forceinline__ float row_partial32(const float *qs, const float *row, int d, int li) {
+    float acc = 0.0f;
+    if (VEC4) {
+        const float4 *r4 = reinterpret_cast<const float4 *>(row);
+        const float4 *q4 = reinterpret_cast<const float4 *>(qs);
+        for (int f = li; f < d / 4; f += LPR) {
+            const float4 xv = r4[f], qv = q4[f];
+            float u = qv.x - xv.x;
+            acc = fmaf(u, u, acc);
+            u = qv.y - xv.y;
+            acc = fmaf(u, u, acc);
+            u = qv.z - xv.z;
+            acc = fmaf(u, u, acc);
+            u = qv.w - xv.w;
+            acc = fmaf(u, u, acc);
+        }
+    } else {
+        for (int f = li; f < d; f += LPR) {
+            const float u = qs[f] - row[f];
+            acc = fmaf(u, u, acc);
+        }
+    }
+    return acc;
+}
+
+// Sum over the LPR lanes of a row group; every lane of the group must call.
+template <int LPR>
+__device__ __forceinline__ float group_sum(float acc) {
+#pragma unroll
+    for (int m = LPR / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, WAVE);
+    return acc;
+}
 
 template <int LPR, bool VEC4>
 __global__ __launch_bounds__(256) void k_rerank(const float *__restrict__ Q, int d,
@@ -619,34 +655,191 @@ __global__ __launch_bounds__(256) void k_rerank(const float *__restrict__ Q, int
          i0 += stride) {
         const int64_t i = i0 + sub;
         float acc = 0.0f;
+        if (i < nc) acc = row_partial32<LPR, VEC4>(qs, base + static_cast<int64_t>(cq[i]) * d, d, li);
+        acc = group_sum<LPR>(acc);
+        if (li == 0 && i < nc) dq[i] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 re-rank with an exact FP32 boundary re-check.
+//
+// The library keeps xb = bf16(fl32(x - mu)) for every base row, mu being the
+// mean rounded to BF16 (so integer-valued data stay exact), and e(x) = the
+// FP64 norm of xb - (x - mu), rounded up.  With qc = fl32(q - mu) and
+// u~ = fl32(qc - xb), the exact difference u = q - x satisfies
+//   ||u~ - u|| <= E = e(x) + 2^-24 (||q - mu|| + ||u~||)   (two FP32 roundings),
+// and the FP32 sums of d squares (this kernel's and the FP32 path's) are
+// within a relative 2(d+2)2^-24 of their exact values.  So the FP32 path's
+// distance d32 of the row lies in [lb, ub] with
+//   s = sqrt(d~),  ub = (s(1+g) + E)^2 (1+g),  lb = max(0, s(1-g) - E)^2 (1-g),
+// g = 2(d+2)2^-24 + 2^-18: the extra 2^-18 covers the few FP32 roundings of
+// evaluating these bounds (each <= 2^-24 relative, sqrt within 2 ulp).  If
+// tau is the k-th smallest ub, every row of the FP32 path's top-k has
+// lb <= tau; k_recheck recomputes exactly those rows with the FP32 path's
+// own arithmetic.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+
+__device__ __forceinline__ float f32_round_up(double v) {
+    float f = static_cast<float>(v);
+    if (static_cast<double>(f) < v) f = nextafterf(f, __uint_as_float(0x7f800000u));
+    return f;
+}
+
+
+template <int LPR, bool VEC8>
+__global__ __launch_bounds__(256) void k_rerank16(const float *__restrict__ Q, int d,
+                                                  const float *__restrict__ mu,
+                                                  const uint16_t *__restrict__ base16,
+                                                  const float *__restrict__ rowerr,
+                                                  const int32_t *__restrict__ cand,
+                                                  const uint32_t *__restrict__ cand_count,
+                                                  int64_t cap, float *__restrict__ ub_out,
+                                                  float *__restrict__ lb_out) {
+    extern __shared__ float qs[];
+    __shared__ float rq_part[WAVES];
+    const int q = blockIdx.y;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    float sq = 0.0f;
+    for (int t = threadIdx.x; t < d; t += BLOCK) {
+        const float v = Q[static_cast<int64_t>(q) * d + t] - mu[t];
+        qs[t] = v;
+        sq = fmaf(v, v, sq);
+    }
+#pragma unroll
+    for (int m = WAVE / 2; m > 0; m >>= 1) sq += __shfl_xor(sq, m, WAVE);
+    if (lane == 0) rq_part[wave] = sq;
+    __syncthreads();
+    float rq2 = 0.0f;
+    for (int w = 0; w < WAVES; w++) rq2 += rq_part[w];
+    // ||q - mu||, inflated for the FP32 roundings of q - mu and of the sum
+    const float rq = sqrtf(rq2) * (1.0f + (d + 8) * 0x1p-23f);
+    const int64_t nc = cand_count[q];
+    constexpr int RPW = WAVE / LPR;
+    const int sub = lane / LPR, li = lane % LPR;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVES * RPW;
+    const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
+    const float g = 2.0f * (d + 2) * 0x1p-24f + 0x1p-18f;
+    for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * RPW; i0 < nc;
+         i0 += stride) {
+        const int64_t i = i0 + sub;
+        float acc = 0.0f;
+        int64_t id = 0;
         if (i < nc) {
-            const int64_t id = cq[i];
-            const float *row = base + id * d;
-            if (VEC4) {
-                const float4 *r4 = reinterpret_cast<const float4 *>(row);
-                const float4 *q4 = reinterpret_cast<const float4 *>(qs);
-                for (int f = li; f < d / 4; f += LPR) {
-                    const float4 xv = r4[f], qv = q4[f];
-                    float u = qv.x - xv.x;
-                    acc = fmaf(u, u, acc);
-                    u = qv.y - xv.y;
-                    acc = fmaf(u, u, acc);
-                    u = qv.z - xv.z;
-                    acc = fmaf(u, u, acc);
-                    u = qv.w - xv.w;
-                    acc = fmaf(u, u, acc);
+            id = cq[i];
+            const uint16_t *row = base16 + id * d;
+            if (VEC8) {
+                const uint4 *r8 = reinterpret_cast<const uint4 *>(row);
+                for (int f = li; f < d / 8; f += LPR) {
+                    const uint4 v = r8[f];
+                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                    for (int c = 0; c < 4; c++) {
+                        float u = qs[8 * f + 2 * c] - bf16_bits_to_f32(w[c] & 0xffffu);
+                        acc = fmaf(u, u, acc);
+                        u = qs[8 * f + 2 * c + 1] - bf16_bits_to_f32(w[c] >> 16);
+                        acc = fmaf(u, u, acc);
+                    }
                 }
             } else {
                 for (int f = li; f < d; f += LPR) {
-                    const float u = qs[f] - row[f];
+                    const float u = qs[f] - bf16_bits_to_f32(row[f]);
                     acc = fmaf(u, u, acc);
                 }
             }
         }
-#pragma unroll
-        for (int m = LPR / 2; m > 0; m >>= 1) acc += __shfl_xor(acc, m, WAVE);
-        if (li == 0 && i < nc) dq[i] = acc;
+        acc = group_sum<LPR>(acc);
+        if (li == 0 && i < nc) {
+            const float s = sqrtf(acc > 0.0f ? acc : 0.0f);
+            const float su = s * (1.0f + g);
+            const float E = rowerr[id] + 0x1p-22f * (rq + su + 1.0f);
+            const float hs = su + E;
+            const float ls = s * (1.0f - g) - E;
+            ub_out[static_cast<int64_t>(q) * cap + i] = hs * hs * (1.0f + g);
+            lb_out[static_cast<int64_t>(q) * cap + i] = ls > 0.0f ? ls * ls * (1.0f - g) : 0.0f;
+        }
     }
+}
+
+// FP32 re-check of the rows whose lower bound reaches the query's tau (the
+// k-th smallest upper bound, from the top-k of the bounds).  Each lane tests
+// one candidate; the kept ones are compacted into LDS and then re-ranked by
+// row groups with the FP32 path's arithmetic.  Kept rows go to (rk_ids,
+// rk_dist).  grid (G, nq), block 256.
+constexpr int RC_CHUNK = 1024;
+
+template <int LPR, bool VEC4>
+__global__ __launch_bounds__(256) void k_recheck(const float *__restrict__ Q, int d,
+                                                 const float *__restrict__ base,
+                                                 const int32_t *__restrict__ cand,
+                                                 const uint32_t *__restrict__ cand_count,
+                                                 const float *__restrict__ lb, int64_t cap,
+                                                 const float *__restrict__ tau_d, int k,
+                                                 int32_t *__restrict__ rk_ids,
+                                                 float *__restrict__ rk_dist,
+                                                 uint32_t *__restrict__ rk_count) {
+    extern __shared__ float qs[];
+    __shared__ int32_t kept[RC_CHUNK];
+    __shared__ uint32_t nkept;
+    const int q = blockIdx.y;
+    for (int t = threadIdx.x; t < d; t += BLOCK) qs[t] = Q[static_cast<int64_t>(q) * d + t];
+    const int64_t nc = cand_count[q];
+    const float tau = tau_d[static_cast<int64_t>(q) * k + (k - 1)];  // +inf when |C| < k
+    constexpr int RPW = WAVE / LPR;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int sub = lane / LPR, li = lane % LPR;
+    const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
+    const float *lq = lb + static_cast<int64_t>(q) * cap;
+    for (int64_t c0 = static_cast<int64_t>(blockIdx.x) * RC_CHUNK; c0 < nc;
+         c0 += static_cast<int64_t>(gridDim.x) * RC_CHUNK) {
+        if (threadIdx.x == 0) nkept = 0u;
+        __syncthreads();
+        for (int j = threadIdx.x; j < RC_CHUNK; j += BLOCK) {
+            const int64_t i = c0 + j;
+            if (i < nc && lq[i] <= tau) kept[atomicAdd(&nkept, 1u)] = cq[i];
+        }
+        __syncthreads();
+        const int m = static_cast<int>(nkept);
+        for (int r0 = wave * RPW; r0 < m; r0 += WAVES * RPW) {
+            const int r = r0 + sub;
+            float acc = 0.0f;
+            if (r < m) acc = row_partial32<LPR, VEC4>(qs, base + static_cast<int64_t>(kept[r]) * d, d, li);
+            acc = group_sum<LPR>(acc);
+            if (r < m && li == 0) {
+                const uint32_t p = atomicAdd(&rk_count[q], 1u);
+                rk_ids[static_cast<int64_t>(q) * cap + p] = kept[r];
+                rk_dist[static_cast<int64_t>(q) * cap + p] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// BF16 copy of the base centred at mu, and each row's exact quantization
+// error norm (FP64, rounded up).  One wavefront per row.
+__global__ __launch_bounds__(256) void k_prep_bf16(const float *__restrict__ base, int64_t n, int d,
+                                                   const float *__restrict__ mu,
+                                                   uint16_t *__restrict__ base16,
+                                                   float *__restrict__ rowerr) {
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * WAVES + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (row >= n) return;
+    double e2 = 0.0;
+    for (int t = lane; t < d; t += WAVE) {
+        const float x = base[row * d + t];
+        const float c = x - mu[t];
+        const uint32_t b = __float_as_uint(c);
+        const uint32_t h = (b + 0x7fffu + ((b >> 16) & 1u)) >> 16;  // round to nearest even
+        base16[row * d + t] = static_cast<uint16_t>(h);
+        const double err = static_cast<double>(bf16_bits_to_f32(h)) -
+                           (static_cast<double>(x) - static_cast<double>(mu[t]));
+        e2 += err * err;
+    }
+#pragma unroll
+    for (int m = WAVE / 2; m > 0; m >>= 1) e2 += __shfl_xor(e2, m, WAVE);
+    if (lane == 0) rowerr[row] = f32_round_up(sqrt(e2) * (1.0 + 0x1p-50));
 }
 
 // ---------------------------------------------------------------------------
@@ -846,18 +1039,72 @@ hipError_t launch_rerank(const float *Q, int nq, int d, const float *base, const
                          hipStream_t st) {
     dim3 grid(blocks_per_q, nq);
     size_t lds = sizeof(float) * static_cast<size_t>(d);
-    const int lpr = rerank_lanes_per_row(d);
+#define TACO_RR(L, V) k_rerank<L, V><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist)
     if (d % 4 != 0) {
-        k_rerank<64, false><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist);
+        TACO_RR(64, false);
     } else {
-        switch (lpr) {
-        case 4: k_rerank<4, true><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist); break;
-        case 8: k_rerank<8, true><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist); break;
-        case 16: k_rerank<16, true><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist); break;
-        case 32: k_rerank<32, true><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist); break;
-        default: k_rerank<64, true><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, cap, cand_dist); break;
+        switch (rerank_lanes_per_row(d)) {
+        case 4: TACO_RR(4, true); break;
+        case 8: TACO_RR(8, true); break;
+        case 16: TACO_RR(16, true); break;
+        case 32: TACO_RR(32, true); break;
+        default: TACO_RR(64, true); break;
         }
     }
+#undef TACO_RR
+    return hipGetLastError();
+}
+
+hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const uint16_t *base16,
+                           const float *rowerr, const int32_t *cand, const uint32_t *cand_count,
+                           int64_t cap, float *ub, float *lb, int blocks_per_q, hipStream_t st) {
+    dim3 grid(blocks_per_q, nq);
+    size_t lds = sizeof(float) * static_cast<size_t>(d);
+#define TACO_RR16(L, V) \
+    k_rerank16<L, V><<<grid, BLOCK, lds, st>>>(Q, d, mu, base16, rowerr, cand, cand_count, cap, ub, lb)
+    if (d % 8 != 0) {
+        TACO_RR16(64, false);
+    } else {
+        // same lanes per row as the FP32 kernel, each lane reading 16 bytes = 8 values
+        switch (rerank_lanes_per_row(d) / 2 < 4 ? 4 : rerank_lanes_per_row(d) / 2) {
+        case 4: TACO_RR16(4, true); break;
+        case 8: TACO_RR16(8, true); break;
+        case 16: TACO_RR16(16, true); break;
+        default: TACO_RR16(32, true); break;
+        }
+    }
+#undef TACO_RR16
+    return hipGetLastError();
+}
+
+hipError_t launch_recheck(const float *Q, int nq, int d, const float *base, const int32_t *cand,
+                          const uint32_t *cand_count, const float *lb, int64_t cap,
+                          const float *tau_d, int k, int32_t *rk_ids, float *rk_dist,
+                          uint32_t *rk_count, int blocks_per_q, hipStream_t st) {
+    dim3 grid(blocks_per_q, nq);
+    size_t lds = sizeof(float) * static_cast<size_t>(d);
+#define TACO_RC(L, V)                                                                        \
+    k_recheck<L, V><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, lb, cap, tau_d, k, \
+                                              rk_ids, rk_dist, rk_count)
+    if (d % 4 != 0) {
+        TACO_RC(64, false);
+    } else {
+        switch (rerank_lanes_per_row(d)) {
+        case 4: TACO_RC(4, true); break;
+        case 8: TACO_RC(8, true); break;
+        case 16: TACO_RC(16, true); break;
+        case 32: TACO_RC(32, true); break;
+        default: TACO_RC(64, true); break;
+        }
+    }
+#undef TACO_RC
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_bf16(const float *base, int64_t n, int d, const float *mu, uint16_t *base16,
+                            float *rowerr, hipStream_t st) {
+    k_prep_bf16<<<static_cast<unsigned>((n + WAVES - 1) / WAVES), BLOCK, 0, st>>>(base, n, d, mu,
+                                                                                 base16, rowerr);
     return hipGetLastError();
 }
 

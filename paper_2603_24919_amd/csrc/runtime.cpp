@@ -62,8 +62,8 @@ struct Reader {
     }
 };
 
-const char *kKernelNames[] = {"transform", "probe", "count", "select", "rerank", "topk"};
-enum Kern { K_TRANSFORM = 0, K_PROBE, K_COUNT, K_SELECT, K_RERANK, K_TOPK, K_COUNT_ };
+const char *kKernelNames[] = {"transform", "probe", "count", "select", "rerank", "topk", "recheck"};
+enum Kern { K_TRANSFORM = 0, K_PROBE, K_COUNT, K_SELECT, K_RERANK, K_TOPK, K_RECHECK, K_COUNT_ };
 
 struct Timing {
     int kernel;
@@ -85,7 +85,7 @@ struct tc_index {
     // options
     int rule = TC_RULE_PRINTED;
     int64_t max_batch = 0;  // 0: automatic
-    int64_t scratch_budget = int64_t(16) << 30;
+    int64_t scratch_budget = int64_t(32) << 30;
     bool profile = false;
     // scratch for one batch of Qb queries
     int64_t Qb = 0;
@@ -96,6 +96,17 @@ struct tc_index {
     int32_t *cand = nullptr;
     float *cand_dist = nullptr;
     uint32_t *sc = nullptr;  // packed collision counts, [Qb][T*W bytes]
+    // BF16 re-rank form (built when first selected)
+    int precision = TC_FP32;
+    float *mu = nullptr;         // [d] mean rounded to BF16
+    uint16_t *base16 = nullptr;  // [n][d] bf16(x - mu)
+    float *rowerr = nullptr;     // [n] norm of each row's BF16 error, rounded up
+    float *lb = nullptr;         // [Qb][n] lower bounds of the FP32 distances
+    int32_t *rk_ids = nullptr;   // [Qb][n] re-checked candidates
+    uint32_t *rk_count = nullptr;
+    int64_t *tau_ids = nullptr;  // [Qb][1024] top-k of the upper bounds
+    float *tau_d = nullptr;
+    std::vector<float> mean_host;
     // profiling
     std::vector<Timing> pending;
     double total_ms[K_COUNT_] = {0};
@@ -114,7 +125,17 @@ void free_scratch(tc_index *x) {
     (void)hipFree(x->cand);
     (void)hipFree(x->cand_dist);
     (void)hipFree(x->sc);
+    (void)hipFree(x->lb);
+    (void)hipFree(x->rk_ids);
+    (void)hipFree(x->rk_count);
+    (void)hipFree(x->tau_ids);
+    (void)hipFree(x->tau_d);
     x->sc = nullptr;
+    x->lb = nullptr;
+    x->rk_ids = nullptr;
+    x->rk_count = nullptr;
+    x->tau_ids = nullptr;
+    x->tau_d = nullptr;
     x->qt = nullptr;
     x->cells = x->ncells = nullptr;
     x->retrieved = nullptr;
@@ -139,7 +160,8 @@ int dmalloc(T **p, size_t count, const char *what) {
 // Candidate slots are n per query (|C| can reach n), plus one byte of packed
 // count per id; the batch size follows from the scratch budget.
 int64_t batch_for(const tc_index *x) {
-    const int64_t per_q = 8 * x->n + int64_t(x->T) * x->W * x->bits / 8;
+    int64_t per_q = 8 * x->n + int64_t(x->T) * x->W * x->bits / 8;
+    if (x->precision == TC_BF16) per_q += 8 * x->n;
     int64_t qb = x->scratch_budget / per_q;
     int64_t cap = x->max_batch > 0 ? x->max_batch : 4096;
     if (qb > cap) qb = cap;
@@ -161,6 +183,13 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->cand_dist, size_t(qb) * x->n, "candidate distances"))) return rc;
     if ((rc = dmalloc(&x->sc, size_t(qb) * x->T * (size_t(x->W) * x->bits / 32), "packed counts")))
         return rc;
+    if (x->precision == TC_BF16) {
+        if ((rc = dmalloc(&x->lb, size_t(qb) * x->n, "distance lower bounds"))) return rc;
+        if ((rc = dmalloc(&x->rk_ids, size_t(qb) * x->n, "re-checked candidates"))) return rc;
+        if ((rc = dmalloc(&x->rk_count, size_t(qb), "re-check counts"))) return rc;
+        if ((rc = dmalloc(&x->tau_ids, size_t(qb) * 1024, "bound top-k ids"))) return rc;
+        if ((rc = dmalloc(&x->tau_d, size_t(qb) * 1024, "bound top-k"))) return rc;
+    }
     x->Qb = qb;
     return TC_OK;
 }
@@ -189,6 +218,9 @@ void free_all(tc_index *x) {
     (void)hipFree(x->offs);
     (void)hipFree(x->ids);
     (void)hipFree(x->off2d);
+    (void)hipFree(x->mu);
+    (void)hipFree(x->base16);
+    (void)hipFree(x->rowerr);
     for (auto &t : x->pending) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
@@ -215,6 +247,27 @@ struct DeviceGuard {
         if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
     }
 };
+
+// BF16 form of the base (once): mu = the mean rounded to BF16, then the
+// centred BF16 rows and their error norms on the device.
+int build_bf16(tc_index *x) {
+    if (x->base16) return TC_OK;
+    std::vector<float> mu(x->d);
+    for (int t = 0; t < x->d; t++) {
+        uint32_t b;
+        memcpy(&b, &x->mean_host[t], 4);
+        b = ((b + 0x7fffu + ((b >> 16) & 1u)) >> 16) << 16;
+        memcpy(&mu[t], &b, 4);
+    }
+    int rc;
+    if ((rc = upload(&x->mu, mu, "BF16 centre"))) return rc;
+    if ((rc = dmalloc(&x->base16, size_t(x->n) * x->d, "BF16 base"))) return rc;
+    if ((rc = dmalloc(&x->rowerr, size_t(x->n), "BF16 row errors"))) return rc;
+    TC_HIP(taco::launch_prep_bf16(x->base, x->n, x->d, x->mu, x->base16, x->rowerr, nullptr),
+           "building the BF16 base");
+    TC_HIP(hipDeviceSynchronize(), "building the BF16 base");
+    return TC_OK;
+}
 
 int load(const char *path, int device, tc_index *x) {
     Reader r;
@@ -288,6 +341,7 @@ int load(const char *path, int device, tc_index *x) {
     x->max_lds = static_cast<int>(prop.sharedMemPerBlock);
     int rc;
     if ((rc = upload(&x->mean, mean, "mean"))) return rc;
+    x->mean_host = mean;
     if ((rc = upload(&x->B, B, "transform"))) return rc;
     if ((rc = upload(&x->C1, C1, "half-1 centroids"))) return rc;
     if ((rc = upload(&x->C2, C2, "half-2 centroids"))) return rc;
@@ -385,17 +439,46 @@ int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, dou
         TC_HIP(taco::launch_select(cl, sl, x->sc, st), "select kernel");
         record(x, K_SELECT, st, false);
 
-        record(x, K_RERANK, st, true);
-        TC_HIP(taco::launch_rerank(Qb, nb, x->d, x->base, x->cand, x->cand_count, cap, x->cand_dist,
-                                   rr_blocks, st),
-               "rerank kernel");
-        record(x, K_RERANK, st, false);
+        if (x->precision == TC_BF16) {
+            // bounds from the BF16 rows, the k-th smallest upper bound, then
+            // the FP32 path's arithmetic on every row that can still make the top k
+            TC_HIP(taco::launch_fill_u32(x->rk_count, nb, 0u, st), "clearing re-check counts");
+            record(x, K_RERANK, st, true);
+            TC_HIP(taco::launch_rerank16(Qb, nb, x->d, x->mu, x->base16, x->rowerr, x->cand,
+                                         x->cand_count, cap, x->cand_dist, x->lb, rr_blocks, st),
+                   "BF16 rerank kernel");
+            record(x, K_RERANK, st, false);
+            record(x, K_TOPK, st, true);
+            TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, x->tau_ids,
+                                     x->tau_d, st),
+                   "bound top-k kernel");
+            record(x, K_TOPK, st, false);
+            record(x, K_RECHECK, st, true);
+            TC_HIP(taco::launch_recheck(Qb, nb, x->d, x->base, x->cand, x->cand_count, x->lb, cap,
+                                        x->tau_d, k, x->rk_ids, x->cand_dist, x->rk_count,
+                                        rr_blocks, st),
+                   "re-check kernel");
+            record(x, K_RECHECK, st, false);
+            record(x, K_TOPK, st, true);
+            TC_HIP(taco::launch_topk(x->rk_ids, x->cand_dist, x->rk_count, cap, nb, k, ids + b0 * k,
+                                     dists + b0 * k, st),
+                   "top-k kernel");
+            record(x, K_TOPK, st, false);
+            if (dump && dump->nrecheck)
+                TC_HIP(taco::launch_u32_to_i64(x->rk_count, dump->nrecheck + b0, nb, st), "dump nrecheck");
+        } else {
+            record(x, K_RERANK, st, true);
+            TC_HIP(taco::launch_rerank(Qb, nb, x->d, x->base, x->cand, x->cand_count, cap,
+                                       x->cand_dist, rr_blocks, st),
+                   "rerank kernel");
+            record(x, K_RERANK, st, false);
 
-        record(x, K_TOPK, st, true);
-        TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, ids + b0 * k,
-                                 dists + b0 * k, st),
-               "top-k kernel");
-        record(x, K_TOPK, st, false);
+            record(x, K_TOPK, st, true);
+            TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, ids + b0 * k,
+                                     dists + b0 * k, st),
+                   "top-k kernel");
+            record(x, K_TOPK, st, false);
+        }
 
         if (dump) {
             const hipMemcpyKind dd = hipMemcpyDeviceToDevice;
@@ -415,7 +498,7 @@ int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, dou
             if (dump->cand)
                 TC_HIP(hipMemcpyAsync(dump->cand + b0 * x->n, x->cand, sizeof(int32_t) * size_t(nb) * x->n, dd, st),
                        "dump cand");
-            if (dump->cand_dist)
+            if (dump->cand_dist && x->precision == TC_FP32)
                 TC_HIP(hipMemcpyAsync(dump->cand_dist + b0 * x->n, x->cand_dist,
                                       sizeof(float) * size_t(nb) * x->n, dd, st), "dump cand_dist");
         }
@@ -493,6 +576,15 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
         x->W = static_cast<int>(value);
         if (int rc = build_tiles(x)) return rc;
         return alloc_scratch(x);
+    case TC_OPT_PRECISION: {
+        if (value != TC_FP32 && value != TC_BF16) return fail(TC_EINVAL, "precision must be TC_FP32 or TC_BF16");
+        TC_HIP(hipDeviceSynchronize(), "synchronizing before re-sizing scratch");
+        if (value == TC_BF16) {
+            if (int rc = build_bf16(x)) return rc;
+        }
+        x->precision = static_cast<int>(value);
+        return alloc_scratch(x);
+    }
     case TC_OPT_PROFILE:
         if (value != 0 && value != 1) return fail(TC_EINVAL, "profile must be 0 or 1");
         x->profile = value != 0;

@@ -168,3 +168,29 @@ def test_bench_workload_full_size_sampled(taco_mod):
         for i, qi in enumerate(sample[:4]):
             compare_query(gs, i, oidx.query(Q[qi], alpha, w.beta, w.k), w.Ns, w.k, f"{w.name} a={alpha}")
     idx.close()
+
+
+def _bf16_cases():
+    W = synthdata.WORKLOADS
+    return [W["tiny-gmm-20k-d128"]] + scaled_workloads()
+
+
+@pytest.mark.parametrize("w", _bf16_cases(), ids=lambda w: w.name)
+def test_bf16_rerank_equals_fp32(taco_mod, w):
+    """The BF16 re-rank with its FP32 boundary re-check returns exactly the
+    FP32 path's ids and distances (bit for bit), re-checking few rows."""
+    t = taco_mod
+    X, Q = synthdata.base_and_queries(w)
+    path = workload_index(w, X)
+    print(f"[{w.name}] bf16 vs fp32", flush=True)
+    for k, alpha, beta in ((10, 0.05, 0.005), (1, 0.02, 0.01), (100, 0.01, 0.02)):
+        idx = t.Index(path, 0)
+        g32 = gpu_search(idx, Q, k, alpha, beta, ("ncand",))
+        idx.set_option(t.TC_OPT_PRECISION, t.TC_BF16)
+        g16 = gpu_search(idx, Q, k, alpha, beta, ("ncand", "nrecheck"))
+        idx.close()
+        assert np.array_equal(g16["ids"], g32["ids"]), (w.name, k)
+        assert np.array_equal(g16["dists"].view(np.uint32), g32["dists"].view(np.uint32)), (w.name, k)
+        nr, nc = g16["nrecheck"], g16["ncand"]
+        assert np.all(nr >= np.minimum(k, nc)) and np.all(nr <= nc)
+        print(f"[{w.name}] k={k}: re-checked {nr.mean():.1f} of {nc.mean():.0f} candidates", flush=True)
