@@ -73,8 +73,21 @@ enum tc_option {
                                search stream (read with tc_kernel_time); 0: off      */
     TC_OPT_SCRATCH_BYTES = 5, /* candidate-scratch budget in bytes used to pick the
                                batch size (>= 8*n); default 32 GiB                   */
-    TC_OPT_PRECISION = 6    /* tc_precision of the re-rank; default TC_FP32         */
+    TC_OPT_PRECISION = 6,   /* tc_precision of the re-rank; default TC_FP32         */
+    TC_OPT_COUNT_MODE = 7   /* tc_count_mode; default TC_COUNT_AUTO                  */
 };
+
+/* How collision counting and candidate selection are launched.
+ *   TC_COUNT_SPLIT: one launch counts (LDS tiles, level histogram, packed
+ *                   counts to HBM), a second one selects from the counts.
+ *   TC_COUNT_FUSED: one cooperative, persistent launch; the workgroups of a
+ *                   query's tiles wait for each other's histogram and
+ *                   select straight from LDS.  Needs all tiles of a query
+ *                   resident at once (n up to ~64 Mi ids on MI355X).
+ *   TC_COUNT_AUTO:  the split launches (measured faster on MI355X for
+ *                   uniform budgets).
+ * Results are identical. */
+enum tc_count_mode { TC_COUNT_AUTO = 0, TC_COUNT_SPLIT = 1, TC_COUNT_FUSED = 2 };
 
 /* Arithmetic of the re-rank step.
  *   TC_FP32: FP32 squared distances from the FP32 base rows.
@@ -166,13 +179,19 @@ int tc_search_debug(tc_index *index, const float *queries, int64_t nq, int32_t k
 /*
  * Kernel timing, recorded while TC_OPT_PROFILE is 1.  Waits for the recorded
  * events, then reports for `kernel` -- one of "transform", "probe", "count",
- * "select", "rerank", "topk", "recheck" -- the summed duration in milliseconds and the
+ * "select", "rerank", "topk", "recheck", "count_select" -- the summed duration in milliseconds and the
  * number of launches since the last tc_profile_reset.  Host outputs.
  */
 int tc_kernel_time(tc_index *index, const char *kernel, double *total_ms, int64_t *launches);
 
 /* Forget recorded kernel timings. */
 int tc_profile_reset(tc_index *index);
+
+/* Synchronizes the index's device and returns, then clears, its device error
+ * word (host out): bit 0 is set if a workgroup of the fused count/select
+ * kernel gave up waiting for the other tiles of its query (results of that
+ * search are then invalid).  Used by the tests; 0 in normal operation. */
+int tc_device_errors(tc_index *index, uint32_t *flags);
 
 /* Queries processed per internal batch with the current options (host out). */
 int tc_batch_capacity(const tc_index *index, int64_t *queries_per_batch);

@@ -17,7 +17,8 @@ __all__ = [
     "TC_OK", "TC_EINVAL", "TC_EIO", "TC_EFORMAT", "TC_ENOMEM", "TC_EDEVICE",
     "TC_RULE_PRINTED", "TC_RULE_PROSE", "TC_OPT_SELECT_RULE", "TC_OPT_MAX_BATCH",
     "TC_OPT_TILE_IDS", "TC_OPT_PROFILE", "TC_OPT_SCRATCH_BYTES", "TC_OPT_PRECISION",
-    "TC_FP32", "TC_BF16", "KERNELS",
+    "TC_FP32", "TC_BF16", "TC_OPT_COUNT_MODE", "TC_COUNT_AUTO", "TC_COUNT_SPLIT",
+    "TC_COUNT_FUSED", "KERNELS", "tc_device_errors",
     "TacoError", "TacoLibraryMissing", "lib_path", "load_library",
     "tc_load_index", "tc_free_index", "tc_index_info", "tc_set_option", "tc_search",
     "tc_search_debug", "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity",
@@ -29,7 +30,9 @@ TC_RULE_PRINTED, TC_RULE_PROSE = 0, 1
 TC_OPT_SELECT_RULE, TC_OPT_MAX_BATCH, TC_OPT_TILE_IDS, TC_OPT_PROFILE, TC_OPT_SCRATCH_BYTES = 1, 2, 3, 4, 5
 TC_OPT_PRECISION = 6
 TC_FP32, TC_BF16 = 0, 1
-KERNELS = ("transform", "probe", "count", "select", "rerank", "topk", "recheck")
+TC_OPT_COUNT_MODE = 7
+TC_COUNT_AUTO, TC_COUNT_SPLIT, TC_COUNT_FUSED = 0, 1, 2
+KERNELS = ("transform", "probe", "count", "select", "rerank", "topk", "recheck", "count_select")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libtaco_hip.so"
@@ -83,10 +86,11 @@ def load_library():
     L.tc_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
     L.tc_profile_reset.argtypes = [vp]
     L.tc_batch_capacity.argtypes = [vp, C.POINTER(i64)]
+    L.tc_device_errors.argtypes = [vp, C.POINTER(C.c_uint32)]
     L.tc_last_error.restype = C.c_char_p
     L.tc_last_error.argtypes = []
     for f in ("tc_load_index", "tc_index_info", "tc_set_option", "tc_search", "tc_search_debug",
-              "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity"):
+              "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity", "tc_device_errors"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -193,6 +197,12 @@ def tc_profile_reset(index) -> None:
     _check(load_library().tc_profile_reset(index))
 
 
+def tc_device_errors(index) -> int:
+    v = C.c_uint32()
+    _check(load_library().tc_device_errors(index, C.byref(v)))
+    return v.value
+
+
 def tc_batch_capacity(index) -> int:
     v = C.c_int64()
     _check(load_library().tc_batch_capacity(index, C.byref(v)))
@@ -251,3 +261,6 @@ class Index:
 
     def batch_capacity(self) -> int:
         return tc_batch_capacity(self.handle)
+
+    def device_errors(self) -> int:
+        return tc_device_errors(self.handle)

@@ -42,6 +42,10 @@ size_t count_lds_bytes(int W, int bits);
 hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, hipStream_t st);
 hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
                          hipStream_t st);
+size_t fused_lds_bytes(int W, int bits);
+hipError_t fused_max_blocks(int W, int bits, int *blocks_per_cu);
+hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int NG, uint32_t *arrive,
+                               uint32_t *err, uint32_t spin_limit, hipStream_t st);
 int rerank_lanes_per_row(int d);
 hipError_t launch_rerank(const float *Q, int nq, int d, const float *base, const int32_t *cand,
                          const uint32_t *cand_count, int64_t cap, float *cand_dist, int blocks_per_q,

@@ -415,6 +415,37 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L) 
     }
 }
 
+// Level histogram of a tile's packed counts, added into hsum[1..16] as
+// "ids with count >= v".  Each thread keeps two levels per register (16-bit
+// halves: a thread sees at most W/CT_BLOCK <= 1024 ids of a tile).  The
+// per-word level loop stops at the first level no lane of the wavefront reaches.
+template <int BITS>
+__device__ __forceinline__ void tile_ge_counts(const uint32_t *cnt, int words, uint32_t *hsum) {
+    uint32_t ge2[8];
+#pragma unroll
+    for (int v = 0; v < 8; v++) ge2[v] = 0u;
+    for (int i0 = 0; i0 < words; i0 += CT_BLOCK) {
+        const int i = i0 + threadIdx.x;
+        const uint32_t w = i < words ? cnt[i] : 0u;
+#pragma unroll
+        for (int v = 1; v <= 16; v++) {
+            uint32_t m0, m1;
+            ge_masks<BITS>(w, static_cast<uint32_t>(v), m0, m1);
+            if (!__any((m0 | m1) != 0u)) break;
+            ge2[(v - 1) / 2] += static_cast<uint32_t>(__popc(m0) + __popc(m1)) << (16 * ((v - 1) & 1));
+        }
+    }
+    const int lane = threadIdx.x % WAVE;
+#pragma unroll
+    for (int v = 0; v < 8; v++) {
+        const uint32_t lo = wave_sum_u32(ge2[v] & 0xffffu), hi = wave_sum_u32(ge2[v] >> 16);
+        if (lane == 0) {
+            if (lo) atomicAdd(&hsum[2 * v + 1], lo);
+            if (hi) atomicAdd(&hsum[2 * v + 2], hi);
+        }
+    }
+}
+
 // grid (T, nq), block CT_BLOCK, dynamic LDS count_lds_size(W, BITS).  Adds
 // the tile's level counts to hist[q] and stores the packed counts to
 // sc[q][t] (W*BITS/8 bytes).
@@ -428,30 +459,9 @@ __global__ __launch_bounds__(CT_BLOCK) void k_count(CountArgs a, uint32_t *__res
     if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
     count_tile<BITS>(a, q, t, L);
 
-    // Level histogram of the tile: ge[v] counts the ids with count >= v, so
-    // level v holds ge[v] - ge[v+1].  Ids past n hold 0 and count nowhere.
-    // The per-word loop stops at the first level no lane reaches.
-    const int words = a.W / (32 / BITS);
-    uint32_t ge[17];
-#pragma unroll
-    for (int v = 0; v < 17; v++) ge[v] = 0u;
-    for (int i0 = 0; i0 < words; i0 += CT_BLOCK) {
-        const int i = i0 + threadIdx.x;
-        const uint32_t w = i < words ? L.cnt[i] : 0u;
-#pragma unroll
-        for (int v = 1; v <= 16; v++) {
-            uint32_t m0, m1;
-            ge_masks<BITS>(w, static_cast<uint32_t>(v), m0, m1);
-            if (!__any((m0 | m1) != 0u)) break;
-            ge[v] += __popc(m0) + __popc(m1);
-        }
-    }
-    const int lane = threadIdx.x % WAVE;
-#pragma unroll
-    for (int v = 1; v <= 16; v++) {
-        const uint32_t sv = wave_sum_u32(ge[v]);
-        if (lane == 0 && sv) atomicAdd(&hsum[v], sv);
-    }
+    // Level histogram of the tile: hsum[v] = ids with count >= v, so level v
+    // holds hsum[v] - hsum[v+1].  Ids past n hold 0 and count nowhere.
+    tile_ge_counts<BITS>(L.cnt, a.W / (32 / BITS), hsum);
     __syncthreads();
     if (threadIdx.x >= 1 && threadIdx.x <= a.Ns) {
         const uint32_t hv = hsum[threadIdx.x] - hsum[threadIdx.x + 1];
@@ -590,6 +600,124 @@ __global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int
         }
     }
     if (__any(scount != 0u)) flush_stage(stage, scount, counter, cq, lane);
+}
+
+// ---------------------------------------------------------------------------
+// count + select fused in one cooperative, persistent launch.  The grid is
+// exactly as large as the GPU can hold at once (cooperative launch), split
+// into NG groups of T workgroups; workgroup t of group g serves tile t of
+// queries g, g + NG, ...  After counting its tile and adding the tile's level
+// counts to hist[q], a workgroup arrives on arrive[q] and waits until all T
+// tiles of q have arrived.  Every member of a group is resident and works
+// through the same queries in the same order, so the wait ends; it is also
+// bounded (spin_limit polls), setting *err and going on if ever exceeded.
+// Then the threshold comes from the complete histogram and candidates are
+// compacted straight from LDS: no packed counts go to HBM.
+// ---------------------------------------------------------------------------
+
+struct FuseArgs {
+    int nq, NG;
+    uint32_t *hist;       // [nq][Ns+1], zero before the launch
+    uint32_t *arrive;     // [nq], zero before the launch
+    uint32_t *err;        // set to 1 if a wait timed out
+    uint32_t spin_limit;
+};
+
+template <int BITS>
+__global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, SelectArgs sa, FuseArgs f) {
+    constexpr int PER_WORD = 32 / BITS;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const CountLds L = carve<BITS>(lds_raw, a.W);
+    __shared__ uint32_t hsum[18];
+    __shared__ uint32_t hq[17];
+    __shared__ int s_last;
+    // candidate staging reuses the slice table (idle during compaction):
+    // CT_FSTAGE slots per wavefront
+    constexpr int CT_FSTAGE = CT_CHUNK * 12 / 4 / (CT_BLOCK / WAVE) >= 128 ? 128 : 64;
+    static_assert(CT_FSTAGE * (CT_BLOCK / WAVE) * 4 <= CT_CHUNK * 12, "staging must fit the slice table");
+    const int t = blockIdx.x % a.T, g = blockIdx.x / a.T;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int words = a.W / PER_WORD;
+    const int64_t tile_lo = static_cast<int64_t>(t) * a.W;
+    const int tile_n = static_cast<int>(min<int64_t>(a.W, a.n - tile_lo));
+    for (int q = g; q < f.nq; q += f.NG) {
+        if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
+        count_tile<BITS>(a, q, t, L);
+        tile_ge_counts<BITS>(L.cnt, words, hsum);
+        __syncthreads();
+        uint32_t *hg = f.hist + static_cast<int64_t>(q) * (a.Ns + 1);
+        if (threadIdx.x >= 1 && threadIdx.x <= a.Ns) {
+            const uint32_t hv = hsum[threadIdx.x] - hsum[threadIdx.x + 1];
+            if (hv) atomicAdd(&hg[threadIdx.x], hv);
+            __threadfence();
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(&f.arrive[q], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            uint32_t polls = 0;
+            while (__hip_atomic_load(&f.arrive[q], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <
+                   static_cast<uint32_t>(a.T)) {
+                if (++polls > f.spin_limit) {
+                    atomicOr(f.err, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            for (int v = 1; v <= a.Ns; v++)
+                hq[v] = __hip_atomic_load(&hg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_last = select_threshold(hq, a.Ns, a.n, sa.R, sa.rule);
+            if (t == 0) {
+                if (sa.dump_last) sa.dump_last[q] = s_last;
+                if (sa.dump_hist) {
+                    int64_t above0 = 0;
+                    for (int v = 1; v <= a.Ns; v++) above0 += hq[v];
+                    sa.dump_hist[static_cast<int64_t>(q) * (a.Ns + 1)] = a.n - above0;
+                    for (int v = 1; v <= a.Ns; v++)
+                        sa.dump_hist[static_cast<int64_t>(q) * (a.Ns + 1) + v] = hq[v];
+                }
+            }
+        }
+        __syncthreads();
+        const int last = s_last;
+        const uint32_t lv = static_cast<uint32_t>(last > 0 ? last : 0);
+        int32_t *cq = sa.cand + static_cast<int64_t>(q) * sa.cap;
+        uint32_t *stage = reinterpret_cast<uint32_t *>(L.st) + wave * CT_FSTAGE;
+        uint32_t scount = 0;
+        for (int i0 = 0; i0 < words; i0 += CT_BLOCK) {
+            const int i = i0 + threadIdx.x;
+            const bool in = i < words;
+            const uint32_t w = in ? L.cnt[i] : 0u;
+            if (sa.dump_sc && in) {
+                for (int b = 0; b < PER_WORD; b++) {
+                    const int loc = i * PER_WORD + b;
+                    if (loc < tile_n)
+                        sa.dump_sc[static_cast<int64_t>(q) * a.n + tile_lo + loc] =
+                            static_cast<uint8_t>((w >> (BITS * b)) & ((1u << BITS) - 1u));
+                }
+            }
+            uint32_t m[2];
+            ge_masks<BITS>(w, lv, m[0], m[1]);
+            if (!in) m[0] = m[1] = 0u;
+            if (!__any((m[0] | m[1]) != 0u)) continue;
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+#pragma unroll
+                for (int hh = 0; hh < (BITS == 4 ? 2 : 1); hh++) {
+                    const int loc = i * PER_WORD + (BITS == 8 ? b : 2 * b + hh);
+                    const bool flag = ((m[hh] >> (8 * b + 7)) & 1u) && loc < tile_n;
+                    const uint64_t mask = __ballot(flag);
+                    if (mask == 0ull) continue;
+                    if (scount > CT_FSTAGE - WAVE) flush_stage(stage, scount, sa.cand_count + q, cq, lane);
+                    if (flag)
+                        stage[scount + __popcll(mask & lanes_below(lane))] =
+                            static_cast<uint32_t>(tile_lo + loc);
+                    scount += static_cast<uint32_t>(__popcll(mask));
+                }
+            }
+        }
+        if (__any(scount != 0u)) flush_stage(stage, scount, sa.cand_count + q, cq, lane);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1025,6 +1153,32 @@ hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint
     else
         k_select<8><<<grid, SEL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words4, s4);
     return hipGetLastError();
+}
+
+size_t fused_lds_bytes(int W, int bits) {
+    return count_lds_size(W, bits) + (18 + 17 + 1) * sizeof(uint32_t);
+}
+
+hipError_t fused_max_blocks(int W, int bits, int *blocks_per_cu) {
+    const int bytes = static_cast<int>(count_lds_size(W, bits));
+    const void *k = bits == 4 ? reinterpret_cast<const void *>(k_count_select<4>)
+                              : reinterpret_cast<const void *>(k_count_select<8>);
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, CT_BLOCK, bytes);
+}
+
+hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int NG, uint32_t *arrive,
+                               uint32_t *err, uint32_t spin_limit, hipStream_t st) {
+    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
+    SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
+                  s.dump_hist};
+    FuseArgs f{c.nq, NG, const_cast<uint32_t *>(s.hist), arrive, err, spin_limit};
+    void *args[] = {&a, &sa, &f};
+    const void *k = c.bits == 4 ? reinterpret_cast<const void *>(k_count_select<4>)
+                                : reinterpret_cast<const void *>(k_count_select<8>);
+    return hipLaunchCooperativeKernel(k, dim3(static_cast<unsigned>(NG) * c.T), dim3(CT_BLOCK), args,
+                                      static_cast<unsigned>(count_lds_size(c.W, c.bits)), st);
 }
 
 int rerank_lanes_per_row(int d) {

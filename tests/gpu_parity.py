@@ -38,6 +38,7 @@ def gpu_search(idx, Q, k, alpha, beta, fields=None):
     else:
         ids, dists = idx.search_debug(q, k, alpha, beta, dump)
     torch.cuda.synchronize()
+    assert idx.device_errors() == 0, "a fused count/select wait timed out"
     out = {f: t.cpu().numpy() for f, t in (dump or {}).items()}
     out["ids"], out["dists"] = ids.cpu().numpy(), dists.cpu().numpy()
     return out

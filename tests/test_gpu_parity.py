@@ -194,3 +194,28 @@ def test_bf16_rerank_equals_fp32(taco_mod, w):
         nr, nc = g16["nrecheck"], g16["ncand"]
         assert np.all(nr >= np.minimum(k, nc)) and np.all(nr <= nc)
         print(f"[{w.name}] k={k}: re-checked {nr.mean():.1f} of {nc.mean():.0f} candidates", flush=True)
+
+
+@pytest.mark.parametrize("mode", ["split", "fused"])
+def test_count_modes_all_stages(taco_mod, tiny, mode):
+    """The split (count, then select) and fused (one cooperative launch)
+    counting paths both match the oracle stage by stage, also with several
+    tiles per query and several batches."""
+    t = taco_mod
+    m = t.TC_COUNT_SPLIT if mode == "split" else t.TC_COUNT_FUSED
+    print(f"[tiny] count mode {mode}", flush=True)
+    for opts in (((t.TC_OPT_COUNT_MODE, m),),
+                 ((t.TC_OPT_TILE_IDS, 4096), (t.TC_OPT_COUNT_MODE, m), (t.TC_OPT_MAX_BATCH, 13))):
+        _run_all(t, tiny["path"], tiny["oidx"], tiny["Q"], 10, 0.05, 0.005, 0, f"tiny {mode}",
+                 options=opts)
+
+
+@pytest.mark.parametrize("w", scaled_workloads(), ids=lambda w: w.name)
+def test_workload_shapes_split_mode(taco_mod, w):
+    t = taco_mod
+    X, Q = synthdata.base_and_queries(w)
+    path = workload_index(w, X)
+    oidx = O.OracleIndex(path)
+    print(f"[{w.name}] split mode", flush=True)
+    _run_all(t, path, oidx, Q, 10, 0.05, 0.005, 0, w.name + " split",
+             options=((t.TC_OPT_COUNT_MODE, t.TC_COUNT_SPLIT),))
