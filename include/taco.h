@@ -74,7 +74,14 @@ enum tc_option {
     TC_OPT_SCRATCH_BYTES = 5, /* candidate-scratch budget in bytes used to pick the
                                batch size (>= 8*n); default 32 GiB                   */
     TC_OPT_PRECISION = 6,   /* tc_precision of the re-rank; default TC_FP32         */
-    TC_OPT_COUNT_MODE = 7   /* tc_count_mode; default TC_COUNT_AUTO                  */
+    TC_OPT_COUNT_MODE = 7,  /* tc_count_mode; default TC_COUNT_AUTO                  */
+    TC_OPT_GRAPH = 8,       /* 1: capture each call's launch sequence into a HIP
+                               graph (on a private stream) and replay it on the
+                               caller's stream while the call's pointers, sizes,
+                               budgets and options stay the same; 0: off (default).
+                               Calls with stage dumps never use the graph.          */
+    TC_OPT_PROBE_QPW = 9,   /* queries (wavefronts) per probe workgroup: 1,2,4,8; 4 */
+    TC_OPT_RERANK_BLOCKS = 10 /* re-rank workgroups per query, [1, 1024]; default 32 */
 };
 
 /* How collision counting and candidate selection are launched.
@@ -149,6 +156,41 @@ int tc_search(tc_index *index, const float *queries, int64_t nq, int32_t k, doub
               double beta, int64_t *ids, float *dists, void *stream);
 
 /*
+ * k-ANNS with per-query budgets (query-aware collision ratio and k; Alg 6 with
+ * Alg 4's stop test per query).  Inputs stay on the device:
+ *   queries  device, f32 [nq][d].
+ *   alpha    device, f64 [nq]: collision ratio of each query in (0, 1]; its
+ *            budget ceil(alpha*n) is evaluated on the device in IEEE double
+ *            (the same expression as tc_search) and clamped to [1, n].
+ *   k        device, i32 [nq]: results wanted for each query, in [1, k_max].
+ *   k_max    host, the row length of ids/dists, 1 <= k_max <= min(n, 1024).
+ *   beta     re-rank ratio shared by the batch, 0 <= beta <= 1.
+ *   ids      device, i64 [nq][k_max]; dists device, f32 [nq][k_max]: row q
+ *            holds query q's k[q] results, then (-1, +inf) padding.
+ * An alpha or k out of range is clamped and sets bit 1 of the device error
+ * word (tc_device_errors).  Same kernels as tc_search; with TC_OPT_GRAPH the
+ * whole call is one graph launch.
+ */
+int tc_search_batched(tc_index *index, const float *queries, int64_t nq, const double *alpha,
+                      const int32_t *k, int32_t k_max, double beta, int64_t *ids, float *dists,
+                      void *stream);
+
+/*
+ * Autotuner.  Times the search of `queries` (device, f32 [nq][d]) with the
+ * given k, alpha and beta under candidate launch configurations -- LDS tile
+ * width (ids per counting tile), split or fused counting, queries per probe
+ * workgroup, re-rank workgroups per query, re-rank precision -- by coordinate
+ * descent (1 warm-up + 3 timed runs each, HIP events on `stream`), and leaves
+ * the fastest applied.  All candidates give identical results.  With a
+ * cache_path (host string, may be NULL) a matching entry (same GPU, index
+ * shape, nq, k, alpha, beta) is applied without measuring, and a new result
+ * is appended as one JSON object per line.  `report` (host, may be NULL)
+ * receives a text summary, truncated to report_len.  Synchronous.
+ */
+int tc_autotune(tc_index *index, const float *queries, int64_t nq, int32_t k, double alpha,
+                double beta, void *stream, const char *cache_path, char *report, size_t report_len);
+
+/*
  * Per-stage outputs of tc_search, for parity checks.  Every member is a
  * device pointer sized for the call's nq and may be NULL (stage not dumped).
  * K = l*l.
@@ -179,7 +221,7 @@ int tc_search_debug(tc_index *index, const float *queries, int64_t nq, int32_t k
 /*
  * Kernel timing, recorded while TC_OPT_PROFILE is 1.  Waits for the recorded
  * events, then reports for `kernel` -- one of "transform", "probe", "count",
- * "select", "rerank", "topk", "recheck", "count_select" -- the summed duration in milliseconds and the
+ * "select", "rerank", "topk", "recheck", "count_select", "graph" -- the summed duration in milliseconds and the
  * number of launches since the last tc_profile_reset.  Host outputs.
  */
 int tc_kernel_time(tc_index *index, const char *kernel, double *total_ms, int64_t *launches);

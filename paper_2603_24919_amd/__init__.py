@@ -18,7 +18,8 @@ __all__ = [
     "TC_RULE_PRINTED", "TC_RULE_PROSE", "TC_OPT_SELECT_RULE", "TC_OPT_MAX_BATCH",
     "TC_OPT_TILE_IDS", "TC_OPT_PROFILE", "TC_OPT_SCRATCH_BYTES", "TC_OPT_PRECISION",
     "TC_FP32", "TC_BF16", "TC_OPT_COUNT_MODE", "TC_COUNT_AUTO", "TC_COUNT_SPLIT",
-    "TC_COUNT_FUSED", "KERNELS", "tc_device_errors",
+    "TC_COUNT_FUSED", "TC_OPT_GRAPH", "TC_OPT_PROBE_QPW", "TC_OPT_RERANK_BLOCKS", "KERNELS",
+    "tc_device_errors", "tc_search_batched", "tc_autotune",
     "TacoError", "TacoLibraryMissing", "lib_path", "load_library",
     "tc_load_index", "tc_free_index", "tc_index_info", "tc_set_option", "tc_search",
     "tc_search_debug", "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity",
@@ -32,7 +33,9 @@ TC_OPT_PRECISION = 6
 TC_FP32, TC_BF16 = 0, 1
 TC_OPT_COUNT_MODE = 7
 TC_COUNT_AUTO, TC_COUNT_SPLIT, TC_COUNT_FUSED = 0, 1, 2
-KERNELS = ("transform", "probe", "count", "select", "rerank", "topk", "recheck", "count_select")
+TC_OPT_GRAPH, TC_OPT_PROBE_QPW, TC_OPT_RERANK_BLOCKS = 8, 9, 10
+KERNELS = ("transform", "probe", "count", "select", "rerank", "topk", "recheck", "count_select",
+           "graph")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libtaco_hip.so"
@@ -87,10 +90,13 @@ def load_library():
     L.tc_profile_reset.argtypes = [vp]
     L.tc_batch_capacity.argtypes = [vp, C.POINTER(i64)]
     L.tc_device_errors.argtypes = [vp, C.POINTER(C.c_uint32)]
+    L.tc_search_batched.argtypes = [vp, vp, i64, vp, vp, i32, dbl, vp, vp, vp]
+    L.tc_autotune.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, C.c_char_p, C.c_char_p, C.c_size_t]
     L.tc_last_error.restype = C.c_char_p
     L.tc_last_error.argtypes = []
     for f in ("tc_load_index", "tc_index_info", "tc_set_option", "tc_search", "tc_search_debug",
-              "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity", "tc_device_errors"):
+              "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity", "tc_device_errors",
+              "tc_search_batched", "tc_autotune"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -187,6 +193,39 @@ def tc_search_debug(index, queries, k: int, alpha: float, beta: float, dump=None
     return ids, dists
 
 
+def tc_search_batched(index, queries, alpha, k, k_max: int, beta: float, ids=None, dists=None,
+                      stream=None):
+    """Per-query budgets: ``alpha`` (CUDA float64 [nq]) and ``k`` (CUDA int32
+    [nq]); returns ``(ids int64 [nq, k_max], dists float32 [nq, k_max])``."""
+    import torch
+    nq = int(queries.shape[0])
+    dev = queries.device
+    if queries.dtype != torch.float32 or not queries.is_cuda or not queries.is_contiguous():
+        raise ValueError("queries must be a contiguous float32 CUDA tensor")
+    _check_tensor(alpha, torch.float64, (nq,), dev, "alpha")
+    _check_tensor(k, torch.int32, (nq,), dev, "k")
+    if ids is None:
+        ids = torch.empty((nq, k_max), dtype=torch.int64, device=dev)
+    if dists is None:
+        dists = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
+    _check_tensor(ids, torch.int64, (nq, k_max), dev, "ids")
+    _check_tensor(dists, torch.float32, (nq, k_max), dev, "dists")
+    _check(load_library().tc_search_batched(index, queries.data_ptr(), nq, alpha.data_ptr(),
+                                            k.data_ptr(), int(k_max), float(beta), ids.data_ptr(),
+                                            dists.data_ptr(), _stream_handle(stream, dev)))
+    return ids, dists
+
+
+def tc_autotune(index, queries, k: int, alpha: float, beta: float, cache_path=None, stream=None) -> str:
+    """Tune the launch configuration on this batch; returns the report."""
+    buf = C.create_string_buffer(8192)
+    _check(load_library().tc_autotune(
+        index, queries.data_ptr(), int(queries.shape[0]), int(k), float(alpha), float(beta),
+        _stream_handle(stream, queries.device), None if cache_path is None else os.fsencode(cache_path),
+        buf, len(buf)))
+    return buf.value.decode()
+
+
 def tc_kernel_time(index, kernel: str) -> Tuple[float, int]:
     ms, n = C.c_double(), C.c_int64()
     _check(load_library().tc_kernel_time(index, kernel.encode(), C.byref(ms), C.byref(n)))
@@ -235,6 +274,12 @@ class Index:
 
     def search(self, queries, k: int, alpha: float, beta: float, **kw):
         return tc_search(self.handle, queries, k, alpha, beta, **kw)
+
+    def search_batched(self, queries, alpha, k, k_max: int, beta: float, **kw):
+        return tc_search_batched(self.handle, queries, alpha, k, k_max, beta, **kw)
+
+    def autotune(self, queries, k: int, alpha: float, beta: float, cache_path=None, **kw) -> str:
+        return tc_autotune(self.handle, queries, k, alpha, beta, cache_path=cache_path, **kw)
 
     def search_debug(self, queries, k: int, alpha: float, beta: float, dump, **kw):
         return tc_search_debug(self.handle, queries, k, alpha, beta, dump, **kw)

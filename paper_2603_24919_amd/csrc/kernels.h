@@ -35,8 +35,10 @@ hipError_t launch_transform(const float *Q, int nq, int d, const float *mean, co
                             int M, float *qt, hipStream_t st);
 hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, int h2, int l,
                         int K, const float *C1, const float *C2, const uint32_t *offs, int64_t A,
-                        int32_t *cells, int32_t *ncells, int64_t *retrieved, float *dump_cdist,
-                        int32_t *dump_corder, hipStream_t st);
+                        const int64_t *A_q, int32_t *cells, int32_t *ncells, int64_t *retrieved,
+                        float *dump_cdist, int32_t *dump_corder, int qpw, hipStream_t st);
+hipError_t launch_budgets(const double *alpha, const int32_t *kq, int nq, int64_t n, int k_max,
+                          int64_t *A, int32_t *kc, uint32_t *err, hipStream_t st);
 hipError_t prepare_count_kernels(int W, int bits);
 size_t count_lds_bytes(int W, int bits);
 hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, hipStream_t st);
@@ -55,11 +57,12 @@ hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const
                            int64_t cap, float *ub, float *lb, int blocks_per_q, hipStream_t st);
 hipError_t launch_recheck(const float *Q, int nq, int d, const float *base, const int32_t *cand,
                           const uint32_t *cand_count, const float *lb, int64_t cap,
-                          const float *tau_d, int k, int32_t *rk_ids, float *rk_dist,
-                          uint32_t *rk_count, int blocks_per_q, hipStream_t st);
+                          const float *tau_d, int k, const int32_t *kq, int k_max, int32_t *rk_ids,
+                          float *rk_dist, uint32_t *rk_count, int blocks_per_q, hipStream_t st);
 hipError_t launch_prep_bf16(const float *base, int64_t n, int d, const float *mu, uint16_t *base16,
                             float *rowerr, hipStream_t st);
 hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32_t *cand_count,
-                       int64_t cap, int nq, int k, int64_t *ids, float *dists, hipStream_t st);
+                       int64_t cap, int nq, int k, const int32_t *kq, int k_max, int64_t *ids,
+                       float *dists, hipStream_t st);
 
 }  // namespace taco

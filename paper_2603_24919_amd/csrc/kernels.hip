@@ -83,6 +83,28 @@ __global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t v) {
     for (; i < count; i += stride) p[i] = v;
 }
 
+// Per-query collision budgets of the batched search: A = ceil(alpha*n) in
+// IEEE double (the host's expression), clamped to [1, n]; k clamped to
+// [1, k_max].  A value out of range sets bit 1 of *err.
+__global__ void k_budgets(const double *alpha, const int32_t *kq, int nq, int64_t n, int k_max,
+                          int64_t *A, int32_t *kc, uint32_t *err) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const double a = alpha[q];
+    bool bad = !(a > 0.0 && a <= 1.0);
+    double v = bad ? static_cast<double>(n) : ceil(a * static_cast<double>(n));
+    if (v < 1.0) v = 1.0;
+    if (v > static_cast<double>(n)) v = static_cast<double>(n);
+    A[q] = static_cast<int64_t>(v);
+    int k = kq[q];
+    if (k < 1 || k > k_max) {
+        bad = true;
+        k = k < 1 ? 1 : k_max;
+    }
+    kc[q] = k;
+    if (bad) atomicOr(err, 2u);
+}
+
 __global__ void k_u32_to_i64(const uint32_t *src, int64_t *dst, int64_t count) {
     int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < count) dst[i] = static_cast<int64_t>(src[i]);
@@ -169,27 +191,31 @@ __global__ __launch_bounds__(256) void k_transform(const float *__restrict__ Q, 
 // so this visits cells in exactly the order of Alg 4's heap (distance, row)
 // and stops at the same cell: the first one that brings the retrieved count
 // to at least A.
-// grid (ceil(nq/4), Ns), block 256; dynamic LDS: K cell sizes of subspace j.
+// grid (ceil(nq/QPW), Ns), block 64*QPW (one query per wavefront); dynamic
+// LDS: the K cell sizes of subspace j.  The budget is A_q[q] when A_q is
+// given, else A.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_probe(
+template <int QPW>
+__global__ __launch_bounds__(64 * QPW) void k_probe(
     const float *__restrict__ qt, int nq, int M, int s, int h1, int h2, int l, int K,
     const float *__restrict__ C1, const float *__restrict__ C2,
-    const uint32_t *__restrict__ offs, int64_t A, int32_t *__restrict__ cells,
-    int32_t *__restrict__ ncells, int64_t *__restrict__ retrieved,
+    const uint32_t *__restrict__ offs, int64_t A_all, const int64_t *__restrict__ A_q,
+    int32_t *__restrict__ cells, int32_t *__restrict__ ncells, int64_t *__restrict__ retrieved,
     float *__restrict__ dump_cdist, int32_t *__restrict__ dump_corder) {
     extern __shared__ uint32_t sizes[];  // [K]
-    __shared__ float rawD[WAVES][2][WAVE];
-    __shared__ float sortD[WAVES][2][WAVE];
-    __shared__ int32_t order[WAVES][2][WAVE];
+    __shared__ float rawD[QPW][2][WAVE];
+    __shared__ float sortD[QPW][2][WAVE];
+    __shared__ int32_t order[QPW][2][WAVE];
 
     const int j = blockIdx.y, Ns = gridDim.y;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int q = blockIdx.x * WAVES + wave;
+    const int q = blockIdx.x * QPW + wave;
     const uint32_t *off = offs + static_cast<int64_t>(j) * (K + 1);
-    for (int c = threadIdx.x; c < K; c += BLOCK) sizes[c] = off[c + 1] - off[c];
+    for (int c = threadIdx.x; c < K; c += 64 * QPW) sizes[c] = off[c + 1] - off[c];
     __syncthreads();
     if (q >= nq) return;  // no block-wide barrier below this point
+    const int64_t A = A_q ? A_q[q] : A_all;
 
     const float *x = qt + static_cast<int64_t>(q) * M + static_cast<int64_t>(j) * s;
     float d1 = 0.0f, d2 = 0.0f;
@@ -904,7 +930,8 @@ __global__ __launch_bounds__(256) void k_recheck(const float *__restrict__ Q, in
                                                  const int32_t *__restrict__ cand,
                                                  const uint32_t *__restrict__ cand_count,
                                                  const float *__restrict__ lb, int64_t cap,
-                                                 const float *__restrict__ tau_d, int k,
+                                                 const float *__restrict__ tau_d, int k_all,
+                                                 const int32_t *__restrict__ kq, int k_max,
                                                  int32_t *__restrict__ rk_ids,
                                                  float *__restrict__ rk_dist,
                                                  uint32_t *__restrict__ rk_count) {
@@ -914,7 +941,8 @@ __global__ __launch_bounds__(256) void k_recheck(const float *__restrict__ Q, in
     const int q = blockIdx.y;
     for (int t = threadIdx.x; t < d; t += BLOCK) qs[t] = Q[static_cast<int64_t>(q) * d + t];
     const int64_t nc = cand_count[q];
-    const float tau = tau_d[static_cast<int64_t>(q) * k + (k - 1)];  // +inf when |C| < k
+    const int k = kq ? kq[q] : k_all;
+    const float tau = tau_d[static_cast<int64_t>(q) * k_max + (k - 1)];  // +inf when |C| < k
     constexpr int RPW = WAVE / LPR;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int sub = lane / LPR, li = lane % LPR;
@@ -980,16 +1008,20 @@ __global__ __launch_bounds__(256) void k_prep_bf16(const float *__restrict__ bas
 
 constexpr int TOPK_MAX = 1024;
 
+// k is kq[q] when kq is given (else k_all); results go to rows of k_max
+// entries, padded with (-1, +inf) past k or past |C|.
 __global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
                                               const float *__restrict__ cand_dist,
                                               const uint32_t *__restrict__ cand_count,
-                                              int64_t cap, int k, int64_t *__restrict__ ids_out,
+                                              int64_t cap, int k_all, const int32_t *__restrict__ kq,
+                                              int k_max, int64_t *__restrict__ ids_out,
                                               float *__restrict__ d_out) {
     __shared__ uint32_t hist[256];
     __shared__ uint64_t sel[TOPK_MAX];
     __shared__ uint32_t nsel;
     __shared__ uint32_t s_digit, s_need, s_full;
     const int q = blockIdx.x;
+    const int k = kq ? kq[q] : k_all;
     const int64_t nc = cand_count[q];
     const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
     const float *dq = cand_dist + static_cast<int64_t>(q) * cap;
@@ -1061,8 +1093,8 @@ __global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
             __syncthreads();
         }
     }
-    for (int i = threadIdx.x; i < k; i += BLOCK) {
-        const int64_t o = static_cast<int64_t>(q) * k + i;
+    for (int i = threadIdx.x; i < k_max; i += BLOCK) {
+        const int64_t o = static_cast<int64_t>(q) * k_max + i;
         if (i < m) {
             ids_out[o] = static_cast<int64_t>(static_cast<uint32_t>(sel[i] & 0xffffffffu));
             d_out[o] = __uint_as_float(static_cast<uint32_t>(sel[i] >> 32));
@@ -1108,12 +1140,26 @@ hipError_t launch_transform(const float *Q, int nq, int d, const float *mean, co
 
 hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, int h2, int l,
                         int K, const float *C1, const float *C2, const uint32_t *offs, int64_t A,
-                        int32_t *cells, int32_t *ncells, int64_t *retrieved, float *dump_cdist,
-                        int32_t *dump_corder, hipStream_t st) {
-    dim3 grid((nq + WAVES - 1) / WAVES, Ns);
+                        const int64_t *A_q, int32_t *cells, int32_t *ncells, int64_t *retrieved,
+                        float *dump_cdist, int32_t *dump_corder, int qpw, hipStream_t st) {
     size_t lds = sizeof(uint32_t) * static_cast<size_t>(K);
-    k_probe<<<grid, BLOCK, lds, st>>>(qt, nq, M, s, h1, h2, l, K, C1, C2, offs, A, cells, ncells,
-                                      retrieved, dump_cdist, dump_corder);
+#define TACO_PROBE(Q)                                                                          \
+    k_probe<Q><<<dim3((nq + Q - 1) / Q, Ns), 64 * Q, lds, st>>>(                               \
+        qt, nq, M, s, h1, h2, l, K, C1, C2, offs, A, A_q, cells, ncells, retrieved, dump_cdist, \
+        dump_corder)
+    switch (qpw) {
+    case 1: TACO_PROBE(1); break;
+    case 2: TACO_PROBE(2); break;
+    case 8: TACO_PROBE(8); break;
+    default: TACO_PROBE(4); break;
+    }
+#undef TACO_PROBE
+    return hipGetLastError();
+}
+
+hipError_t launch_budgets(const double *alpha, const int32_t *kq, int nq, int64_t n, int k_max,
+                          int64_t *A, int32_t *kc, uint32_t *err, hipStream_t st) {
+    k_budgets<<<(nq + 255) / 256, 256, 0, st>>>(alpha, kq, nq, n, k_max, A, kc, err);
     return hipGetLastError();
 }
 
@@ -1233,13 +1279,13 @@ hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const
 
 hipError_t launch_recheck(const float *Q, int nq, int d, const float *base, const int32_t *cand,
                           const uint32_t *cand_count, const float *lb, int64_t cap,
-                          const float *tau_d, int k, int32_t *rk_ids, float *rk_dist,
-                          uint32_t *rk_count, int blocks_per_q, hipStream_t st) {
+                          const float *tau_d, int k, const int32_t *kq, int k_max, int32_t *rk_ids,
+                          float *rk_dist, uint32_t *rk_count, int blocks_per_q, hipStream_t st) {
     dim3 grid(blocks_per_q, nq);
     size_t lds = sizeof(float) * static_cast<size_t>(d);
 #define TACO_RC(L, V)                                                                        \
     k_recheck<L, V><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, lb, cap, tau_d, k, \
-                                              rk_ids, rk_dist, rk_count)
+                                              kq, k_max, rk_ids, rk_dist, rk_count)
     if (d % 4 != 0) {
         TACO_RC(64, false);
     } else {
@@ -1263,8 +1309,9 @@ hipError_t launch_prep_bf16(const float *base, int64_t n, int d, const float *mu
 }
 
 hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32_t *cand_count,
-                       int64_t cap, int nq, int k, int64_t *ids, float *dists, hipStream_t st) {
-    k_topk<<<nq, BLOCK, 0, st>>>(cand, cand_dist, cand_count, cap, k, ids, dists);
+                       int64_t cap, int nq, int k, const int32_t *kq, int k_max, int64_t *ids,
+                       float *dists, hipStream_t st) {
+    k_topk<<<nq, BLOCK, 0, st>>>(cand, cand_dist, cand_count, cap, k, kq, k_max, ids, dists);
     return hipGetLastError();
 }
 

@@ -10,8 +10,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -63,12 +65,25 @@ struct Reader {
 };
 
 const char *kKernelNames[] = {"transform", "probe", "count", "select", "rerank", "topk", "recheck",
-                              "count_select"};
-enum Kern { K_TRANSFORM = 0, K_PROBE, K_COUNT, K_SELECT, K_RERANK, K_TOPK, K_RECHECK, K_FUSED, K_COUNT_ };
+                              "count_select", "graph"};
+enum Kern {
+    K_TRANSFORM = 0, K_PROBE, K_COUNT, K_SELECT, K_RERANK, K_TOPK, K_RECHECK, K_FUSED, K_GRAPH, K_COUNT_
+};
 
 struct Timing {
     int kernel;
     hipEvent_t start, stop;
+};
+
+// Everything a captured graph bakes in; a call with another key is captured again.
+struct GraphKey {
+    const void *Q, *kq, *alpha_dev, *ids, *dists;
+    int64_t nq;
+    int k, k_max;
+    uint64_t alpha_bits, beta_bits;
+    int precision, count_mode, W, qpw, rule, rr_blocks;
+    int64_t Qb;
+    bool operator==(const GraphKey &o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 
 }  // namespace
@@ -89,6 +104,17 @@ struct tc_index {
     int count_mode = TC_COUNT_AUTO;
     uint32_t *err = nullptr;     // device error word of the fused kernel
     uint32_t *arrive = nullptr;  // [Qb] tile arrivals per query
+    int64_t *Aq = nullptr;       // [Qb] per-query collision budgets (batched calls)
+    int32_t *kq = nullptr;       // [Qb] per-query k, clamped
+    int probe_qpw = 4;           // queries (wavefronts) per probe workgroup
+    int rr_blocks = 32;          // re-rank workgroups per query
+    // graph capture of whole calls
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    GraphKey graph_key;
+    int64_t graph_captures = 0;
     // options
     int rule = TC_RULE_PRINTED;
     int64_t max_batch = 0;  // 0: automatic
@@ -122,7 +148,19 @@ struct tc_index {
 
 namespace {
 
+void drop_graph(tc_index *x) {
+    if (x->graph_exec) (void)hipGraphExecDestroy(x->graph_exec);
+    if (x->graph) (void)hipGraphDestroy(x->graph);
+    x->graph_exec = nullptr;
+    x->graph = nullptr;
+}
+
 void free_scratch(tc_index *x) {
+    drop_graph(x);
+    (void)hipFree(x->Aq);
+    (void)hipFree(x->kq);
+    x->Aq = nullptr;
+    x->kq = nullptr;
     (void)hipFree(x->qt);
     (void)hipFree(x->cells);
     (void)hipFree(x->ncells);
@@ -189,6 +227,8 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->hist, size_t(qb) * (x->Ns + 1), "level histograms"))) return rc;
     if ((rc = dmalloc(&x->cand_count, size_t(qb), "candidate counts"))) return rc;
     if ((rc = dmalloc(&x->arrive, size_t(qb), "tile arrivals"))) return rc;
+    if ((rc = dmalloc(&x->Aq, size_t(qb), "per-query budgets"))) return rc;
+    if ((rc = dmalloc(&x->kq, size_t(qb), "per-query k"))) return rc;
     if ((rc = dmalloc(&x->cand, size_t(qb) * x->n, "candidates"))) return rc;
     if ((rc = dmalloc(&x->cand_dist, size_t(qb) * x->n, "candidate distances"))) return rc;
     if ((rc = dmalloc(&x->sc, size_t(qb) * x->T * (size_t(x->W) * x->bits / 32), "packed counts")))
@@ -244,6 +284,8 @@ void free_all(tc_index *x) {
         (void)hipEventDestroy(t.stop);
     }
     x->pending.clear();
+    if (x->cap_stream) (void)hipStreamDestroy(x->cap_stream);
+    x->cap_stream = nullptr;
 }
 
 template <typename T>
@@ -411,36 +453,55 @@ int resolve_timings(tc_index *x) {
     return TC_OK;
 }
 
-int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, double beta,
-           int64_t *ids, float *dists, void *stream, const tc_stage_dump *dump) {
-    if (!x) return fail(TC_EINVAL, "index is NULL");
-    if (nq < 0) return fail(TC_EINVAL, "nq < 0");
-    if (nq == 0) return TC_OK;
-    if (!Q || !ids || !dists) return fail(TC_EINVAL, "queries, ids and dists must be non-NULL");
-    if (k < 1 || int64_t(k) > x->n || k > 1024) return fail(TC_EINVAL, "k must be in [1, min(n, 1024)]");
-    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(TC_EINVAL, "alpha must be in (0, 1]");
-    if (!(beta >= 0.0 && beta <= 1.0)) return fail(TC_EINVAL, "beta must be in [0, 1]");
-    DeviceGuard g(x->device);
-    hipStream_t st = static_cast<hipStream_t>(stream);
+// One search call: uniform budgets (alpha, k) or per-query ones (alpha_dev,
+// kq_dev, device arrays), results in rows of k_max.
+struct Call {
+    const float *Q = nullptr;
+    int64_t nq = 0;
+    int k = 0;
+    const int32_t *kq_dev = nullptr;
+    int k_max = 0;
+    double alpha = 0.0;
+    const double *alpha_dev = nullptr;
+    double beta = 0.0;
+    int64_t *ids = nullptr;
+    float *dists = nullptr;
+    const tc_stage_dump *dump = nullptr;
+};
+
+// The launch sequence of a call, batch after batch, on stream st.  Nothing
+// here waits on the host, so it can also be captured into a graph.
+int enqueue(tc_index *x, const Call &c, hipStream_t st) {
+    const tc_stage_dump *dump = c.dump;
     // budgets in IEEE double (Alg 4 stop test, Alg 5 budget)
-    double a = std::ceil(alpha * double(x->n));
+    double a = std::ceil(c.alpha * double(x->n));
     if (a < 1.0) a = 1.0;
     if (a > double(x->n)) a = double(x->n);
-    double r = std::floor(beta * double(x->n));
+    double r = std::floor(c.beta * double(x->n));
     if (r < 0.0) r = 0.0;
     if (r > double(x->n)) r = double(x->n);
     const int64_t A = static_cast<int64_t>(a), R = static_cast<int64_t>(r);
     const int64_t cap = x->n;
-    const int rr_blocks = 32;
+    const int rr_blocks = x->rr_blocks;
+    const int k = c.k, k_max = c.k_max;
     // AUTO takes the split launches: on MI355X the ~T*nq independent
     // workgroups of the split form overlap better than the fused groups'
     // lock-step rounds (10.2 vs 17.3 ms per 10k-query step at n = 1M)
     const bool fused = x->count_mode == TC_COUNT_FUSED;
-    if (fused && x->fused_groups <= 0)
-        return fail(TC_EINVAL, "the fused count/select kernel cannot keep all tiles of a query resident");
-    for (int64_t b0 = 0; b0 < nq; b0 += x->Qb) {
-        const int nb = static_cast<int>(std::min<int64_t>(x->Qb, nq - b0));
-        const float *Qb = Q + b0 * x->d;
+    for (int64_t b0 = 0; b0 < c.nq; b0 += x->Qb) {
+        const int nb = static_cast<int>(std::min<int64_t>(x->Qb, c.nq - b0));
+        const float *Qb = c.Q + b0 * x->d;
+        int64_t *ids = c.ids + b0 * k_max;
+        float *dists = c.dists + b0 * k_max;
+        const int64_t *Aq = nullptr;
+        const int32_t *kq = nullptr;
+        if (c.alpha_dev) {
+            TC_HIP(taco::launch_budgets(c.alpha_dev + b0, c.kq_dev + b0, nb, x->n, k_max, x->Aq, x->kq,
+                                        x->err, st),
+                   "budget kernel");
+            Aq = x->Aq;
+            kq = x->kq;
+        }
         TC_HIP(taco::launch_fill_u32(x->hist, int64_t(nb) * (x->Ns + 1), 0u, st), "clearing histograms");
         TC_HIP(taco::launch_fill_u32(x->cand_count, nb, 0u, st), "clearing candidate counts");
 
@@ -452,7 +513,8 @@ int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, dou
         int32_t *dco = dump && dump->corder ? dump->corder + b0 * x->Ns * 2 * x->l : nullptr;
         record(x, K_PROBE, st, true);
         TC_HIP(taco::launch_probe(x->qt, nb, x->Ns, x->M, x->s, x->h1, x->h2, x->l, x->K, x->C1,
-                                  x->C2, x->offs, A, x->cells, x->ncells, x->retrieved, dcd, dco, st),
+                                  x->C2, x->offs, A, Aq, x->cells, x->ncells, x->retrieved, dcd, dco,
+                                  x->probe_qpw, st),
                "probe kernel");
         record(x, K_PROBE, st, false);
 
@@ -488,19 +550,19 @@ int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, dou
                    "BF16 rerank kernel");
             record(x, K_RERANK, st, false);
             record(x, K_TOPK, st, true);
-            TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, x->tau_ids,
-                                     x->tau_d, st),
+            TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, kq, k_max,
+                                     x->tau_ids, x->tau_d, st),
                    "bound top-k kernel");
             record(x, K_TOPK, st, false);
             record(x, K_RECHECK, st, true);
             TC_HIP(taco::launch_recheck(Qb, nb, x->d, x->base, x->cand, x->cand_count, x->lb, cap,
-                                        x->tau_d, k, x->rk_ids, x->cand_dist, x->rk_count,
+                                        x->tau_d, k, kq, k_max, x->rk_ids, x->cand_dist, x->rk_count,
                                         rr_blocks, st),
                    "re-check kernel");
             record(x, K_RECHECK, st, false);
             record(x, K_TOPK, st, true);
-            TC_HIP(taco::launch_topk(x->rk_ids, x->cand_dist, x->rk_count, cap, nb, k, ids + b0 * k,
-                                     dists + b0 * k, st),
+            TC_HIP(taco::launch_topk(x->rk_ids, x->cand_dist, x->rk_count, cap, nb, k, kq, k_max, ids,
+                                     dists, st),
                    "top-k kernel");
             record(x, K_TOPK, st, false);
             if (dump && dump->nrecheck)
@@ -513,8 +575,8 @@ int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, dou
             record(x, K_RERANK, st, false);
 
             record(x, K_TOPK, st, true);
-            TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, ids + b0 * k,
-                                     dists + b0 * k, st),
+            TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, kq, k_max, ids,
+                                     dists, st),
                    "top-k kernel");
             record(x, K_TOPK, st, false);
         }
@@ -543,6 +605,85 @@ int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, dou
         }
     }
     return TC_OK;
+}
+
+int run(tc_index *x, const Call &c, void *stream) {
+    if (c.nq == 0) return TC_OK;
+    DeviceGuard g(x->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (x->count_mode == TC_COUNT_FUSED && x->fused_groups <= 0)
+        return fail(TC_EINVAL, "the fused count/select kernel cannot keep all tiles of a query resident");
+    if (!x->use_graph || c.dump) return enqueue(x, c, st);
+    GraphKey key;
+    memset(&key, 0, sizeof key);
+    key.Q = c.Q;
+    key.kq = c.kq_dev;
+    key.alpha_dev = c.alpha_dev;
+    key.ids = c.ids;
+    key.dists = c.dists;
+    key.nq = c.nq;
+    key.k = c.k;
+    key.k_max = c.k_max;
+    memcpy(&key.alpha_bits, &c.alpha, 8);
+    memcpy(&key.beta_bits, &c.beta, 8);
+    key.precision = x->precision;
+    key.count_mode = x->count_mode;
+    key.W = x->W;
+    key.qpw = x->probe_qpw;
+    key.rule = x->rule;
+    key.rr_blocks = x->rr_blocks;
+    key.Qb = x->Qb;
+    if (!x->graph_exec || !(key == x->graph_key)) {
+        drop_graph(x);
+        if (!x->cap_stream)
+            TC_HIP(hipStreamCreateWithFlags(&x->cap_stream, hipStreamNonBlocking), "creating the capture stream");
+        const bool prof = x->profile;
+        x->profile = false;  // no timing events inside a graph
+        TC_HIP(hipStreamBeginCapture(x->cap_stream, hipStreamCaptureModeThreadLocal), "beginning capture");
+        int rc = enqueue(x, c, x->cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(x->cap_stream, &graph);
+        x->profile = prof;
+        if (rc != TC_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "ending capture");
+        x->graph = graph;
+        e = hipGraphInstantiate(&x->graph_exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(x);
+            return hip_fail(e, "instantiating the search graph");
+        }
+        x->graph_key = key;
+        x->graph_captures++;
+    }
+    record(x, K_GRAPH, st, true);
+    TC_HIP(hipGraphLaunch(x->graph_exec, st), "launching the search graph");
+    record(x, K_GRAPH, st, false);
+    return TC_OK;
+}
+
+int search(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, double beta,
+           int64_t *ids, float *dists, void *stream, const tc_stage_dump *dump) {
+    if (!x) return fail(TC_EINVAL, "index is NULL");
+    if (nq < 0) return fail(TC_EINVAL, "nq < 0");
+    if (nq == 0) return TC_OK;
+    if (!Q || !ids || !dists) return fail(TC_EINVAL, "queries, ids and dists must be non-NULL");
+    if (k < 1 || int64_t(k) > x->n || k > 1024) return fail(TC_EINVAL, "k must be in [1, min(n, 1024)]");
+    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(TC_EINVAL, "alpha must be in (0, 1]");
+    if (!(beta >= 0.0 && beta <= 1.0)) return fail(TC_EINVAL, "beta must be in [0, 1]");
+    Call c;
+    c.Q = Q;
+    c.nq = nq;
+    c.k = k;
+    c.k_max = k;
+    c.alpha = alpha;
+    c.beta = beta;
+    c.ids = ids;
+    c.dists = dists;
+    c.dump = dump;
+    return run(x, c, stream);
 }
 
 }  // namespace
@@ -631,6 +772,20 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
             return fail(TC_EINVAL, "the fused count/select kernel is unavailable for this index");
         x->count_mode = static_cast<int>(value);
         return TC_OK;
+    case TC_OPT_GRAPH:
+        if (value != 0 && value != 1) return fail(TC_EINVAL, "graph must be 0 or 1");
+        x->use_graph = value != 0;
+        if (!x->use_graph) drop_graph(x);
+        return TC_OK;
+    case TC_OPT_PROBE_QPW:
+        if (value != 1 && value != 2 && value != 4 && value != 8)
+            return fail(TC_EINVAL, "queries per probe workgroup must be 1, 2, 4 or 8");
+        x->probe_qpw = static_cast<int>(value);
+        return TC_OK;
+    case TC_OPT_RERANK_BLOCKS:
+        if (value < 1 || value > 1024) return fail(TC_EINVAL, "re-rank workgroups per query must be in [1, 1024]");
+        x->rr_blocks = static_cast<int>(value);
+        return TC_OK;
     case TC_OPT_PROFILE:
         if (value != 0 && value != 1) return fail(TC_EINVAL, "profile must be 0 or 1");
         x->profile = value != 0;
@@ -643,6 +798,31 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
 int tc_search(tc_index *x, const float *queries, int64_t nq, int32_t k, double alpha, double beta,
               int64_t *ids, float *dists, void *stream) {
     return search(x, queries, nq, k, alpha, beta, ids, dists, stream, nullptr);
+}
+
+int tc_search_batched(tc_index *x, const float *queries, int64_t nq, const double *alpha,
+                      const int32_t *k, int32_t k_max, double beta, int64_t *ids, float *dists,
+                      void *stream) {
+    if (!x) return fail(TC_EINVAL, "index is NULL");
+    if (nq < 0) return fail(TC_EINVAL, "nq < 0");
+    if (nq == 0) return TC_OK;
+    if (!queries || !alpha || !k || !ids || !dists)
+        return fail(TC_EINVAL, "queries, alpha, k, ids and dists must be non-NULL");
+    if (k_max < 1 || int64_t(k_max) > x->n || k_max > 1024)
+        return fail(TC_EINVAL, "k_max must be in [1, min(n, 1024)]");
+    if (!(beta >= 0.0 && beta <= 1.0)) return fail(TC_EINVAL, "beta must be in [0, 1]");
+    Call c;
+    c.Q = queries;
+    c.nq = nq;
+    c.k = k_max;
+    c.kq_dev = k;
+    c.k_max = k_max;
+    c.alpha = 0.5;
+    c.alpha_dev = alpha;
+    c.beta = beta;
+    c.ids = ids;
+    c.dists = dists;
+    return run(x, c, stream);
 }
 
 int tc_search_debug(tc_index *x, const float *queries, int64_t nq, int32_t k, double alpha,
@@ -674,6 +854,166 @@ int tc_profile_reset(tc_index *x) {
         x->launches[i] = 0;
     }
     return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct TuneConfig {
+    int W, mode, qpw, rr, precision;
+};
+
+std::string tune_key(const tc_index *x, int64_t nq, int k, double alpha, double beta) {
+    hipDeviceProp_t prop;
+    std::string dev = hipGetDeviceProperties(&prop, x->device) == hipSuccess ? prop.gcnArchName : "gpu";
+    for (auto &ch : dev)
+        if (ch == ' ' || ch == '\t' || ch == '"') ch = '_';
+    std::ostringstream os;
+    os << dev << "|cu" << x->num_cu << "|n" << x->n << "|d" << x->d << "|Ns" << x->Ns << "|s" << x->s << "|l"
+       << x->l << "|nq" << nq << "|k" << k << "|a" << alpha << "|b" << beta;
+    return os.str();
+}
+
+int apply_config(tc_index *x, const TuneConfig &c) {
+    int rc;
+    if (c.W != x->W && (rc = tc_set_option(x, TC_OPT_TILE_IDS, c.W))) return rc;
+    if (c.precision != x->precision && (rc = tc_set_option(x, TC_OPT_PRECISION, c.precision))) return rc;
+    if ((rc = tc_set_option(x, TC_OPT_COUNT_MODE, c.mode))) return rc;
+    if ((rc = tc_set_option(x, TC_OPT_PROBE_QPW, c.qpw))) return rc;
+    return tc_set_option(x, TC_OPT_RERANK_BLOCKS, c.rr);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double alpha, double beta,
+                void *stream, const char *cache_path, char *report, size_t report_len) {
+    if (!x || !queries || nq < 1) return fail(TC_EINVAL, "index and a non-empty query batch are required");
+    if (k < 1 || int64_t(k) > x->n || k > 1024) return fail(TC_EINVAL, "k must be in [1, min(n, 1024)]");
+    if (!(alpha > 0.0 && alpha <= 1.0) || !(beta >= 0.0 && beta <= 1.0))
+        return fail(TC_EINVAL, "alpha must be in (0, 1] and beta in [0, 1]");
+    DeviceGuard g(x->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const std::string key = tune_key(x, nq, k, alpha, beta);
+    std::ostringstream rep;
+    auto finish = [&](int rc) {
+        if (report && report_len) {
+            std::string s = rep.str();
+            size_t m = std::min(s.size(), report_len - 1);
+            memcpy(report, s.data(), m);
+            report[m] = 0;
+        }
+        return rc;
+    };
+    // cache: one JSON object per line {"key": ..., "W": ..., ...}
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
+            TuneConfig c{};
+            if (sscanf(line.c_str() + line.find("\"W\""), "\"W\": %d, \"mode\": %d, \"qpw\": %d, \"rr\": %d, \"precision\": %d",
+                       &c.W, &c.mode, &c.qpw, &c.rr, &c.precision) == 5) {
+                int rc = apply_config(x, c);
+                rep << "cached " << key << " W=" << c.W << " mode=" << c.mode << " qpw=" << c.qpw
+                    << " rr=" << c.rr << " precision=" << c.precision << "\n";
+                return finish(rc);
+            }
+        }
+    }
+    int64_t *ids = nullptr;
+    float *dists = nullptr;
+    int rc;
+    if ((rc = dmalloc(&ids, size_t(nq) * k, "autotune ids"))) return finish(rc);
+    if ((rc = dmalloc(&dists, size_t(nq) * k, "autotune dists"))) {
+        (void)hipFree(ids);
+        return finish(rc);
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const bool graph = x->use_graph, prof = x->profile;
+    x->use_graph = false;
+    x->profile = false;
+    auto measure = [&](const TuneConfig &c, double *ms) -> int {
+        int r = apply_config(x, c);
+        if (r) return r;
+        if ((r = search(x, queries, nq, k, alpha, beta, ids, dists, st, nullptr))) return r;
+        TC_HIP(hipEventRecord(e0, st), "autotune timing");
+        for (int i = 0; i < 3; i++)
+            if ((r = search(x, queries, nq, k, alpha, beta, ids, dists, st, nullptr))) return r;
+        TC_HIP(hipEventRecord(e1, st), "autotune timing");
+        TC_HIP(hipEventSynchronize(e1), "autotune timing");
+        float f = 0.0f;
+        TC_HIP(hipEventElapsedTime(&f, e0, e1), "autotune timing");
+        *ms = f / 3.0;
+        rep << "W=" << c.W << " mode=" << c.mode << " qpw=" << c.qpw << " rr=" << c.rr
+            << " precision=" << c.precision << " ms=" << *ms << "\n";
+        return TC_OK;
+    };
+    TuneConfig best{x->W, x->count_mode == TC_COUNT_AUTO ? TC_COUNT_SPLIT : x->count_mode, x->probe_qpw,
+                    x->rr_blocks, x->precision};
+    double best_ms = 1e30;
+    // coordinate descent: tile width x count mode, then probe queries per
+    // workgroup, then re-rank workgroups per query, then re-rank precision
+    std::vector<int> Ws = x->bits == 4 ? std::vector<int>{65536, 131072, 262144}
+                                       : std::vector<int>{32768, 65536, 131072};
+    for (int W : Ws) {
+        if (taco::count_lds_bytes(W, x->bits) > size_t(x->max_lds)) continue;
+        for (int mode : {TC_COUNT_SPLIT, TC_COUNT_FUSED}) {
+            TuneConfig c = best;
+            c.W = W;
+            c.mode = mode;
+            if (mode == TC_COUNT_FUSED) {
+                // the fused form needs its groups resident at this width
+                if ((rc = tc_set_option(x, TC_OPT_TILE_IDS, W))) goto done;
+                if (x->fused_groups <= 0) continue;
+            }
+            double ms;
+            if ((rc = measure(c, &ms))) goto done;
+            if (ms < best_ms) best_ms = ms, best = c;
+        }
+    }
+    for (int qpw : {1, 2, 4, 8}) {
+        TuneConfig c = best;
+        c.qpw = qpw;
+        double ms;
+        if ((rc = measure(c, &ms))) goto done;
+        if (ms < best_ms) best_ms = ms, best = c;
+    }
+    for (int rr : {16, 32, 64}) {
+        TuneConfig c = best;
+        c.rr = rr;
+        double ms;
+        if ((rc = measure(c, &ms))) goto done;
+        if (ms < best_ms) best_ms = ms, best = c;
+    }
+    for (int p : {TC_FP32, TC_BF16}) {
+        TuneConfig c = best;
+        c.precision = p;
+        double ms;
+        if ((rc = measure(c, &ms))) goto done;
+        if (ms < best_ms) best_ms = ms, best = c;
+    }
+    rc = apply_config(x, best);
+    rep << "best W=" << best.W << " mode=" << best.mode << " qpw=" << best.qpw << " rr=" << best.rr
+        << " precision=" << best.precision << " ms=" << best_ms << "\n";
+    if (rc == TC_OK && cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        out << "{\"key\": \"" << key << "\", \"W\": " << best.W << ", \"mode\": " << best.mode
+            << ", \"qpw\": " << best.qpw << ", \"rr\": " << best.rr << ", \"precision\": " << best.precision
+            << ", \"ms\": " << best_ms << "}\n";
+    }
+done:
+    x->use_graph = graph;
+    x->profile = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(ids);
+    (void)hipFree(dists);
+    return finish(rc);
 }
 
 int tc_device_errors(tc_index *x, uint32_t *flags) {

@@ -219,3 +219,133 @@ def test_workload_shapes_split_mode(taco_mod, w):
     print(f"[{w.name}] split mode", flush=True)
     _run_all(t, path, oidx, Q, 10, 0.05, 0.005, 0, w.name + " split",
              options=((t.TC_OPT_COUNT_MODE, t.TC_COUNT_SPLIT),))
+
+
+def _batched_inputs(w, nq, seed=5):
+    alpha, k = synthdata.query_budgets(nq, seed)
+    return alpha, k
+
+
+@pytest.mark.parametrize("w", [synthdata.WORKLOADS["tiny-gmm-20k-d128"]] + scaled_workloads()[3:],
+                         ids=lambda w: w.name)
+def test_batched_per_query_budgets(taco_mod, w):
+    """tc_search_batched with query-aware budgets (alpha log-uniform in
+    [0.005, 0.1], k in {1, 10, 100}) matches the oracle query by query."""
+    import torch
+    t = taco_mod
+    X, Q = synthdata.base_and_queries(w)
+    path = workload_index(w, X)
+    oidx = O.OracleIndex(path)
+    alpha, k = _batched_inputs(w, Q.shape[0])
+    k_max = 100
+    print(f"[{w.name}] batched budgets", flush=True)
+    for prec in (t.TC_FP32, t.TC_BF16):
+        idx = t.Index(path, 0)
+        idx.set_option(t.TC_OPT_PRECISION, prec)
+        q = torch.from_numpy(Q).cuda()
+        ids, dists = idx.search_batched(q, torch.from_numpy(alpha).cuda(), torch.from_numpy(k).cuda(),
+                                        k_max, 0.005)
+        torch.cuda.synchronize()
+        assert idx.device_errors() == 0
+        ids, dists = ids.cpu().numpy(), dists.cpu().numpy()
+        idx.close()
+        for qi in range(Q.shape[0]):
+            r = oidx.query(Q[qi], float(alpha[qi]), 0.005, int(k[qi]))
+            kk = int(k[qi])
+            check_topk_row(ids[qi, :kk], dists[qi, :kk], r, f"{w.name} q{qi} k={kk}")
+            assert np.all(ids[qi, kk:] == -1) and np.all(np.isinf(dists[qi, kk:]))
+
+
+def check_topk_row(gi, gd, r, label):
+    from gpu_parity import check_topk
+    cand_d = np.full(int(r["sc"].size), np.inf)
+    cand_d[r["cand"]] = r["cand_d32"]
+    check_topk(gi, gd, r["ids"], r["d32"], cand_d, label)
+
+
+def test_batched_clamps_bad_budgets(taco_mod, tiny):
+    import torch
+    t = taco_mod
+    idx = t.Index(tiny["path"], 0)
+    q = torch.from_numpy(tiny["Q"][:4]).cuda()
+    alpha = torch.tensor([0.05, 0.0, 2.0, float("nan")], dtype=torch.float64, device="cuda")
+    k = torch.tensor([10, 0, 10, 11], dtype=torch.int32, device="cuda")
+    ids, _ = idx.search_batched(q, alpha, k, 10, 0.005)
+    torch.cuda.synchronize()
+    assert idx.device_errors() & 2
+    assert idx.device_errors() == 0  # cleared by the read
+    assert ids.shape == (4, 10)
+    with pytest.raises(t.TacoError):
+        idx.search_batched(q, alpha, k, 1025, 0.005)
+    idx.close()
+
+
+def test_graph_replays_match_eager(taco_mod, tiny):
+    """A captured search graph replayed several times, with eager work and
+    synchronizations between replays, gives the eager results every time, and
+    reads the current contents of its input buffers."""
+    import torch
+    t = taco_mod
+    Q = tiny["Q"]
+    idx = t.Index(tiny["path"], 0)
+    q = torch.from_numpy(Q[:50]).cuda()
+    alpha = torch.from_numpy(synthdata.query_budgets(50, 9)[0]).cuda()
+    kk = torch.full((50,), 10, dtype=torch.int32, device="cuda")
+    e_ids, e_d = idx.search(q, 10, 0.05, 0.005)
+    b_ids, b_d = idx.search_batched(q, alpha, kk, 10, 0.005)
+    torch.cuda.synchronize()
+    e_ids, e_d, b_ids, b_d = (x.clone() for x in (e_ids, e_d, b_ids, b_d))
+    idx.set_option(t.TC_OPT_GRAPH, 1)
+    ids = torch.empty((50, 10), dtype=torch.int64, device="cuda")
+    dists = torch.empty((50, 10), dtype=torch.float32, device="cuda")
+    for rep in range(4):
+        ids.fill_(-7)
+        idx.search(q, 10, 0.05, 0.005, ids=ids, dists=dists)
+        torch.cuda.synchronize()
+        assert torch.equal(ids, e_ids) and torch.equal(dists, e_d), rep
+        _ = (q * 2.0).sum().item()  # eager work between replays
+    for rep in range(3):
+        ids.fill_(-7)
+        idx.search_batched(q, alpha, kk, 10, 0.005, ids=ids, dists=dists)
+        torch.cuda.synchronize()
+        assert torch.equal(ids, b_ids) and torch.equal(dists, b_d), rep
+    # same pointers, new contents: the graph must read the new queries
+    q2 = torch.from_numpy(Q[50:100]).cuda()
+    idx.set_option(t.TC_OPT_GRAPH, 0)
+    e2_ids, e2_d = idx.search(q2, 10, 0.05, 0.005)
+    torch.cuda.synchronize()
+    idx.set_option(t.TC_OPT_GRAPH, 1)
+    idx.search(q, 10, 0.05, 0.005, ids=ids, dists=dists)
+    q.copy_(q2)
+    idx.search(q, 10, 0.05, 0.005, ids=ids, dists=dists)
+    torch.cuda.synchronize()
+    assert torch.equal(ids, e2_ids) and torch.equal(dists, e2_d)
+    assert idx.device_errors() == 0
+    idx.close()
+
+
+def test_autotune_keeps_results_and_caches(taco_mod, tiny, tmp_path):
+    import torch
+    t = taco_mod
+    idx = t.Index(tiny["path"], 0)
+    q = torch.from_numpy(tiny["Q"]).cuda()
+    ref_ids, ref_d = idx.search(q, 10, 0.05, 0.005)
+    torch.cuda.synchronize()
+    ref_ids, ref_d = ref_ids.clone(), ref_d.clone()
+    cache = str(tmp_path / "tune.jsonl")
+    rep = idx.autotune(q, 10, 0.05, 0.005, cache_path=cache)
+    print(rep, flush=True)
+    assert "best" in rep
+    ids, d = idx.search(q, 10, 0.05, 0.005)
+    torch.cuda.synchronize()
+    assert torch.equal(ids, ref_ids) and torch.equal(d, ref_d)
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"W"' in lines[0]
+    idx2 = t.Index(tiny["path"], 0)
+    rep2 = idx2.autotune(q, 10, 0.05, 0.005, cache_path=cache)
+    assert rep2.startswith("cached")
+    ids2, d2 = idx2.search(q, 10, 0.05, 0.005)
+    torch.cuda.synchronize()
+    assert torch.equal(ids2, ref_ids) and torch.equal(d2, ref_d)
+    idx.close()
+    idx2.close()
