@@ -15,7 +15,12 @@ Legs:
     oracle's Alg 1-3), computes the FP64 ground truth of the recall sample,
     and times the oracle's own query on a bounded sample on the host cores.
   * GPU leg: loads the index through the C-ABI and times K steps per alpha
-    with HIP events on the search stream, per kernel as well.
+    with HIP events on the search stream, per kernel as well, on two paths:
+    "fp32" (default launch configuration, FP32 re-rank) and "tuned" (the
+    library's autotuner picks tile width, count mode, probe packing, re-rank
+    spread and re-rank precision per alpha; results are identical to FP32).
+    The tuned path is also timed replaying its captured HIP graph.  The
+    reported value is the tuned path's; both paths are listed under "paths".
 
 Prints one JSON line.
 """
@@ -37,7 +42,7 @@ WORKLOAD = "gmm-int-1m-d128"
 METRIC = "QPS at recall@10=0.95 on 1 MI355X; BF16/FP8+batched vs FP32 plain"
 RECALL_TARGET = 0.95
 HBM_PEAK_GBS = 8000.0
-KERNELS = ("transform", "probe", "count", "select", "rerank", "topk")
+KERNELS = ("transform", "probe", "count", "select", "rerank", "topk", "recheck", "count_select")
 
 
 def log(msg):
@@ -78,20 +83,23 @@ def cpu_baseline_recall(ids, gt_d64, X, Qs, k):
 
 def cpu_baseline_timing(path, X, Q, w, gt, alphas, sample):
     """The oracle as it stands, parallel over queries with OpenMP on the host
-    cores, on `sample` queries per alpha; one warm-up query first."""
+    cores, timed on the first `sample` queries per alpha (one warm-up batch
+    first); its recall is read on the first queries that have ground truth."""
     from oracle import oracle as O
     oidx = O.OracleIndex(path)
     threads = O.max_threads()
     pts = []
     Qs = Q[:sample]
+    S = min(sample, gt[1].shape[0])
     for a in alphas:
         oidx.query_batch(Qs[:threads], a, w.beta, w.k)
         t = time.time()
         ids = oidx.query_batch(Qs, a, w.beta, w.k)
         dt = time.time() - t
-        rec = O.recall_at_k(ids, gt[1][:sample], X, Qs, w.k)
+        rec = O.recall_at_k(ids[:S], gt[1][:S], X, Qs[:S], w.k)
         pts.append(dict(alpha=a, qps=sample / dt, recall=rec, seconds=dt))
-        log(f"oracle alpha={a}: {sample / dt:.1f} QPS on {threads} threads, recall {rec:.4f}")
+        log(f"oracle alpha={a}: {sample / dt:.1f} QPS on {threads} threads over {sample} queries, "
+            f"recall {rec:.4f}")
     oidx.close()
     return pts, threads
 
@@ -101,19 +109,25 @@ def cpu_baseline_timing(path, X, Q, w, gt, alphas, sample):
 # ---------------------------------------------------------------------------
 
 def qps_at_recall(points, target=RECALL_TARGET):
-    """QPS at the target recall from (recall, qps) points: the best QPS of a
-    point at or above the target, or the linear interpolation between a
-    faster point below and a slower point above it (Pareto frontier)."""
-    best = None
-    for p in points:
-        if p["recall"] >= target:
-            best = p["qps"] if best is None else max(best, p["qps"])
-    for lo in points:
-        for hi in points:
-            if lo["recall"] < target <= hi["recall"] and lo["qps"] > hi["qps"]:
-                f = (hi["recall"] - target) / (hi["recall"] - lo["recall"])
-                v = hi["qps"] + f * (lo["qps"] - hi["qps"])
-                best = v if best is None else max(best, v)
+    """QPS at the target recall from (recall, qps) points: the Pareto
+    frontier (no other point has both higher recall and higher QPS), sorted
+    by recall, is read at the target -- the best QPS of a frontier point at
+    or above it, else None if no point reaches it, and where the frontier
+    steps across the target, the linear interpolation between the two
+    neighbouring frontier points if that is higher."""
+    front = [p for p in points
+             if not any(o["recall"] >= p["recall"] and o["qps"] >= p["qps"] and
+                        (o["recall"] > p["recall"] or o["qps"] > p["qps"]) for o in points)]
+    front.sort(key=lambda p: p["recall"])
+    above = [p for p in front if p["recall"] >= target]
+    if not above:
+        return None
+    best = max(p["qps"] for p in above)
+    below = [p for p in front if p["recall"] < target]
+    if below:
+        lo, hi = below[-1], above[0]
+        f = (hi["recall"] - target) / (hi["recall"] - lo["recall"])
+        best = max(best, hi["qps"] + f * (lo["qps"] - hi["qps"]))
     return best
 
 
@@ -141,13 +155,16 @@ def traffic_from_profiles(kernel):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def algorithmic_bytes(idx, q, w, alpha, nq):
+def algorithmic_bytes(idx, q, w, alpha, nq, bf16=False):
     """Bytes the method must move, per kernel, for one step at this alpha:
     count: ids of the probed lists (4 B each) + the slice bounds and probed
     cell ids (12 B per probed cell); select: the candidate ids written (4 B);
-    rerank: each candidate's row (4d B), id and distance (8 B) plus the query
-    (4d B); topk: candidate keys (8 B each) and the output (12k B)."""
+    count_select: both; rerank: each candidate's row (4d B, or 2d B plus its
+    4 B error bound in BF16), id and distance (8 B) plus the query (4d B);
+    topk: candidate keys (8 B each) and the output (12k B); recheck: the
+    candidates' lower bounds (4 B each)."""
     import torch
+    import paper_2603_24919_amd as taco
     dump = idx.dump_buffers(nq, ("retrieved", "ncells", "ncand"))
     idx.search_debug(q, w.k, alpha, w.beta, dump)
     torch.cuda.synchronize()
@@ -160,9 +177,141 @@ def algorithmic_bytes(idx, q, w, alpha, nq):
         probe=nq * w.M * 4.0 + 4.0 * P,
         count=4.0 * R + 12.0 * P,
         select=4.0 * C + 4.0 * P,
-        rerank=C * (4.0 * d + 8.0) + nq * 4.0 * d,
+        count_select=4.0 * R + 16.0 * P + 4.0 * C,
+        rerank=C * ((2.0 * d + 4.0 if bf16 else 4.0 * d) + 8.0) + nq * 4.0 * d,
         topk=8.0 * C + 12.0 * w.k * nq,
+        recheck=4.0 * C,
     ), dict(retrieved=R / nq, probed_cells=P / nq, candidates=C / nq)
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries (run after a profiled bench; they read only its CSVs)
+# ---------------------------------------------------------------------------
+
+_SHORT = (("k_count_select", "count_select"), ("k_count", "count"), ("k_select", "select"),
+          ("k_rerank16", "rerank"), ("k_rerank", "rerank"), ("k_recheck", "recheck"),
+          ("k_topk", "topk"), ("k_probe", "probe"), ("k_transform", "transform"),
+          ("k_prep_bf16", "prep_bf16"), ("k_build_off2d", "build_off2d"), ("k_budgets", "budgets"),
+          ("k_fill_u32", "fill"), ("k_u32_to_i64", "u32_to_i64"))
+
+
+def short_kernel_name(full):
+    for key, short in _SHORT:
+        if "taco::" + key + "<" in full or "taco::" + key + "(" in full:
+            return short
+    return None
+
+
+def summarize_stats(stats_csv, bench_json, out_md, command):
+    """Markdown table of rocprofv3's per-kernel statistics (its
+    kernel_stats.csv, or the results database) next to the bench's own
+    HIP-event timing of the same run."""
+    import csv
+    line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    op = line["roofline"]
+    pts = line["paths"][op["path"]]["points"]
+    ev = next(p for p in pts if p["alpha"] == op["alpha"])["kernels"]
+    if stats_csv.endswith(".db"):
+        import sqlite3
+        con = sqlite3.connect(stats_csv)
+        rows = [dict(Name=r[0], Calls=r[1], TotalDurationNs=r[2] * 1e3, AverageNs=r[3] * 1e3, Percentage=r[4])
+                for r in con.execute("select name, total_calls, total_duration, average, percentage "
+                                     "from top_kernels order by total_duration desc")]
+    else:
+        rows = list(csv.DictReader(open(stats_csv)))
+    out = [f"# rocprofv3 kernel statistics: {line['config']['workload']}, alpha={op['alpha']}, "
+           f"{op['path']} path", "", "Command (from the repository root, TMPDIR=/tmp):", "",
+           "```", command, "```", "",
+           f"Tuned configuration: {line['config'].get('tuned_config')}", "",
+           "rocprofv3 averages cover every launch of the process (warm-up, the timed steps, the "
+           "stage-count pass and the recall pass); the bench column is the HIP-event average "
+           "over the timed steps only.", "",
+           "| kernel | calls | rocprof avg (us) | bench avg (us) | rocprof total (ms) | % |",
+           "|---|---|---|---|---|---|"]
+    for r in rows:
+        short = short_kernel_name(r["Name"])
+        b = ev.get(short, {}).get("ms_per_launch") if short else None
+        out.append(f"| {short or r['Name'][:40]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{'' if b is None else f'{b * 1e3:.1f}'} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                   f"{float(r['Percentage']):.1f} |")
+    out += ["", f"Dominant kernel at the operating point: {op['kernel']}, "
+            f"{op['alg_bytes_per_launch'] / 1e6:.1f} MB algorithmic per launch, "
+            f"{op['achieved']:.1f} GB/s achieved = {op['frac']:.4f} of {op['peak']:.0f} GB/s.", ""]
+    open(out_md, "w").write("\n".join(out))
+
+
+def _counter_means(csv_path, counter):
+    import csv
+    per = {}
+    copies = []
+    if csv_path.endswith(".db"):
+        import sqlite3
+        con = sqlite3.connect(csv_path)
+        src = [dict(Kernel_Name=r[0], Counter_Name=r[1], Counter_Value=r[2]) for r in
+               con.execute("select kernel_name, counter_name, value from counters_collection")]
+    else:
+        src = csv.DictReader(open(csv_path))
+    for r in src:
+        if r["Counter_Name"] != counter:
+            continue
+        v = float(r["Counter_Value"])
+        if "copyBuffer" in r["Kernel_Name"]:
+            copies.append(v)
+            continue
+        short = short_kernel_name(r["Kernel_Name"])
+        if short:
+            per.setdefault(short, []).append(v)
+    return {k: (sum(v) / len(v), len(v)) for k, v in per.items()}, copies
+
+
+def summarize_traffic(fetch_csv, write_csv, bench_json, out_json, command, copy_bytes=1 << 30):
+    """HBM bytes per launch from FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch), each scaled by what the same counter reads for a device copy
+    of `copy_bytes` (the largest copy dispatch of the run)."""
+    line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    fetch, fc = _counter_means(fetch_csv, "FETCH_SIZE")
+    write, wc = _counter_means(write_csv, "WRITE_SIZE")
+    f_scale = copy_bytes / (max(fc) * 1024.0) if fc else 1.0
+    w_scale = copy_bytes / (max(wc) * 1024.0) if wc else 1.0
+    kern = {}
+    for k in sorted(set(fetch) | set(write)):
+        fk, nf = fetch.get(k, (0.0, 0))
+        wk, nw = write.get(k, (0.0, 0))
+        kern[k] = dict(fetch_KiB=fk, write_KiB=wk, dispatches=max(nf, nw),
+                       hbm_bytes_per_launch=fk * 1024.0 * f_scale + wk * 1024.0 * w_scale)
+    rec = dict(workload=line["config"]["workload"], alpha=line["config"]["alpha"],
+               path=line["config"]["path"], tuned_config=line["config"].get("tuned_config"),
+               source_hash=source_hash(), copy_bytes=copy_bytes,
+               fetch_scale=f_scale, write_scale=w_scale,
+               copy_fetch_KiB=max(fc) if fc else None, copy_write_KiB=max(wc) if wc else None,
+               command=command, kernels=kern)
+    json.dump(rec, open(out_json, "w"), indent=1)
+
+
+def timed_steps(idx, taco, qd, w, a, ids, dists, stream, steps, warmup, profile=True):
+    """Warm-up, then exactly `steps` searches of the whole batch between two
+    events on the search stream.  Returns (ms, per-kernel totals)."""
+    import torch
+    for _ in range(warmup):
+        idx.search(qd, w.k, a, w.beta, ids=ids, dists=dists, stream=stream)
+    torch.cuda.synchronize()
+    if profile:
+        idx.set_option(taco.TC_OPT_PROFILE, 1)
+        idx.profile_reset()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        idx.search(qd, w.k, a, w.beta, ids=ids, dists=dists, stream=stream)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    kern = {}
+    if profile:
+        for kname in KERNELS:
+            tot, n = idx.kernel_time(kname)
+            kern[kname] = dict(ms_total=tot, launches=n)
+        idx.set_option(taco.TC_OPT_PROFILE, 0)
+    return start.elapsed_time(stop), kern
 
 
 def main():
@@ -171,10 +320,27 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--recall-sample", type=int, default=1000)
-    ap.add_argument("--cpu-sample", type=int, default=400)
+    ap.add_argument("--cpu-sample", type=int, default=4000)
+    ap.add_argument("--alpha", type=float, default=None,
+                    help="run only this collision ratio of the sweep (profiling runs)")
+    ap.add_argument("--paths", default="fp32,tuned", help="comma list of fp32, tuned")
     ap.add_argument("--skip-cpu-baseline", action="store_true",
                     help="omit the oracle timing (profiling runs); the line then has no cpu_baseline")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotune cache file (JSON lines); default a file under TMPDIR")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (a known-size kernel for counter scaling)")
+    ap.add_argument("--summarize-stats", nargs=2, metavar=("KERNEL_STATS_CSV", "BENCH_JSON"))
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"))
+    ap.add_argument("--summary-out")
+    ap.add_argument("--summary-command", default="")
     args = ap.parse_args()
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats, args.summary_out, args.summary_command)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, args.summary_out, args.summary_command)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps(dict(error="this build measures one GPU only; run with --gpus 1",
@@ -185,6 +351,8 @@ def main():
     import paper_2603_24919_amd as taco
 
     w = synthdata.WORKLOADS[WORKLOAD]
+    alphas = list(w.alphas) if args.alpha is None else [args.alpha]
+    paths = [p for p in args.paths.split(",") if p]
     t0 = time.time()
     X, Q = synthdata.base_and_queries(w)
     log(f"generated {w.n}x{w.d} base and {w.nq} queries in {time.time() - t0:.1f}s")
@@ -194,85 +362,103 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    idx = taco.Index(path, 0)
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copied 1 GiB device-to-device for counter calibration")
     qd = torch.from_numpy(Q).to(dev)
     ids = torch.empty((w.nq, w.k), dtype=torch.int64, device=dev)
     dists = torch.empty((w.nq, w.k), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
-    batches = -(-w.nq // idx.batch_capacity())
+    tune_cache = args.tune_cache or os.path.join(os.environ.get("TMPDIR", "/tmp"), "taco_bench_tune.jsonl")
 
-    sweep = []
-    for a in w.alphas:
-        for _ in range(args.warmup):
-            idx.search(qd, w.k, a, w.beta, ids=ids, dists=dists, stream=stream)
-        torch.cuda.synchronize()
-        idx.set_option(taco.TC_OPT_PROFILE, 1)
-        idx.profile_reset()
-        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        start.record(stream)
-        for _ in range(args.steps):
-            idx.search(qd, w.k, a, w.beta, ids=ids, dists=dists, stream=stream)
-        stop.record(stream)
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(stop)
-        kern = {}
-        for kname in KERNELS:
-            tot, n = idx.kernel_time(kname)
-            kern[kname] = dict(ms_total=tot, launches=n)
-        idx.set_option(taco.TC_OPT_PROFILE, 0)
-        rec = cpu_baseline_recall(ids[:S].cpu().numpy(), gt[1], X, Q[:S], w.k)
-        alg, avg = algorithmic_bytes(idx, qd, w, a, w.nq)
-        for kname in KERNELS:
-            launches = max(kern[kname]["launches"], 1)
-            kern[kname]["ms_per_launch"] = kern[kname]["ms_total"] / launches
-            kern[kname]["alg_bytes_per_launch"] = alg[kname] / batches
-            kern[kname]["alg_GBps"] = (alg[kname] / batches) / (kern[kname]["ms_per_launch"] * 1e-3) / 1e9 \
-                if kern[kname]["ms_per_launch"] > 0 else None
-        qps = w.nq * args.steps / (ms * 1e-3)
-        sweep.append(dict(alpha=a, qps=qps, recall=rec, ms_per_step=ms / args.steps, kernels=kern,
-                          per_query=avg))
-        log(f"GPU alpha={a}: {qps:,.0f} QPS, {ms / args.steps:.3f} ms/step, recall@10 {rec:.4f}; "
-            + ", ".join(f"{k} {v['ms_total'] / args.steps:.3f}" for k, v in kern.items()))
+    results = {}
+    for pname in paths:
+        idx = taco.Index(path, 0)
+        sweep = []
+        for a in alphas:
+            tuned = None
+            if pname == "tuned":
+                tuned = idx.autotune(qd, w.k, a, w.beta, cache_path=tune_cache, stream=stream)
+                log(f"tuned alpha={a}: " + tuned.strip().splitlines()[-1])
+            batches = -(-w.nq // idx.batch_capacity())
+            ms, kern = timed_steps(idx, taco, qd, w, a, ids, dists, stream, args.steps, args.warmup)
+            rec = cpu_baseline_recall(ids[:S].cpu().numpy(), gt[1], X, Q[:S], w.k)
+            alg, avg = algorithmic_bytes(idx, qd, w, a, w.nq,
+                                         bf16=tuned is not None and "precision=1" in tuned.strip().splitlines()[-1])
+            for kname in KERNELS:
+                launches = max(kern[kname]["launches"], 1)
+                kern[kname]["ms_per_launch"] = kern[kname]["ms_total"] / launches
+                b = alg.get(kname)
+                kern[kname]["alg_bytes_per_launch"] = None if b is None else b * args.steps / launches
+                kern[kname]["alg_GBps"] = None if (b is None or kern[kname]["ms_total"] <= 0) else \
+                    (b * args.steps) / (kern[kname]["ms_total"] * 1e-3) / 1e9
+            qps = w.nq * args.steps / (ms * 1e-3)
+            point = dict(alpha=a, qps=qps, recall=rec, ms_per_step=ms / args.steps, kernels=kern,
+                         per_query=avg, batches_per_step=batches)
+            if pname == "tuned":
+                point["config"] = tuned.strip().splitlines()[-1]
+                idx.set_option(taco.TC_OPT_GRAPH, 1)
+                gms, _ = timed_steps(idx, taco, qd, w, a, ids, dists, stream, args.steps, args.warmup,
+                                     profile=False)
+                idx.set_option(taco.TC_OPT_GRAPH, 0)
+                point["graph_qps"] = w.nq * args.steps / (gms * 1e-3)
+            sweep.append(point)
+            log(f"{pname} alpha={a}: {qps:,.0f} QPS, {ms / args.steps:.3f} ms/step, recall@10 {rec:.4f}; "
+                + ", ".join(f"{k} {v['ms_total'] / args.steps:.3f}" for k, v in kern.items()
+                            if v["ms_total"] > 0)
+                + (f"; graph {point['graph_qps']:,.0f} QPS" if "graph_qps" in point else ""))
+        idx.close()
+        results[pname] = sweep
 
+    main_path = "tuned" if "tuned" in results else paths[0]
+    sweep = results[main_path]
     value = qps_at_recall(sweep)
-    # operating point: the fastest alpha at or above the target (else the
-    # most accurate one)
     ok = [p for p in sweep if p["recall"] >= RECALL_TARGET]
     op = max(ok, key=lambda p: p["qps"]) if ok else max(sweep, key=lambda p: p["recall"])
-    dom = max(KERNELS, key=lambda k_: op["kernels"][k_]["ms_total"])
+    dom = max(op["kernels"], key=lambda k_: op["kernels"][k_]["ms_total"])
     dk = op["kernels"][dom]
     achieved = dk["alg_GBps"]
     traffic = traffic_from_profiles(dom)
     roofline = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=None if achieved is None else achieved / HBM_PEAK_GBS,
                     traffic=traffic, alg_bytes_per_launch=dk["alg_bytes_per_launch"],
-                    ms_per_launch=dk["ms_per_launch"])
+                    ms_per_launch=dk["ms_per_launch"], alpha=op["alpha"], path=main_path)
 
     cpu = None
     if not args.skip_cpu_baseline:
-        pts, threads = cpu_baseline_timing(path, X, Q, w, gt, w.alphas, min(args.cpu_sample, S))
-        cpu_v = qps_at_recall(pts)
-        cpu = dict(value=cpu_v, unit="queries/s", cores=threads, kind="oracle",
-                   sample=f"first {min(args.cpu_sample, S)} queries at each alpha of the sweep, "
-                          f"OpenMP over queries; value read at recall@10=0.95 like the GPU's",
+        cs = min(args.cpu_sample, w.nq)
+        pts, threads = cpu_baseline_timing(path, X, Q, w, gt, alphas, cs)
+        cpu = dict(value=qps_at_recall(pts), unit="queries/s", cores=threads, kind="oracle",
+                   sample=f"first {cs} of the {w.nq} queries at each alpha of the sweep, OpenMP over "
+                          f"queries, recall on the first {min(cs, S)}; value read at recall@10=0.95 "
+                          f"like the GPU's",
+                   seconds=sum(p["seconds"] for p in pts),
                    points=[dict(alpha=p["alpha"], qps=p["qps"], recall=p["recall"]) for p in pts])
 
+    prec_bf16 = "precision=1" in str(op.get("config", ""))
     line = dict(
         metric=METRIC, value=value, unit="queries/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=op["ms_per_step"], higher_is_better=True, scaling="weak",
-        vs_baseline=None, dtype="f32", data="synthetic",
+        vs_baseline=None, dtype="bf16+f32" if prec_bf16 else "f32", data="synthetic",
         config=dict(workload=WORKLOAD, n=w.n, d=w.d, Ns=w.Ns, s=w.s, l=w.l,
-                    queries_per_step=w.nq, k=w.k, beta=w.beta, alphas=list(w.alphas),
-                    alpha=op["alpha"], path="fp32-plain", recall_at_10=op["recall"],
-                    recall_sample=S, batches_per_step=batches),
-        sweep=[dict(alpha=p["alpha"], qps=p["qps"], recall=p["recall"], ms_per_step=p["ms_per_step"],
-                    per_query=p["per_query"],
-                    kernels={k_: dict(ms_per_launch=v["ms_per_launch"], launches=v["launches"],
-                                      alg_GBps=v["alg_GBps"]) for k_, v in p["kernels"].items()})
-               for p in sweep],
+                    queries_per_step=w.nq, k=w.k, beta=w.beta, alphas=alphas,
+                    alpha=op["alpha"], path=main_path, recall_at_10=op["recall"],
+                    recall_sample=S, batches_per_step=op["batches_per_step"],
+                    tuned_config=op.get("config")),
+        paths={pn: dict(value=qps_at_recall(sw),
+                        points=[dict(alpha=p["alpha"], qps=p["qps"], recall=p["recall"],
+                                     ms_per_step=p["ms_per_step"], graph_qps=p.get("graph_qps"),
+                                     config=p.get("config"), per_query=p["per_query"],
+                                     kernels={k_: dict(ms_per_launch=v["ms_per_launch"],
+                                                       launches=v["launches"], alg_GBps=v["alg_GBps"])
+                                              for k_, v in p["kernels"].items() if v["launches"]})
+                                for p in sw])
+               for pn, sw in results.items()},
         roofline=roofline, cpu_baseline=cpu)
-    idx.close()
     print(json.dumps(line), flush=True)
 
 

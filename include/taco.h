@@ -121,7 +121,8 @@ enum tc_precision { TC_FP32 = 0, TC_BF16 = 1 };
  *   out    host; receives the new index (NULL on failure).
  * Returns TC_EIO (unreadable), TC_EFORMAT (bad header, checksum, offsets not
  * partitioning [0,n), ids out of range or not ascending in a cell, Ns > 16,
- * l > 64, n >= 2^31), TC_ENOMEM or TC_EDEVICE.  Synchronous.
+ * l > 64, n >= 2^31, Ns*n >= 2^30 -- the id lists are addressed with 32-bit
+ * byte offsets), TC_ENOMEM or TC_EDEVICE.  Synchronous.
  */
 int tc_load_index(const char *path, int device, tc_index **out);
 

@@ -39,13 +39,13 @@ hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, i
                         float *dump_cdist, int32_t *dump_corder, int qpw, hipStream_t st);
 hipError_t launch_budgets(const double *alpha, const int32_t *kq, int nq, int64_t n, int k_max,
                           int64_t *A, int32_t *kc, uint32_t *err, hipStream_t st);
-hipError_t prepare_count_kernels(int W, int bits);
+hipError_t prepare_count_kernels(int W, int bits, int Ns);
 size_t count_lds_bytes(int W, int bits);
 hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, hipStream_t st);
 hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
                          hipStream_t st);
 size_t fused_lds_bytes(int W, int bits);
-hipError_t fused_max_blocks(int W, int bits, int *blocks_per_cu);
+hipError_t fused_max_blocks(int W, int bits, int Ns, int *blocks_per_cu);
 hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int NG, uint32_t *arrive,
                                uint32_t *err, uint32_t spin_limit, hipStream_t st);
 int rerank_lanes_per_row(int d);

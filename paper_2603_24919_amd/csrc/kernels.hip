@@ -301,11 +301,16 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 // nibbles when Ns <= 15, bytes when Ns = 16 (adding 1 << BITS*(id%slot)
 // never carries because counts never exceed Ns).  The probed cells of all Ns
 // subspaces form one list.  For a chunk of CT_CHUNK of them, every thread
-// first looks up (in parallel) the slice of a cell's id list that falls in
-// the tile (index-time table off2d) into LDS; then groups of CT_LPS lanes
-// walk whole slices, reading consecutive ids, CT_UNROLL slices in flight per
-// group.  The tile's level histogram and its packed counts go to HBM; the
-// select kernel streams the packed counts back.
+// looks up (index-time table off2d) the slice of one cell's id list that
+// falls in the tile; the non-empty slices are compacted and laid end to end
+// as one run of "positions" (block-wide prefix sums).  Wavefronts then walk
+// that run in windows of 64 consecutive positions, CT_UNROLL windows in
+// flight, so every lane reads one id per window whatever the slice lengths
+// (cell sizes are skewed: a few long slices would otherwise serialise their
+// walker).  A window table names the slice holding each window's first
+// position; a lane steps forward from it across the (rare) slice boundaries
+// inside its window.  The tile's level histogram and its packed counts go to
+// HBM; the select kernel streams the packed counts back.
 // ---------------------------------------------------------------------------
 
 #ifndef TACO_CT_BLOCK
@@ -314,14 +319,11 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 #ifndef TACO_CT_UNROLL
 #define TACO_CT_UNROLL 8
 #endif
-#ifndef TACO_CT_LPS
-#define TACO_CT_LPS 64
-#endif
 constexpr int CT_BLOCK = TACO_CT_BLOCK;
-constexpr int CT_UNROLL = TACO_CT_UNROLL;
-constexpr int CT_LPS = TACO_CT_LPS;             // lanes per slice
-constexpr int CT_GROUPS = CT_BLOCK / CT_LPS;    // slice walkers per workgroup
-constexpr int CT_CHUNK = 1024;                  // slices staged in LDS at a time
+constexpr int CT_UNROLL = TACO_CT_UNROLL;       // windows in flight per wavefront
+constexpr int CT_WAVES = CT_BLOCK / WAVE;
+constexpr int CT_CHUNK = CT_BLOCK;              // slices staged at a time, one per thread
+constexpr int CT_WT = 1024;                     // windows per position segment
 constexpr int CT_STAGE = 256;                   // per-wavefront candidate staging slots
 
 struct CountArgs {
@@ -333,26 +335,40 @@ struct CountArgs {
     const int32_t *ncells;   // [nq][Ns]
 };
 
-// LDS carve-up of k_count (dynamic part).
+// LDS carve-up of k_count (dynamic part).  dl and pos are adjacent (the
+// fused kernel stages candidates there once counting is done).
 struct CountLds {
-    uint64_t *st;     // [CT_CHUNK] slice start in ids
-    uint32_t *len;    // [CT_CHUNK] slice length
     uint32_t *cnt;    // W*BITS/32 words of packed counts
+    uint32_t *dl;     // [CT_CHUNK] start (element of ids) minus first position, per
+                      // non-empty slice: position p of the slice is element dl + p
+    uint32_t *pos;    // [CT_CHUNK + 1] first position of each non-empty slice
+    uint16_t *wt;     // [CT_WT] slice holding the first position of each window
     int32_t *pP;      // [17] prefix of probed cells over subspaces
+    uint32_t *wsum;   // [2 * CT_WAVES] per-wavefront totals of the prefix sums
 };
 
 __host__ __device__ constexpr size_t count_lds_size(int W, int bits) {
-    return static_cast<size_t>(CT_CHUNK) * 12 + static_cast<size_t>(W) * bits / 8 + 17 * 4;
+    return static_cast<size_t>(W) * bits / 8 + static_cast<size_t>(CT_CHUNK) * 4 +
+           static_cast<size_t>(CT_CHUNK + 1) * 4 + static_cast<size_t>(CT_WT) * 2 + 17 * 4 +
+           2 * CT_WAVES * 4;
 }
 
 template <int BITS>
 __device__ __forceinline__ CountLds carve(unsigned char *lds, int W) {
     CountLds c;
-    c.st = reinterpret_cast<uint64_t *>(lds);
-    c.len = reinterpret_cast<uint32_t *>(lds + CT_CHUNK * 8);
-    c.cnt = c.len + CT_CHUNK;
-    c.pP = reinterpret_cast<int32_t *>(c.cnt + W / (32 / BITS));
+    c.cnt = reinterpret_cast<uint32_t *>(lds);
+    c.dl = c.cnt + W / (32 / BITS);
+    c.pos = c.dl + CT_CHUNK;
+    c.wt = reinterpret_cast<uint16_t *>(c.pos + CT_CHUNK + 1);
+    c.pP = reinterpret_cast<int32_t *>(c.wt + CT_WT);
+    c.wsum = reinterpret_cast<uint32_t *>(c.pP + 17);
     return c;
+}
+
+// Id j*n + i of the id lists [Ns][n]; the index loader guarantees Ns*n <
+// 2^30, so the byte offset fits 32 bits and the load takes a scalar base.
+__device__ __forceinline__ uint32_t load_id(const uint32_t *ids, uint32_t e) {
+    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const unsigned char *>(ids) + (e << 2));
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -361,10 +377,55 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Adds one to the packed count of tile-local id loc; returns the count it
+// held before.
 template <int BITS>
-__device__ __forceinline__ void bump(uint32_t *cnt, uint32_t loc) {
+__device__ __forceinline__ uint32_t bump(uint32_t *cnt, uint32_t loc) {
     constexpr uint32_t PER = 32 / BITS;
-    atomicAdd(&cnt[loc / PER], 1u << ((loc % PER) * BITS));
+    const uint32_t sh = (loc % PER) * BITS;
+    const uint32_t old = atomicAdd(&cnt[loc / PER], 1u << sh);
+    return (old >> sh) & ((1u << BITS) - 1u);
+}
+
+// Level transitions seen by one lane.  Byte c of lo (c < 8) or of hi (c >=
+// 8) counts the bumps that found a count of c.  An id's count rises by one
+// per bump, so the ids whose final count is >= v are exactly the bumps that
+// found v - 1: the tile's level histogram is the sum of these bytes over
+// all lanes, with no pass over the counts.  HI: counts of 8 and more occur
+// (Ns > 8).  A byte holds at most 255: the walk flushes before that.
+template <bool HI>
+struct Trans {
+    uint64_t lo, hi;
+    __device__ __forceinline__ void add(uint32_t c) {
+        const uint64_t inc = 1ull << ((c & 7u) << 3);
+        if (!HI || c < 8u)
+            lo += inc;
+        else
+            hi += inc;
+    }
+};
+
+// Adds the wavefront's transitions to hsum[c + 1] ("ids with count >=
+// c + 1") and clears them.  Bytes are spread to 16-bit fields first; a
+// field's wavefront sum is at most 64 * 255 and cannot carry.
+__device__ __forceinline__ void trans_fold(uint64_t x, int base, uint32_t *hsum, int lane) {
+    const uint64_t ev = x & 0x00FF00FF00FF00FFull, od = (x >> 8) & 0x00FF00FF00FF00FFull;
+    const uint32_t s0 = wave_sum_u32(static_cast<uint32_t>(ev)), s1 = wave_sum_u32(static_cast<uint32_t>(ev >> 32));
+    const uint32_t s2 = wave_sum_u32(static_cast<uint32_t>(od)), s3 = wave_sum_u32(static_cast<uint32_t>(od >> 32));
+    if (lane == 0) {
+        const uint32_t v[8] = {s0 & 0xffffu, s2 & 0xffffu, s0 >> 16, s2 >> 16,
+                               s1 & 0xffffu, s3 & 0xffffu, s1 >> 16, s3 >> 16};
+#pragma unroll
+        for (int c = 0; c < 8; c++)
+            if (v[c]) atomicAdd(&hsum[base + c + 1], v[c]);
+    }
+}
+
+template <bool HI>
+__device__ __forceinline__ void trans_flush(Trans<HI> &T, uint32_t *hsum, int lane) {
+    if (__any(T.lo != 0ull)) trans_fold(T.lo, 0, hsum, lane);
+    if (HI && __any(T.hi != 0ull)) trans_fold(T.hi, 8, hsum, lane);
+    T.lo = T.hi = 0ull;
 }
 
 // Byte masks of the counts >= v held in a packed word: bit 7 of byte b of
@@ -384,9 +445,64 @@ __device__ __forceinline__ void ge_masks(uint32_t w, uint32_t v, uint32_t &m0, u
     }
 }
 
-// Counts the collisions of tile t of query q into L.cnt.
-template <int BITS>
-__device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L) {
+// One round of a wavefront's walk: windows w0 + u*CT_WAVES (u < CT_UNROLL)
+// of the current position segment, one position per lane and window.  The
+// lane's slice is the window's first slice s0 (window table) plus the number
+// of slice ends at or below its position; those ends are pos[s0+1..], held
+// one per lane, and only the few that fall inside the window (a ballot)
+// are compared.  GUARD: some windows or positions of the round lie past the
+// segment (its last round); otherwise no lane needs a bounds test.
+template <int BITS, bool HI, bool GUARD>
+__device__ __forceinline__ void walk_round(const CountArgs &a, const CountLds &L, uint32_t seg,
+                                           uint32_t seg_end, uint32_t nwin, uint32_t tne, uint32_t w0,
+                                           uint32_t tile_lo, int lane, Trans<HI> &tr) {
+    uint32_t s0[CT_UNROLL], e[CT_UNROLL], id[CT_UNROLL];
+#pragma unroll
+    for (int u = 0; u < CT_UNROLL; u++) {
+        const uint32_t wi = w0 + u * CT_WAVES;
+        s0[u] = (!GUARD || wi < nwin) ? __builtin_amdgcn_readfirstlane(L.wt[wi]) : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < CT_UNROLL; u++) e[u] = L.pos[min(s0[u] + 1u + static_cast<uint32_t>(lane), tne)];
+#pragma unroll
+    for (int u = 0; u < CT_UNROLL; u++) {
+        const uint32_t wi = w0 + u * CT_WAVES;
+        const uint32_t p0 = seg + wi * WAVE, p = p0 + static_cast<uint32_t>(lane);
+        // ends inside the window sit in the lowest lanes (pos ascends); the
+        // clamped lanes past tne hold the run's end, which no valid p reaches
+        const int k = (!GUARD || wi < nwin) ? __popcll(__ballot(e[u] < p0 + WAVE)) : 0;
+        uint32_t sl = s0[u];
+        for (int b = 0; b < k; b++)
+            sl += static_cast<uint32_t>(__builtin_amdgcn_readlane(e[u], b)) <= p ? 1u : 0u;
+        e[u] = sl;
+    }
+#pragma unroll
+    for (int u = 0; u < CT_UNROLL; u++) e[u] = L.dl[GUARD ? min(e[u], tne - 1u) : e[u]];
+#pragma unroll
+    for (int u = 0; u < CT_UNROLL; u++) {
+        const uint32_t p = seg + (w0 + u * CT_WAVES) * WAVE + static_cast<uint32_t>(lane);
+        if (GUARD) {
+            id[u] = 0xffffffffu;
+            if (p < seg_end) id[u] = load_id(a.ids, e[u] + p);
+        } else {
+            id[u] = load_id(a.ids, e[u] + p);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < CT_UNROLL; u++) {
+        if (GUARD) {
+            if (id[u] != 0xffffffffu) tr.add(bump<BITS>(L.cnt, id[u] - tile_lo));
+        } else {
+            tr.add(bump<BITS>(L.cnt, id[u] - tile_lo));
+        }
+    }
+}
+
+// Counts the collisions of tile t of query q into L.cnt and adds the
+// tile's "count >= v" totals to hsum[v] (hsum zeroed by the caller before;
+// complete after the caller's next barrier).
+template <int BITS, bool HI>
+__device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, uint32_t *hsum) {
     const int words = a.W / (32 / BITS);
     for (int i = threadIdx.x; i < words; i += CT_BLOCK) L.cnt[i] = 0u;
     if (threadIdx.x == 0) {
@@ -401,94 +517,89 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L) 
     const int totalP = L.pP[a.Ns];
     const uint32_t tile_lo = static_cast<uint32_t>(t) * static_cast<uint32_t>(a.W);
     const int32_t *cq = a.cells + static_cast<int64_t>(q) * a.Ns * a.K;
-    const int grp = threadIdx.x / CT_LPS, lig = threadIdx.x % CT_LPS;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    Trans<HI> tr{0ull, 0ull};
+    int held = 0;  // bound on any byte of tr: bumps per lane since the last flush
     for (int c0 = 0; c0 < totalP; c0 += CT_CHUNK) {
         const int nsl = min(CT_CHUNK, totalP - c0);
-        for (int i = threadIdx.x; i < nsl; i += CT_BLOCK) {
-            const int g = c0 + i;
+        // this thread's slice
+        uint32_t len = 0u, st = 0u;
+        if (static_cast<int>(threadIdx.x) < nsl) {
+            const int g = c0 + static_cast<int>(threadIdx.x);
             int j = 0;
             while (L.pP[j + 1] <= g) j++;
             const int cell = cq[static_cast<int64_t>(j) * a.K + (g - L.pP[j])];
             const int64_t b = (static_cast<int64_t>(j) * a.K + cell) * (a.T + 1) + t;
             const uint32_t lo = a.off2d[b];
-            L.len[i] = a.off2d[b + 1] - lo;
-            L.st[i] = static_cast<uint64_t>(j) * static_cast<uint64_t>(a.n) + lo;
+            len = a.off2d[b + 1] - lo;
+            st = static_cast<uint32_t>(j) * static_cast<uint32_t>(a.n) + lo;
+        }
+        // compacted index and first position of each non-empty slice
+        const uint32_t ne = len > 0u ? 1u : 0u;
+        const uint32_t ine = wave_incl_scan_u32(ne, lane), ipos = wave_incl_scan_u32(len, lane);
+        if (lane == WAVE - 1) {
+            L.wsum[wave] = ine;
+            L.wsum[CT_WAVES + wave] = ipos;
         }
         __syncthreads();
-        for (int s0 = grp; s0 < nsl; s0 += CT_GROUPS * CT_UNROLL) {
-            uint32_t id[CT_UNROLL];
-#pragma unroll
-            for (int u = 0; u < CT_UNROLL; u++) {
-                const int s = s0 + u * CT_GROUPS;
-                id[u] = 0xffffffffu;
-                if (s < nsl && static_cast<uint32_t>(lig) < L.len[s]) id[u] = a.ids[L.st[s] + lig];
-            }
-#pragma unroll
-            for (int u = 0; u < CT_UNROLL; u++)
-                if (id[u] != 0xffffffffu) bump<BITS>(L.cnt, id[u] - tile_lo);
-            // the rest of slices longer than one pass
-#pragma unroll 1
-            for (int u = 0; u < CT_UNROLL; u++) {
-                const int s = s0 + u * CT_GROUPS;
-                if (s >= nsl) break;
-                const uint32_t n_s = L.len[s];
-                const uint64_t b_s = L.st[s];
-                for (uint32_t i = CT_LPS + lig; i < n_s; i += CT_LPS)
-                    bump<BITS>(L.cnt, a.ids[b_s + i] - tile_lo);
-            }
+        // lane w holds wavefront w's totals; sums over the lanes below this
+        // wavefront's index give its offsets, over all lanes the chunk's totals
+        const uint32_t x1 = lane < CT_WAVES ? L.wsum[lane] : 0u;
+        const uint32_t x2 = lane < CT_WAVES ? L.wsum[CT_WAVES + lane] : 0u;
+        const uint32_t bne = wave_sum_u32(lane < wave ? x1 : 0u), bpos = wave_sum_u32(lane < wave ? x2 : 0u);
+        const uint32_t tne = wave_sum_u32(x1), tpos = wave_sum_u32(x2);
+        const uint32_t ci = bne + ine - ne, p0 = bpos + ipos - len;
+        if (len > 0u) {
+            L.dl[ci] = st - p0;
+            L.pos[ci] = p0;
         }
+        if (threadIdx.x == 0) L.pos[tne] = tpos;
         __syncthreads();
-    }
-}
-
-// Level histogram of a tile's packed counts, added into hsum[1..16] as
-// "ids with count >= v".  Each thread keeps two levels per register (16-bit
-// halves: a thread sees at most W/CT_BLOCK <= 1024 ids of a tile).  The
-// per-word level loop stops at the first level no lane of the wavefront reaches.
-template <int BITS>
-__device__ __forceinline__ void tile_ge_counts(const uint32_t *cnt, int words, uint32_t *hsum) {
-    uint32_t ge2[8];
-#pragma unroll
-    for (int v = 0; v < 8; v++) ge2[v] = 0u;
-    for (int i0 = 0; i0 < words; i0 += CT_BLOCK) {
-        const int i = i0 + threadIdx.x;
-        const uint32_t w = i < words ? cnt[i] : 0u;
-#pragma unroll
-        for (int v = 1; v <= 16; v++) {
-            uint32_t m0, m1;
-            ge_masks<BITS>(w, static_cast<uint32_t>(v), m0, m1);
-            if (!__any((m0 | m1) != 0u)) break;
-            ge2[(v - 1) / 2] += static_cast<uint32_t>(__popc(m0) + __popc(m1)) << (16 * ((v - 1) & 1));
+        for (uint32_t seg = 0; seg < tpos; seg += CT_WT * WAVE) {
+            const uint32_t seg_end = min(tpos, seg + static_cast<uint32_t>(CT_WT * WAVE));
+            // window table of this segment: every window start (a multiple
+            // of 64) lies in exactly one non-empty slice
+            if (len > 0u) {
+                const uint32_t lo_p = max(p0, seg), hi_p = min(p0 + len, seg_end);
+                for (uint32_t wp = (lo_p + WAVE - 1) / WAVE * WAVE; wp < hi_p; wp += WAVE)
+                    L.wt[(wp - seg) / WAVE] = static_cast<uint16_t>(ci);
+            }
+            __syncthreads();
+            const uint32_t nwin = (seg_end - seg + WAVE - 1) / WAVE;
+            const uint32_t nfull = (seg_end - seg) / WAVE;  // windows with all 64 positions in range
+            for (uint32_t w0 = wave; w0 < nwin; w0 += CT_WAVES * CT_UNROLL) {
+                if (held > 255 - CT_UNROLL) {
+                    trans_flush<HI>(tr, hsum, lane);
+                    held = 0;
+                }
+                held += CT_UNROLL;
+                if (w0 + (CT_UNROLL - 1) * CT_WAVES < nfull)
+                    walk_round<BITS, HI, false>(a, L, seg, seg_end, nwin, tne, w0, tile_lo, lane, tr);
+                else
+                    walk_round<BITS, HI, true>(a, L, seg, seg_end, nwin, tne, w0, tile_lo, lane, tr);
+            }
+            __syncthreads();
         }
     }
-    const int lane = threadIdx.x % WAVE;
-#pragma unroll
-    for (int v = 0; v < 8; v++) {
-        const uint32_t lo = wave_sum_u32(ge2[v] & 0xffffu), hi = wave_sum_u32(ge2[v] >> 16);
-        if (lane == 0) {
-            if (lo) atomicAdd(&hsum[2 * v + 1], lo);
-            if (hi) atomicAdd(&hsum[2 * v + 2], hi);
-        }
-    }
+    trans_flush<HI>(tr, hsum, lane);
 }
 
 // grid (T, nq), block CT_BLOCK, dynamic LDS count_lds_size(W, BITS).  Adds
 // the tile's level counts to hist[q] and stores the packed counts to
 // sc[q][t] (W*BITS/8 bytes).
-template <int BITS>
-__global__ __launch_bounds__(CT_BLOCK) void k_count(CountArgs a, uint32_t *__restrict__ hist,
+template <int BITS, bool HI>
+__global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__restrict__ hist,
                                                    uint4 *__restrict__ sc) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const CountLds L = carve<BITS>(lds_raw, a.W);
     __shared__ uint32_t hsum[18];
     const int t = blockIdx.x, q = blockIdx.y;
     if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
-    count_tile<BITS>(a, q, t, L);
+    count_tile<BITS, HI>(a, q, t, L, hsum);
+    __syncthreads();
 
     // Level histogram of the tile: hsum[v] = ids with count >= v, so level v
     // holds hsum[v] - hsum[v+1].  Ids past n hold 0 and count nowhere.
-    tile_ge_counts<BITS>(L.cnt, a.W / (32 / BITS), hsum);
-    __syncthreads();
     if (threadIdx.x >= 1 && threadIdx.x <= a.Ns) {
         const uint32_t hv = hsum[threadIdx.x] - hsum[threadIdx.x + 1];
         if (hv) atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], hv);
@@ -649,7 +760,7 @@ struct FuseArgs {
     uint32_t spin_limit;
 };
 
-template <int BITS>
+template <int BITS, bool HI>
 __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, SelectArgs sa, FuseArgs f) {
     constexpr int PER_WORD = 32 / BITS;
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -659,8 +770,8 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
     __shared__ int s_last;
     // candidate staging reuses the slice table (idle during compaction):
     // CT_FSTAGE slots per wavefront
-    constexpr int CT_FSTAGE = CT_CHUNK * 12 / 4 / (CT_BLOCK / WAVE) >= 128 ? 128 : 64;
-    static_assert(CT_FSTAGE * (CT_BLOCK / WAVE) * 4 <= CT_CHUNK * 12, "staging must fit the slice table");
+    constexpr int CT_FSTAGE = 2 * CT_CHUNK / CT_WAVES >= 128 ? 128 : 64;
+    static_assert(CT_FSTAGE * CT_WAVES <= 2 * CT_CHUNK, "staging must fit the slice table");
     const int t = blockIdx.x % a.T, g = blockIdx.x / a.T;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int words = a.W / PER_WORD;
@@ -668,8 +779,7 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
     const int tile_n = static_cast<int>(min<int64_t>(a.W, a.n - tile_lo));
     for (int q = g; q < f.nq; q += f.NG) {
         if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
-        count_tile<BITS>(a, q, t, L);
-        tile_ge_counts<BITS>(L.cnt, words, hsum);
+        count_tile<BITS, HI>(a, q, t, L, hsum);
         __syncthreads();
         uint32_t *hg = f.hist + static_cast<int64_t>(q) * (a.Ns + 1);
         if (threadIdx.x >= 1 && threadIdx.x <= a.Ns) {
@@ -707,7 +817,7 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
         const int last = s_last;
         const uint32_t lv = static_cast<uint32_t>(last > 0 ? last : 0);
         int32_t *cq = sa.cand + static_cast<int64_t>(q) * sa.cap;
-        uint32_t *stage = reinterpret_cast<uint32_t *>(L.st) + wave * CT_FSTAGE;
+        uint32_t *stage = L.dl + wave * CT_FSTAGE;
         uint32_t scount = 0;
         for (int i0 = 0; i0 < words; i0 += CT_BLOCK) {
             const int i = i0 + threadIdx.x;
@@ -1165,21 +1275,36 @@ hipError_t launch_budgets(const double *alpha, const int32_t *kq, int nq, int64_
 
 size_t count_lds_bytes(int W, int bits) { return count_lds_size(W, bits) + 18 * sizeof(uint32_t); }
 
-hipError_t prepare_count_kernels(int W, int bits) {
+// Instances: nibble counts up to 8 levels (Ns <= 8), nibbles with up to
+// 15, bytes (Ns = 16).
+static const void *count_kernel(int bits, int Ns) {
+    if (bits == 8) return reinterpret_cast<const void *>(k_count<8, true>);
+    return Ns > 8 ? reinterpret_cast<const void *>(k_count<4, true>)
+                  : reinterpret_cast<const void *>(k_count<4, false>);
+}
+
+static const void *count_select_kernel(int bits, int Ns) {
+    if (bits == 8) return reinterpret_cast<const void *>(k_count_select<8, true>);
+    return Ns > 8 ? reinterpret_cast<const void *>(k_count_select<4, true>)
+                  : reinterpret_cast<const void *>(k_count_select<4, false>);
+}
+
+hipError_t prepare_count_kernels(int W, int bits, int Ns) {
     const int bytes = static_cast<int>(count_lds_size(W, bits));
-    const void *k = bits == 4 ? reinterpret_cast<const void *>(k_count<4>)
-                              : reinterpret_cast<const void *>(k_count<8>);
-    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return hipFuncSetAttribute(count_kernel(bits, Ns), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, hipStream_t st) {
     CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
     dim3 grid(c.T, c.nq);
     uint4 *s4 = reinterpret_cast<uint4 *>(sc);
-    if (c.bits == 4)
-        k_count<4><<<grid, CT_BLOCK, count_lds_size(c.W, 4), st>>>(a, hist, s4);
+    const size_t lds = count_lds_size(c.W, c.bits);
+    if (c.bits == 8)
+        k_count<8, true><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4);
+    else if (c.Ns > 8)
+        k_count<4, true><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4);
     else
-        k_count<8><<<grid, CT_BLOCK, count_lds_size(c.W, 8), st>>>(a, hist, s4);
+        k_count<4, false><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4);
     return hipGetLastError();
 }
 
@@ -1205,10 +1330,9 @@ size_t fused_lds_bytes(int W, int bits) {
     return count_lds_size(W, bits) + (18 + 17 + 1) * sizeof(uint32_t);
 }
 
-hipError_t fused_max_blocks(int W, int bits, int *blocks_per_cu) {
+hipError_t fused_max_blocks(int W, int bits, int Ns, int *blocks_per_cu) {
     const int bytes = static_cast<int>(count_lds_size(W, bits));
-    const void *k = bits == 4 ? reinterpret_cast<const void *>(k_count_select<4>)
-                              : reinterpret_cast<const void *>(k_count_select<8>);
+    const void *k = count_select_kernel(bits, Ns);
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, CT_BLOCK, bytes);
@@ -1221,8 +1345,7 @@ hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int 
                   s.dump_hist};
     FuseArgs f{c.nq, NG, const_cast<uint32_t *>(s.hist), arrive, err, spin_limit};
     void *args[] = {&a, &sa, &f};
-    const void *k = c.bits == 4 ? reinterpret_cast<const void *>(k_count_select<4>)
-                                : reinterpret_cast<const void *>(k_count_select<8>);
+    const void *k = count_select_kernel(c.bits, c.Ns);
     return hipLaunchCooperativeKernel(k, dim3(static_cast<unsigned>(NG) * c.T), dim3(CT_BLOCK), args,
                                       static_cast<unsigned>(count_lds_size(c.W, c.bits)), st);
 }

@@ -253,13 +253,13 @@ int build_tiles(tc_index *x) {
     TC_HIP(taco::launch_build_off2d(x->ids, x->offs, x->Ns, x->K, x->n, x->T, x->W, x->off2d,
                                     nullptr),
            "building tile offsets");
-    TC_HIP(taco::prepare_count_kernels(x->W, x->bits), "setting LDS size of the count kernels");
+    TC_HIP(taco::prepare_count_kernels(x->W, x->bits, x->Ns), "setting LDS size of the count kernels");
     TC_HIP(hipDeviceSynchronize(), "building tile offsets");
     // How many groups of T co-resident workgroups the fused kernel can keep.
     x->fused_groups = 0;
     if (x->coop && taco::fused_lds_bytes(x->W, x->bits) <= size_t(x->max_lds)) {
         int per_cu = 0;
-        TC_HIP(taco::fused_max_blocks(x->W, x->bits, &per_cu), "occupancy of the fused kernel");
+        TC_HIP(taco::fused_max_blocks(x->W, x->bits, x->Ns, &per_cu), "occupancy of the fused kernel");
         x->fused_groups = per_cu * x->num_cu / x->T;
     }
     return TC_OK;
@@ -352,10 +352,10 @@ int load(const char *path, int device, tc_index *x) {
     x->M = x->Ns * x->s;
     x->K = x->l * x->l;
     if (x->n <= 0 || x->n >= (int64_t(1) << 31) || x->d <= 0 || x->Ns <= 0 || x->Ns > 16 ||
-        x->s < 2 || x->M > x->d || x->l <= 0 || x->l > 64 || x->h1 != x->s / 2 ||
-        x->h2 != x->s - x->s / 2)
-        return fail(TC_EFORMAT, "index shape out of range (need n < 2^31, Ns <= 16, l <= 64, "
-                                "Ns*s <= d, halves s/2 and s - s/2)");
+        int64_t(x->Ns) * x->n >= (int64_t(1) << 30) || x->s < 2 || x->M > x->d || x->l <= 0 ||
+        x->l > 64 || x->h1 != x->s / 2 || x->h2 != x->s - x->s / 2)
+        return fail(TC_EFORMAT, "index shape out of range (need n < 2^31, Ns <= 16, Ns*n < 2^30, "
+                                "l <= 64, Ns*s <= d, halves s/2 and s - s/2)");
     const size_t n = size_t(x->n), d = size_t(x->d), Ns = size_t(x->Ns), l = size_t(x->l),
                  K = size_t(x->K), M = size_t(x->M);
     std::vector<float> mean(d), B(d * M), C1(Ns * l * x->h1), C2(Ns * l * x->h2);

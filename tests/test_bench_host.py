@@ -1,0 +1,61 @@
+"""Host-side pieces of bench.py: the recall-frontier read-out, the kernel
+name mapping and the counter scaling (no GPU)."""
+import csv
+import json
+
+import pytest
+
+import bench
+
+
+def test_qps_at_recall_frontier():
+    pts = [dict(recall=0.90, qps=1000.0), dict(recall=0.97, qps=400.0), dict(recall=0.99, qps=300.0)]
+    # interpolation between the fast point below and the slow point above
+    v = bench.qps_at_recall(pts, 0.95)
+    assert v == pytest.approx(400.0 + (0.97 - 0.95) / (0.97 - 0.90) * 600.0)
+    # a point at or above the target that is faster wins
+    pts.append(dict(recall=0.96, qps=900.0))
+    assert bench.qps_at_recall(pts, 0.95) >= 900.0
+    assert bench.qps_at_recall([dict(recall=0.5, qps=1.0)], 0.95) is None
+
+
+def test_short_kernel_names():
+    f = bench.short_kernel_name
+    assert f("void taco::k_count_select<4>(taco::FuseArgs)") == "count_select"
+    assert f("void taco::k_count<8>(taco::CountArgs, unsigned int*)") == "count"
+    assert f("taco::k_select(taco::SelectArgs, int)") == "select"
+    assert f("void taco::k_rerank16<16, true>(float const*)") == "rerank"
+    assert f("void taco::k_rerank<16, true>(float const*)") == "rerank"
+    assert f("void taco::k_recheck<16, true>(float const*)") == "recheck"
+    assert f("__amd_rocclr_copyBuffer") is None
+
+
+def _write_pmc(path, counter, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh, quoting=csv.QUOTE_NONNUMERIC)
+        w.writerow(["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"])
+        for i, (name, v) in enumerate(rows):
+            w.writerow([i, name, counter, v])
+
+
+def test_summarize_traffic_scales_by_copy(tmp_path):
+    kib = 1 << 20  # a 1 GiB copy read as exactly 1 GiB
+    _write_pmc(tmp_path / "f.csv", "FETCH_SIZE",
+               [("__amd_rocclr_copyBuffer", kib / 2), ("__amd_rocclr_copyBuffer", 4.0),
+                ("void taco::k_count<4>(taco::CountArgs, unsigned int*)", 100.0),
+                ("void taco::k_count<4>(taco::CountArgs, unsigned int*)", 300.0)])
+    _write_pmc(tmp_path / "w.csv", "WRITE_SIZE",
+               [("__amd_rocclr_copyBuffer", kib),
+                ("void taco::k_count<4>(taco::CountArgs, unsigned int*)", 50.0)])
+    line = dict(config=dict(workload="w", alpha=0.05, path="tuned", tuned_config="x"))
+    (tmp_path / "b.json").write_text("log\n" + json.dumps(line) + "\n")
+    out = tmp_path / "t.json"
+    bench.summarize_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "b.json"),
+                            str(out), "cmd")
+    rec = json.loads(out.read_text())
+    # the copy's fetch read half its size: fetch counts are doubled
+    assert rec["fetch_scale"] == pytest.approx(2.0)
+    assert rec["write_scale"] == pytest.approx(1.0)
+    c = rec["kernels"]["count"]
+    assert c["dispatches"] == 2
+    assert c["hbm_bytes_per_launch"] == pytest.approx(200.0 * 1024 * 2 + 50.0 * 1024)
