@@ -317,7 +317,7 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 #define TACO_CT_BLOCK 1024
 #endif
 #ifndef TACO_CT_UNROLL
-#define TACO_CT_UNROLL 8
+#define TACO_CT_UNROLL 4
 #endif
 constexpr int CT_BLOCK = TACO_CT_BLOCK;
 constexpr int CT_UNROLL = TACO_CT_UNROLL;       // windows in flight per wavefront
@@ -446,17 +446,18 @@ __device__ __forceinline__ void ge_masks(uint32_t w, uint32_t v, uint32_t &m0, u
 }
 
 // One round of a wavefront's walk: windows w0 + u*CT_WAVES (u < CT_UNROLL)
-// of the current position segment, one position per lane and window.  The
-// lane's slice is the window's first slice s0 (window table) plus the number
-// of slice ends at or below its position; those ends are pos[s0+1..], held
-// one per lane, and only the few that fall inside the window (a ballot)
-// are compared.  GUARD: some windows or positions of the round lie past the
-// segment (its last round); otherwise no lane needs a bounds test.
-template <int BITS, bool HI, bool GUARD>
-__device__ __forceinline__ void walk_round(const CountArgs &a, const CountLds &L, uint32_t seg,
-                                           uint32_t seg_end, uint32_t nwin, uint32_t tne, uint32_t w0,
-                                           uint32_t tile_lo, int lane, Trans<HI> &tr) {
-    uint32_t s0[CT_UNROLL], e[CT_UNROLL], id[CT_UNROLL];
+// of the current position segment, one position per lane and window; the
+// ids are loaded into id[] (0xffffffff where the position lies past the
+// segment).  The lane's slice is the window's first slice s0 (window table)
+// plus the number of slice ends at or below its position; those ends are
+// pos[s0+1..], held one per lane, and only the few that fall inside the
+// window (a ballot) are compared.  GUARD: some windows or positions of the
+// round lie past the segment; otherwise no lane needs a bounds test.
+template <bool GUARD>
+__device__ __forceinline__ void walk_load(const CountArgs &a, const CountLds &L, uint32_t seg,
+                                          uint32_t seg_end, uint32_t nwin, uint32_t tne, uint32_t w0,
+                                          int lane, uint32_t (&id)[CT_UNROLL]) {
+    uint32_t s0[CT_UNROLL], e[CT_UNROLL];
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) {
         const uint32_t wi = w0 + u * CT_WAVES;
@@ -488,6 +489,12 @@ __device__ __forceinline__ void walk_round(const CountArgs &a, const CountLds &L
             id[u] = load_id(a.ids, e[u] + p);
         }
     }
+}
+
+// The LDS increments of one round (ids of 0xffffffff skipped when GUARD).
+template <int BITS, bool HI, bool GUARD>
+__device__ __forceinline__ void walk_bump(const CountLds &L, uint32_t tile_lo, const uint32_t (&id)[CT_UNROLL],
+                                          Trans<HI> &tr) {
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) {
         if (GUARD) {
@@ -567,16 +574,38 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
             __syncthreads();
             const uint32_t nwin = (seg_end - seg + WAVE - 1) / WAVE;
             const uint32_t nfull = (seg_end - seg) / WAVE;  // windows with all 64 positions in range
-            for (uint32_t w0 = wave; w0 < nwin; w0 += CT_WAVES * CT_UNROLL) {
+            constexpr uint32_t STRIDE = CT_WAVES * CT_UNROLL, SPAN = (CT_UNROLL - 1) * CT_WAVES;
+            // rounds whose windows all lie in [0, nfull): software-pipelined,
+            // the next round's ids are in flight during this round's increments
+            uint32_t w0 = static_cast<uint32_t>(wave);
+            uint32_t id[CT_UNROLL];
+            bool have = w0 + SPAN < nfull;
+            if (have) walk_load<false>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
+            while (have) {
+                const uint32_t wn = w0 + STRIDE;
+                const bool nhave = wn + SPAN < nfull;
+                uint32_t nid[CT_UNROLL];
+                if (nhave) walk_load<false>(a, L, seg, seg_end, nwin, tne, wn, lane, nid);
                 if (held > 255 - CT_UNROLL) {
                     trans_flush<HI>(tr, hsum, lane);
                     held = 0;
                 }
                 held += CT_UNROLL;
-                if (w0 + (CT_UNROLL - 1) * CT_WAVES < nfull)
-                    walk_round<BITS, HI, false>(a, L, seg, seg_end, nwin, tne, w0, tile_lo, lane, tr);
-                else
-                    walk_round<BITS, HI, true>(a, L, seg, seg_end, nwin, tne, w0, tile_lo, lane, tr);
+                walk_bump<BITS, HI, false>(L, tile_lo, id, tr);
+#pragma unroll
+                for (int u = 0; u < CT_UNROLL; u++) id[u] = nid[u];
+                w0 = wn;
+                have = nhave;
+            }
+            // the segment's last round(s), bounds-tested
+            for (; w0 < nwin; w0 += STRIDE) {
+                if (held > 255 - CT_UNROLL) {
+                    trans_flush<HI>(tr, hsum, lane);
+                    held = 0;
+                }
+                held += CT_UNROLL;
+                walk_load<true>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
+                walk_bump<BITS, HI, true>(L, tile_lo, id, tr);
             }
             __syncthreads();
         }
@@ -651,6 +680,53 @@ __device__ __forceinline__ void flush_stage(uint32_t *stage, uint32_t &scount, u
     scount = 0;
 }
 
+// Appends the ids flagged in a lane's NM masks (bit 8b+7 of mask i flags
+// id_of(i, b)) to the query's candidate list, in lane order: an exclusive
+// prefix sum over the wavefront places each lane's ids, which go to the
+// wavefront's LDS stage of CAP slots, or straight to the list (one
+// reservation) when they outnumber the stage.
+template <int CAP, int NM, typename IdOf>
+__device__ __forceinline__ void append_flagged(const uint32_t (&m)[NM], IdOf id_of, uint32_t *stage,
+                                               uint32_t &scount, uint32_t *counter, int32_t *out,
+                                               int lane) {
+    uint32_t cnt = 0u;
+#pragma unroll
+    for (int i = 0; i < NM; i++) cnt += static_cast<uint32_t>(__popc(m[i]));
+    const uint32_t inc = wave_incl_scan_u32(cnt, lane);
+    const uint32_t total = static_cast<uint32_t>(__builtin_amdgcn_readlane(inc, WAVE - 1));
+    if (total == 0u) return;
+    uint32_t j = inc - cnt;
+    if (scount + total > static_cast<uint32_t>(CAP)) flush_stage(stage, scount, counter, out, lane);
+    if (total <= static_cast<uint32_t>(CAP)) {
+        j += scount;
+#pragma unroll
+        for (int i = 0; i < NM; i++) {
+            uint32_t mm = m[i];
+            while (mm != 0u) {
+                const int bit = __builtin_ctz(mm);
+                mm &= mm - 1u;
+                stage[j++] = id_of(i, bit >> 3);
+            }
+        }
+        scount += total;
+        wave_sync_lds();
+    } else {
+        uint32_t base = 0u;
+        if (lane == 0) base = atomicAdd(counter, total);
+        base = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(base));
+        j += base;
+#pragma unroll
+        for (int i = 0; i < NM; i++) {
+            uint32_t mm = m[i];
+            while (mm != 0u) {
+                const int bit = __builtin_ctz(mm);
+                mm &= mm - 1u;
+                out[j++] = static_cast<int32_t>(id_of(i, bit >> 3));
+            }
+        }
+    }
+}
+
 // Streaming pass over the packed counts of one query: Alg 5's threshold from
 // the level histogram, then compaction of C = {id : SC[id] >= last} through
 // per-wavefront LDS staging.  grid (blocks per query, nq), block SEL_BLOCK;
@@ -707,33 +783,29 @@ __global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int
                             (wv[b / PER_WORD] >> (BITS * (b % PER_WORD))) & ((1u << BITS) - 1u));
                 }
             }
-            uint32_t m[4][2];
-            bool anyv = false;
+            // masks 2c+h: word c, even (h = 0) or odd (h = 1) nibbles; bytes: h = 0 only
+            uint32_t m[8];
 #pragma unroll
             for (int c = 0; c < 4; c++) {
-                ge_masks<BITS>(wv[c], lv, m[c][0], m[c][1]);
-                if (!in) m[c][0] = m[c][1] = 0u;
-                anyv |= (m[c][0] | m[c][1]) != 0u;
+                ge_masks<BITS>(wv[c], lv, m[2 * c], m[2 * c + 1]);
+                if (!in) m[2 * c] = m[2 * c + 1] = 0u;
             }
-            if (!__any(anyv)) continue;
+            if (in && id0 + PER_VEC > n) {
+                // the last word of the last tile: ids past n are padding
 #pragma unroll
-            for (int c = 0; c < 4; c++) {
-#pragma unroll
-                for (int b = 0; b < 4; b++) {
-#pragma unroll
-                    for (int hh = 0; hh < (BITS == 4 ? 2 : 1); hh++) {
-                        const int slot = BITS == 8 ? b : 2 * b + hh;
-                        const int64_t id = id0 + c * PER_WORD + slot;
-                        const bool flag = ((m[c][hh] >> (8 * b + 7)) & 1u) && id < n;
-                        const uint64_t mask = __ballot(flag);
-                        if (mask == 0ull) continue;
-                        if (scount > CT_STAGE - WAVE) flush_stage(stage, scount, counter, cq, lane);
-                        if (flag)
-                            stage[scount + __popcll(mask & lanes_below(lane))] = static_cast<uint32_t>(id);
-                        scount += static_cast<uint32_t>(__popcll(mask));
+                for (int i = 0; i < 8; i++)
+                    for (int b = 0; b < 4; b++) {
+                        const int c = i / 2, hh = i % 2;
+                        const int64_t id = id0 + c * PER_WORD + (BITS == 8 ? b : 2 * b + hh);
+                        if (id >= n) m[i] &= ~(0x80u << (8 * b));
                     }
-                }
             }
+            append_flagged<CT_STAGE, 8>(
+                m,
+                [&](int i, int b) {
+                    return static_cast<uint32_t>(id0 + (i / 2) * PER_WORD + (BITS == 8 ? b : 2 * b + (i % 2)));
+                },
+                stage, scount, counter, cq, lane);
         }
     }
     if (__any(scount != 0u)) flush_stage(stage, scount, counter, cq, lane);
@@ -834,22 +906,18 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
             uint32_t m[2];
             ge_masks<BITS>(w, lv, m[0], m[1]);
             if (!in) m[0] = m[1] = 0u;
-            if (!__any((m[0] | m[1]) != 0u)) continue;
-#pragma unroll
-            for (int b = 0; b < 4; b++) {
-#pragma unroll
-                for (int hh = 0; hh < (BITS == 4 ? 2 : 1); hh++) {
-                    const int loc = i * PER_WORD + (BITS == 8 ? b : 2 * b + hh);
-                    const bool flag = ((m[hh] >> (8 * b + 7)) & 1u) && loc < tile_n;
-                    const uint64_t mask = __ballot(flag);
-                    if (mask == 0ull) continue;
-                    if (scount > CT_FSTAGE - WAVE) flush_stage(stage, scount, sa.cand_count + q, cq, lane);
-                    if (flag)
-                        stage[scount + __popcll(mask & lanes_below(lane))] =
-                            static_cast<uint32_t>(tile_lo + loc);
-                    scount += static_cast<uint32_t>(__popcll(mask));
-                }
+            if (in && i * PER_WORD + PER_WORD > tile_n) {
+                // ids past n in the last tile are padding
+                for (int i2 = 0; i2 < 2; i2++)
+                    for (int b = 0; b < 4; b++)
+                        if (i * PER_WORD + (BITS == 8 ? b : 2 * b + i2) >= tile_n) m[i2] &= ~(0x80u << (8 * b));
             }
+            append_flagged<CT_FSTAGE, 2>(
+                m,
+                [&](int i2, int b) {
+                    return static_cast<uint32_t>(tile_lo + i * PER_WORD + (BITS == 8 ? b : 2 * b + i2));
+                },
+                stage, scount, sa.cand_count + q, cq, lane);
         }
         if (__any(scount != 0u)) flush_stage(stage, scount, sa.cand_count + q, cq, lane);
         __syncthreads();
