@@ -212,7 +212,21 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int q = blockIdx.x * QPW + wave;
     const uint32_t *off = offs + static_cast<int64_t>(j) * (K + 1);
-    for (int c = threadIdx.x; c < K; c += 64 * QPW) sizes[c] = off[c + 1] - off[c];
+    // eight cells per thread in flight at a time
+    for (int c0 = 0; c0 < K; c0 += 8 * 64 * QPW) {
+        uint32_t lo[8], hi[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int c = c0 + threadIdx.x + u * 64 * QPW;
+            lo[u] = c < K ? off[c] : 0u;
+            hi[u] = c < K ? off[c + 1] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int c = c0 + threadIdx.x + u * 64 * QPW;
+            if (c < K) sizes[c] = hi[u] - lo[u];
+        }
+    }
     __syncthreads();
     if (q >= nq) return;  // no block-wide barrier below this point
     const int64_t A = A_q ? A_q[q] : A_all;
@@ -220,15 +234,39 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
     const float *x = qt + static_cast<int64_t>(q) * M + static_cast<int64_t>(j) * s;
     float d1 = 0.0f, d2 = 0.0f;
     if (lane < l) {
+        // loads of 8 terms are issued together; the sums keep the ascending
+        // one-fma-per-term order
         const float *c1 = C1 + (static_cast<int64_t>(j) * l + lane) * h1;
         const float *c2 = C2 + (static_cast<int64_t>(j) * l + lane) * h2;
-        for (int t = 0; t < h1; t++) {
-            float u = x[t] - c1[t];
-            d1 = fmaf(u, u, d1);
+        for (int t0 = 0; t0 < h1; t0 += 8) {
+            float xs[8], cs[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                xs[u] = t0 + u < h1 ? x[t0 + u] : 0.0f;
+                cs[u] = t0 + u < h1 ? c1[t0 + u] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                if (t0 + u < h1) {
+                    const float v = xs[u] - cs[u];
+                    d1 = fmaf(v, v, d1);
+                }
+            }
         }
-        for (int t = 0; t < h2; t++) {
-            float u = x[h1 + t] - c2[t];
-            d2 = fmaf(u, u, d2);
+        for (int t0 = 0; t0 < h2; t0 += 8) {
+            float xs[8], cs[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                xs[u] = t0 + u < h2 ? x[h1 + t0 + u] : 0.0f;
+                cs[u] = t0 + u < h2 ? c2[t0 + u] : 0.0f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                if (t0 + u < h2) {
+                    const float v = xs[u] - cs[u];
+                    d2 = fmaf(v, v, d2);
+                }
+            }
         }
         rawD[wave][0][lane] = d1;
         rawD[wave][1][lane] = d2;
@@ -238,6 +276,7 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (lane < l) {
         int r1 = 0, r2 = 0;
+#pragma unroll 8
         for (int c = 0; c < l; c++) {
             float a = rawD[wave][0][c], b = rawD[wave][1][c];
             r1 += (a < d1) || (a == d1 && c < lane);
@@ -264,30 +303,53 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 
     // Tournament: lane r holds row r (half-1 rank r) with its next column and
     // key bits (keys are >= +0, so their bit patterns order like the floats).
-    // Each step finds the smallest key, then the lowest row holding it.
-    const float *D2s = sortD[wave][1];
+    // Each step finds the smallest key, then the lowest row holding it.  The
+    // sorted half-2 distances sit one per lane, so a step touches no memory;
+    // PB steps run before their cells' sizes are read (one LDS read per
+    // lane) and scanned for the step that reaches the budget A.  Steps past
+    // it are discarded.
+    constexpr int PB = 16;
     const float my_d1 = lane < l ? sortD[wave][0][lane] : 0.0f;
+    const float my_d2 = lane < l ? sortD[wave][1][lane] : 0.0f;
     const int my_o1 = lane < l ? order[wave][0][lane] : 0;
     const int my_o2 = lane < l ? order[wave][1][lane] : 0;
+    const float d2_0 = __uint_as_float(static_cast<uint32_t>(
+        __builtin_amdgcn_readlane(static_cast<int>(__float_as_uint(my_d2)), 0)));
     int col = 0;
-    uint32_t kb = lane < l ? __float_as_uint(my_d1 + D2s[0]) : 0xffffffffu;
+    uint32_t kb = lane < l ? __float_as_uint(my_d1 + d2_0) : 0xffffffffu;
     int32_t *out = cells + qj * K;
     int64_t got = 0;
     int nc = 0;
-    while (nc < K) {
-        const uint32_t kmin = wave_min_u32_dpp(kb);
-        if (kmin == 0xffffffffu) break;
-        const int w = static_cast<int>(__builtin_ctzll(__ballot(kb == kmin)));
-        const int cw = __builtin_amdgcn_readlane(col, w);
-        const int cell = __builtin_amdgcn_readlane(my_o1, w) * l + __builtin_amdgcn_readlane(my_o2, cw);
-        if (lane == 0) out[nc] = cell;
-        nc++;
-        got += sizes[cell];
-        if (got >= A) break;
-        if (lane == w) {
-            col++;
-            kb = col < l ? __float_as_uint(my_d1 + D2s[col]) : 0xffffffffu;
+    bool done = false;
+    while (!done) {
+        int cellv = 0;  // lane s: the cell of step s of this batch
+        int nb = 0;
+        for (; nb < PB; nb++) {
+            const uint32_t kmin = wave_min_u32_dpp(kb);
+            if (kmin == 0xffffffffu) break;
+            const int w = static_cast<int>(__builtin_ctzll(__ballot(kb == kmin)));
+            const int cw = __builtin_amdgcn_readlane(col, w);
+            const int cell = __builtin_amdgcn_readlane(my_o1, w) * l + __builtin_amdgcn_readlane(my_o2, cw);
+            if (lane == nb) cellv = cell;
+            const int nx = cw + 1 < l ? cw + 1 : 0;
+            const uint32_t d2n = static_cast<uint32_t>(
+                __builtin_amdgcn_readlane(static_cast<int>(__float_as_uint(my_d2)), nx));
+            if (lane == w) {
+                col = cw + 1;
+                kb = col < l ? __float_as_uint(my_d1 + __uint_as_float(d2n)) : 0xffffffffu;
+            }
         }
+        if (nb == 0) break;
+        // sizes of this batch's cells, their running sum, and the first step
+        // whose running total reaches A
+        const uint32_t sz = lane < nb ? sizes[cellv] : 0u;
+        const uint32_t run = wave_incl_scan_u32(sz, lane);
+        const uint64_t hit = __ballot(lane < nb && got + static_cast<int64_t>(run) >= A);
+        const int take = hit ? static_cast<int>(__builtin_ctzll(hit)) + 1 : nb;
+        if (lane < take) out[nc + lane] = cellv;
+        got += static_cast<int64_t>(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(run), take - 1)));
+        nc += take;
+        done = hit != 0ull || nb < PB;
     }
     if (lane == 0) {
         ncells[qj] = nc;
@@ -1181,10 +1243,59 @@ __global__ __launch_bounds__(256) void k_prep_bf16(const float *__restrict__ bas
 // and order like (distance, id) because distances are >= +0.  An MSB-first
 // radix select over 8-bit digits finds the smallest prefix whose bucket is
 // taken whole; exactly k keys fall at or below it.  They are gathered to LDS
-// and bitonic-sorted.
+// and bitonic-sorted.  The digits start below the bits all keys share (from
+// the block's minimum and maximum key), so the first pass already splits
+// the candidates; each pass picks its digit with a block prefix sum over the
+// 256 buckets.
 // ---------------------------------------------------------------------------
 
 constexpr int TOPK_MAX = 1024;
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int m = WAVE / 2; m > 0; m >>= 1) {
+        const uint64_t o = __shfl_xor(v, m, WAVE);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int m = WAVE / 2; m > 0; m >>= 1) {
+        const uint64_t o = __shfl_xor(v, m, WAVE);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+constexpr int TK_KPT = 32;  // keys per thread kept in registers (|C| <= 256 * TK_KPT)
+
+// Calls f(key) for every candidate key of the query: from registers when
+// they all fit, else streamed from memory eight loads per thread at a time.
+template <typename F>
+__device__ __forceinline__ void for_keys(bool reg, const uint64_t (&kr)[TK_KPT], int64_t nc,
+                                         const int32_t *cq, const float *dq, F f) {
+    if (reg) {
+#pragma unroll
+        for (int u = 0; u < TK_KPT; u++)
+            if (static_cast<int64_t>(threadIdx.x) + u * BLOCK < nc) f(kr[u]);
+    } else {
+        for (int64_t i0 = threadIdx.x; i0 < nc; i0 += 8 * BLOCK) {
+            uint64_t kk[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int64_t i = i0 + u * BLOCK;
+                kk[u] = i < nc ? (static_cast<uint64_t>(__float_as_uint(dq[i])) << 32) |
+                                     static_cast<uint32_t>(cq[i])
+                               : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++)
+                if (i0 + u * BLOCK < nc) f(kk[u]);
+        }
+    }
+}
 
 // k is kq[q] when kq is given (else k_all); results go to rows of k_max
 // entries, padded with (-1, +inf) past k or past |C|.
@@ -1195,6 +1306,8 @@ __global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
                                               int k_max, int64_t *__restrict__ ids_out,
                                               float *__restrict__ d_out) {
     __shared__ uint32_t hist[256];
+    __shared__ uint32_t wtot[WAVES];
+    __shared__ uint64_t wred[2 * WAVES];
     __shared__ uint64_t sel[TOPK_MAX];
     __shared__ uint32_t nsel;
     __shared__ uint32_t s_digit, s_need, s_full;
@@ -1203,52 +1316,83 @@ __global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
     const int64_t nc = cand_count[q];
     const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
     const float *dq = cand_dist + static_cast<int64_t>(q) * cap;
-    auto key_of = [&](int64_t i) -> uint64_t {
-        return (static_cast<uint64_t>(__float_as_uint(dq[i])) << 32) | static_cast<uint32_t>(cq[i]);
-    };
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const bool reg = nc <= static_cast<int64_t>(BLOCK) * TK_KPT;
+    uint64_t kr[TK_KPT];
+    if (reg) {
+#pragma unroll
+        for (int u = 0; u < TK_KPT; u++) {
+            const int64_t i = threadIdx.x + u * BLOCK;
+            kr[u] = i < nc ? (static_cast<uint64_t>(__float_as_uint(dq[i])) << 32) | static_cast<uint32_t>(cq[i])
+                           : 0ull;
+        }
+    }
     if (threadIdx.x == 0) nsel = 0u;
-    __syncthreads();
     int shift = 64;
     uint64_t prefix = 0;
     if (nc > k) {
+        // bits above `shift` are common to all keys: prefix holds them
+        uint64_t mn = ~0ull, mx = 0ull;
+        for_keys(reg, kr, nc, cq, dq, [&](uint64_t kk) {
+            mn = kk < mn ? kk : mn;
+            mx = kk > mx ? kk : mx;
+        });
+        mn = wave_min_u64(mn);
+        mx = wave_max_u64(mx);
+        if (lane == 0) {
+            wred[wave] = mn;
+            wred[WAVES + wave] = mx;
+        }
+        __syncthreads();
+        mn = wred[0];
+        mx = wred[WAVES];
+        for (int w = 1; w < WAVES; w++) {
+            mn = wred[w] < mn ? wred[w] : mn;
+            mx = wred[WAVES + w] > mx ? wred[WAVES + w] : mx;
+        }
+        shift = 64 - __clzll(static_cast<long long>(mn ^ mx));  // mn != mx: keys are unique
+        prefix = shift == 64 ? 0ull : mn >> shift;
         uint32_t need = static_cast<uint32_t>(k);
         bool done = false;
         while (!done && shift > 0) {
-            shift -= 8;
+            const int sh2 = shift > 8 ? shift - 8 : 0;
+            const uint32_t dmask = (1u << (shift - sh2)) - 1u;
             hist[threadIdx.x] = 0u;
             __syncthreads();
-            for (int64_t i = threadIdx.x; i < nc; i += BLOCK) {
-                const uint64_t kk = key_of(i);
-                const bool match = shift == 56 || (kk >> (shift + 8)) == prefix;
-                if (match) atomicAdd(&hist[(kk >> shift) & 255u], 1u);
+            for_keys(reg, kr, nc, cq, dq, [&](uint64_t kk) {
+                if (shift == 64 || (kk >> shift) == prefix)
+                    atomicAdd(&hist[static_cast<uint32_t>(kk >> sh2) & dmask], 1u);
+            });
+            __syncthreads();
+            // the bucket where the running count reaches `need`
+            const uint32_t hv = hist[threadIdx.x];
+            const uint32_t inc = wave_incl_scan_u32(hv, lane);
+            if (lane == WAVE - 1) wtot[wave] = inc;
+            __syncthreads();
+            uint32_t before = 0u;
+            for (int w = 0; w < wave; w++) before += wtot[w];
+            const uint32_t incl = before + inc, excl = incl - hv;
+            if (excl < need && need <= incl) {
+                s_digit = threadIdx.x;
+                s_need = need - excl;
+                s_full = hv == need - excl;
             }
             __syncthreads();
-            if (threadIdx.x == 0) {
-                uint32_t cum = 0, dg = 0;
-                for (dg = 0; dg < 255; dg++) {
-                    if (cum + hist[dg] >= need) break;
-                    cum += hist[dg];
-                }
-                s_digit = dg;
-                s_need = need - cum;
-                s_full = hist[dg] == need - cum;
-            }
-            __syncthreads();
-            prefix = (prefix << 8) | s_digit;
+            prefix = (prefix << (shift - sh2)) | s_digit;
             need = s_need;
             done = s_full != 0u;
+            shift = sh2;
             __syncthreads();
         }
     }
-    // gather: every key (nc <= k) or the keys whose top (64-shift) bits <= prefix
-    for (int64_t i = threadIdx.x; i < nc; i += BLOCK) {
-        const uint64_t kk = key_of(i);
-        const bool take = nc <= k || (kk >> shift) <= prefix;
-        if (take) {
+    __syncthreads();
+    // gather: every key (|C| <= k) or the keys whose top (64-shift) bits <= prefix
+    for_keys(reg, kr, nc, cq, dq, [&](uint64_t kk) {
+        if (nc <= k || (kk >> shift) <= prefix) {
             const uint32_t p = atomicAdd(&nsel, 1u);
             if (p < TOPK_MAX) sel[p] = kk;
         }
-    }
+    });
     __syncthreads();
     const int m = static_cast<int>(min<uint32_t>(nsel, static_cast<uint32_t>(k)));
     int P = 1;
