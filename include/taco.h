@@ -81,7 +81,9 @@ enum tc_option {
                                budgets and options stay the same; 0: off (default).
                                Calls with stage dumps never use the graph.          */
     TC_OPT_PROBE_QPW = 9,   /* queries (wavefronts) per probe workgroup: 1,2,4,8; 4 */
-    TC_OPT_RERANK_BLOCKS = 10 /* re-rank workgroups per query, [1, 1024]; default 32 */
+    TC_OPT_RERANK_BLOCKS = 10, /* re-rank workgroups per query, [1, 1024]; default 32 */
+    TC_OPT_CDIST_PRECISION = 11 /* tc_cdist_precision of the half-subspace centroid
+                               distances that order the probe; default TC_CDIST_FP32 */
 };
 
 /* How collision counting and candidate selection are launched.
@@ -106,6 +108,22 @@ enum tc_count_mode { TC_COUNT_AUTO = 0, TC_COUNT_SPLIT = 1, TC_COUNT_FUSED = 2 }
  *            distances) are identical to TC_FP32; fewer bytes are read.
  *            Not a precision form of the paper, which states none. */
 enum tc_precision { TC_FP32 = 0, TC_BF16 = 1 };
+
+/* Arithmetic of the query-to-centroid distances of each half subspace
+ * (Alg 6's distance step, Alg 4's inputs).
+ *   TC_CDIST_FP32: one fused multiply-add per term in ascending order from
+ *                  +0 (the oracle's chain): probed cells, counts and
+ *                  candidates are bit-exact.
+ *   TC_CDIST_BF16, TC_CDIST_FP8: |x|^2 + |c|^2 - 2 x.c with the norms in
+ *                  FP32 and the cross term on the matrix cores (BF16, or
+ *                  OCP e4m3 with one scale per subspace for the centroids
+ *                  and per (query, subspace) for the query), FP32
+ *                  accumulation, clamped at 0.  The probe order then follows
+ *                  these distances, so probed cells may differ from the
+ *                  FP32 form near ties; counts stay exact integers for the
+ *                  cells probed.  Not a form of the paper.
+ * Changing the form builds the packed centroids on first use (synchronous). */
+enum tc_cdist_precision { TC_CDIST_FP32 = 0, TC_CDIST_BF16 = 1, TC_CDIST_FP8 = 2 };
 
 /*
  * Load an index file onto GPU `device` and build its derived device tables.
@@ -222,7 +240,8 @@ int tc_search_debug(tc_index *index, const float *queries, int64_t nq, int32_t k
 /*
  * Kernel timing, recorded while TC_OPT_PROFILE is 1.  Waits for the recorded
  * events, then reports for `kernel` -- one of "transform", "probe", "count",
- * "select", "rerank", "topk", "recheck", "count_select", "graph" -- the summed duration in milliseconds and the
+ * "select", "rerank", "topk", "recheck", "count_select", "graph", "cdist" -- the summed duration in
+ * milliseconds and the
  * number of launches since the last tc_profile_reset.  Host outputs.
  */
 int tc_kernel_time(tc_index *index, const char *kernel, double *total_ms, int64_t *launches);

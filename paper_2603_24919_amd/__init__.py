@@ -19,6 +19,7 @@ __all__ = [
     "TC_OPT_TILE_IDS", "TC_OPT_PROFILE", "TC_OPT_SCRATCH_BYTES", "TC_OPT_PRECISION",
     "TC_FP32", "TC_BF16", "TC_OPT_COUNT_MODE", "TC_COUNT_AUTO", "TC_COUNT_SPLIT",
     "TC_COUNT_FUSED", "TC_OPT_GRAPH", "TC_OPT_PROBE_QPW", "TC_OPT_RERANK_BLOCKS", "KERNELS",
+    "TC_OPT_CDIST_PRECISION", "TC_CDIST_FP32", "TC_CDIST_BF16", "TC_CDIST_FP8",
     "tc_device_errors", "tc_search_batched", "tc_autotune",
     "TacoError", "TacoLibraryMissing", "lib_path", "load_library",
     "tc_load_index", "tc_free_index", "tc_index_info", "tc_set_option", "tc_search",
@@ -34,8 +35,10 @@ TC_FP32, TC_BF16 = 0, 1
 TC_OPT_COUNT_MODE = 7
 TC_COUNT_AUTO, TC_COUNT_SPLIT, TC_COUNT_FUSED = 0, 1, 2
 TC_OPT_GRAPH, TC_OPT_PROBE_QPW, TC_OPT_RERANK_BLOCKS = 8, 9, 10
+TC_OPT_CDIST_PRECISION = 11
+TC_CDIST_FP32, TC_CDIST_BF16, TC_CDIST_FP8 = 0, 1, 2
 KERNELS = ("transform", "probe", "count", "select", "rerank", "topk", "recheck", "count_select",
-           "graph")
+           "graph", "cdist")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libtaco_hip.so"

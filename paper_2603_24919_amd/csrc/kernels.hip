@@ -182,6 +182,179 @@ __global__ __launch_bounds__(256) void k_transform(const float *__restrict__ Q, 
 }
 
 // ---------------------------------------------------------------------------
+// centroid distances on the matrix cores (the reduced-precision form).
+// D = |x|^2 + |c|^2 - 2 x.c for each half-subspace centroid c, with x the
+// query's half; the norms are FP32 from the FP32 values and only the cross
+// term runs on MFMA, with BF16 or FP8 (e4m3) operands and FP32 accumulation.
+// All half-subspaces at once form one contraction q' (nq x M) times a block-
+// diagonal matrix (M x Ns*2*l): column (j, h, c) holds centroid c of half h
+// of subspace j in the rows of that half and zeros elsewhere, so a 16-column
+// tile only needs the 32-row blocks its halves cover.  FP8 operands are
+// scaled: centroids by one factor per subspace, a query's values by one
+// factor per (query, subspace), each mapping the largest magnitude to 240
+// (finite in both e4m3 variants), so every product in a column's sum
+// carries the same two factors.
+// ---------------------------------------------------------------------------
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+constexpr float FP8_RANGE = 240.0f;
+
+// Round-to-nearest-even FP32 -> BF16 bits (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return static_cast<uint16_t>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Packs four FP32 values (already scaled) into four e4m3 bytes.
+__device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) {
+    const float lim = FP8_RANGE;
+    a = fminf(fmaxf(a, -lim), lim);
+    b = fminf(fmaxf(b, -lim), lim);
+    c = fminf(fmaxf(c, -lim), lim);
+    d = fminf(fmaxf(d, -lim), lim);
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+    return static_cast<uint32_t>(w);
+}
+
+// Per (query, subspace): the two half norms |x_h|^2 (one fma per term,
+// ascending) and the FP8 query scale max|x| / 240 (1 when the half values
+// are all zero).  grid ceil(nq*Ns/256), block 256.
+__global__ __launch_bounds__(256) void k_qstats(const float *__restrict__ qt, int nq, int Ns, int M,
+                                                int s, int h1, float *__restrict__ qn,
+                                                float *__restrict__ qsc) {
+    const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (t >= static_cast<int64_t>(nq) * Ns) return;
+    const int64_t q = t / Ns;
+    const int j = static_cast<int>(t % Ns);
+    const float *x = qt + q * M + static_cast<int64_t>(j) * s;
+    float n1 = 0.0f, n2 = 0.0f, mx = 0.0f;
+    for (int u = 0; u < s; u++) {
+        const float v = x[u];
+        if (u < h1)
+            n1 = fmaf(v, v, n1);
+        else
+            n2 = fmaf(v, v, n2);
+        mx = fmaxf(mx, fabsf(v));
+    }
+    qn[t * 2] = n1;
+    qn[t * 2 + 1] = n2;
+    qsc[t] = mx > 0.0f ? mx / FP8_RANGE : 1.0f;
+}
+
+// Column col = (j*2 + h)*l + c of the block-diagonal centroid matrix, stored
+// transposed: cT[col][k] for k < Kp (bf16 bits or e4m3 bytes), with its
+// FP32 norm.  FP8 centroids are divided by csc[j] (max |C| of subspace j
+// over 240).  grid Ncol, block 64.
+template <bool FP8>
+__global__ __launch_bounds__(64) void k_prep_cent(const float *__restrict__ C1, const float *__restrict__ C2,
+                                                  int Ns, int s, int h1, int h2, int l, int Kp,
+                                                  const float *__restrict__ csc, void *__restrict__ cT,
+                                                  float *__restrict__ cnorm) {
+    const int col = blockIdx.x;
+    const int j = col / (2 * l), h = (col / l) % 2, c = col % l;
+    const int hh = h ? h2 : h1;
+    const int base = j * s + (h ? h1 : 0);
+    const float *src = (h ? C2 + (static_cast<int64_t>(j) * l + c) * h2 : C1 + (static_cast<int64_t>(j) * l + c) * h1);
+    const float inv = FP8 ? 1.0f / csc[j] : 1.0f;
+    for (int k4 = threadIdx.x * 4; k4 < Kp; k4 += 64 * 4) {
+        float v[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int t = k4 + e - base;
+            v[e] = (t >= 0 && t < hh) ? src[t] : 0.0f;
+        }
+        if (FP8) {
+            reinterpret_cast<uint32_t *>(cT)[(static_cast<int64_t>(col) * Kp + k4) / 4] =
+                fp8x4(v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv);
+        } else {
+            uint16_t *o = reinterpret_cast<uint16_t *>(cT) + static_cast<int64_t>(col) * Kp + k4;
+#pragma unroll
+            for (int e = 0; e < 4; e++) o[e] = bf16_rne(v[e]);
+        }
+    }
+    if (threadIdx.x == 0) {
+        float nn = 0.0f;
+        for (int t = 0; t < hh; t++) nn = fmaf(src[t], src[t], nn);
+        cnorm[col] = nn;
+    }
+}
+
+// One 16 x 16 tile (16 queries x 16 columns) per wavefront, four column
+// tiles per workgroup.  Operand layouts of the 16x16x32 MFMA: lane L holds
+// row (L % 16) of A and column (L % 16) of B at k = 8*(L / 16) .. +8; the
+// result tile gives lane L column (L % 16), rows 4*(L / 16) .. +4.
+// grid (ceil(Ncol/64), ceil(nq/16)), block 256.  cd[q][j][h][c] = max(D, 0).
+template <bool FP8>
+__global__ __launch_bounds__(256) void k_cdist_mfma(const float *__restrict__ qt, int nq, int M, int Ns,
+                                                    int s, int h1, int h2, int l, int Kp,
+                                                    const void *__restrict__ cT, const float *__restrict__ cnorm,
+                                                    const float *__restrict__ csc, const float *__restrict__ qn,
+                                                    const float *__restrict__ qsc, float *__restrict__ cd) {
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int ncol = Ns * 2 * l;
+    const int n0 = (blockIdx.x * 4 + wave) * 16;
+    if (n0 >= ncol) return;
+    const int q0 = blockIdx.y * 16;
+    // rows of the block-diagonal matrix this tile's columns can hold
+    const int cl = min(n0 + 15, ncol - 1);
+    const int jf = n0 / (2 * l), hf = (n0 / l) % 2, jl = cl / (2 * l), hl = (cl / l) % 2;
+    const int k_lo = (jf * s + (hf ? h1 : 0)) / 32 * 32;
+    const int k_hi = min(Kp, (jl * s + (hl ? s : h1) + 31) / 32 * 32);
+    const int r = lane % 16, kq8 = 8 * (lane / 16);
+    const int qa = q0 + r;                     // this lane's query row of A
+    const int colb = min(n0 + r, ncol - 1);    // this lane's column of B
+    f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = k_lo; k0 < k_hi; k0 += 32) {
+        const int kb = k0 + kq8;
+        float a[8];
+#pragma unroll
+        for (int e = 0; e < 8; e++) a[e] = (qa < nq && kb + e < M) ? qt[static_cast<int64_t>(qa) * M + kb + e] : 0.0f;
+        if (FP8) {
+            // the A values of this lane lie in subspaces (kb)/s .. (kb+7)/s;
+            // each is scaled by its own (query, subspace) factor
+            float sa[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int jj = min((kb + e) / s, Ns - 1);
+                sa[e] = a[e] / (qa < nq ? qsc[static_cast<int64_t>(qa) * Ns + jj] : 1.0f);
+            }
+            const uint32_t lo = fp8x4(sa[0], sa[1], sa[2], sa[3]), hi = fp8x4(sa[4], sa[5], sa[6], sa[7]);
+            const long av = static_cast<long>((static_cast<uint64_t>(hi) << 32) | lo);
+            const long bv = *reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(cT) +
+                                                            static_cast<int64_t>(colb) * Kp + kb);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
+        } else {
+            bf16x8_t av, bv;
+            const uint16_t *bp = reinterpret_cast<const uint16_t *>(cT) + static_cast<int64_t>(colb) * Kp + kb;
+            const uint4 braw = *reinterpret_cast<const uint4 *>(bp);
+            uint16_t ab[8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) ab[e] = bf16_rne(a[e]);
+            __builtin_memcpy(&av, ab, 16);
+            __builtin_memcpy(&bv, &braw, 16);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        }
+    }
+    const int col = n0 + lane % 16;
+    if (col >= ncol) return;
+    const int j = col / (2 * l), h = (col / l) % 2, c = col % l;
+    const float cn = cnorm[col];
+    const float cs = FP8 ? csc[j] : 1.0f;
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+        const int q = q0 + 4 * (lane / 16) + v;
+        if (q >= nq) continue;
+        const int64_t qj = static_cast<int64_t>(q) * Ns + j;
+        const float scale = FP8 ? qsc[qj] * cs : 1.0f;
+        const float dot = acc[v] * scale;
+        const float dd = qn[qj * 2 + h] + cn - 2.0f * dot;
+        cd[(qj * 2 + h) * l + c] = fmaxf(dd, 0.0f);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // probe: one wavefront per (query, subspace).  Lane c computes the squared
 // distance of each half of q' to centroid c, ranks them (stable: ties keep
 // the lower centroid id first), then runs a tournament over the l rows of
@@ -202,7 +375,7 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
     const float *__restrict__ C1, const float *__restrict__ C2,
     const uint32_t *__restrict__ offs, int64_t A_all, const int64_t *__restrict__ A_q,
     int32_t *__restrict__ cells, int32_t *__restrict__ ncells, int64_t *__restrict__ retrieved,
-    float *__restrict__ dump_cdist, int32_t *__restrict__ dump_corder) {
+    float *__restrict__ dump_cdist, int32_t *__restrict__ dump_corder, const float *__restrict__ pre) {
     extern __shared__ uint32_t sizes[];  // [K]
     __shared__ float rawD[QPW][2][WAVE];
     __shared__ float sortD[QPW][2][WAVE];
@@ -233,7 +406,13 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 
     const float *x = qt + static_cast<int64_t>(q) * M + static_cast<int64_t>(j) * s;
     float d1 = 0.0f, d2 = 0.0f;
-    if (lane < l) {
+    if (pre && lane < l) {
+        const int64_t qj0 = static_cast<int64_t>(q) * Ns + j;
+        d1 = pre[(qj0 * 2 + 0) * l + lane];
+        d2 = pre[(qj0 * 2 + 1) * l + lane];
+        rawD[wave][0][lane] = d1;
+        rawD[wave][1][lane] = d2;
+    } else if (lane < l) {
         // loads of 8 terms are issued together; the sums keep the ascending
         // one-fma-per-term order
         const float *c1 = C1 + (static_cast<int64_t>(j) * l + lane) * h1;
@@ -1463,12 +1642,13 @@ hipError_t launch_transform(const float *Q, int nq, int d, const float *mean, co
 hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, int h2, int l,
                         int K, const float *C1, const float *C2, const uint32_t *offs, int64_t A,
                         const int64_t *A_q, int32_t *cells, int32_t *ncells, int64_t *retrieved,
-                        float *dump_cdist, int32_t *dump_corder, int qpw, hipStream_t st) {
+                        float *dump_cdist, int32_t *dump_corder, const float *pre, int qpw,
+                        hipStream_t st) {
     size_t lds = sizeof(uint32_t) * static_cast<size_t>(K);
 #define TACO_PROBE(Q)                                                                          \
     k_probe<Q><<<dim3((nq + Q - 1) / Q, Ns), 64 * Q, lds, st>>>(                               \
         qt, nq, M, s, h1, h2, l, K, C1, C2, offs, A, A_q, cells, ncells, retrieved, dump_cdist, \
-        dump_corder)
+        dump_corder, pre)
     switch (qpw) {
     case 1: TACO_PROBE(1); break;
     case 2: TACO_PROBE(2); break;
@@ -1476,6 +1656,31 @@ hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, i
     default: TACO_PROBE(4); break;
     }
 #undef TACO_PROBE
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_centroids(const float *C1, const float *C2, int Ns, int s, int h1, int h2, int l,
+                                 int Kp, bool fp8, const float *csc, void *cT, float *cnorm, hipStream_t st) {
+    const int ncol = Ns * 2 * l;
+    if (fp8)
+        k_prep_cent<true><<<ncol, 64, 0, st>>>(C1, C2, Ns, s, h1, h2, l, Kp, csc, cT, cnorm);
+    else
+        k_prep_cent<false><<<ncol, 64, 0, st>>>(C1, C2, Ns, s, h1, h2, l, Kp, csc, cT, cnorm);
+    return hipGetLastError();
+}
+
+hipError_t launch_cdist_mfma(const float *qt, int nq, int M, int Ns, int s, int h1, int h2, int l, int Kp,
+                             bool fp8, const void *cT, const float *cnorm, const float *csc, float *qn,
+                             float *qsc, float *cd, hipStream_t st) {
+    if (nq <= 0) return hipSuccess;
+    const int64_t pairs = static_cast<int64_t>(nq) * Ns;
+    k_qstats<<<static_cast<unsigned>((pairs + 255) / 256), 256, 0, st>>>(qt, nq, Ns, M, s, h1, qn, qsc);
+    const int ncol = Ns * 2 * l;
+    dim3 grid((ncol + 63) / 64, (nq + 15) / 16);
+    if (fp8)
+        k_cdist_mfma<true><<<grid, 256, 0, st>>>(qt, nq, M, Ns, s, h1, h2, l, Kp, cT, cnorm, csc, qn, qsc, cd);
+    else
+        k_cdist_mfma<false><<<grid, 256, 0, st>>>(qt, nq, M, Ns, s, h1, h2, l, Kp, cT, cnorm, csc, qn, qsc, cd);
     return hipGetLastError();
 }
 

@@ -65,9 +65,10 @@ struct Reader {
 };
 
 const char *kKernelNames[] = {"transform", "probe", "count", "select", "rerank", "topk", "recheck",
-                              "count_select", "graph"};
+                              "count_select", "graph", "cdist"};
 enum Kern {
-    K_TRANSFORM = 0, K_PROBE, K_COUNT, K_SELECT, K_RERANK, K_TOPK, K_RECHECK, K_FUSED, K_GRAPH, K_COUNT_
+    K_TRANSFORM = 0, K_PROBE, K_COUNT, K_SELECT, K_RERANK, K_TOPK, K_RECHECK, K_FUSED, K_GRAPH, K_CDIST,
+    K_COUNT_
 };
 
 struct Timing {
@@ -81,7 +82,7 @@ struct GraphKey {
     int64_t nq;
     int k, k_max;
     uint64_t alpha_bits, beta_bits;
-    int precision, count_mode, W, qpw, rule, rr_blocks;
+    int precision, count_mode, W, qpw, rule, rr_blocks, cdist;
     int64_t Qb;
     bool operator==(const GraphKey &o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
@@ -140,6 +141,15 @@ struct tc_index {
     int64_t *tau_ids = nullptr;  // [Qb][1024] top-k of the upper bounds
     float *tau_d = nullptr;
     std::vector<float> mean_host;
+    // reduced-precision centroid distances (built when first selected)
+    int cdist = TC_CDIST_FP32;
+    int Kp = 0;                  // M rounded up to 32
+    void *cT = nullptr;          // [Ns*2*l][Kp] bf16 or e4m3, block-diagonal, transposed
+    float *cnorm = nullptr;      // [Ns*2*l] FP32 centroid norms
+    float *csc = nullptr;        // [Ns] FP8 centroid scales
+    int cT_form = TC_CDIST_FP32; // form cT currently holds
+    std::vector<float> C1h, C2h; // host copies of the centroids
+    float *qn = nullptr, *qsc = nullptr, *cd = nullptr;  // per-batch scratch
     // profiling
     std::vector<Timing> pending;
     double total_ms[K_COUNT_] = {0};
@@ -177,6 +187,10 @@ void free_scratch(tc_index *x) {
     (void)hipFree(x->rk_count);
     (void)hipFree(x->tau_ids);
     (void)hipFree(x->tau_d);
+    (void)hipFree(x->qn);
+    (void)hipFree(x->qsc);
+    (void)hipFree(x->cd);
+    x->qn = x->qsc = x->cd = nullptr;
     x->sc = nullptr;
     x->lb = nullptr;
     x->rk_ids = nullptr;
@@ -233,6 +247,9 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->cand_dist, size_t(qb) * x->n, "candidate distances"))) return rc;
     if ((rc = dmalloc(&x->sc, size_t(qb) * x->T * (size_t(x->W) * x->bits / 32), "packed counts")))
         return rc;
+    if ((rc = dmalloc(&x->qn, size_t(qb) * x->Ns * 2, "query half norms"))) return rc;
+    if ((rc = dmalloc(&x->qsc, size_t(qb) * x->Ns, "query scales"))) return rc;
+    if ((rc = dmalloc(&x->cd, size_t(qb) * x->Ns * 2 * x->l, "centroid distances"))) return rc;
     if (x->precision == TC_BF16) {
         if ((rc = dmalloc(&x->lb, size_t(qb) * x->n, "distance lower bounds"))) return rc;
         if ((rc = dmalloc(&x->rk_ids, size_t(qb) * x->n, "re-checked candidates"))) return rc;
@@ -279,6 +296,9 @@ void free_all(tc_index *x) {
     (void)hipFree(x->mu);
     (void)hipFree(x->base16);
     (void)hipFree(x->rowerr);
+    (void)hipFree(x->cT);
+    (void)hipFree(x->cnorm);
+    (void)hipFree(x->csc);
     for (auto &t : x->pending) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
@@ -326,6 +346,41 @@ int build_bf16(tc_index *x) {
     TC_HIP(taco::launch_prep_bf16(x->base, x->n, x->d, x->mu, x->base16, x->rowerr, nullptr),
            "building the BF16 base");
     TC_HIP(hipDeviceSynchronize(), "building the BF16 base");
+    return TC_OK;
+}
+
+// The block-diagonal centroid matrix of the reduced-precision centroid
+// distances in the given form, with FP32 norms and (FP8) one scale per
+// subspace: the largest centroid magnitude of the subspace over 240.
+int build_cdist(tc_index *x, int form) {
+    if (x->cT && x->cT_form == form) return TC_OK;
+    (void)hipFree(x->cT);
+    x->cT = nullptr;
+    x->Kp = (x->M + 31) / 32 * 32;
+    const int ncol = x->Ns * 2 * x->l;
+    std::vector<float> csc(x->Ns, 1.0f);
+    for (int j = 0; j < x->Ns; j++) {
+        float mx = 0.0f;
+        for (int c = 0; c < x->l; c++) {
+            for (int t = 0; t < x->h1; t++)
+                mx = std::max(mx, std::fabs(x->C1h[(size_t(j) * x->l + c) * x->h1 + t]));
+            for (int t = 0; t < x->h2; t++)
+                mx = std::max(mx, std::fabs(x->C2h[(size_t(j) * x->l + c) * x->h2 + t]));
+        }
+        csc[j] = mx > 0.0f ? mx / 240.0f : 1.0f;
+    }
+    int rc;
+    if (!x->csc && (rc = upload(&x->csc, csc, "centroid scales"))) return rc;
+    if (!x->cnorm && (rc = dmalloc(&x->cnorm, size_t(ncol), "centroid norms"))) return rc;
+    const size_t bytes = size_t(ncol) * x->Kp * (form == TC_CDIST_FP8 ? 1 : 2);
+    uint8_t *ct = nullptr;
+    if ((rc = dmalloc(&ct, bytes, "packed centroids"))) return rc;
+    x->cT = ct;
+    TC_HIP(taco::launch_prep_centroids(x->C1, x->C2, x->Ns, x->s, x->h1, x->h2, x->l, x->Kp,
+                                       form == TC_CDIST_FP8, x->csc, x->cT, x->cnorm, nullptr),
+           "packing the centroids");
+    TC_HIP(hipDeviceSynchronize(), "packing the centroids");
+    x->cT_form = form;
     return TC_OK;
 }
 
@@ -410,6 +465,8 @@ int load(const char *path, int device, tc_index *x) {
     if ((rc = upload(&x->B, B, "transform"))) return rc;
     if ((rc = upload(&x->C1, C1, "half-1 centroids"))) return rc;
     if ((rc = upload(&x->C2, C2, "half-2 centroids"))) return rc;
+    x->C1h = C1;
+    x->C2h = C2;
     if ((rc = upload(&x->offs, offs, "cell offsets"))) return rc;
     if ((rc = upload(&x->ids, ids, "cell ids"))) return rc;
     if ((rc = upload(&x->base, base, "base vectors"))) return rc;
@@ -512,9 +569,19 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
         float *dcd = dump && dump->cdist ? dump->cdist + b0 * x->Ns * 2 * x->l : nullptr;
         int32_t *dco = dump && dump->corder ? dump->corder + b0 * x->Ns * 2 * x->l : nullptr;
         record(x, K_PROBE, st, true);
+        const float *pre = nullptr;
+        if (x->cdist != TC_CDIST_FP32) {
+            record(x, K_CDIST, st, true);
+            TC_HIP(taco::launch_cdist_mfma(x->qt, nb, x->M, x->Ns, x->s, x->h1, x->h2, x->l, x->Kp,
+                                           x->cdist == TC_CDIST_FP8, x->cT, x->cnorm, x->csc, x->qn,
+                                           x->qsc, x->cd, st),
+                   "centroid distance kernel");
+            record(x, K_CDIST, st, false);
+            pre = x->cd;
+        }
         TC_HIP(taco::launch_probe(x->qt, nb, x->Ns, x->M, x->s, x->h1, x->h2, x->l, x->K, x->C1,
                                   x->C2, x->offs, A, Aq, x->cells, x->ncells, x->retrieved, dcd, dco,
-                                  x->probe_qpw, st),
+                                  pre, x->probe_qpw, st),
                "probe kernel");
         record(x, K_PROBE, st, false);
 
@@ -632,6 +699,7 @@ int run(tc_index *x, const Call &c, void *stream) {
     key.qpw = x->probe_qpw;
     key.rule = x->rule;
     key.rr_blocks = x->rr_blocks;
+    key.cdist = x->cdist;
     key.Qb = x->Qb;
     if (!x->graph_exec || !(key == x->graph_key)) {
         drop_graph(x);
@@ -765,6 +833,16 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
         x->precision = static_cast<int>(value);
         return alloc_scratch(x);
     }
+    case TC_OPT_CDIST_PRECISION:
+        if (value != TC_CDIST_FP32 && value != TC_CDIST_BF16 && value != TC_CDIST_FP8)
+            return fail(TC_EINVAL, "centroid-distance precision must be TC_CDIST_FP32, _BF16 or _FP8");
+        if (value != TC_CDIST_FP32) {
+            TC_HIP(hipDeviceSynchronize(), "synchronizing before packing the centroids");
+            if (int rc = build_cdist(x, static_cast<int>(value))) return rc;
+        }
+        drop_graph(x);
+        x->cdist = static_cast<int>(value);
+        return TC_OK;
     case TC_OPT_COUNT_MODE:
         if (value != TC_COUNT_AUTO && value != TC_COUNT_SPLIT && value != TC_COUNT_FUSED)
             return fail(TC_EINVAL, "unknown count mode");

@@ -85,3 +85,26 @@ def test_null_index_and_bad_options_rejected():
     assert L.tc_kernel_time(None, b"count", None, None) == taco.TC_EINVAL
     L.tc_free_index(None)  # no-op
     assert "NULL" in taco.tc_last_error()
+
+
+def _header_enums():
+    src = open(os.path.join(ROOT, "include", "taco.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    vals = {}
+    for body in re.findall(r"enum\s+\w+\s*\{(.*?)\}", src, flags=re.S):
+        for name, v in re.findall(r"\b(TC_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            vals[name] = int(v)
+    return vals
+
+
+def test_binding_constants_match_the_header():
+    vals = _header_enums()
+    assert len(vals) >= 25
+    for name, v in vals.items():
+        assert getattr(taco, name) == v, name
+
+
+def test_kernel_names_match_the_header():
+    src = open(os.path.join(ROOT, "include", "taco.h")).read()
+    doc = src[src.index("Kernel timing"):src.index("int tc_kernel_time")]
+    assert tuple(re.findall(r'"([a-z_]+)"', doc)) == taco.KERNELS
