@@ -6,21 +6,27 @@ already resident in HBM.  The workload is the 1M x 128 integer Gaussian
 mixture (1,024 components, sigma U[5,25]) with Ns=8 subspaces of 16 dims,
 50x50 IMI cells per subspace, 10,000 queries, k=10, beta=0.005, swept over
 alpha in {0.01, 0.03, 0.05}.  The reported value is QPS at recall@10 = 0.95,
-read off the (recall, QPS) points of the sweep (recall from FP64 ground
-truth on a sample of the queries).
+read off the Pareto frontier of the (recall, QPS) points of the sweep;
+recall is tie-aware against FP64 exact k-NN distances of a sample of the
+queries (computed here with numpy).
 
 Legs:
   * cpu_baseline leg (the oracle, test infrastructure): builds the serialized
     index from the workload's seed (the index builder of the method is the
-    oracle's Alg 1-3), computes the FP64 ground truth of the recall sample,
-    and times the oracle's own query on a bounded sample on the host cores.
+    oracle's Alg 1-3; both paths search this same file) and times the
+    oracle's own query on a bounded sample on the host cores.
   * GPU leg: loads the index through the C-ABI and times K steps per alpha
-    with HIP events on the search stream, per kernel as well, on two paths:
-    "fp32" (default launch configuration, FP32 re-rank) and "tuned" (the
+    with HIP events on the search stream, per kernel as well, on three
+    paths: "fp32" (default launch configuration, FP32 re-rank), "tuned" (the
     library's autotuner picks tile width, count mode, probe packing, re-rank
-    spread and re-rank precision per alpha; results are identical to FP32).
-    The tuned path is also timed replaying its captured HIP graph.  The
-    reported value is the tuned path's; both paths are listed under "paths".
+    spread and re-rank precision per alpha; results are identical to FP32)
+    and "lowp" (tuned, plus FP8 centroid distances on the matrix cores,
+    which may change the probe near ties).  Tuned and lowp are also timed
+    replaying their captured HIP graphs.  The reported value is the tuned
+    path's; all paths are listed under "paths".
+  * precision report: relative error of the BF16 and FP8 centroid distances
+    against FP64, recall@10 of each form per alpha and its loss against the
+    FP32 form, and the fraction of candidates the BF16 re-rank re-checks.
 
 Prints one JSON line.
 """
@@ -68,20 +74,7 @@ def cpu_baseline_index(w, X):
     return path
 
 
-def cpu_baseline_ground_truth(X, Qs, k):
-    from oracle import oracle as O
-    t = time.time()
-    ids, d64 = O.bruteforce(X, Qs, k)
-    log(f"FP64 ground truth for {Qs.shape[0]} queries in {time.time() - t:.1f}s")
-    return ids, d64
-
-
-def cpu_baseline_recall(ids, gt_d64, X, Qs, k):
-    from oracle import oracle as O
-    return O.recall_at_k(ids, gt_d64, X, Qs, k)
-
-
-def cpu_baseline_timing(path, X, Q, w, gt, alphas, sample):
+def cpu_baseline_timing(path, X, Q, w, kth, alphas, sample):
     """The oracle as it stands, parallel over queries with OpenMP on the host
     cores, timed on the first `sample` queries per alpha (one warm-up batch
     first); its recall is read on the first queries that have ground truth."""
@@ -90,13 +83,13 @@ def cpu_baseline_timing(path, X, Q, w, gt, alphas, sample):
     threads = O.max_threads()
     pts = []
     Qs = Q[:sample]
-    S = min(sample, gt[1].shape[0])
+    S = min(sample, kth.shape[0])
     for a in alphas:
         oidx.query_batch(Qs[:threads], a, w.beta, w.k)
         t = time.time()
         ids = oidx.query_batch(Qs, a, w.beta, w.k)
         dt = time.time() - t
-        rec = O.recall_at_k(ids[:S], gt[1][:S], X, Qs[:S], w.k)
+        rec = recall_at_k(ids[:S], kth[:S], X, Qs[:S], w.k)
         pts.append(dict(alpha=a, qps=sample / dt, recall=rec, seconds=dt))
         log(f"oracle alpha={a}: {sample / dt:.1f} QPS on {threads} threads over {sample} queries, "
             f"recall {rec:.4f}")
@@ -107,6 +100,101 @@ def cpu_baseline_timing(path, X, Q, w, gt, alphas, sample):
 # ---------------------------------------------------------------------------
 # helpers
 # ---------------------------------------------------------------------------
+
+def kth_neighbour_fp64(X, Qs, k, chunk=64):
+    """FP64 squared distance of each query's k-th nearest base row: a
+    shortlist of k+32 rows from the expanded form |x|^2 - 2 x.q in FP64,
+    then the direct sum of squared differences on the shortlist."""
+    X64 = X.astype(np.float64)
+    xn = (X64 * X64).sum(1)
+    out = np.empty(Qs.shape[0])
+    m = min(k + 32, X.shape[0])
+    for c0 in range(0, Qs.shape[0], chunk):
+        q = Qs[c0:c0 + chunk].astype(np.float64)
+        approx = xn[None, :] - 2.0 * (q @ X64.T)
+        short = np.argpartition(approx, m - 1, axis=1)[:, :m]
+        for i in range(q.shape[0]):
+            d = ((X64[short[i]] - q[i]) ** 2).sum(1)
+            out[c0 + i] = np.sort(d)[k - 1]
+    return out
+
+
+def recall_at_k(ids, kth, X, Qs, k):
+    """Mean recall@k (Section 5.1), tie-aware: a returned id is a true
+    neighbour when its FP64 distance is at most the k-th true distance (up
+    to 1e-12 relative, for summation-order differences)."""
+    hits = 0
+    for i in range(ids.shape[0]):
+        r = ids[i, :k]
+        r = r[r >= 0]
+        if r.size:
+            d = ((X[r].astype(np.float64) - Qs[i].astype(np.float64)) ** 2).sum(1)
+            hits += int(np.count_nonzero(d <= kth[i] * (1.0 + 1e-12)))
+    return hits / float(ids.shape[0] * k)
+
+
+def index_centroids(path):
+    """The half-subspace centroids C1 [Ns][l][h1], C2 [Ns][l][h2] read from
+    the index file (128-byte header, then mean, B, C1, C2, all f32)."""
+    hdr = np.fromfile(path, dtype=np.uint8, count=128)
+    d, Ns, s, h1, h2, l = (int(v) for v in hdr[24:48].view(np.int32))
+    off = 128 + 4 * (d + d * Ns * s)
+    c1 = np.fromfile(path, dtype=np.float32, count=Ns * l * h1, offset=off).reshape(Ns, l, h1)
+    c2 = np.fromfile(path, dtype=np.float32, count=Ns * l * h2, offset=off + 4 * Ns * l * h1).reshape(Ns, l, h2)
+    return c1, c2
+
+
+def precision_report(taco, path, qd, w, X, Q, kth, S, alpha, nq_err=200):
+    """The reduced-precision forms against FP64 and against the FP32 form:
+    relative error of the centroid distances (BF16 / FP8 on the matrix
+    cores), recall@10 of each form at every alpha, and for the BF16 re-rank
+    the fraction of candidates re-checked in FP32."""
+    import torch
+    c1, c2 = index_centroids(path)
+    Ns, l, h1 = c1.shape
+    rep = {}
+    forms = (("fp32", taco.TC_CDIST_FP32), ("bf16", taco.TC_CDIST_BF16), ("fp8", taco.TC_CDIST_FP8))
+    for name, val in forms:
+        idx = taco.Index(path, 0)
+        idx.set_option(taco.TC_OPT_CDIST_PRECISION, val)
+        P = min(nq_err, w.nq)
+        dump = idx.dump_buffers(P, ("qt", "cdist"))
+        idx.search_debug(qd[:P], w.k, alpha, w.beta, dump)
+        torch.cuda.synchronize()
+        qt = dump["qt"].cpu().numpy().astype(np.float64)
+        cd = dump["cdist"].cpu().numpy().astype(np.float64)
+        s = qt.shape[1] // Ns
+        rel = []
+        for j in range(Ns):
+            for h, (cen, lo, hi) in enumerate(((c1[j], 0, h1), (c2[j], h1, s))):
+                x = qt[:, j * s + lo:j * s + hi]
+                ex = ((x[:, None, :] - cen[None, :, :].astype(np.float64)) ** 2).sum(2)
+                m = ex > 0
+                rel.append(np.abs(cd[:, j, h, :][m] - ex[m]) / ex[m])
+        rel = np.concatenate(rel)
+        recalls = {}
+        ids = torch.empty((w.nq, w.k), dtype=torch.int64, device=qd.device)
+        dists = torch.empty((w.nq, w.k), dtype=torch.float32, device=qd.device)
+        for a in w.alphas:
+            idx.search(qd, w.k, a, w.beta, ids=ids, dists=dists)
+            torch.cuda.synchronize()
+            recalls[a] = recall_at_k(ids[:S].cpu().numpy(), kth, X, Q[:S], w.k)
+        idx.close()
+        rep[name] = dict(cdist_rel_err_max=float(rel.max()), cdist_rel_err_mean=float(rel.mean()),
+                         recall_at_10=recalls)
+    for name in ("bf16", "fp8"):
+        rep[name]["recall_loss_points"] = {a: 100.0 * (rep["fp32"]["recall_at_10"][a] - rep[name]["recall_at_10"][a])
+                                           for a in w.alphas}
+    idx = taco.Index(path, 0)
+    idx.set_option(taco.TC_OPT_PRECISION, taco.TC_BF16)
+    dump = idx.dump_buffers(w.nq, ("ncand", "nrecheck"))
+    idx.search_debug(qd, w.k, alpha, w.beta, dump)
+    torch.cuda.synchronize()
+    rep["bf16_rerank_recheck_fraction"] = float(dump["nrecheck"].sum().item()) / max(1.0, float(dump["ncand"].sum().item()))
+    idx.close()
+    rep["cdist_error_sample"] = f"first {min(nq_err, w.nq)} queries, all half-subspace centroids, alpha={alpha}"
+    return rep
+
 
 def qps_at_recall(points, target=RECALL_TARGET):
     """QPS at the target recall from (recall, qps) points: the Pareto
@@ -323,7 +411,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4000)
     ap.add_argument("--alpha", type=float, default=None,
                     help="run only this collision ratio of the sweep (profiling runs)")
-    ap.add_argument("--paths", default="fp32,tuned", help="comma list of fp32, tuned")
+    ap.add_argument("--paths", default="fp32,tuned,lowp",
+                    help="comma list of fp32 (defaults), tuned (autotuned, exact), lowp (tuned + FP8 "
+                         "centroid distances on the matrix cores)")
+    ap.add_argument("--skip-precision-report", action="store_true")
     ap.add_argument("--skip-cpu-baseline", action="store_true",
                     help="omit the oracle timing (profiling runs); the line then has no cpu_baseline")
     ap.add_argument("--tune-cache", default=None,
@@ -358,7 +449,9 @@ def main():
     log(f"generated {w.n}x{w.d} base and {w.nq} queries in {time.time() - t0:.1f}s")
     path = cpu_baseline_index(w, X)
     S = min(args.recall_sample, w.nq)
-    gt = cpu_baseline_ground_truth(X, Q[:S], w.k)
+    t0 = time.time()
+    kth = kth_neighbour_fp64(X, Q[:S], w.k)
+    log(f"FP64 k-th neighbour distances of {S} queries in {time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -381,12 +474,14 @@ def main():
         sweep = []
         for a in alphas:
             tuned = None
-            if pname == "tuned":
+            if pname in ("tuned", "lowp"):
                 tuned = idx.autotune(qd, w.k, a, w.beta, cache_path=tune_cache, stream=stream)
-                log(f"tuned alpha={a}: " + tuned.strip().splitlines()[-1])
+                log(f"{pname} alpha={a}: " + tuned.strip().splitlines()[-1])
+            if pname == "lowp":
+                idx.set_option(taco.TC_OPT_CDIST_PRECISION, taco.TC_CDIST_FP8)
             batches = -(-w.nq // idx.batch_capacity())
             ms, kern = timed_steps(idx, taco, qd, w, a, ids, dists, stream, args.steps, args.warmup)
-            rec = cpu_baseline_recall(ids[:S].cpu().numpy(), gt[1], X, Q[:S], w.k)
+            rec = recall_at_k(ids[:S].cpu().numpy(), kth, X, Q[:S], w.k)
             alg, avg = algorithmic_bytes(idx, qd, w, a, w.nq,
                                          bf16=tuned is not None and "precision=1" in tuned.strip().splitlines()[-1])
             for kname in KERNELS:
@@ -399,8 +494,8 @@ def main():
             qps = w.nq * args.steps / (ms * 1e-3)
             point = dict(alpha=a, qps=qps, recall=rec, ms_per_step=ms / args.steps, kernels=kern,
                          per_query=avg, batches_per_step=batches)
-            if pname == "tuned":
-                point["config"] = tuned.strip().splitlines()[-1]
+            if tuned is not None:
+                point["config"] = tuned.strip().splitlines()[-1] + (" cdist=fp8" if pname == "lowp" else "")
                 idx.set_option(taco.TC_OPT_GRAPH, 1)
                 gms, _ = timed_steps(idx, taco, qd, w, a, ids, dists, stream, args.steps, args.warmup,
                                      profile=False)
@@ -428,10 +523,16 @@ def main():
                     traffic=traffic, alg_bytes_per_launch=dk["alg_bytes_per_launch"],
                     ms_per_launch=dk["ms_per_launch"], alpha=op["alpha"], path=main_path)
 
+    precision = None
+    if not args.skip_precision_report:
+        t0 = time.time()
+        precision = precision_report(taco, path, qd, w, X, Q, kth, S, op["alpha"])
+        log(f"precision report in {time.time() - t0:.1f}s: " + json.dumps(precision))
+
     cpu = None
     if not args.skip_cpu_baseline:
         cs = min(args.cpu_sample, w.nq)
-        pts, threads = cpu_baseline_timing(path, X, Q, w, gt, alphas, cs)
+        pts, threads = cpu_baseline_timing(path, X, Q, w, kth, alphas, cs)
         cpu = dict(value=qps_at_recall(pts), unit="queries/s", cores=threads, kind="oracle",
                    sample=f"first {cs} of the {w.nq} queries at each alpha of the sweep, OpenMP over "
                           f"queries, recall on the first {min(cs, S)}; value read at recall@10=0.95 "
@@ -458,7 +559,7 @@ def main():
                                               for k_, v in p["kernels"].items() if v["launches"]})
                                 for p in sw])
                for pn, sw in results.items()},
-        roofline=roofline, cpu_baseline=cpu)
+        roofline=roofline, cpu_baseline=cpu, precision=precision)
     print(json.dumps(line), flush=True)
 
 

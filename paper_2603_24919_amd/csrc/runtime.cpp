@@ -74,6 +74,7 @@ enum Kern {
 struct Timing {
     int kernel;
     hipEvent_t start, stop;
+    bool stopped;
 };
 
 // Everything a captured graph bakes in; a call with another key is captured again.
@@ -487,27 +488,45 @@ int load(const char *path, int device, tc_index *x) {
 void record(tc_index *x, int kern, hipStream_t st, bool begin) {
     if (!x->profile) return;
     if (begin) {
-        Timing t{kern, nullptr, nullptr};
-        if (hipEventCreate(&t.start) != hipSuccess || hipEventCreate(&t.stop) != hipSuccess) return;
+        Timing t{kern, nullptr, nullptr, false};
+        if (hipEventCreate(&t.start) != hipSuccess) return;
+        if (hipEventCreate(&t.stop) != hipSuccess) {
+            (void)hipEventDestroy(t.start);
+            return;
+        }
         (void)hipEventRecord(t.start, st);
         x->pending.push_back(t);
-    } else if (!x->pending.empty() && x->pending.back().kernel == kern) {
-        (void)hipEventRecord(x->pending.back().stop, st);
+        return;
+    }
+    // the latest open interval of this kernel (intervals may nest)
+    for (auto it = x->pending.rbegin(); it != x->pending.rend(); ++it) {
+        if (it->kernel == kern && !it->stopped) {
+            (void)hipEventRecord(it->stop, st);
+            it->stopped = true;
+            return;
+        }
     }
 }
 
 int resolve_timings(tc_index *x) {
+    int rc = TC_OK;
     for (auto &t : x->pending) {
-        TC_HIP(hipEventSynchronize(t.stop), "waiting for profiled kernels");
-        float ms = 0.0f;
-        TC_HIP(hipEventElapsedTime(&ms, t.start, t.stop), "hipEventElapsedTime");
-        x->total_ms[t.kernel] += ms;
-        x->launches[t.kernel] += 1;
+        // an interval left open (its launch failed) is dropped
+        if (t.stopped && rc == TC_OK) {
+            float ms = 0.0f;
+            if (hipEventSynchronize(t.stop) != hipSuccess || hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess) {
+                (void)hipGetLastError();
+                rc = fail(TC_EDEVICE, "reading profiling events failed");
+            } else {
+                x->total_ms[t.kernel] += ms;
+                x->launches[t.kernel] += 1;
+            }
+        }
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
     }
     x->pending.clear();
-    return TC_OK;
+    return rc;
 }
 
 // One search call: uniform budgets (alpha, k) or per-query ones (alpha_dev,
@@ -568,7 +587,6 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
 
         float *dcd = dump && dump->cdist ? dump->cdist + b0 * x->Ns * 2 * x->l : nullptr;
         int32_t *dco = dump && dump->corder ? dump->corder + b0 * x->Ns * 2 * x->l : nullptr;
-        record(x, K_PROBE, st, true);
         const float *pre = nullptr;
         if (x->cdist != TC_CDIST_FP32) {
             record(x, K_CDIST, st, true);
@@ -579,6 +597,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             record(x, K_CDIST, st, false);
             pre = x->cd;
         }
+        record(x, K_PROBE, st, true);
         TC_HIP(taco::launch_probe(x->qt, nb, x->Ns, x->M, x->s, x->h1, x->h2, x->l, x->K, x->C1,
                                   x->C2, x->offs, A, Aq, x->cells, x->ncells, x->retrieved, dcd, dco,
                                   pre, x->probe_qpw, st),

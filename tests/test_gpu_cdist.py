@@ -168,3 +168,24 @@ def test_cdist_mfma_recall_loss(taco_mod, form):
     print(f"[cdist {form}] recall@10 fp32 {rec['fp32']} {form} {rec[form]}", flush=True)
     for a in w.alphas:
         assert rec[form][a] >= rec["fp32"][a] - 0.005, (a, rec)
+
+
+def test_profiling_with_cdist_form(taco_mod):
+    """Every kernel's timing reads back with the MFMA form on (its launches
+    sit between the transform's and the probe's)."""
+    t = taco_mod
+    w = synthdata.WORKLOADS["tiny-gmm-20k-d128"]
+    X, Q = synthdata.base_and_queries(w)
+    idx = t.Index(workload_index(w, X), 0)
+    try:
+        idx.set_option(t.TC_OPT_CDIST_PRECISION, t.TC_CDIST_FP8)
+        idx.set_option(t.TC_OPT_PRECISION, t.TC_BF16)
+        idx.set_option(t.TC_OPT_PROFILE, 1)
+        idx.profile_reset()
+        gpu_search(idx, Q, w.k, 0.05, w.beta)
+        got = {k: idx.kernel_time(k) for k in t.KERNELS}
+    finally:
+        idx.close()
+    for k in ("transform", "cdist", "probe", "count", "select", "rerank", "recheck"):
+        assert got[k][1] >= 1 and got[k][0] > 0.0, (k, got[k])
+    assert got["topk"][1] >= 2
