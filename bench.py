@@ -243,12 +243,13 @@ def traffic_from_profiles(kernel):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
-def algorithmic_bytes(idx, q, w, alpha, nq, bf16=False):
+def algorithmic_bytes(idx, q, w, alpha, nq, precision=0):
     """Bytes the method must move, per kernel, for one step at this alpha:
     count: ids of the probed lists (4 B each) + the slice bounds and probed
     cell ids (12 B per probed cell); select: the candidate ids written (4 B);
-    count_select: both; rerank: each candidate's row (4d B, or 2d B plus its
-    4 B error bound in BF16), id and distance (8 B) plus the query (4d B);
+    count_select: both; rerank: each candidate's row (4d B; 2d B plus its
+    4 B error bound in BF16; d B plus offset, step and error bound, 12 B, in
+    8 bits), id and distance (8 B) plus the query (4d B);
     topk: candidate keys (8 B each) and the output (12k B); recheck: the
     candidates' lower bounds (4 B each)."""
     import torch
@@ -266,7 +267,7 @@ def algorithmic_bytes(idx, q, w, alpha, nq, bf16=False):
         count=4.0 * R + 12.0 * P,
         select=4.0 * C + 4.0 * P,
         count_select=4.0 * R + 16.0 * P + 4.0 * C,
-        rerank=C * ((2.0 * d + 4.0 if bf16 else 4.0 * d) + 8.0) + nq * 4.0 * d,
+        rerank=C * ({0: 4.0 * d, 1: 2.0 * d + 4.0, 2: d + 12.0}[precision] + 8.0) + nq * 4.0 * d,
         topk=8.0 * C + 12.0 * w.k * nq,
         recheck=4.0 * C,
     ), dict(retrieved=R / nq, probed_cells=P / nq, candidates=C / nq)
@@ -482,8 +483,10 @@ def main():
             batches = -(-w.nq // idx.batch_capacity())
             ms, kern = timed_steps(idx, taco, qd, w, a, ids, dists, stream, args.steps, args.warmup)
             rec = recall_at_k(ids[:S].cpu().numpy(), kth, X, Q[:S], w.k)
-            alg, avg = algorithmic_bytes(idx, qd, w, a, w.nq,
-                                         bf16=tuned is not None and "precision=1" in tuned.strip().splitlines()[-1])
+            prec = 0
+            if tuned is not None and "precision=" in tuned:
+                prec = int(tuned.strip().splitlines()[-1].split("precision=")[1].split()[0])
+            alg, avg = algorithmic_bytes(idx, qd, w, a, w.nq, precision=prec)
             for kname in KERNELS:
                 launches = max(kern[kname]["launches"], 1)
                 kern[kname]["ms_per_launch"] = kern[kname]["ms_total"] / launches
@@ -540,11 +543,13 @@ def main():
                    seconds=sum(p["seconds"] for p in pts),
                    points=[dict(alpha=p["alpha"], qps=p["qps"], recall=p["recall"]) for p in pts])
 
-    prec_bf16 = "precision=1" in str(op.get("config", ""))
+    cfg = str(op.get("config", ""))
     line = dict(
         metric=METRIC, value=value, unit="queries/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=op["ms_per_step"], higher_is_better=True, scaling="weak",
-        vs_baseline=None, dtype="bf16+f32" if prec_bf16 else "f32", data="synthetic",
+        vs_baseline=None,
+        dtype="bf16+f32" if "precision=1" in cfg else ("u8+f32" if "precision=2" in cfg else "f32"),
+        data="synthetic",
         config=dict(workload=WORKLOAD, n=w.n, d=w.d, Ns=w.Ns, s=w.s, l=w.l,
                     queries_per_step=w.nq, k=w.k, beta=w.beta, alphas=alphas,
                     alpha=op["alpha"], path=main_path, recall_at_10=op["recall"],

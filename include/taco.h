@@ -106,8 +106,12 @@ enum tc_count_mode { TC_COUNT_AUTO = 0, TC_COUNT_SPLIT = 1, TC_COUNT_FUSED = 2 }
  *            whose interval reaches the k-th smallest upper bound are then
  *            recomputed with the TC_FP32 arithmetic.  Results (ids and
  *            distances) are identical to TC_FP32; fewer bytes are read.
- *            Not a precision form of the paper, which states none. */
-enum tc_precision { TC_FP32 = 0, TC_BF16 = 1 };
+ *   TC_U8:   the same with 8-bit rows: per row an offset (its minimum), a
+ *            step ((max - min)/255; 1 for rows of integers spanning at most
+ *            255, which are then exact) and one code per value (built on
+ *            first use, d + 12 bytes per row).  Results identical to TC_FP32.
+ * Neither is a precision form of the paper, which states none. */
+enum tc_precision { TC_FP32 = 0, TC_BF16 = 1, TC_U8 = 2 };
 
 /* Arithmetic of the query-to-centroid distances of each half subspace
  * (Alg 6's distance step, Alg 4's inputs).
@@ -228,7 +232,7 @@ typedef struct tc_stage_dump {
     int32_t *cand;      /* [nq][n]          candidate ids (first ncand, any order)   */
     float *cand_dist;   /* [nq][n]          their distances, aligned with cand
                                             (TC_FP32 re-rank only)                  */
-    int64_t *nrecheck;  /* [nq]             rows re-checked in FP32 (TC_BF16 only)   */
+    int64_t *nrecheck;  /* [nq]             rows re-checked in FP32 (TC_BF16, TC_U8)  */
 } tc_stage_dump;
 
 /* tc_search that also writes the stages requested in `dump` (host pointer to

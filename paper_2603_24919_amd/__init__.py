@@ -19,7 +19,7 @@ __all__ = [
     "TC_OPT_TILE_IDS", "TC_OPT_PROFILE", "TC_OPT_SCRATCH_BYTES", "TC_OPT_PRECISION",
     "TC_FP32", "TC_BF16", "TC_OPT_COUNT_MODE", "TC_COUNT_AUTO", "TC_COUNT_SPLIT",
     "TC_COUNT_FUSED", "TC_OPT_GRAPH", "TC_OPT_PROBE_QPW", "TC_OPT_RERANK_BLOCKS", "KERNELS",
-    "TC_OPT_CDIST_PRECISION", "TC_CDIST_FP32", "TC_CDIST_BF16", "TC_CDIST_FP8",
+    "TC_OPT_CDIST_PRECISION", "TC_CDIST_FP32", "TC_CDIST_BF16", "TC_CDIST_FP8", "TC_U8",
     "tc_device_errors", "tc_search_batched", "tc_autotune",
     "TacoError", "TacoLibraryMissing", "lib_path", "load_library",
     "tc_load_index", "tc_free_index", "tc_index_info", "tc_set_option", "tc_search",
@@ -31,7 +31,7 @@ TC_OK, TC_EINVAL, TC_EIO, TC_EFORMAT, TC_ENOMEM, TC_EDEVICE = 0, -1, -2, -3, -4,
 TC_RULE_PRINTED, TC_RULE_PROSE = 0, 1
 TC_OPT_SELECT_RULE, TC_OPT_MAX_BATCH, TC_OPT_TILE_IDS, TC_OPT_PROFILE, TC_OPT_SCRATCH_BYTES = 1, 2, 3, 4, 5
 TC_OPT_PRECISION = 6
-TC_FP32, TC_BF16 = 0, 1
+TC_FP32, TC_BF16, TC_U8 = 0, 1, 2
 TC_OPT_COUNT_MODE = 7
 TC_COUNT_AUTO, TC_COUNT_SPLIT, TC_COUNT_FUSED = 0, 1, 2
 TC_OPT_GRAPH, TC_OPT_PROBE_QPW, TC_OPT_RERANK_BLOCKS = 8, 9, 10

@@ -65,6 +65,13 @@ hipError_t launch_rerank(const float *Q, int nq, int d, const float *base, const
 hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const uint16_t *base16,
                            const float *rowerr, const int32_t *cand, const uint32_t *cand_count,
                            int64_t cap, float *ub, float *lb, int blocks_per_q, hipStream_t st);
+// 8-bit rows with a 16-byte (offset, step, error) record per row (exact for
+// integer rows within 255); plain: every record is (0, 1, 0) and none is read
+hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, const float4 *meta, bool plain,
+                          const int32_t *cand, const uint32_t *cand_count, int64_t cap, float *ub, float *lb,
+                          int blocks_per_q, hipStream_t st);
+hipError_t launch_prep_u8(const float *base, int64_t n, int d, uint8_t *base8, float4 *meta, uint32_t *plain,
+                          hipStream_t st);
 hipError_t launch_recheck(const float *Q, int nq, int d, const float *base, const int32_t *cand,
                           const uint32_t *cand_count, const float *lb, int64_t cap,
                           const float *tau_d, int k, const int32_t *kq, int k_max, int32_t *rk_ids,

@@ -1207,6 +1207,11 @@ __device__ __forceinline__ float group_sum(float acc) {
     return acc;
 }
 
+// Rows handled at once by a lane group of the re-rank kernels: the chunk
+// loop runs outside and the rows inside, so the loads of RU rows are in
+// flight together, while each row's terms keep the order of row_partial32.
+constexpr int RU = 4;
+
 template <int LPR, bool VEC4>
 __global__ __launch_bounds__(256) void k_rerank(const float *__restrict__ Q, int d,
                                                 const float *__restrict__ base,
@@ -1225,12 +1230,47 @@ __global__ __launch_bounds__(256) void k_rerank(const float *__restrict__ Q, int
     const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
     float *dq = cand_dist + static_cast<int64_t>(q) * cap;
     for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * RPW; i0 < nc;
-         i0 += stride) {
-        const int64_t i = i0 + sub;
-        float acc = 0.0f;
-        if (i < nc) acc = row_partial32<LPR, VEC4>(qs, base + static_cast<int64_t>(cq[i]) * d, d, li);
-        acc = group_sum<LPR>(acc);
-        if (li == 0 && i < nc) dq[i] = acc;
+         i0 += stride * RU) {
+        int64_t row[RU];
+        float acc[RU];
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            const int64_t i = i0 + u * stride + sub;
+            row[u] = i < nc ? static_cast<int64_t>(cq[i]) * d : -1;
+            acc[u] = 0.0f;
+        }
+        if (VEC4) {
+            const float4 *q4 = reinterpret_cast<const float4 *>(qs);
+            for (int f = li; f < d / 4; f += LPR) {
+                float4 xv[RU];
+#pragma unroll
+                for (int u = 0; u < RU; u++)
+                    xv[u] = row[u] >= 0 ? reinterpret_cast<const float4 *>(base + row[u])[f]
+                                        : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float4 qv = q4[f];
+#pragma unroll
+                for (int u = 0; u < RU; u++) {
+                    float v = qv.x - xv[u].x;
+                    acc[u] = fmaf(v, v, acc[u]);
+                    v = qv.y - xv[u].y;
+                    acc[u] = fmaf(v, v, acc[u]);
+                    v = qv.z - xv[u].z;
+                    acc[u] = fmaf(v, v, acc[u]);
+                    v = qv.w - xv[u].w;
+                    acc[u] = fmaf(v, v, acc[u]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < RU; u++)
+                if (row[u] >= 0) acc[u] = row_partial32<LPR, false>(qs, base + row[u], d, li);
+        }
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            const float a = group_sum<LPR>(acc[u]);
+            const int64_t i = i0 + u * stride + sub;
+            if (li == 0 && i < nc) dq[i] = a;
+        }
     }
 }
 
@@ -1296,42 +1336,165 @@ __global__ __launch_bounds__(256) void k_rerank16(const float *__restrict__ Q, i
     const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
     const float g = 2.0f * (d + 2) * 0x1p-24f + 0x1p-18f;
     for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * RPW; i0 < nc;
-         i0 += stride) {
-        const int64_t i = i0 + sub;
-        float acc = 0.0f;
-        int64_t id = 0;
-        if (i < nc) {
-            id = cq[i];
-            const uint16_t *row = base16 + id * d;
-            if (VEC8) {
-                const uint4 *r8 = reinterpret_cast<const uint4 *>(row);
-                for (int f = li; f < d / 8; f += LPR) {
-                    const uint4 v = r8[f];
-                    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+         i0 += stride * RU) {
+        int64_t id[RU];
+        float acc[RU];
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            const int64_t i = i0 + u * stride + sub;
+            id[u] = i < nc ? static_cast<int64_t>(cq[i]) : -1;
+            acc[u] = 0.0f;
+        }
+        if (VEC8) {
+            for (int f = li; f < d / 8; f += LPR) {
+                uint4 v[RU];
+#pragma unroll
+                for (int u = 0; u < RU; u++)
+                    v[u] = id[u] >= 0 ? reinterpret_cast<const uint4 *>(base16 + id[u] * d)[f]
+                                      : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+                for (int u = 0; u < RU; u++) {
+                    const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
 #pragma unroll
                     for (int c = 0; c < 4; c++) {
-                        float u = qs[8 * f + 2 * c] - bf16_bits_to_f32(w[c] & 0xffffu);
-                        acc = fmaf(u, u, acc);
-                        u = qs[8 * f + 2 * c + 1] - bf16_bits_to_f32(w[c] >> 16);
-                        acc = fmaf(u, u, acc);
+                        float x = qs[8 * f + 2 * c] - bf16_bits_to_f32(w[c] & 0xffffu);
+                        acc[u] = fmaf(x, x, acc[u]);
+                        x = qs[8 * f + 2 * c + 1] - bf16_bits_to_f32(w[c] >> 16);
+                        acc[u] = fmaf(x, x, acc[u]);
                     }
                 }
-            } else {
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                if (id[u] < 0) continue;
+                const uint16_t *row = base16 + id[u] * d;
                 for (int f = li; f < d; f += LPR) {
-                    const float u = qs[f] - bf16_bits_to_f32(row[f]);
-                    acc = fmaf(u, u, acc);
+                    const float x = qs[f] - bf16_bits_to_f32(row[f]);
+                    acc[u] = fmaf(x, x, acc[u]);
                 }
             }
         }
-        acc = group_sum<LPR>(acc);
-        if (li == 0 && i < nc) {
-            const float s = sqrtf(acc > 0.0f ? acc : 0.0f);
-            const float su = s * (1.0f + g);
-            const float E = rowerr[id] + 0x1p-22f * (rq + su + 1.0f);
-            const float hs = su + E;
-            const float ls = s * (1.0f - g) - E;
-            ub_out[static_cast<int64_t>(q) * cap + i] = hs * hs * (1.0f + g);
-            lb_out[static_cast<int64_t>(q) * cap + i] = ls > 0.0f ? ls * ls * (1.0f - g) : 0.0f;
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            const float sum = group_sum<LPR>(acc[u]);
+            const int64_t i = i0 + u * stride + sub;
+            if (li == 0 && i < nc) {
+                const float s = sqrtf(sum > 0.0f ? sum : 0.0f);
+                const float su = s * (1.0f + g);
+                const float E = rowerr[id[u]] + 0x1p-22f * (rq + su + 1.0f);
+                const float hs = su + E;
+                const float ls = s * (1.0f - g) - E;
+                ub_out[static_cast<int64_t>(q) * cap + i] = hs * hs * (1.0f + g);
+                lb_out[static_cast<int64_t>(q) * cap + i] = ls > 0.0f ? ls * ls * (1.0f - g) : 0.0f;
+            }
+        }
+    }
+}
+
+// The same bounds from 8-bit rows: row i is stored as codes c_t with its
+// own offset lo_i and step sc_i, x^_t = fl(lo_i + fl(c_t * sc_i)); the
+// preparation kernel computes the row's error bound against exactly these
+// values and keeps (lo, sc, error) in one 16-byte record per row, read
+// with one load.  PLAIN: every row has offset 0, step 1 and error 0 (integer
+// data in [0, 255]), and no record is read.  The query is used as is (no
+// centring), so its only rounding is inside the distance.
+// grid (G, nq), block 256, dynamic LDS d floats.
+template <int LPR, bool VEC16, bool PLAIN>
+__global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, int d,
+                                                 const uint8_t *__restrict__ base8,
+                                                 const float4 *__restrict__ meta,
+                                                 const int32_t *__restrict__ cand,
+                                                 const uint32_t *__restrict__ cand_count,
+                                                 int64_t cap, float *__restrict__ ub_out,
+                                                 float *__restrict__ lb_out) {
+    extern __shared__ float qs[];
+    __shared__ float rq_part[WAVES];
+    const int q = blockIdx.y;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    float sq = 0.0f;
+    for (int t = threadIdx.x; t < d; t += BLOCK) {
+        const float v = Q[static_cast<int64_t>(q) * d + t];
+        qs[t] = v;
+        sq = fmaf(v, v, sq);
+    }
+#pragma unroll
+    for (int m = WAVE / 2; m > 0; m >>= 1) sq += __shfl_xor(sq, m, WAVE);
+    if (lane == 0) rq_part[wave] = sq;
+    __syncthreads();
+    float rq2 = 0.0f;
+    for (int w = 0; w < WAVES; w++) rq2 += rq_part[w];
+    const float rq = sqrtf(rq2) * (1.0f + (d + 8) * 0x1p-23f);
+    const int64_t nc = cand_count[q];
+    constexpr int RPW = WAVE / LPR;
+    const int sub = lane / LPR, li = lane % LPR;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVES * RPW;
+    const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
+    const float g = 2.0f * (d + 2) * 0x1p-24f + 0x1p-18f;
+    for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * RPW; i0 < nc;
+         i0 += stride * RU) {
+        int64_t id[RU];
+        float acc[RU], lo[RU], sc[RU], er[RU];
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            const int64_t i = i0 + u * stride + sub;
+            id[u] = i < nc ? static_cast<int64_t>(cq[i]) : -1;
+            acc[u] = 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            // plain rows: offset 0, step 1, error 0 (the codes are the values)
+            const float4 m = (PLAIN || id[u] < 0) ? make_float4(0.0f, 1.0f, 0.0f, 0.0f) : meta[id[u]];
+            lo[u] = m.x;
+            sc[u] = m.y;
+            er[u] = m.z;
+        }
+        if (VEC16) {
+            for (int f = li; f < d / 16; f += LPR) {
+                uint4 v[RU];
+#pragma unroll
+                for (int u = 0; u < RU; u++)
+                    v[u] = id[u] >= 0 ? reinterpret_cast<const uint4 *>(base8 + id[u] * d)[f]
+                                      : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+                for (int u = 0; u < RU; u++) {
+                    const uint32_t w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                    for (int c = 0; c < 4; c++) {
+#pragma unroll
+                        for (int b = 0; b < 4; b++) {
+                            const float xh = lo[u] + static_cast<float>((w[c] >> (8 * b)) & 0xffu) * sc[u];
+                            const float x = qs[16 * f + 4 * c + b] - xh;
+                            acc[u] = fmaf(x, x, acc[u]);
+                        }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                if (id[u] < 0) continue;
+                const uint8_t *row = base8 + id[u] * d;
+                for (int f = li; f < d; f += LPR) {
+                    const float xh = lo[u] + static_cast<float>(row[f]) * sc[u];
+                    const float x = qs[f] - xh;
+                    acc[u] = fmaf(x, x, acc[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < RU; u++) {
+            const float sum = group_sum<LPR>(acc[u]);
+            const int64_t i = i0 + u * stride + sub;
+            if (li == 0 && i < nc) {
+                const float s = sqrtf(sum > 0.0f ? sum : 0.0f);
+                const float su = s * (1.0f + g);
+                const float E = er[u] + 0x1p-22f * (rq + su + 1.0f);
+                const float hs = su + E;
+                const float ls = s * (1.0f - g) - E;
+                ub_out[static_cast<int64_t>(q) * cap + i] = hs * hs * (1.0f + g);
+                lb_out[static_cast<int64_t>(q) * cap + i] = ls > 0.0f ? ls * ls * (1.0f - g) : 0.0f;
+            }
         }
     }
 }
@@ -1415,6 +1578,61 @@ __global__ __launch_bounds__(256) void k_prep_bf16(const float *__restrict__ bas
 #pragma unroll
     for (int m = WAVE / 2; m > 0; m >>= 1) e2 += __shfl_xor(e2, m, WAVE);
     if (lane == 0) rowerr[row] = f32_round_up(sqrt(e2) * (1.0 + 0x1p-50));
+}
+
+// 8-bit copy of the base: per row an offset, a step, the codes, and the
+// exact FP64 norm of the row's quantization error against the values the
+// re-rank reconstructs, rounded up; (offset, step, error, 0) form one 16-byte
+// record per row.  Rows of integers in [0, 255] get offset 0 and step 1 (the
+// codes are the values, error 0); other rows of integers spanning at most
+// 255 get their minimum and step 1 (exact); the rest their minimum and
+// (max - min)/255.  *plain is cleared unless every row is of the first kind.
+// One wavefront per row.
+__global__ __launch_bounds__(256) void k_prep_u8(const float *__restrict__ base, int64_t n, int d,
+                                                 uint8_t *__restrict__ base8, float4 *__restrict__ meta,
+                                                 uint32_t *__restrict__ plain) {
+    const int64_t row = static_cast<int64_t>(blockIdx.x) * WAVES + threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE;
+    if (row >= n) return;
+    float mn = __uint_as_float(0x7f800000u), mx = -mn;
+    bool integral = true;
+    for (int t = lane; t < d; t += WAVE) {
+        const float x = base[row * d + t];
+        mn = fminf(mn, x);
+        mx = fmaxf(mx, x);
+        integral = integral && x == rintf(x);
+    }
+#pragma unroll
+    for (int m = WAVE / 2; m > 0; m >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, m, WAVE));
+        mx = fmaxf(mx, __shfl_xor(mx, m, WAVE));
+    }
+    integral = __all(integral);
+    float lo = mn, sc = (mx - mn) / 255.0f;
+    if (integral && mn >= 0.0f && mx <= 255.0f) {
+        lo = 0.0f;
+        sc = 1.0f;
+    } else if (integral && mx - mn <= 255.0f) {
+        sc = 1.0f;
+    }
+    if (!(sc > 0.0f)) sc = 1.0f;
+    double e2 = 0.0;
+    for (int t = lane; t < d; t += WAVE) {
+        const float x = base[row * d + t];
+        const float c = fminf(fmaxf(rintf((x - lo) / sc), 0.0f), 255.0f);
+        const uint32_t code = static_cast<uint32_t>(c);
+        base8[row * d + t] = static_cast<uint8_t>(code);
+        const float xh = lo + static_cast<float>(code) * sc;
+        const double err = static_cast<double>(xh) - static_cast<double>(x);
+        e2 += err * err;
+    }
+#pragma unroll
+    for (int m = WAVE / 2; m > 0; m >>= 1) e2 += __shfl_xor(e2, m, WAVE);
+    if (lane == 0) {
+        const float err = f32_round_up(sqrt(e2) * (1.0 + 0x1p-50));
+        meta[row] = make_float4(lo, sc, err, 0.0f);
+        if (!(lo == 0.0f && sc == 1.0f && err == 0.0f)) atomicAnd(plain, 0u);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1814,6 +2032,43 @@ hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const
         }
     }
 #undef TACO_RR16
+    return hipGetLastError();
+}
+
+hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, const float4 *meta, bool plain,
+                          const int32_t *cand, const uint32_t *cand_count, int64_t cap, float *ub, float *lb,
+                          int blocks_per_q, hipStream_t st) {
+    dim3 grid(blocks_per_q, nq);
+    size_t lds = sizeof(float) * static_cast<size_t>(d);
+#define TACO_RR8(L, V)                                                                                    \
+    do {                                                                                                  \
+        if (plain)                                                                                        \
+            k_rerank8<L, V, true><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb); \
+        else                                                                                              \
+            k_rerank8<L, V, false><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb); \
+    } while (0)
+    if (d % 16 != 0) {
+        TACO_RR8(64, false);
+    } else {
+        // each lane reads 16 bytes = 16 codes; a row's chunks spread over LPR lanes
+        const int chunks = d / 16;
+        int lpr = 4;
+        while (lpr < 32 && lpr * 2 <= chunks) lpr <<= 1;
+        switch (lpr) {
+        case 4: TACO_RR8(4, true); break;
+        case 8: TACO_RR8(8, true); break;
+        case 16: TACO_RR8(16, true); break;
+        default: TACO_RR8(32, true); break;
+        }
+    }
+#undef TACO_RR8
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_u8(const float *base, int64_t n, int d, uint8_t *base8, float4 *meta, uint32_t *plain,
+                          hipStream_t st) {
+    const int64_t blocks = (n + WAVES - 1) / WAVES;
+    k_prep_u8<<<static_cast<unsigned>(blocks), BLOCK, 0, st>>>(base, n, d, base8, meta, plain);
     return hipGetLastError();
 }
 

@@ -136,6 +136,9 @@ struct tc_index {
     float *mu = nullptr;         // [d] mean rounded to BF16
     uint16_t *base16 = nullptr;  // [n][d] bf16(x - mu)
     float *rowerr = nullptr;     // [n] norm of each row's BF16 error, rounded up
+    uint8_t *base8 = nullptr;    // [n][d] 8-bit codes (re-rank in TC_U8)
+    float4 *rmeta = nullptr;     // [n] per-row (offset, step, error bound, 0) of the codes
+    bool u8_plain = false;       // every row: offset 0, step 1, error 0
     float *lb = nullptr;         // [Qb][n] lower bounds of the FP32 distances
     int32_t *rk_ids = nullptr;   // [Qb][n] re-checked candidates
     uint32_t *rk_count = nullptr;
@@ -223,7 +226,7 @@ int dmalloc(T **p, size_t count, const char *what) {
 // count per id; the batch size follows from the scratch budget.
 int64_t batch_for(const tc_index *x) {
     int64_t per_q = 8 * x->n + int64_t(x->T) * x->W * x->bits / 8;
-    if (x->precision == TC_BF16) per_q += 8 * x->n;
+    if (x->precision != TC_FP32) per_q += 8 * x->n;
     int64_t qb = x->scratch_budget / per_q;
     int64_t cap = x->max_batch > 0 ? x->max_batch : 4096;
     if (qb > cap) qb = cap;
@@ -251,7 +254,7 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->qn, size_t(qb) * x->Ns * 2, "query half norms"))) return rc;
     if ((rc = dmalloc(&x->qsc, size_t(qb) * x->Ns, "query scales"))) return rc;
     if ((rc = dmalloc(&x->cd, size_t(qb) * x->Ns * 2 * x->l, "centroid distances"))) return rc;
-    if (x->precision == TC_BF16) {
+    if (x->precision != TC_FP32) {
         if ((rc = dmalloc(&x->lb, size_t(qb) * x->n, "distance lower bounds"))) return rc;
         if ((rc = dmalloc(&x->rk_ids, size_t(qb) * x->n, "re-checked candidates"))) return rc;
         if ((rc = dmalloc(&x->rk_count, size_t(qb), "re-check counts"))) return rc;
@@ -300,6 +303,8 @@ void free_all(tc_index *x) {
     (void)hipFree(x->cT);
     (void)hipFree(x->cnorm);
     (void)hipFree(x->csc);
+    (void)hipFree(x->base8);
+    (void)hipFree(x->rmeta);
     for (auto &t : x->pending) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
@@ -347,6 +352,24 @@ int build_bf16(tc_index *x) {
     TC_HIP(taco::launch_prep_bf16(x->base, x->n, x->d, x->mu, x->base16, x->rowerr, nullptr),
            "building the BF16 base");
     TC_HIP(hipDeviceSynchronize(), "building the BF16 base");
+    return TC_OK;
+}
+
+int build_u8(tc_index *x) {
+    if (x->base8) return TC_OK;
+    int rc;
+    if ((rc = dmalloc(&x->base8, size_t(x->n) * x->d, "8-bit base"))) return rc;
+    if ((rc = dmalloc(&x->rmeta, size_t(x->n), "8-bit row records"))) return rc;
+    uint32_t *plain = nullptr;
+    if ((rc = dmalloc(&plain, 1, "8-bit plain flag"))) return rc;
+    const uint32_t one = 1u;
+    TC_HIP(hipMemcpy(plain, &one, sizeof one, hipMemcpyHostToDevice), "8-bit plain flag");
+    TC_HIP(taco::launch_prep_u8(x->base, x->n, x->d, x->base8, x->rmeta, plain, nullptr),
+           "building the 8-bit base");
+    uint32_t got = 0u;
+    TC_HIP(hipMemcpy(&got, plain, sizeof got, hipMemcpyDeviceToHost), "8-bit plain flag");
+    (void)hipFree(plain);
+    x->u8_plain = got != 0u;
     return TC_OK;
 }
 
@@ -626,14 +649,19 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             record(x, K_SELECT, st, false);
         }
 
-        if (x->precision == TC_BF16) {
-            // bounds from the BF16 rows, the k-th smallest upper bound, then
-            // the FP32 path's arithmetic on every row that can still make the top k
+        if (x->precision != TC_FP32) {
+            // bounds from the BF16 or 8-bit rows, the k-th smallest upper bound,
+            // then the FP32 path's arithmetic on every row that can still make the top k
             TC_HIP(taco::launch_fill_u32(x->rk_count, nb, 0u, st), "clearing re-check counts");
             record(x, K_RERANK, st, true);
-            TC_HIP(taco::launch_rerank16(Qb, nb, x->d, x->mu, x->base16, x->rowerr, x->cand,
-                                         x->cand_count, cap, x->cand_dist, x->lb, rr_blocks, st),
-                   "BF16 rerank kernel");
+            if (x->precision == TC_BF16)
+                TC_HIP(taco::launch_rerank16(Qb, nb, x->d, x->mu, x->base16, x->rowerr, x->cand,
+                                             x->cand_count, cap, x->cand_dist, x->lb, rr_blocks, st),
+                       "BF16 rerank kernel");
+            else
+                TC_HIP(taco::launch_rerank8(Qb, nb, x->d, x->base8, x->rmeta, x->u8_plain, x->cand,
+                                            x->cand_count, cap, x->cand_dist, x->lb, rr_blocks, st),
+                       "8-bit rerank kernel");
             record(x, K_RERANK, st, false);
             record(x, K_TOPK, st, true);
             TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, kq, k_max,
@@ -844,10 +872,14 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
         if (int rc = build_tiles(x)) return rc;
         return alloc_scratch(x);
     case TC_OPT_PRECISION: {
-        if (value != TC_FP32 && value != TC_BF16) return fail(TC_EINVAL, "precision must be TC_FP32 or TC_BF16");
+        if (value != TC_FP32 && value != TC_BF16 && value != TC_U8)
+            return fail(TC_EINVAL, "precision must be TC_FP32, TC_BF16 or TC_U8");
         TC_HIP(hipDeviceSynchronize(), "synchronizing before re-sizing scratch");
         if (value == TC_BF16) {
             if (int rc = build_bf16(x)) return rc;
+        }
+        if (value == TC_U8) {
+            if (int rc = build_u8(x)) return rc;
         }
         x->precision = static_cast<int>(value);
         return alloc_scratch(x);
@@ -1087,7 +1119,7 @@ int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double
         if ((rc = measure(c, &ms))) goto done;
         if (ms < best_ms) best_ms = ms, best = c;
     }
-    for (int p : {TC_FP32, TC_BF16}) {
+    for (int p : {TC_FP32, TC_BF16, TC_U8}) {
         TuneConfig c = best;
         c.precision = p;
         double ms;

@@ -175,18 +175,20 @@ def _bf16_cases():
     return [W["tiny-gmm-20k-d128"]] + scaled_workloads()
 
 
+@pytest.mark.parametrize("prec", ["bf16", "u8"])
 @pytest.mark.parametrize("w", _bf16_cases(), ids=lambda w: w.name)
-def test_bf16_rerank_equals_fp32(taco_mod, w):
-    """The BF16 re-rank with its FP32 boundary re-check returns exactly the
-    FP32 path's ids and distances (bit for bit), re-checking few rows."""
+def test_bounded_rerank_equals_fp32(taco_mod, w, prec):
+    """The BF16 and 8-bit re-ranks with their FP32 boundary re-check return
+    exactly the FP32 path's ids and distances (bit for bit), re-checking a
+    subset of the candidates."""
     t = taco_mod
     X, Q = synthdata.base_and_queries(w)
     path = workload_index(w, X)
-    print(f"[{w.name}] bf16 vs fp32", flush=True)
+    print(f"[{w.name}] {prec} vs fp32", flush=True)
     for k, alpha, beta in ((10, 0.05, 0.005), (1, 0.02, 0.01), (100, 0.01, 0.02)):
         idx = t.Index(path, 0)
         g32 = gpu_search(idx, Q, k, alpha, beta, ("ncand",))
-        idx.set_option(t.TC_OPT_PRECISION, t.TC_BF16)
+        idx.set_option(t.TC_OPT_PRECISION, t.TC_BF16 if prec == "bf16" else t.TC_U8)
         g16 = gpu_search(idx, Q, k, alpha, beta, ("ncand", "nrecheck"))
         idx.close()
         assert np.array_equal(g16["ids"], g32["ids"]), (w.name, k)
