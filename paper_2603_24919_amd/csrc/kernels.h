@@ -72,10 +72,11 @@ hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, c
                           int blocks_per_q, hipStream_t st);
 hipError_t launch_prep_u8(const float *base, int64_t n, int d, uint8_t *base8, float4 *meta, uint32_t *plain,
                           hipStream_t st);
-hipError_t launch_recheck(const float *Q, int nq, int d, const float *base, const int32_t *cand,
-                          const uint32_t *cand_count, const float *lb, int64_t cap,
-                          const float *tau_d, int k, const int32_t *kq, int k_max, int32_t *rk_ids,
-                          float *rk_dist, uint32_t *rk_count, int blocks_per_q, hipStream_t st);
+// FP32 re-check of the rows with lb <= tau, then the top-k of those rows
+hipError_t launch_recheck_topk(const float *Q, int nq, int d, const float *base, const int32_t *cand,
+                               const uint32_t *cand_count, const float *lb, int64_t cap, const float *tau_d,
+                               int k, const int32_t *kq, int k_max, int32_t *rk_ids, float *rk_dist,
+                               uint32_t *rk_count, int64_t *ids_out, float *d_out, hipStream_t st);
 hipError_t launch_prep_bf16(const float *base, int64_t n, int d, const float *mu, uint16_t *base16,
                             float *rowerr, hipStream_t st);
 hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32_t *cand_count,

@@ -2,14 +2,19 @@
 //
 // One launch per pipeline step, all stream-ordered on the caller's stream:
 //   k_transform   q' = B^T (q - mean)                 (Alg 6 transform step)
+//   k_cdist_mfma  (reduced-precision form) half-subspace centroid distances
+//                 on the matrix cores
 //   k_probe       half distances, their order, and the cell probe of Alg 4
 //                 for one (query, subspace) per wavefront
 //   k_count       per-point collision counts of a tile of ids, held in LDS,
-//                 reduced to the SC level histogram (Alg 6 count step,
+//                 and the tile's SC level histogram (Alg 6 count step,
 //                 Alg 5 histogram)
-//   k_select      the same counts rebuilt, Alg 5 threshold, candidate
-//                 compaction
-//   k_rerank      exact FP32 squared distances of the candidates
+//   k_select      Alg 5 threshold and candidate compaction from the packed
+//                 counts
+//   k_rerank      exact FP32 squared distances of the candidates, or
+//   k_rerank16/8  intervals from BF16 or 8-bit rows, k_topk on their upper
+//                 bounds, then k_recheck_topk: FP32 distances of the rows
+//                 that can still make the top k, and their top k
 //   k_topk        k smallest (distance, id) pairs by radix select
 //
 // Integer-deciding arithmetic (transform, half distances, cell keys) uses
@@ -1169,7 +1174,7 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
 // re-rank: squared L2 distance of each candidate row to its query, FP32.
 // LPR lanes cooperate on a row with 16-byte loads; the query sits in LDS.
 // The per-lane partial sums and the xor tree inside each LPR-lane group are
-// shared with k_recheck, so a row's FP32 distance is the same bits wherever
+// shared with k_recheck_topk, so a row's FP32 distance is the same bits wherever
 // it is computed.  grid (G, nq), block 256, dynamic LDS d floats.
 // ---------------------------------------------------------------------------
 
@@ -1289,7 +1294,7 @@ __global__ __launch_bounds__(256) void k_rerank(const float *__restrict__ Q, int
 // g = 2(d+2)2^-24 + 2^-18: the extra 2^-18 covers the few FP32 roundings of
 // evaluating these bounds (each <= 2^-24 relative, sqrt within 2 ulp).  If
 // tau is the k-th smallest ub, every row of the FP32 path's top-k has
-// lb <= tau; k_recheck recomputes exactly those rows with the FP32 path's
+// lb <= tau; k_recheck_topk recomputes exactly those rows with the FP32 path's
 // own arithmetic.
 // ---------------------------------------------------------------------------
 
@@ -1499,61 +1504,7 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
     }
 }
 
-// FP32 re-check of the rows whose lower bound reaches the query's tau (the
-// k-th smallest upper bound, from the top-k of the bounds).  Each lane tests
-// one candidate; the kept ones are compacted into LDS and then re-ranked by
-// row groups with the FP32 path's arithmetic.  Kept rows go to (rk_ids,
-// rk_dist).  grid (G, nq), block 256.
-constexpr int RC_CHUNK = 1024;
-
-template <int LPR, bool VEC4>
-__global__ __launch_bounds__(256) void k_recheck(const float *__restrict__ Q, int d,
-                                                 const float *__restrict__ base,
-                                                 const int32_t *__restrict__ cand,
-                                                 const uint32_t *__restrict__ cand_count,
-                                                 const float *__restrict__ lb, int64_t cap,
-                                                 const float *__restrict__ tau_d, int k_all,
-                                                 const int32_t *__restrict__ kq, int k_max,
-                                                 int32_t *__restrict__ rk_ids,
-                                                 float *__restrict__ rk_dist,
-                                                 uint32_t *__restrict__ rk_count) {
-    extern __shared__ float qs[];
-    __shared__ int32_t kept[RC_CHUNK];
-    __shared__ uint32_t nkept;
-    const int q = blockIdx.y;
-    for (int t = threadIdx.x; t < d; t += BLOCK) qs[t] = Q[static_cast<int64_t>(q) * d + t];
-    const int64_t nc = cand_count[q];
-    const int k = kq ? kq[q] : k_all;
-    const float tau = tau_d[static_cast<int64_t>(q) * k_max + (k - 1)];  // +inf when |C| < k
-    constexpr int RPW = WAVE / LPR;
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int sub = lane / LPR, li = lane % LPR;
-    const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
-    const float *lq = lb + static_cast<int64_t>(q) * cap;
-    for (int64_t c0 = static_cast<int64_t>(blockIdx.x) * RC_CHUNK; c0 < nc;
-         c0 += static_cast<int64_t>(gridDim.x) * RC_CHUNK) {
-        if (threadIdx.x == 0) nkept = 0u;
-        __syncthreads();
-        for (int j = threadIdx.x; j < RC_CHUNK; j += BLOCK) {
-            const int64_t i = c0 + j;
-            if (i < nc && lq[i] <= tau) kept[atomicAdd(&nkept, 1u)] = cq[i];
-        }
-        __syncthreads();
-        const int m = static_cast<int>(nkept);
-        for (int r0 = wave * RPW; r0 < m; r0 += WAVES * RPW) {
-            const int r = r0 + sub;
-            float acc = 0.0f;
-            if (r < m) acc = row_partial32<LPR, VEC4>(qs, base + static_cast<int64_t>(kept[r]) * d, d, li);
-            acc = group_sum<LPR>(acc);
-            if (r < m && li == 0) {
-                const uint32_t p = atomicAdd(&rk_count[q], 1u);
-                rk_ids[static_cast<int64_t>(q) * cap + p] = kept[r];
-                rk_dist[static_cast<int64_t>(q) * cap + p] = acc;
-            }
-        }
-        __syncthreads();
-    }
-}
+constexpr int RC_CHUNK = 2048;  // candidates tested per round of the re-check
 
 // BF16 copy of the base centred at mu, and each row's exact quantization
 // error norm (FP64, rounded up).  One wavefront per row.
@@ -1694,25 +1645,17 @@ __device__ __forceinline__ void for_keys(bool reg, const uint64_t (&kr)[TK_KPT],
     }
 }
 
-// k is kq[q] when kq is given (else k_all); results go to rows of k_max
-// entries, padded with (-1, +inf) past k or past |C|.
-__global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
-                                              const float *__restrict__ cand_dist,
-                                              const uint32_t *__restrict__ cand_count,
-                                              int64_t cap, int k_all, const int32_t *__restrict__ kq,
-                                              int k_max, int64_t *__restrict__ ids_out,
-                                              float *__restrict__ d_out) {
+// The k smallest of the nc keys (dq[i] bits << 32 | cq[i]) of query q, by
+// the whole workgroup (256 threads, all must call); results go to row q of
+// (ids_out, d_out), k_max entries, padded with (-1, +inf) past k or past nc.
+__device__ void topk_select(int q, const int32_t *__restrict__ cq, const float *__restrict__ dq, int64_t nc,
+                            int k, int k_max, int64_t *__restrict__ ids_out, float *__restrict__ d_out) {
     __shared__ uint32_t hist[256];
     __shared__ uint32_t wtot[WAVES];
     __shared__ uint64_t wred[2 * WAVES];
     __shared__ uint64_t sel[TOPK_MAX];
     __shared__ uint32_t nsel;
     __shared__ uint32_t s_digit, s_need, s_full;
-    const int q = blockIdx.x;
-    const int k = kq ? kq[q] : k_all;
-    const int64_t nc = cand_count[q];
-    const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
-    const float *dq = cand_dist + static_cast<int64_t>(q) * cap;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const bool reg = nc <= static_cast<int64_t>(BLOCK) * TK_KPT;
     uint64_t kr[TK_KPT];
@@ -1822,6 +1765,87 @@ __global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
             d_out[o] = __uint_as_float(0x7f800000u);
         }
     }
+}
+
+// k is kq[q] when kq is given (else k_all).  grid nq, block 256.
+__global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
+                                              const float *__restrict__ cand_dist,
+                                              const uint32_t *__restrict__ cand_count,
+                                              int64_t cap, int k_all, const int32_t *__restrict__ kq,
+                                              int k_max, int64_t *__restrict__ ids_out,
+                                              float *__restrict__ d_out) {
+    const int q = blockIdx.x;
+    topk_select(q, cand + static_cast<int64_t>(q) * cap, cand_dist + static_cast<int64_t>(q) * cap,
+                cand_count[q], kq ? kq[q] : k_all, k_max, ids_out, d_out);
+}
+
+// FP32 re-check of the rows whose lower bound reaches the query's tau (the
+// k-th smallest upper bound), then the top-k of those rows, one workgroup per
+// query.  Chunks of RC_CHUNK candidates are tested (eight loads per thread in
+// flight), the kept ones compacted into LDS and re-ranked by row groups with
+// the FP32 path's own arithmetic (row_partial32 and group_sum with the same
+// lanes per row); the kept (id, distance) pairs go to (rk_ids, rk_dist), and
+// their top k to the output rows.  grid nq, block 256, dynamic LDS d floats.
+template <int LPR, bool VEC4>
+__global__ __launch_bounds__(256) void k_recheck_topk(const float *__restrict__ Q, int d,
+                                                      const float *__restrict__ base,
+                                                      const int32_t *__restrict__ cand,
+                                                      const uint32_t *__restrict__ cand_count,
+                                                      const float *__restrict__ lb, int64_t cap,
+                                                      const float *__restrict__ tau_d, int k_all,
+                                                      const int32_t *__restrict__ kq, int k_max,
+                                                      int32_t *__restrict__ rk_ids, float *__restrict__ rk_dist,
+                                                      uint32_t *__restrict__ rk_count,
+                                                      int64_t *__restrict__ ids_out, float *__restrict__ d_out) {
+    extern __shared__ float qs[];
+    __shared__ int32_t kept[RC_CHUNK];
+    __shared__ uint32_t nkept, nrk;
+    const int q = blockIdx.x;
+    for (int t = threadIdx.x; t < d; t += BLOCK) qs[t] = Q[static_cast<int64_t>(q) * d + t];
+    const int64_t nc = cand_count[q];
+    const int k = kq ? kq[q] : k_all;
+    const float tau = tau_d[static_cast<int64_t>(q) * k_max + (k - 1)];  // +inf when |C| < k
+    constexpr int RPW = WAVE / LPR;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int sub = lane / LPR, li = lane % LPR;
+    const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
+    const float *lq = lb + static_cast<int64_t>(q) * cap;
+    int32_t *rq_ids = rk_ids + static_cast<int64_t>(q) * cap;
+    float *rq_d = rk_dist + static_cast<int64_t>(q) * cap;
+    if (threadIdx.x == 0) nrk = 0u;
+    for (int64_t c0 = 0; c0 < nc; c0 += RC_CHUNK) {
+        if (threadIdx.x == 0) nkept = 0u;
+        __syncthreads();
+        constexpr int PER = RC_CHUNK / BLOCK;
+        float lv[PER];
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int64_t i = c0 + threadIdx.x + u * BLOCK;
+            lv[u] = i < nc ? lq[i] : __uint_as_float(0x7f800000u);
+        }
+#pragma unroll
+        for (int u = 0; u < PER; u++) {
+            const int64_t i = c0 + threadIdx.x + u * BLOCK;
+            if (i < nc && lv[u] <= tau) kept[atomicAdd(&nkept, 1u)] = cq[i];
+        }
+        __syncthreads();
+        const int m = static_cast<int>(nkept);
+        for (int r0 = wave * RPW; r0 < m; r0 += WAVES * RPW) {
+            const int r = r0 + sub;
+            float acc = 0.0f;
+            if (r < m) acc = row_partial32<LPR, VEC4>(qs, base + static_cast<int64_t>(kept[r]) * d, d, li);
+            acc = group_sum<LPR>(acc);
+            if (r < m && li == 0) {
+                const uint32_t p = atomicAdd(&nrk, 1u);
+                rq_ids[p] = kept[r];
+                rq_d[p] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    const int64_t m_all = nrk;
+    if (threadIdx.x == 0) rk_count[q] = static_cast<uint32_t>(m_all);
+    topk_select(q, rq_ids, rq_d, m_all, k, k_max, ids_out, d_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -2072,15 +2096,14 @@ hipError_t launch_prep_u8(const float *base, int64_t n, int d, uint8_t *base8, f
     return hipGetLastError();
 }
 
-hipError_t launch_recheck(const float *Q, int nq, int d, const float *base, const int32_t *cand,
-                          const uint32_t *cand_count, const float *lb, int64_t cap,
-                          const float *tau_d, int k, const int32_t *kq, int k_max, int32_t *rk_ids,
-                          float *rk_dist, uint32_t *rk_count, int blocks_per_q, hipStream_t st) {
-    dim3 grid(blocks_per_q, nq);
+hipError_t launch_recheck_topk(const float *Q, int nq, int d, const float *base, const int32_t *cand,
+                               const uint32_t *cand_count, const float *lb, int64_t cap, const float *tau_d,
+                               int k, const int32_t *kq, int k_max, int32_t *rk_ids, float *rk_dist,
+                               uint32_t *rk_count, int64_t *ids_out, float *d_out, hipStream_t st) {
     size_t lds = sizeof(float) * static_cast<size_t>(d);
-#define TACO_RC(L, V)                                                                        \
-    k_recheck<L, V><<<grid, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, lb, cap, tau_d, k, \
-                                              kq, k_max, rk_ids, rk_dist, rk_count)
+#define TACO_RC(L, V)                                                                                 \
+    k_recheck_topk<L, V><<<nq, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, lb, cap, tau_d, k, kq, \
+                                                 k_max, rk_ids, rk_dist, rk_count, ids_out, d_out)
     if (d % 4 != 0) {
         TACO_RC(64, false);
     } else {

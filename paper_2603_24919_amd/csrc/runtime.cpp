@@ -652,7 +652,6 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
         if (x->precision != TC_FP32) {
             // bounds from the BF16 or 8-bit rows, the k-th smallest upper bound,
             // then the FP32 path's arithmetic on every row that can still make the top k
-            TC_HIP(taco::launch_fill_u32(x->rk_count, nb, 0u, st), "clearing re-check counts");
             record(x, K_RERANK, st, true);
             if (x->precision == TC_BF16)
                 TC_HIP(taco::launch_rerank16(Qb, nb, x->d, x->mu, x->base16, x->rowerr, x->cand,
@@ -669,16 +668,11 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                    "bound top-k kernel");
             record(x, K_TOPK, st, false);
             record(x, K_RECHECK, st, true);
-            TC_HIP(taco::launch_recheck(Qb, nb, x->d, x->base, x->cand, x->cand_count, x->lb, cap,
-                                        x->tau_d, k, kq, k_max, x->rk_ids, x->cand_dist, x->rk_count,
-                                        rr_blocks, st),
-                   "re-check kernel");
+            TC_HIP(taco::launch_recheck_topk(Qb, nb, x->d, x->base, x->cand, x->cand_count, x->lb, cap,
+                                             x->tau_d, k, kq, k_max, x->rk_ids, x->cand_dist, x->rk_count,
+                                             ids, dists, st),
+                   "re-check and top-k kernel");
             record(x, K_RECHECK, st, false);
-            record(x, K_TOPK, st, true);
-            TC_HIP(taco::launch_topk(x->rk_ids, x->cand_dist, x->rk_count, cap, nb, k, kq, k_max, ids,
-                                     dists, st),
-                   "top-k kernel");
-            record(x, K_TOPK, st, false);
             if (dump && dump->nrecheck)
                 TC_HIP(taco::launch_u32_to_i64(x->rk_count, dump->nrecheck + b0, nb, st), "dump nrecheck");
         } else {

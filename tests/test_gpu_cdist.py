@@ -188,4 +188,4 @@ def test_profiling_with_cdist_form(taco_mod):
         idx.close()
     for k in ("transform", "cdist", "probe", "count", "select", "rerank", "recheck"):
         assert got[k][1] >= 1 and got[k][0] > 0.0, (k, got[k])
-    assert got["topk"][1] >= 2
+    assert got["topk"][1] >= 1  # the bounds; the final top-k runs inside the re-check
