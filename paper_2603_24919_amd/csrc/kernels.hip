@@ -1648,7 +1648,7 @@ __device__ __forceinline__ void for_keys(bool reg, const uint64_t (&kr)[TK_KPT],
 // The k smallest of the nc keys (dq[i] bits << 32 | cq[i]) of query q, by
 // the whole workgroup (256 threads, all must call); results go to row q of
 // (ids_out, d_out), k_max entries, padded with (-1, +inf) past k or past nc.
-__device__ void topk_select(int q, const int32_t *__restrict__ cq, const float *__restrict__ dq, int64_t nc,
+__device__ __forceinline__ void topk_select(int q, const int32_t *__restrict__ cq, const float *__restrict__ dq, int64_t nc,
                             int k, int k_max, int64_t *__restrict__ ids_out, float *__restrict__ d_out) {
     __shared__ uint32_t hist[256];
     __shared__ uint32_t wtot[WAVES];
