@@ -138,6 +138,20 @@ __global__ void k_build_off2d(const uint32_t *ids, const uint32_t *offs, int Ns,
     }
 }
 
+// The id lists as the count walk reads them for tile width W: an id's
+// tile-local position loc = id mod W becomes (byte offset of its packed
+// word) << 5 | (its bit position in the word), so an increment needs no
+// index arithmetic.  Offsets stay below 2^16 (the LDS), so the code is
+// below 2^21 and never collides with the walk's 0xffffffff "no id".
+__global__ void k_encode_ids(const uint32_t *__restrict__ ids, int64_t count, int W, int bits,
+                             uint32_t *__restrict__ enc) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t per = 32u / static_cast<uint32_t>(bits);
+    const uint32_t loc = ids[i] % static_cast<uint32_t>(W);
+    enc[i] = (((loc / per) * 4u) << 5) | ((loc % per) * static_cast<uint32_t>(bits));
+}
+
 // ---------------------------------------------------------------------------
 // transform: qt[q][m] = chain over t of fma(B[t][m], fl32(Q[q][t] - mean[t]))
 // block (64, 4): x = output column, y = group of QPT queries.
@@ -575,7 +589,7 @@ constexpr int CT_STAGE = 256;                   // per-wavefront candidate stagi
 struct CountArgs {
     int Ns, K, T, W;
     int64_t n;
-    const uint32_t *ids;     // [Ns][n]
+    const uint32_t *ids;     // [Ns][n] encoded for the tile width (see k_encode_ids)
     const uint32_t *off2d;   // [Ns][K][T+1]
     const int32_t *cells;    // [nq][Ns][K]
     const int32_t *ncells;   // [nq][Ns]
@@ -623,13 +637,14 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Adds one to the packed count of tile-local id loc; returns the count it
-// held before.
+// Adds one to the packed count of an id given in its encoded form (byte
+// offset of its packed word << 5 | its bit position in the word); returns
+// the count it held before.
 template <int BITS>
-__device__ __forceinline__ uint32_t bump(uint32_t *cnt, uint32_t loc) {
-    constexpr uint32_t PER = 32 / BITS;
-    const uint32_t sh = (loc % PER) * BITS;
-    const uint32_t old = atomicAdd(&cnt[loc / PER], 1u << sh);
+__device__ __forceinline__ uint32_t bump(uint32_t *cnt, uint32_t enc) {
+    const uint32_t sh = enc & 31u;
+    uint32_t *w = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(cnt) + (enc >> 5));
+    const uint32_t old = atomicAdd(w, 1u << sh);
     return (old >> sh) & ((1u << BITS) - 1u);
 }
 
@@ -739,14 +754,14 @@ __device__ __forceinline__ void walk_load(const CountArgs &a, const CountLds &L,
 
 // The LDS increments of one round (ids of 0xffffffff skipped when GUARD).
 template <int BITS, bool HI, bool GUARD>
-__device__ __forceinline__ void walk_bump(const CountLds &L, uint32_t tile_lo, const uint32_t (&id)[CT_UNROLL],
+__device__ __forceinline__ void walk_bump(const CountLds &L, const uint32_t (&id)[CT_UNROLL],
                                           Trans<HI> &tr) {
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) {
         if (GUARD) {
-            if (id[u] != 0xffffffffu) tr.add(bump<BITS>(L.cnt, id[u] - tile_lo));
+            if (id[u] != 0xffffffffu) tr.add(bump<BITS>(L.cnt, id[u]));
         } else {
-            tr.add(bump<BITS>(L.cnt, id[u] - tile_lo));
+            tr.add(bump<BITS>(L.cnt, id[u]));
         }
     }
 }
@@ -768,7 +783,6 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
     }
     __syncthreads();
     const int totalP = L.pP[a.Ns];
-    const uint32_t tile_lo = static_cast<uint32_t>(t) * static_cast<uint32_t>(a.W);
     const int32_t *cq = a.cells + static_cast<int64_t>(q) * a.Ns * a.K;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     Trans<HI> tr{0ull, 0ull};
@@ -837,7 +851,7 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
                     held = 0;
                 }
                 held += CT_UNROLL;
-                walk_bump<BITS, HI, false>(L, tile_lo, id, tr);
+                walk_bump<BITS, HI, false>(L, id, tr);
 #pragma unroll
                 for (int u = 0; u < CT_UNROLL; u++) id[u] = nid[u];
                 w0 = wn;
@@ -851,7 +865,7 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
                 }
                 held += CT_UNROLL;
                 walk_load<true>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
-                walk_bump<BITS, HI, true>(L, tile_lo, id, tr);
+                walk_bump<BITS, HI, true>(L, id, tr);
             }
             __syncthreads();
         }
@@ -882,7 +896,11 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
     const int vec = a.W * BITS / 128;  // 16-byte words per tile
     const uint4 *c4 = reinterpret_cast<const uint4 *>(L.cnt);
     uint4 *dst = sc + (static_cast<int64_t>(q) * a.T + t) * vec;
-    for (int i = threadIdx.x; i < vec; i += CT_BLOCK) dst[i] = c4[i];
+    // streamed past the caches: the id lists should stay resident there
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 *c4v = reinterpret_cast<const u32x4 *>(c4);
+    u32x4 *dstv = reinterpret_cast<u32x4 *>(dst);
+    for (int i = threadIdx.x; i < vec; i += CT_BLOCK) __builtin_nontemporal_store(c4v[i], &dstv[i]);
 }
 
 struct SelectArgs {
@@ -1014,7 +1032,10 @@ __global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int
 #pragma unroll
         for (int u = 0; u < SEL_UNROLL; u++) {
             const int64_t i = i0 + u * stride + threadIdx.x;
-            v[u] = i < words4 ? src[i] : make_uint4(0u, 0u, 0u, 0u);
+            typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+            u32x4 t = {0u, 0u, 0u, 0u};
+            if (i < words4) t = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(src) + i);
+            v[u] = make_uint4(t.x, t.y, t.z, t.w);
         }
 #pragma unroll
         for (int u = 0; u < SEL_UNROLL; u++) {
@@ -1871,6 +1892,11 @@ hipError_t launch_build_off2d(const uint32_t *ids, const uint32_t *offs, int Ns,
     int64_t work = static_cast<int64_t>(Ns) * K;
     k_build_off2d<<<static_cast<unsigned>((work + 255) / 256), 256, 0, st>>>(ids, offs, Ns, K, n,
                                                                              T, W, off2d);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_ids(const uint32_t *ids, int64_t count, int W, int bits, uint32_t *enc, hipStream_t st) {
+    k_encode_ids<<<static_cast<unsigned>((count + 255) / 256), 256, 0, st>>>(ids, count, W, bits, enc);
     return hipGetLastError();
 }
 

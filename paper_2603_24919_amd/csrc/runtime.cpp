@@ -97,6 +97,7 @@ struct tc_index {
     // index on the device
     float *mean = nullptr, *B = nullptr, *C1 = nullptr, *C2 = nullptr, *base = nullptr;
     uint32_t *offs = nullptr, *ids = nullptr, *off2d = nullptr;
+    uint32_t *ids_enc = nullptr;  // [Ns][n] ids encoded for the current tile width
     int W = 65536, T = 1;
     int bits = 8;  // packed-count width: 4 when Ns <= 15, else 8
     int max_lds = 65536;
@@ -274,6 +275,9 @@ int build_tiles(tc_index *x) {
     TC_HIP(taco::launch_build_off2d(x->ids, x->offs, x->Ns, x->K, x->n, x->T, x->W, x->off2d,
                                     nullptr),
            "building tile offsets");
+    if (!x->ids_enc && (rc = dmalloc(&x->ids_enc, size_t(x->Ns) * x->n, "encoded id lists"))) return rc;
+    TC_HIP(taco::launch_encode_ids(x->ids, int64_t(x->Ns) * x->n, x->W, x->bits, x->ids_enc, nullptr),
+           "encoding the id lists");
     TC_HIP(taco::prepare_count_kernels(x->W, x->bits, x->Ns), "setting LDS size of the count kernels");
     TC_HIP(hipDeviceSynchronize(), "building tile offsets");
     // How many groups of T co-resident workgroups the fused kernel can keep.
@@ -296,6 +300,7 @@ void free_all(tc_index *x) {
     (void)hipFree(x->offs);
     (void)hipFree(x->ids);
     (void)hipFree(x->off2d);
+    (void)hipFree(x->ids_enc);
     (void)hipFree(x->err);
     (void)hipFree(x->mu);
     (void)hipFree(x->base16);
@@ -627,7 +632,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                "probe kernel");
         record(x, K_PROBE, st, false);
 
-        taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids, x->off2d, x->cells,
+        taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids_enc, x->off2d, x->cells,
                              x->ncells};
         taco::SelectLaunch sl{x->hist, R, x->rule, cap, x->cand, x->cand_count,
                               dump && dump->sc ? dump->sc + b0 * x->n : nullptr,
