@@ -26,7 +26,9 @@ def test_short_kernel_names():
     assert f("taco::k_select(taco::SelectArgs, int)") == "select"
     assert f("void taco::k_rerank16<16, true>(float const*)") == "rerank"
     assert f("void taco::k_rerank<16, true>(float const*)") == "rerank"
-    assert f("void taco::k_recheck<16, true>(float const*)") == "recheck"
+    assert f("void taco::k_recheck_topk<16, true>(float const*)") == "recheck"
+    assert f("void taco::k_rerank8<8, true, true>(float const*)") == "rerank"
+    assert f("void taco::k_cdist_mfma<true>(float const*)") == "cdist"
     assert f("__amd_rocclr_copyBuffer") is None
 
 
