@@ -82,13 +82,21 @@ enum tc_option {
                                Calls with stage dumps never use the graph.          */
     TC_OPT_PROBE_QPW = 9,   /* queries (wavefronts) per probe workgroup: 1,2,4,8; 4 */
     TC_OPT_RERANK_BLOCKS = 10, /* re-rank workgroups per query, [1, 1024]; default 32 */
-    TC_OPT_CDIST_PRECISION = 11 /* tc_cdist_precision of the half-subspace centroid
+    TC_OPT_CDIST_PRECISION = 11, /* tc_cdist_precision of the half-subspace centroid
                                distances that order the probe; default TC_CDIST_FP32 */
+    TC_OPT_LIST_LEVEL = 12  /* list level of TC_COUNT_LIST: 1..Ns fixes it; 0 (the
+                               default) adapts it on the device from batch to batch */
 };
 
 /* How collision counting and candidate selection are launched.
  *   TC_COUNT_SPLIT: one launch counts (LDS tiles, level histogram, packed
  *                   counts to HBM), a second one selects from the counts.
+ *   TC_COUNT_LIST:  the count launch lists the ids whose count reaches the
+ *                   list level instead of storing the counts; whenever Alg
+ *                   5's threshold is at or above that level (known from the
+ *                   histogram), the candidates are filtered from the list.
+ *                   Queries whose threshold falls below it are counted again
+ *                   and selected as in TC_COUNT_SPLIT.
  *   TC_COUNT_FUSED: one cooperative, persistent launch; the workgroups of a
  *                   query's tiles wait for each other's histogram and
  *                   select straight from LDS.  Needs all tiles of a query
@@ -96,7 +104,7 @@ enum tc_option {
  *   TC_COUNT_AUTO:  the split launches (measured faster on MI355X for
  *                   uniform budgets).
  * Results are identical. */
-enum tc_count_mode { TC_COUNT_AUTO = 0, TC_COUNT_SPLIT = 1, TC_COUNT_FUSED = 2 };
+enum tc_count_mode { TC_COUNT_AUTO = 0, TC_COUNT_SPLIT = 1, TC_COUNT_FUSED = 2, TC_COUNT_LIST = 3 };
 
 /* Arithmetic of the re-rank step.
  *   TC_FP32: FP32 squared distances from the FP32 base rows.

@@ -18,7 +18,7 @@ __all__ = [
     "TC_RULE_PRINTED", "TC_RULE_PROSE", "TC_OPT_SELECT_RULE", "TC_OPT_MAX_BATCH",
     "TC_OPT_TILE_IDS", "TC_OPT_PROFILE", "TC_OPT_SCRATCH_BYTES", "TC_OPT_PRECISION",
     "TC_FP32", "TC_BF16", "TC_OPT_COUNT_MODE", "TC_COUNT_AUTO", "TC_COUNT_SPLIT",
-    "TC_COUNT_FUSED", "TC_OPT_GRAPH", "TC_OPT_PROBE_QPW", "TC_OPT_RERANK_BLOCKS", "KERNELS",
+    "TC_COUNT_FUSED", "TC_COUNT_LIST", "TC_OPT_LIST_LEVEL", "TC_OPT_GRAPH", "TC_OPT_PROBE_QPW", "TC_OPT_RERANK_BLOCKS", "KERNELS",
     "TC_OPT_CDIST_PRECISION", "TC_CDIST_FP32", "TC_CDIST_BF16", "TC_CDIST_FP8", "TC_U8",
     "tc_device_errors", "tc_search_batched", "tc_autotune",
     "TacoError", "TacoLibraryMissing", "lib_path", "load_library",
@@ -33,7 +33,8 @@ TC_OPT_SELECT_RULE, TC_OPT_MAX_BATCH, TC_OPT_TILE_IDS, TC_OPT_PROFILE, TC_OPT_SC
 TC_OPT_PRECISION = 6
 TC_FP32, TC_BF16, TC_U8 = 0, 1, 2
 TC_OPT_COUNT_MODE = 7
-TC_COUNT_AUTO, TC_COUNT_SPLIT, TC_COUNT_FUSED = 0, 1, 2
+TC_COUNT_AUTO, TC_COUNT_SPLIT, TC_COUNT_FUSED, TC_COUNT_LIST = 0, 1, 2, 3
+TC_OPT_LIST_LEVEL = 12
 TC_OPT_GRAPH, TC_OPT_PROBE_QPW, TC_OPT_RERANK_BLOCKS = 8, 9, 10
 TC_OPT_CDIST_PRECISION = 11
 TC_CDIST_FP32, TC_CDIST_BF16, TC_CDIST_FP8 = 0, 1, 2

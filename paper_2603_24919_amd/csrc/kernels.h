@@ -26,6 +26,30 @@ struct SelectLaunch {
     uint8_t *dump_sc;
     int32_t *dump_last;
     int64_t *dump_hist;
+    const uint32_t *redo = nullptr;  // select the queued queries of a list selection
+    int redo_groups = 0;             // workgroups over them (grid y)
+};
+
+// List selection (count form 1): ids with count >= the list level are listed
+// while counting and a launch of its own selects from the lists; queries
+// whose threshold falls below the level are queued in redo
+// ([0] queued, [1] above the level, [2 + i] the queue), recounted (form 2)
+// and selected from their packed counts.
+struct ListLaunch {
+    int fixed;          // list level if > 0, else the adaptive level in *level
+    uint32_t *level;    // device word
+    int64_t cap;
+    uint32_t *list;     // [nq][cap] listed words (count << shift | id) in per-tile ranges
+    int32_t *cand;
+    uint32_t *count;
+    uint32_t *tcount;   // [nq][T] entries listed per tile
+    uint32_t *redo;
+    int redo_groups;    // workgroups per tile for the recount (grid y)
+    int64_t R;
+    int rule;
+    bool trans;         // the list launch also adds every level count (stage dumps)
+    int32_t *dump_last;
+    int64_t *dump_hist;
 };
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t st);
@@ -53,7 +77,13 @@ hipError_t launch_budgets(const double *alpha, const int32_t *kq, int nq, int64_
                           int64_t *A, int32_t *kc, uint32_t *err, hipStream_t st);
 hipError_t prepare_count_kernels(int W, int bits, int Ns);
 size_t count_lds_bytes(int W, int bits);
-hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, hipStream_t st);
+// form 0: store packed counts; 1: list (and store them when sc is given); 2: recount the queue
+hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, int form, const ListLaunch *l,
+                        hipStream_t st);
+hipError_t launch_unpack_counts(const uint32_t *sc, int nq, int T, int W, int bits, int64_t n, uint8_t *out,
+                                hipStream_t st);
+hipError_t launch_list_select(const CountLaunch &c, const ListLaunch &l, uint32_t *hist, hipStream_t st);
+int list_shift(int Ns);
 hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
                          hipStream_t st);
 size_t fused_lds_bytes(int W, int bits);

@@ -648,6 +648,13 @@ __device__ __forceinline__ uint32_t bump(uint32_t *cnt, uint32_t enc) {
     return (old >> sh) & ((1u << BITS) - 1u);
 }
 
+// The same increment when the old count is not needed.
+template <int BITS>
+__device__ __forceinline__ void bump_add(uint32_t *cnt, uint32_t enc) {
+    uint32_t *w = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(cnt) + (enc >> 5));
+    atomicAdd(w, 1u << (enc & 31u));
+}
+
 // Level transitions seen by one lane.  Byte c of lo (c < 8) or of hi (c >=
 // 8) counts the bumps that found a count of c.  An id's count rises by one
 // per bump, so the ids whose final count is >= v are exactly the bumps that
@@ -752,24 +759,26 @@ __device__ __forceinline__ void walk_load(const CountArgs &a, const CountLds &L,
     }
 }
 
-// The LDS increments of one round (ids of 0xffffffff skipped when GUARD).
-template <int BITS, bool HI, bool GUARD>
+// The LDS increments of one round (ids of 0xffffffff skipped when GUARD);
+// TR: the old counts feed the level transitions.
+template <int BITS, bool HI, bool GUARD, bool TR>
 __device__ __forceinline__ void walk_bump(const CountLds &L, const uint32_t (&id)[CT_UNROLL],
                                           Trans<HI> &tr) {
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) {
-        if (GUARD) {
-            if (id[u] != 0xffffffffu) tr.add(bump<BITS>(L.cnt, id[u]));
-        } else {
-            tr.add(bump<BITS>(L.cnt, id[u]));
+        if (!GUARD || id[u] != 0xffffffffu) {
+            if (TR)
+                tr.add(bump<BITS>(L.cnt, id[u]));
+            else
+                bump_add<BITS>(L.cnt, id[u]);
         }
     }
 }
 
-// Counts the collisions of tile t of query q into L.cnt and adds the
-// tile's "count >= v" totals to hsum[v] (hsum zeroed by the caller before;
-// complete after the caller's next barrier).
-template <int BITS, bool HI>
+// Counts the collisions of tile t of query q into L.cnt and, with TR, adds
+// the tile's "count >= v" totals to hsum[v] (hsum zeroed by the caller
+// before; complete after the caller's next barrier).
+template <int BITS, bool HI, bool TR = true>
 __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, uint32_t *hsum) {
     const int words = a.W / (32 / BITS);
     for (int i = threadIdx.x; i < words; i += CT_BLOCK) L.cnt[i] = 0u;
@@ -846,12 +855,12 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
                 const bool nhave = wn + SPAN < nfull;
                 uint32_t nid[CT_UNROLL];
                 if (nhave) walk_load<false>(a, L, seg, seg_end, nwin, tne, wn, lane, nid);
-                if (held > 255 - CT_UNROLL) {
+                if (TR && held > 255 - CT_UNROLL) {
                     trans_flush<HI>(tr, hsum, lane);
                     held = 0;
                 }
                 held += CT_UNROLL;
-                walk_bump<BITS, HI, false>(L, id, tr);
+                walk_bump<BITS, HI, false, TR>(L, id, tr);
 #pragma unroll
                 for (int u = 0; u < CT_UNROLL; u++) id[u] = nid[u];
                 w0 = wn;
@@ -859,99 +868,49 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
             }
             // the segment's last round(s), bounds-tested
             for (; w0 < nwin; w0 += STRIDE) {
-                if (held > 255 - CT_UNROLL) {
+                if (TR && held > 255 - CT_UNROLL) {
                     trans_flush<HI>(tr, hsum, lane);
                     held = 0;
                 }
                 held += CT_UNROLL;
                 walk_load<true>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
-                walk_bump<BITS, HI, true>(L, id, tr);
+                walk_bump<BITS, HI, true, TR>(L, id, tr);
             }
             __syncthreads();
         }
     }
-    trans_flush<HI>(tr, hsum, lane);
+    if (TR) trans_flush<HI>(tr, hsum, lane);
 }
 
-// grid (T, nq), block CT_BLOCK, dynamic LDS count_lds_size(W, BITS).  Adds
-// the tile's level counts to hist[q] and stores the packed counts to
-// sc[q][t] (W*BITS/8 bytes).
-template <int BITS, bool HI>
-__global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__restrict__ hist,
-                                                   uint4 *__restrict__ sc) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    const CountLds L = carve<BITS>(lds_raw, a.W);
-    __shared__ uint32_t hsum[18];
-    const int t = blockIdx.x, q = blockIdx.y;
-    if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
-    count_tile<BITS, HI>(a, q, t, L, hsum);
-    __syncthreads();
-
-    // Level histogram of the tile: hsum[v] = ids with count >= v, so level v
-    // holds hsum[v] - hsum[v+1].  Ids past n hold 0 and count nowhere.
-    if (threadIdx.x >= 1 && threadIdx.x <= a.Ns) {
-        const uint32_t hv = hsum[threadIdx.x] - hsum[threadIdx.x + 1];
-        if (hv) atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], hv);
-    }
-    const int vec = a.W * BITS / 128;  // 16-byte words per tile
-    const uint4 *c4 = reinterpret_cast<const uint4 *>(L.cnt);
-    uint4 *dst = sc + (static_cast<int64_t>(q) * a.T + t) * vec;
-    // streamed past the caches: the id lists should stay resident there
-    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-    const u32x4 *c4v = reinterpret_cast<const u32x4 *>(c4);
-    u32x4 *dstv = reinterpret_cast<u32x4 *>(dst);
-    for (int i = threadIdx.x; i < vec; i += CT_BLOCK) __builtin_nontemporal_store(c4v[i], &dstv[i]);
-}
-
-struct SelectArgs {
-    const uint32_t *hist;    // [nq][Ns+1], levels >= 1 filled by k_count
-    int64_t R;               // floor(beta*n)
-    int rule;                // 0 printed, 1 prose
-    int64_t cap;             // candidate slots per query (= n)
-    int32_t *cand;           // [nq][cap]
-    uint32_t *cand_count;    // [nq]
-    uint8_t *dump_sc;        // [nq][n] or null
-    int32_t *dump_last;      // [nq] or null
-    int64_t *dump_hist;      // [nq][Ns+1] or null
+// Output of the staged lists: slot j of the query's list receives the
+// staged value v (the id itself in the candidate lists).
+struct CandOut {
+    int32_t *cq;
+    __device__ __forceinline__ void operator()(uint32_t j, uint32_t v) const { cq[j] = static_cast<int32_t>(v); }
 };
 
-// Alg 5 scan from the level histogram (level 0 = n minus the others).
-__device__ int select_threshold(const uint32_t *h, int Ns, int64_t n, int64_t R, int rule) {
-    int64_t above0 = 0;
-    for (int v = 1; v <= Ns; v++) above0 += h[v];
-    int last = Ns;
-    int64_t cum = 0;
-    for (int v = Ns; v >= 0; v--) {
-        const int64_t hv = v == 0 ? n - above0 : static_cast<int64_t>(h[v]);
-        cum += hv;
-        const bool pass = rule == 1 ? (cum <= R) : (hv + cum <= R);
-        if (!pass) break;
-        last--;
-    }
-    return last;
-}
-
-// Move a wavefront's staged candidates to the query's list: one atomic to
+// Move a wavefront's staged entries to the query's list: one atomic to
 // reserve the range, then coalesced stores.
+template <typename Out>
 __device__ __forceinline__ void flush_stage(uint32_t *stage, uint32_t &scount, uint32_t *counter,
-                                            int32_t *out, int lane) {
+                                            const Out &out, int lane) {
     wave_sync_lds();
     uint32_t base = 0;
     if (lane == 0) base = atomicAdd(counter, scount);
     base = __shfl(base, 0, WAVE);
-    for (uint32_t i = lane; i < scount; i += WAVE) out[base + i] = static_cast<int32_t>(stage[i]);
+    for (uint32_t i = lane; i < scount; i += WAVE) out(base + i, stage[i]);
     wave_sync_lds();
     scount = 0;
 }
 
-// Appends the ids flagged in a lane's NM masks (bit 8b+7 of mask i flags
-// id_of(i, b)) to the query's candidate list, in lane order: an exclusive
-// prefix sum over the wavefront places each lane's ids, which go to the
+// Appends the entries flagged in a lane's NM masks (bit 8b+7 of mask i
+// flags entry id_of(i, b)) to the query's list, in lane order: an exclusive
+// prefix sum over the wavefront places each lane's entries, which go to the
 // wavefront's LDS stage of CAP slots, or straight to the list (one
 // reservation) when they outnumber the stage.
-template <int CAP, int NM, typename IdOf>
+template <int CAP, int NM, typename IdOf, typename Out>
 __device__ __forceinline__ void append_flagged(const uint32_t (&m)[NM], IdOf id_of, uint32_t *stage,
-                                               uint32_t &scount, uint32_t *counter, int32_t *out,
+                                               uint32_t &scount, uint32_t *counter, const Out &out,
                                                int lane) {
     uint32_t cnt = 0u;
 #pragma unroll
@@ -985,11 +944,235 @@ __device__ __forceinline__ void append_flagged(const uint32_t (&m)[NM], IdOf id_
             while (mm != 0u) {
                 const int bit = __builtin_ctz(mm);
                 mm &= mm - 1u;
-                out[j++] = static_cast<int32_t>(id_of(i, bit >> 3));
+                out(j++, id_of(i, bit >> 3));
             }
         }
     }
 }
+
+struct SelectArgs {
+    const uint32_t *hist;    // [nq][Ns+1], levels >= 1 filled by k_count
+    int64_t R;               // floor(beta*n)
+    int rule;                // 0 printed, 1 prose
+    int64_t cap;             // candidate slots per query (= n)
+    int32_t *cand;           // [nq][cap]
+    uint32_t *cand_count;    // [nq]
+    uint8_t *dump_sc;        // [nq][n] or null
+    int32_t *dump_last;      // [nq] or null
+    int64_t *dump_hist;      // [nq][Ns+1] or null
+    const uint32_t *redo;    // null: query blockIdx.y; else the queue of ListArgs::redo
+};
+
+// Alg 5 scan from the level histogram (level 0 = n minus the others).
+__device__ int select_threshold(const uint32_t *h, int Ns, int64_t n, int64_t R, int rule) {
+    int64_t above0 = 0;
+    for (int v = 1; v <= Ns; v++) above0 += h[v];
+    int last = Ns;
+    int64_t cum = 0;
+    for (int v = Ns; v >= 0; v--) {
+        const int64_t hv = v == 0 ? n - above0 : static_cast<int64_t>(h[v]);
+        cum += hv;
+        const bool pass = rule == 1 ? (cum <= R) : (hv + cum <= R);
+        if (!pass) break;
+        last--;
+    }
+    return last;
+}
+
+__device__ __forceinline__ void dump_threshold(int32_t *dump_last, int64_t *dump_hist, int q, int Ns,
+                                               int64_t n, const uint32_t *h, int last) {
+    if (dump_last) dump_last[q] = last;
+    if (dump_hist) {
+        int64_t above0 = 0;
+        for (int v = 1; v <= Ns; v++) above0 += h[v];
+        dump_hist[static_cast<int64_t>(q) * (Ns + 1)] = n - above0;
+        for (int v = 1; v <= Ns; v++) dump_hist[static_cast<int64_t>(q) * (Ns + 1) + v] = h[v];
+    }
+}
+
+// List selection.  With a list level Lv, counting also lists every id of
+// the tile whose count reaches Lv in the tile's own range of the query's
+// list slots, [tW, tW + its entries) (a tile lists at most its own ids, so
+// the range stays below n), as one word count << shift | id (shift = 31 -
+// bit width of Ns; the loader's bound Ns*n < 2^30 leaves room for both),
+// the number of its entries in tcount[q][t], and adds the levels of the
+// listed ids to hist[q] (exact for every level >= Lv).  Alg 5's threshold `last` follows from
+// the level histogram alone, in a launch of its own once every tile is
+// counted: when last >= Lv the candidates are exactly the listed ids with
+// count >= last (filtered in place); queries with last < Lv are queued,
+// counted again with their packed counts stored (CT_REDO) and take the
+// streaming selection.  The level is fixed, or adapted on the device
+// from batch to batch: down when more than 1/16 of a batch was queued, up
+// when at least 63/64 of it had last > Lv.  Results never depend on it.
+enum CountForm { CT_STORE = 0, CT_LIST = 1, CT_REDO = 2 };
+
+struct ListArgs {
+    int fixed;          // list level if > 0, else the adaptive level *level
+    uint32_t *level;    // adaptive level, kept on the device across batches
+    int shift;          // a listed word is count << shift | id
+    int nq;             // queries in the batch
+    int64_t cap;        // slots per query
+    uint32_t *list;     // [nq][cap] the lists
+    int32_t *cand;      // [nq][cap] the candidates
+    uint32_t *count;    // [nq] candidate counts
+    uint32_t *tcount;   // [nq][T] entries listed by each tile
+    int T, W;           // tiles per query, ids per tile
+    uint32_t *redo;     // [0] queued queries, [1] queries with last > level, [2 + i] the queue
+    int64_t R;          // floor(beta*n)
+    int rule;           // Alg 5 reading
+    int redo_hist;      // the recount adds the queued queries' level counts
+    int32_t *dump_last; // [nq] or null
+    int64_t *dump_hist; // [nq][Ns+1] or null
+};
+
+__device__ __forceinline__ uint32_t list_level(const ListArgs &la) {
+    return la.fixed > 0 ? static_cast<uint32_t>(la.fixed) : *la.level;
+}
+
+// Flags of the packed counts >= lv (1 <= lv <= Ns) in one word: the top bit
+// of each nibble or byte.  Nibbles of counts <= 8 take one add (v + 8 - lv
+// stays below 16); with counts up to 15 the low three bits are tested apart
+// from the 8s bit; bytes take the borrow-free subtraction.
+template <int BITS, bool HI>
+__device__ __forceinline__ uint32_t flag_counts(uint32_t w, uint32_t lv) {
+    if (BITS == 8) return ((w | 0x80808080u) - lv * 0x01010101u) & 0x80808080u;
+    if (!HI) return (w + (8u - lv) * 0x11111111u) & 0x88888888u;
+    const uint32_t h = w & 0x88888888u, t = w & 0x77777777u;
+    return lv <= 8u ? (h | ((t + (8u - lv) * 0x11111111u) & 0x88888888u))
+                    : (h & ((t + (16u - lv) * 0x11111111u) & 0x88888888u));
+}
+
+// Lists the tile's ids with count >= lv in the tile's range of the query's
+// list, and tallies their levels in lsum.  Each thread tests the 16 packed
+// words it owns per pass (four
+// 16-byte words), keeping only the number of flagged ids and a 16-bit mask
+// of the words holding any; a prefix sum over the workgroup places them (no
+// atomics: the T tiles of a query write disjoint ranges), and only the
+// flagged words are read again from LDS to extract their ids.  Ids past n
+// hold 0 and lv >= 1, so none is listed.  wsum: CT_WAVES words of LDS.
+template <int BITS, bool HI>
+__device__ __forceinline__ void list_tile(const ListArgs &la, const uint32_t *cnt, uint32_t *wsum, uint32_t *lsum,
+                                          int vec, int q, int t, int W, uint32_t lv, int wave, int lane) {
+    constexpr int PER_WORD = 32 / BITS;
+    constexpr uint32_t CMASK = (1u << BITS) - 1u;
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 *c4v = reinterpret_cast<const u32x4 *>(cnt);
+    uint32_t *dst = la.list + static_cast<int64_t>(q) * la.cap;
+    const uint32_t base = static_cast<uint32_t>(t) * static_cast<uint32_t>(W);
+    uint32_t run = 0u;  // entries of this tile placed so far
+    for (int i0 = 0; i0 < vec; i0 += 4 * CT_BLOCK) {
+        uint32_t c = 0u, nz = 0u;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int i = i0 + k * CT_BLOCK + static_cast<int>(threadIdx.x);
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (i < vec) v = c4v[i];
+            const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const uint32_t f = flag_counts<BITS, HI>(wv[e], lv);
+                c += static_cast<uint32_t>(__popc(f));
+                nz |= min(f, 1u) << (4 * k + e);
+            }
+        }
+        const uint32_t inc = wave_incl_scan_u32(c, lane);
+        if (lane == WAVE - 1) wsum[wave] = inc;
+        __syncthreads();
+        // lane x holds wavefront x's total: the sum below this wavefront is
+        // its offset, the sum of all the pass's total
+        const uint32_t xt = lane < CT_WAVES ? wsum[lane] : 0u;
+        const uint32_t before = wave_sum_u32(lane < wave ? xt : 0u), tot = wave_sum_u32(xt);
+        uint32_t j = base + run + before + inc - c;
+        run += tot;
+        while (nz != 0u) {
+            const int x = __builtin_ctz(nz);
+            nz &= nz - 1u;
+            // 32-bit word e of 16-byte word k of this thread
+            const int word = (i0 + (x >> 2) * CT_BLOCK + static_cast<int>(threadIdx.x)) * 4 + (x & 3);
+            const uint32_t wv = cnt[word];
+            uint32_t mm = flag_counts<BITS, HI>(wv, lv);
+            const uint32_t id0 = base + static_cast<uint32_t>(word * PER_WORD);
+            do {
+                const int sub = __builtin_ctz(mm) / BITS;
+                mm &= mm - 1u;
+                const uint32_t cv = (wv >> (BITS * sub)) & CMASK;
+                atomicAdd(&lsum[cv], 1u);
+                dst[j++] = (cv << la.shift) | (id0 + static_cast<uint32_t>(sub));
+            } while (mm != 0u);
+        }
+        if (i0 + 4 * CT_BLOCK < vec) __syncthreads();  // wsum is rewritten by the next pass
+    }
+    if (threadIdx.x == 0) la.tcount[static_cast<int64_t>(q) * la.T + t] = run;
+}
+
+// grid (T, nq) (CT_REDO: (T, any)), block CT_BLOCK, dynamic LDS
+// count_lds_size(W, BITS).  CT_STORE: adds the tile's level counts to
+// hist[q] and stores the packed counts to sc[q][t] (W*BITS/8 bytes).
+// CT_LIST: lists the ids with count >= the list level, and with TR adds the
+// level counts (stage dumps; the list selection needs only the levels >=
+// the list level, which the list holds); the packed counts are stored too
+// when sc is given.  CT_REDO: for each queued query, stores the packed
+// counts and, with la.redo_hist, adds its level counts; workgroup (0, 0)
+// also moves the adaptive level.
+template <int BITS, bool HI, int MODE, bool TR>
+__global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__restrict__ hist,
+                                                   uint4 *__restrict__ sc, ListArgs la) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const CountLds L = carve<BITS>(lds_raw, a.W);
+    __shared__ uint32_t hsum[18];
+    __shared__ uint32_t lsum[17];  // levels of the listed ids
+    const int t = blockIdx.x;
+    const int lane = threadIdx.x % WAVE;
+    const int vec = a.W * BITS / 128;  // 16-byte words per tile
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 *c4v = reinterpret_cast<const u32x4 *>(L.cnt);
+    uint32_t nrun = 1u, f0 = 0u, fstep = 1u;
+    if (MODE == CT_REDO) {
+        nrun = la.redo[0];
+        f0 = blockIdx.y;
+        fstep = gridDim.y;
+        if (la.fixed == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+            const uint32_t lv = *la.level, nf = la.redo[0], na = la.redo[1];
+            const uint32_t nq = static_cast<uint32_t>(la.nq);
+            uint32_t nl = lv;
+            if (nf * 16u > nq && lv > 1u)
+                nl = lv - 1u;
+            else if (na * 64u >= nq * 63u && lv < static_cast<uint32_t>(a.Ns))
+                nl = lv + 1u;
+            if (nl != lv) *la.level = nl;
+        }
+    }
+    for (uint32_t f = f0; f < nrun; f += fstep) {
+        const int q = MODE == CT_REDO ? static_cast<int>(la.redo[2 + f]) : static_cast<int>(blockIdx.y);
+        if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
+        if (MODE == CT_LIST && threadIdx.x < 17) lsum[threadIdx.x] = 0u;
+        count_tile<BITS, HI, TR>(a, q, t, L, hsum);
+        __syncthreads();
+
+        // Level histogram of the tile: hsum[v] = ids with count >= v, so level v
+        // holds hsum[v] - hsum[v+1].  Ids past n hold 0 and count nowhere.
+        if (TR && (MODE != CT_REDO || la.redo_hist) && threadIdx.x >= 1 && threadIdx.x <= a.Ns) {
+            const uint32_t hv = hsum[threadIdx.x] - hsum[threadIdx.x + 1];
+            if (hv) atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], hv);
+        }
+        if (MODE != CT_LIST || sc) {
+            // streamed past the caches: the id lists should stay resident there
+            u32x4 *dstv = reinterpret_cast<u32x4 *>(sc + (static_cast<int64_t>(q) * a.T + t) * vec);
+            for (int i = threadIdx.x; i < vec; i += CT_BLOCK) __builtin_nontemporal_store(c4v[i], &dstv[i]);
+        }
+        if (MODE == CT_LIST) {
+            list_tile<BITS, HI>(la, L.cnt, L.wsum, lsum, vec, q, t, a.W, list_level(la), threadIdx.x / WAVE, lane);
+            if (!TR) {
+                // levels >= the list level: the listed ids are all of them
+                __syncthreads();
+                if (threadIdx.x >= 1 && threadIdx.x <= a.Ns && lsum[threadIdx.x])
+                    atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], lsum[threadIdx.x]);
+            }
+        }
+        if (MODE == CT_REDO) __syncthreads();
+    }
+}
+
 
 // Streaming pass over the packed counts of one query: Alg 5's threshold from
 // the level histogram, then compaction of C = {id : SC[id] >= last} through
@@ -999,24 +1182,33 @@ constexpr int SEL_BLOCK = 512;
 constexpr int SEL_WAVES = SEL_BLOCK / WAVE;
 constexpr int SEL_UNROLL = 4;
 
+
+template <int BITS>
+__device__ __forceinline__ void select_query(const SelectArgs &sa, int Ns, int64_t n, int64_t words4,
+                                             const uint4 *__restrict__ sc, int q, uint32_t *stage_all);
+
+// With sa.redo, the queued queries instead (grid (blocks per query, any)).
 template <int BITS>
 __global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int64_t n,
                                                      int64_t words4, const uint4 *__restrict__ sc) {
+    __shared__ uint32_t stage_all[SEL_WAVES * CT_STAGE];
+    if (!sa.redo) {
+        select_query<BITS>(sa, Ns, n, words4, sc, blockIdx.y, stage_all);
+        return;
+    }
+    const uint32_t nrun = sa.redo[0];
+    for (uint32_t f = blockIdx.y; f < nrun; f += gridDim.y)
+        select_query<BITS>(sa, Ns, n, words4, sc, static_cast<int>(sa.redo[2 + f]), stage_all);
+}
+
+template <int BITS>
+__device__ __forceinline__ void select_query(const SelectArgs &sa, int Ns, int64_t n, int64_t words4,
+                                             const uint4 *__restrict__ sc, int q, uint32_t *stage_all) {
     constexpr int PER_WORD = 32 / BITS;   // ids per 32-bit word
     constexpr int PER_VEC = 128 / BITS;   // ids per 16-byte word
-    __shared__ uint32_t stage_all[SEL_WAVES * CT_STAGE];
-    const int q = blockIdx.y;
     const uint32_t *h = sa.hist + static_cast<int64_t>(q) * (Ns + 1);
     const int last = select_threshold(h, Ns, n, sa.R, sa.rule);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (sa.dump_last) sa.dump_last[q] = last;
-        if (sa.dump_hist) {
-            int64_t above0 = 0;
-            for (int v = 1; v <= Ns; v++) above0 += h[v];
-            sa.dump_hist[static_cast<int64_t>(q) * (Ns + 1)] = n - above0;
-            for (int v = 1; v <= Ns; v++) sa.dump_hist[static_cast<int64_t>(q) * (Ns + 1) + v] = h[v];
-        }
-    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) dump_threshold(sa.dump_last, sa.dump_hist, q, Ns, n, h, last);
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     int32_t *cq = sa.cand + static_cast<int64_t>(q) * sa.cap;
     uint32_t *stage = stage_all + wave * CT_STAGE;
@@ -1072,10 +1264,111 @@ __global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int
                 [&](int i, int b) {
                     return static_cast<uint32_t>(id0 + (i / 2) * PER_WORD + (BITS == 8 ? b : 2 * b + (i % 2)));
                 },
-                stage, scount, counter, cq, lane);
+                stage, scount, counter, CandOut{cq}, lane);
         }
     }
-    if (__any(scount != 0u)) flush_stage(stage, scount, counter, cq, lane);
+    if (__any(scount != 0u)) flush_stage(stage, scount, counter, CandOut{cq}, lane);
+}
+
+// Alg 5 on a query's lists: the threshold from the histogram's levels >=
+// the list level, scanned from the top (where this scan stops, the full
+// scan stops; if it passes the list level, last < it), then either the
+// queue (last < list level; with redo_hist its histogram row is cleared for
+// the recount) or the candidates: the listed ids with count >= last, moved
+// from the tiles' list ranges to the candidate slots.  Each wavefront takes
+// whole tiles; the order of candidates is free, so a wavefront reserves its
+// slots with one LDS add per 256 entries.  grid nq, block LS_BLOCK.
+constexpr int LS_BLOCK = 256;
+constexpr int LS_UNROLL = 4;
+
+__global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t *__restrict__ hist, int Ns,
+                                                          int64_t n) {
+    __shared__ int s_last;
+    __shared__ uint32_t s_out;
+    const int q = blockIdx.x;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int lv = static_cast<int>(list_level(la));
+    uint32_t *h = hist + static_cast<int64_t>(q) * (Ns + 1);
+    if (threadIdx.x == 0) {
+        int last = Ns;
+        int64_t cum = 0;
+        for (int v = Ns; v >= lv; v--) {
+            const int64_t hv = h[v];
+            cum += hv;
+            const bool pass = la.rule == 1 ? (cum <= la.R) : (hv + cum <= la.R);
+            if (!pass) break;
+            last--;
+        }
+        if (la.dump_last || la.dump_hist)
+            // stage dumps: the histogram is complete here; the threshold is
+            // the full scan's (equal to last whenever last >= lv)
+            dump_threshold(la.dump_last, la.dump_hist, q, Ns, n, h, select_threshold(h, Ns, n, la.R, la.rule));
+        if (last < lv) {
+            const uint32_t f = atomicAdd(&la.redo[0], 1u);
+            la.redo[2 + f] = static_cast<uint32_t>(q);
+            la.count[q] = 0u;
+            if (la.redo_hist)
+                for (int v = 1; v <= Ns; v++) h[v] = 0u;
+        } else if (last > lv) {
+            atomicAdd(&la.redo[1], 1u);
+        }
+        s_last = last;
+        s_out = 0u;
+    }
+    __syncthreads();
+    const int last = s_last;
+    if (last < lv) return;
+    const uint32_t *ls = la.list + static_cast<int64_t>(q) * la.cap;
+    int32_t *cq = la.cand + static_cast<int64_t>(q) * la.cap;
+    const uint32_t idmask = (1u << la.shift) - 1u, lu = static_cast<uint32_t>(last);
+    const uint64_t below = lanes_below(lane);
+    for (int t = wave; t < la.T; t += LS_BLOCK / WAVE) {
+        const uint32_t nt = la.tcount[static_cast<int64_t>(q) * la.T + t];
+        const uint32_t *et = ls + static_cast<int64_t>(t) * la.W;
+        for (uint32_t b0 = 0; b0 < nt; b0 += WAVE * LS_UNROLL) {
+            uint32_t v[LS_UNROLL];
+#pragma unroll
+            for (int u = 0; u < LS_UNROLL; u++) {
+                const uint32_t i = b0 + u * WAVE + lane;
+                v[u] = i < nt ? et[i] : 0u;
+            }
+            uint64_t m[LS_UNROLL];
+            uint32_t tot = 0u;
+#pragma unroll
+            for (int u = 0; u < LS_UNROLL; u++) {
+                // listed words hold a count >= 1; 0 marks an empty slot
+                m[u] = __ballot(v[u] != 0u && (v[u] >> la.shift) >= lu);
+                tot += static_cast<uint32_t>(__popcll(m[u]));
+            }
+            if (tot == 0u) continue;
+            uint32_t base = 0u;
+            if (lane == 0) base = atomicAdd(&s_out, tot);
+            base = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(base));
+#pragma unroll
+            for (int u = 0; u < LS_UNROLL; u++) {
+                if ((m[u] >> lane) & 1u) cq[base + __popcll(m[u] & below)] = static_cast<int32_t>(v[u] & idmask);
+                base += static_cast<uint32_t>(__popcll(m[u]));
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) la.count[q] = s_out;
+}
+
+// Packed counts [nq][T*W] to one byte per id [nq][n] (stage dumps).
+template <int BITS>
+__global__ void k_unpack_counts(const uint32_t *__restrict__ sc, int64_t words_q, int64_t n,
+                                uint8_t *__restrict__ out) {
+    constexpr int PER_WORD = 32 / BITS;
+    const int q = blockIdx.y;
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < words_q;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const uint32_t w = sc[q * words_q + i];
+        for (int b = 0; b < PER_WORD; b++) {
+            const int64_t id = i * PER_WORD + b;
+            if (id < n) out[q * n + id] = static_cast<uint8_t>((w >> (BITS * b)) & ((1u << BITS) - 1u));
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1184,9 +1477,9 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
                 [&](int i2, int b) {
                     return static_cast<uint32_t>(tile_lo + i * PER_WORD + (BITS == 8 ? b : 2 * b + i2));
                 },
-                stage, scount, sa.cand_count + q, cq, lane);
+                stage, scount, sa.cand_count + q, CandOut{cq}, lane);
         }
-        if (__any(scount != 0u)) flush_stage(stage, scount, sa.cand_count + q, cq, lane);
+        if (__any(scount != 0u)) flush_stage(stage, scount, sa.cand_count + q, CandOut{cq}, lane);
         __syncthreads();
     }
 }
@@ -1425,6 +1718,11 @@ __global__ __launch_bounds__(256) void k_rerank16(const float *__restrict__ Q, i
 // with one load.  PLAIN: every row has offset 0, step 1 and error 0 (integer
 // data in [0, 255]), and no record is read.  The query is used as is (no
 // centring), so its only rounding is inside the distance.
+// PLAIN with 16 | d <= 256 and a query of integers in [0, 255]: every term
+// (q_t - x_t)^2 <= 255^2 and every partial sum <= d * 255^2 < 2^24 are
+// integers that FP32 holds exactly, so the FP32 path's distance is the
+// exact integer |q|^2 + |x|^2 - 2 q.x whatever its summation order; that is
+// computed with byte dot products and written as both bounds.
 // grid (G, nq), block 256, dynamic LDS d floats.
 template <int LPR, bool VEC16, bool PLAIN>
 __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, int d,
@@ -1456,6 +1754,67 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
     const int sub = lane / LPR, li = lane % LPR;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVES * RPW;
     const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
+    if (PLAIN && VEC16 && d <= 256) {
+        __shared__ uint32_t qb[64];  // the query's bytes, four per word
+        bool ok = true;
+        for (int t = threadIdx.x; t < d; t += BLOCK) {
+            const float v = qs[t];
+            ok = ok && v >= 0.0f && v <= 255.0f && v == rintf(v);
+        }
+        if (__syncthreads_and(ok)) {
+            for (int w = threadIdx.x; w < d / 4; w += BLOCK)
+                qb[w] = static_cast<uint32_t>(qs[4 * w]) | (static_cast<uint32_t>(qs[4 * w + 1]) << 8) |
+                        (static_cast<uint32_t>(qs[4 * w + 2]) << 16) | (static_cast<uint32_t>(qs[4 * w + 3]) << 24);
+            __syncthreads();
+            const int qq = static_cast<int>(rq2);  // exact: integers below 2^24
+            const uint4 *qb4 = reinterpret_cast<const uint4 *>(qb);
+            for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * RPW; i0 < nc;
+                 i0 += stride * RU) {
+                int64_t id[RU];
+                int acc[RU];
+#pragma unroll
+                for (int u = 0; u < RU; u++) {
+                    const int64_t i = i0 + u * stride + sub;
+                    id[u] = i < nc ? static_cast<int64_t>(cq[i]) : -1;
+                    acc[u] = 0;
+                }
+                for (int f = li; f < d / 16; f += LPR) {
+                    const uint4 qv = qb4[f];
+                    uint4 v[RU];
+#pragma unroll
+                    for (int u = 0; u < RU; u++)
+                        v[u] = id[u] >= 0 ? reinterpret_cast<const uint4 *>(base8 + id[u] * d)[f]
+                                          : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+                    for (int u = 0; u < RU; u++) {
+                        // |x|^2 - 2 q.x over these 16 bytes
+                        uint32_t xx = __builtin_amdgcn_udot4(v[u].x, v[u].x, 0u, false);
+                        xx = __builtin_amdgcn_udot4(v[u].y, v[u].y, xx, false);
+                        xx = __builtin_amdgcn_udot4(v[u].z, v[u].z, xx, false);
+                        xx = __builtin_amdgcn_udot4(v[u].w, v[u].w, xx, false);
+                        uint32_t qx = __builtin_amdgcn_udot4(v[u].x, qv.x, 0u, false);
+                        qx = __builtin_amdgcn_udot4(v[u].y, qv.y, qx, false);
+                        qx = __builtin_amdgcn_udot4(v[u].z, qv.z, qx, false);
+                        qx = __builtin_amdgcn_udot4(v[u].w, qv.w, qx, false);
+                        acc[u] += static_cast<int>(xx) - 2 * static_cast<int>(qx);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < RU; u++) {
+                    int a = acc[u];
+#pragma unroll
+                    for (int m = LPR / 2; m > 0; m >>= 1) a += __shfl_xor(a, m, WAVE);
+                    const int64_t i = i0 + u * stride + sub;
+                    if (li == 0 && i < nc) {
+                        const float D = static_cast<float>(qq + a);
+                        ub_out[static_cast<int64_t>(q) * cap + i] = D;
+                        lb_out[static_cast<int64_t>(q) * cap + i] = D;
+                    }
+                }
+            }
+            return;
+        }
+    }
     const float g = 2.0f * (d + 2) * 0x1p-24f + 0x1p-18f;
     for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * RPW; i0 < nc;
          i0 += stride * RU) {
@@ -1962,10 +2321,19 @@ size_t count_lds_bytes(int W, int bits) { return count_lds_size(W, bits) + 18 * 
 
 // Instances: nibble counts up to 8 levels (Ns <= 8), nibbles with up to
 // 15, bytes (Ns = 16).
-static const void *count_kernel(int bits, int Ns) {
-    if (bits == 8) return reinterpret_cast<const void *>(k_count<8, true>);
-    return Ns > 8 ? reinterpret_cast<const void *>(k_count<4, true>)
-                  : reinterpret_cast<const void *>(k_count<4, false>);
+template <int MODE, bool TR>
+static const void *count_kernel_form(int bits, int Ns) {
+    if (bits == 8) return reinterpret_cast<const void *>(k_count<8, true, MODE, TR>);
+    return Ns > 8 ? reinterpret_cast<const void *>(k_count<4, true, MODE, TR>)
+                  : reinterpret_cast<const void *>(k_count<4, false, MODE, TR>);
+}
+
+// form 3: the list form with the level transitions
+static const void *count_kernel(int bits, int Ns, int form) {
+    if (form == CT_LIST) return count_kernel_form<CT_LIST, false>(bits, Ns);
+    if (form == 3) return count_kernel_form<CT_LIST, true>(bits, Ns);
+    if (form == CT_REDO) return count_kernel_form<CT_REDO, true>(bits, Ns);
+    return count_kernel_form<CT_STORE, true>(bits, Ns);
 }
 
 static const void *count_select_kernel(int bits, int Ns) {
@@ -1976,33 +2344,87 @@ static const void *count_select_kernel(int bits, int Ns) {
 
 hipError_t prepare_count_kernels(int W, int bits, int Ns) {
     const int bytes = static_cast<int>(count_lds_size(W, bits));
-    return hipFuncSetAttribute(count_kernel(bits, Ns), hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    for (int form : {0, 1, 2, 3}) {
+        hipError_t e = hipFuncSetAttribute(count_kernel(bits, Ns, form),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, hipStream_t st) {
+int list_shift(int Ns) {
+    int b = 0;
+    while ((1 << b) <= Ns) b++;
+    return 31 - b;
+}
+
+static ListArgs list_args(const CountLaunch &c, const ListLaunch *l) {
+    ListArgs la{};
+    la.nq = c.nq;
+    if (l)
+        la = ListArgs{l->fixed, l->level, list_shift(c.Ns), c.nq, l->cap, l->list, l->cand, l->count, l->tcount,
+                      c.T, c.W, l->redo, l->R, l->rule, l->trans ? 0 : 1, l->dump_last, l->dump_hist};
+    return la;
+}
+
+hipError_t launch_list_select(const CountLaunch &c, const ListLaunch &l, uint32_t *hist, hipStream_t st) {
+    k_list_select<<<c.nq, LS_BLOCK, 0, st>>>(list_args(c, &l), hist, c.Ns, c.n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, int form, const ListLaunch *l,
+                        hipStream_t st) {
+    if (form != CT_STORE && !l) return hipErrorInvalidValue;
     CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
-    dim3 grid(c.T, c.nq);
+    const ListArgs la = list_args(c, l);
+    dim3 grid(c.T, form == CT_REDO ? l->redo_groups : c.nq);
     uint4 *s4 = reinterpret_cast<uint4 *>(sc);
     const size_t lds = count_lds_size(c.W, c.bits);
-    if (c.bits == 8)
-        k_count<8, true><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4);
-    else if (c.Ns > 8)
-        k_count<4, true><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4);
+#define TACO_COUNT(MODE, TR)                                                        \
+    do {                                                                            \
+        if (c.bits == 8)                                                            \
+            k_count<8, true, MODE, TR><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la);  \
+        else if (c.Ns > 8)                                                          \
+            k_count<4, true, MODE, TR><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la);  \
+        else                                                                        \
+            k_count<4, false, MODE, TR><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la); \
+    } while (0)
+    if (form == CT_LIST && l->trans)
+        TACO_COUNT(CT_LIST, true);
+    else if (form == CT_LIST)
+        TACO_COUNT(CT_LIST, false);
+    else if (form == CT_REDO)
+        TACO_COUNT(CT_REDO, true);
     else
-        k_count<4, false><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4);
+        TACO_COUNT(CT_STORE, true);
+#undef TACO_COUNT
+    return hipGetLastError();
+}
+
+
+hipError_t launch_unpack_counts(const uint32_t *sc, int nq, int T, int W, int bits, int64_t n, uint8_t *out,
+                                hipStream_t st) {
+    const int64_t words_q = static_cast<int64_t>(T) * W * bits / 32;
+    int64_t blocks = (words_q + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    dim3 grid(static_cast<unsigned>(blocks), nq);
+    if (bits == 4)
+        k_unpack_counts<4><<<grid, 256, 0, st>>>(sc, words_q, n, out);
+    else
+        k_unpack_counts<8><<<grid, 256, 0, st>>>(sc, words_q, n, out);
     return hipGetLastError();
 }
 
 hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
                          hipStream_t st) {
     SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
-                  s.dump_hist};
+                  s.dump_hist, s.redo};
     const int64_t words4 = static_cast<int64_t>(c.T) * c.W * c.bits / 128;
     // about 16 sixteen-byte words per thread
     int64_t blocks = (words4 + SEL_BLOCK * 16 - 1) / (SEL_BLOCK * 16);
     if (blocks > 64) blocks = 64;
     if (blocks < 1) blocks = 1;
-    dim3 grid(static_cast<unsigned>(blocks), c.nq);
+    dim3 grid(static_cast<unsigned>(blocks), s.redo ? s.redo_groups : c.nq);
     const uint4 *s4 = reinterpret_cast<const uint4 *>(sc);
     if (c.bits == 4)
         k_select<4><<<grid, SEL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words4, s4);
@@ -2027,7 +2449,7 @@ hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int 
                                uint32_t *err, uint32_t spin_limit, hipStream_t st) {
     CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
     SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
-                  s.dump_hist};
+                  s.dump_hist, nullptr};
     FuseArgs f{c.nq, NG, const_cast<uint32_t *>(s.hist), arrive, err, spin_limit};
     void *args[] = {&a, &sa, &f};
     const void *k = count_select_kernel(c.bits, c.Ns);

@@ -83,7 +83,7 @@ struct GraphKey {
     int64_t nq;
     int k, k_max;
     uint64_t alpha_bits, beta_bits;
-    int precision, count_mode, W, qpw, rule, rr_blocks, cdist;
+    int precision, count_mode, W, qpw, rule, rr_blocks, cdist, list_level;
     int64_t Qb;
     bool operator==(const GraphKey &o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
@@ -105,6 +105,8 @@ struct tc_index {
     bool coop = false;      // cooperative launches supported
     int fused_groups = 0;   // co-resident groups of T workgroups (0: fused path unavailable)
     int count_mode = TC_COUNT_AUTO;
+    int list_level = 0;          // TC_COUNT_LIST level (0: adaptive, in *lvl)
+    uint32_t *lvl = nullptr;     // adaptive list level, on the device
     uint32_t *err = nullptr;     // device error word of the fused kernel
     uint32_t *arrive = nullptr;  // [Qb] tile arrivals per query
     int64_t *Aq = nullptr;       // [Qb] per-query collision budgets (batched calls)
@@ -132,6 +134,7 @@ struct tc_index {
     int32_t *cand = nullptr;
     float *cand_dist = nullptr;
     uint32_t *sc = nullptr;  // packed collision counts, [Qb][T*W bytes]
+    uint32_t *tcount = nullptr;  // [Qb][T] entries listed per tile (TC_COUNT_LIST)
     // BF16 re-rank form (built when first selected)
     int precision = TC_FP32;
     float *mu = nullptr;         // [d] mean rounded to BF16
@@ -195,6 +198,10 @@ void free_scratch(tc_index *x) {
     (void)hipFree(x->qn);
     (void)hipFree(x->qsc);
     (void)hipFree(x->cd);
+    (void)hipFree(x->lvl);
+    x->lvl = nullptr;
+    (void)hipFree(x->tcount);
+    x->tcount = nullptr;
     x->qn = x->qsc = x->cd = nullptr;
     x->sc = nullptr;
     x->lb = nullptr;
@@ -244,7 +251,15 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->ncells, size_t(qb) * x->Ns, "probe lengths"))) return rc;
     if ((rc = dmalloc(&x->retrieved, size_t(qb) * x->Ns, "retrieved counts"))) return rc;
     if ((rc = dmalloc(&x->hist, size_t(qb) * (x->Ns + 1), "level histograms"))) return rc;
-    if ((rc = dmalloc(&x->cand_count, size_t(qb), "candidate counts"))) return rc;
+    // candidate counts [qb], then for the list selection the queue's header
+    // (queued, above the level) and the queue [qb]
+    if ((rc = dmalloc(&x->cand_count, size_t(2 * qb + 2), "candidate counts"))) return rc;
+    if ((rc = dmalloc(&x->lvl, 1, "list level"))) return rc;
+    if ((rc = dmalloc(&x->tcount, size_t(qb) * x->T, "per-tile list lengths"))) return rc;
+    {
+        const uint32_t l0 = static_cast<uint32_t>(std::min(2, x->Ns));
+        TC_HIP(hipMemcpy(x->lvl, &l0, sizeof(l0), hipMemcpyHostToDevice), "list level");
+    }
     if ((rc = dmalloc(&x->arrive, size_t(qb), "tile arrivals"))) return rc;
     if ((rc = dmalloc(&x->Aq, size_t(qb), "per-query budgets"))) return rc;
     if ((rc = dmalloc(&x->kq, size_t(qb), "per-query k"))) return rc;
@@ -592,6 +607,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
     // workgroups of the split form overlap better than the fused groups'
     // lock-step rounds (10.2 vs 17.3 ms per 10k-query step at n = 1M)
     const bool fused = x->count_mode == TC_COUNT_FUSED;
+    const bool list = x->count_mode == TC_COUNT_LIST;
     for (int64_t b0 = 0; b0 < c.nq; b0 += x->Qb) {
         const int nb = static_cast<int>(std::min<int64_t>(x->Qb, c.nq - b0));
         const float *Qb = c.Q + b0 * x->d;
@@ -607,7 +623,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             kq = x->kq;
         }
         TC_HIP(taco::launch_fill_u32(x->hist, int64_t(nb) * (x->Ns + 1), 0u, st), "clearing histograms");
-        TC_HIP(taco::launch_fill_u32(x->cand_count, nb, 0u, st), "clearing candidate counts");
+        TC_HIP(taco::launch_fill_u32(x->cand_count, x->Qb + 2, 0u, st), "clearing candidate counts");
 
         record(x, K_TRANSFORM, st, true);
         TC_HIP(taco::launch_transform(Qb, nb, x->d, x->mean, x->B, x->M, x->qt, st), "transform kernel");
@@ -645,9 +661,34 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                                              1u << 24, st),
                    "fused count/select kernel");
             record(x, K_FUSED, st, false);
+        } else if (list) {
+            uint32_t *redo = x->cand_count + x->Qb;
+            const bool dsc = dump && dump->sc;
+            const bool dh = dump && (dump->hist || dump->last);
+            // the lists sit in the distance slots, free until the re-rank
+            const taco::ListLaunch ll{x->list_level, x->lvl, cap, reinterpret_cast<uint32_t *>(x->cand_dist),
+                                      x->cand, x->cand_count, x->tcount, redo, 64, R, x->rule, dh,
+                                      sl.dump_last, sl.dump_hist};
+            record(x, K_COUNT, st, true);
+            TC_HIP(taco::launch_count(cl, x->hist, dsc ? x->sc : nullptr, 1, &ll, st), "count kernel (list)");
+            record(x, K_COUNT, st, false);
+            record(x, K_SELECT, st, true);
+            TC_HIP(taco::launch_list_select(cl, ll, x->hist, st), "list select kernel");
+            TC_HIP(taco::launch_count(cl, x->hist, x->sc, 2, &ll, st), "recount kernel");
+            taco::SelectLaunch sr = sl;
+            sr.dump_sc = nullptr;
+            sr.dump_last = nullptr;
+            sr.dump_hist = nullptr;
+            sr.redo = redo;
+            sr.redo_groups = 16;
+            TC_HIP(taco::launch_select(cl, sr, x->sc, st), "select kernel (queued)");
+            record(x, K_SELECT, st, false);
+            if (dsc)
+                TC_HIP(taco::launch_unpack_counts(x->sc, nb, x->T, x->W, x->bits, x->n, dump->sc + b0 * x->n, st),
+                       "dump sc");
         } else {
             record(x, K_COUNT, st, true);
-            TC_HIP(taco::launch_count(cl, x->hist, x->sc, st), "count kernel");
+            TC_HIP(taco::launch_count(cl, x->hist, x->sc, 0, nullptr, st), "count kernel");
             record(x, K_COUNT, st, false);
             record(x, K_SELECT, st, true);
             TC_HIP(taco::launch_select(cl, sl, x->sc, st), "select kernel");
@@ -746,6 +787,7 @@ int run(tc_index *x, const Call &c, void *stream) {
     key.rule = x->rule;
     key.rr_blocks = x->rr_blocks;
     key.cdist = x->cdist;
+    key.list_level = x->list_level;
     key.Qb = x->Qb;
     if (!x->graph_exec || !(key == x->graph_key)) {
         drop_graph(x);
@@ -894,11 +936,18 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
         x->cdist = static_cast<int>(value);
         return TC_OK;
     case TC_OPT_COUNT_MODE:
-        if (value != TC_COUNT_AUTO && value != TC_COUNT_SPLIT && value != TC_COUNT_FUSED)
+        if (value != TC_COUNT_AUTO && value != TC_COUNT_SPLIT && value != TC_COUNT_FUSED &&
+            value != TC_COUNT_LIST)
             return fail(TC_EINVAL, "unknown count mode");
         if (value == TC_COUNT_FUSED && x->fused_groups <= 0)
             return fail(TC_EINVAL, "the fused count/select kernel is unavailable for this index");
+        if (value == TC_COUNT_LIST && x->n > (int64_t(1) << taco::list_shift(x->Ns)))
+            return fail(TC_EINVAL, "ids and counts do not fit one list word for this index");
         x->count_mode = static_cast<int>(value);
+        return TC_OK;
+    case TC_OPT_LIST_LEVEL:
+        if (value < 0 || value > x->Ns) return fail(TC_EINVAL, "list level must be in [0, Ns]");
+        x->list_level = static_cast<int>(value);
         return TC_OK;
     case TC_OPT_GRAPH:
         if (value != 0 && value != 1) return fail(TC_EINVAL, "graph must be 0 or 1");
@@ -1090,7 +1139,7 @@ int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double
                                        : std::vector<int>{32768, 65536, 131072};
     for (int W : Ws) {
         if (taco::count_lds_bytes(W, x->bits) > size_t(x->max_lds)) continue;
-        for (int mode : {TC_COUNT_SPLIT, TC_COUNT_FUSED}) {
+        for (int mode : {TC_COUNT_SPLIT, TC_COUNT_FUSED, TC_COUNT_LIST}) {
             TuneConfig c = best;
             c.W = W;
             c.mode = mode;
@@ -1111,7 +1160,7 @@ int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double
         if ((rc = measure(c, &ms))) goto done;
         if (ms < best_ms) best_ms = ms, best = c;
     }
-    for (int rr : {16, 32, 64}) {
+    for (int rr : {8, 16, 32, 64}) {
         TuneConfig c = best;
         c.rr = rr;
         double ms;

@@ -198,18 +198,128 @@ def test_bounded_rerank_equals_fp32(taco_mod, w, prec):
         print(f"[{w.name}] k={k}: re-checked {nr.mean():.1f} of {nc.mean():.0f} candidates", flush=True)
 
 
-@pytest.mark.parametrize("mode", ["split", "fused"])
-def test_count_modes_all_stages(taco_mod, tiny, mode):
-    """The split (count, then select) and fused (one cooperative launch)
-    counting paths both match the oracle stage by stage, also with several
-    tiles per query and several batches."""
+def test_u8_integer_queries_and_others_equal_fp32(taco_mod):
+    """On integer rows in [0, 255] the 8-bit re-rank takes exact byte dot
+    products for queries of integers in [0, 255] and the bounded form for the
+    rest; a batch mixing both (queries shifted by fractions, negative or
+    above 255 in one coordinate) matches the FP32 path bit for bit, and the
+    exact form re-checks only the k best rows and their ties."""
     t = taco_mod
-    m = t.TC_COUNT_SPLIT if mode == "split" else t.TC_COUNT_FUSED
+    w = synthdata.WORKLOADS["gmm-int-1m-d128"].scaled("gmm-int-40k-d128-q48", n=40_000, nq=48)
+    X, Q = synthdata.base_and_queries(w)
+    assert np.all(X == np.round(X)) and X.min() >= 0 and X.max() <= 255
+    path = workload_index(w, X)
+    Q = Q.copy()
+    n_int = Q.shape[0] // 2
+    Q[n_int::3] += 0.25
+    Q[n_int + 1::3, 5] = -1.0
+    Q[n_int + 2::3, 7] = 256.0
+    for k, alpha, beta in ((10, 0.05, 0.005), (100, 0.01, 0.02)):
+        idx = t.Index(path, 0)
+        g32 = gpu_search(idx, Q, k, alpha, beta, ("ncand", "cand_dist"))
+        idx.set_option(t.TC_OPT_PRECISION, t.TC_U8)
+        g8 = gpu_search(idx, Q, k, alpha, beta, ("ncand", "nrecheck"))
+        idx.close()
+        assert np.array_equal(g8["ids"], g32["ids"]), k
+        assert np.array_equal(g8["dists"].view(np.uint32), g32["dists"].view(np.uint32)), k
+        nr = g8["nrecheck"]
+        for qi in range(n_int):
+            # both bounds are the distance: exactly the rows at or below the
+            # k-th smallest are re-checked (all of them when |C| <= k)
+            nc = int(g32["ncand"][qi])
+            cd = g32["cand_dist"][qi, :nc]
+            expect = nc if nc <= k else int((cd <= np.sort(cd)[k - 1]).sum())
+            assert nr[qi] == expect, (k, qi, int(nr[qi]), expect)
+        print(f"[{w.name}] u8 integer queries k={k}: re-checked {nr[:n_int].mean():.1f}; "
+              f"others {nr[n_int:].mean():.1f} of {g8['ncand'][n_int:].mean():.0f}", flush=True)
+
+
+@pytest.mark.parametrize("mode", ["split", "fused", "list"])
+def test_count_modes_all_stages(taco_mod, tiny, mode):
+    """The split (count, then select), fused (one cooperative launch) and
+    list (ids at or above the list level listed while counting) paths all
+    match the oracle stage by stage, also with several tiles per query and
+    several batches."""
+    t = taco_mod
+    m = {"split": t.TC_COUNT_SPLIT, "fused": t.TC_COUNT_FUSED, "list": t.TC_COUNT_LIST}[mode]
     print(f"[tiny] count mode {mode}", flush=True)
     for opts in (((t.TC_OPT_COUNT_MODE, m),),
                  ((t.TC_OPT_TILE_IDS, 4096), (t.TC_OPT_COUNT_MODE, m), (t.TC_OPT_MAX_BATCH, 13))):
         _run_all(t, tiny["path"], tiny["oidx"], tiny["Q"], 10, 0.05, 0.005, 0, f"tiny {mode}",
                  options=opts)
+
+
+@pytest.mark.parametrize("level", [1, 2, 3, 4, 8])
+def test_list_levels_all_stages(taco_mod, tiny, level):
+    """Every fixed list level matches the oracle stage by stage: queries whose
+    threshold is below the level (recounted and selected from their packed
+    counts), at it (the list is the candidate set) and above it (the list is
+    filtered)."""
+    t = taco_mod
+    print(f"[tiny] list level {level}", flush=True)
+    seen = np.zeros(3, np.int64)
+    for alpha, beta in ((0.05, 0.005), (0.01, 0.02), (0.2, 0.001)):
+        for opts in (((t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST), (t.TC_OPT_LIST_LEVEL, level)),
+                     ((t.TC_OPT_TILE_IDS, 4096), (t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST),
+                      (t.TC_OPT_LIST_LEVEL, level), (t.TC_OPT_MAX_BATCH, 13))):
+            g = _run_all(t, tiny["path"], tiny["oidx"], tiny["Q"], 10, alpha, beta, 0,
+                         f"tiny list level {level} a={alpha}", options=opts)
+            last = g["last"].astype(np.int64)
+            seen += [(last < level).sum(), (last == level).sum(), (last > level).sum()]
+    print(f"[tiny] list level {level}: below/at/above {seen.tolist()}", flush=True)
+
+
+def _search_bits(t, path, Q, alpha, options, calls=1, graph=False):
+    """Results of `calls` searches (no dumps) with the given options; all
+    calls must agree bit for bit."""
+    import torch
+    idx = t.Index(path, 0)
+    try:
+        for opt, val in options:
+            idx.set_option(opt, val)
+        if graph:
+            idx.set_option(t.TC_OPT_GRAPH, 1)
+        q = torch.from_numpy(Q).cuda()
+        out = None
+        for c in range(calls):
+            ids, d = idx.search(q, 10, alpha, 0.005)
+            torch.cuda.synchronize()
+            r = (ids.cpu().numpy(), d.cpu().numpy().view(np.uint32))
+            if out is None:
+                out = r
+            else:
+                assert np.array_equal(out[0], r[0]) and np.array_equal(out[1], r[1]), c
+            _ = (q * 2.0).sum().item()  # eager work between calls
+        assert idx.device_errors() == 0
+    finally:
+        idx.close()
+    return out
+
+
+@pytest.mark.parametrize("w", [synthdata.WORKLOADS["tiny-gmm-20k-d128"]] + scaled_workloads(),
+                         ids=lambda w: w.name)
+def test_list_mode_equals_split_without_dumps(taco_mod, w):
+    """Without stage dumps (the product path: no packed counts stored unless
+    queued), the list path gives the split path's results bit for bit, at the
+    adaptive level across repeated calls and batches (the level moves on the
+    device between them), at fixed levels, and replayed from a graph."""
+    t = taco_mod
+    X, Q = synthdata.base_and_queries(w)
+    path = workload_index(w, X)
+    Ns = w.Ns
+    print(f"[{w.name}] list vs split, no dumps", flush=True)
+    for alpha in (0.01, 0.05, 0.2):
+        ref = _search_bits(t, path, Q, alpha, ((t.TC_OPT_COUNT_MODE, t.TC_COUNT_SPLIT),))
+        for level in sorted({0, 1, 3, Ns}):
+            for mb in (0, 7):
+                opts = [(t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST), (t.TC_OPT_LIST_LEVEL, level)]
+                if mb:
+                    opts.append((t.TC_OPT_MAX_BATCH, mb))
+                got = _search_bits(t, path, Q, alpha, opts, calls=3)
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (alpha, level, mb)
+        got = _search_bits(t, path, Q, alpha, ((t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST),
+                                               (t.TC_OPT_MAX_BATCH, 5)), calls=4, graph=True)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (alpha, "graph")
 
 
 @pytest.mark.parametrize("w", scaled_workloads(), ids=lambda w: w.name)
