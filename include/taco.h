@@ -240,7 +240,8 @@ typedef struct tc_stage_dump {
     int32_t *cand;      /* [nq][n]          candidate ids (first ncand, any order)   */
     float *cand_dist;   /* [nq][n]          their distances, aligned with cand
                                             (TC_FP32 re-rank only)                  */
-    int64_t *nrecheck;  /* [nq]             rows re-checked in FP32 (TC_BF16, TC_U8)  */
+    int64_t *nrecheck;  /* [nq] rows re-checked in FP32 (TC_BF16, TC_U8; 0 when the
+                           8-bit bounds are the distances themselves)           */
 } tc_stage_dump;
 
 /* tc_search that also writes the stages requested in `dump` (host pointer to

@@ -98,17 +98,20 @@ hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const
                            const float *rowerr, const int32_t *cand, const uint32_t *cand_count,
                            int64_t cap, float *ub, float *lb, int blocks_per_q, hipStream_t st);
 // 8-bit rows with a 16-byte (offset, step, error) record per row (exact for
-// integer rows within 255); plain: every record is (0, 1, 0) and none is read
+// integer rows within 255); plain: every record is (0, 1, 0) and none is read.
+// exact[q] (optional) is set when both bounds are the FP32 distance.
 hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, const float4 *meta, bool plain,
                           const int32_t *cand, const uint32_t *cand_count, int64_t cap, float *ub, float *lb,
-                          int blocks_per_q, hipStream_t st);
+                          uint32_t *exact, int blocks_per_q, hipStream_t st);
 hipError_t launch_prep_u8(const float *base, int64_t n, int d, uint8_t *base8, float4 *meta, uint32_t *plain,
                           hipStream_t st);
-// FP32 re-check of the rows with lb <= tau, then the top-k of those rows
+// FP32 re-check of the rows with lb <= tau, then the top-k of those rows;
+// queries with exact[q] set (exact may be null) copy the bound top-k rows
 hipError_t launch_recheck_topk(const float *Q, int nq, int d, const float *base, const int32_t *cand,
                                const uint32_t *cand_count, const float *lb, int64_t cap, const float *tau_d,
                                int k, const int32_t *kq, int k_max, int32_t *rk_ids, float *rk_dist,
-                               uint32_t *rk_count, int64_t *ids_out, float *d_out, hipStream_t st);
+                               uint32_t *rk_count, int64_t *ids_out, float *d_out, const uint32_t *exact,
+                               const int64_t *tau_ids, hipStream_t st);
 hipError_t launch_prep_bf16(const float *base, int64_t n, int d, const float *mu, uint16_t *base16,
                             float *rowerr, hipStream_t st);
 hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32_t *cand_count,

@@ -1722,7 +1722,9 @@ __global__ __launch_bounds__(256) void k_rerank16(const float *__restrict__ Q, i
 // (q_t - x_t)^2 <= 255^2 and every partial sum <= d * 255^2 < 2^24 are
 // integers that FP32 holds exactly, so the FP32 path's distance is the
 // exact integer |q|^2 + |x|^2 - 2 q.x whatever its summation order; that is
-// computed with byte dot products and written as both bounds.
+// computed with byte dot products and written as both bounds, and
+// exact[q] (when given) says so: the top k of the upper bounds is then the
+// result itself.
 // grid (G, nq), block 256, dynamic LDS d floats.
 template <int LPR, bool VEC16, bool PLAIN>
 __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, int d,
@@ -1731,7 +1733,7 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
                                                  const int32_t *__restrict__ cand,
                                                  const uint32_t *__restrict__ cand_count,
                                                  int64_t cap, float *__restrict__ ub_out,
-                                                 float *__restrict__ lb_out) {
+                                                 float *__restrict__ lb_out, uint32_t *__restrict__ exact) {
     extern __shared__ float qs[];
     __shared__ float rq_part[WAVES];
     const int q = blockIdx.y;
@@ -1754,14 +1756,19 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
     const int sub = lane / LPR, li = lane % LPR;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVES * RPW;
     const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
+    bool integral = false;
     if (PLAIN && VEC16 && d <= 256) {
-        __shared__ uint32_t qb[64];  // the query's bytes, four per word
         bool ok = true;
         for (int t = threadIdx.x; t < d; t += BLOCK) {
             const float v = qs[t];
             ok = ok && v >= 0.0f && v <= 255.0f && v == rintf(v);
         }
-        if (__syncthreads_and(ok)) {
+        integral = __syncthreads_and(ok) != 0;
+    }
+    if (exact && blockIdx.x == 0 && threadIdx.x == 0) exact[q] = integral ? 1u : 0u;
+    if (PLAIN && VEC16 && d <= 256) {
+        __shared__ uint32_t qb[64];  // the query's bytes, four per word
+        if (integral) {
             for (int w = threadIdx.x; w < d / 4; w += BLOCK)
                 qb[w] = static_cast<uint32_t>(qs[4 * w]) | (static_cast<uint32_t>(qs[4 * w + 1]) << 8) |
                         (static_cast<uint32_t>(qs[4 * w + 2]) << 16) | (static_cast<uint32_t>(qs[4 * w + 3]) << 24);
@@ -2025,6 +2032,26 @@ __device__ __forceinline__ void for_keys(bool reg, const uint64_t (&kr)[TK_KPT],
     }
 }
 
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint32_t>(v)), m, WAVE));
+    const uint32_t hi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint32_t>(v >> 32)), m, WAVE));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Ascending bitonic sort of one value per lane across the wavefront.
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v, int lane) {
+#pragma unroll
+    for (int size = 2; size <= WAVE; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint64_t o = shfl_xor_u64(v, stride);
+            const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
+            v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+        }
+    }
+    return v;
+}
+
 // The k smallest of the nc keys (dq[i] bits << 32 | cq[i]) of query q, by
 // the whole workgroup (256 threads, all must call); results go to row q of
 // (ids_out, d_out), k_max entries, padded with (-1, +inf) past k or past nc.
@@ -2048,9 +2075,35 @@ __device__ __forceinline__ void topk_select(int q, const int32_t *__restrict__ c
         }
     }
     if (threadIdx.x == 0) nsel = 0u;
+    bool gathered = false;
+    if (nc > k && k <= WAVE) {
+        // Each wavefront's k-th smallest lane minimum is >= the k-th
+        // smallest key (those k minima are k distinct keys); the smallest
+        // such bound over the wavefronts usually leaves a few dozen keys.
+        // Two passes over the keys, also when they are streamed.
+        uint64_t tmin = ~0ull;
+        for_keys(reg, kr, nc, cq, dq, [&](uint64_t kk) { tmin = kk < tmin ? kk : tmin; });
+        const uint64_t srt = wave_sort_u64(tmin, lane);
+        const uint32_t tlo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(srt)), k - 1));
+        const uint32_t thi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(srt >> 32)), k - 1));
+        if (lane == 0) wred[wave] = (static_cast<uint64_t>(thi) << 32) | tlo;
+        __syncthreads();
+        uint64_t bound = wred[0];
+        for (int w = 1; w < WAVES; w++) bound = wred[w] < bound ? wred[w] : bound;
+        for_keys(reg, kr, nc, cq, dq, [&](uint64_t kk) {
+            if (kk <= bound) {
+                const uint32_t p = atomicAdd(&nsel, 1u);
+                if (p < TOPK_MAX) sel[p] = kk;
+            }
+        });
+        __syncthreads();
+        gathered = nsel <= static_cast<uint32_t>(TOPK_MAX);
+        __syncthreads();
+        if (!gathered && threadIdx.x == 0) nsel = 0u;
+    }
     int shift = 64;
     uint64_t prefix = 0;
-    if (nc > k) {
+    if (!gathered && nc > k) {
         // bits above `shift` are common to all keys: prefix holds them
         uint64_t mn = ~0ull, mx = 0ull;
         for_keys(reg, kr, nc, cq, dq, [&](uint64_t kk) {
@@ -2107,17 +2160,22 @@ __device__ __forceinline__ void topk_select(int q, const int32_t *__restrict__ c
     }
     __syncthreads();
     // gather: every key (|C| <= k) or the keys whose top (64-shift) bits <= prefix
-    for_keys(reg, kr, nc, cq, dq, [&](uint64_t kk) {
-        if (nc <= k || (kk >> shift) <= prefix) {
-            const uint32_t p = atomicAdd(&nsel, 1u);
-            if (p < TOPK_MAX) sel[p] = kk;
-        }
-    });
-    __syncthreads();
-    const int m = static_cast<int>(min<uint32_t>(nsel, static_cast<uint32_t>(k)));
+    if (!gathered) {
+        for_keys(reg, kr, nc, cq, dq, [&](uint64_t kk) {
+            if (nc <= k || (kk >> shift) <= prefix) {
+                const uint32_t p = atomicAdd(&nsel, 1u);
+                if (p < TOPK_MAX) sel[p] = kk;
+            }
+        });
+        __syncthreads();
+    }
+    // sort the gathered keys (exactly min(|C|, k) of them after the radix
+    // select; at least k after the bound) and keep the first k
+    const int ns = static_cast<int>(min<uint32_t>(nsel, static_cast<uint32_t>(TOPK_MAX)));
+    const int m = min(ns, k);
     int P = 1;
-    while (P < m) P <<= 1;
-    for (int i = m + threadIdx.x; i < P; i += BLOCK) sel[i] = ~0ull;
+    while (P < ns) P <<= 1;
+    for (int i = ns + threadIdx.x; i < P; i += BLOCK) sel[i] = ~0ull;
     __syncthreads();
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -2165,7 +2223,9 @@ __global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
 // flight), the kept ones compacted into LDS and re-ranked by row groups with
 // the FP32 path's own arithmetic (row_partial32 and group_sum with the same
 // lanes per row); the kept (id, distance) pairs go to (rk_ids, rk_dist), and
-// their top k to the output rows.  grid nq, block 256, dynamic LDS d floats.
+// their top k to the output rows.  A query with exact[q] set (its bounds are
+// the FP32 distances) takes the top k of the bounds as they are.  grid nq,
+// block 256, dynamic LDS d floats.
 template <int LPR, bool VEC4>
 __global__ __launch_bounds__(256) void k_recheck_topk(const float *__restrict__ Q, int d,
                                                       const float *__restrict__ base,
@@ -2176,11 +2236,22 @@ __global__ __launch_bounds__(256) void k_recheck_topk(const float *__restrict__ 
                                                       const int32_t *__restrict__ kq, int k_max,
                                                       int32_t *__restrict__ rk_ids, float *__restrict__ rk_dist,
                                                       uint32_t *__restrict__ rk_count,
-                                                      int64_t *__restrict__ ids_out, float *__restrict__ d_out) {
+                                                      int64_t *__restrict__ ids_out, float *__restrict__ d_out,
+                                                      const uint32_t *__restrict__ exact,
+                                                      const int64_t *__restrict__ tau_ids) {
     extern __shared__ float qs[];
     __shared__ int32_t kept[RC_CHUNK];
     __shared__ uint32_t nkept, nrk;
     const int q = blockIdx.x;
+    if (exact && exact[q]) {
+        for (int i = threadIdx.x; i < k_max; i += BLOCK) {
+            const int64_t o = static_cast<int64_t>(q) * k_max + i;
+            ids_out[o] = tau_ids[o];
+            d_out[o] = tau_d[o];
+        }
+        if (threadIdx.x == 0) rk_count[q] = 0u;
+        return;
+    }
     for (int t = threadIdx.x; t < d; t += BLOCK) qs[t] = Q[static_cast<int64_t>(q) * d + t];
     const int64_t nc = cand_count[q];
     const int k = kq ? kq[q] : k_all;
@@ -2509,15 +2580,17 @@ hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const
 
 hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, const float4 *meta, bool plain,
                           const int32_t *cand, const uint32_t *cand_count, int64_t cap, float *ub, float *lb,
-                          int blocks_per_q, hipStream_t st) {
+                          uint32_t *exact, int blocks_per_q, hipStream_t st) {
     dim3 grid(blocks_per_q, nq);
     size_t lds = sizeof(float) * static_cast<size_t>(d);
 #define TACO_RR8(L, V)                                                                                    \
     do {                                                                                                  \
         if (plain)                                                                                        \
-            k_rerank8<L, V, true><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb); \
+            k_rerank8<L, V, true><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb, \
+                                                            exact);                                           \
         else                                                                                              \
-            k_rerank8<L, V, false><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb); \
+            k_rerank8<L, V, false><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb, \
+                                                             exact);                                          \
     } while (0)
     if (d % 16 != 0) {
         TACO_RR8(64, false);
@@ -2547,11 +2620,12 @@ hipError_t launch_prep_u8(const float *base, int64_t n, int d, uint8_t *base8, f
 hipError_t launch_recheck_topk(const float *Q, int nq, int d, const float *base, const int32_t *cand,
                                const uint32_t *cand_count, const float *lb, int64_t cap, const float *tau_d,
                                int k, const int32_t *kq, int k_max, int32_t *rk_ids, float *rk_dist,
-                               uint32_t *rk_count, int64_t *ids_out, float *d_out, hipStream_t st) {
+                               uint32_t *rk_count, int64_t *ids_out, float *d_out, const uint32_t *exact,
+                               const int64_t *tau_ids, hipStream_t st) {
     size_t lds = sizeof(float) * static_cast<size_t>(d);
 #define TACO_RC(L, V)                                                                                 \
     k_recheck_topk<L, V><<<nq, BLOCK, lds, st>>>(Q, d, base, cand, cand_count, lb, cap, tau_d, k, kq, \
-                                                 k_max, rk_ids, rk_dist, rk_count, ids_out, d_out)
+                                                 k_max, rk_ids, rk_dist, rk_count, ids_out, d_out, exact, tau_ids)
     if (d % 4 != 0) {
         TACO_RC(64, false);
     } else {

@@ -146,6 +146,7 @@ struct tc_index {
     float *lb = nullptr;         // [Qb][n] lower bounds of the FP32 distances
     int32_t *rk_ids = nullptr;   // [Qb][n] re-checked candidates
     uint32_t *rk_count = nullptr;
+    uint32_t *exact = nullptr;   // [Qb] the 8-bit bounds are the FP32 distances
     int64_t *tau_ids = nullptr;  // [Qb][1024] top-k of the upper bounds
     float *tau_d = nullptr;
     std::vector<float> mean_host;
@@ -194,6 +195,8 @@ void free_scratch(tc_index *x) {
     (void)hipFree(x->rk_ids);
     (void)hipFree(x->rk_count);
     (void)hipFree(x->tau_ids);
+    (void)hipFree(x->exact);
+    x->exact = nullptr;
     (void)hipFree(x->tau_d);
     (void)hipFree(x->qn);
     (void)hipFree(x->qsc);
@@ -275,6 +278,7 @@ int alloc_scratch(tc_index *x) {
         if ((rc = dmalloc(&x->rk_ids, size_t(qb) * x->n, "re-checked candidates"))) return rc;
         if ((rc = dmalloc(&x->rk_count, size_t(qb), "re-check counts"))) return rc;
         if ((rc = dmalloc(&x->tau_ids, size_t(qb) * 1024, "bound top-k ids"))) return rc;
+        if ((rc = dmalloc(&x->exact, size_t(qb), "exact-bound flags"))) return rc;
         if ((rc = dmalloc(&x->tau_d, size_t(qb) * 1024, "bound top-k"))) return rc;
     }
     x->Qb = qb;
@@ -705,7 +709,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                        "BF16 rerank kernel");
             else
                 TC_HIP(taco::launch_rerank8(Qb, nb, x->d, x->base8, x->rmeta, x->u8_plain, x->cand,
-                                            x->cand_count, cap, x->cand_dist, x->lb, rr_blocks, st),
+                                            x->cand_count, cap, x->cand_dist, x->lb, x->exact, rr_blocks, st),
                        "8-bit rerank kernel");
             record(x, K_RERANK, st, false);
             record(x, K_TOPK, st, true);
@@ -716,7 +720,8 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             record(x, K_RECHECK, st, true);
             TC_HIP(taco::launch_recheck_topk(Qb, nb, x->d, x->base, x->cand, x->cand_count, x->lb, cap,
                                              x->tau_d, k, kq, k_max, x->rk_ids, x->cand_dist, x->rk_count,
-                                             ids, dists, st),
+                                             ids, dists, x->precision == TC_U8 ? x->exact : nullptr, x->tau_ids,
+                                             st),
                    "re-check and top-k kernel");
             record(x, K_RECHECK, st, false);
             if (dump && dump->nrecheck)
