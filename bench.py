@@ -277,7 +277,7 @@ def algorithmic_bytes(idx, q, w, alpha, nq, precision=0):
 # rocprofv3 summaries (run after a profiled bench; they read only its CSVs)
 # ---------------------------------------------------------------------------
 
-_SHORT = (("k_count_select", "count_select"), ("k_count", "count"), ("k_select", "select"),
+_SHORT = (("k_count_select", "count_select"), ("k_list_select", "list_select"), ("k_select", "select"),
           ("k_rerank16", "rerank"), ("k_rerank8", "rerank"), ("k_rerank", "rerank"),
           ("k_recheck_topk", "recheck"), ("k_topk", "topk"), ("k_probe", "probe"),
           ("k_transform", "transform"), ("k_cdist_mfma", "cdist"), ("k_qstats", "cdist"),
@@ -287,6 +287,12 @@ _SHORT = (("k_count_select", "count_select"), ("k_count", "count"), ("k_select",
 
 
 def short_kernel_name(full):
+    """Short name of a library kernel (None for others).  The count kernel's
+    third template argument is its form: 2 is the recount of the queries a
+    list selection queued, timed within the selection stage."""
+    if "taco::k_count<" in full:
+        args = full.split("taco::k_count<", 1)[1].split(">", 1)[0].split(",")
+        return "recount" if len(args) >= 3 and args[2].strip() == "2" else "count"
     for key, short in _SHORT:
         if "taco::" + key + "<" in full or "taco::" + key + "(" in full:
             return short
@@ -325,6 +331,10 @@ def summarize_stats(stats_csv, bench_json, out_md, command):
         out.append(f"| {short or r['Name'][:40]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{'' if b is None else f'{b * 1e3:.1f}'} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                    f"{float(r['Percentage']):.1f} |")
+    if any(short_kernel_name(r["Name"]) in ("list_select", "recount") for r in rows):
+        out += ["", "With the list selection, the bench's select time covers its three launches "
+                "(list_select, recount and the streaming select of the queued queries); the "
+                "recount is the count kernel's third form."]
     out += ["", f"Dominant kernel at the operating point: {op['kernel']}, "
             f"{op['alg_bytes_per_launch'] / 1e6:.1f} MB algorithmic per launch, "
             f"{op['achieved']:.1f} GB/s achieved = {op['frac']:.4f} of {op['peak']:.0f} GB/s.", ""]

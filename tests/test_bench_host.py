@@ -23,6 +23,9 @@ def test_short_kernel_names():
     f = bench.short_kernel_name
     assert f("void taco::k_count_select<4>(taco::FuseArgs)") == "count_select"
     assert f("void taco::k_count<8>(taco::CountArgs, unsigned int*)") == "count"
+    assert f("void taco::k_count<4, false, 1, false>(taco::CountArgs, unsigned int*)") == "count"
+    assert f("void taco::k_count<4, false, 2, true>(taco::CountArgs, unsigned int*)") == "recount"
+    assert f("taco::k_list_select(taco::ListArgs, unsigned int*, int, long)") == "list_select"
     assert f("taco::k_select(taco::SelectArgs, int)") == "select"
     assert f("void taco::k_rerank16<16, true>(float const*)") == "rerank"
     assert f("void taco::k_rerank<16, true>(float const*)") == "rerank"
