@@ -21,9 +21,11 @@ Legs:
     library's autotuner picks tile width, count mode, probe packing, re-rank
     spread and re-rank precision per alpha; results are identical to FP32)
     and "lowp" (tuned, plus FP8 centroid distances on the matrix cores,
-    which may change the probe near ties).  Tuned and lowp are also timed
-    replaying their captured HIP graphs.  The reported value is the tuned
-    path's; all paths are listed under "paths".
+    which may change the probe near ties).  Tuned and lowp run as captured
+    HIP graphs (TC_OPT_GRAPH): their QPS is the replay rate, with recall read
+    from the replays' results, and an eager run gives the per-kernel timing
+    (eager_qps beside it).  The reported value is the tuned path's; all paths
+    are listed under "paths".
   * precision report: relative error of the BF16 and FP8 centroid distances
     against FP64, recall@10 of each form per alpha and its loss against the
     FP32 form, and the fraction of candidates the BF16 re-rank re-checks.
@@ -510,14 +512,21 @@ def main():
             point = dict(alpha=a, qps=qps, recall=rec, ms_per_step=ms / args.steps, kernels=kern,
                          per_query=avg, batches_per_step=batches)
             if tuned is not None:
+                # the tuned paths run as the library's captured graph (TC_OPT_GRAPH): the value is
+                # the replay rate, with recall re-read from the replays' own results; the eager
+                # run above gives the per-kernel timing
                 point["config"] = tuned.strip().splitlines()[-1] + (" cdist=fp8" if pname == "lowp" else "")
                 idx.set_option(taco.TC_OPT_GRAPH, 1)
+                ids.fill_(-1)
                 gms, _ = timed_steps(idx, taco, qd, w, a, ids, dists, stream, args.steps, args.warmup,
                                      profile=False)
                 idx.set_option(taco.TC_OPT_GRAPH, 0)
-                point["graph_qps"] = w.nq * args.steps / (gms * 1e-3)
+                grec = recall_at_k(ids[:S].cpu().numpy(), kth, X, Q[:S], w.k)
+                point.update(eager_qps=qps, eager_ms_per_step=ms / args.steps,
+                             graph_qps=w.nq * args.steps / (gms * 1e-3))
+                point.update(qps=point["graph_qps"], ms_per_step=gms / args.steps, recall=min(rec, grec))
             sweep.append(point)
-            log(f"{pname} alpha={a}: {qps:,.0f} QPS, {ms / args.steps:.3f} ms/step, recall@10 {rec:.4f}; "
+            log(f"{pname} alpha={a}: eager {qps:,.0f} QPS, {ms / args.steps:.3f} ms/step, recall@10 {rec:.4f}; "
                 + ", ".join(f"{k} {v['ms_total'] / args.steps:.3f}" for k, v in kern.items()
                             if v["ms_total"] > 0)
                 + (f"; graph {point['graph_qps']:,.0f} QPS" if "graph_qps" in point else ""))
@@ -570,6 +579,7 @@ def main():
         paths={pn: dict(value=qps_at_recall(sw),
                         points=[dict(alpha=p["alpha"], qps=p["qps"], recall=p["recall"],
                                      ms_per_step=p["ms_per_step"], graph_qps=p.get("graph_qps"),
+                                     eager_qps=p.get("eager_qps"),
                                      config=p.get("config"), per_query=p["per_query"],
                                      kernels={k_: dict(ms_per_launch=v["ms_per_launch"],
                                                        launches=v["launches"], alg_GBps=v["alg_GBps"])

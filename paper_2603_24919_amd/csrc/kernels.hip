@@ -1722,9 +1722,10 @@ __global__ __launch_bounds__(256) void k_rerank16(const float *__restrict__ Q, i
 // (q_t - x_t)^2 <= 255^2 and every partial sum <= d * 255^2 < 2^24 are
 // integers that FP32 holds exactly, so the FP32 path's distance is the
 // exact integer |q|^2 + |x|^2 - 2 q.x whatever its summation order; that is
-// computed with byte dot products and written as both bounds, and
-// exact[q] (when given) says so: the top k of the upper bounds is then the
-// result itself.
+// computed with byte dot products and written as the upper bound, and
+// exact[q] says so: the top k of the upper bounds is then the result itself
+// and the lower bounds are not written (nor read).  Without exact the
+// bounded form runs for every query.
 // grid (G, nq), block 256, dynamic LDS d floats.
 template <int LPR, bool VEC16, bool PLAIN>
 __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, int d,
@@ -1736,7 +1737,7 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
                                                  float *__restrict__ lb_out, uint32_t *__restrict__ exact) {
     extern __shared__ float qs[];
     __shared__ float rq_part[WAVES];
-    const int q = blockIdx.y;
+    const int q = blockIdx.y, chunk = blockIdx.x;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     float sq = 0.0f;
     for (int t = threadIdx.x; t < d; t += BLOCK) {
@@ -1757,7 +1758,7 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVES * RPW;
     const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
     bool integral = false;
-    if (PLAIN && VEC16 && d <= 256) {
+    if (PLAIN && VEC16 && d <= 256 && exact) {
         bool ok = true;
         for (int t = threadIdx.x; t < d; t += BLOCK) {
             const float v = qs[t];
@@ -1765,8 +1766,8 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
         }
         integral = __syncthreads_and(ok) != 0;
     }
-    if (exact && blockIdx.x == 0 && threadIdx.x == 0) exact[q] = integral ? 1u : 0u;
-    if (PLAIN && VEC16 && d <= 256) {
+    if (exact && chunk == 0 && threadIdx.x == 0) exact[q] = integral ? 1u : 0u;
+    if (PLAIN && VEC16 && d <= 256 && exact) {
         __shared__ uint32_t qb[64];  // the query's bytes, four per word
         if (integral) {
             for (int w = threadIdx.x; w < d / 4; w += BLOCK)
@@ -1775,7 +1776,7 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
             __syncthreads();
             const int qq = static_cast<int>(rq2);  // exact: integers below 2^24
             const uint4 *qb4 = reinterpret_cast<const uint4 *>(qb);
-            for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * RPW; i0 < nc;
+            for (int64_t i0 = (static_cast<int64_t>(chunk) * WAVES + wave) * RPW; i0 < nc;
                  i0 += stride * RU) {
                 int64_t id[RU];
                 int acc[RU];
@@ -1812,18 +1813,16 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
 #pragma unroll
                     for (int m = LPR / 2; m > 0; m >>= 1) a += __shfl_xor(a, m, WAVE);
                     const int64_t i = i0 + u * stride + sub;
-                    if (li == 0 && i < nc) {
-                        const float D = static_cast<float>(qq + a);
-                        ub_out[static_cast<int64_t>(q) * cap + i] = D;
-                        lb_out[static_cast<int64_t>(q) * cap + i] = D;
-                    }
+                    // the lower bound is not needed: the re-check takes the bound
+                    // top k as it is for a flagged query
+                    if (li == 0 && i < nc) ub_out[static_cast<int64_t>(q) * cap + i] = static_cast<float>(qq + a);
                 }
             }
             return;
         }
     }
     const float g = 2.0f * (d + 2) * 0x1p-24f + 0x1p-18f;
-    for (int64_t i0 = (static_cast<int64_t>(blockIdx.x) * WAVES + wave) * RPW; i0 < nc;
+    for (int64_t i0 = (static_cast<int64_t>(chunk) * WAVES + wave) * RPW; i0 < nc;
          i0 += stride * RU) {
         int64_t id[RU];
         float acc[RU], lo[RU], sc[RU], er[RU];

@@ -1139,7 +1139,7 @@ int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double
                     x->rr_blocks, x->precision};
     double best_ms = 1e30;
     // coordinate descent: tile width x count mode, then probe queries per
-    // workgroup, then re-rank workgroups per query, then re-rank precision
+    // workgroup, re-rank precision, then re-rank workgroups per query
     std::vector<int> Ws = x->bits == 4 ? std::vector<int>{65536, 131072, 262144}
                                        : std::vector<int>{32768, 65536, 131072};
     for (int W : Ws) {
@@ -1165,16 +1165,16 @@ int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double
         if ((rc = measure(c, &ms))) goto done;
         if (ms < best_ms) best_ms = ms, best = c;
     }
-    for (int rr : {8, 16, 32, 64}) {
+    for (int p : {TC_FP32, TC_BF16, TC_U8}) {
         TuneConfig c = best;
-        c.rr = rr;
+        c.precision = p;
         double ms;
         if ((rc = measure(c, &ms))) goto done;
         if (ms < best_ms) best_ms = ms, best = c;
     }
-    for (int p : {TC_FP32, TC_BF16, TC_U8}) {
+    for (int rr : {8, 16, 32, 64}) {
         TuneConfig c = best;
-        c.precision = p;
+        c.rr = rr;
         double ms;
         if ((rc = measure(c, &ms))) goto done;
         if (ms < best_ms) best_ms = ms, best = c;

@@ -204,8 +204,8 @@ def test_u8_integer_queries_and_others_equal_fp32(taco_mod):
     """On integer rows in [0, 255] the 8-bit re-rank takes exact byte dot
     products for queries of integers in [0, 255] and the bounded form for the
     rest; a batch mixing both (queries shifted by fractions, negative or
-    above 255 in one coordinate) matches the FP32 path bit for bit, and the
-    exact form re-checks no row."""
+    above 255 in one coordinate) matches the FP32 path bit for bit, also in
+    ragged batches, and the exact form re-checks no row."""
     t = taco_mod
     w = synthdata.WORKLOADS["gmm-int-1m-d128"].scaled("gmm-int-40k-d128-q48", n=40_000, nq=48)
     X, Q = synthdata.base_and_queries(w)
@@ -216,10 +216,13 @@ def test_u8_integer_queries_and_others_equal_fp32(taco_mod):
     Q[n_int::3] += 0.25
     Q[n_int + 1::3, 5] = -1.0
     Q[n_int + 2::3, 7] = 256.0
-    for k, alpha, beta in ((10, 0.05, 0.005), (100, 0.01, 0.02)):
+    for k, alpha, beta, mb in ((10, 0.05, 0.005, 0), (100, 0.01, 0.02, 0), (10, 0.05, 0.005, 13)):
+        # mb: batches of 13 (a ragged last one)
         idx = t.Index(path, 0)
         g32 = gpu_search(idx, Q, k, alpha, beta, ("ncand",))
         idx.set_option(t.TC_OPT_PRECISION, t.TC_U8)
+        if mb:
+            idx.set_option(t.TC_OPT_MAX_BATCH, mb)
         g8 = gpu_search(idx, Q, k, alpha, beta, ("ncand", "nrecheck"))
         idx.close()
         assert np.array_equal(g8["ids"], g32["ids"]), k
