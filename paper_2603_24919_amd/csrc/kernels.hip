@@ -583,7 +583,7 @@ constexpr int CT_BLOCK = TACO_CT_BLOCK;
 constexpr int CT_UNROLL = TACO_CT_UNROLL;       // windows in flight per wavefront
 constexpr int CT_WAVES = CT_BLOCK / WAVE;
 constexpr int CT_CHUNK = CT_BLOCK;              // slices staged at a time, one per thread
-constexpr int CT_WT = 1024;                     // windows per position segment
+constexpr int CT_WT = 512;                      // windows per position segment
 constexpr int CT_STAGE = 256;                   // per-wavefront candidate staging slots
 
 struct CountArgs {
@@ -595,17 +595,21 @@ struct CountArgs {
     const int32_t *ncells;   // [nq][Ns]
 };
 
-// LDS carve-up of k_count (dynamic part).  dl and pos are adjacent (the
+// LDS carve-up of k_count (dynamic part).  dl and sb are adjacent (the
 // fused kernel stages candidates there once counting is done).
 struct CountLds {
     uint32_t *cnt;    // W*BITS/32 words of packed counts
     uint32_t *dl;     // [CT_CHUNK] start (element of ids) minus first position, per
                       // non-empty slice: position p of the slice is element dl + p
-    uint32_t *pos;    // [CT_CHUNK + 1] first position of each non-empty slice
+    uint32_t *sb;     // [2 * CT_WT] of a region of CT_CHUNK + 1 words: bit p of the
+                      // segment is set when a non-empty slice starts at position p
     uint16_t *wt;     // [CT_WT] slice holding the first position of each window
     int32_t *pP;      // [17] prefix of probed cells over subspaces
     uint32_t *wsum;   // [2 * CT_WAVES] per-wavefront totals of the prefix sums
 };
+
+static_assert(2 * CT_WT <= CT_CHUNK + 1, "the start bitmap must fit its region");
+static_assert(CT_CHUNK % 2 == 0, "the start bitmap is read in 64-bit words");
 
 __host__ __device__ constexpr size_t count_lds_size(int W, int bits) {
     return static_cast<size_t>(W) * bits / 8 + static_cast<size_t>(CT_CHUNK) * 4 +
@@ -618,8 +622,8 @@ __device__ __forceinline__ CountLds carve(unsigned char *lds, int W) {
     CountLds c;
     c.cnt = reinterpret_cast<uint32_t *>(lds);
     c.dl = c.cnt + W / (32 / BITS);
-    c.pos = c.dl + CT_CHUNK;
-    c.wt = reinterpret_cast<uint16_t *>(c.pos + CT_CHUNK + 1);
+    c.sb = c.dl + CT_CHUNK;  // 8-byte aligned: W*BITS/32 and CT_CHUNK are even
+    c.wt = reinterpret_cast<uint16_t *>(c.sb + CT_CHUNK + 1);
     c.pP = reinterpret_cast<int32_t *>(c.wt + CT_WT);
     c.wsum = reinterpret_cast<uint32_t *>(c.pP + 17);
     return c;
@@ -717,33 +721,29 @@ __device__ __forceinline__ void ge_masks(uint32_t w, uint32_t v, uint32_t &m0, u
 // of the current position segment, one position per lane and window; the
 // ids are loaded into id[] (0xffffffff where the position lies past the
 // segment).  The lane's slice is the window's first slice s0 (window table)
-// plus the number of slice ends at or below its position; those ends are
-// pos[s0+1..], held one per lane, and only the few that fall inside the
-// window (a ballot) are compared.  GUARD: some windows or positions of the
-// round lie past the segment; otherwise no lane needs a bounds test.
+// plus the number of slices starting after the window's first position and
+// at or before the lane's: bits 1..lane of the window's 64-bit word of the
+// start bitmap, one masked bit count.  GUARD: some windows or positions of
+// the round lie past the segment; otherwise no lane needs a bounds test.
 template <bool GUARD>
 __device__ __forceinline__ void walk_load(const CountArgs &a, const CountLds &L, uint32_t seg,
                                           uint32_t seg_end, uint32_t nwin, uint32_t tne, uint32_t w0,
                                           int lane, uint32_t (&id)[CT_UNROLL]) {
-    uint32_t s0[CT_UNROLL], e[CT_UNROLL];
+    uint32_t e[CT_UNROLL];
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) {
         const uint32_t wi = w0 + u * CT_WAVES;
-        s0[u] = (!GUARD || wi < nwin) ? __builtin_amdgcn_readfirstlane(L.wt[wi]) : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < CT_UNROLL; u++) e[u] = L.pos[min(s0[u] + 1u + static_cast<uint32_t>(lane), tne)];
-#pragma unroll
-    for (int u = 0; u < CT_UNROLL; u++) {
-        const uint32_t wi = w0 + u * CT_WAVES;
-        const uint32_t p0 = seg + wi * WAVE, p = p0 + static_cast<uint32_t>(lane);
-        // ends inside the window sit in the lowest lanes (pos ascends); the
-        // clamped lanes past tne hold the run's end, which no valid p reaches
-        const int k = (!GUARD || wi < nwin) ? __popcll(__ballot(e[u] < p0 + WAVE)) : 0;
-        uint32_t sl = s0[u];
-        for (int b = 0; b < k; b++)
-            sl += static_cast<uint32_t>(__builtin_amdgcn_readlane(e[u], b)) <= p ? 1u : 0u;
-        e[u] = sl;
+        uint32_t s0 = 0u, mlo = 0u, mhi = 0u;
+        if (!GUARD || wi < nwin) {
+            // uniform addresses: every lane reads the same entries
+            s0 = L.wt[wi];
+            const uint2 m = reinterpret_cast<const uint2 *>(L.sb)[wi];
+            mlo = m.x;
+            mhi = m.y;
+        }
+        // the word shifted down by one: bit j - 1 flags a start at window offset j
+        const uint32_t lo1 = (mlo >> 1) | (mhi << 31), hi1 = mhi >> 1;
+        e[u] = __builtin_amdgcn_mbcnt_hi(hi1, __builtin_amdgcn_mbcnt_lo(lo1, s0));
     }
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) e[u] = L.dl[GUARD ? min(e[u], tne - 1u) : e[u]];
@@ -825,20 +825,19 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
         const uint32_t bne = wave_sum_u32(lane < wave ? x1 : 0u), bpos = wave_sum_u32(lane < wave ? x2 : 0u);
         const uint32_t tne = wave_sum_u32(x1), tpos = wave_sum_u32(x2);
         const uint32_t ci = bne + ine - ne, p0 = bpos + ipos - len;
-        if (len > 0u) {
-            L.dl[ci] = st - p0;
-            L.pos[ci] = p0;
-        }
-        if (threadIdx.x == 0) L.pos[tne] = tpos;
+        if (len > 0u) L.dl[ci] = st - p0;
         __syncthreads();
         for (uint32_t seg = 0; seg < tpos; seg += CT_WT * WAVE) {
             const uint32_t seg_end = min(tpos, seg + static_cast<uint32_t>(CT_WT * WAVE));
-            // window table of this segment: every window start (a multiple
-            // of 64) lies in exactly one non-empty slice
+            for (int i = threadIdx.x; i < 2 * CT_WT; i += CT_BLOCK) L.sb[i] = 0u;
+            __syncthreads();
+            // window table and start bitmap of this segment: every window
+            // start (a multiple of 64) lies in exactly one non-empty slice
             if (len > 0u) {
                 const uint32_t lo_p = max(p0, seg), hi_p = min(p0 + len, seg_end);
                 for (uint32_t wp = (lo_p + WAVE - 1) / WAVE * WAVE; wp < hi_p; wp += WAVE)
                     L.wt[(wp - seg) / WAVE] = static_cast<uint16_t>(ci);
+                if (p0 >= seg && p0 < seg_end) atomicOr(&L.sb[(p0 - seg) / 32], 1u << ((p0 - seg) % 32));
             }
             __syncthreads();
             const uint32_t nwin = (seg_end - seg + WAVE - 1) / WAVE;
@@ -1711,6 +1710,38 @@ __global__ __launch_bounds__(256) void k_rerank16(const float *__restrict__ Q, i
     }
 }
 
+// Per query of a batch, for the exact 8-bit re-rank, in rows of d/4 + 4
+// words (16-byte aligned for d % 16 == 0): words w < d/4 hold values
+// 4w..4w+3 as bytes, word d/4 is 1 when every value is an integer in
+// [0, 255] (else 0), word d/4 + 1 is |q|^2 (exact then: integers below 2^24
+// for d <= 256).  One wavefront per query; d % 16 == 0, d <= 256.
+__global__ __launch_bounds__(256) void k_qbytes(const float *__restrict__ Q, int nq, int d,
+                                                uint32_t *__restrict__ info) {
+    const int q = blockIdx.x * WAVES + threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    if (q >= nq) return;
+    const float *qv = Q + static_cast<int64_t>(q) * d;
+    uint32_t *out = info + static_cast<int64_t>(q) * (d / 4 + 4);
+    bool ok = true;
+    float sq = 0.0f;
+    for (int w = lane; w < d / 4; w += WAVE) {
+        uint32_t word = 0u;
+        for (int b = 0; b < 4; b++) {
+            const float v = qv[4 * w + b];
+            ok = ok && v >= 0.0f && v <= 255.0f && v == rintf(v);
+            sq = fmaf(v, v, sq);
+            word |= (ok ? static_cast<uint32_t>(v) : 0u) << (8 * b);
+        }
+        out[w] = word;
+    }
+#pragma unroll
+    for (int m = WAVE / 2; m > 0; m >>= 1) sq += __shfl_xor(sq, m, WAVE);
+    const bool all = __all(ok);
+    if (lane == 0) {
+        out[d / 4] = all ? 1u : 0u;
+        out[d / 4 + 1] = all ? static_cast<uint32_t>(sq) : 0u;
+    }
+}
+
 // The same bounds from 8-bit rows: row i is stored as codes c_t with its
 // own offset lo_i and step sc_i, x^_t = fl(lo_i + fl(c_t * sc_i)); the
 // preparation kernel computes the row's error bound against exactly these
@@ -1718,7 +1749,8 @@ __global__ __launch_bounds__(256) void k_rerank16(const float *__restrict__ Q, i
 // with one load.  PLAIN: every row has offset 0, step 1 and error 0 (integer
 // data in [0, 255]), and no record is read.  The query is used as is (no
 // centring), so its only rounding is inside the distance.
-// PLAIN with 16 | d <= 256 and a query of integers in [0, 255]: every term
+// PLAIN with 16 | d <= 256 and a query of integers in [0, 255] (qinfo, from
+// k_qbytes; null: never): every term
 // (q_t - x_t)^2 <= 255^2 and every partial sum <= d * 255^2 < 2^24 are
 // integers that FP32 holds exactly, so the FP32 path's distance is the
 // exact integer |q|^2 + |x|^2 - 2 q.x whatever its summation order; that is
@@ -1734,11 +1766,66 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
                                                  const int32_t *__restrict__ cand,
                                                  const uint32_t *__restrict__ cand_count,
                                                  int64_t cap, float *__restrict__ ub_out,
-                                                 float *__restrict__ lb_out, uint32_t *__restrict__ exact) {
+                                                 float *__restrict__ lb_out, uint32_t *__restrict__ exact,
+                                                 const uint32_t *__restrict__ qinfo) {
     extern __shared__ float qs[];
     __shared__ float rq_part[WAVES];
     const int q = blockIdx.y, chunk = blockIdx.x;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int64_t nc = cand_count[q];
+    constexpr int RPW = WAVE / LPR;
+    const int sub = lane / LPR, li = lane % LPR;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVES * RPW;
+    const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
+    const uint32_t *info = qinfo ? qinfo + static_cast<int64_t>(q) * (d / 4 + 4) : nullptr;
+    const bool integral = PLAIN && VEC16 && info && info[d / 4] != 0u;
+    if (exact && chunk == 0 && threadIdx.x == 0) exact[q] = integral ? 1u : 0u;
+    if (PLAIN && VEC16 && integral) {
+        const int qq = static_cast<int>(info[d / 4 + 1]);
+        const uint4 *qb4 = reinterpret_cast<const uint4 *>(info);
+        for (int64_t i0 = (static_cast<int64_t>(chunk) * WAVES + wave) * RPW; i0 < nc; i0 += stride * RU) {
+            int64_t id[RU];
+            int acc[RU];
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                const int64_t i = i0 + u * stride + sub;
+                id[u] = i < nc ? static_cast<int64_t>(cq[i]) : -1;
+                acc[u] = 0;
+            }
+            for (int f = li; f < d / 16; f += LPR) {
+                const uint4 qv = qb4[f];
+                uint4 v[RU];
+#pragma unroll
+                for (int u = 0; u < RU; u++)
+                    v[u] = id[u] >= 0 ? reinterpret_cast<const uint4 *>(base8 + id[u] * d)[f]
+                                      : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+                for (int u = 0; u < RU; u++) {
+                    // |x|^2 - 2 q.x over these 16 bytes
+                    uint32_t xx = __builtin_amdgcn_udot4(v[u].x, v[u].x, 0u, false);
+                    xx = __builtin_amdgcn_udot4(v[u].y, v[u].y, xx, false);
+                    xx = __builtin_amdgcn_udot4(v[u].z, v[u].z, xx, false);
+                    xx = __builtin_amdgcn_udot4(v[u].w, v[u].w, xx, false);
+                    uint32_t qx = __builtin_amdgcn_udot4(v[u].x, qv.x, 0u, false);
+                    qx = __builtin_amdgcn_udot4(v[u].y, qv.y, qx, false);
+                    qx = __builtin_amdgcn_udot4(v[u].z, qv.z, qx, false);
+                    qx = __builtin_amdgcn_udot4(v[u].w, qv.w, qx, false);
+                    acc[u] += static_cast<int>(xx) - 2 * static_cast<int>(qx);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < RU; u++) {
+                int a = acc[u];
+#pragma unroll
+                for (int m = LPR / 2; m > 0; m >>= 1) a += __shfl_xor(a, m, WAVE);
+                const int64_t i = i0 + u * stride + sub;
+                // the lower bound is not needed: the re-check takes the bound
+                // top k as it is for a flagged query
+                if (li == 0 && i < nc) ub_out[static_cast<int64_t>(q) * cap + i] = static_cast<float>(qq + a);
+            }
+        }
+        return;
+    }
     float sq = 0.0f;
     for (int t = threadIdx.x; t < d; t += BLOCK) {
         const float v = Q[static_cast<int64_t>(q) * d + t];
@@ -1752,75 +1839,6 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
     float rq2 = 0.0f;
     for (int w = 0; w < WAVES; w++) rq2 += rq_part[w];
     const float rq = sqrtf(rq2) * (1.0f + (d + 8) * 0x1p-23f);
-    const int64_t nc = cand_count[q];
-    constexpr int RPW = WAVE / LPR;
-    const int sub = lane / LPR, li = lane % LPR;
-    const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVES * RPW;
-    const int32_t *cq = cand + static_cast<int64_t>(q) * cap;
-    bool integral = false;
-    if (PLAIN && VEC16 && d <= 256 && exact) {
-        bool ok = true;
-        for (int t = threadIdx.x; t < d; t += BLOCK) {
-            const float v = qs[t];
-            ok = ok && v >= 0.0f && v <= 255.0f && v == rintf(v);
-        }
-        integral = __syncthreads_and(ok) != 0;
-    }
-    if (exact && chunk == 0 && threadIdx.x == 0) exact[q] = integral ? 1u : 0u;
-    if (PLAIN && VEC16 && d <= 256 && exact) {
-        __shared__ uint32_t qb[64];  // the query's bytes, four per word
-        if (integral) {
-            for (int w = threadIdx.x; w < d / 4; w += BLOCK)
-                qb[w] = static_cast<uint32_t>(qs[4 * w]) | (static_cast<uint32_t>(qs[4 * w + 1]) << 8) |
-                        (static_cast<uint32_t>(qs[4 * w + 2]) << 16) | (static_cast<uint32_t>(qs[4 * w + 3]) << 24);
-            __syncthreads();
-            const int qq = static_cast<int>(rq2);  // exact: integers below 2^24
-            const uint4 *qb4 = reinterpret_cast<const uint4 *>(qb);
-            for (int64_t i0 = (static_cast<int64_t>(chunk) * WAVES + wave) * RPW; i0 < nc;
-                 i0 += stride * RU) {
-                int64_t id[RU];
-                int acc[RU];
-#pragma unroll
-                for (int u = 0; u < RU; u++) {
-                    const int64_t i = i0 + u * stride + sub;
-                    id[u] = i < nc ? static_cast<int64_t>(cq[i]) : -1;
-                    acc[u] = 0;
-                }
-                for (int f = li; f < d / 16; f += LPR) {
-                    const uint4 qv = qb4[f];
-                    uint4 v[RU];
-#pragma unroll
-                    for (int u = 0; u < RU; u++)
-                        v[u] = id[u] >= 0 ? reinterpret_cast<const uint4 *>(base8 + id[u] * d)[f]
-                                          : make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
-                    for (int u = 0; u < RU; u++) {
-                        // |x|^2 - 2 q.x over these 16 bytes
-                        uint32_t xx = __builtin_amdgcn_udot4(v[u].x, v[u].x, 0u, false);
-                        xx = __builtin_amdgcn_udot4(v[u].y, v[u].y, xx, false);
-                        xx = __builtin_amdgcn_udot4(v[u].z, v[u].z, xx, false);
-                        xx = __builtin_amdgcn_udot4(v[u].w, v[u].w, xx, false);
-                        uint32_t qx = __builtin_amdgcn_udot4(v[u].x, qv.x, 0u, false);
-                        qx = __builtin_amdgcn_udot4(v[u].y, qv.y, qx, false);
-                        qx = __builtin_amdgcn_udot4(v[u].z, qv.z, qx, false);
-                        qx = __builtin_amdgcn_udot4(v[u].w, qv.w, qx, false);
-                        acc[u] += static_cast<int>(xx) - 2 * static_cast<int>(qx);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < RU; u++) {
-                    int a = acc[u];
-#pragma unroll
-                    for (int m = LPR / 2; m > 0; m >>= 1) a += __shfl_xor(a, m, WAVE);
-                    const int64_t i = i0 + u * stride + sub;
-                    // the lower bound is not needed: the re-check takes the bound
-                    // top k as it is for a flagged query
-                    if (li == 0 && i < nc) ub_out[static_cast<int64_t>(q) * cap + i] = static_cast<float>(qq + a);
-                }
-            }
-            return;
-        }
-    }
     const float g = 2.0f * (d + 2) * 0x1p-24f + 0x1p-18f;
     for (int64_t i0 = (static_cast<int64_t>(chunk) * WAVES + wave) * RPW; i0 < nc;
          i0 += stride * RU) {
@@ -2490,9 +2508,11 @@ hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint
     SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
                   s.dump_hist, s.redo};
     const int64_t words4 = static_cast<int64_t>(c.T) * c.W * c.bits / 128;
-    // about 16 sixteen-byte words per thread
-    int64_t blocks = (words4 + SEL_BLOCK * 16 - 1) / (SEL_BLOCK * 16);
-    if (blocks > 64) blocks = 64;
+    // about 16 sixteen-byte words per thread; the few queued queries of a
+    // list selection get one word per thread
+    const int64_t per = s.redo ? 1 : 16;
+    int64_t blocks = (words4 + SEL_BLOCK * per - 1) / (SEL_BLOCK * per);
+    if (blocks > (s.redo ? 256 : 64)) blocks = s.redo ? 256 : 64;
     if (blocks < 1) blocks = 1;
     dim3 grid(static_cast<unsigned>(blocks), s.redo ? s.redo_groups : c.nq);
     const uint4 *s4 = reinterpret_cast<const uint4 *>(sc);
@@ -2577,19 +2597,25 @@ hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const
     return hipGetLastError();
 }
 
+hipError_t launch_qbytes(const float *Q, int nq, int d, uint32_t *info, hipStream_t st) {
+    if (d % 16 != 0 || d > 256) return hipErrorInvalidValue;
+    k_qbytes<<<(nq + WAVES - 1) / WAVES, BLOCK, 0, st>>>(Q, nq, d, info);
+    return hipGetLastError();
+}
+
 hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, const float4 *meta, bool plain,
                           const int32_t *cand, const uint32_t *cand_count, int64_t cap, float *ub, float *lb,
-                          uint32_t *exact, int blocks_per_q, hipStream_t st) {
+                          uint32_t *exact, const uint32_t *qinfo, int blocks_per_q, hipStream_t st) {
     dim3 grid(blocks_per_q, nq);
     size_t lds = sizeof(float) * static_cast<size_t>(d);
 #define TACO_RR8(L, V)                                                                                    \
     do {                                                                                                  \
         if (plain)                                                                                        \
             k_rerank8<L, V, true><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb, \
-                                                            exact);                                           \
+                                                            exact, qinfo);                                    \
         else                                                                                              \
             k_rerank8<L, V, false><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb, \
-                                                             exact);                                          \
+                                                             exact, qinfo);                                   \
     } while (0)
     if (d % 16 != 0) {
         TACO_RR8(64, false);

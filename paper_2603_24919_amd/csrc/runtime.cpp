@@ -147,6 +147,7 @@ struct tc_index {
     int32_t *rk_ids = nullptr;   // [Qb][n] re-checked candidates
     uint32_t *rk_count = nullptr;
     uint32_t *exact = nullptr;   // [Qb] the 8-bit bounds are the FP32 distances
+    uint32_t *qinfo = nullptr;   // [Qb][d/4 + 4] per-query bytes, integrality, |q|^2
     int64_t *tau_ids = nullptr;  // [Qb][1024] top-k of the upper bounds
     float *tau_d = nullptr;
     std::vector<float> mean_host;
@@ -197,6 +198,8 @@ void free_scratch(tc_index *x) {
     (void)hipFree(x->tau_ids);
     (void)hipFree(x->exact);
     x->exact = nullptr;
+    (void)hipFree(x->qinfo);
+    x->qinfo = nullptr;
     (void)hipFree(x->tau_d);
     (void)hipFree(x->qn);
     (void)hipFree(x->qsc);
@@ -279,6 +282,7 @@ int alloc_scratch(tc_index *x) {
         if ((rc = dmalloc(&x->rk_count, size_t(qb), "re-check counts"))) return rc;
         if ((rc = dmalloc(&x->tau_ids, size_t(qb) * 1024, "bound top-k ids"))) return rc;
         if ((rc = dmalloc(&x->exact, size_t(qb), "exact-bound flags"))) return rc;
+        if ((rc = dmalloc(&x->qinfo, size_t(qb) * (x->d / 4 + 4), "query bytes"))) return rc;
         if ((rc = dmalloc(&x->tau_d, size_t(qb) * 1024, "bound top-k"))) return rc;
     }
     x->Qb = qb;
@@ -707,10 +711,15 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                 TC_HIP(taco::launch_rerank16(Qb, nb, x->d, x->mu, x->base16, x->rowerr, x->cand,
                                              x->cand_count, cap, x->cand_dist, x->lb, rr_blocks, st),
                        "BF16 rerank kernel");
-            else
+            else {
+                // exact form: plain rows, 16 | d <= 256
+                const bool ex = x->u8_plain && x->d % 16 == 0 && x->d <= 256;
+                if (ex) TC_HIP(taco::launch_qbytes(Qb, nb, x->d, x->qinfo, st), "query bytes kernel");
                 TC_HIP(taco::launch_rerank8(Qb, nb, x->d, x->base8, x->rmeta, x->u8_plain, x->cand,
-                                            x->cand_count, cap, x->cand_dist, x->lb, x->exact, rr_blocks, st),
+                                            x->cand_count, cap, x->cand_dist, x->lb, x->exact,
+                                            ex ? x->qinfo : nullptr, rr_blocks, st),
                        "8-bit rerank kernel");
+            }
             record(x, K_RERANK, st, false);
             record(x, K_TOPK, st, true);
             TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, kq, k_max,
