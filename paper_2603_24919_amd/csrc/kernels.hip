@@ -601,11 +601,14 @@ struct CountLds {
     uint32_t *cnt;    // W*BITS/32 words of packed counts
     uint32_t *dl;     // [CT_CHUNK] start (element of ids) minus first position, per
                       // non-empty slice: position p of the slice is element dl + p
-    uint32_t *sb;     // [2 * CT_WT] of a region of CT_CHUNK + 1 words: bit p of the
-                      // segment is set when a non-empty slice starts at position p
+    uint32_t *sb;     // [2 * CT_WT] of a region of CT_CHUNK + 1 words: bit p - 1 of
+                      // the segment is set when a non-empty slice starts at position
+                      // p > 0 of the segment
     uint16_t *wt;     // [CT_WT] slice holding the first position of each window
     int32_t *pP;      // [17] prefix of probed cells over subspaces
     uint32_t *wsum;   // [2 * CT_WAVES] per-wavefront totals of the prefix sums
+    uint32_t *hsum;   // [18] the tile's "count >= v" totals
+    uint32_t *lsum;   // [17] levels of the listed ids
 };
 
 static_assert(2 * CT_WT <= CT_CHUNK + 1, "the start bitmap must fit its region");
@@ -614,7 +617,7 @@ static_assert(CT_CHUNK % 2 == 0, "the start bitmap is read in 64-bit words");
 __host__ __device__ constexpr size_t count_lds_size(int W, int bits) {
     return static_cast<size_t>(W) * bits / 8 + static_cast<size_t>(CT_CHUNK) * 4 +
            static_cast<size_t>(CT_CHUNK + 1) * 4 + static_cast<size_t>(CT_WT) * 2 + 17 * 4 +
-           2 * CT_WAVES * 4;
+           2 * CT_WAVES * 4 + (18 + 17) * 4;
 }
 
 template <int BITS>
@@ -626,6 +629,8 @@ __device__ __forceinline__ CountLds carve(unsigned char *lds, int W) {
     c.wt = reinterpret_cast<uint16_t *>(c.sb + CT_CHUNK + 1);
     c.pP = reinterpret_cast<int32_t *>(c.wt + CT_WT);
     c.wsum = reinterpret_cast<uint32_t *>(c.pP + 17);
+    c.hsum = c.wsum + 2 * CT_WAVES;
+    c.lsum = c.hsum + 18;
     return c;
 }
 
@@ -722,8 +727,8 @@ __device__ __forceinline__ void ge_masks(uint32_t w, uint32_t v, uint32_t &m0, u
 // ids are loaded into id[] (0xffffffff where the position lies past the
 // segment).  The lane's slice is the window's first slice s0 (window table)
 // plus the number of slices starting after the window's first position and
-// at or before the lane's: bits 1..lane of the window's 64-bit word of the
-// start bitmap, one masked bit count.  GUARD: some windows or positions of
+// at or before the lane's: the bits below the lane in the window's 64-bit
+// word of the start bitmap (stored one position down), one masked count.  GUARD: some windows or positions of
 // the round lie past the segment; otherwise no lane needs a bounds test.
 template <bool GUARD>
 __device__ __forceinline__ void walk_load(const CountArgs &a, const CountLds &L, uint32_t seg,
@@ -741,9 +746,7 @@ __device__ __forceinline__ void walk_load(const CountArgs &a, const CountLds &L,
             mlo = m.x;
             mhi = m.y;
         }
-        // the word shifted down by one: bit j - 1 flags a start at window offset j
-        const uint32_t lo1 = (mlo >> 1) | (mhi << 31), hi1 = mhi >> 1;
-        e[u] = __builtin_amdgcn_mbcnt_hi(hi1, __builtin_amdgcn_mbcnt_lo(lo1, s0));
+        e[u] = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, s0));
     }
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) e[u] = L.dl[GUARD ? min(e[u], tne - 1u) : e[u]];
@@ -837,7 +840,7 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
                 const uint32_t lo_p = max(p0, seg), hi_p = min(p0 + len, seg_end);
                 for (uint32_t wp = (lo_p + WAVE - 1) / WAVE * WAVE; wp < hi_p; wp += WAVE)
                     L.wt[(wp - seg) / WAVE] = static_cast<uint16_t>(ci);
-                if (p0 >= seg && p0 < seg_end) atomicOr(&L.sb[(p0 - seg) / 32], 1u << ((p0 - seg) % 32));
+                if (p0 > seg && p0 < seg_end) atomicOr(&L.sb[(p0 - seg - 1) / 32], 1u << ((p0 - seg - 1) % 32));
             }
             __syncthreads();
             const uint32_t nwin = (seg_end - seg + WAVE - 1) / WAVE;
@@ -1116,10 +1119,11 @@ __device__ __forceinline__ void list_tile(const ListArgs &la, const uint32_t *cn
 template <int BITS, bool HI, int MODE, bool TR>
 __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__restrict__ hist,
                                                    uint4 *__restrict__ sc, ListArgs la) {
+    // no static LDS: the packed counts start at address 0, so an increment's
+    // byte offset is its address
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const CountLds L = carve<BITS>(lds_raw, a.W);
-    __shared__ uint32_t hsum[18];
-    __shared__ uint32_t lsum[17];  // levels of the listed ids
+    uint32_t *hsum = L.hsum, *lsum = L.lsum;
     const int t = blockIdx.x;
     const int lane = threadIdx.x % WAVE;
     const int vec = a.W * BITS / 128;  // 16-byte words per tile
@@ -2405,7 +2409,7 @@ hipError_t launch_budgets(const double *alpha, const int32_t *kq, int nq, int64_
     return hipGetLastError();
 }
 
-size_t count_lds_bytes(int W, int bits) { return count_lds_size(W, bits) + 18 * sizeof(uint32_t); }
+size_t count_lds_bytes(int W, int bits) { return count_lds_size(W, bits); }
 
 // Instances: nibble counts up to 8 levels (Ns <= 8), nibbles with up to
 // 15, bytes (Ns = 16).
