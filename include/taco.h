@@ -63,8 +63,8 @@ enum tc_select_rule { TC_RULE_PRINTED = 0, TC_RULE_PROSE = 1 };
 enum tc_option {
     TC_OPT_SELECT_RULE = 1, /* tc_select_rule; default TC_RULE_PRINTED                 */
     TC_OPT_MAX_BATCH = 2,   /* max queries per internal batch (>= 1); scratch is
-                               re-sized to fit; default: what 32 GiB of candidate
-                               scratch allows, at most 4096                          */
+                               re-sized to fit; default: what 64 GiB of candidate
+                               scratch allows, at most 8192                          */
     TC_OPT_TILE_IDS = 3,    /* ids per LDS counting tile: a multiple of 1024 whose
                                packed counts (4 bits per id when Ns <= 15, else 8)
                                fit the GPU's LDS per workgroup; default 64 KB of
@@ -72,7 +72,7 @@ enum tc_option {
     TC_OPT_PROFILE = 4,     /* 1: time every kernel launch with HIP events on the
                                search stream (read with tc_kernel_time); 0: off      */
     TC_OPT_SCRATCH_BYTES = 5, /* candidate-scratch budget in bytes used to pick the
-                               batch size (>= 8*n); default 32 GiB                   */
+                               batch size (>= 8*n); default 64 GiB                   */
     TC_OPT_PRECISION = 6,   /* tc_precision of the re-rank; default TC_FP32         */
     TC_OPT_COUNT_MODE = 7,  /* tc_count_mode; default TC_COUNT_AUTO                  */
     TC_OPT_GRAPH = 8,       /* 1: capture each call's launch sequence into a HIP

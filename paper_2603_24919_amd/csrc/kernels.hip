@@ -2244,7 +2244,9 @@ __global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
 // flight), the kept ones compacted into LDS and re-ranked by row groups with
 // the FP32 path's own arithmetic (row_partial32 and group_sum with the same
 // lanes per row); the kept (id, distance) pairs go to (rk_ids, rk_dist), and
-// their top k to the output rows.  A query with exact[q] set (its bounds are
+// their top k to the output rows.  rk_ids may share memory with lb: a
+// chunk's lower bounds are read before its kept rows are written, and kept
+// rows land below the chunk's end.  A query with exact[q] set (its bounds are
 // the FP32 distances) takes the top k of the bounds as they are.  grid nq,
 // block 256, dynamic LDS d floats.
 template <int LPR, bool VEC4>
@@ -2252,10 +2254,10 @@ __global__ __launch_bounds__(256) void k_recheck_topk(const float *__restrict__ 
                                                       const float *__restrict__ base,
                                                       const int32_t *__restrict__ cand,
                                                       const uint32_t *__restrict__ cand_count,
-                                                      const float *__restrict__ lb, int64_t cap,
+                                                      const float *lb, int64_t cap,
                                                       const float *__restrict__ tau_d, int k_all,
                                                       const int32_t *__restrict__ kq, int k_max,
-                                                      int32_t *__restrict__ rk_ids, float *__restrict__ rk_dist,
+                                                      int32_t *rk_ids, float *__restrict__ rk_dist,
                                                       uint32_t *__restrict__ rk_count,
                                                       int64_t *__restrict__ ids_out, float *__restrict__ d_out,
                                                       const uint32_t *__restrict__ exact,

@@ -123,7 +123,7 @@ struct tc_index {
     // options
     int rule = TC_RULE_PRINTED;
     int64_t max_batch = 0;  // 0: automatic
-    int64_t scratch_budget = int64_t(32) << 30;
+    int64_t scratch_budget = int64_t(64) << 30;
     bool profile = false;
     // scratch for one batch of Qb queries
     int64_t Qb = 0;
@@ -144,7 +144,6 @@ struct tc_index {
     float4 *rmeta = nullptr;     // [n] per-row (offset, step, error bound, 0) of the codes
     bool u8_plain = false;       // every row: offset 0, step 1, error 0
     float *lb = nullptr;         // [Qb][n] lower bounds of the FP32 distances
-    int32_t *rk_ids = nullptr;   // [Qb][n] re-checked candidates
     uint32_t *rk_count = nullptr;
     uint32_t *exact = nullptr;   // [Qb] the 8-bit bounds are the FP32 distances
     uint32_t *qinfo = nullptr;   // [Qb][d/4 + 4] per-query bytes, integrality, |q|^2
@@ -193,7 +192,6 @@ void free_scratch(tc_index *x) {
     (void)hipFree(x->arrive);
     x->arrive = nullptr;
     (void)hipFree(x->lb);
-    (void)hipFree(x->rk_ids);
     (void)hipFree(x->rk_count);
     (void)hipFree(x->tau_ids);
     (void)hipFree(x->exact);
@@ -211,7 +209,6 @@ void free_scratch(tc_index *x) {
     x->qn = x->qsc = x->cd = nullptr;
     x->sc = nullptr;
     x->lb = nullptr;
-    x->rk_ids = nullptr;
     x->rk_count = nullptr;
     x->tau_ids = nullptr;
     x->tau_d = nullptr;
@@ -236,13 +233,15 @@ int dmalloc(T **p, size_t count, const char *what) {
     return TC_OK;
 }
 
-// Candidate slots are n per query (|C| can reach n), plus one byte of packed
-// count per id; the batch size follows from the scratch budget.
+// Candidate slots are n per query (|C| can reach n): ids and distances, and
+// in the bounded re-ranks the lower bounds (which also hold the re-checked
+// ids), plus the packed counts; the batch size follows from the scratch
+// budget.
 int64_t batch_for(const tc_index *x) {
     int64_t per_q = 8 * x->n + int64_t(x->T) * x->W * x->bits / 8;
-    if (x->precision != TC_FP32) per_q += 8 * x->n;
+    if (x->precision != TC_FP32) per_q += 4 * x->n;
     int64_t qb = x->scratch_budget / per_q;
-    int64_t cap = x->max_batch > 0 ? x->max_batch : 4096;
+    int64_t cap = x->max_batch > 0 ? x->max_batch : 8192;
     if (qb > cap) qb = cap;
     if (qb < 1) qb = 1;
     return qb;
@@ -278,7 +277,6 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->cd, size_t(qb) * x->Ns * 2 * x->l, "centroid distances"))) return rc;
     if (x->precision != TC_FP32) {
         if ((rc = dmalloc(&x->lb, size_t(qb) * x->n, "distance lower bounds"))) return rc;
-        if ((rc = dmalloc(&x->rk_ids, size_t(qb) * x->n, "re-checked candidates"))) return rc;
         if ((rc = dmalloc(&x->rk_count, size_t(qb), "re-check counts"))) return rc;
         if ((rc = dmalloc(&x->tau_ids, size_t(qb) * 1024, "bound top-k ids"))) return rc;
         if ((rc = dmalloc(&x->exact, size_t(qb), "exact-bound flags"))) return rc;
@@ -728,7 +726,8 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             record(x, K_TOPK, st, false);
             record(x, K_RECHECK, st, true);
             TC_HIP(taco::launch_recheck_topk(Qb, nb, x->d, x->base, x->cand, x->cand_count, x->lb, cap,
-                                             x->tau_d, k, kq, k_max, x->rk_ids, x->cand_dist, x->rk_count,
+                                             x->tau_d, k, kq, k_max, reinterpret_cast<int32_t *>(x->lb),
+                                             x->cand_dist, x->rk_count,
                                              ids, dists, x->precision == TC_U8 ? x->exact : nullptr, x->tau_ids,
                                              st),
                    "re-check and top-k kernel");
