@@ -44,10 +44,12 @@ constexpr int WAVES = BLOCK / WAVE;
 // back as a uniform value.
 __device__ __forceinline__ uint32_t wave_min_u32_dpp(uint32_t v) {
     int x = static_cast<int>(v);
+    // old value = the minimum's identity, so lanes outside row_mask leave x
+    // unchanged and each stage can fold into one v_min with a DPP source
 #define TACO_DPP_MIN(ctrl, rows)                                                           \
     x = static_cast<int>(min(static_cast<uint32_t>(x),                                     \
                              static_cast<uint32_t>(__builtin_amdgcn_update_dpp(            \
-                                 x, x, ctrl, rows, 0xf, false))))
+                                 -1, x, ctrl, rows, 0xf, false))))
     TACO_DPP_MIN(0xb1, 0xf);   // quad_perm [1,0,3,2]
     TACO_DPP_MIN(0x4e, 0xf);   // quad_perm [2,3,0,1]
     TACO_DPP_MIN(0x141, 0xf);  // row_half_mirror
