@@ -60,20 +60,27 @@ __device__ __forceinline__ uint32_t wave_min_u32_dpp(uint32_t v) {
     return static_cast<uint32_t>(__builtin_amdgcn_readlane(x, 63));
 }
 
-__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
-#pragma unroll
-    for (int m = WAVE / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, WAVE);
-    return v;
+// Inclusive prefix sum over the (fully active) wavefront with DPP moves, no
+// LDS: row shifts by 1, 2 and 3 (out-of-row sources read 0) give sums of
+// four, shifts by 4 and 8 restricted to the upper banks of each row give the
+// row's prefix, and two row broadcasts carry rows 0 and 0-1 into the rows
+// above.
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
+    (void)lane;
+    const int v0 = static_cast<int>(v);
+    int x = v0 + __builtin_amdgcn_update_dpp(0, v0, 0x111, 0xf, 0xf, true);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, v0, 0x112, 0xf, 0xf, true);          // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, v0, 0x113, 0xf, 0xf, true);          // row_shr:3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xe, false);          // row_shr:4, lanes 4-15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xc, false);          // row_shr:8, lanes 8-15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);          // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);          // row_bcast:31 into rows 2, 3
+    return static_cast<uint32_t>(x);
 }
 
-// Inclusive prefix sum over the wavefront.
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        uint32_t t = __shfl_up(v, o, WAVE);
-        if (lane >= o) v += t;
-    }
-    return v;
+// Sum over the (fully active) wavefront, as a uniform value.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(wave_incl_scan_u32(v, 0)), WAVE - 1));
 }
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) {
