@@ -1538,6 +1538,24 @@ __device__ __forceinline__ float group_sum(float acc) {
     return acc;
 }
 
+// Integer sum over groups of LPR lanes (4, 8 or 16; wider groups use
+// shuffles), every lane of a group receiving it, with DPP moves: quad swaps,
+// then half-row and row mirrors, each pairing a lane with one in the other
+// half of its group.  Exact, so the pairing order does not matter.
+template <int LPR>
+__device__ __forceinline__ int group_sum_i32(int a) {
+    if (LPR > 16) {
+#pragma unroll
+        for (int m = LPR / 2; m > 0; m >>= 1) a += __shfl_xor(a, m, WAVE);
+        return a;
+    }
+    a += __builtin_amdgcn_update_dpp(0, a, 0xb1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+    a += __builtin_amdgcn_update_dpp(0, a, 0x4e, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+    if (LPR >= 8) a += __builtin_amdgcn_update_dpp(0, a, 0x141, 0xf, 0xf, false);  // row_half_mirror
+    if (LPR >= 16) a += __builtin_amdgcn_update_dpp(0, a, 0x140, 0xf, 0xf, false);  // row_mirror
+    return a;
+}
+
 // Rows handled at once by a lane group of the re-rank kernels: the chunk
 // loop runs outside and the rows inside, so the loads of RU rows are in
 // flight together, while each row's terms keep the order of row_partial32.
@@ -1828,9 +1846,7 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
             }
 #pragma unroll
             for (int u = 0; u < RU; u++) {
-                int a = acc[u];
-#pragma unroll
-                for (int m = LPR / 2; m > 0; m >>= 1) a += __shfl_xor(a, m, WAVE);
+                const int a = group_sum_i32<LPR>(acc[u]);
                 const int64_t i = i0 + u * stride + sub;
                 // the lower bound is not needed: the re-check takes the bound
                 // top k as it is for a flagged query
