@@ -577,9 +577,12 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 // flight, so every lane reads one id per window whatever the slice lengths
 // (cell sizes are skewed: a few long slices would otherwise serialise their
 // walker).  A window table names the slice holding each window's first
-// position; a lane steps forward from it across the (rare) slice boundaries
-// inside its window.  The tile's level histogram and its packed counts go to
-// HBM; the select kernel streams the packed counts back.
+// position and a bitmap marks every position that starts a slice; a lane
+// finds its own slice by adding to the window's first slice the number of
+// starts at or below its position in the window (one mbcnt over the 64-bit
+// word), so no lane loops.  Per tile, the level histogram goes to HBM with
+// either the packed counts (streamed back by the select kernel) or the list
+// of ids that reached the list level.
 // ---------------------------------------------------------------------------
 
 #ifndef TACO_CT_BLOCK
