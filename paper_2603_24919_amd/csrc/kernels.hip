@@ -147,18 +147,43 @@ __global__ void k_build_off2d(const uint32_t *ids, const uint32_t *offs, int Ns,
     }
 }
 
-// The id lists as the count walk reads them for tile width W: an id's
-// tile-local position loc = id mod W becomes (byte offset of its packed
-// word) << 5 | (its bit position in the word), so an increment needs no
-// index arithmetic.  Offsets stay below 2^16 (the LDS), so the code is
-// below 2^21 and never collides with the walk's 0xffffffff "no id".
-__global__ void k_encode_ids(const uint32_t *__restrict__ ids, int64_t count, int W, int bits,
-                             uint32_t *__restrict__ enc) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= count) return;
+// The id lists as the count walk reads them for tile width W.  Every slice
+// (subspace j, cell c, tile t) of the lists is laid out on its own, padded
+// to a whole number of 4-id groups: group offsets pad[(j*K + c)*(T+1) + t]
+// (pad[.. + T] ends the cell), taken from the unpadded positions raw[] of
+// k_build_off2d.  An id's tile-local position loc = id mod W becomes (byte
+// offset of its packed word) << 5 | (its bit position in the word), so an
+// increment needs no index arithmetic; a pad becomes a word of the
+// CT_DUMMY-word region that follows the W*bits/8 bytes of counts, spread
+// over its words by position.  Offsets stay below 2^17 (the LDS), so codes
+// stay below 2^22 and never collide with the walk's 0xffffffff "no id".
+// One wavefront per slice.
+constexpr uint32_t CT_DUMMY = 64;
+__global__ void k_encode_ids(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ raw,
+                             const uint32_t *__restrict__ pad, int Ns, int K, int T, int64_t n, int W,
+                             int bits, uint32_t *__restrict__ enc) {
+    const int64_t sl = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / WAVE;
+    if (sl >= static_cast<int64_t>(Ns) * K * T) return;
+    const uint32_t lane = threadIdx.x % WAVE;
+    const int64_t jc = sl / T;
+    const int t = static_cast<int>(sl % T), j = static_cast<int>(jc / K);
+    const int64_t b = jc * (T + 1) + t;
+    const uint32_t lo = raw[b], len = raw[b + 1] - lo;
+    const uint32_t g0 = pad[b], m = (pad[b + 1] - g0) * 4u;
+    const uint32_t *src = ids + static_cast<int64_t>(j) * n + lo;
+    uint32_t *dst = enc + static_cast<int64_t>(g0) * 4;
     const uint32_t per = 32u / static_cast<uint32_t>(bits);
-    const uint32_t loc = ids[i] % static_cast<uint32_t>(W);
-    enc[i] = (((loc / per) * 4u) << 5) | ((loc % per) * static_cast<uint32_t>(bits));
+    const uint32_t cnt_bytes = static_cast<uint32_t>(W) * static_cast<uint32_t>(bits) / 8u;
+    for (uint32_t e = lane; e < m; e += WAVE) {
+        uint32_t v;
+        if (e < len) {
+            const uint32_t loc = src[e] % static_cast<uint32_t>(W);
+            v = (((loc / per) * 4u) << 5) | ((loc % per) * static_cast<uint32_t>(bits));
+        } else {
+            v = (cnt_bytes + 4u * ((e + g0 * 4u) % CT_DUMMY)) << 5;
+        }
+        dst[e] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -572,11 +597,13 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 // subspaces form one list.  For a chunk of CT_CHUNK of them, every thread
 // looks up (index-time table off2d) the slice of one cell's id list that
 // falls in the tile; the non-empty slices are compacted and laid end to end
-// as one run of "positions" (block-wide prefix sums).  Wavefronts then walk
-// that run in windows of 64 consecutive positions, CT_UNROLL windows in
-// flight, so every lane reads one id per window whatever the slice lengths
-// (cell sizes are skewed: a few long slices would otherwise serialise their
-// walker).  A window table names the slice holding each window's first
+// as one run of "positions" (block-wide prefix sums).  A position is a group
+// of four ids: the device lists pad every slice to whole groups, with pads
+// that increment a dummy word, so one 16-byte load and one slice lookup serve
+// four increments.  Wavefronts then walk that run in windows of 64
+// consecutive positions, CT_UNROLL windows in flight, so every lane reads one
+// group per window whatever the slice lengths (cell sizes are skewed: a few
+// long slices would otherwise serialise their walker).  A window table names the slice holding each window's first
 // position and a bitmap marks every position that starts a slice; a lane
 // finds its own slice by adding to the window's first slice the number of
 // starts at or below its position in the window (one mbcnt over the 64-bit
@@ -589,10 +616,10 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 #define TACO_CT_BLOCK 1024
 #endif
 #ifndef TACO_CT_UNROLL
-#define TACO_CT_UNROLL 4
+#define TACO_CT_UNROLL 2
 #endif
 constexpr int CT_BLOCK = TACO_CT_BLOCK;
-constexpr int CT_UNROLL = TACO_CT_UNROLL;       // windows in flight per wavefront
+constexpr int CT_UNROLL = TACO_CT_UNROLL;       // windows (groups per lane) in flight per wavefront
 constexpr int CT_WAVES = CT_BLOCK / WAVE;
 constexpr int CT_CHUNK = CT_BLOCK;              // slices staged at a time, one per thread
 constexpr int CT_WT = 512;                      // windows per position segment
@@ -601,8 +628,8 @@ constexpr int CT_STAGE = 256;                   // per-wavefront candidate stagi
 struct CountArgs {
     int Ns, K, T, W;
     int64_t n;
-    const uint32_t *ids;     // [Ns][n] encoded for the tile width (see k_encode_ids)
-    const uint32_t *off2d;   // [Ns][K][T+1]
+    const uint32_t *ids;     // padded 4-id groups encoded for the tile width (see k_encode_ids)
+    const uint32_t *off2d;   // [Ns][K][T+1] group offsets of the slices in ids
     const int32_t *cells;    // [nq][Ns][K]
     const int32_t *ncells;   // [nq][Ns]
 };
@@ -610,9 +637,10 @@ struct CountArgs {
 // LDS carve-up of k_count (dynamic part).  dl and sb are adjacent (the
 // fused kernel stages candidates there once counting is done).
 struct CountLds {
-    uint32_t *cnt;    // W*BITS/32 words of packed counts
-    uint32_t *dl;     // [CT_CHUNK] start (element of ids) minus first position, per
-                      // non-empty slice: position p of the slice is element dl + p
+    uint32_t *cnt;    // W*BITS/32 words of packed counts, then CT_DUMMY words that
+                      // the pads of the id lists increment
+    uint32_t *dl;     // [CT_CHUNK] start (group of ids) minus first position, per
+                      // non-empty slice: position p of the slice is group dl + p
     uint32_t *sb;     // [2 * CT_WT] of a region of CT_CHUNK + 1 words: bit p - 1 of
                       // the segment is set when a non-empty slice starts at position
                       // p > 0 of the segment
@@ -627,7 +655,7 @@ static_assert(2 * CT_WT <= CT_CHUNK + 1, "the start bitmap must fit its region")
 static_assert(CT_CHUNK % 2 == 0, "the start bitmap is read in 64-bit words");
 
 __host__ __device__ constexpr size_t count_lds_size(int W, int bits) {
-    return static_cast<size_t>(W) * bits / 8 + static_cast<size_t>(CT_CHUNK) * 4 +
+    return static_cast<size_t>(W) * bits / 8 + CT_DUMMY * 4 + static_cast<size_t>(CT_CHUNK) * 4 +
            static_cast<size_t>(CT_CHUNK + 1) * 4 + static_cast<size_t>(CT_WT) * 2 + 17 * 4 +
            2 * CT_WAVES * 4 + (18 + 17) * 4;
 }
@@ -636,8 +664,8 @@ template <int BITS>
 __device__ __forceinline__ CountLds carve(unsigned char *lds, int W) {
     CountLds c;
     c.cnt = reinterpret_cast<uint32_t *>(lds);
-    c.dl = c.cnt + W / (32 / BITS);
-    c.sb = c.dl + CT_CHUNK;  // 8-byte aligned: W*BITS/32 and CT_CHUNK are even
+    c.dl = c.cnt + W / (32 / BITS) + CT_DUMMY;
+    c.sb = c.dl + CT_CHUNK;  // 8-byte aligned: W*BITS/32, CT_DUMMY and CT_CHUNK are even
     c.wt = reinterpret_cast<uint16_t *>(c.sb + CT_CHUNK + 1);
     c.pP = reinterpret_cast<int32_t *>(c.wt + CT_WT);
     c.wsum = reinterpret_cast<uint32_t *>(c.pP + 17);
@@ -646,10 +674,10 @@ __device__ __forceinline__ CountLds carve(unsigned char *lds, int W) {
     return c;
 }
 
-// Id j*n + i of the id lists [Ns][n]; the index loader guarantees Ns*n <
-// 2^30, so the byte offset fits 32 bits and the load takes a scalar base.
-__device__ __forceinline__ uint32_t load_id(const uint32_t *ids, uint32_t e) {
-    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const unsigned char *>(ids) + (e << 2));
+// Group g of the padded id lists; the tiling keeps them below 2^30 ids, so
+// the byte offset fits 32 bits and the load takes a scalar base.
+__device__ __forceinline__ uint4 load_group(const uint32_t *ids, uint32_t g) {
+    return *reinterpret_cast<const uint4 *>(reinterpret_cast<const unsigned char *>(ids) + (g << 4));
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -735,9 +763,9 @@ __device__ __forceinline__ void ge_masks(uint32_t w, uint32_t v, uint32_t &m0, u
 }
 
 // One round of a wavefront's walk: windows w0 + u*CT_WAVES (u < CT_UNROLL)
-// of the current position segment, one position per lane and window; the
-// ids are loaded into id[] (0xffffffff where the position lies past the
-// segment).  The lane's slice is the window's first slice s0 (window table)
+// of the current position segment, one position (group) per lane and
+// window; the groups are loaded into id[] (all 0xffffffff where the position
+// lies past the segment).  The lane's slice is the window's first slice s0 (window table)
 // plus the number of slices starting after the window's first position and
 // at or before the lane's: the bits below the lane in the window's 64-bit
 // word of the start bitmap (stored one position down), one masked count.  GUARD: some windows or positions of
@@ -745,7 +773,7 @@ __device__ __forceinline__ void ge_masks(uint32_t w, uint32_t v, uint32_t &m0, u
 template <bool GUARD>
 __device__ __forceinline__ void walk_load(const CountArgs &a, const CountLds &L, uint32_t seg,
                                           uint32_t seg_end, uint32_t nwin, uint32_t tne, uint32_t w0,
-                                          int lane, uint32_t (&id)[CT_UNROLL]) {
+                                          int lane, uint4 (&id)[CT_UNROLL]) {
     uint32_t e[CT_UNROLL];
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) {
@@ -766,26 +794,37 @@ __device__ __forceinline__ void walk_load(const CountArgs &a, const CountLds &L,
     for (int u = 0; u < CT_UNROLL; u++) {
         const uint32_t p = seg + (w0 + u * CT_WAVES) * WAVE + static_cast<uint32_t>(lane);
         if (GUARD) {
-            id[u] = 0xffffffffu;
-            if (p < seg_end) id[u] = load_id(a.ids, e[u] + p);
+            id[u] = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+            if (p < seg_end) id[u] = load_group(a.ids, e[u] + p);
         } else {
-            id[u] = load_id(a.ids, e[u] + p);
+            id[u] = load_group(a.ids, e[u] + p);
         }
     }
 }
 
-// The LDS increments of one round (ids of 0xffffffff skipped when GUARD);
-// TR: the old counts feed the level transitions.
+// The LDS increments of one round (groups of 0xffffffff skipped when
+// GUARD); TR: the old counts feed the level transitions, except those of
+// the pads (codes at or above lim, the dummy words).
+template <int BITS, bool HI, bool TR>
+__device__ __forceinline__ void bump_one(const CountLds &L, uint32_t enc, uint32_t lim, Trans<HI> &tr) {
+    if (TR) {
+        const uint32_t old = bump<BITS>(L.cnt, enc);
+        if (enc < lim) tr.add(old);
+    } else {
+        bump_add<BITS>(L.cnt, enc);
+    }
+}
+
 template <int BITS, bool HI, bool GUARD, bool TR>
-__device__ __forceinline__ void walk_bump(const CountLds &L, const uint32_t (&id)[CT_UNROLL],
+__device__ __forceinline__ void walk_bump(const CountLds &L, const uint4 (&id)[CT_UNROLL], uint32_t lim,
                                           Trans<HI> &tr) {
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) {
-        if (!GUARD || id[u] != 0xffffffffu) {
-            if (TR)
-                tr.add(bump<BITS>(L.cnt, id[u]));
-            else
-                bump_add<BITS>(L.cnt, id[u]);
+        if (!GUARD || id[u].x != 0xffffffffu) {
+            bump_one<BITS, HI, TR>(L, id[u].x, lim, tr);
+            bump_one<BITS, HI, TR>(L, id[u].y, lim, tr);
+            bump_one<BITS, HI, TR>(L, id[u].z, lim, tr);
+            bump_one<BITS, HI, TR>(L, id[u].w, lim, tr);
         }
     }
 }
@@ -811,6 +850,8 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     Trans<HI> tr{0ull, 0ull};
     int held = 0;  // bound on any byte of tr: bumps per lane since the last flush
+    constexpr int PER_ROUND = 4 * CT_UNROLL;  // bumps per lane and round
+    const uint32_t lim = (static_cast<uint32_t>(a.W) * BITS / 8u) << 5;  // first pad code
     for (int c0 = 0; c0 < totalP; c0 += CT_CHUNK) {
         const int nsl = min(CT_CHUNK, totalP - c0);
         // this thread's slice
@@ -821,9 +862,8 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
             while (L.pP[j + 1] <= g) j++;
             const int cell = cq[static_cast<int64_t>(j) * a.K + (g - L.pP[j])];
             const int64_t b = (static_cast<int64_t>(j) * a.K + cell) * (a.T + 1) + t;
-            const uint32_t lo = a.off2d[b];
-            len = a.off2d[b + 1] - lo;
-            st = static_cast<uint32_t>(j) * static_cast<uint32_t>(a.n) + lo;
+            st = a.off2d[b];
+            len = a.off2d[b + 1] - st;
         }
         // compacted index and first position of each non-empty slice
         const uint32_t ne = len > 0u ? 1u : 0u;
@@ -861,20 +901,20 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
             // rounds whose windows all lie in [0, nfull): software-pipelined,
             // the next round's ids are in flight during this round's increments
             uint32_t w0 = static_cast<uint32_t>(wave);
-            uint32_t id[CT_UNROLL];
+            uint4 id[CT_UNROLL];
             bool have = w0 + SPAN < nfull;
             if (have) walk_load<false>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
             while (have) {
                 const uint32_t wn = w0 + STRIDE;
                 const bool nhave = wn + SPAN < nfull;
-                uint32_t nid[CT_UNROLL];
+                uint4 nid[CT_UNROLL];
                 if (nhave) walk_load<false>(a, L, seg, seg_end, nwin, tne, wn, lane, nid);
-                if (TR && held > 255 - CT_UNROLL) {
+                if (TR && held > 255 - PER_ROUND) {
                     trans_flush<HI>(tr, hsum, lane);
                     held = 0;
                 }
-                held += CT_UNROLL;
-                walk_bump<BITS, HI, false, TR>(L, id, tr);
+                held += PER_ROUND;
+                walk_bump<BITS, HI, false, TR>(L, id, lim, tr);
 #pragma unroll
                 for (int u = 0; u < CT_UNROLL; u++) id[u] = nid[u];
                 w0 = wn;
@@ -882,13 +922,13 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
             }
             // the segment's last round(s), bounds-tested
             for (; w0 < nwin; w0 += STRIDE) {
-                if (TR && held > 255 - CT_UNROLL) {
+                if (TR && held > 255 - PER_ROUND) {
                     trans_flush<HI>(tr, hsum, lane);
                     held = 0;
                 }
-                held += CT_UNROLL;
+                held += PER_ROUND;
                 walk_load<true>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
-                walk_bump<BITS, HI, true, TR>(L, id, tr);
+                walk_bump<BITS, HI, true, TR>(L, id, lim, tr);
             }
             __syncthreads();
         }
@@ -2376,8 +2416,10 @@ hipError_t launch_build_off2d(const uint32_t *ids, const uint32_t *offs, int Ns,
     return hipGetLastError();
 }
 
-hipError_t launch_encode_ids(const uint32_t *ids, int64_t count, int W, int bits, uint32_t *enc, hipStream_t st) {
-    k_encode_ids<<<static_cast<unsigned>((count + 255) / 256), 256, 0, st>>>(ids, count, W, bits, enc);
+hipError_t launch_encode_ids(const uint32_t *ids, const uint32_t *raw, const uint32_t *pad, int Ns, int K, int T,
+                             int64_t n, int W, int bits, uint32_t *enc, hipStream_t st) {
+    const int64_t slices = static_cast<int64_t>(Ns) * K * T;
+    k_encode_ids<<<static_cast<unsigned>((slices + 3) / 4), 256, 0, st>>>(ids, raw, pad, Ns, K, T, n, W, bits, enc);
     return hipGetLastError();
 }
 

@@ -97,7 +97,8 @@ struct tc_index {
     // index on the device
     float *mean = nullptr, *B = nullptr, *C1 = nullptr, *C2 = nullptr, *base = nullptr;
     uint32_t *offs = nullptr, *ids = nullptr, *off2d = nullptr;
-    uint32_t *ids_enc = nullptr;  // [Ns][n] ids encoded for the current tile width
+    uint32_t *ids_enc = nullptr;  // id lists in padded 4-id groups, encoded for the tile width
+    size_t ids_enc_cap = 0;       // elements allocated for ids_enc
     int W = 65536, T = 1;
     int bits = 8;  // packed-count width: 4 when Ns <= 15, else 8
     int max_lds = 65536;
@@ -287,18 +288,60 @@ int alloc_scratch(tc_index *x) {
     return TC_OK;
 }
 
+// Tiling for the tile width W: the start of every (subspace, cell, tile)
+// slice of the id lists, then the padded lists the count walk reads, each
+// slice rounded up to whole 4-id groups.
 int build_tiles(tc_index *x) {
     x->T = static_cast<int>((x->n + x->W - 1) / x->W);
     (void)hipFree(x->off2d);
     x->off2d = nullptr;
-    int rc = dmalloc(&x->off2d, size_t(x->Ns) * x->K * (x->T + 1), "tile offsets");
+    const size_t entries = size_t(x->Ns) * x->K * (x->T + 1);
+    uint32_t *raw = nullptr;
+    int rc = dmalloc(&raw, entries, "tile offsets");
     if (rc) return rc;
-    TC_HIP(taco::launch_build_off2d(x->ids, x->offs, x->Ns, x->K, x->n, x->T, x->W, x->off2d,
-                                    nullptr),
-           "building tile offsets");
-    if (!x->ids_enc && (rc = dmalloc(&x->ids_enc, size_t(x->Ns) * x->n, "encoded id lists"))) return rc;
-    TC_HIP(taco::launch_encode_ids(x->ids, int64_t(x->Ns) * x->n, x->W, x->bits, x->ids_enc, nullptr),
-           "encoding the id lists");
+    std::vector<uint32_t> h(entries);
+    hipError_t e = taco::launch_build_off2d(x->ids, x->offs, x->Ns, x->K, x->n, x->T, x->W, raw, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(h.data(), raw, entries * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        (void)hipFree(raw);
+        return fail(TC_EDEVICE, std::string("building tile offsets: ") + hipGetErrorString(e));
+    }
+    // group offsets, slice after slice in (subspace, cell, tile) order
+    uint64_t groups = 0;
+    for (size_t c = 0; c < entries; c += size_t(x->T) + 1) {
+        for (int t = 0; t < x->T; t++) {
+            const uint32_t len = h[c + t + 1] - h[c + t];
+            h[c + t] = static_cast<uint32_t>(groups);
+            groups += (len + 3u) / 4u;
+        }
+        h[c + x->T] = static_cast<uint32_t>(groups);
+    }
+    const size_t padded = size_t(groups) * 4;
+    if (padded >= (size_t(1) << 30)) {
+        (void)hipFree(raw);
+        return fail(TC_EINVAL, "the padded id lists exceed 2^30 entries");
+    }
+    if ((rc = dmalloc(&x->off2d, entries, "tile offsets"))) {
+        (void)hipFree(raw);
+        return rc;
+    }
+    if (x->ids_enc_cap < padded) {
+        (void)hipFree(x->ids_enc);
+        x->ids_enc = nullptr;
+        x->ids_enc_cap = 0;
+        if ((rc = dmalloc(&x->ids_enc, padded, "encoded id lists"))) {
+            (void)hipFree(raw);
+            return rc;
+        }
+        x->ids_enc_cap = padded;
+    }
+    e = hipMemcpy(x->off2d, h.data(), entries * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = taco::launch_encode_ids(x->ids, raw, x->off2d, x->Ns, x->K, x->T, x->n, x->W, x->bits, x->ids_enc,
+                                    nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipFree(raw);
+    if (e != hipSuccess) return fail(TC_EDEVICE, std::string("encoding the id lists: ") + hipGetErrorString(e));
     TC_HIP(taco::prepare_count_kernels(x->W, x->bits, x->Ns), "setting LDS size of the count kernels");
     TC_HIP(hipDeviceSynchronize(), "building tile offsets");
     // How many groups of T co-resident workgroups the fused kernel can keep.
