@@ -834,15 +834,14 @@ __device__ __forceinline__ void walk_bump(const CountLds &L, const uint4 (&id)[C
 // before; complete after the caller's next barrier).
 template <int BITS, bool HI, bool TR = true>
 __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, uint32_t *hsum) {
-    const int words = a.W / (32 / BITS);
-    for (int i = threadIdx.x; i < words; i += CT_BLOCK) L.cnt[i] = 0u;
-    if (threadIdx.x == 0) {
-        int acc = 0;
-        L.pP[0] = 0;
-        for (int j = 0; j < a.Ns; j++) {
-            acc += a.ncells[static_cast<int64_t>(q) * a.Ns + j];
-            L.pP[j + 1] = acc;
-        }
+    const int vec = a.W * BITS / 128;  // 16-byte words of counts
+    for (int i = threadIdx.x; i < vec; i += CT_BLOCK) reinterpret_cast<uint4 *>(L.cnt)[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (threadIdx.x < WAVE) {
+        // the subspaces' cell counts in one load per lane, then a prefix sum
+        const int j = static_cast<int>(threadIdx.x);
+        const uint32_t v = j < a.Ns ? static_cast<uint32_t>(a.ncells[static_cast<int64_t>(q) * a.Ns + j]) : 0u;
+        const uint32_t inc = wave_incl_scan_u32(v, j);
+        if (j <= a.Ns) L.pP[j] = static_cast<int32_t>(inc - v);
     }
     __syncthreads();
     const int totalP = L.pP[a.Ns];
