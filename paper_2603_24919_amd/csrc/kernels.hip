@@ -2261,6 +2261,18 @@ __device__ __forceinline__ void topk_select(int q, const int32_t *__restrict__ c
     // select; at least k after the bound) and keep the first k
     const int ns = static_cast<int>(min<uint32_t>(nsel, static_cast<uint32_t>(TOPK_MAX)));
     const int m = min(ns, k);
+    if (ns <= WAVE && k_max <= WAVE) {
+        // one wavefront sorts them in registers (no workgroup barriers)
+        if (wave == 0) {
+            const uint64_t v = wave_sort_u64(lane < ns ? sel[lane] : ~0ull, lane);
+            if (lane < k_max) {
+                const int64_t o = static_cast<int64_t>(q) * k_max + lane;
+                ids_out[o] = lane < m ? static_cast<int64_t>(static_cast<uint32_t>(v & 0xffffffffu)) : -1;
+                d_out[o] = lane < m ? __uint_as_float(static_cast<uint32_t>(v >> 32)) : __uint_as_float(0x7f800000u);
+            }
+        }
+        return;
+    }
     int P = 1;
     while (P < ns) P <<= 1;
     for (int i = ns + threadIdx.x; i < P; i += BLOCK) sel[i] = ~0ull;
