@@ -486,6 +486,13 @@ def main():
     results = {}
     for pname in paths:
         idx = taco.Index(path, 0)
+        if pname in ("tuned", "lowp"):
+            # one batch per step when the GPU has room: candidate scratch is sized for the
+            # worst case (every point a candidate), ~12.5 MB per query at 1M points, so a
+            # 10k-query batch takes ~125 GB of the 288 GB; at most 60% of what is free
+            free, _ = torch.cuda.mem_get_info(dev)
+            idx.set_option(taco.TC_OPT_SCRATCH_BYTES, int(free * 0.6))
+            idx.set_option(taco.TC_OPT_MAX_BATCH, w.nq)
         sweep = []
         for a in alphas:
             tuned = None
