@@ -83,6 +83,26 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(wave_incl_scan_u32(v, 0)), WAVE - 1));
 }
 
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint32_t>(v)), m, WAVE));
+    const uint32_t hi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint32_t>(v >> 32)), m, WAVE));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Ascending bitonic sort of one value per lane across the wavefront.
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v, int lane) {
+#pragma unroll
+    for (int size = 2; size <= WAVE; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint64_t o = shfl_xor_u64(v, stride);
+            const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
+            v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+        }
+    }
+    return v;
+}
+
 __device__ __forceinline__ uint64_t lanes_below(int lane) {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
@@ -409,8 +429,9 @@ __global__ __launch_bounds__(256) void k_cdist_mfma(const float *__restrict__ qt
 
 // ---------------------------------------------------------------------------
 // probe: one wavefront per (query, subspace).  Lane c computes the squared
-// distance of each half of q' to centroid c, ranks them (stable: ties keep
-// the lower centroid id first), then runs a tournament over the l rows of
+// distance of each half of q' to centroid c, sorts them across the
+// wavefront (stable: ties keep the lower centroid id first), then runs a
+// tournament over the l rows of
 // the cell grid: lane r holds row r's next unprobed column and its key
 // fl32(D1s[r] + D2s[col]); each step takes the lexicographic minimum of
 // (key, row) across the wavefront.  Rows are non-decreasing along columns,
@@ -430,9 +451,6 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
     int32_t *__restrict__ cells, int32_t *__restrict__ ncells, int64_t *__restrict__ retrieved,
     float *__restrict__ dump_cdist, int32_t *__restrict__ dump_corder, const float *__restrict__ pre) {
     extern __shared__ uint32_t sizes[];  // [K]
-    __shared__ float rawD[QPW][2][WAVE];
-    __shared__ float sortD[QPW][2][WAVE];
-    __shared__ int32_t order[QPW][2][WAVE];
 
     const int j = blockIdx.y, Ns = gridDim.y;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -463,8 +481,6 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
         const int64_t qj0 = static_cast<int64_t>(q) * Ns + j;
         d1 = pre[(qj0 * 2 + 0) * l + lane];
         d2 = pre[(qj0 * 2 + 1) * l + lane];
-        rawD[wave][0][lane] = d1;
-        rawD[wave][1][lane] = d2;
     } else if (lane < l) {
         // loads of 8 terms are issued together; the sums keep the ascending
         // one-fma-per-term order
@@ -500,28 +516,20 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
                 }
             }
         }
-        rawD[wave][0][lane] = d1;
-        rawD[wave][1][lane] = d2;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < l) {
-        int r1 = 0, r2 = 0;
-#pragma unroll 8
-        for (int c = 0; c < l; c++) {
-            float a = rawD[wave][0][c], b = rawD[wave][1][c];
-            r1 += (a < d1) || (a == d1 && c < lane);
-            r2 += (b < d2) || (b == d2 && c < lane);
-        }
-        order[wave][0][r1] = lane;
-        order[wave][1][r2] = lane;
-        sortD[wave][0][r1] = d1;
-        sortD[wave][1][r2] = d2;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // Stable ascending order of each half: a wavefront sort of (distance
+    // bits, centroid) keys; distances are >= 0 (adding +0 turns a -0 into
+    // +0), so the bits order like the values and equal distances keep the
+    // lower centroid first.  Lane r then holds the rank-r distance and its
+    // centroid.
+    const uint64_t s1 = wave_sort_u64(lane < l ? (static_cast<uint64_t>(__float_as_uint(d1 + 0.0f)) << 32) |
+                                                     static_cast<uint32_t>(lane)
+                                               : ~0ull,
+                                      lane);
+    const uint64_t s2 = wave_sort_u64(lane < l ? (static_cast<uint64_t>(__float_as_uint(d2 + 0.0f)) << 32) |
+                                                     static_cast<uint32_t>(lane)
+                                               : ~0ull,
+                                      lane);
 
     const int64_t qj = static_cast<int64_t>(q) * Ns + j;
     if (dump_cdist && lane < l) {
@@ -529,8 +537,8 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
         dump_cdist[(qj * 2 + 1) * l + lane] = d2;
     }
     if (dump_corder && lane < l) {
-        dump_corder[(qj * 2 + 0) * l + lane] = order[wave][0][lane];
-        dump_corder[(qj * 2 + 1) * l + lane] = order[wave][1][lane];
+        dump_corder[(qj * 2 + 0) * l + lane] = static_cast<int32_t>(static_cast<uint32_t>(s1));
+        dump_corder[(qj * 2 + 1) * l + lane] = static_cast<int32_t>(static_cast<uint32_t>(s2));
     }
 
     // Tournament: lane r holds row r (half-1 rank r) with its next column and
@@ -541,10 +549,10 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
     // lane) and scanned for the step that reaches the budget A.  Steps past
     // it are discarded.
     constexpr int PB = 16;
-    const float my_d1 = lane < l ? sortD[wave][0][lane] : 0.0f;
-    const float my_d2 = lane < l ? sortD[wave][1][lane] : 0.0f;
-    const int my_o1 = lane < l ? order[wave][0][lane] : 0;
-    const int my_o2 = lane < l ? order[wave][1][lane] : 0;
+    const float my_d1 = lane < l ? __uint_as_float(static_cast<uint32_t>(s1 >> 32)) : 0.0f;
+    const float my_d2 = lane < l ? __uint_as_float(static_cast<uint32_t>(s2 >> 32)) : 0.0f;
+    const int my_o1 = lane < l ? static_cast<int>(static_cast<uint32_t>(s1)) : 0;
+    const int my_o2 = lane < l ? static_cast<int>(static_cast<uint32_t>(s2)) : 0;
     const float d2_0 = __uint_as_float(static_cast<uint32_t>(
         __builtin_amdgcn_readlane(static_cast<int>(__float_as_uint(my_d2)), 0)));
     int col = 0;
@@ -2118,26 +2126,6 @@ __device__ __forceinline__ void for_keys(bool reg, const uint64_t (&kr)[TK_KPT],
                 if (i0 + u * BLOCK < nc) f(kk[u]);
         }
     }
-}
-
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-    const uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint32_t>(v)), m, WAVE));
-    const uint32_t hi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint32_t>(v >> 32)), m, WAVE));
-    return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
-// Ascending bitonic sort of one value per lane across the wavefront.
-__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t v, int lane) {
-#pragma unroll
-    for (int size = 2; size <= WAVE; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const uint64_t o = shfl_xor_u64(v, stride);
-            const bool keep_min = ((lane & stride) == 0) == ((lane & size) == 0);
-            v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
-        }
-    }
-    return v;
 }
 
 // The k smallest of the nc keys (dq[i] bits << 32 | cq[i]) of query q, by
