@@ -12,7 +12,8 @@ struct CountLaunch {
     const uint32_t *ids;    // the id lists in 4-id groups, every (subspace, cell, tile)
                             // slice padded to whole groups, encoded for the tile width
                             // by launch_encode_ids
-    const uint32_t *off2d;  // [Ns][K][T+1] first group of each tile's slice of each cell
+    const uint32_t *off2d;  // [Ns][K][T][2] first and end group of each tile's slice of each
+                            // cell; slices are laid out tile by tile
     const int32_t *cells;   // [nq][Ns][K] probed cells
     const int32_t *ncells;  // [nq][Ns]
 };
@@ -57,8 +58,8 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t s
 hipError_t launch_u32_to_i64(const uint32_t *src, int64_t *dst, int64_t count, hipStream_t st);
 hipError_t launch_build_off2d(const uint32_t *ids, const uint32_t *offs, int Ns, int K, int64_t n,
                               int T, int W, uint32_t *off2d, hipStream_t st);
-// raw: [Ns][K][T+1] slice starts in ids[j] (launch_build_off2d); pad: the
-// same in groups of the padded lists enc (pad[.. + T] ends the cell).
+// raw: [Ns][K][T+1] slice starts in ids[j] (launch_build_off2d); pad:
+// [Ns][K][T][2] first and end group of each slice in the padded lists enc.
 hipError_t launch_encode_ids(const uint32_t *ids, const uint32_t *raw, const uint32_t *pad, int Ns, int K, int T,
                              int64_t n, int W, int bits, uint32_t *enc, hipStream_t st);
 hipError_t launch_transform(const float *Q, int nq, int d, const float *mean, const float *B,

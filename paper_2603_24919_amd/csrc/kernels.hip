@@ -169,11 +169,13 @@ __global__ void k_build_off2d(const uint32_t *ids, const uint32_t *offs, int Ns,
 
 // The id lists as the count walk reads them for tile width W.  Every slice
 // (subspace j, cell c, tile t) of the lists is laid out on its own, padded
-// to a whole number of 4-id groups: group offsets pad[(j*K + c)*(T+1) + t]
-// (pad[.. + T] ends the cell), taken from the unpadded positions raw[] of
-// k_build_off2d.  An id's tile-local position loc = id mod W becomes (byte
-// offset of its packed word) << 5 | (its bit position in the word), so an
-// increment needs no index arithmetic; a pad becomes a word of the
+// to a whole number of 4-id groups: its first and end group are
+// pad[((j*K + c)*T + t)*2 + {0, 1}] (the host lays the slices out tile by
+// tile), its ids those of the unpadded positions raw[(j*K + c)*(T+1) + t]
+// up to [.. + t + 1] of k_build_off2d.  An id's tile-local position
+// loc = id mod W becomes (byte offset of its packed word) << 5 | (its bit
+// position in the word), so an increment needs no index arithmetic; a pad
+// becomes a word of the
 // CT_DUMMY-word region that follows the W*bits/8 bytes of counts, spread
 // over its words by position.  Offsets stay below 2^17 (the LDS), so codes
 // stay below 2^22 and never collide with the walk's 0xffffffff "no id".
@@ -187,9 +189,9 @@ __global__ void k_encode_ids(const uint32_t *__restrict__ ids, const uint32_t *_
     const uint32_t lane = threadIdx.x % WAVE;
     const int64_t jc = sl / T;
     const int t = static_cast<int>(sl % T), j = static_cast<int>(jc / K);
-    const int64_t b = jc * (T + 1) + t;
+    const int64_t b = jc * (T + 1) + t, bp = (jc * T + t) * 2;
     const uint32_t lo = raw[b], len = raw[b + 1] - lo;
-    const uint32_t g0 = pad[b], m = (pad[b + 1] - g0) * 4u;
+    const uint32_t g0 = pad[bp], m = (pad[bp + 1] - g0) * 4u;
     const uint32_t *src = ids + static_cast<int64_t>(j) * n + lo;
     uint32_t *dst = enc + static_cast<int64_t>(g0) * 4;
     const uint32_t per = 32u / static_cast<uint32_t>(bits);
@@ -637,7 +639,7 @@ struct CountArgs {
     int Ns, K, T, W;
     int64_t n;
     const uint32_t *ids;     // padded 4-id groups encoded for the tile width (see k_encode_ids)
-    const uint32_t *off2d;   // [Ns][K][T+1] group offsets of the slices in ids
+    const uint32_t *off2d;   // [Ns][K][T][2] first and end group of each slice in ids
     const int32_t *cells;    // [nq][Ns][K]
     const int32_t *ncells;   // [nq][Ns]
 };
@@ -868,9 +870,9 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
             int j = 0;
             while (L.pP[j + 1] <= g) j++;
             const int cell = cq[static_cast<int64_t>(j) * a.K + (g - L.pP[j])];
-            const int64_t b = (static_cast<int64_t>(j) * a.K + cell) * (a.T + 1) + t;
-            st = a.off2d[b];
-            len = a.off2d[b + 1] - st;
+            const uint2 se = reinterpret_cast<const uint2 *>(a.off2d)[(static_cast<int64_t>(j) * a.K + cell) * a.T + t];
+            st = se.x;
+            len = se.y - se.x;
         }
         // compacted index and first position of each non-empty slice
         const uint32_t ne = len > 0u ? 1u : 0u;

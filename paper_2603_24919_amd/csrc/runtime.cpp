@@ -306,22 +306,28 @@ int build_tiles(tc_index *x) {
         (void)hipFree(raw);
         return fail(TC_EDEVICE, std::string("building tile offsets: ") + hipGetErrorString(e));
     }
-    // group offsets, slice after slice in (subspace, cell, tile) order
+    // (first, end) group of every slice, laid out tile by tile: the
+    // workgroups of one tile, which the grid places on one XCD, then read
+    // one contiguous part of the lists
+    const size_t slices = size_t(x->Ns) * x->K;
+    std::vector<uint32_t> pr(slices * x->T * 2);
     uint64_t groups = 0;
-    for (size_t c = 0; c < entries; c += size_t(x->T) + 1) {
-        for (int t = 0; t < x->T; t++) {
+    for (int t = 0; t < x->T; t++) {
+        for (size_t jc = 0; jc < slices; jc++) {
+            const size_t c = jc * (size_t(x->T) + 1);
             const uint32_t len = h[c + t + 1] - h[c + t];
-            h[c + t] = static_cast<uint32_t>(groups);
+            const size_t e = (jc * x->T + t) * 2;
+            pr[e] = static_cast<uint32_t>(groups);
             groups += (len + 3u) / 4u;
+            pr[e + 1] = static_cast<uint32_t>(groups);
         }
-        h[c + x->T] = static_cast<uint32_t>(groups);
     }
     const size_t padded = size_t(groups) * 4;
     if (padded >= (size_t(1) << 30)) {
         (void)hipFree(raw);
         return fail(TC_EINVAL, "the padded id lists exceed 2^30 entries");
     }
-    if ((rc = dmalloc(&x->off2d, entries, "tile offsets"))) {
+    if ((rc = dmalloc(&x->off2d, pr.size(), "tile offsets"))) {
         (void)hipFree(raw);
         return rc;
     }
@@ -335,7 +341,7 @@ int build_tiles(tc_index *x) {
         }
         x->ids_enc_cap = padded;
     }
-    e = hipMemcpy(x->off2d, h.data(), entries * sizeof(uint32_t), hipMemcpyHostToDevice);
+    e = hipMemcpy(x->off2d, pr.data(), pr.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = taco::launch_encode_ids(x->ids, raw, x->off2d, x->Ns, x->K, x->T, x->n, x->W, x->bits, x->ids_enc,
                                     nullptr);
