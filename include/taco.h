@@ -80,7 +80,8 @@ enum tc_option {
                                caller's stream while the call's pointers, sizes,
                                budgets and options stay the same; 0: off (default).
                                Calls with stage dumps never use the graph.          */
-    TC_OPT_PROBE_QPW = 9,   /* queries (wavefronts) per probe workgroup: 1,2,4,8; 4 */
+    TC_OPT_PROBE_QPW = 9,   /* queries (wavefronts) per probe workgroup: 1, 2, 4, 8
+                               or 16; default 4                                      */
     TC_OPT_RERANK_BLOCKS = 10, /* re-rank workgroups per query, [1, 1024]; default 32 */
     TC_OPT_CDIST_PRECISION = 11, /* tc_cdist_precision of the half-subspace centroid
                                distances that order the probe; default TC_CDIST_FP32 */

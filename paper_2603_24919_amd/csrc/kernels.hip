@@ -2445,6 +2445,7 @@ hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, i
     case 1: TACO_PROBE(1); break;
     case 2: TACO_PROBE(2); break;
     case 8: TACO_PROBE(8); break;
+    case 16: TACO_PROBE(16); break;
     default: TACO_PROBE(4); break;
     }
 #undef TACO_PROBE

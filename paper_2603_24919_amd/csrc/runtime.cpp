@@ -1017,8 +1017,8 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
         if (!x->use_graph) drop_graph(x);
         return TC_OK;
     case TC_OPT_PROBE_QPW:
-        if (value != 1 && value != 2 && value != 4 && value != 8)
-            return fail(TC_EINVAL, "queries per probe workgroup must be 1, 2, 4 or 8");
+        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+            return fail(TC_EINVAL, "queries per probe workgroup must be 1, 2, 4, 8 or 16");
         x->probe_qpw = static_cast<int>(value);
         return TC_OK;
     case TC_OPT_RERANK_BLOCKS:
@@ -1215,7 +1215,7 @@ int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double
             if (ms < best_ms) best_ms = ms, best = c;
         }
     }
-    for (int qpw : {1, 2, 4, 8}) {
+    for (int qpw : {1, 2, 4, 8, 16}) {
         TuneConfig c = best;
         c.qpw = qpw;
         double ms;

@@ -251,6 +251,18 @@ def test_count_modes_all_stages(taco_mod, tiny, mode):
                  options=opts)
 
 
+@pytest.mark.parametrize("qpw", [1, 2, 8, 16])
+def test_probe_widths_all_stages(taco_mod, tiny, qpw):
+    """Every probe workgroup width (queries per workgroup) matches the oracle
+    stage by stage, also when the batch leaves the last workgroup partly
+    empty."""
+    t = taco_mod
+    print(f"[tiny] probe queries per workgroup {qpw}", flush=True)
+    for opts in (((t.TC_OPT_PROBE_QPW, qpw),), ((t.TC_OPT_PROBE_QPW, qpw), (t.TC_OPT_MAX_BATCH, 13))):
+        _run_all(t, tiny["path"], tiny["oidx"], tiny["Q"], 10, 0.05, 0.005, 0, f"tiny qpw {qpw}",
+                 options=opts)
+
+
 @pytest.mark.parametrize("level", [1, 2, 3, 4, 8])
 def test_list_levels_all_stages(taco_mod, tiny, level):
     """Every fixed list level matches the oracle stage by stage: queries whose
