@@ -52,6 +52,9 @@ struct ListLaunch {
     bool trans;         // the list launch also adds every level count (stage dumps)
     int32_t *dump_last;
     int64_t *dump_hist;
+    uint32_t *toff;     // [nq][T+1] first candidate slot of each tile (candidates grouped by
+                        // tile), [q][0] = 0xffffffff when query q's are not; or null
+    uint32_t *tlev;     // [nq][T][Ns+1] listed ids per tile and level; or null (then no toff)
 };
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t count, uint32_t v, hipStream_t st);
@@ -106,9 +109,11 @@ hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const
 // integer rows within 255); plain: every record is (0, 1, 0) and none is read.
 // exact[q] (optional) is set when both bounds are the FP32 distance.
 // qinfo (optional, from launch_qbytes): per-query integrality, |q|^2 and bytes
+// toff: [nq][T+1] candidates grouped by tile (k_list_select), or null
 hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, const float4 *meta, bool plain,
                           const int32_t *cand, const uint32_t *cand_count, int64_t cap, float *ub, float *lb,
-                          uint32_t *exact, const uint32_t *qinfo, int blocks_per_q, hipStream_t st);
+                          uint32_t *exact, const uint32_t *qinfo, const uint32_t *toff, int T, int blocks_per_q,
+                          hipStream_t st);
 // [nq][d/4 + 4]: the values as bytes, an integer-in-[0,255] flag, |q|^2 (16 | d <= 256)
 hipError_t launch_qbytes(const float *Q, int nq, int d, uint32_t *info, hipStream_t st);
 hipError_t launch_prep_u8(const float *base, int64_t n, int d, uint8_t *base8, float4 *meta, uint32_t *plain,

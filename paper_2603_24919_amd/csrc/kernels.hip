@@ -1086,6 +1086,9 @@ struct ListArgs {
     int redo_hist;      // the recount adds the queued queries' level counts
     int32_t *dump_last; // [nq] or null
     int64_t *dump_hist; // [nq][Ns+1] or null
+    uint32_t *toff;     // [nq][T+1] first candidate of each tile, or null (see k_list_select)
+    uint32_t *tlev;     // [nq][T][Ns+1] listed ids per tile and level (levels >= the list
+                        // level; 0 below), or null
 };
 
 __device__ __forceinline__ uint32_t list_level(const ListArgs &la) {
@@ -1226,11 +1229,13 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
         }
         if (MODE == CT_LIST) {
             list_tile<BITS, HI>(la, L.cnt, L.wsum, lsum, vec, q, t, a.W, list_level(la), threadIdx.x / WAVE, lane);
-            if (!TR) {
+            __syncthreads();
+            if (threadIdx.x <= static_cast<unsigned>(a.Ns)) {
+                const uint32_t c = lsum[threadIdx.x];
+                if (la.tlev) la.tlev[(static_cast<int64_t>(q) * a.T + t) * (a.Ns + 1) + threadIdx.x] = c;
                 // levels >= the list level: the listed ids are all of them
-                __syncthreads();
-                if (threadIdx.x >= 1 && threadIdx.x <= a.Ns && lsum[threadIdx.x])
-                    atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], lsum[threadIdx.x]);
+                if (!TR && threadIdx.x >= 1 && c)
+                    atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], c);
             }
         }
         if (MODE == CT_REDO) __syncthreads();
@@ -1340,18 +1345,30 @@ __device__ __forceinline__ void select_query(const SelectArgs &sa, int Ns, int64
 // queue (last < list level; with redo_hist its histogram row is cleared for
 // the recount) or the candidates: the listed ids with count >= last, moved
 // from the tiles' list ranges to the candidate slots.  Each wavefront takes
-// whole tiles; the order of candidates is free, so a wavefront reserves its
-// slots with one LDS add per 256 entries.  grid nq, block LS_BLOCK.
+// whole tiles.  With toff and tlev (and at most LS_TMAX tiles) the
+// candidates are grouped by tile, in list order inside a tile: each tile's
+// count is the sum of its listed ids' levels >= last (tlev, from the count
+// kernel), and toff[q][t] receives the first slot of tile t
+// (toff[q][T] = their number), so the re-rank can hand all candidates of a
+// tile, i.e. of one id range, to workgroups on one XCD.  Without toff, or
+// with more tiles, a wavefront reserves its slots with one LDS add per 256
+// entries and toff[q][0] (if given) is TOFF_NONE, as for a queued query.
+// grid nq, block LS_BLOCK.
 constexpr int LS_BLOCK = 256;
 constexpr int LS_UNROLL = 4;
+constexpr int LS_TMAX = 128;
+constexpr uint32_t TOFF_NONE = 0xffffffffu;
 
 __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t *__restrict__ hist, int Ns,
                                                           int64_t n) {
     __shared__ int s_last;
     __shared__ uint32_t s_out;
+    __shared__ uint32_t s_tc[LS_TMAX + 1];
     const int q = blockIdx.x;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int lv = static_cast<int>(list_level(la));
+    const bool grouped = la.toff != nullptr && la.tlev != nullptr && la.T <= LS_TMAX;
+    uint32_t *tq = la.toff ? la.toff + static_cast<int64_t>(q) * (la.T + 1) : nullptr;
     uint32_t *h = hist + static_cast<int64_t>(q) * (Ns + 1);
     if (threadIdx.x == 0) {
         int last = Ns;
@@ -1367,6 +1384,7 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
             // stage dumps: the histogram is complete here; the threshold is
             // the full scan's (equal to last whenever last >= lv)
             dump_threshold(la.dump_last, la.dump_hist, q, Ns, n, h, select_threshold(h, Ns, n, la.R, la.rule));
+        if (tq && (last < lv || !grouped)) tq[0] = TOFF_NONE;
         if (last < lv) {
             const uint32_t f = atomicAdd(&la.redo[0], 1u);
             la.redo[2 + f] = static_cast<uint32_t>(q);
@@ -1386,6 +1404,53 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
     int32_t *cq = la.cand + static_cast<int64_t>(q) * la.cap;
     const uint32_t idmask = (1u << la.shift) - 1u, lu = static_cast<uint32_t>(last);
     const uint64_t below = lanes_below(lane);
+    if (grouped) {
+        // candidates per tile: its listed ids at levels >= last
+        for (int t = threadIdx.x; t < la.T; t += LS_BLOCK) {
+            const uint32_t *lt = la.tlev + (static_cast<int64_t>(q) * la.T + t) * (Ns + 1);
+            uint32_t c = 0u;
+#pragma unroll
+            for (int v = 1; v <= 16; v++)
+                if (v >= last && v <= Ns) c += lt[v];
+            s_tc[t] = c;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t acc = 0u;
+            for (int t = 0; t < la.T; t++) {
+                const uint32_t c = s_tc[t];
+                s_tc[t] = acc;
+                tq[t] = acc;
+                acc += c;
+            }
+            tq[la.T] = acc;
+            s_out = acc;
+        }
+        __syncthreads();
+        // pass 2: each tile's candidates from its first slot, in list order
+        for (int t = wave; t < la.T; t += LS_BLOCK / WAVE) {
+            const uint32_t nt = la.tcount[static_cast<int64_t>(q) * la.T + t];
+            const uint32_t *et = ls + static_cast<int64_t>(t) * la.W;
+            uint32_t base = s_tc[t];
+            for (uint32_t b0 = 0; b0 < nt; b0 += WAVE * LS_UNROLL) {
+                uint32_t v[LS_UNROLL];
+#pragma unroll
+                for (int u = 0; u < LS_UNROLL; u++) {
+                    const uint32_t i = b0 + u * WAVE + lane;
+                    v[u] = i < nt ? et[i] : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < LS_UNROLL; u++) {
+                    const uint64_t m = __ballot(v[u] != 0u && (v[u] >> la.shift) >= lu);
+                    if ((m >> lane) & 1u) cq[base + __popcll(m & below)] = static_cast<int32_t>(v[u] & idmask);
+                    base += static_cast<uint32_t>(__popcll(m));
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) la.count[q] = s_out;
+        return;
+    }
     for (int t = wave; t < la.T; t += LS_BLOCK / WAVE) {
         const uint32_t nt = la.tcount[static_cast<int64_t>(q) * la.T + t];
         const uint32_t *et = ls + static_cast<int64_t>(t) * la.W;
@@ -1850,7 +1915,8 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
                                                  const uint32_t *__restrict__ cand_count,
                                                  int64_t cap, float *__restrict__ ub_out,
                                                  float *__restrict__ lb_out, uint32_t *__restrict__ exact,
-                                                 const uint32_t *__restrict__ qinfo) {
+                                                 const uint32_t *__restrict__ qinfo,
+                                                 const uint32_t *__restrict__ toff, int T) {
     extern __shared__ float qs[];
     __shared__ float rq_part[WAVES];
     const int q = blockIdx.y, chunk = blockIdx.x;
@@ -1866,13 +1932,14 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
     if (PLAIN && VEC16 && integral) {
         const int qq = static_cast<int>(info[d / 4 + 1]);
         const uint4 *qb4 = reinterpret_cast<const uint4 *>(info);
-        for (int64_t i0 = (static_cast<int64_t>(chunk) * WAVES + wave) * RPW; i0 < nc; i0 += stride * RU) {
+        // RU rows per lane group at slots i0 + u*step + sub below end
+        auto pass = [&](int64_t i0, int64_t step, int64_t end) {
             int64_t id[RU];
             int acc[RU];
 #pragma unroll
             for (int u = 0; u < RU; u++) {
-                const int64_t i = i0 + u * stride + sub;
-                id[u] = i < nc ? static_cast<int64_t>(cq[i]) : -1;
+                const int64_t i = i0 + u * step + sub;
+                id[u] = i < end ? static_cast<int64_t>(cq[i]) : -1;
                 acc[u] = 0;
             }
             for (int f = li; f < d / 16; f += LPR) {
@@ -1899,11 +1966,32 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
 #pragma unroll
             for (int u = 0; u < RU; u++) {
                 const int a = group_sum_i32<LPR>(acc[u]);
-                const int64_t i = i0 + u * stride + sub;
+                const int64_t i = i0 + u * step + sub;
                 // the lower bound is not needed: the re-check takes the bound
                 // top k as it is for a flagged query
-                if (li == 0 && i < nc) ub_out[static_cast<int64_t>(q) * cap + i] = static_cast<float>(qq + a);
+                if (li == 0 && i < end) ub_out[static_cast<int64_t>(q) * cap + i] = static_cast<float>(qq + a);
             }
+        };
+        const uint32_t *tq = toff ? toff + static_cast<int64_t>(q) * (T + 1) : nullptr;
+        if (tq && tq[0] != 0xffffffffu && gridDim.x % 8 == 0) {
+            // candidates grouped by tile (id range): workgroup chunk takes the
+            // tiles t = chunk (mod 8), each split between the gridDim.x / 8
+            // workgroups of that residue.  Workgroup (q, chunk) has linear id
+            // q*gridDim.x + chunk, and the dispatcher deals linear ids to the
+            // 8 XCDs in turn, so one XCD serves one id range of the rows (more
+            // hits in its L2).  Any placement gives the same results.
+            const int nparts = gridDim.x / 8, part = chunk / 8;
+            const int64_t lstride = static_cast<int64_t>(WAVES) * RPW;
+            for (int t = chunk % 8; t < T; t += 8) {
+                const int64_t a0 = tq[t], a1 = tq[t + 1];
+                const int64_t per = (a1 - a0 + nparts - 1) / nparts;
+                const int64_t r0 = a0 + per * part, r1 = min(a1, r0 + per);
+                for (int64_t i0 = r0 + static_cast<int64_t>(wave) * RPW; i0 < r1; i0 += lstride * RU)
+                    pass(i0, lstride, r1);
+            }
+        } else {
+            for (int64_t i0 = (static_cast<int64_t>(chunk) * WAVES + wave) * RPW; i0 < nc; i0 += stride * RU)
+                pass(i0, stride, nc);
         }
         return;
     }
@@ -2529,7 +2617,8 @@ static ListArgs list_args(const CountLaunch &c, const ListLaunch *l) {
     la.nq = c.nq;
     if (l)
         la = ListArgs{l->fixed, l->level, list_shift(c.Ns), c.nq, l->cap, l->list, l->cand, l->count, l->tcount,
-                      c.T, c.W, l->redo, l->R, l->rule, l->trans ? 0 : 1, l->dump_last, l->dump_hist};
+                      c.T, c.W, l->redo, l->R, l->rule, l->trans ? 0 : 1, l->dump_last, l->dump_hist,
+                      l->toff, l->tlev};
     return la;
 }
 
@@ -2683,17 +2772,18 @@ hipError_t launch_qbytes(const float *Q, int nq, int d, uint32_t *info, hipStrea
 
 hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, const float4 *meta, bool plain,
                           const int32_t *cand, const uint32_t *cand_count, int64_t cap, float *ub, float *lb,
-                          uint32_t *exact, const uint32_t *qinfo, int blocks_per_q, hipStream_t st) {
+                          uint32_t *exact, const uint32_t *qinfo, const uint32_t *toff, int T, int blocks_per_q,
+                          hipStream_t st) {
     dim3 grid(blocks_per_q, nq);
     size_t lds = sizeof(float) * static_cast<size_t>(d);
 #define TACO_RR8(L, V)                                                                                    \
     do {                                                                                                  \
         if (plain)                                                                                        \
             k_rerank8<L, V, true><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb, \
-                                                            exact, qinfo);                                    \
+                                                            exact, qinfo, toff, T);                           \
         else                                                                                              \
             k_rerank8<L, V, false><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb, \
-                                                             exact, qinfo);                                   \
+                                                             exact, qinfo, toff, T);                          \
     } while (0)
     if (d % 16 != 0) {
         TACO_RR8(64, false);

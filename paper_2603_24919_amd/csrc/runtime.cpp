@@ -136,6 +136,8 @@ struct tc_index {
     float *cand_dist = nullptr;
     uint32_t *sc = nullptr;  // packed collision counts, [Qb][T*W bytes]
     uint32_t *tcount = nullptr;  // [Qb][T] entries listed per tile (TC_COUNT_LIST)
+    uint32_t *toff = nullptr;    // [Qb][T+1] first candidate slot per tile (TC_COUNT_LIST)
+    uint32_t *tlev = nullptr;    // [Qb][T][Ns+1] listed ids per tile and level (TC_COUNT_LIST)
     // BF16 re-rank form (built when first selected)
     int precision = TC_FP32;
     float *mu = nullptr;         // [d] mean rounded to BF16
@@ -207,6 +209,10 @@ void free_scratch(tc_index *x) {
     x->lvl = nullptr;
     (void)hipFree(x->tcount);
     x->tcount = nullptr;
+    (void)hipFree(x->toff);
+    x->toff = nullptr;
+    (void)hipFree(x->tlev);
+    x->tlev = nullptr;
     x->qn = x->qsc = x->cd = nullptr;
     x->sc = nullptr;
     x->lb = nullptr;
@@ -262,6 +268,8 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->cand_count, size_t(2 * qb + 2), "candidate counts"))) return rc;
     if ((rc = dmalloc(&x->lvl, 1, "list level"))) return rc;
     if ((rc = dmalloc(&x->tcount, size_t(qb) * x->T, "per-tile list lengths"))) return rc;
+    if ((rc = dmalloc(&x->toff, size_t(qb) * (x->T + 1), "per-tile candidate offsets"))) return rc;
+    if ((rc = dmalloc(&x->tlev, size_t(qb) * x->T * (x->Ns + 1), "per-tile listed levels"))) return rc;
     {
         const uint32_t l0 = static_cast<uint32_t>(std::min(2, x->Ns));
         TC_HIP(hipMemcpy(x->lvl, &l0, sizeof(l0), hipMemcpyHostToDevice), "list level");
@@ -723,7 +731,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             // the lists sit in the distance slots, free until the re-rank
             const taco::ListLaunch ll{x->list_level, x->lvl, cap, reinterpret_cast<uint32_t *>(x->cand_dist),
                                       x->cand, x->cand_count, x->tcount, redo, 64, R, x->rule, dh,
-                                      sl.dump_last, sl.dump_hist};
+                                      sl.dump_last, sl.dump_hist, x->toff, x->tlev};
             record(x, K_COUNT, st, true);
             TC_HIP(taco::launch_count(cl, x->hist, dsc ? x->sc : nullptr, 1, &ll, st), "count kernel (list)");
             record(x, K_COUNT, st, false);
@@ -764,7 +772,8 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                 if (ex) TC_HIP(taco::launch_qbytes(Qb, nb, x->d, x->qinfo, st), "query bytes kernel");
                 TC_HIP(taco::launch_rerank8(Qb, nb, x->d, x->base8, x->rmeta, x->u8_plain, x->cand,
                                             x->cand_count, cap, x->cand_dist, x->lb, x->exact,
-                                            ex ? x->qinfo : nullptr, rr_blocks, st),
+                                            ex ? x->qinfo : nullptr, list ? x->toff : nullptr, x->T,
+                                            rr_blocks, st),
                        "8-bit rerank kernel");
             }
             record(x, K_RERANK, st, false);
