@@ -109,11 +109,15 @@ hipError_t launch_rerank16(const float *Q, int nq, int d, const float *mu, const
 // integer rows within 255); plain: every record is (0, 1, 0) and none is read.
 // exact[q] (optional) is set when both bounds are the FP32 distance.
 // qinfo (optional, from launch_qbytes): per-query integrality, |q|^2 and bytes
-// toff: [nq][T+1] candidates grouped by tile (k_list_select), or null
+// toff: [nq][T+1] candidates grouped by tile (k_list_select), or null;
+// perm: the order in which the queries are taken (launch_query_order), or null
 hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, const float4 *meta, bool plain,
                           const int32_t *cand, const uint32_t *cand_count, int64_t cap, float *ub, float *lb,
-                          uint32_t *exact, const uint32_t *qinfo, const uint32_t *toff, int T, int blocks_per_q,
-                          hipStream_t st);
+                          uint32_t *exact, const uint32_t *qinfo, const uint32_t *toff, int T,
+                          const int32_t *perm, int blocks_per_q, hipStream_t st);
+// perm[i] = the query of rank i when the batch is ordered by the first cell
+// probed in subspace 0 (cells: [nq][Ns][K]); K <= 4096
+hipError_t launch_query_order(const int32_t *cells, int nq, int Ns, int K, int32_t *perm, hipStream_t st);
 // [nq][d/4 + 4]: the values as bytes, an integer-in-[0,255] flag, |q|^2 (16 | d <= 256)
 hipError_t launch_qbytes(const float *Q, int nq, int d, uint32_t *info, hipStream_t st);
 hipError_t launch_prep_u8(const float *base, int64_t n, int d, uint8_t *base8, float4 *meta, uint32_t *plain,

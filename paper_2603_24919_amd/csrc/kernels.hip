@@ -600,6 +600,46 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 }
 
 // ---------------------------------------------------------------------------
+// Query order of a batch for the re-rank: one workgroup sorts the queries by
+// the first cell they probe in subspace 0 (their nearest cell there) with a
+// counting sort over the K cells.  Queries near each other probe the same
+// cells and share many candidates; run one after another, they find those
+// rows in L2.  Any order gives the same results.  perm[i] is the query of
+// rank i; dynamic LDS: K words (K <= 4096).
+// ---------------------------------------------------------------------------
+
+constexpr int ORD_BLOCK = 1024;
+
+__global__ __launch_bounds__(ORD_BLOCK) void k_query_order(const int32_t *__restrict__ cells, int nq, int Ns,
+                                                           int K, int32_t *__restrict__ perm) {
+    extern __shared__ uint32_t bins[];
+    __shared__ uint32_t wsum[ORD_BLOCK / WAVE];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    for (int i = threadIdx.x; i < K; i += ORD_BLOCK) bins[i] = 0u;
+    __syncthreads();
+    auto key = [&](int q) { return min(max(cells[static_cast<int64_t>(q) * Ns * K], 0), K - 1); };
+    for (int q = threadIdx.x; q < nq; q += ORD_BLOCK) atomicAdd(&bins[key(q)], 1u);
+    __syncthreads();
+    // exclusive prefix over the bins: a contiguous run of bins per thread
+    const int per = (K + ORD_BLOCK - 1) / ORD_BLOCK;
+    const int b0 = min(K, static_cast<int>(threadIdx.x) * per), b1 = min(K, b0 + per);
+    uint32_t sum = 0u;
+    for (int b = b0; b < b1; b++) sum += bins[b];
+    const uint32_t inc = wave_incl_scan_u32(sum, lane);
+    if (lane == WAVE - 1) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (int w = 0; w < wave; w++) run += wsum[w];
+    for (int b = b0; b < b1; b++) {
+        const uint32_t c = bins[b];
+        bins[b] = run;
+        run += c;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nq; q += ORD_BLOCK) perm[atomicAdd(&bins[key(q)], 1u)] = q;
+}
+
+// ---------------------------------------------------------------------------
 // count / select: workgroup (tile t, query q) owns ids [t*W, t*W + W) and
 // keeps their collision counts packed in LDS, BITS bits per id: 4-bit
 // nibbles when Ns <= 15, bytes when Ns = 16 (adding 1 << BITS*(id%slot)
@@ -1916,10 +1956,11 @@ __global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, in
                                                  int64_t cap, float *__restrict__ ub_out,
                                                  float *__restrict__ lb_out, uint32_t *__restrict__ exact,
                                                  const uint32_t *__restrict__ qinfo,
-                                                 const uint32_t *__restrict__ toff, int T) {
+                                                 const uint32_t *__restrict__ toff, int T,
+                                                 const int32_t *__restrict__ perm) {
     extern __shared__ float qs[];
     __shared__ float rq_part[WAVES];
-    const int q = blockIdx.y, chunk = blockIdx.x;
+    const int q = perm ? perm[blockIdx.y] : static_cast<int>(blockIdx.y), chunk = blockIdx.x;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int64_t nc = cand_count[q];
     constexpr int RPW = WAVE / LPR;
@@ -2512,6 +2553,12 @@ hipError_t launch_encode_ids(const uint32_t *ids, const uint32_t *raw, const uin
     return hipGetLastError();
 }
 
+hipError_t launch_query_order(const int32_t *cells, int nq, int Ns, int K, int32_t *perm, hipStream_t st) {
+    if (K > 4096) return hipErrorInvalidValue;
+    k_query_order<<<1, ORD_BLOCK, sizeof(uint32_t) * static_cast<size_t>(K), st>>>(cells, nq, Ns, K, perm);
+    return hipGetLastError();
+}
+
 hipError_t launch_transform(const float *Q, int nq, int d, const float *mean, const float *B,
                             int M, float *qt, hipStream_t st) {
     dim3 grid((M + 63) / 64, (nq + TR_Q - 1) / TR_Q), block(64, 4);
@@ -2772,18 +2819,18 @@ hipError_t launch_qbytes(const float *Q, int nq, int d, uint32_t *info, hipStrea
 
 hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, const float4 *meta, bool plain,
                           const int32_t *cand, const uint32_t *cand_count, int64_t cap, float *ub, float *lb,
-                          uint32_t *exact, const uint32_t *qinfo, const uint32_t *toff, int T, int blocks_per_q,
-                          hipStream_t st) {
+                          uint32_t *exact, const uint32_t *qinfo, const uint32_t *toff, int T,
+                          const int32_t *perm, int blocks_per_q, hipStream_t st) {
     dim3 grid(blocks_per_q, nq);
     size_t lds = sizeof(float) * static_cast<size_t>(d);
 #define TACO_RR8(L, V)                                                                                    \
     do {                                                                                                  \
         if (plain)                                                                                        \
             k_rerank8<L, V, true><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb, \
-                                                            exact, qinfo, toff, T);                           \
+                                                            exact, qinfo, toff, T, perm);                     \
         else                                                                                              \
             k_rerank8<L, V, false><<<grid, BLOCK, lds, st>>>(Q, d, base8, meta, cand, cand_count, cap, ub, lb, \
-                                                             exact, qinfo, toff, T);                          \
+                                                             exact, qinfo, toff, T, perm);                    \
     } while (0)
     if (d % 16 != 0) {
         TACO_RR8(64, false);

@@ -138,6 +138,7 @@ struct tc_index {
     uint32_t *tcount = nullptr;  // [Qb][T] entries listed per tile (TC_COUNT_LIST)
     uint32_t *toff = nullptr;    // [Qb][T+1] first candidate slot per tile (TC_COUNT_LIST)
     uint32_t *tlev = nullptr;    // [Qb][T][Ns+1] listed ids per tile and level (TC_COUNT_LIST)
+    int32_t *perm = nullptr;     // [Qb] order in which the re-rank takes the queries
     // BF16 re-rank form (built when first selected)
     int precision = TC_FP32;
     float *mu = nullptr;         // [d] mean rounded to BF16
@@ -213,6 +214,8 @@ void free_scratch(tc_index *x) {
     x->toff = nullptr;
     (void)hipFree(x->tlev);
     x->tlev = nullptr;
+    (void)hipFree(x->perm);
+    x->perm = nullptr;
     x->qn = x->qsc = x->cd = nullptr;
     x->sc = nullptr;
     x->lb = nullptr;
@@ -270,6 +273,7 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->tcount, size_t(qb) * x->T, "per-tile list lengths"))) return rc;
     if ((rc = dmalloc(&x->toff, size_t(qb) * (x->T + 1), "per-tile candidate offsets"))) return rc;
     if ((rc = dmalloc(&x->tlev, size_t(qb) * x->T * (x->Ns + 1), "per-tile listed levels"))) return rc;
+    if ((rc = dmalloc(&x->perm, size_t(qb), "query order"))) return rc;
     {
         const uint32_t l0 = static_cast<uint32_t>(std::min(2, x->Ns));
         TC_HIP(hipMemcpy(x->lvl, &l0, sizeof(l0), hipMemcpyHostToDevice), "list level");
@@ -770,10 +774,12 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                 // exact form: plain rows, 16 | d <= 256
                 const bool ex = x->u8_plain && x->d % 16 == 0 && x->d <= 256;
                 if (ex) TC_HIP(taco::launch_qbytes(Qb, nb, x->d, x->qinfo, st), "query bytes kernel");
+                const bool order = x->K <= 4096;
+                if (order) TC_HIP(taco::launch_query_order(x->cells, nb, x->Ns, x->K, x->perm, st), "query order kernel");
                 TC_HIP(taco::launch_rerank8(Qb, nb, x->d, x->base8, x->rmeta, x->u8_plain, x->cand,
                                             x->cand_count, cap, x->cand_dist, x->lb, x->exact,
                                             ex ? x->qinfo : nullptr, list ? x->toff : nullptr, x->T,
-                                            rr_blocks, st),
+                                            order ? x->perm : nullptr, rr_blocks, st),
                        "8-bit rerank kernel");
             }
             record(x, K_RERANK, st, false);
