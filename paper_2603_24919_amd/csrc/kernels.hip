@@ -1716,7 +1716,10 @@ __device__ __forceinline__ int group_sum_i32(int a) {
 // Rows handled at once by a lane group of the re-rank kernels: the chunk
 // loop runs outside and the rows inside, so the loads of RU rows are in
 // flight together, while each row's terms keep the order of row_partial32.
-constexpr int RU = 4;
+#ifndef TACO_RU
+#define TACO_RU 4
+#endif
+constexpr int RU = TACO_RU;
 
 template <int LPR, bool VEC4>
 __global__ __launch_bounds__(256) void k_rerank(const float *__restrict__ Q, int d,
@@ -1948,7 +1951,7 @@ __global__ __launch_bounds__(256) void k_qbytes(const float *__restrict__ Q, int
 // bounded form runs for every query.
 // grid (G, nq), block 256, dynamic LDS d floats.
 template <int LPR, bool VEC16, bool PLAIN>
-__global__ __launch_bounds__(256) void k_rerank8(const float *__restrict__ Q, int d,
+__global__ __launch_bounds__(256, PLAIN ? 8 : 1) void k_rerank8(const float *__restrict__ Q, int d,
                                                  const uint8_t *__restrict__ base8,
                                                  const float4 *__restrict__ meta,
                                                  const int32_t *__restrict__ cand,
