@@ -16,6 +16,7 @@ struct CountLaunch {
                             // cell; slices are laid out tile by tile
     const int32_t *cells;   // [nq][Ns][K] probed cells
     const int32_t *ncells;  // [nq][Ns]
+    const int32_t *perm = nullptr;  // [nq] order in which the count takes the queries, or null
 };
 
 struct SelectLaunch {

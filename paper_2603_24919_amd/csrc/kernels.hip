@@ -682,6 +682,7 @@ struct CountArgs {
     const uint32_t *off2d;   // [Ns][K][T][2] first and end group of each slice in ids
     const int32_t *cells;    // [nq][Ns][K]
     const int32_t *ncells;   // [nq][Ns]
+    const int32_t *perm;     // [nq] query of each grid row (k_query_order), or null
 };
 
 // LDS carve-up of k_count (dynamic part).  dl and sb are adjacent (the
@@ -1250,7 +1251,8 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
         }
     }
     for (uint32_t f = f0; f < nrun; f += fstep) {
-        const int q = MODE == CT_REDO ? static_cast<int>(la.redo[2 + f]) : static_cast<int>(blockIdx.y);
+        const int q = MODE == CT_REDO ? static_cast<int>(la.redo[2 + f])
+                                      : (a.perm ? a.perm[blockIdx.y] : static_cast<int>(blockIdx.y));
         if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
         if (MODE == CT_LIST && threadIdx.x < 17) lsum[threadIdx.x] = 0u;
         count_tile<BITS, HI, TR>(a, q, t, L, hsum);
@@ -2680,7 +2682,7 @@ hipError_t launch_list_select(const CountLaunch &c, const ListLaunch &l, uint32_
 hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, int form, const ListLaunch *l,
                         hipStream_t st) {
     if (form != CT_STORE && !l) return hipErrorInvalidValue;
-    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
+    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells, c.perm};
     const ListArgs la = list_args(c, l);
     dim3 grid(c.T, form == CT_REDO ? l->redo_groups : c.nq);
     uint4 *s4 = reinterpret_cast<uint4 *>(sc);
@@ -2754,7 +2756,7 @@ hipError_t fused_max_blocks(int W, int bits, int Ns, int *blocks_per_cu) {
 
 hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int NG, uint32_t *arrive,
                                uint32_t *err, uint32_t spin_limit, hipStream_t st) {
-    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells};
+    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells, c.perm};
     SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
                   s.dump_hist, nullptr};
     FuseArgs f{c.nq, NG, const_cast<uint32_t *>(s.hist), arrive, err, spin_limit};

@@ -715,8 +715,12 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                "probe kernel");
         record(x, K_PROBE, st, false);
 
+        // the order in which the count and re-rank take the queries (any order
+        // gives the same results)
+        const bool order = x->K <= 4096;
+        if (order) TC_HIP(taco::launch_query_order(x->cells, nb, x->Ns, x->K, x->perm, st), "query order kernel");
         taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids_enc, x->off2d, x->cells,
-                             x->ncells};
+                             x->ncells, order ? x->perm : nullptr};
         taco::SelectLaunch sl{x->hist, R, x->rule, cap, x->cand, x->cand_count,
                               dump && dump->sc ? dump->sc + b0 * x->n : nullptr,
                               dump && dump->last ? dump->last + b0 : nullptr,
@@ -774,8 +778,6 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                 // exact form: plain rows, 16 | d <= 256
                 const bool ex = x->u8_plain && x->d % 16 == 0 && x->d <= 256;
                 if (ex) TC_HIP(taco::launch_qbytes(Qb, nb, x->d, x->qinfo, st), "query bytes kernel");
-                const bool order = x->K <= 4096;
-                if (order) TC_HIP(taco::launch_query_order(x->cells, nb, x->Ns, x->K, x->perm, st), "query order kernel");
                 TC_HIP(taco::launch_rerank8(Qb, nb, x->d, x->base8, x->rmeta, x->u8_plain, x->cand,
                                             x->cand_count, cap, x->cand_dist, x->lb, x->exact,
                                             ex ? x->qinfo : nullptr, list ? x->toff : nullptr, x->T,
