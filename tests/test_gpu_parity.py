@@ -336,6 +336,27 @@ def test_list_mode_equals_split_without_dumps(taco_mod, w):
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (alpha, "graph")
 
 
+def test_list_mode_many_tiles(taco_mod):
+    """Past the tiles the list selection groups (137 tiles of 1,024 ids), its
+    candidates stay ungrouped and the re-rank takes them interleaved; with 18
+    tiles they are grouped by tile and the exact 8-bit re-rank hands each tile
+    residue to its own workgroups.  Both equal the split path bit for bit, in
+    FP32 and in the 8-bit re-rank, with 8 and 16 re-rank workgroups."""
+    t = taco_mod
+    w = synthdata.WORKLOADS["gmm-int-1m-d128"].scaled("gmm-int-140k-d128", n=140_000, nq=16)
+    X, Q = synthdata.base_and_queries(w)
+    path = workload_index(w, X)
+    print(f"[{w.name}] list vs split, many tiles", flush=True)
+    for prec in (t.TC_FP32, t.TC_U8):
+        for tile in (1024, 8192):
+            base = ((t.TC_OPT_PRECISION, prec), (t.TC_OPT_TILE_IDS, tile))
+            ref = _search_bits(t, path, Q, 0.05, base + ((t.TC_OPT_COUNT_MODE, t.TC_COUNT_SPLIT),))
+            for rr in (8, 16):
+                got = _search_bits(t, path, Q, 0.05, base + ((t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST),
+                                                             (t.TC_OPT_RERANK_BLOCKS, rr)), calls=2)
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (prec, tile, rr)
+
+
 @pytest.mark.parametrize("w", scaled_workloads(), ids=lambda w: w.name)
 def test_workload_shapes_split_mode(taco_mod, w):
     t = taco_mod
