@@ -14,8 +14,8 @@ struct CountLaunch {
                             // by launch_encode_ids
     const uint32_t *off2d;  // [Ns][K][T][2] first and end group of each tile's slice of each
                             // cell; slices are laid out tile by tile
-    const int32_t *cells;   // [nq][Ns][K] probed cells
-    const int32_t *ncells;  // [nq][Ns]
+    const int32_t *flat;    // [nq][Ns*K] probed cells as rows j*K + cell (launch_flatten_cells)
+    const uint32_t *ftot;   // [nq] number of probed cells
     const int32_t *perm = nullptr;  // [nq] order in which the count takes the queries, or null
 };
 
@@ -116,6 +116,10 @@ hipError_t launch_rerank8(const float *Q, int nq, int d, const uint8_t *base8, c
                           const int32_t *cand, const uint32_t *cand_count, int64_t cap, float *ub, float *lb,
                           uint32_t *exact, const uint32_t *qinfo, const uint32_t *toff, int T,
                           const int32_t *perm, int blocks_per_q, hipStream_t st);
+// The probed cells (cells [nq][Ns][K], ncells [nq][Ns]) as one list per
+// query of rows j*K + cell (flat [nq][Ns*K]) and its length (ftot [nq])
+hipError_t launch_flatten_cells(const int32_t *cells, const int32_t *ncells, int nq, int Ns, int K, int32_t *flat,
+                                uint32_t *ftot, hipStream_t st);
 // perm[i] = the query of rank i when the batch is ordered by the first cell
 // probed in subspace 0 (cells: [nq][Ns][K]); K <= 4096
 hipError_t launch_query_order(const int32_t *cells, int nq, int Ns, int K, int32_t *perm, hipStream_t st);

@@ -608,6 +608,30 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 // rank i; dynamic LDS: K words (K <= 4096).
 // ---------------------------------------------------------------------------
 
+// The probed cells of each query as one list in subspace order, as index
+// rows j*K + cell (the count kernels' slice lookups take one load), and
+// their number.  grid nq, block 256.
+__global__ __launch_bounds__(256) void k_flatten_cells(const int32_t *__restrict__ cells,
+                                                       const int32_t *__restrict__ ncells, int Ns, int K,
+                                                       int32_t *__restrict__ flat, uint32_t *__restrict__ ftot) {
+    __shared__ int pre[17];
+    const int q = blockIdx.x;
+    if (threadIdx.x < WAVE) {
+        const int j = static_cast<int>(threadIdx.x);
+        const uint32_t v = j < Ns ? static_cast<uint32_t>(ncells[static_cast<int64_t>(q) * Ns + j]) : 0u;
+        const uint32_t inc = wave_incl_scan_u32(v, j);
+        if (j <= Ns) pre[j] = static_cast<int>(inc - v);
+    }
+    __syncthreads();
+    int32_t *fq = flat + static_cast<int64_t>(q) * Ns * K;
+    for (int j = 0; j < Ns; j++) {
+        const int32_t *cj = cells + (static_cast<int64_t>(q) * Ns + j) * K;
+        const int n0 = pre[j], nj = pre[j + 1] - pre[j];
+        for (int i = threadIdx.x; i < nj; i += 256) fq[n0 + i] = j * K + cj[i];
+    }
+    if (threadIdx.x == 0) ftot[q] = static_cast<uint32_t>(pre[Ns]);
+}
+
 constexpr int ORD_BLOCK = 1024;
 
 __global__ __launch_bounds__(ORD_BLOCK) void k_query_order(const int32_t *__restrict__ cells, int nq, int Ns,
@@ -680,8 +704,8 @@ struct CountArgs {
     int64_t n;
     const uint32_t *ids;     // padded 4-id groups encoded for the tile width (see k_encode_ids)
     const uint32_t *off2d;   // [Ns][K][T][2] first and end group of each slice in ids
-    const int32_t *cells;    // [nq][Ns][K]
-    const int32_t *ncells;   // [nq][Ns]
+    const int32_t *flat;     // [nq][Ns*K] probed cells as index rows j*K + cell (k_flatten_cells)
+    const uint32_t *ftot;    // [nq] probed cells in all subspaces
     const int32_t *perm;     // [nq] query of each grid row (k_query_order), or null
 };
 
@@ -696,7 +720,6 @@ struct CountLds {
                       // the segment is set when a non-empty slice starts at position
                       // p > 0 of the segment
     uint16_t *wt;     // [CT_WT] slice holding the first position of each window
-    int32_t *pP;      // [17] prefix of probed cells over subspaces
     uint32_t *wsum;   // [2 * CT_WAVES] per-wavefront totals of the prefix sums
     uint32_t *hsum;   // [18] the tile's "count >= v" totals
     uint32_t *lsum;   // [17] levels of the listed ids
@@ -707,7 +730,7 @@ static_assert(CT_CHUNK % 2 == 0, "the start bitmap is read in 64-bit words");
 
 __host__ __device__ constexpr size_t count_lds_size(int W, int bits) {
     return static_cast<size_t>(W) * bits / 8 + CT_DUMMY * 4 + static_cast<size_t>(CT_CHUNK) * 4 +
-           static_cast<size_t>(CT_CHUNK + 1) * 4 + static_cast<size_t>(CT_WT) * 2 + 17 * 4 +
+           static_cast<size_t>(CT_CHUNK + 1) * 4 + static_cast<size_t>(CT_WT) * 2 +
            2 * CT_WAVES * 4 + (18 + 17) * 4;
 }
 
@@ -718,8 +741,7 @@ __device__ __forceinline__ CountLds carve(unsigned char *lds, int W) {
     c.dl = c.cnt + W / (32 / BITS) + CT_DUMMY;
     c.sb = c.dl + CT_CHUNK;  // 8-byte aligned: W*BITS/32, CT_DUMMY and CT_CHUNK are even
     c.wt = reinterpret_cast<uint16_t *>(c.sb + CT_CHUNK + 1);
-    c.pP = reinterpret_cast<int32_t *>(c.wt + CT_WT);
-    c.wsum = reinterpret_cast<uint32_t *>(c.pP + 17);
+    c.wsum = reinterpret_cast<uint32_t *>(c.wt + CT_WT);
     c.hsum = c.wsum + 2 * CT_WAVES;
     c.lsum = c.hsum + 18;
     return c;
@@ -887,16 +909,9 @@ template <int BITS, bool HI, bool TR = true>
 __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, uint32_t *hsum) {
     const int vec = a.W * BITS / 128;  // 16-byte words of counts
     for (int i = threadIdx.x; i < vec; i += CT_BLOCK) reinterpret_cast<uint4 *>(L.cnt)[i] = make_uint4(0u, 0u, 0u, 0u);
-    if (threadIdx.x < WAVE) {
-        // the subspaces' cell counts in one load per lane, then a prefix sum
-        const int j = static_cast<int>(threadIdx.x);
-        const uint32_t v = j < a.Ns ? static_cast<uint32_t>(a.ncells[static_cast<int64_t>(q) * a.Ns + j]) : 0u;
-        const uint32_t inc = wave_incl_scan_u32(v, j);
-        if (j <= a.Ns) L.pP[j] = static_cast<int32_t>(inc - v);
-    }
-    __syncthreads();
-    const int totalP = L.pP[a.Ns];
-    const int32_t *cq = a.cells + static_cast<int64_t>(q) * a.Ns * a.K;
+    // (the counts are cleared before the barriers ahead of the walk)
+    const int totalP = static_cast<int>(a.ftot[q]);
+    const int32_t *fq = a.flat + static_cast<int64_t>(q) * a.Ns * a.K;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     Trans<HI> tr{0ull, 0ull};
     int held = 0;  // bound on any byte of tr: bumps per lane since the last flush
@@ -907,11 +922,8 @@ __device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, 
         // this thread's slice
         uint32_t len = 0u, st = 0u;
         if (static_cast<int>(threadIdx.x) < nsl) {
-            const int g = c0 + static_cast<int>(threadIdx.x);
-            int j = 0;
-            while (L.pP[j + 1] <= g) j++;
-            const int cell = cq[static_cast<int64_t>(j) * a.K + (g - L.pP[j])];
-            const uint2 se = reinterpret_cast<const uint2 *>(a.off2d)[(static_cast<int64_t>(j) * a.K + cell) * a.T + t];
+            const int64_t row = fq[c0 + static_cast<int>(threadIdx.x)];
+            const uint2 se = reinterpret_cast<const uint2 *>(a.off2d)[row * a.T + t];
             st = se.x;
             len = se.y - se.x;
         }
@@ -2558,6 +2570,12 @@ hipError_t launch_encode_ids(const uint32_t *ids, const uint32_t *raw, const uin
     return hipGetLastError();
 }
 
+hipError_t launch_flatten_cells(const int32_t *cells, const int32_t *ncells, int nq, int Ns, int K, int32_t *flat,
+                                uint32_t *ftot, hipStream_t st) {
+    if (nq > 0) k_flatten_cells<<<nq, 256, 0, st>>>(cells, ncells, Ns, K, flat, ftot);
+    return hipGetLastError();
+}
+
 hipError_t launch_query_order(const int32_t *cells, int nq, int Ns, int K, int32_t *perm, hipStream_t st) {
     if (K > 4096) return hipErrorInvalidValue;
     k_query_order<<<1, ORD_BLOCK, sizeof(uint32_t) * static_cast<size_t>(K), st>>>(cells, nq, Ns, K, perm);
@@ -2682,7 +2700,7 @@ hipError_t launch_list_select(const CountLaunch &c, const ListLaunch &l, uint32_
 hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, int form, const ListLaunch *l,
                         hipStream_t st) {
     if (form != CT_STORE && !l) return hipErrorInvalidValue;
-    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells, c.perm};
+    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.flat, c.ftot, c.perm};
     const ListArgs la = list_args(c, l);
     dim3 grid(c.T, form == CT_REDO ? l->redo_groups : c.nq);
     uint4 *s4 = reinterpret_cast<uint4 *>(sc);
@@ -2756,7 +2774,7 @@ hipError_t fused_max_blocks(int W, int bits, int Ns, int *blocks_per_cu) {
 
 hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int NG, uint32_t *arrive,
                                uint32_t *err, uint32_t spin_limit, hipStream_t st) {
-    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.cells, c.ncells, c.perm};
+    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.flat, c.ftot, c.perm};
     SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
                   s.dump_hist, nullptr};
     FuseArgs f{c.nq, NG, const_cast<uint32_t *>(s.hist), arrive, err, spin_limit};

@@ -138,7 +138,9 @@ struct tc_index {
     uint32_t *tcount = nullptr;  // [Qb][T] entries listed per tile (TC_COUNT_LIST)
     uint32_t *toff = nullptr;    // [Qb][T+1] first candidate slot per tile (TC_COUNT_LIST)
     uint32_t *tlev = nullptr;    // [Qb][T][Ns+1] listed ids per tile and level (TC_COUNT_LIST)
-    int32_t *perm = nullptr;     // [Qb] order in which the re-rank takes the queries
+    int32_t *perm = nullptr;     // [Qb] order in which the count and re-rank take the queries
+    int32_t *flat = nullptr;     // [Qb][Ns*K] probed cells as index rows, subspace after subspace
+    uint32_t *ftot = nullptr;    // [Qb] probed cells per query
     // BF16 re-rank form (built when first selected)
     int precision = TC_FP32;
     float *mu = nullptr;         // [d] mean rounded to BF16
@@ -216,6 +218,10 @@ void free_scratch(tc_index *x) {
     x->tlev = nullptr;
     (void)hipFree(x->perm);
     x->perm = nullptr;
+    (void)hipFree(x->flat);
+    x->flat = nullptr;
+    (void)hipFree(x->ftot);
+    x->ftot = nullptr;
     x->qn = x->qsc = x->cd = nullptr;
     x->sc = nullptr;
     x->lb = nullptr;
@@ -274,6 +280,8 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->toff, size_t(qb) * (x->T + 1), "per-tile candidate offsets"))) return rc;
     if ((rc = dmalloc(&x->tlev, size_t(qb) * x->T * (x->Ns + 1), "per-tile listed levels"))) return rc;
     if ((rc = dmalloc(&x->perm, size_t(qb), "query order"))) return rc;
+    if ((rc = dmalloc(&x->flat, size_t(qb) * x->Ns * x->K, "probed cell rows"))) return rc;
+    if ((rc = dmalloc(&x->ftot, size_t(qb), "probed cell totals"))) return rc;
     {
         const uint32_t l0 = static_cast<uint32_t>(std::min(2, x->Ns));
         TC_HIP(hipMemcpy(x->lvl, &l0, sizeof(l0), hipMemcpyHostToDevice), "list level");
@@ -719,8 +727,10 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
         // gives the same results)
         const bool order = x->K <= 4096;
         if (order) TC_HIP(taco::launch_query_order(x->cells, nb, x->Ns, x->K, x->perm, st), "query order kernel");
-        taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids_enc, x->off2d, x->cells,
-                             x->ncells, order ? x->perm : nullptr};
+        TC_HIP(taco::launch_flatten_cells(x->cells, x->ncells, nb, x->Ns, x->K, x->flat, x->ftot, st),
+               "probed cell list kernel");
+        taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids_enc, x->off2d, x->flat,
+                             x->ftot, order ? x->perm : nullptr};
         taco::SelectLaunch sl{x->hist, R, x->rule, cap, x->cand, x->cand_count,
                               dump && dump->sc ? dump->sc + b0 * x->n : nullptr,
                               dump && dump->last ? dump->last + b0 : nullptr,
