@@ -284,7 +284,7 @@ _SHORT = (("k_count_select", "count_select"), ("k_list_select", "list_select"), 
           ("k_recheck_topk", "recheck"), ("k_topk", "topk"), ("k_probe", "probe"),
           ("k_transform", "transform"), ("k_cdist_mfma", "cdist"), ("k_qstats", "cdist"),
           ("k_prep_cent", "prep_cent"), ("k_prep_bf16", "prep_bf16"), ("k_prep_u8", "prep_u8"), ("k_qbytes", "qbytes"),
-          ("k_query_order", "query_order"),
+          ("k_query_order", "query_order"), ("k_flatten_cells", "flatten"),
           ("k_encode_ids", "encode_ids"), ("k_build_off2d", "build_off2d"), ("k_budgets", "budgets"),
           ("k_fill_u32", "fill"), ("k_u32_to_i64", "u32_to_i64"))
 

@@ -28,6 +28,7 @@ def test_short_kernel_names():
     assert f("taco::k_list_select(taco::ListArgs, unsigned int*, int, long)") == "list_select"
     assert f("taco::k_qbytes(float const*, int, int, unsigned int*)") == "qbytes"
     assert f("taco::k_query_order(int const*, int, int, int, int*)") == "query_order"
+    assert f("taco::k_flatten_cells(int const*, int const*, int, int, int*, unsigned int*)") == "flatten"
     assert f("taco::k_select(taco::SelectArgs, int)") == "select"
     assert f("void taco::k_rerank16<16, true>(float const*)") == "rerank"
     assert f("void taco::k_rerank<16, true>(float const*)") == "rerank"
