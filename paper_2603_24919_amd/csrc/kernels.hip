@@ -610,26 +610,25 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
 
 // The probed cells of each query as one list in subspace order, as index
 // rows j*K + cell (the count kernels' slice lookups take one load), and
-// their number.  grid nq, block 256.
+// their number.  One wavefront per query; grid ceil(nq/4), block 256.
 __global__ __launch_bounds__(256) void k_flatten_cells(const int32_t *__restrict__ cells,
-                                                       const int32_t *__restrict__ ncells, int Ns, int K,
+                                                       const int32_t *__restrict__ ncells, int nq, int Ns, int K,
                                                        int32_t *__restrict__ flat, uint32_t *__restrict__ ftot) {
-    __shared__ int pre[17];
-    const int q = blockIdx.x;
-    if (threadIdx.x < WAVE) {
-        const int j = static_cast<int>(threadIdx.x);
-        const uint32_t v = j < Ns ? static_cast<uint32_t>(ncells[static_cast<int64_t>(q) * Ns + j]) : 0u;
-        const uint32_t inc = wave_incl_scan_u32(v, j);
-        if (j <= Ns) pre[j] = static_cast<int>(inc - v);
-    }
-    __syncthreads();
+    const int lane = threadIdx.x % WAVE;
+    const int q = blockIdx.x * 4 + static_cast<int>(threadIdx.x / WAVE);
+    if (q >= nq) return;
+    // lane j < Ns: subspace j's count and first slot
+    const uint32_t v = lane < Ns ? static_cast<uint32_t>(ncells[static_cast<int64_t>(q) * Ns + lane]) : 0u;
+    const uint32_t pre = wave_incl_scan_u32(v, lane) - v;
     int32_t *fq = flat + static_cast<int64_t>(q) * Ns * K;
     for (int j = 0; j < Ns; j++) {
         const int32_t *cj = cells + (static_cast<int64_t>(q) * Ns + j) * K;
-        const int n0 = pre[j], nj = pre[j + 1] - pre[j];
-        for (int i = threadIdx.x; i < nj; i += 256) fq[n0 + i] = j * K + cj[i];
+        const int n0 = __builtin_amdgcn_readlane(static_cast<int>(pre), j);
+        const int nj = __builtin_amdgcn_readlane(static_cast<int>(v), j);
+        for (int i = lane; i < nj; i += WAVE) fq[n0 + i] = j * K + cj[i];
     }
-    if (threadIdx.x == 0) ftot[q] = static_cast<uint32_t>(pre[Ns]);
+    const int tot = __builtin_amdgcn_readlane(static_cast<int>(pre + v), Ns - 1);
+    if (lane == 0) ftot[q] = static_cast<uint32_t>(tot);
 }
 
 constexpr int ORD_BLOCK = 1024;
@@ -640,9 +639,20 @@ __global__ __launch_bounds__(ORD_BLOCK) void k_query_order(const int32_t *__rest
     __shared__ uint32_t wsum[ORD_BLOCK / WAVE];
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     for (int i = threadIdx.x; i < K; i += ORD_BLOCK) bins[i] = 0u;
-    __syncthreads();
+    // this thread's keys (queries threadIdx.x + u*ORD_BLOCK), loaded together
+    constexpr int KPT = 16;
+    int kq[KPT];
+#pragma unroll
+    for (int u = 0; u < KPT; u++) {
+        const int q = static_cast<int>(threadIdx.x) + u * ORD_BLOCK;
+        kq[u] = q < nq ? min(max(cells[static_cast<int64_t>(q) * Ns * K], 0), K - 1) : 0;
+    }
     auto key = [&](int q) { return min(max(cells[static_cast<int64_t>(q) * Ns * K], 0), K - 1); };
-    for (int q = threadIdx.x; q < nq; q += ORD_BLOCK) atomicAdd(&bins[key(q)], 1u);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < KPT; u++)
+        if (static_cast<int>(threadIdx.x) + u * ORD_BLOCK < nq) atomicAdd(&bins[kq[u]], 1u);
+    for (int q = static_cast<int>(threadIdx.x) + KPT * ORD_BLOCK; q < nq; q += ORD_BLOCK) atomicAdd(&bins[key(q)], 1u);
     __syncthreads();
     // exclusive prefix over the bins: a contiguous run of bins per thread
     const int per = (K + ORD_BLOCK - 1) / ORD_BLOCK;
@@ -660,7 +670,13 @@ __global__ __launch_bounds__(ORD_BLOCK) void k_query_order(const int32_t *__rest
         run += c;
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < nq; q += ORD_BLOCK) perm[atomicAdd(&bins[key(q)], 1u)] = q;
+#pragma unroll
+    for (int u = 0; u < KPT; u++) {
+        const int q = static_cast<int>(threadIdx.x) + u * ORD_BLOCK;
+        if (q < nq) perm[atomicAdd(&bins[kq[u]], 1u)] = q;
+    }
+    for (int q = static_cast<int>(threadIdx.x) + KPT * ORD_BLOCK; q < nq; q += ORD_BLOCK)
+        perm[atomicAdd(&bins[key(q)], 1u)] = q;
 }
 
 // ---------------------------------------------------------------------------
@@ -2572,7 +2588,7 @@ hipError_t launch_encode_ids(const uint32_t *ids, const uint32_t *raw, const uin
 
 hipError_t launch_flatten_cells(const int32_t *cells, const int32_t *ncells, int nq, int Ns, int K, int32_t *flat,
                                 uint32_t *ftot, hipStream_t st) {
-    if (nq > 0) k_flatten_cells<<<nq, 256, 0, st>>>(cells, ncells, Ns, K, flat, ftot);
+    if (nq > 0) k_flatten_cells<<<(nq + 3) / 4, 256, 0, st>>>(cells, ncells, nq, Ns, K, flat, ftot);
     return hipGetLastError();
 }
 
