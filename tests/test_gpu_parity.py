@@ -148,9 +148,11 @@ def test_bench_workload_full_size_sampled(taco_mod):
     rng = np.random.default_rng(2024)
     sample = np.sort(rng.choice(w.nq, 12, replace=False))
     small = ("retrieved", "ncells", "hist", "last", "ncand")
+    ref = {}
     for alpha in w.alphas:
         print(f"[{w.name}] alpha={alpha}: full batch", flush=True)
         g = gpu_search(idx, Q, w.k, alpha, w.beta, small)
+        ref[alpha] = (g["ids"], g["dists"].view(np.uint32))
         A = O.budget_A(alpha, w.n)
         levels = np.arange(w.Ns + 1)
         assert np.all(g["hist"].sum(axis=1) == w.n)
@@ -168,6 +170,19 @@ def test_bench_workload_full_size_sampled(taco_mod):
         for i, qi in enumerate(sample[:4]):
             compare_query(gs, i, oidx.query(Q[qi], alpha, w.beta, w.k), w.Ns, w.k, f"{w.name} a={alpha}")
     idx.close()
+    # the benchmark's tuned configuration: list selection, exact 8-bit re-rank,
+    # 8 re-rank and 2 probe queries per workgroup, all 10,000 queries in one
+    # batch, replayed from a graph; bit for bit the results above
+    import torch
+    t = taco_mod
+    free, _ = torch.cuda.mem_get_info(0)
+    opts = ((t.TC_OPT_PRECISION, t.TC_U8), (t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST),
+            (t.TC_OPT_RERANK_BLOCKS, 8), (t.TC_OPT_PROBE_QPW, 2),
+            (t.TC_OPT_SCRATCH_BYTES, int(free * 0.6)), (t.TC_OPT_MAX_BATCH, w.nq))
+    for alpha in w.alphas:
+        print(f"[{w.name}] alpha={alpha}: tuned configuration", flush=True)
+        got = _search_bits(t, path, Q, alpha, opts, calls=2, graph=True)
+        assert np.array_equal(got[0], ref[alpha][0]) and np.array_equal(got[1], ref[alpha][1]), alpha
 
 
 def _bf16_cases():
