@@ -566,6 +566,8 @@ __global__ __launch_bounds__(64 * QPW) void k_probe(
     while (!done) {
         int cellv = 0;  // lane s: the cell of step s of this batch
         int nb = 0;
+        // (fully unrolled: the steps' loop control folds away)
+#pragma unroll
         for (; nb < PB; nb++) {
             const uint32_t kmin = wave_min_u32_dpp(kb);
             if (kmin == 0xffffffffu) break;
