@@ -2764,8 +2764,8 @@ hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint
                   s.dump_hist, s.redo};
     const int64_t words4 = static_cast<int64_t>(c.T) * c.W * c.bits / 128;
     // about 16 sixteen-byte words per thread; the few queued queries of a
-    // list selection get one word per thread
-    const int64_t per = s.redo ? 1 : 16;
+    // list selection get four (one pass of SEL_UNROLL loads)
+    const int64_t per = s.redo ? 4 : 16;
     int64_t blocks = (words4 + SEL_BLOCK * per - 1) / (SEL_BLOCK * per);
     if (blocks > (s.redo ? 256 : 64)) blocks = s.redo ? 256 : 64;
     if (blocks < 1) blocks = 1;

@@ -761,7 +761,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             sr.dump_last = nullptr;
             sr.dump_hist = nullptr;
             sr.redo = redo;
-            sr.redo_groups = 64;
+            sr.redo_groups = 128;
             TC_HIP(taco::launch_select(cl, sr, x->sc, st), "select kernel (queued)");
             record(x, K_SELECT, st, false);
             if (dsc)
