@@ -275,6 +275,83 @@ int tc_batch_capacity(const tc_index *index, int64_t *queries_per_batch);
 /* Message for the calling thread's last failed call ("" if none). */
 const char *tc_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Index construction on the GPU (Alg 1-3, Sections 3.2 and 4.1).
+ *
+ * The stage calls below take device buffers of the current device, enqueue
+ * on `stream`, then synchronize it (they free their own scratch) before
+ * returning.  Integer results (allocation, labels, cells) are exact and
+ * reproducible; FP64 statistics use a fixed reduction order.
+ * ------------------------------------------------------------------------ */
+
+/* Alg 1, mean and covariance: mean[d] = column means of X (device, n x d
+ * row-major, FP32), cov[d][d] = 1/(n-1) sum (x - mean)(x - mean)^T, both FP64
+ * device outputs.  n >= 2.  TC_EINVAL, TC_ENOMEM, TC_EDEVICE. */
+int tc_build_stats(const float *X, int64_t n, int32_t d, double *mean, double *cov, void *stream);
+
+/* Alg 1, spectral decomposition of the symmetric cov (device, d x d FP64),
+ * 1 <= d <= 128 (cyclic Jacobi in one workgroup's LDS).  evals[d] descending
+ * (ties keep the lower index); evecs[r][c] = component r of eigenvector c,
+ * each vector signed so that its largest-magnitude component (the first on
+ * ties) is positive.  Device outputs.  TC_EINVAL beyond d = 128. */
+int tc_build_eigen(const double *cov, int32_t d, double *evals, double *evecs, void *stream);
+
+/* Alg 2, eigensystem allocation (host in, host out, no GPU work).  Eigenvalues
+ * are floored at 1e-12 of the largest and scaled by the smallest (so all are
+ * >= 1); in descending order each goes to the bucket of smallest eigenvalue
+ * product among those holding fewer than s (lowest bucket on ties), products
+ * compared as FP64 sums of logs.  cols[Ns*s] = the buckets concatenated, each
+ * in append order (indices into evals).  TC_EINVAL if Ns*s > d or no
+ * eigenvalue is positive. */
+int tc_build_allocate(const double *evals, int32_t d, int32_t Ns, int32_t s, int32_t *cols);
+
+/* Alg 1, data transformation: T[i][m] = sum_t B[t][m] fl32(X[i][t] - mean[t])
+ * in the canonical FP32 chain of the query transform (one fmaf per term, t
+ * ascending).  X (n x d), mean (d), B (d x M), T (n x M): device, FP32. */
+int tc_build_transform(const float *X, int64_t n, int32_t d, const float *mean, const float *B,
+                       int32_t M, float *T, void *stream);
+
+/* Alg 3, k-means on every half-subspace.  Half g = 2j + hf covers columns
+ * [j*s + hf*(s/2), +h) of T (device, n x ld FP32), h = s/2 or s - s/2 (<= 32).
+ * Training sample: the rows train[0..n_train) (host, ascending) or, when
+ * train is NULL, every row.  init (host, [2*Ns][l]) gives each half's l Forgy
+ * seeds as positions into the sample.  `iters` Lloyd steps in FP64: assign to
+ * the nearest centroid (ties to the lower id), move each centroid to the mean
+ * of its points (sums per block of 65536 sample positions in position order,
+ * blocks added in order); an empty cluster takes the sample point farthest
+ * from its centroid, not yet taken in that step (ties to the lower position).
+ * Then cent (device, [2*Ns][l][s - s/2] FP32, the first h entries of a row
+ * used) = the centroids rounded to FP32, and assign (device, [2*Ns][n]) = the
+ * label of every row with the FP32 query-side distance chain (ties to the
+ * lower id).  l <= 64. */
+int tc_build_kmeans(const float *T, int64_t n, int32_t ld, int32_t Ns, int32_t s, int32_t l,
+                    int32_t iters, const int64_t *init, const int64_t *train, int64_t n_train,
+                    float *cent, int32_t *assign, void *stream);
+
+/* Alg 3, inverted multi-index as CSR: point i is in cell assign[2j][i]*l +
+ * assign[2j+1][i] of subspace j.  offsets (device, [Ns][l*l+1]) and ids
+ * (device, [Ns][n], ascending inside each cell).  l*l <= 4096. */
+int tc_build_imi(const int32_t *assign, int64_t n, int32_t Ns, int32_t l, uint32_t *offsets,
+                 uint32_t *ids, void *stream);
+
+/* Alg 1-3 end to end on `device`: statistics, eigensolver, allocation,
+ * transform, k-means and IMI of the base (device, n x d FP32; the index keeps
+ * its own copy), then the index is prepared for search as tc_load_index
+ * would.  init/train/n_train as for tc_build_kmeans; seed is recorded in the
+ * index file.  mean (host, d) and B (host, d x Ns*s), both or neither, skip
+ * the statistics and eigensolver (required when d > 128).  stage_ms (host,
+ * 6 or NULL) receives the GPU time of: statistics, eigensolver, allocation
+ * and uploads, transform, k-means, IMI.  Synchronous.  TC_EINVAL, TC_ENOMEM,
+ * TC_EDEVICE. */
+int tc_build_index(const float *base, int64_t n, int32_t d, int32_t Ns, int32_t s, int32_t l,
+                   int32_t iters, const int64_t *init, const int64_t *train, int64_t n_train,
+                   uint64_t seed, const float *mean, const float *B, int device, tc_index **out,
+                   double *stage_ms);
+
+/* Writes the index in the file layout tc_load_index reads (TACOIDX1 v1).
+ * Synchronous.  TC_EIO if the file cannot be written. */
+int tc_save_index(const tc_index *index, const char *path);
+
 #ifdef __cplusplus
 }
 #endif

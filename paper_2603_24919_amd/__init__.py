@@ -13,6 +13,8 @@ import ctypes as C
 import os
 from typing import Dict, Optional, Tuple
 
+import numpy as np
+
 __all__ = [
     "TC_OK", "TC_EINVAL", "TC_EIO", "TC_EFORMAT", "TC_ENOMEM", "TC_EDEVICE",
     "TC_RULE_PRINTED", "TC_RULE_PROSE", "TC_OPT_SELECT_RULE", "TC_OPT_MAX_BATCH",
@@ -98,9 +100,20 @@ def load_library():
     L.tc_autotune.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, C.c_char_p, C.c_char_p, C.c_size_t]
     L.tc_last_error.restype = C.c_char_p
     L.tc_last_error.argtypes = []
+    L.tc_build_stats.argtypes = [vp, i64, i32, vp, vp, vp]
+    L.tc_build_eigen.argtypes = [vp, i32, vp, vp, vp]
+    L.tc_build_allocate.argtypes = [vp, i32, i32, i32, vp]
+    L.tc_build_transform.argtypes = [vp, i64, i32, vp, vp, i32, vp, vp]
+    L.tc_build_kmeans.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, i64, vp, vp, vp]
+    L.tc_build_imi.argtypes = [vp, i64, i32, i32, vp, vp, vp]
+    L.tc_build_index.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, i64, C.c_uint64, vp, vp,
+                                 C.c_int, C.POINTER(vp), vp]
+    L.tc_save_index.argtypes = [vp, C.c_char_p]
     for f in ("tc_load_index", "tc_index_info", "tc_set_option", "tc_search", "tc_search_debug",
               "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity", "tc_device_errors",
-              "tc_search_batched", "tc_autotune"):
+              "tc_search_batched", "tc_autotune", "tc_build_stats", "tc_build_eigen",
+              "tc_build_allocate", "tc_build_transform", "tc_build_kmeans", "tc_build_imi",
+              "tc_build_index", "tc_save_index"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -154,6 +167,124 @@ def _check_tensor(t, dtype, shape, device, name):
         raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape {tuple(shape)}")
     if device is not None and t.device != torch.device(device):
         raise ValueError(f"{name} must live on {device}")
+
+
+# --------------------------------------------------------------------------
+# Index construction (Alg 1-3).  Argument marshalling only: every stage runs
+# in the library's kernels (Alg 2 in its host code).
+# --------------------------------------------------------------------------
+
+def _host_i64(a) -> Optional[np.ndarray]:
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int64)
+
+
+def tc_build_stats(X, stream=None):
+    """Alg 1 statistics of ``X`` (CUDA float32 [n, d]): FP64 (mean [d], cov [d, d])."""
+    import torch
+    n, d = X.shape
+    _check_tensor(X, torch.float32, (n, d), None, "X")
+    mean = torch.empty(d, dtype=torch.float64, device=X.device)
+    cov = torch.empty((d, d), dtype=torch.float64, device=X.device)
+    _check(load_library().tc_build_stats(_ptr(X), n, d, _ptr(mean), _ptr(cov),
+                                         _stream_handle(stream, X.device)))
+    return mean, cov
+
+
+def tc_build_eigen(cov, stream=None):
+    """Alg 1 spectral decomposition of ``cov`` (CUDA float64 [d, d]):
+    (evals [d] descending, evecs [d, d] with eigenvectors as columns)."""
+    import torch
+    d = cov.shape[0]
+    _check_tensor(cov, torch.float64, (d, d), None, "cov")
+    ev = torch.empty(d, dtype=torch.float64, device=cov.device)
+    V = torch.empty((d, d), dtype=torch.float64, device=cov.device)
+    _check(load_library().tc_build_eigen(_ptr(cov), d, _ptr(ev), _ptr(V), _stream_handle(stream, cov.device)))
+    return ev, V
+
+
+def tc_build_allocate(evals, Ns: int, s: int) -> np.ndarray:
+    """Alg 2 on host eigenvalues (descending): column order, [Ns*s] int32."""
+    ev = np.ascontiguousarray(evals, dtype=np.float64)
+    cols = np.empty(Ns * s, dtype=np.int32)
+    _check(load_library().tc_build_allocate(ev.ctypes.data, ev.size, Ns, s, cols.ctypes.data))
+    return cols
+
+
+def tc_build_transform(X, mean, B, stream=None):
+    """T = B^T (X - mean) row by row (CUDA float32 in and out)."""
+    import torch
+    n, d = X.shape
+    M = B.shape[1]
+    _check_tensor(X, torch.float32, (n, d), None, "X")
+    _check_tensor(mean, torch.float32, (d,), X.device, "mean")
+    _check_tensor(B, torch.float32, (d, M), X.device, "B")
+    T = torch.empty((n, M), dtype=torch.float32, device=X.device)
+    _check(load_library().tc_build_transform(_ptr(X), n, d, _ptr(mean), _ptr(B), M, _ptr(T),
+                                             _stream_handle(stream, X.device)))
+    return T
+
+
+def tc_build_kmeans(T, Ns: int, s: int, l: int, iters: int, init, train=None, stream=None):
+    """Alg 3 k-means of every half-subspace of ``T`` (CUDA float32 [n, ld]);
+    ``init`` host [Ns, 2, l] seed positions, ``train`` host sorted rows or None.
+    Returns (cent float32 [2*Ns, l, s - s//2], assign int32 [2*Ns, n])."""
+    import torch
+    n, ld = T.shape
+    _check_tensor(T, torch.float32, (n, ld), None, "T")
+    init = _host_i64(init)
+    train = _host_i64(train)
+    if init.size != 2 * Ns * l:
+        raise ValueError("init must hold 2*Ns*l positions")
+    cent = torch.empty((2 * Ns, l, s - s // 2), dtype=torch.float32, device=T.device)
+    assign = torch.empty((2 * Ns, n), dtype=torch.int32, device=T.device)
+    _check(load_library().tc_build_kmeans(
+        _ptr(T), n, ld, Ns, s, l, iters, init.ctypes.data,
+        None if train is None else train.ctypes.data, 0 if train is None else train.size,
+        _ptr(cent), _ptr(assign), _stream_handle(stream, T.device)))
+    return cent, assign
+
+
+def tc_build_imi(assign, Ns: int, l: int, stream=None):
+    """Alg 3 IMI from labels (CUDA int32 [2*Ns, n]): (offsets uint32 as int32
+    [Ns, l*l+1], ids as int32 [Ns, n])."""
+    import torch
+    G, n = assign.shape
+    _check_tensor(assign, torch.int32, (2 * Ns, n), None, "assign")
+    offs = torch.empty((Ns, l * l + 1), dtype=torch.int32, device=assign.device)
+    ids = torch.empty((Ns, n), dtype=torch.int32, device=assign.device)
+    _check(load_library().tc_build_imi(_ptr(assign), n, Ns, l, _ptr(offs), _ptr(ids),
+                                       _stream_handle(stream, assign.device)))
+    return offs, ids
+
+
+def tc_build_index(base, Ns: int, s: int, l: int, iters: int, init, train=None, seed: int = 0,
+                   mean=None, B=None, device: int = 0):
+    """Alg 1-3 on the GPU from ``base`` (CUDA float32 [n, d]).  Returns
+    (index handle, stage milliseconds [statistics, eigensolver, allocation,
+    transform, k-means, IMI])."""
+    import torch
+    n, d = base.shape
+    _check_tensor(base, torch.float32, (n, d), device, "base")
+    init = _host_i64(init)
+    train = _host_i64(train)
+    if init.size != 2 * Ns * l:
+        raise ValueError("init must hold 2*Ns*l positions")
+    if (mean is None) != (B is None):
+        raise ValueError("give both mean and B, or neither")
+    m32 = None if mean is None else np.ascontiguousarray(mean, dtype=np.float32)
+    B32 = None if B is None else np.ascontiguousarray(B, dtype=np.float32)
+    ms = np.zeros(6, dtype=np.float64)
+    h = C.c_void_p()
+    _check(load_library().tc_build_index(
+        _ptr(base), n, d, Ns, s, l, iters, init.ctypes.data,
+        None if train is None else train.ctypes.data, 0 if train is None else train.size,
+        int(seed) & (2**64 - 1), None if m32 is None else m32.ctypes.data,
+        None if B32 is None else B32.ctypes.data, int(device), C.byref(h), ms.ctypes.data))
+    return h, ms
+
+
+def tc_save_index(index, path: str) -> None:
+    _check(load_library().tc_save_index(index, os.fsencode(path)))
 
 
 def tc_search(index, queries, k: int, alpha: float, beta: float, ids=None, dists=None,
@@ -255,12 +386,26 @@ def tc_batch_capacity(index) -> int:
 class Index:
     """Owning wrapper of a loaded index."""
 
-    def __init__(self, path: str, device: int = 0):
+    def __init__(self, path: Optional[str], device: int = 0, handle=None):
         self.device = int(device)
-        self.handle = tc_load_index(path, self.device)
+        self.handle = handle if handle is not None else tc_load_index(path, self.device)
+        self.stage_ms = None
         info = tc_index_info(self.handle)
         self.n, self.d, self.Ns, self.s, self.l = (info[x] for x in ("n", "d", "Ns", "s", "l"))
         self.M, self.K = self.Ns * self.s, self.l * self.l
+
+    @classmethod
+    def build(cls, base, Ns: int, s: int, l: int, iters: int, init, train=None, seed: int = 0,
+              mean=None, B=None, device: int = 0) -> "Index":
+        """Index built on the GPU from ``base`` (Alg 1-3); ``stage_ms`` holds the
+        stage times of the build."""
+        h, ms = tc_build_index(base, Ns, s, l, iters, init, train, seed, mean, B, device)
+        idx = cls(None, device, handle=h)
+        idx.stage_ms = ms
+        return idx
+
+    def save(self, path: str) -> None:
+        tc_save_index(self.handle, path)
 
     def close(self):
         if self.handle:

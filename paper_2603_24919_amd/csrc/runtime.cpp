@@ -17,6 +17,7 @@
 #include <string>
 #include <vector>
 
+#include "build.h"
 #include "kernels.h"
 #include "taco.h"
 
@@ -92,6 +93,7 @@ struct GraphKey {
 
 struct tc_index {
     int device = 0;
+    uint64_t seed = 0;  // build seed recorded in the index file
     int64_t n = 0;
     int d = 0, Ns = 0, s = 0, h1 = 0, h2 = 0, l = 0, M = 0, K = 0;
     // index on the device
@@ -503,48 +505,25 @@ int build_cdist(tc_index *x, int form) {
     return TC_OK;
 }
 
-int load(const char *path, int device, tc_index *x) {
-    Reader r;
-    r.f = fopen(path, "rb");
-    if (!r.f) return fail(TC_EIO, std::string("cannot open index file ") + path);
-    unsigned char hdr[128];
-    if (!r.read(hdr, sizeof hdr)) return fail(TC_EFORMAT, "index file shorter than its header");
-    uint32_t ver, hb;
-    int32_t dims[6];
-    memcpy(&ver, hdr + 8, 4);
-    memcpy(&hb, hdr + 12, 4);
-    memcpy(&x->n, hdr + 16, 8);
-    memcpy(dims, hdr + 24, 24);
-    if (memcmp(hdr, "TACOIDX1", 8) != 0 || ver != 1u || hb != 128u)
-        return fail(TC_EFORMAT, "not a version-1 TACOIDX1 index file");
-    x->d = dims[0];
-    x->Ns = dims[1];
-    x->s = dims[2];
-    x->h1 = dims[3];
-    x->h2 = dims[4];
-    x->l = dims[5];
+// Shape limits the kernels rely on; fills M and K.
+int check_shape(tc_index *x, int code) {
     x->M = x->Ns * x->s;
     x->K = x->l * x->l;
     if (x->n <= 0 || x->n >= (int64_t(1) << 31) || x->d <= 0 || x->Ns <= 0 || x->Ns > 16 ||
         int64_t(x->Ns) * x->n >= (int64_t(1) << 30) || x->s < 2 || x->M > x->d || x->l <= 0 ||
         x->l > 64 || x->h1 != x->s / 2 || x->h2 != x->s - x->s / 2)
-        return fail(TC_EFORMAT, "index shape out of range (need n < 2^31, Ns <= 16, Ns*n < 2^30, "
-                                "l <= 64, Ns*s <= d, halves s/2 and s - s/2)");
-    const size_t n = size_t(x->n), d = size_t(x->d), Ns = size_t(x->Ns), l = size_t(x->l),
-                 K = size_t(x->K), M = size_t(x->M);
-    std::vector<float> mean(d), B(d * M), C1(Ns * l * x->h1), C2(Ns * l * x->h2);
-    std::vector<uint64_t> off64(Ns * (K + 1));
-    std::vector<uint32_t> ids(Ns * n);
-    std::vector<float> base(n * d);
-    if (!r.read(mean.data(), 4 * mean.size()) || !r.read(B.data(), 4 * B.size()) ||
-        !r.read(C1.data(), 4 * C1.size()) || !r.read(C2.data(), 4 * C2.size()) ||
-        !r.read(off64.data(), 8 * off64.size()) || !r.read(ids.data(), 4 * ids.size()) ||
-        !r.read(base.data(), 4 * base.size()))
-        return fail(TC_EFORMAT, "index file truncated");
-    uint64_t want = 0;
-    const uint64_t got = r.sum.h;
-    if (fread(&want, 1, 8, r.f) != 8 || want != got)
-        return fail(TC_EFORMAT, "index checksum mismatch");
+        return fail(code, "index shape out of range (need n < 2^31, Ns <= 16, Ns*n < 2^30, "
+                          "l <= 64, Ns*s <= d, halves s/2 and s - s/2)");
+    return TC_OK;
+}
+
+// Checks the inverted lists and puts an index on the device: the arrays of
+// the file layout on the host, the base rows from the host or the device.
+int install(tc_index *x, int device, const std::vector<float> &mean, const std::vector<float> &B,
+            const std::vector<float> &C1, const std::vector<float> &C2,
+            const std::vector<uint64_t> &off64, const std::vector<uint32_t> &ids,
+            const float *base_host, const float *base_dev) {
+    const size_t n = size_t(x->n), d = size_t(x->d), Ns = size_t(x->Ns), K = size_t(x->K);
     // The kernels rely on these: offsets partition [0, n), ids are in range
     // and ascending inside each cell, every point appears once per subspace.
     std::vector<uint32_t> offs(Ns * (K + 1));
@@ -588,7 +567,10 @@ int load(const char *path, int device, tc_index *x) {
     x->C2h = C2;
     if ((rc = upload(&x->offs, offs, "cell offsets"))) return rc;
     if ((rc = upload(&x->ids, ids, "cell ids"))) return rc;
-    if ((rc = upload(&x->base, base, "base vectors"))) return rc;
+    if ((rc = dmalloc(&x->base, n * d, "base vectors"))) return rc;
+    TC_HIP(hipMemcpy(x->base, base_dev ? base_dev : base_host, sizeof(float) * n * d,
+                     base_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice),
+           "base vectors");
     if ((rc = dmalloc(&x->err, 1, "error word"))) return rc;
     TC_HIP(hipMemset(x->err, 0, sizeof(uint32_t)), "clearing the error word");
     // Counts are 4-bit when they cannot exceed 15.  Default tile: 64 KB of
@@ -601,6 +583,47 @@ int load(const char *path, int device, tc_index *x) {
     if ((rc = build_tiles(x))) return rc;
     if ((rc = alloc_scratch(x))) return rc;
     return TC_OK;
+}
+
+int load(const char *path, int device, tc_index *x) {
+    Reader r;
+    r.f = fopen(path, "rb");
+    if (!r.f) return fail(TC_EIO, std::string("cannot open index file ") + path);
+    unsigned char hdr[128];
+    if (!r.read(hdr, sizeof hdr)) return fail(TC_EFORMAT, "index file shorter than its header");
+    uint32_t ver, hb;
+    int32_t dims[6];
+    memcpy(&ver, hdr + 8, 4);
+    memcpy(&hb, hdr + 12, 4);
+    memcpy(&x->n, hdr + 16, 8);
+    memcpy(dims, hdr + 24, 24);
+    memcpy(&x->seed, hdr + 48, 8);
+    if (memcmp(hdr, "TACOIDX1", 8) != 0 || ver != 1u || hb != 128u)
+        return fail(TC_EFORMAT, "not a version-1 TACOIDX1 index file");
+    x->d = dims[0];
+    x->Ns = dims[1];
+    x->s = dims[2];
+    x->h1 = dims[3];
+    x->h2 = dims[4];
+    x->l = dims[5];
+    int rc;
+    if ((rc = check_shape(x, TC_EFORMAT))) return rc;
+    const size_t n = size_t(x->n), d = size_t(x->d), Ns = size_t(x->Ns), l = size_t(x->l),
+                 K = size_t(x->K), M = size_t(x->M);
+    std::vector<float> mean(d), B(d * M), C1(Ns * l * x->h1), C2(Ns * l * x->h2);
+    std::vector<uint64_t> off64(Ns * (K + 1));
+    std::vector<uint32_t> ids(Ns * n);
+    std::vector<float> base(n * d);
+    if (!r.read(mean.data(), 4 * mean.size()) || !r.read(B.data(), 4 * B.size()) ||
+        !r.read(C1.data(), 4 * C1.size()) || !r.read(C2.data(), 4 * C2.size()) ||
+        !r.read(off64.data(), 8 * off64.size()) || !r.read(ids.data(), 4 * ids.size()) ||
+        !r.read(base.data(), 4 * base.size()))
+        return fail(TC_EFORMAT, "index file truncated");
+    uint64_t want = 0;
+    const uint64_t got = r.sum.h;
+    if (fread(&want, 1, 8, r.f) != 8 || want != got)
+        return fail(TC_EFORMAT, "index checksum mismatch");
+    return install(x, device, mean, B, C1, C2, off64, ids, base.data(), nullptr);
 }
 
 void record(tc_index *x, int kern, hipStream_t st, bool begin) {
@@ -1298,5 +1321,400 @@ int tc_batch_capacity(const tc_index *x, int64_t *qpb) {
 }
 
 const char *tc_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Index construction on the GPU (Alg 1-3) and index files.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Device buffers of one call, freed on every exit path.
+struct BuildBuffers {
+    std::vector<void *> ptrs;
+    ~BuildBuffers() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    int get(T **p, size_t count, const char *what) {
+        *p = nullptr;
+        void *v = nullptr;
+        if (hipMalloc(&v, sizeof(T) * std::max<size_t>(count, 1)) != hipSuccess)
+            return fail(TC_ENOMEM, std::string("device allocation failed: ") + what);
+        ptrs.push_back(v);
+        *p = static_cast<T *>(v);
+        return TC_OK;
+    }
+};
+
+struct StreamEvents {
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> ev;
+    ~StreamEvents() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        if (st) (void)hipStreamDestroy(st);
+    }
+};
+
+// Alg 2 (eigensystem allocation).  Eigenvalues are floored at 1e-12 of the
+// largest and scaled by the smallest so that all are >= 1; taken in
+// descending order (ties keep the lower index), each goes to the bucket with
+// the smallest product of eigenvalues among those holding fewer than s, the
+// lowest such bucket on ties.  Products are compared as FP64 sums of logs.
+// cols = the buckets concatenated, each in append order.
+int allocate_eigenpairs(const double *evals, int d, int Ns, int s, int32_t *cols) {
+    if (!evals || !cols) return fail(TC_EINVAL, "evals or cols is NULL");
+    if (d <= 0 || Ns <= 0 || s <= 0 || int64_t(Ns) * s > d) return fail(TC_EINVAL, "need Ns*s <= d");
+    std::vector<double> lam(evals, evals + d);
+    double mx = lam[0];
+    for (double v : lam) mx = std::max(mx, v);
+    for (double &v : lam) v = std::max(v, 1e-12 * mx);
+    double mn = lam[0];
+    for (double v : lam) mn = std::min(mn, v);
+    if (!(mn > 0.0)) return fail(TC_EINVAL, "the covariance has no positive eigenvalue");
+    for (double &v : lam) v = v / mn;
+    std::vector<int> order(d);
+    for (int i = 0; i < d; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lam[a] > lam[b]; });
+    std::vector<double> logp(Ns, 0.0);
+    std::vector<std::vector<int>> bucket(Ns);
+    for (int i = 0; i < Ns * s; i++) {
+        const int e = order[i];
+        int best = -1;
+        for (int j = 0; j < Ns; j++)
+            if (int(bucket[j].size()) < s && (best < 0 || logp[j] < logp[best])) best = j;
+        bucket[best].push_back(e);
+        logp[best] += std::log(lam[e]);
+    }
+    int m = 0;
+    for (int j = 0; j < Ns; j++)
+        for (int e : bucket[j]) cols[m++] = e;
+    return TC_OK;
+}
+
+// T = B^T (X - mean) row by row, in launches of at most 2^19 rows.
+hipError_t transform_rows(const float *X, int64_t n, int d, const float *mean, const float *B, int M,
+                          float *T, hipStream_t st) {
+    const int64_t step = int64_t(1) << 19;
+    for (int64_t r = 0; r < n; r += step) {
+        const int rows = static_cast<int>(std::min(step, n - r));
+        hipError_t e = taco::launch_transform(X + r * d, rows, d, mean, B, M, T + r * M, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int check_kmeans_args(int64_t n, int ld, int Ns, int s, int l, int iters, const int64_t *init,
+                      const int64_t *train, int64_t nt) {
+    if (n <= 0 || Ns <= 0 || s < 2 || int64_t(Ns) * s > ld || l < 1 || l > 64 || iters < 0)
+        return fail(TC_EINVAL, "k-means shape out of range (l <= 64, Ns*s <= ld, s >= 2)");
+    if (s - s / 2 > taco::bld::KM_HMAX) return fail(TC_EINVAL, "half-subspace wider than 32");
+    if (!init) return fail(TC_EINVAL, "init is NULL");
+    if (nt < l || nt > n) return fail(TC_EINVAL, "the training sample must hold between l and n points");
+    for (int64_t i = 0; i < 2 * int64_t(Ns) * l; i++)
+        if (init[i] < 0 || init[i] >= nt) return fail(TC_EINVAL, "seed position outside the training sample");
+    if (train)
+        for (int64_t p = 0; p < nt; p++)
+            if (train[p] < 0 || train[p] >= n) return fail(TC_EINVAL, "training row out of range");
+    return TC_OK;
+}
+
+// k-means of every half plus the final labels, on stream st.
+int run_kmeans(BuildBuffers &bb, const float *T, int64_t n, int ld, int Ns, int s, int l, int iters,
+               const int64_t *init, const int64_t *train, int64_t nt, float *cent, int32_t *assign,
+               hipStream_t st) {
+    int64_t *dinit = nullptr, *dtrain = nullptr;
+    int rc;
+    const size_t ni = 2 * size_t(Ns) * l;
+    if ((rc = bb.get(&dinit, ni, "k-means seeds"))) return rc;
+    TC_HIP(hipMemcpyAsync(dinit, init, sizeof(int64_t) * ni, hipMemcpyHostToDevice, st), "k-means seeds");
+    if (train) {
+        if ((rc = bb.get(&dtrain, size_t(nt), "training rows"))) return rc;
+        TC_HIP(hipMemcpyAsync(dtrain, train, sizeof(int64_t) * size_t(nt), hipMemcpyHostToDevice, st),
+               "training rows");
+    }
+    taco::bld::KmArgs a;
+    a.T = T;
+    a.n = n;
+    a.ld = ld;
+    a.Ns = Ns;
+    a.s = s;
+    a.l = l;
+    a.iters = iters;
+    a.init = dinit;
+    a.train = dtrain;
+    a.nt = nt;
+    unsigned char *scr = nullptr;
+    if ((rc = bb.get(&scr, taco::bld::km_scratch_bytes(a), "k-means scratch"))) return rc;
+    TC_HIP(taco::bld::launch_kmeans(a, cent, assign, scr, st), "k-means");
+    return TC_OK;
+}
+
+int run_imi(BuildBuffers &bb, const int32_t *assign, int64_t n, int Ns, int l, uint32_t *offsets,
+            uint32_t *ids, hipStream_t st) {
+    uint32_t *scr = nullptr;
+    int rc;
+    if ((rc = bb.get(&scr, taco::bld::imi_scratch_words(n, Ns, l), "IMI scratch"))) return rc;
+    TC_HIP(taco::bld::launch_imi(assign, n, Ns, l, offsets, ids, scr, st), "IMI");
+    return TC_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.0f;
+    return ms;
+}
+
+int build(const float *X, int64_t n, int d, int Ns, int s, int l, int iters, const int64_t *init,
+          const int64_t *train, int64_t n_train, uint64_t seed, const float *mean_in, const float *B_in,
+          int device, tc_index *x, double *stage_ms) {
+    if (!X) return fail(TC_EINVAL, "base is NULL");
+    x->n = n;
+    x->d = d;
+    x->Ns = Ns;
+    x->s = s;
+    x->h1 = s / 2;
+    x->h2 = s - s / 2;
+    x->l = l;
+    x->seed = seed;
+    int rc;
+    if ((rc = check_shape(x, TC_EINVAL))) return rc;
+    if (n < 2) return fail(TC_EINVAL, "the covariance needs n >= 2");
+    if ((mean_in == nullptr) != (B_in == nullptr)) return fail(TC_EINVAL, "give both mean and B, or neither");
+    if (!B_in && d > taco::bld::EIG_MAX)
+        return fail(TC_EINVAL, "the GPU eigensolver takes d <= 128; pass mean and B for a larger d");
+    const int64_t nt = train ? n_train : n;
+    const int M = Ns * s, K = l * l, G = 2 * Ns, HM = s - s / 2;
+    if ((rc = check_kmeans_args(n, M, Ns, s, l, iters, init, train, nt))) return rc;
+    int ndev = 0;
+    TC_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(TC_EINVAL, "no such HIP device");
+    DeviceGuard g(device);
+    StreamEvents se;
+    TC_HIP(hipStreamCreateWithFlags(&se.st, hipStreamNonBlocking), "hipStreamCreate");
+    se.ev.resize(7);
+    for (auto &e : se.ev) TC_HIP(hipEventCreate(&e), "hipEventCreate");
+    hipStream_t st = se.st;
+    BuildBuffers bb;
+    std::vector<float> mean32(d), B32(size_t(d) * M);
+    TC_HIP(hipEventRecord(se.ev[0], st), "hipEventRecord");
+    if (!B_in) {
+        double *mean64, *cov, *sscr, *evals, *evecs, *escr;
+        if ((rc = bb.get(&mean64, d, "mean")) || (rc = bb.get(&cov, size_t(d) * d, "covariance")) ||
+            (rc = bb.get(&sscr, taco::bld::stats_scratch(n, d), "statistics scratch")) ||
+            (rc = bb.get(&evals, d, "eigenvalues")) || (rc = bb.get(&evecs, size_t(d) * d, "eigenvectors")) ||
+            (rc = bb.get(&escr, taco::bld::eigen_scratch(d), "rotations")))
+            return rc;
+        TC_HIP(taco::bld::launch_stats(X, n, d, mean64, cov, sscr, st), "mean and covariance");
+        TC_HIP(hipEventRecord(se.ev[1], st), "hipEventRecord");
+        TC_HIP(taco::bld::launch_eigen(cov, d, evals, evecs, escr, st), "eigensolver");
+        TC_HIP(hipEventRecord(se.ev[2], st), "hipEventRecord");
+        std::vector<double> hm(d), hl(d), hv(size_t(d) * d);
+        TC_HIP(hipMemcpyAsync(hm.data(), mean64, sizeof(double) * d, hipMemcpyDeviceToHost, st), "mean");
+        TC_HIP(hipMemcpyAsync(hl.data(), evals, sizeof(double) * d, hipMemcpyDeviceToHost, st), "eigenvalues");
+        TC_HIP(hipMemcpyAsync(hv.data(), evecs, sizeof(double) * d * d, hipMemcpyDeviceToHost, st), "eigenvectors");
+        TC_HIP(hipStreamSynchronize(st), "statistics");
+        std::vector<int32_t> cols(M);
+        if ((rc = allocate_eigenpairs(hl.data(), d, Ns, s, cols.data()))) return rc;
+        for (int r = 0; r < d; r++)
+            for (int m = 0; m < M; m++) B32[size_t(r) * M + m] = static_cast<float>(hv[size_t(r) * d + cols[m]]);
+        for (int t = 0; t < d; t++) mean32[t] = static_cast<float>(hm[t]);
+    } else {
+        TC_HIP(hipEventRecord(se.ev[1], st), "hipEventRecord");
+        TC_HIP(hipEventRecord(se.ev[2], st), "hipEventRecord");
+        std::copy(mean_in, mean_in + d, mean32.begin());
+        std::copy(B_in, B_in + size_t(d) * M, B32.begin());
+    }
+    float *dmean, *dB, *T, *cent;
+    int32_t *assign;
+    uint32_t *offs, *ids;
+    if ((rc = bb.get(&dmean, d, "mean")) || (rc = bb.get(&dB, size_t(d) * M, "transform")) ||
+        (rc = bb.get(&T, size_t(n) * M, "transformed base")) ||
+        (rc = bb.get(&cent, size_t(G) * l * HM, "centroids")) ||
+        (rc = bb.get(&assign, size_t(G) * n, "labels")) ||
+        (rc = bb.get(&offs, size_t(Ns) * (K + 1), "cell offsets")) || (rc = bb.get(&ids, size_t(Ns) * n, "cell ids")))
+        return rc;
+    TC_HIP(hipMemcpyAsync(dmean, mean32.data(), sizeof(float) * d, hipMemcpyHostToDevice, st), "mean");
+    TC_HIP(hipMemcpyAsync(dB, B32.data(), sizeof(float) * B32.size(), hipMemcpyHostToDevice, st), "transform");
+    TC_HIP(hipEventRecord(se.ev[3], st), "hipEventRecord");
+    TC_HIP(transform_rows(X, n, d, dmean, dB, M, T, st), "transform");
+    TC_HIP(hipEventRecord(se.ev[4], st), "hipEventRecord");
+    if ((rc = run_kmeans(bb, T, n, M, Ns, s, l, iters, init, train, nt, cent, assign, st))) return rc;
+    TC_HIP(hipEventRecord(se.ev[5], st), "hipEventRecord");
+    if ((rc = run_imi(bb, assign, n, Ns, l, offs, ids, st))) return rc;
+    TC_HIP(hipEventRecord(se.ev[6], st), "hipEventRecord");
+    std::vector<float> hc(size_t(G) * l * HM);
+    std::vector<uint32_t> ho(size_t(Ns) * (K + 1)), hids(size_t(Ns) * n);
+    TC_HIP(hipMemcpyAsync(hc.data(), cent, sizeof(float) * hc.size(), hipMemcpyDeviceToHost, st), "centroids");
+    TC_HIP(hipMemcpyAsync(ho.data(), offs, sizeof(uint32_t) * ho.size(), hipMemcpyDeviceToHost, st), "offsets");
+    TC_HIP(hipMemcpyAsync(hids.data(), ids, sizeof(uint32_t) * hids.size(), hipMemcpyDeviceToHost, st), "ids");
+    TC_HIP(hipStreamSynchronize(st), "index build");
+    if (stage_ms)
+        for (int i = 0; i < 6; i++) stage_ms[i] = elapsed(se.ev[i], se.ev[i + 1]);
+    const int h1 = s / 2, h2 = s - s / 2;
+    std::vector<float> C1(size_t(Ns) * l * h1), C2(size_t(Ns) * l * h2);
+    for (int j = 0; j < Ns; j++)
+        for (int c = 0; c < l; c++) {
+            for (int t = 0; t < h1; t++) C1[(size_t(j) * l + c) * h1 + t] = hc[((size_t(2 * j)) * l + c) * HM + t];
+            for (int t = 0; t < h2; t++) C2[(size_t(j) * l + c) * h2 + t] = hc[((size_t(2 * j + 1)) * l + c) * HM + t];
+        }
+    std::vector<uint64_t> off64(ho.begin(), ho.end());
+    return install(x, device, mean32, B32, C1, C2, off64, hids, nullptr, X);
+}
+
+int save(const tc_index *x, const char *path) {
+    DeviceGuard g(x->device);
+    const size_t n = size_t(x->n), d = size_t(x->d), Ns = size_t(x->Ns), K = size_t(x->K), M = size_t(x->M);
+    std::vector<float> B(d * M), base(n * d);
+    std::vector<uint32_t> offs(Ns * (K + 1)), ids(Ns * n);
+    TC_HIP(hipMemcpy(B.data(), x->B, sizeof(float) * B.size(), hipMemcpyDeviceToHost), "transform");
+    TC_HIP(hipMemcpy(offs.data(), x->offs, sizeof(uint32_t) * offs.size(), hipMemcpyDeviceToHost), "offsets");
+    TC_HIP(hipMemcpy(ids.data(), x->ids, sizeof(uint32_t) * ids.size(), hipMemcpyDeviceToHost), "ids");
+    TC_HIP(hipMemcpy(base.data(), x->base, sizeof(float) * base.size(), hipMemcpyDeviceToHost), "base");
+    std::vector<uint64_t> off64(offs.begin(), offs.end());
+    unsigned char hdr[128];
+    memset(hdr, 0, sizeof hdr);
+    const uint32_t ver = 1, hb = 128;
+    const uint64_t flags = 0;
+    const int32_t dims[6] = {x->d, x->Ns, x->s, x->h1, x->h2, x->l};
+    memcpy(hdr, "TACOIDX1", 8);
+    memcpy(hdr + 8, &ver, 4);
+    memcpy(hdr + 12, &hb, 4);
+    memcpy(hdr + 16, &x->n, 8);
+    memcpy(hdr + 24, dims, 24);
+    memcpy(hdr + 48, &x->seed, 8);
+    memcpy(hdr + 56, &flags, 8);
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(TC_EIO, std::string("cannot create index file ") + path);
+    Fnv sum;
+    bool ok = true;
+    auto put = [&](const void *p, size_t nb) {
+        sum.add(p, nb);
+        ok = ok && fwrite(p, 1, nb, f) == nb;
+    };
+    put(hdr, sizeof hdr);
+    put(x->mean_host.data(), 4 * d);
+    put(B.data(), 4 * B.size());
+    put(x->C1h.data(), 4 * x->C1h.size());
+    put(x->C2h.data(), 4 * x->C2h.size());
+    put(off64.data(), 8 * off64.size());
+    put(ids.data(), 4 * ids.size());
+    put(base.data(), 4 * base.size());
+    ok = ok && fwrite(&sum.h, 1, 8, f) == 8;
+    ok = (fclose(f) == 0) && ok;
+    return ok ? TC_OK : fail(TC_EIO, std::string("cannot write index file ") + path);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tc_build_stats(const float *X, int64_t n, int32_t d, double *mean, double *cov, void *stream) {
+    if (!X || !mean || !cov) return fail(TC_EINVAL, "NULL buffer");
+    if (n < 2 || d < 1) return fail(TC_EINVAL, "need n >= 2 and d >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BuildBuffers bb;
+    double *scr;
+    int rc;
+    if ((rc = bb.get(&scr, taco::bld::stats_scratch(n, d), "statistics scratch"))) return rc;
+    TC_HIP(taco::bld::launch_stats(X, n, d, mean, cov, scr, st), "mean and covariance");
+    TC_HIP(hipStreamSynchronize(st), "mean and covariance");
+    return TC_OK;
+}
+
+int tc_build_eigen(const double *cov, int32_t d, double *evals, double *evecs, void *stream) {
+    if (!cov || !evals || !evecs) return fail(TC_EINVAL, "NULL buffer");
+    if (d < 1 || d > taco::bld::EIG_MAX) return fail(TC_EINVAL, "the GPU eigensolver takes 1 <= d <= 128");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BuildBuffers bb;
+    double *scr;
+    int rc;
+    if ((rc = bb.get(&scr, taco::bld::eigen_scratch(d), "rotations"))) return rc;
+    TC_HIP(taco::bld::launch_eigen(cov, d, evals, evecs, scr, st), "eigensolver");
+    TC_HIP(hipStreamSynchronize(st), "eigensolver");
+    return TC_OK;
+}
+
+int tc_build_allocate(const double *evals, int32_t d, int32_t Ns, int32_t s, int32_t *cols) {
+    return allocate_eigenpairs(evals, d, Ns, s, cols);
+}
+
+int tc_build_transform(const float *X, int64_t n, int32_t d, const float *mean, const float *B, int32_t M,
+                       float *T, void *stream) {
+    if (!X || !mean || !B || !T) return fail(TC_EINVAL, "NULL buffer");
+    if (n < 0 || d < 1 || M < 1 || M > d) return fail(TC_EINVAL, "need n >= 0 and 1 <= M <= d");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    TC_HIP(transform_rows(X, n, d, mean, B, M, T, st), "transform");
+    TC_HIP(hipStreamSynchronize(st), "transform");
+    return TC_OK;
+}
+
+int tc_build_kmeans(const float *T, int64_t n, int32_t ld, int32_t Ns, int32_t s, int32_t l, int32_t iters,
+                    const int64_t *init, const int64_t *train, int64_t n_train, float *cent,
+                    int32_t *assign, void *stream) {
+    if (!T || !cent || !assign) return fail(TC_EINVAL, "NULL buffer");
+    const int64_t nt = train ? n_train : n;
+    int rc;
+    if ((rc = check_kmeans_args(n, ld, Ns, s, l, iters, init, train, nt))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BuildBuffers bb;
+    if ((rc = run_kmeans(bb, T, n, ld, Ns, s, l, iters, init, train, nt, cent, assign, st))) return rc;
+    TC_HIP(hipStreamSynchronize(st), "k-means");
+    return TC_OK;
+}
+
+int tc_build_imi(const int32_t *assign, int64_t n, int32_t Ns, int32_t l, uint32_t *offsets, uint32_t *ids,
+                 void *stream) {
+    if (!assign || !offsets || !ids) return fail(TC_EINVAL, "NULL buffer");
+    if (n <= 0 || n >= (int64_t(1) << 31) || Ns < 1 || l < 1 || l * l > taco::bld::IMI_KMAX)
+        return fail(TC_EINVAL, "need 0 < n < 2^31, Ns >= 1 and l*l <= 4096");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    BuildBuffers bb;
+    int rc;
+    if ((rc = run_imi(bb, assign, n, Ns, l, offsets, ids, st))) return rc;
+    std::vector<uint32_t> ends(Ns);
+    for (int j = 0; j < Ns; j++)
+        TC_HIP(hipMemcpyAsync(&ends[j], offsets + (size_t(j) + 1) * (size_t(l) * l + 1) - 1, sizeof(uint32_t),
+                              hipMemcpyDeviceToHost, st),
+               "offsets");
+    TC_HIP(hipStreamSynchronize(st), "IMI");
+    for (int j = 0; j < Ns; j++)
+        if (ends[j] != uint32_t(n)) return fail(TC_EINVAL, "a label lies outside [0, l)");
+    return TC_OK;
+}
+
+int tc_build_index(const float *base, int64_t n, int32_t d, int32_t Ns, int32_t s, int32_t l, int32_t iters,
+                   const int64_t *init, const int64_t *train, int64_t n_train, uint64_t seed,
+                   const float *mean, const float *B, int device, tc_index **out, double *stage_ms) {
+    if (!out) return fail(TC_EINVAL, "out is NULL");
+    *out = nullptr;
+    tc_index *x = new (std::nothrow) tc_index();
+    if (!x) return fail(TC_ENOMEM, "host allocation failed");
+    int rc;
+    try {
+        rc = build(base, n, d, Ns, s, l, iters, init, train, n_train, seed, mean, B, device, x, stage_ms);
+    } catch (const std::bad_alloc &) {
+        rc = fail(TC_ENOMEM, "host allocation failed while building the index");
+    }
+    if (rc != TC_OK) {
+        DeviceGuard g(x->device);
+        free_all(x);
+        delete x;
+        return rc;
+    }
+    *out = x;
+    g_err.clear();
+    return TC_OK;
+}
+
+int tc_save_index(const tc_index *x, const char *path) {
+    if (!x || !path) return fail(TC_EINVAL, "index or path is NULL");
+    try {
+        return save(x, path);
+    } catch (const std::bad_alloc &) {
+        return fail(TC_ENOMEM, "host allocation failed while writing the index");
+    }
+}
 
 }  // extern "C"
