@@ -62,18 +62,46 @@ def log(msg):
 # ---------------------------------------------------------------------------
 
 def cpu_baseline_index(w, X):
-    """Serialized index built by the oracle from the workload seed (cached)."""
+    """Serialized index built by the oracle from the workload seed (cached).
+    Returns (path, seconds the oracle's build took, or None when cached)."""
     from oracle import oracle as O
     cache = os.environ.get("TACO_CACHE") or os.path.join(ROOT, ".taco_cache")
     os.makedirs(cache, exist_ok=True)
     path = os.path.join(cache, f"{w.name}-n{w.n}-s{w.seed:x}.tcx")
+    built_s = None
     if not os.path.exists(path):
         t = time.time()
         tmp = path + ".tmp%d" % os.getpid()
         O.build_workload_index(w, tmp, X)
         os.replace(tmp, path)
-        log(f"oracle built the index in {time.time() - t:.1f}s -> {path}")
-    return path
+        built_s = time.time() - t
+        log(f"oracle built the index in {built_s:.1f}s on {O.max_threads()} threads -> {path}")
+    return path, built_s
+
+
+BUILD_STAGES = ("stats", "eigen", "allocate", "transform", "kmeans", "imi")
+
+
+def gpu_build_leg(taco, torch, w, X, dev, reps):
+    """Alg 1-3 on the GPU from the base already resident in HBM: the
+    library's HIP-event times of each stage (statistics, eigensolver, Alg 2
+    and uploads, transform, k-means, IMI); one warm-up build, then the
+    fastest of ``reps``."""
+    xb = torch.from_numpy(X).to(dev)
+    train, init = synthdata.kmeans_seeding(w)
+    runs = []
+    for r in range(reps + 1):
+        idx = taco.Index.build(xb, w.Ns, w.s, w.l, w.iters, init, train, w.seed)
+        ms = np.array(idx.stage_ms, dtype=float)
+        idx.close()
+        if r:
+            runs.append(ms)
+    del xb
+    best = min(runs, key=lambda m: float(m.sum()))
+    return dict(workload=WORKLOAD, n=w.n, d=w.d, Ns=w.Ns, s=w.s, l=w.l, kmeans_iters=w.iters,
+                gpu_ms=float(best.sum()), stages_ms=dict(zip(BUILD_STAGES, map(float, best))),
+                reps=reps, timing="HIP events around each stage, base resident in HBM; the "
+                                  "index's search preparation and the host copies excluded")
 
 
 def cpu_baseline_timing(path, X, Q, w, kth, alphas, sample):
@@ -299,6 +327,11 @@ def short_kernel_name(full):
     for key, short in _SHORT:
         if "taco::" + key + "<" in full or "taco::" + key + "(" in full:
             return short
+    if "taco::bld::" in full:
+        # index-build kernels: build_<name without the k_ prefix>
+        rest = full.split("taco::bld::", 1)[1].replace("(anonymous namespace)::", "")
+        name = rest.split("(", 1)[0].split("<", 1)[0].split("::")[-1]
+        return "build_" + (name[2:] if name.startswith("k_") else name)
     return None
 
 
@@ -431,6 +464,8 @@ def main():
                     help="comma list of fp32 (defaults), tuned (autotuned, exact), lowp (tuned + FP8 "
                          "centroid distances on the matrix cores)")
     ap.add_argument("--skip-precision-report", action="store_true")
+    ap.add_argument("--skip-build", action="store_true", help="omit the GPU index-build leg")
+    ap.add_argument("--build-reps", type=int, default=3)
     ap.add_argument("--skip-cpu-baseline", action="store_true",
                     help="omit the oracle timing (profiling runs); the line then has no cpu_baseline")
     ap.add_argument("--tune-cache", default=None,
@@ -463,7 +498,7 @@ def main():
     t0 = time.time()
     X, Q = synthdata.base_and_queries(w)
     log(f"generated {w.n}x{w.d} base and {w.nq} queries in {time.time() - t0:.1f}s")
-    path = cpu_baseline_index(w, X)
+    path, oracle_build_s = cpu_baseline_index(w, X)
     S = min(args.recall_sample, w.nq)
     t0 = time.time()
     kth = kth_neighbour_fp64(X, Q[:S], w.k)
@@ -555,6 +590,16 @@ def main():
                     traffic=traffic, alg_bytes_per_launch=dk["alg_bytes_per_launch"],
                     ms_per_launch=dk["ms_per_launch"], alpha=op["alpha"], path=main_path)
 
+    build = None
+    if not args.skip_build:
+        t0 = time.time()
+        build = gpu_build_leg(taco, torch, w, X, dev, args.build_reps)
+        build["oracle_s"] = oracle_build_s
+        build["oracle_note"] = ("the oracle's build of the same index (Alg 1-3, OpenMP over points) in "
+                                "this run" if oracle_build_s is not None else "index cached: not timed")
+        log(f"GPU index build: {build['gpu_ms']:.1f} ms (" + ", ".join(
+            f"{k} {v:.2f}" for k, v in build["stages_ms"].items()) + f") in {time.time() - t0:.1f}s")
+
     precision = None
     if not args.skip_precision_report:
         t0 = time.time()
@@ -594,7 +639,7 @@ def main():
                                               for k_, v in p["kernels"].items() if v["launches"]})
                                 for p in sw])
                for pn, sw in results.items()},
-        roofline=roofline, cpu_baseline=cpu, precision=precision)
+        roofline=roofline, cpu_baseline=cpu, precision=precision, index_build=build)
     print(json.dumps(line), flush=True)
 
 

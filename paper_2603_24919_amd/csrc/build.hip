@@ -295,9 +295,11 @@ __device__ __forceinline__ Half half_of(int g, int s) {
 __device__ __forceinline__ int64_t row_of(const int64_t *train, int64_t p) { return train ? train[p] : p; }
 
 // cent[g][c][:h] = the seed point's half, in FP64.
-__global__ __launch_bounds__(256) void k_km_seed(KmArgs a, int HM, double *__restrict__ cent) {
+__global__ __launch_bounds__(256) void k_km_seed(KmArgs a, int HM, int nblk, double *__restrict__ cent,
+                                                 uint32_t *__restrict__ pcnt) {
     const int g = blockIdx.x;
     const Half H = half_of(g, a.s);
+    for (int i = threadIdx.x; i < nblk * a.l; i += 256) pcnt[static_cast<int64_t>(g) * nblk * a.l + i] = 0u;
     for (int i = threadIdx.x; i < a.l * H.h; i += 256) {
         const int c = i / H.h, t = i % H.h;
         const int64_t r = row_of(a.train, a.init[static_cast<int64_t>(g) * a.l + c]);
@@ -307,88 +309,160 @@ __global__ __launch_bounds__(256) void k_km_seed(KmArgs a, int HM, double *__res
 
 // Label and FP64 distance of each sample point to its nearest centroid.
 // grid (ceil(nt/256), 2*Ns).
+static_assert(KM_BLOCK % 256 == 0, "a label-counting workgroup must lie in one block");
+
+// Also counts the labels of each partial-sum block: a workgroup's 256
+// positions lie in one block (KM_BLOCK is a multiple of 256); integer adds
+// in any order give the same counts.
 template <int HX>
-__global__ __launch_bounds__(256) void k_km_assign(KmArgs a, int HM, const double *__restrict__ cent,
-                                                   int32_t *__restrict__ lab, double *__restrict__ far) {
+__global__ __launch_bounds__(256) void k_km_assign(KmArgs a, int HM, int nblk, const double *__restrict__ cent,
+                                                   int32_t *__restrict__ lab, double *__restrict__ far,
+                                                   uint32_t *__restrict__ pcnt) {
     __shared__ double C[64 * HX];
+    __shared__ uint32_t hc[64];
     const int g = blockIdx.y;
     const Half H = half_of(g, a.s);
     for (int i = threadIdx.x; i < a.l * H.h; i += 256)
         C[i] = cent[(static_cast<int64_t>(g) * a.l + i / H.h) * HM + i % H.h];
+    if (threadIdx.x < 64) hc[threadIdx.x] = 0;
     __syncthreads();
     const int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    if (p >= a.nt) return;
-    const float *x = a.T + row_of(a.train, p) * a.ld + H.off;
-    double xv[HX];
-#pragma unroll
-    for (int t = 0; t < HX; t++) xv[t] = t < H.h ? static_cast<double>(x[t]) : 0.0;
-    int best = 0;
-    double bd = 0.0;
-    for (int c = 0; c < a.l; c++) {
-        double s = 0.0;
-#pragma unroll
-        for (int t = 0; t < HX; t++) {
-            if (t < H.h) {
-                const double u = xv[t] - C[c * H.h + t];
-                s += u * u;
-            }
-        }
-        if (c == 0 || s < bd) {
-            bd = s;
-            best = c;
-        }
-    }
-    lab[static_cast<int64_t>(g) * a.nt + p] = best;
-    far[static_cast<int64_t>(g) * a.nt + p] = bd;
-}
-
-constexpr int KM_CH = 256;       // sample positions staged per step
-constexpr int KM_PBLOCK = 512;   // threads of the partial-sum kernel
-
-// psum[g][b][c][t], pcnt[g][b][c]: sums of x_t and counts over the points of
-// block b labelled c, in ascending position order.  One thread per (c, t);
-// grid (nblk, 2*Ns).
-__global__ __launch_bounds__(KM_PBLOCK) void k_km_partial(KmArgs a, int HM, int nblk,
-                                                          const int32_t *__restrict__ lab,
-                                                          double *__restrict__ psum,
-                                                          uint32_t *__restrict__ pcnt) {
-    __shared__ int32_t L[KM_CH];
-    __shared__ float X[KM_CH * KM_HMAX];
-    const int g = blockIdx.y, b = blockIdx.x;
-    const Half H = half_of(g, a.s);
-    const int64_t lo = static_cast<int64_t>(b) * KM_BLOCK;
-    const int64_t hi = min(lo + KM_BLOCK, a.nt);
-    const int pairs = a.l * H.h;
-    for (int base = 0; base < pairs; base += KM_PBLOCK) {
-        const int idx = base + threadIdx.x;
-        const bool act = idx < pairs;
-        const int c = act ? idx / H.h : -1, t = act ? idx % H.h : 0;
-        double acc = 0.0;
-        uint32_t cnt = 0;
-        for (int64_t p0 = lo; p0 < hi; p0 += KM_CH) {
-            const int m = static_cast<int>(min<int64_t>(KM_CH, hi - p0));
-            for (int i = threadIdx.x; i < m; i += KM_PBLOCK) L[i] = lab[static_cast<int64_t>(g) * a.nt + p0 + i];
-            for (int i = threadIdx.x; i < m * H.h; i += KM_PBLOCK) {
-                const int pi = i / H.h, tt = i % H.h;
-                X[i] = a.T[row_of(a.train, p0 + pi) * a.ld + H.off + tt];
-            }
-            __syncthreads();
-            if (act) {
-                for (int i = 0; i < m; i++) {
-                    if (L[i] == c) {
-                        acc += static_cast<double>(X[i * H.h + t]);
-                        cnt++;
-                    }
+    const int64_t b = (static_cast<int64_t>(blockIdx.x) * 256) / KM_BLOCK;
+    if (p < a.nt) {
+        const float *x = a.T + row_of(a.train, p) * a.ld + H.off;
+        double xv[HX];
+    #pragma unroll
+        for (int t = 0; t < HX; t++) xv[t] = t < H.h ? static_cast<double>(x[t]) : 0.0;
+        int best = 0;
+        double bd = 0.0;
+        for (int c = 0; c < a.l; c++) {
+            double s = 0.0;
+    #pragma unroll
+            for (int t = 0; t < HX; t++) {
+                if (t < H.h) {
+                    const double u = xv[t] - C[c * H.h + t];
+                    s += u * u;
                 }
             }
-            __syncthreads();
+            if (c == 0 || s < bd) {
+                bd = s;
+                best = c;
+            }
         }
-        if (act) {
-            const int64_t o = (static_cast<int64_t>(g) * nblk + b) * a.l + c;
-            psum[o * HM + t] = acc;
-            if (t == 0) pcnt[o] = cnt;
+        lab[static_cast<int64_t>(g) * a.nt + p] = best;
+        far[static_cast<int64_t>(g) * a.nt + p] = bd;
+        atomicAdd(&hc[best], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < a.l && hc[threadIdx.x])
+        atomicAdd(&pcnt[(static_cast<int64_t>(g) * nblk + b) * a.l + threadIdx.x], hc[threadIdx.x]);
+}
+
+constexpr int KM_PBLOCK = 512;                   // threads of the partial-sum kernel
+constexpr int KM_PW = KM_PBLOCK / WAVE;           // its waves
+constexpr int KM_XVALS = 4096;                    // staged values per chunk
+constexpr int KM_XPT = KM_XVALS / KM_PBLOCK;      // staged values per thread
+constexpr int KM_PPT = 64 * KM_HMAX / KM_PBLOCK;  // (cluster, dim) pairs per thread
+
+// psum[g][b][c][t]: sums of x_t over the points of block b labelled c, in
+// ascending position order.  grid (nblk, 2*Ns).  The block streams through
+// LDS in chunks of ch = min(512, 4096/h) points, thread j holding point j of
+// the chunk; the next chunk is loaded into registers while the current one
+// is summed.  Per chunk, the points are listed cluster by cluster in position
+// order (a stable counting sort: per-wave membership masks, prefix sums over
+// waves and clusters), then each (cluster, dim) pair adds its own cluster's
+// points in list order, i.e. in position order.
+__global__ __launch_bounds__(KM_PBLOCK) void k_km_partial(KmArgs a, int HM, int nblk,
+                                                          const int32_t *__restrict__ lab,
+                                                          double *__restrict__ psum) {
+    __shared__ float X[2][KM_XVALS];
+    __shared__ unsigned long long wm[2][KM_PW][64];  // wm[.][w][c]: lanes of wave w labelled c
+    __shared__ uint32_t wbase[KM_PW][64];            // points of cluster c in earlier waves
+    __shared__ uint32_t cst[64], ctot[64];           // list start and size of cluster c
+    __shared__ uint16_t list[KM_PBLOCK];
+    const int g = blockIdx.y, b = blockIdx.x, tid = threadIdx.x;
+    const int lane = tid % WAVE, w = tid / WAVE;
+    const Half H = half_of(g, a.s);
+    const int hh = H.h;
+    const int ch = min(KM_PBLOCK, KM_XVALS / hh);
+    const int64_t lo = static_cast<int64_t>(b) * KM_BLOCK;
+    const int64_t hi = min(lo + KM_BLOCK, a.nt);
+    const int nch = static_cast<int>((hi - lo + ch - 1) / ch);
+    const int pairs = a.l * hh;
+    const int32_t *lg = lab + static_cast<int64_t>(g) * a.nt;
+    double acc[KM_PPT];
+    int pc[KM_PPT], pt[KM_PPT];
+#pragma unroll
+    for (int u = 0; u < KM_PPT; u++) {
+        const int idx = u * KM_PBLOCK + tid;
+        pc[u] = idx < pairs ? idx / hh : -1;
+        pt[u] = idx < pairs ? idx % hh : 0;
+        acc[u] = 0.0;
+    }
+    int rl;
+    float rv[KM_XPT];
+    auto fetch = [&](int k) {
+        const int64_t p0 = lo + static_cast<int64_t>(k) * ch;
+        const int m = static_cast<int>(min<int64_t>(ch, hi - p0));
+        rl = tid < m ? lg[p0 + tid] : -1;
+#pragma unroll
+        for (int u = 0; u < KM_XPT; u++) {
+            const int i = u * KM_PBLOCK + tid;
+            const int pi = i / hh, tt = i - pi * hh;
+            rv[u] = pi < m ? a.T[row_of(a.train, p0 + pi) * a.ld + H.off + tt] : 0.0f;
+        }
+    };
+    reinterpret_cast<unsigned long long *>(wm)[tid] = 0ull;
+    reinterpret_cast<unsigned long long *>(wm)[KM_PBLOCK + tid] = 0ull;
+    fetch(0);
+    __syncthreads();
+    for (int k = 0; k < nch; k++) {
+        const int buf = k & 1;
+        const int lb = rl;
+#pragma unroll
+        for (int u = 0; u < KM_XPT; u++) X[buf][u * KM_PBLOCK + tid] = rv[u];
+        if (lb >= 0) atomicOr(&wm[buf][w][lb], 1ull << lane);
+        __syncthreads();
+        if (k + 1 < nch) fetch(k + 1);
+        reinterpret_cast<unsigned long long *>(wm[buf ^ 1])[tid] = 0ull;  // for chunk k + 1
+        if (w == 0) {
+            uint32_t run = 0;
+            if (lane < a.l) {
+                for (int v = 0; v < KM_PW; v++) {
+                    wbase[v][lane] = run;
+                    run += static_cast<uint32_t>(__popcll(wm[buf][v][lane]));
+                }
+                ctot[lane] = run;
+            }
+            uint32_t incl = run;
+#pragma unroll
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, WAVE);
+                if (lane >= o) incl += y;
+            }
+            if (lane < a.l) cst[lane] = incl - run;
+        }
+        __syncthreads();
+        if (lb >= 0) {
+            const unsigned long long below = (1ull << lane) - 1ull;
+            const uint32_t rank = static_cast<uint32_t>(__popcll(wm[buf][w][lb] & below));
+            list[cst[lb] + wbase[w][lb] + rank] = static_cast<uint16_t>(tid);
+        }
+        __syncthreads();
+        const float *xb = X[buf];
+#pragma unroll
+        for (int u = 0; u < KM_PPT; u++) {
+            if (pc[u] < 0) continue;
+            const int e0 = cst[pc[u]], e1 = e0 + ctot[pc[u]];
+            const float *xt = xb + pt[u];
+            double s = acc[u];
+            for (int e = e0; e < e1; e++) s += static_cast<double>(xt[list[e] * hh]);
+            acc[u] = s;
         }
     }
+#pragma unroll
+    for (int u = 0; u < KM_PPT; u++)
+        if (pc[u] >= 0) psum[((static_cast<int64_t>(g) * nblk + b) * a.l + pc[u]) * HM + pt[u]] = acc[u];
 }
 
 constexpr int KM_UBLOCK = 1024;
@@ -399,7 +473,7 @@ constexpr int KM_UBLOCK = 1024;
 // grid (2*Ns).
 __global__ __launch_bounds__(KM_UBLOCK) void k_km_update(KmArgs a, int HM, int nblk,
                                                          const double *__restrict__ psum,
-                                                         const uint32_t *__restrict__ pcnt,
+                                                         uint32_t *__restrict__ pcnt,
                                                          const double *__restrict__ far,
                                                          double *__restrict__ cent) {
     __shared__ int64_t cnt[64];
@@ -411,7 +485,11 @@ __global__ __launch_bounds__(KM_UBLOCK) void k_km_update(KmArgs a, int HM, int n
     const int tid = threadIdx.x;
     for (int c = tid; c < a.l; c += KM_UBLOCK) {
         int64_t s = 0;
-        for (int b = 0; b < nblk; b++) s += pcnt[(static_cast<int64_t>(g) * nblk + b) * a.l + c];
+        for (int b = 0; b < nblk; b++) {
+            uint32_t *pc = pcnt + (static_cast<int64_t>(g) * nblk + b) * a.l + c;
+            s += *pc;
+            *pc = 0u;  // the next assignment step counts afresh
+        }
         cnt[c] = s;
     }
     __syncthreads();
@@ -709,17 +787,17 @@ hipError_t launch_kmeans(const KmArgs &a, float *cent, int32_t *assign, void *sc
     double *far = reinterpret_cast<double *>(carve(p, sizeof(double) * size_t(G * a.nt)));
     double *psum = reinterpret_cast<double *>(carve(p, sizeof(double) * size_t(G * nb * a.l * HM)));
     uint32_t *pcnt = reinterpret_cast<uint32_t *>(carve(p, sizeof(uint32_t) * size_t(G * nb * a.l)));
-    k_km_seed<<<G, 256, 0, st>>>(a, HM, c64);
+    const int nbi = static_cast<int>(nb);
+    k_km_seed<<<G, 256, 0, st>>>(a, HM, nbi, c64, pcnt);
     const dim3 ga(static_cast<unsigned>((a.nt + 255) / 256), G);
     for (int it = 0; it < a.iters; it++) {
         if (HM <= 8)
-            k_km_assign<8><<<ga, 256, 0, st>>>(a, HM, c64, lab, far);
+            k_km_assign<8><<<ga, 256, 0, st>>>(a, HM, nbi, c64, lab, far, pcnt);
         else if (HM <= 16)
-            k_km_assign<16><<<ga, 256, 0, st>>>(a, HM, c64, lab, far);
+            k_km_assign<16><<<ga, 256, 0, st>>>(a, HM, nbi, c64, lab, far, pcnt);
         else
-            k_km_assign<32><<<ga, 256, 0, st>>>(a, HM, c64, lab, far);
-        k_km_partial<<<dim3(static_cast<unsigned>(nb), G), KM_PBLOCK, 0, st>>>(a, HM, static_cast<int>(nb), lab,
-                                                                              psum, pcnt);
+            k_km_assign<32><<<ga, 256, 0, st>>>(a, HM, nbi, c64, lab, far, pcnt);
+        k_km_partial<<<dim3(static_cast<unsigned>(nb), G), KM_PBLOCK, 0, st>>>(a, HM, nbi, lab, psum);
         k_km_update<<<G, KM_UBLOCK, 0, st>>>(a, HM, static_cast<int>(nb), psum, pcnt, far, c64);
     }
     const int64_t cc = int64_t(G) * a.l * HM;

@@ -35,6 +35,8 @@ def test_short_kernel_names():
     assert f("void taco::k_recheck_topk<16, true>(float const*)") == "recheck"
     assert f("void taco::k_rerank8<8, true, true>(float const*)") == "rerank"
     assert f("void taco::k_cdist_mfma<true>(float const*)") == "cdist"
+    assert f("void taco::bld::(anonymous namespace)::k_km_assign<8>(taco::bld::KmArgs, int)") == "build_km_assign"
+    assert f("taco::bld::(anonymous namespace)::k_jacobi(double const*, int, int)") == "build_jacobi"
     assert f("__amd_rocclr_copyBuffer") is None
 
 
