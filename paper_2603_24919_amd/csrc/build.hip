@@ -307,42 +307,44 @@ __global__ __launch_bounds__(256) void k_km_seed(KmArgs a, int HM, int nblk, dou
     }
 }
 
-// Label and FP64 distance of each sample point to its nearest centroid.
-// grid (ceil(nt/256), 2*Ns).
-static_assert(KM_BLOCK % 256 == 0, "a label-counting workgroup must lie in one block");
+constexpr int KM_APW = 256;  // sample positions per assignment workgroup (one per thread)
+static_assert(KM_BLOCK % KM_APW == 0, "a label-counting workgroup must lie in one block");
 
-// Also counts the labels of each partial-sum block: a workgroup's 256
-// positions lie in one block (KM_BLOCK is a multiple of 256); integer adds
-// in any order give the same counts.
+// Label and FP64 distance of each sample point to its nearest centroid.
+// grid (ceil(nt/256), 2*Ns).  Also counts the labels of each partial-sum
+// block (a workgroup's positions lie in one block); integer adds in any
+// order give the same counts.
 template <int HX>
 __global__ __launch_bounds__(256) void k_km_assign(KmArgs a, int HM, int nblk, const double *__restrict__ cent,
                                                    int32_t *__restrict__ lab, double *__restrict__ far,
                                                    uint32_t *__restrict__ pcnt) {
-    __shared__ double C[64 * HX];
+    __shared__ double C[64 * HX];  // row c: the centroid, zero-padded to HX
     __shared__ uint32_t hc[64];
     const int g = blockIdx.y;
     const Half H = half_of(g, a.s);
-    for (int i = threadIdx.x; i < a.l * H.h; i += 256)
-        C[i] = cent[(static_cast<int64_t>(g) * a.l + i / H.h) * HM + i % H.h];
+    for (int i = threadIdx.x; i < a.l * HX; i += 256) {
+        const int c = i / HX, t = i % HX;
+        C[i] = t < H.h ? cent[(static_cast<int64_t>(g) * a.l + c) * HM + t] : 0.0;
+    }
     if (threadIdx.x < 64) hc[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-    const int64_t b = (static_cast<int64_t>(blockIdx.x) * 256) / KM_BLOCK;
+    const int64_t pb = static_cast<int64_t>(blockIdx.x) * KM_APW;
+    const int64_t b = pb / KM_BLOCK;
+    const int64_t p = pb + threadIdx.x;
     if (p < a.nt) {
         const float *x = a.T + row_of(a.train, p) * a.ld + H.off;
         double xv[HX];
-    #pragma unroll
+#pragma unroll
         for (int t = 0; t < HX; t++) xv[t] = t < H.h ? static_cast<double>(x[t]) : 0.0;
+        // Terms past h are (+0 - +0)^2 = +0, which leave the sum unchanged.
         int best = 0;
         double bd = 0.0;
         for (int c = 0; c < a.l; c++) {
             double s = 0.0;
-    #pragma unroll
+#pragma unroll
             for (int t = 0; t < HX; t++) {
-                if (t < H.h) {
-                    const double u = xv[t] - C[c * H.h + t];
-                    s += u * u;
-                }
+                const double u = xv[t] - C[c * HX + t];
+                s += u * u;
             }
             if (c == 0 || s < bd) {
                 bd = s;
@@ -562,11 +564,13 @@ __global__ __launch_bounds__(256) void k_km_round(const double *__restrict__ cen
 template <int HX>
 __global__ __launch_bounds__(256) void k_km_label(KmArgs a, int HM, const float *__restrict__ cent,
                                                   int32_t *__restrict__ assign) {
-    __shared__ float C[64 * HX];
+    __shared__ float C[64 * HX];  // row c: the centroid, zero-padded to HX
     const int g = blockIdx.y;
     const Half H = half_of(g, a.s);
-    for (int i = threadIdx.x; i < a.l * H.h; i += 256)
-        C[i] = cent[(static_cast<int64_t>(g) * a.l + i / H.h) * HM + i % H.h];
+    for (int i = threadIdx.x; i < a.l * HX; i += 256) {
+        const int c = i / HX, t = i % HX;
+        C[i] = t < H.h ? cent[(static_cast<int64_t>(g) * a.l + c) * HM + t] : 0.0f;
+    }
     __syncthreads();
     const int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (r >= a.n) return;
@@ -576,14 +580,13 @@ __global__ __launch_bounds__(256) void k_km_label(KmArgs a, int HM, const float 
     for (int t = 0; t < HX; t++) xv[t] = t < H.h ? x[t] : 0.0f;
     int best = 0;
     float bd = 0.0f;
+    // Terms past h are fmaf(+0, +0, acc) = acc.
     for (int c = 0; c < a.l; c++) {
         float acc = 0.0f;
 #pragma unroll
         for (int t = 0; t < HX; t++) {
-            if (t < H.h) {
-                const float u = xv[t] - C[c * H.h + t];
-                acc = fmaf(u, u, acc);
-            }
+            const float u = xv[t] - C[c * HX + t];
+            acc = fmaf(u, u, acc);
         }
         if (c == 0 || acc < bd) {
             bd = acc;
@@ -789,7 +792,7 @@ hipError_t launch_kmeans(const KmArgs &a, float *cent, int32_t *assign, void *sc
     uint32_t *pcnt = reinterpret_cast<uint32_t *>(carve(p, sizeof(uint32_t) * size_t(G * nb * a.l)));
     const int nbi = static_cast<int>(nb);
     k_km_seed<<<G, 256, 0, st>>>(a, HM, nbi, c64, pcnt);
-    const dim3 ga(static_cast<unsigned>((a.nt + 255) / 256), G);
+    const dim3 ga(static_cast<unsigned>((a.nt + KM_APW - 1) / KM_APW), G);
     for (int it = 0; it < a.iters; it++) {
         if (HM <= 8)
             k_km_assign<8><<<ga, 256, 0, st>>>(a, HM, nbi, c64, lab, far, pcnt);
