@@ -79,6 +79,24 @@ def cpu_baseline_index(w, X):
     return path, built_s
 
 
+def cpu_baseline_build_time(w, X):
+    """Seconds the oracle takes to build the workload's index (into a
+    scratch file, removed afterwards): the index-build baseline when the
+    cached index was not built in this run."""
+    from oracle import oracle as O
+    import tempfile
+    fd, tmp = tempfile.mkstemp(suffix=".tcx")
+    os.close(fd)
+    try:
+        t = time.time()
+        O.build_workload_index(w, tmp, X)
+        dt = time.time() - t
+    finally:
+        os.unlink(tmp)
+    log(f"oracle built the index in {dt:.1f}s on {O.max_threads()} threads (timing only)")
+    return dt
+
+
 BUILD_STAGES = ("stats", "eigen", "allocate", "transform", "kmeans", "imi")
 
 
@@ -341,6 +359,8 @@ def summarize_stats(stats_csv, bench_json, out_md, command):
     HIP-event timing of the same run."""
     import csv
     line = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    if "roofline" not in line:
+        return summarize_build_stats(stats_csv, line, out_md, command)
     op = line["roofline"]
     pts = line["paths"][op["path"]]["points"]
     ev = next(p for p in pts if p["alpha"] == op["alpha"])["kernels"]
@@ -374,6 +394,31 @@ def summarize_stats(stats_csv, bench_json, out_md, command):
     out += ["", f"Dominant kernel at the operating point: {op['kernel']}, "
             f"{op['alg_bytes_per_launch'] / 1e6:.1f} MB algorithmic per launch, "
             f"{op['achieved']:.1f} GB/s achieved = {op['frac']:.4f} of {op['peak']:.0f} GB/s.", ""]
+    open(out_md, "w").write("\n".join(out))
+
+
+def summarize_build_stats(stats_csv, line, out_md, command):
+    """Markdown table of rocprofv3's per-kernel statistics of a --build-only
+    run, with the bench's per-stage HIP-event times of the same run."""
+    import csv
+    b = line["index_build"]
+    rows = list(csv.DictReader(open(stats_csv)))
+    out = [f"# rocprofv3 kernel statistics: GPU index build (Alg 1-3), {b['workload']}", "",
+           "Command (from the repository root, TMPDIR=/tmp):", "", "```", command, "```", "",
+           f"n = {b['n']}, d = {b['d']}, Ns = {b['Ns']}, s = {b['s']}, l = {b['l']}, "
+           f"{b['kmeans_iters']} k-means iterations; {b['reps'] + 1} builds in the process "
+           "(one warm-up), so per-build counts are calls / "
+           f"{b['reps'] + 1}.", "",
+           "Bench stage times of the fastest build (HIP events, ms): " +
+           ", ".join(f"{k} {v:.2f}" for k, v in b["stages_ms"].items()) +
+           f"; total {b['gpu_ms']:.1f} ms.", "",
+           "| kernel | calls | rocprof avg (us) | rocprof total (ms) | % |", "|---|---|---|---|---|"]
+    for r in rows:
+        short = short_kernel_name(r["Name"])
+        out.append(f"| {short or r['Name'][:40]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    out += ["", "transform and encode_ids/build_off2d here are the base transform of the build and "
+            "the search preparation of each built index.", ""]
     open(out_md, "w").write("\n".join(out))
 
 
@@ -465,6 +510,9 @@ def main():
                          "centroid distances on the matrix cores)")
     ap.add_argument("--skip-precision-report", action="store_true")
     ap.add_argument("--skip-build", action="store_true", help="omit the GPU index-build leg")
+    ap.add_argument("--build-only", action="store_true",
+                    help="run only the GPU index-build leg (and the oracle's build time unless "
+                         "--skip-cpu-baseline); prints its own JSON line")
     ap.add_argument("--build-reps", type=int, default=3)
     ap.add_argument("--skip-cpu-baseline", action="store_true",
                     help="omit the oracle timing (profiling runs); the line then has no cpu_baseline")
@@ -506,6 +554,20 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.build_only:
+        build = gpu_build_leg(taco, torch, w, X, dev, args.build_reps)
+        obs = oracle_build_s
+        if obs is None and not args.skip_cpu_baseline:
+            obs = cpu_baseline_build_time(w, X)
+        build["oracle_s"] = obs
+        if obs:
+            build["gpu_vs_oracle"] = obs * 1e3 / build["gpu_ms"]
+        log(f"GPU index build: {build['gpu_ms']:.1f} ms (" + ", ".join(
+            f"{k} {v:.2f}" for k, v in build["stages_ms"].items()) + ")")
+        print(json.dumps(dict(metric="GPU index build time (Alg 1-3)", value=build["gpu_ms"], unit="ms",
+                              n_gpus=1, higher_is_better=False, data="synthetic",
+                              config=dict(workload=WORKLOAD), index_build=build)), flush=True)
+        return
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -594,9 +656,13 @@ def main():
     if not args.skip_build:
         t0 = time.time()
         build = gpu_build_leg(taco, torch, w, X, dev, args.build_reps)
+        if oracle_build_s is None and not args.skip_cpu_baseline:
+            oracle_build_s = cpu_baseline_build_time(w, X)
         build["oracle_s"] = oracle_build_s
-        build["oracle_note"] = ("the oracle's build of the same index (Alg 1-3, OpenMP over points) in "
-                                "this run" if oracle_build_s is not None else "index cached: not timed")
+        build["oracle_note"] = ("the oracle's build of the same index (Alg 1-3, OpenMP over points on the "
+                                "host cores) in this run" if oracle_build_s is not None else "not timed")
+        if oracle_build_s:
+            build["gpu_vs_oracle"] = oracle_build_s * 1e3 / build["gpu_ms"]
         log(f"GPU index build: {build['gpu_ms']:.1f} ms (" + ", ".join(
             f"{k} {v:.2f}" for k, v in build["stages_ms"].items()) + f") in {time.time() - t0:.1f}s")
 
