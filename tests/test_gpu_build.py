@@ -281,3 +281,30 @@ def test_build_index_1m_file_identical_given_oracle_basis(taco_mod, tmp_path):
     out, ms = _gpu_build_file(taco_mod, w, X, tmp_path, True, O.OracleIndex(path))
     print(f"[build] 1M stage ms {ms}", flush=True)
     assert _digest(out) == _digest(path)
+
+
+@pytest.mark.parametrize("name,n,kw", [
+    # d = 960, s = 60 (halves of 30), l = 32: the caller passes mean and B
+    ("aniso-1m-d960", 6000, {}),
+    # d = 96, s = 12, l = 64 (K = 4096 cells), a training sample of 2/3 of the rows
+    ("sphere-10m-d96", 150_000, {"n_train": 100_000}),
+    # d = 256, Ns = 16, l = 40
+    ("zipf-1m-d256", 20_000, {}),
+])
+def test_build_index_other_workloads_identical_given_oracle_basis(taco_mod, tmp_path, name, n, kw):
+    w = synthdata.WORKLOADS[name].scaled(f"{name}-n{n}", n=n, nq=0, **kw)
+    X, _ = synthdata.base_and_queries(w, nq=0)
+    path = str(tmp_path / f"{w.name}-oracle.tcx")
+    O.build_workload_index(w, path, X)
+    print(f"[build] {w.name}: oracle index built", flush=True)
+    out, ms = _gpu_build_file(taco_mod, w, X, tmp_path, True, O.OracleIndex(path))
+    print(f"[build] {w.name} stage ms {ms}", flush=True)
+    assert _digest(out) == _digest(path)
+
+
+def test_build_index_requires_basis_beyond_d128(taco_mod):
+    w = synthdata.WORKLOADS["zipf-1m-d256"].scaled("zipf-2k", n=2000, nq=0)
+    X, _ = synthdata.base_and_queries(w, nq=0)
+    train, init = synthdata.kmeans_seeding(w)
+    with pytest.raises(taco_mod.TacoError):
+        taco_mod.Index.build(_dev(X), w.Ns, w.s, w.l, w.iters, init, train, w.seed)
