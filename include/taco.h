@@ -289,11 +289,13 @@ const char *tc_last_error(void);
  * device outputs.  n >= 2.  TC_EINVAL, TC_ENOMEM, TC_EDEVICE. */
 int tc_build_stats(const float *X, int64_t n, int32_t d, double *mean, double *cov, void *stream);
 
-/* Alg 1, spectral decomposition of the symmetric cov (device, d x d FP64),
- * 1 <= d <= 128 (cyclic Jacobi in one workgroup's LDS).  evals[d] descending
- * (ties keep the lower index); evecs[r][c] = component r of eigenvector c,
- * each vector signed so that its largest-magnitude component (the first on
- * ties) is positive.  Device outputs.  TC_EINVAL beyond d = 128. */
+/* Alg 1, spectral decomposition of the symmetric positive semi-definite cov
+ * (device, d x d FP64), 1 <= d <= 4096: two-sided cyclic Jacobi in one
+ * workgroup's LDS up to d = 128, one-sided Jacobi over many workgroups beyond.
+ * evals[d] descending (ties keep the lower index); evecs[r][c] = component r
+ * of eigenvector c, each vector signed so that its largest-magnitude
+ * component (the first on ties) is positive.  Device outputs.  TC_EINVAL
+ * beyond d = 4096. */
 int tc_build_eigen(const double *cov, int32_t d, double *evals, double *evecs, void *stream);
 
 /* Alg 2, eigensystem allocation (host in, host out, no GPU work).  Eigenvalues
@@ -339,7 +341,7 @@ int tc_build_imi(const int32_t *assign, int64_t n, int32_t Ns, int32_t l, uint32
  * its own copy), then the index is prepared for search as tc_load_index
  * would.  init/train/n_train as for tc_build_kmeans; seed is recorded in the
  * index file.  mean (host, d) and B (host, d x Ns*s), both or neither, skip
- * the statistics and eigensolver (required when d > 128).  stage_ms (host,
+ * the statistics and eigensolver (required when d > 4096).  stage_ms (host,
  * 6 or NULL) receives the GPU time of: statistics, eigensolver, allocation
  * and uploads, transform, k-means, IMI.  Synchronous.  TC_EINVAL, TC_ENOMEM,
  * TC_EDEVICE. */

@@ -277,6 +277,142 @@ __global__ __launch_bounds__(EIG_BLOCK) void k_jacobi(const double *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Spectral decomposition for larger d: one-sided (Hestenes) Jacobi.  U = A V
+// is kept column by column; each step orthogonalizes dp/2 disjoint column
+// pairs (round-robin ordering, one workgroup per pair) and applies the same
+// rotation to V.  At convergence the columns of U are lambda_i v_i, so for
+// the positive semi-definite covariance lambda_i = sign(u_i . v_i) |u_i|.
+// Columns are contiguous (column-major), so no step needs a grid-wide
+// barrier; the host launches steps and checks a rotation counter per sweep.
+// ---------------------------------------------------------------------------
+
+constexpr int OSJ_BLOCK = 256;
+constexpr int OSJ_SWEEPS = 40;
+constexpr double OSJ_EPS = 2.220446049250313e-16;  // rotate while |u_p.u_q| > dp eps |u_p| |u_q|
+
+__global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
+
+// U (column-major) = A, padded by a zero column and row for odd d; V = I.
+__global__ __launch_bounds__(256) void k_osj_init(const double *__restrict__ cov, int d, int dp,
+                                                  double *__restrict__ U, double *__restrict__ V) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= static_cast<int64_t>(dp) * dp) return;
+    const int c = static_cast<int>(i / dp), r = static_cast<int>(i % dp);
+    U[i] = (r < d && c < d) ? cov[static_cast<int64_t>(r) * d + c] : 0.0;
+    V[i] = r == c ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(OSJ_BLOCK) void k_osj_step(double *__restrict__ U, double *__restrict__ V,
+                                                        int dp, int step, uint32_t *__restrict__ rotated) {
+    __shared__ double red[3][OSJ_BLOCK / WAVE];
+    const int pr = blockIdx.x;
+    const int a = pr == 0 ? 0 : 1 + (pr - 1 + step) % (dp - 1);
+    const int b = 1 + (dp - 2 - pr + step) % (dp - 1);
+    const int p = min(a, b), q = max(a, b);
+    double *up = U + static_cast<int64_t>(p) * dp, *uq = U + static_cast<int64_t>(q) * dp;
+    double *vp = V + static_cast<int64_t>(p) * dp, *vq = V + static_cast<int64_t>(q) * dp;
+    double al = 0.0, be = 0.0, ga = 0.0;
+    for (int r = threadIdx.x; r < dp; r += OSJ_BLOCK) {
+        const double x = up[r], y = uq[r];
+        al += x * x;
+        be += y * y;
+        ga += x * y;
+    }
+    al = wave_sum(al);
+    be = wave_sum(be);
+    ga = wave_sum(ga);
+    const int w = threadIdx.x / WAVE;
+    if ((threadIdx.x % WAVE) == 0) {
+        red[0][w] = al;
+        red[1][w] = be;
+        red[2][w] = ga;
+    }
+    __syncthreads();
+    al = be = ga = 0.0;
+    for (int i = 0; i < OSJ_BLOCK / WAVE; i++) {
+        al += red[0][i];
+        be += red[1][i];
+        ga += red[2][i];
+    }
+    if (!(fabs(ga) > dp * OSJ_EPS * sqrt(al * be)) || ga == 0.0) return;  // uniform
+    const double zeta = (be - al) / (2.0 * ga);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
+    for (int r = threadIdx.x; r < dp; r += OSJ_BLOCK) {
+        const double x = up[r], y = uq[r];
+        up[r] = c * x - sn * y;
+        uq[r] = sn * x + c * y;
+        const double xv = vp[r], yv = vq[r];
+        vp[r] = c * xv - sn * yv;
+        vq[r] = sn * xv + c * yv;
+    }
+    if (threadIdx.x == 0) atomicAdd(rotated, 1u);
+}
+
+// lam[i] = sign(u_i . v_i) |u_i|, one workgroup per column i < d.
+__global__ __launch_bounds__(OSJ_BLOCK) void k_osj_values(const double *__restrict__ U,
+                                                          const double *__restrict__ V, int dp,
+                                                          double *__restrict__ lam) {
+    __shared__ double red[2][OSJ_BLOCK / WAVE];
+    const int i = blockIdx.x;
+    const double *u = U + static_cast<int64_t>(i) * dp, *v = V + static_cast<int64_t>(i) * dp;
+    double nn = 0.0, uv = 0.0;
+    for (int r = threadIdx.x; r < dp; r += OSJ_BLOCK) {
+        nn += u[r] * u[r];
+        uv += u[r] * v[r];
+    }
+    nn = wave_sum(nn);
+    uv = wave_sum(uv);
+    if ((threadIdx.x % WAVE) == 0) {
+        red[0][threadIdx.x / WAVE] = nn;
+        red[1][threadIdx.x / WAVE] = uv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        nn = uv = 0.0;
+        for (int k = 0; k < OSJ_BLOCK / WAVE; k++) {
+            nn += red[0][k];
+            uv += red[1][k];
+        }
+        lam[i] = uv < 0.0 ? -sqrt(nn) : sqrt(nn);
+    }
+}
+
+// Descending order (ties to the lower index) and the sign convention; one
+// thread per eigenpair.  rank and sign: [d] scratch.
+__global__ __launch_bounds__(256) void k_osj_order(const double *__restrict__ lam, const double *__restrict__ V,
+                                                   int d, int dp, double *__restrict__ evals,
+                                                   int *__restrict__ rank, double *__restrict__ sgn) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= d) return;
+    const double li = lam[i];
+    int r = 0;
+    for (int j = 0; j < d; j++) r += (lam[j] > li) || (lam[j] == li && j < i);
+    rank[i] = r;
+    evals[r] = li;
+    const double *v = V + static_cast<int64_t>(i) * dp;
+    int piv = 0;
+    double best = -1.0;
+    for (int k = 0; k < d; k++) {
+        const double m = fabs(v[k]);
+        if (m > best) {
+            best = m;
+            piv = k;
+        }
+    }
+    sgn[i] = v[piv] < 0.0 ? -1.0 : 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_osj_vectors(const double *__restrict__ V, int d, int dp,
+                                                     const int *__restrict__ rank, const double *__restrict__ sgn,
+                                                     double *__restrict__ evecs) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= static_cast<int64_t>(d) * d) return;
+    const int c = static_cast<int>(e / d), k = static_cast<int>(e % d);
+    evecs[static_cast<int64_t>(k) * d + rank[c]] = sgn[c] * V[static_cast<int64_t>(c) * dp + k];
+}
+
+// ---------------------------------------------------------------------------
 // k-means, all 2*Ns halves in one grid dimension.
 // ---------------------------------------------------------------------------
 
@@ -719,11 +855,19 @@ __global__ __launch_bounds__(IMI_BLOCK) void k_imi_scatter(const int32_t *__rest
 // Launchers.
 // ---------------------------------------------------------------------------
 
+namespace {
+// Row chunks of the covariance: about 4096 workgroups in all, at most 256.
+int cov_chunks(int64_t n, int ntile) {
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(CV_CHUNKS, 4096 / ntile));
+    const int64_t rows = std::max<int64_t>(chunk_rows(n, static_cast<int>(want)), 1);
+    return static_cast<int>((n + rows - 1) / rows);
+}
+}  // namespace
+
 size_t stats_scratch(int64_t n, int d) {
     const int nb = (d + CV_TILE - 1) / CV_TILE;
-    const size_t ntile = size_t(nb) * (nb + 1) / 2;
-    (void)n;
-    return std::max(size_t(ST_CHUNKS) * d, size_t(CV_CHUNKS) * ntile * CV_TILE * CV_TILE);
+    const int ntile = nb * (nb + 1) / 2;
+    return std::max(size_t(ST_CHUNKS) * d, size_t(cov_chunks(n, ntile)) * ntile * CV_TILE * CV_TILE);
 }
 
 hipError_t launch_stats(const float *X, int64_t n, int d, double *mean, double *cov, double *scratch,
@@ -734,8 +878,8 @@ hipError_t launch_stats(const float *X, int64_t n, int d, double *mean, double *
     k_mean<<<(d + 255) / 256, 256, 0, st>>>(scratch, chunks, n, d, mean);
     const int nb = (d + CV_TILE - 1) / CV_TILE;
     const int ntile = nb * (nb + 1) / 2;
-    const int64_t crow = std::max<int64_t>(chunk_rows(n, CV_CHUNKS), 1);
-    const int cchunks = static_cast<int>((n + crow - 1) / crow);
+    const int cchunks = cov_chunks(n, ntile);
+    const int64_t crow = std::max<int64_t>(chunk_rows(n, cchunks), 1);
     k_cov_part<<<dim3(ntile, cchunks), 256, 0, st>>>(X, n, d, mean, crow, nb, scratch);
     const int64_t dd = int64_t(d) * d;
     k_cov_final<<<static_cast<unsigned>((dd + 255) / 256), 256, 0, st>>>(scratch, cchunks, ntile, nb, n, d, cov);
@@ -744,13 +888,43 @@ hipError_t launch_stats(const float *X, int64_t n, int d, double *mean, double *
 
 size_t eigen_scratch(int d) {
     const int dp = d + (d & 1);
-    return size_t(dp) * dp;
+    if (dp <= EIG_MAX) return size_t(dp) * dp;
+    // U, V, lambda, signs, ranks and the rotation counter
+    return 2 * size_t(dp) * dp + 3 * size_t(d) + 2;
 }
+
+namespace {
+hipError_t eigen_one_sided(const double *cov, int d, double *evals, double *evecs, double *scratch,
+                           hipStream_t st) {
+    const int dp = d + (d & 1);
+    double *U = scratch, *V = U + size_t(dp) * dp;
+    double *lam = V + size_t(dp) * dp, *sgn = lam + d;
+    int *rank = reinterpret_cast<int *>(sgn + d);
+    uint32_t *rot = reinterpret_cast<uint32_t *>(lam + 3 * size_t(d) + 1);
+    const int64_t e2 = int64_t(dp) * dp;
+    k_osj_init<<<static_cast<unsigned>((e2 + 255) / 256), 256, 0, st>>>(cov, d, dp, U, V);
+    for (int sweep = 0; sweep < OSJ_SWEEPS; sweep++) {
+        k_zero_u32<<<1, 1, 0, st>>>(rot);
+        hipError_t e;
+        for (int step = 0; step < dp - 1; step++) k_osj_step<<<dp / 2, OSJ_BLOCK, 0, st>>>(U, V, dp, step, rot);
+        uint32_t h = 0;
+        if ((e = hipMemcpyAsync(&h, rot, sizeof h, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        if (h == 0) break;
+    }
+    k_osj_values<<<d, OSJ_BLOCK, 0, st>>>(U, V, dp, lam);
+    k_osj_order<<<(d + 255) / 256, 256, 0, st>>>(lam, V, d, dp, evals, rank, sgn);
+    const int64_t dd = int64_t(d) * d;
+    k_osj_vectors<<<static_cast<unsigned>((dd + 255) / 256), 256, 0, st>>>(V, d, dp, rank, sgn, evecs);
+    return hipGetLastError();
+}
+}  // namespace
 
 hipError_t launch_eigen(const double *cov, int d, double *evals, double *evecs, double *scratch,
                         hipStream_t st) {
     const int dp = d + (d & 1);
-    if (d < 1 || dp > EIG_MAX) return hipErrorInvalidValue;
+    if (d < 1 || d > EIG_MAX_ONE_SIDED) return hipErrorInvalidValue;
+    if (dp > EIG_MAX) return eigen_one_sided(cov, d, evals, evecs, scratch, st);
     const size_t lds = sizeof(double) * size_t(dp) * dp;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_jacobi),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));

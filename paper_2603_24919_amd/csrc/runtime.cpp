@@ -1482,8 +1482,8 @@ int build(const float *X, int64_t n, int d, int Ns, int s, int l, int iters, con
     if ((rc = check_shape(x, TC_EINVAL))) return rc;
     if (n < 2) return fail(TC_EINVAL, "the covariance needs n >= 2");
     if ((mean_in == nullptr) != (B_in == nullptr)) return fail(TC_EINVAL, "give both mean and B, or neither");
-    if (!B_in && d > taco::bld::EIG_MAX)
-        return fail(TC_EINVAL, "the GPU eigensolver takes d <= 128; pass mean and B for a larger d");
+    if (!B_in && d > taco::bld::EIG_MAX_ONE_SIDED)
+        return fail(TC_EINVAL, "the GPU eigensolver takes d <= 4096; pass mean and B for a larger d");
     const int64_t nt = train ? n_train : n;
     const int M = Ns * s, K = l * l, G = 2 * Ns, HM = s - s / 2;
     if ((rc = check_kmeans_args(n, M, Ns, s, l, iters, init, train, nt))) return rc;
@@ -1625,7 +1625,8 @@ int tc_build_stats(const float *X, int64_t n, int32_t d, double *mean, double *c
 
 int tc_build_eigen(const double *cov, int32_t d, double *evals, double *evecs, void *stream) {
     if (!cov || !evals || !evecs) return fail(TC_EINVAL, "NULL buffer");
-    if (d < 1 || d > taco::bld::EIG_MAX) return fail(TC_EINVAL, "the GPU eigensolver takes 1 <= d <= 128");
+    if (d < 1 || d > taco::bld::EIG_MAX_ONE_SIDED)
+        return fail(TC_EINVAL, "the GPU eigensolver takes 1 <= d <= 4096");
     hipStream_t st = static_cast<hipStream_t>(stream);
     BuildBuffers bb;
     double *scr;

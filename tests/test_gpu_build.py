@@ -54,7 +54,7 @@ def _host(t):
 # Alg 1: mean and covariance, spectral decomposition, transform
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,d", [(20000, 128), (1001, 40), (2, 3), (70001, 7)])
+@pytest.mark.parametrize("n,d", [(20000, 128), (1001, 40), (2, 3), (70001, 7), (3000, 960)])
 def test_stats_match_oracle(taco_mod, tiny, n, d):
     print(f"[stats] n={n} d={d}", flush=True)
     if (n, d) == (20000, 128):
@@ -120,7 +120,26 @@ def test_eigen_closed_forms(taco_mod):
 def test_eigen_rejects_large_d(taco_mod):
     import torch
     with pytest.raises(taco_mod.TacoError):
-        taco_mod.tc_build_eigen(torch.eye(130, dtype=torch.float64, device="cuda:0"))
+        taco_mod.tc_build_eigen(torch.eye(4097, dtype=torch.float64, device="cuda:0"))
+
+
+@pytest.mark.parametrize("d", [129, 130, 256, 961])
+def test_eigen_one_sided_random_spd(taco_mod, d):
+    # beyond 128 dimensions: the one-sided form
+    rng = np.random.default_rng(d)
+    A = rng.normal(size=(d, d))
+    cov = A @ A.T / d + np.diag(np.linspace(1.0, 2.0, d))
+    ev, V = taco_mod.tc_build_eigen(_dev(cov))
+    _check_eigen(cov, _host(ev), _host(V), O.eigh_desc(cov))
+
+
+@pytest.mark.parametrize("name,n", [("aniso-1m-d960", 6000), ("zipf-1m-d256", 20000)])
+def test_eigen_one_sided_on_workload_covariance(taco_mod, name, n):
+    w = synthdata.WORKLOADS[name].scaled(f"{name}-n{n}", n=n, nq=0)
+    X, _ = synthdata.base_and_queries(w, nq=0)
+    _, cov = O.mean_cov(X)
+    ev, V = taco_mod.tc_build_eigen(_dev(cov))
+    _check_eigen(cov, _host(ev), _host(V), O.eigh_desc(cov))
 
 
 def test_transform_bit_exact(taco_mod, tiny):
@@ -302,9 +321,17 @@ def test_build_index_other_workloads_identical_given_oracle_basis(taco_mod, tmp_
     assert _digest(out) == _digest(path)
 
 
-def test_build_index_requires_basis_beyond_d128(taco_mod):
-    w = synthdata.WORKLOADS["zipf-1m-d256"].scaled("zipf-2k", n=2000, nq=0)
-    X, _ = synthdata.base_and_queries(w, nq=0)
-    train, init = synthdata.kmeans_seeding(w)
-    with pytest.raises(taco_mod.TacoError):
-        taco_mod.Index.build(_dev(X), w.Ns, w.s, w.l, w.iters, init, train, w.seed)
+def test_build_index_full_gpu_path_d256(taco_mod, tmp_path):
+    # every stage on the GPU beyond 128 dimensions (one-sided eigensolver)
+    w = synthdata.WORKLOADS["zipf-1m-d256"].scaled("zipf-20k", n=20000, nq=50)
+    X, Q = synthdata.base_and_queries(w)
+    opath = str(tmp_path / "zipf-oracle.tcx")
+    O.build_workload_index(w, opath, X)
+    out, ms = _gpu_build_file(taco_mod, w, X, tmp_path, False)
+    print(f"[build] zipf-20k full GPU stage ms {ms}", flush=True)
+    g, o = O.OracleIndex(out), O.OracleIndex(opath)
+    assert np.max(np.abs(g.mean() - o.mean())) <= 1e-5 * np.max(np.abs(o.mean()))
+    gt = O.bruteforce(X, Q, w.k)[1]
+    r_g = O.recall_at_k(g.query_batch(Q, 0.05, w.beta, w.k), gt, X, Q, w.k)
+    r_o = O.recall_at_k(o.query_batch(Q, 0.05, w.beta, w.k), gt, X, Q, w.k)
+    assert r_g >= r_o - 0.02, (r_g, r_o)
