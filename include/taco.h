@@ -291,7 +291,7 @@ int tc_build_stats(const float *X, int64_t n, int32_t d, double *mean, double *c
 
 /* Alg 1, spectral decomposition of the symmetric positive semi-definite cov
  * (device, d x d FP64), 1 <= d <= 4096: two-sided cyclic Jacobi in one
- * workgroup's LDS up to d = 128, one-sided Jacobi over many workgroups beyond.
+ * workgroup's LDS up to d = 32, one-sided Jacobi over many workgroups beyond.
  * evals[d] descending (ties keep the lower index); evecs[r][c] = component r
  * of eigenvector c, each vector signed so that its largest-magnitude
  * component (the first on ties) is positive.  Device outputs.  TC_EINVAL

@@ -19,14 +19,15 @@ hipError_t launch_stats(const float *X, int64_t n, int d, double *mean, double *
                         double *scratch, hipStream_t st);
 
 // ---- Alg 1: spectral decomposition (cyclic Jacobi, one workgroup) --------
-constexpr int EIG_MAX = 128;             // largest d of the one-workgroup form (matrix in LDS)
-constexpr int EIG_MAX_ONE_SIDED = 4096;  // largest d of the one-sided form (beyond EIG_MAX)
+constexpr int EIG_MAX = 128;             // largest d the one-workgroup form can hold (matrix in LDS)
+constexpr int EIG_ONE_WG = 32;           // d up to which that form is used (faster only for small d)
+constexpr int EIG_MAX_ONE_SIDED = 4096;  // largest d of the one-sided form
 // Doubles of scratch launch_eigen needs (the accumulated rotations).
 size_t eigen_scratch(int d);
 // evals[d] descending; evecs[r][c] = component r of eigenvector c, each
 // vector's largest-magnitude component (the first on ties) positive.  For
-// d > EIG_MAX the one-sided form synchronizes the stream once per sweep (the
-// host reads its rotation counter), so it cannot be captured in a graph.
+// d > EIG_ONE_WG the one-sided form synchronizes the stream once per sweep
+// (the host reads its rotation counter), so it cannot be captured in a graph.
 hipError_t launch_eigen(const double *cov, int d, double *evals, double *evecs,
                         double *scratch, hipStream_t st);
 

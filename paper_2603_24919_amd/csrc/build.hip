@@ -888,7 +888,7 @@ hipError_t launch_stats(const float *X, int64_t n, int d, double *mean, double *
 
 size_t eigen_scratch(int d) {
     const int dp = d + (d & 1);
-    if (dp <= EIG_MAX) return size_t(dp) * dp;
+    if (dp <= EIG_ONE_WG) return size_t(dp) * dp;
     // U, V, lambda, signs, ranks and the rotation counter
     return 2 * size_t(dp) * dp + 3 * size_t(d) + 2;
 }
@@ -924,7 +924,8 @@ hipError_t launch_eigen(const double *cov, int d, double *evals, double *evecs, 
                         hipStream_t st) {
     const int dp = d + (d & 1);
     if (d < 1 || d > EIG_MAX_ONE_SIDED) return hipErrorInvalidValue;
-    if (dp > EIG_MAX) return eigen_one_sided(cov, d, evals, evecs, scratch, st);
+    if (dp > EIG_ONE_WG) return eigen_one_sided(cov, d, evals, evecs, scratch, st);
+    static_assert(EIG_ONE_WG <= EIG_MAX, "the one-workgroup form holds at most EIG_MAX");
     const size_t lds = sizeof(double) * size_t(dp) * dp;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_jacobi),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
