@@ -418,7 +418,10 @@ def summarize_build_stats(stats_csv, line, out_md, command):
         out.append(f"| {short or r['Name'][:40]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
     out += ["", "transform and encode_ids/build_off2d here are the base transform of the build and "
-            "the search preparation of each built index.", ""]
+            "the search preparation of each built index.  The stage times above come from this "
+            "profiled run: rocprofv3 adds a few microseconds to every launch, which shows in the "
+            "stage made of many short launches (the one-sided eigensolver, one launch per step); "
+            "the unprofiled bench line (index_build) has the plain figures.", ""]
     open(out_md, "w").write("\n".join(out))
 
 
