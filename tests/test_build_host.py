@@ -62,3 +62,47 @@ def test_alg2_rejects_bad_shapes(taco_mod):
         taco_mod.tc_build_allocate(np.ones(4), 3, 2)  # Ns*s > d
     with pytest.raises(taco_mod.TacoError):
         taco_mod.tc_build_allocate(np.zeros(4), 2, 2)  # no positive eigenvalue
+
+
+def _rc(taco_mod, fn, *args):
+    rc = getattr(taco_mod.load_library(), fn)(*args)
+    return rc, taco_mod.tc_last_error()
+
+
+def test_build_entry_points_reject_bad_arguments_before_any_device_work(taco_mod):
+    import ctypes as C
+    init = np.zeros(2 * 8 * 50, np.int64)
+    fake = C.c_void_p(0x1000)  # never dereferenced: every case fails validation first
+    out = C.c_void_p()
+    # NULL base
+    rc, msg = _rc(taco_mod, "tc_build_index", None, 1000, 128, 8, 16, 50, 20, init.ctypes.data, None, 0,
+                  0, None, None, 0, C.byref(out), None)
+    assert rc == taco_mod.TC_EINVAL and "NULL" in msg
+    # Ns * s > d
+    rc, msg = _rc(taco_mod, "tc_build_index", fake, 1000, 64, 8, 16, 50, 20, init.ctypes.data, None, 0,
+                  0, None, None, 0, C.byref(out), None)
+    assert rc == taco_mod.TC_EINVAL
+    # a seed position outside the sample
+    bad = init.copy()
+    bad[5] = 1000
+    rc, msg = _rc(taco_mod, "tc_build_index", fake, 1000, 128, 8, 16, 50, 20, bad.ctypes.data, None, 0,
+                  0, None, None, 0, C.byref(out), None)
+    assert rc == taco_mod.TC_EINVAL and "seed" in msg
+    # mean without B
+    m = np.zeros(128, np.float32)
+    rc, msg = _rc(taco_mod, "tc_build_index", fake, 1000, 128, 8, 16, 50, 20, init.ctypes.data, None, 0,
+                  0, m.ctypes.data, None, 0, C.byref(out), None)
+    assert rc == taco_mod.TC_EINVAL
+    # training rows out of range
+    train = np.array([0, 5, 2000] + list(range(10, 60)), np.int64)
+    rc, msg = _rc(taco_mod, "tc_build_kmeans", fake, 1000, 128, 8, 16, 50, 1, init.ctypes.data,
+                  train.ctypes.data, train.size, fake, fake, None)
+    assert rc == taco_mod.TC_EINVAL and "training row" in msg
+    # halves wider than 32 (s = 66)
+    rc, msg = _rc(taco_mod, "tc_build_kmeans", fake, 1000, 132, 2, 66, 4, 1, init.ctypes.data, None, 0,
+                  fake, fake, None)
+    assert rc == taco_mod.TC_EINVAL
+    # IMI with more than 4096 cells, and the eigensolver beyond 4096
+    assert _rc(taco_mod, "tc_build_imi", fake, 1000, 2, 65, fake, fake, None)[0] == taco_mod.TC_EINVAL
+    assert _rc(taco_mod, "tc_build_eigen", fake, 4097, fake, fake, None)[0] == taco_mod.TC_EINVAL
+    assert out.value is None
