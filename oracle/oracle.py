@@ -32,6 +32,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 RULE_PRINTED = 0
 RULE_PROSE = 1
+RULE_FIXED = 2  # SuCo's fixed budget: the floor(beta*n) highest SC-scores, ties by id
 
 _f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
@@ -326,6 +327,8 @@ def select(sc: np.ndarray, Ns: int, R: int, rule: int = RULE_PRINTED):
     cand = np.empty(sc.size, np.int32)
     last = C.c_int32(0)
     nc = lib().orc_select(sc, sc.size, Ns, int(R), rule, hist, C.byref(last), cand)
+    if nc < 0:
+        raise MemoryError("orc_select")
     return hist, int(last.value), cand[:nc].copy()
 
 

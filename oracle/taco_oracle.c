@@ -39,9 +39,11 @@
 #define ORC_EFORMAT -3
 #define ORC_ENOMEM -4
 
-/* Candidates-selection readings (Alg 5, see orc_select). */
+/* Candidates-selection readings (Alg 5, see orc_select), and the
+ * fixed-budget rule of SuCo that the paper compares Alg 5 against. */
 #define ORC_RULE_PRINTED 0
 #define ORC_RULE_PROSE 1
+#define ORC_RULE_FIXED 2
 
 /* Fixed reduction block: partial sums are formed per block of this many
  * points and then added in block order, independent of the thread count. */
@@ -536,13 +538,43 @@ int orc_threshold(const int64_t *hist, int Ns, int64_t R, int rule)
     return last;
 }
 
+static int u64cmp(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* The fixed-budget rule (the candidate selection SuCo uses, which Section
+ * 4.3 contrasts with Alg 5): the R points of highest SC-score, ties by lower
+ * id -- the first min(R, n) of all points sorted by (SC descending, id
+ * ascending).  Written as that sort.  cand: the chosen ids ascending;
+ * last_out: the lowest level taken completely (the last chosen point's
+ * SC-score plus one; Ns + 1 when R = 0).  Returns the number chosen. */
+static int64_t select_fixed(const uint8_t *SC, int64_t n, int Ns, int64_t R, int32_t *last_out,
+                            int32_t *cand)
+{
+    int64_t take = R < n ? R : n;
+    uint64_t *key = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    if (!key) return -1;
+    for (int64_t i = 0; i < n; i++) key[i] = ((uint64_t)(255 - SC[i]) << 32) | (uint64_t)i;
+    qsort(key, (size_t)n, sizeof(uint64_t), u64cmp);
+    *last_out = take > 0 ? (int32_t)SC[key[take - 1] & 0xffffffffu] + 1 : Ns + 1;
+    for (int64_t j = 0; j < take; j++) key[j] &= 0xffffffffu;
+    qsort(key, (size_t)take, sizeof(uint64_t), u64cmp);
+    for (int64_t j = 0; j < take; j++) cand[j] = (int32_t)key[j];
+    free(key);
+    return take;
+}
+
 /* Level histogram of SC[0..n), threshold, and the candidates
- * C = { i : SC[i] >= last } in ascending i.  Returns |C|. */
+ * C = { i : SC[i] >= last } in ascending i (for ORC_RULE_FIXED see
+ * select_fixed).  Returns |C|, or -1 if memory runs out. */
 int64_t orc_select(const uint8_t *SC, int64_t n, int Ns, int64_t R, int rule,
                    int64_t *hist, int32_t *last_out, int32_t *cand)
 {
     for (int v = 0; v <= Ns; v++) hist[v] = 0;
     for (int64_t i = 0; i < n; i++) hist[SC[i]]++;
+    if (rule == ORC_RULE_FIXED) return select_fixed(SC, n, Ns, R, last_out, cand);
     int last = orc_threshold(hist, Ns, R, rule);
     int64_t nc = 0;
     for (int64_t i = 0; i < n; i++)
@@ -696,6 +728,7 @@ static int query_one(const orc_index *x, orc_work *w, const float *q, double alp
     int64_t hist[256];
     int32_t last = 0;
     int64_t nc = orc_select(w->sc, n, Ns, R, rule, hist, &last, w->cand);
+    if (nc < 0) return ORC_ENOMEM;
     if (dp && dp->hist) memcpy(dp->hist, hist, sizeof(int64_t) * (size_t)(Ns + 1));
     if (dp && dp->last) dp->last[0] = last;
     if (dp && dp->ncand) dp->ncand[0] = nc;
@@ -727,7 +760,7 @@ static int query_one(const orc_index *x, orc_work *w, const float *q, double alp
 static int check_args(const orc_index *x, double alpha, double beta, int k, int rule)
 {
     if (!x || !(alpha > 0.0 && alpha <= 1.0) || !(beta >= 0.0 && beta <= 1.0) || k < 1 ||
-        (int64_t)k > x->n || (rule != ORC_RULE_PRINTED && rule != ORC_RULE_PROSE) || x->Ns > 255)
+        (int64_t)k > x->n || (rule != ORC_RULE_PRINTED && rule != ORC_RULE_PROSE && rule != ORC_RULE_FIXED) || x->Ns > 255)
         return ORC_EINVAL;
     return ORC_OK;
 }

@@ -502,3 +502,49 @@ def test_workload_recipes_are_seeded_and_shaped():
             assert np.array_equal(X, np.rint(X)) and X.min() >= 0 and X.max() <= 255
         if ws.recipe == "sphere":
             np.testing.assert_allclose(np.linalg.norm(X, axis=1), 1.0, rtol=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# The fixed-budget rule (SuCo's selection, which Section 4.3 contrasts with
+# Alg 5): the floor(beta*n) highest SC-scores, ties broken by the lower id.
+# ---------------------------------------------------------------------------
+
+def test_fixed_budget_hand_case():
+    sc = np.array([3, 3, 2, 2, 2, 1, 1, 0, 0, 0], np.uint8)
+    # R = 3: both 3s, then the lowest id of level 2
+    hist, last, cand = O.select(sc, 3, 3, O.RULE_FIXED)
+    assert list(cand) == [0, 1, 2] and last == 3
+    # R = 5: the whole of level 2 is taken
+    assert list(O.select(sc, 3, 5, O.RULE_FIXED)[2]) == [0, 1, 2, 3, 4]
+    assert O.select(sc, 3, 5, O.RULE_FIXED)[1] == 3
+    # R = 8: one zero, the lowest id among them
+    hist, last, cand = O.select(sc, 3, 8, O.RULE_FIXED)
+    assert list(cand) == [0, 1, 2, 3, 4, 5, 6, 7] and last == 1
+    # R = 0: nothing; R = n: everything
+    assert O.select(sc, 3, 0, O.RULE_FIXED)[2].size == 0 and O.select(sc, 3, 0, O.RULE_FIXED)[1] == 4
+    assert list(O.select(sc, 3, 10, O.RULE_FIXED)[2]) == list(range(10))
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_fixed_budget_properties(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 3000))
+    Ns = int(rng.integers(1, 17))
+    sc = rng.integers(0, Ns + 1, n).astype(np.uint8)
+    if seed % 3 == 0:
+        sc[rng.random(n) < 0.8] = 0  # mostly unprobed points
+    R = int(rng.integers(0, n + 1))
+    hist, last, cand = O.select(sc, Ns, R, O.RULE_FIXED)
+    assert np.array_equal(hist, np.bincount(sc, minlength=Ns + 1))
+    assert cand.size == min(R, n)
+    assert np.all(np.diff(cand) > 0)
+    chosen = np.zeros(n, bool)
+    chosen[cand] = True
+    if cand.size and cand.size < n:
+        assert sc[chosen].min() >= sc[~chosen].max()
+        L = int(sc[chosen].min())
+        # at the boundary level the chosen ids are the smallest ones
+        at = np.flatnonzero(sc == L)
+        k = int(np.count_nonzero(chosen & (sc == L)))
+        assert np.array_equal(np.flatnonzero(chosen & (sc == L)), at[:k])
+        assert last == L + 1
