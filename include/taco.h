@@ -56,8 +56,14 @@ enum tc_status {
  *   TC_RULE_PRINTED: c_j <= beta*n - cum   (as the algorithm prints it), or
  *   TC_RULE_PROSE:   cum <= beta*n         (as the text describes it);
  * the first failing level ends the scan.  Candidates are the points whose
- * SC-score is >= last_collision (every point when it drops to -1). */
-enum tc_select_rule { TC_RULE_PRINTED = 0, TC_RULE_PROSE = 1 };
+ * SC-score is >= last_collision (every point when it drops to -1).
+ *   TC_RULE_FIXED:   not Alg 5 but the fixed budget it is contrasted with in
+ *                    Section 4.3 (SuCo's selection): exactly the floor(beta*n)
+ *                    points of highest SC-score, ties by the lower id.  The
+ *                    reported threshold is the lowest level taken completely.
+ *                    Searches with this rule use the split count form
+ *                    (TC_COUNT_SPLIT) whatever TC_OPT_COUNT_MODE says. */
+enum tc_select_rule { TC_RULE_PRINTED = 0, TC_RULE_PROSE = 1, TC_RULE_FIXED = 2 };
 
 /* Options for tc_set_option. */
 enum tc_option {

@@ -17,7 +17,7 @@ import numpy as np
 
 __all__ = [
     "TC_OK", "TC_EINVAL", "TC_EIO", "TC_EFORMAT", "TC_ENOMEM", "TC_EDEVICE",
-    "TC_RULE_PRINTED", "TC_RULE_PROSE", "TC_OPT_SELECT_RULE", "TC_OPT_MAX_BATCH",
+    "TC_RULE_PRINTED", "TC_RULE_PROSE", "TC_RULE_FIXED", "TC_OPT_SELECT_RULE", "TC_OPT_MAX_BATCH",
     "TC_OPT_TILE_IDS", "TC_OPT_PROFILE", "TC_OPT_SCRATCH_BYTES", "TC_OPT_PRECISION",
     "TC_FP32", "TC_BF16", "TC_OPT_COUNT_MODE", "TC_COUNT_AUTO", "TC_COUNT_SPLIT",
     "TC_COUNT_FUSED", "TC_COUNT_LIST", "TC_OPT_LIST_LEVEL", "TC_OPT_GRAPH", "TC_OPT_PROBE_QPW", "TC_OPT_RERANK_BLOCKS", "KERNELS",
@@ -30,7 +30,7 @@ __all__ = [
 ]
 
 TC_OK, TC_EINVAL, TC_EIO, TC_EFORMAT, TC_ENOMEM, TC_EDEVICE = 0, -1, -2, -3, -4, -5
-TC_RULE_PRINTED, TC_RULE_PROSE = 0, 1
+TC_RULE_PRINTED, TC_RULE_PROSE, TC_RULE_FIXED = 0, 1, 2
 TC_OPT_SELECT_RULE, TC_OPT_MAX_BATCH, TC_OPT_TILE_IDS, TC_OPT_PROFILE, TC_OPT_SCRATCH_BYTES = 1, 2, 3, 4, 5
 TC_OPT_PRECISION = 6
 TC_FP32, TC_BF16, TC_U8 = 0, 1, 2

@@ -1098,9 +1098,22 @@ struct SelectArgs {
 };
 
 // Alg 5 scan from the level histogram (level 0 = n minus the others).
+// Rule 2, the fixed budget (the R highest SC-scores, ties by lower id):
+// the boundary level L is the highest level whose points and those above
+// reach R; the result is L + 1, every point above L is a candidate, and
+// k_select_level adds the first points of level L in id order.
 __device__ int select_threshold(const uint32_t *h, int Ns, int64_t n, int64_t R, int rule) {
     int64_t above0 = 0;
     for (int v = 1; v <= Ns; v++) above0 += h[v];
+    if (rule == 2) {
+        int64_t above = 0;
+        for (int v = Ns; v >= 0; v--) {
+            const int64_t hv = v == 0 ? n - above0 : static_cast<int64_t>(h[v]);
+            if (above + hv >= R) return v + 1;
+            above += hv;
+        }
+        return 0;
+    }
     int last = Ns;
     int64_t cum = 0;
     for (int v = Ns; v >= 0; v--) {
@@ -1409,6 +1422,86 @@ __device__ __forceinline__ void select_query(const SelectArgs &sa, int Ns, int64
         }
     }
     if (__any(scount != 0u)) flush_stage(stage, scount, counter, CandOut{cq}, lane);
+}
+
+// Fixed-budget rule, second part: after k_select has listed the points
+// above the boundary level L, append the first R - (their number) points of
+// level L in id order (ids below n), and set the candidate count.  One
+// workgroup per query walks the packed counts in id order, 256 words at a
+// time, ranking matches by a workgroup prefix sum; it stops once enough are
+// found.  grid nq, block SL_BLOCK.
+constexpr int SL_BLOCK = 256;
+
+template <int BITS>
+__global__ __launch_bounds__(SL_BLOCK) void k_select_level(SelectArgs sa, int Ns, int64_t n, int64_t words,
+                                                           const uint32_t *__restrict__ sc32) {
+    constexpr int PER_WORD = 32 / BITS;
+    constexpr uint32_t MASK = (1u << BITS) - 1u;
+    __shared__ uint32_t wtot[SL_BLOCK / WAVE];
+    __shared__ uint32_t base_s;
+    const int q = blockIdx.x, tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const uint32_t *h = sa.hist + static_cast<int64_t>(q) * (Ns + 1);
+    int64_t above0 = 0;
+    for (int v = 1; v <= Ns; v++) above0 += h[v];
+    int64_t above = 0, need = 0;
+    int L = -1;
+    for (int v = Ns; v >= 0; v--) {
+        const int64_t hv = v == 0 ? n - above0 : static_cast<int64_t>(h[v]);
+        if (above + hv >= sa.R) {
+            L = v;
+            need = sa.R - above;
+            break;
+        }
+        above += hv;
+    }
+    if (L < 0 || need <= 0) return;  // uniform: nothing to add at the boundary level
+    uint32_t *counter = sa.cand_count + q;
+    int32_t *cq = sa.cand + static_cast<int64_t>(q) * sa.cap;
+    if (tid == 0) base_s = *counter;
+    __syncthreads();
+    const int64_t base = base_s;
+    const uint32_t *src = sc32 + static_cast<int64_t>(q) * words;
+    const uint32_t lv = static_cast<uint32_t>(L);
+    int64_t taken = 0;
+    for (int64_t w0 = 0; w0 < words && taken < need; w0 += SL_BLOCK) {
+        const int64_t wi = w0 + tid;
+        uint32_t mbits = 0u;
+        if (wi < words) {
+            const uint32_t word = src[wi];
+#pragma unroll
+            for (int k = 0; k < PER_WORD; k++) {
+                const int64_t id = wi * PER_WORD + k;
+                if (id < n && ((word >> (BITS * k)) & MASK) == lv) mbits |= 1u << k;
+            }
+        }
+        const uint32_t cnt = static_cast<uint32_t>(__popc(mbits));
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, WAVE);
+            if (lane >= o) incl += y;
+        }
+        if (lane == WAVE - 1) wtot[w] = incl;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int i = 0; i < SL_BLOCK / WAVE; i++) {
+            before += i < w ? wtot[i] : 0u;
+            total += wtot[i];
+        }
+        int64_t r = taken + before + incl - cnt;
+        while (mbits) {
+            const int k = __ffs(mbits) - 1;
+            mbits &= mbits - 1u;
+            if (r < need && base + r < sa.cap) cq[base + r] = static_cast<int32_t>(wi * PER_WORD + k);
+            r++;
+        }
+        taken += total;
+        __syncthreads();  // wtot is rewritten by the next round
+    }
+    if (tid == 0) {
+        const int64_t end = base + (taken < need ? taken : need);
+        *counter = static_cast<uint32_t>(end < sa.cap ? end : sa.cap);
+    }
 }
 
 // Alg 5 on a query's lists: the threshold from the histogram's levels >=
@@ -2755,6 +2848,17 @@ hipError_t launch_unpack_counts(const uint32_t *sc, int nq, int T, int W, int bi
         k_unpack_counts<4><<<grid, 256, 0, st>>>(sc, words_q, n, out);
     else
         k_unpack_counts<8><<<grid, 256, 0, st>>>(sc, words_q, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_select_level(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
+                               hipStream_t st) {
+    SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, nullptr, nullptr, nullptr, nullptr};
+    const int64_t words = static_cast<int64_t>(c.T) * c.W * c.bits / 32;
+    if (c.bits == 4)
+        k_select_level<4><<<c.nq, SL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words, sc);
+    else
+        k_select_level<8><<<c.nq, SL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words, sc);
     return hipGetLastError();
 }
 

@@ -704,8 +704,10 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
     // AUTO takes the split launches: on MI355X the ~T*nq independent
     // workgroups of the split form overlap better than the fused groups'
     // lock-step rounds (10.2 vs 17.3 ms per 10k-query step at n = 1M)
-    const bool fused = x->count_mode == TC_COUNT_FUSED;
-    const bool list = x->count_mode == TC_COUNT_LIST;
+    // the fixed-budget rule needs the packed counts of the split form
+    const bool fixed = x->rule == TC_RULE_FIXED;
+    const bool fused = x->count_mode == TC_COUNT_FUSED && !fixed;
+    const bool list = x->count_mode == TC_COUNT_LIST && !fixed;
     for (int64_t b0 = 0; b0 < c.nq; b0 += x->Qb) {
         const int nb = static_cast<int>(std::min<int64_t>(x->Qb, c.nq - b0));
         const float *Qb = c.Q + b0 * x->d;
@@ -796,6 +798,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             record(x, K_COUNT, st, false);
             record(x, K_SELECT, st, true);
             TC_HIP(taco::launch_select(cl, sl, x->sc, st), "select kernel");
+            if (fixed) TC_HIP(taco::launch_select_level(cl, sl, x->sc, st), "boundary-level select kernel");
             record(x, K_SELECT, st, false);
         }
 
@@ -877,7 +880,7 @@ int run(tc_index *x, const Call &c, void *stream) {
     if (c.nq == 0) return TC_OK;
     DeviceGuard g(x->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (x->count_mode == TC_COUNT_FUSED && x->fused_groups <= 0)
+    if (x->count_mode == TC_COUNT_FUSED && x->fused_groups <= 0 && x->rule != TC_RULE_FIXED)
         return fail(TC_EINVAL, "the fused count/select kernel cannot keep all tiles of a query resident");
     if (!x->use_graph || c.dump) return enqueue(x, c, st);
     GraphKey key;
@@ -1003,7 +1006,8 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
     DeviceGuard g(x->device);
     switch (option) {
     case TC_OPT_SELECT_RULE:
-        if (value != TC_RULE_PRINTED && value != TC_RULE_PROSE) return fail(TC_EINVAL, "unknown rule");
+        if (value != TC_RULE_PRINTED && value != TC_RULE_PROSE && value != TC_RULE_FIXED)
+            return fail(TC_EINVAL, "unknown rule");
         x->rule = static_cast<int>(value);
         return TC_OK;
     case TC_OPT_MAX_BATCH:

@@ -511,3 +511,47 @@ def test_autotune_keeps_results_and_caches(taco_mod, tiny, tmp_path):
     assert torch.equal(ids2, ref_ids) and torch.equal(d2, ref_d)
     idx.close()
     idx2.close()
+
+
+# ---------------------------------------------------------------------------
+# The fixed-budget rule (SuCo's selection, contrasted with Alg 5 in Section
+# 4.3): exactly floor(beta*n) candidates, the highest SC-scores, ties by id.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha,beta", [
+    (0.05, 0.005), (0.01, 0.02), (0.2, 0.001),
+    (0.05, 0.0),     # R = 0: no candidates, results padded
+    (0.003, 0.5),    # the boundary level is 0: unprobed points in id order
+    (1.0, 1.0)])     # every point at level Ns, all taken
+def test_tiny_fixed_budget_rule(taco_mod, tiny, alpha, beta):
+    print(f"[tiny] fixed budget alpha={alpha} beta={beta}", flush=True)
+    _run_all(taco_mod, tiny["path"], tiny["oidx"], tiny["Q"], 10, alpha, beta, 2,
+             f"tiny fixed a={alpha} b={beta}")
+
+
+def test_fixed_budget_rule_takes_the_split_form(taco_mod, tiny):
+    """Whatever count form is asked for, the rule runs on the packed counts
+    (stage by stage against the oracle); the exact 8-bit re-rank and the
+    captured graph give the FP32 results bit for bit."""
+    t = taco_mod
+    rule = ((t.TC_OPT_SELECT_RULE, t.TC_RULE_FIXED),)
+    for opts in (((t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST),), ((t.TC_OPT_GRAPH, 1),)):
+        print(f"[tiny] fixed budget with {opts}", flush=True)
+        _run_all(t, tiny["path"], tiny["oidx"], tiny["Q"], 10, 0.05, 0.005, 2, f"tiny fixed {opts}",
+                 options=opts)
+    ref = _search_bits(t, tiny["path"], tiny["Q"], 0.05, rule)
+    got = _search_bits(t, tiny["path"], tiny["Q"], 0.05,
+                       rule + ((t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST), (t.TC_OPT_PRECISION, t.TC_U8)),
+                       calls=2, graph=True)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+def test_fixed_budget_rule_many_tiles(taco_mod):
+    w = synthdata.WORKLOADS["gmm-int-1m-d128"].scaled("gmm-int-140k-d128", n=140_000, nq=16)
+    X, Q = synthdata.base_and_queries(w)
+    path = workload_index(w, X)
+    oidx = O.OracleIndex(path)
+    print(f"[{w.name}] fixed budget, many tiles", flush=True)
+    for beta in (0.005, 0.05):
+        _run_all(taco_mod, path, oidx, Q, 10, 0.05, beta, 2, f"140k fixed b={beta}",
+                 options=((taco_mod.TC_OPT_TILE_IDS, 8192),))
