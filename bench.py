@@ -325,7 +325,7 @@ def algorithmic_bytes(idx, q, w, alpha, nq, precision=0):
 # rocprofv3 summaries (run after a profiled bench; they read only its CSVs)
 # ---------------------------------------------------------------------------
 
-_SHORT = (("k_count_select", "count_select"), ("k_list_select", "list_select"), ("k_select", "select"),
+_SHORT = (("k_count_select", "count_select"), ("k_list_select", "list_select"), ("k_select_level", "select_level"), ("k_select", "select"),
           ("k_rerank16", "rerank"), ("k_rerank8", "rerank"), ("k_rerank", "rerank"),
           ("k_recheck_topk", "recheck"), ("k_topk", "topk"), ("k_probe", "probe"),
           ("k_transform", "transform"), ("k_cdist_mfma", "cdist"), ("k_qstats", "cdist"),
@@ -508,9 +508,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4000)
     ap.add_argument("--alpha", type=float, default=None,
                     help="run only this collision ratio of the sweep (profiling runs)")
-    ap.add_argument("--paths", default="fp32,tuned,lowp",
-                    help="comma list of fp32 (defaults), tuned (autotuned, exact), lowp (tuned + FP8 "
-                         "centroid distances on the matrix cores)")
+    ap.add_argument("--paths", default="fp32,fixed,tuned,lowp",
+                    help="comma list of fp32 (defaults), fixed (defaults with the fixed-budget "
+                         "selection rule, SuCo's, in place of Alg 5), tuned (autotuned, exact), lowp "
+                         "(tuned + FP8 centroid distances on the matrix cores)")
     ap.add_argument("--skip-precision-report", action="store_true")
     ap.add_argument("--skip-build", action="store_true", help="omit the GPU index-build leg")
     ap.add_argument("--build-only", action="store_true",
@@ -587,6 +588,8 @@ def main():
     results = {}
     for pname in paths:
         idx = taco.Index(path, 0)
+        if pname == "fixed":
+            idx.set_option(taco.TC_OPT_SELECT_RULE, taco.TC_RULE_FIXED)
         if pname in ("tuned", "lowp"):
             # one batch per step when the GPU has room: candidate scratch is sized for the
             # worst case (every point a candidate), ~12.5 MB per query at 1M points, so a
