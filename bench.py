@@ -537,7 +537,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps(dict(error="this build measures one GPU only; run with --gpus 1",
+        print(json.dumps(dict(error="the benchmark runs on one GPU only: the path is measured on one GPU's share; run with --gpus 1",
                               n_gpus=args.gpus)), flush=True)
         sys.exit(2)
 
