@@ -496,15 +496,15 @@ __global__ __launch_bounds__(256) void k_km_assign(KmArgs a, int HM, int nblk, c
         atomicAdd(&pcnt[(static_cast<int64_t>(g) * nblk + b) * a.l + threadIdx.x], hc[threadIdx.x]);
 }
 
-constexpr int KM_PBLOCK = 512;                   // threads of the partial-sum kernel
+constexpr int KM_PBLOCK = 1024;                  // threads of the partial-sum kernel
 constexpr int KM_PW = KM_PBLOCK / WAVE;           // its waves
-constexpr int KM_XVALS = 4096;                    // staged values per chunk
+constexpr int KM_XVALS = 8192;                    // staged values per chunk
 constexpr int KM_XPT = KM_XVALS / KM_PBLOCK;      // staged values per thread
 constexpr int KM_PPT = 64 * KM_HMAX / KM_PBLOCK;  // (cluster, dim) pairs per thread
 
 // psum[g][b][c][t]: sums of x_t over the points of block b labelled c, in
 // ascending position order.  grid (nblk, 2*Ns).  The block streams through
-// LDS in chunks of ch = min(512, 4096/h) points, thread j holding point j of
+// LDS in chunks of ch = min(1024, 8192/h) points, thread j holding point j of
 // the chunk; the next chunk is loaded into registers while the current one
 // is summed.  Per chunk, the points are listed cluster by cluster in position
 // order (a stable counting sort: per-wave membership masks, prefix sums over
