@@ -1460,21 +1460,27 @@ __global__ __launch_bounds__(SL_BLOCK) void k_select_level(SelectArgs sa, int Ns
     if (tid == 0) base_s = *counter;
     __syncthreads();
     const int64_t base = base_s;
-    const uint32_t *src = sc32 + static_cast<int64_t>(q) * words;
+    // words is a multiple of 4 (tiles hold a multiple of 1024 ids): each
+    // thread takes one 16-byte word, i.e. four 32-bit words, per round
+    const uint4 *src = reinterpret_cast<const uint4 *>(sc32 + static_cast<int64_t>(q) * words);
+    const int64_t words4 = words / 4;
     const uint32_t lv = static_cast<uint32_t>(L);
     int64_t taken = 0;
-    for (int64_t w0 = 0; w0 < words && taken < need; w0 += SL_BLOCK) {
+    for (int64_t w0 = 0; w0 < words4 && taken < need; w0 += SL_BLOCK) {
         const int64_t wi = w0 + tid;
-        uint32_t mbits = 0u;
-        if (wi < words) {
-            const uint32_t word = src[wi];
+        uint32_t mb[4] = {0u, 0u, 0u, 0u};
+        if (wi < words4) {
+            const uint4 v4 = src[wi];
+            const uint32_t wv[4] = {v4.x, v4.y, v4.z, v4.w};
 #pragma unroll
-            for (int k = 0; k < PER_WORD; k++) {
-                const int64_t id = wi * PER_WORD + k;
-                if (id < n && ((word >> (BITS * k)) & MASK) == lv) mbits |= 1u << k;
-            }
+            for (int j = 0; j < 4; j++)
+#pragma unroll
+                for (int k = 0; k < PER_WORD; k++) {
+                    const int64_t id = (wi * 4 + j) * PER_WORD + k;
+                    if (id < n && ((wv[j] >> (BITS * k)) & MASK) == lv) mb[j] |= 1u << k;
+                }
         }
-        const uint32_t cnt = static_cast<uint32_t>(__popc(mbits));
+        const uint32_t cnt = static_cast<uint32_t>(__popc(mb[0]) + __popc(mb[1]) + __popc(mb[2]) + __popc(mb[3]));
         uint32_t incl = cnt;
 #pragma unroll
         for (int o = 1; o < WAVE; o <<= 1) {
@@ -1489,11 +1495,16 @@ __global__ __launch_bounds__(SL_BLOCK) void k_select_level(SelectArgs sa, int Ns
             total += wtot[i];
         }
         int64_t r = taken + before + incl - cnt;
-        while (mbits) {
-            const int k = __ffs(mbits) - 1;
-            mbits &= mbits - 1u;
-            if (r < need && base + r < sa.cap) cq[base + r] = static_cast<int32_t>(wi * PER_WORD + k);
-            r++;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            uint32_t mbits = mb[j];
+            while (mbits) {
+                const int k = __ffs(mbits) - 1;
+                mbits &= mbits - 1u;
+                if (r < need && base + r < sa.cap)
+                    cq[base + r] = static_cast<int32_t>((wi * 4 + j) * PER_WORD + k);
+                r++;
+            }
         }
         taken += total;
         __syncthreads();  // wtot is rewritten by the next round
