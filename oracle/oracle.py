@@ -8,8 +8,9 @@ inputs come from ``synthdata`` (random draws only).
 What lives where:
   * ``taco_oracle.c`` (loaded here through ctypes): the FP32 canonical
     transform and half distances, k-means (Alg 3's clustering step), the
-    index file writer/reader, Scalable Dynamic Activation (Alg 4) with a
-    literal heap, Query-aware Candidates Selection (Alg 5), the k-ANNS query
+    index file writer/reader, Scalable Dynamic Activation (Alg 4) as the
+    cell order it produces, Query-aware Candidates Selection (Alg 5) as the
+    highest level that exceeds the re-rank budget, the k-ANNS query
     (Alg 6), and FP64 brute-force k-NN (Definition 2).
   * this file: the FP64 statistics of Alg 1 (mean, sample covariance,
     spectral decomposition through LAPACK's symmetric eigensolver), the greedy
@@ -82,11 +83,9 @@ def lib():
         L.orc_index_centroids.argtypes = [C.c_void_p, C.c_int]
         L.orc_index_centroids.restype = C.POINTER(C.c_float)
         L.orc_argsort.argtypes = [_f32p, C.c_int, _i32p]
-        for nm in ("orc_probe", "orc_probe_sorted"):
-            f = getattr(L, nm)
-            f.argtypes = [_f32p, _i32p, _f32p, _i32p, C.c_int, _i64p, C.c_int64, _i32p,
-                          C.POINTER(C.c_int32)]
-            f.restype = C.c_int64
+        L.orc_probe.argtypes = [_f32p, _i32p, _f32p, _i32p, C.c_int, _i64p, C.c_int64, _i32p,
+                                C.POINTER(C.c_int32)]
+        L.orc_probe.restype = C.c_int64
         L.orc_threshold.argtypes = [_i64p, C.c_int, C.c_int64, C.c_int]
         L.orc_threshold.restype = C.c_int
         L.orc_select.argtypes = [_u8p, C.c_int64, C.c_int, C.c_int64, C.c_int, _i64p,
@@ -301,16 +300,16 @@ def argsort(D: np.ndarray) -> np.ndarray:
     return idx
 
 
-def probe(D1, idx1, D2, idx2, sizes, A, closed_form: bool = False):
+def probe(D1, idx1, D2, idx2, sizes, A):
     """Alg 4 on one subspace: returns (cells in retrieval order, retrieved).
-    ``sizes`` are the l*l cell sizes (cell a*l+b)."""
+    ``sizes`` are the l*l cell sizes (cell a*l+b).  See orc_probe for the
+    order the cells are taken in."""
     l = len(D1)
     sizes = np.ascontiguousarray(sizes, np.int64)
     assert sizes.size == l * l and 0 < A <= int(sizes.sum())
     cells = np.empty(l * l, np.int32)
     nc = C.c_int32(0)
-    f = lib().orc_probe_sorted if closed_form else lib().orc_probe
-    got = f(np.ascontiguousarray(D1, np.float32), np.ascontiguousarray(idx1, np.int32),
+    got = lib().orc_probe(np.ascontiguousarray(D1, np.float32), np.ascontiguousarray(idx1, np.int32),
             np.ascontiguousarray(D2, np.float32), np.ascontiguousarray(idx2, np.int32),
             l, sizes, int(A), cells, C.byref(nc))
     return cells[:nc.value].copy(), int(got)

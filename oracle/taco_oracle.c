@@ -8,8 +8,9 @@
  * code, header, table or helper with the GPU library: the two meet only in the
  * serialized index file, which each side reads and writes with its own code.
  *
- * Everything here is written for clarity, not speed: scalar loops, a literal
- * binary heap for Scalable Dynamic Activation, full sorts.  OpenMP is used
+ * Everything here is written for clarity, not speed: scalar loops, full
+ * sorts (Scalable Dynamic Activation is written as the cell order it
+ * produces, all cells sorted by key).  OpenMP is used
  * only across independent points or queries, and every reduction is done in a
  * fixed order, so results do not depend on the thread count.
  *
@@ -383,91 +384,25 @@ void orc_argsort(const float *D, int l, int32_t *idx)
 }
 
 /* ------------------------------------------------------------------------- */
-/* Alg 4: Scalable Dynamic Activation, with a literal min-heap.                */
+/* Alg 4: Scalable Dynamic Activation, by the order it visits cells.           */
 /* ------------------------------------------------------------------------- */
 
-typedef struct {
-    float key;
-    int32_t pos;
-} hent;
-
-/* Heap order: pairs compare as (distance, row position), the natural order
- * of a min-heap of pairs. */
-static int hless(hent a, hent b) { return a.key < b.key || (a.key == b.key && a.pos < b.pos); }
-
-static void hpush(hent *h, int *sz, hent e)
-{
-    int i = (*sz)++;
-    h[i] = e;
-    while (i > 0) {
-        int p = (i - 1) / 2;
-        if (!hless(h[i], h[p])) break;
-        hent t = h[i]; h[i] = h[p]; h[p] = t;
-        i = p;
-    }
-}
-
-static void hpop(hent *h, int *sz)
-{
-    h[0] = h[--(*sz)];
-    int i = 0;
-    for (;;) {
-        int a = 2 * i + 1, b = a + 1, m = i;
-        if (a < *sz && hless(h[a], h[m])) m = a;
-        if (b < *sz && hless(h[b], h[m])) m = b;
-        if (m == i) break;
-        hent t = h[i]; h[i] = h[m]; h[m] = t;
-        i = m;
-    }
-}
-
 /*
- * Probe one subspace's IMI.  D1/D2: distances of the query's two halves to
- * the l centroids of each half; idx1/idx2: their ascending orders; size[c]:
- * number of points in cell c = a*l + b.  Cells are taken in ascending
- * distance-sum order through the heap of activated rows until at least A
- * points are retrieved (the stop test follows each retrieval, so at least
- * one cell is always taken).  Writes the probed cell ids in retrieval order
- * and returns the number of points retrieved.  A must not exceed the total
- * of size[] (else every cell is taken and the heap empties).
- */
-int64_t orc_probe(const float *D1, const int32_t *idx1, const float *D2, const int32_t *idx2,
-                  int l, const int64_t *size, int64_t A, int32_t *cells, int32_t *ncells)
-{
-    hent *heap = (hent *)malloc(sizeof(hent) * (size_t)(l + 1));
-    int32_t *active = (int32_t *)calloc((size_t)l, sizeof(int32_t));
-    int hs = 0, nc = 0;
-    int64_t got = 0;
-    hent first = {D1[idx1[0]] + D2[idx2[0]], 0};
-    hpush(heap, &hs, first);
-    while (hs > 0) {
-        hent sel = heap[0];
-        int pos = sel.pos;
-        int32_t cell = idx1[pos] * l + idx2[active[pos]];
-        cells[nc++] = cell;
-        got += size[cell];
-        if (got >= A) break;
-        if (active[pos] == 0 && pos < l - 1) {
-            hent nx = {D1[idx1[pos + 1]] + D2[idx2[0]], pos + 1};
-            hpush(heap, &hs, nx);
-        }
-        hpop(heap, &hs);
-        if (active[pos] < l - 1) {
-            active[pos]++;
-            sel.key = D1[idx1[pos]] + D2[idx2[active[pos]]];
-            hpush(heap, &hs, sel);
-        }
-    }
-    free(heap);
-    free(active);
-    *ncells = nc;
-    return got;
-}
-
-/*
- * Closed form of the same probe, used only to cross-check orc_probe: all
- * l*l cells sorted by (fl32 key, row rank, column rank), truncated at the
- * first prefix whose sizes reach A.
+ * What Alg 4 computes (Section 4.2).  Half 1's centroids in ascending
+ * distance make the rows of an l x l grid, half 2's the columns; a cell's key
+ * is the sum of its two half distances, fl32(D1[idx1[r]] + D2[idx2[c]]).
+ * Each row is non-decreasing along its columns, row r only becomes active
+ * after row r-1 has given up its first cell, and the active rows offer their
+ * next cell through a min-priority queue of (key, row).  The cells therefore
+ * come out in ascending key order, equal keys in ascending row and then
+ * column rank (a row holds one queue entry at a time and hands out its
+ * columns in order).  Retrieval stops at the first cell that brings the
+ * retrieved total to at least A.  This function states exactly that: every
+ * cell tagged with (key, row rank, column rank), the whole grid sorted, and
+ * the sorted list cut after the first prefix whose sizes reach A (at least
+ * one cell is always taken).  Writes the probed cell ids c = a*l + b in
+ * retrieval order and returns the number of points retrieved.  A must not
+ * exceed the total of size[].
  */
 typedef struct {
     float key;
@@ -482,8 +417,8 @@ static int kcmp(const void *pa, const void *pb)
     return (a->c > b->c) - (a->c < b->c);
 }
 
-int64_t orc_probe_sorted(const float *D1, const int32_t *idx1, const float *D2, const int32_t *idx2,
-                         int l, const int64_t *size, int64_t A, int32_t *cells, int32_t *ncells)
+int64_t orc_probe(const float *D1, const int32_t *idx1, const float *D2, const int32_t *idx2,
+                  int l, const int64_t *size, int64_t A, int32_t *cells, int32_t *ncells)
 {
     int K = l * l;
     kcell *all = (kcell *)malloc(sizeof(kcell) * (size_t)K);
@@ -512,30 +447,30 @@ int64_t orc_probe_sorted(const float *D1, const int32_t *idx1, const float *D2, 
 /* ------------------------------------------------------------------------- */
 
 /*
- * From the level histogram hist[0..Ns] of the SC-scores and the re-rank
- * budget R = floor(beta*n), return last_collision.  Scanning levels from Ns
- * down, the running total cum includes the current level; the level passes
- * when
- *   ORC_RULE_PRINTED: hist[j] <= beta*n - cum, i.e. hist[j] + cum <= R
- *                     (the condition as the algorithm prints it), or
- *   ORC_RULE_PROSE:   cum <= R (the accompanying text: stop once the
- *                     accumulated candidates exceed beta*n),
- * and each passing level lowers last_collision by one; the first failing
- * level stops the scan.  Result can be -1 when every level passes.
+ * Alg 5's threshold (Section 4.3) from the level histogram hist[0..Ns] and
+ * the re-rank budget R = floor(beta*n).  Write S(v) for the number of points
+ * whose SC-score is at least v.  Alg 5 walks the levels from Ns downwards
+ * and stops at the first level where the budget is exceeded; the threshold
+ * is that level, and -1 when no level exceeds it.  "Exceeded" at level v is
+ *   ORC_RULE_PRINTED: hist[v] + S(v) > R  (the test as the algorithm prints
+ *                     it: the level's count against beta*n minus a running
+ *                     total that already includes it), or
+ *   ORC_RULE_PROSE:   S(v) > R            (the text's reading: stop once the
+ *                     accumulated candidates exceed beta*n).
+ * So the threshold is the highest level that exceeds the budget.
  */
 int orc_threshold(const int64_t *hist, int Ns, int64_t R, int rule)
 {
-    int last = Ns;
-    int64_t cum = 0;
-    for (int j = Ns; j >= 0; j--) {
-        cum += hist[j];
-        int pass = rule == ORC_RULE_PROSE ? (cum <= R) : (hist[j] + cum <= R);
-        if (pass)
-            last -= 1;
-        else
-            break;
+    int64_t *S = (int64_t *)malloc(sizeof(int64_t) * (size_t)(Ns + 2));
+    S[Ns + 1] = 0;
+    for (int v = Ns; v >= 0; v--) S[v] = S[v + 1] + hist[v];
+    int top = -1;
+    for (int v = 0; v <= Ns; v++) {
+        int64_t load = rule == ORC_RULE_PROSE ? S[v] : hist[v] + S[v];
+        if (load > R) top = v;
     }
-    return last;
+    free(S);
+    return top;
 }
 
 static int u64cmp(const void *pa, const void *pb)
@@ -548,8 +483,10 @@ static int u64cmp(const void *pa, const void *pb)
  * 4.3 contrasts with Alg 5): the R points of highest SC-score, ties by lower
  * id -- the first min(R, n) of all points sorted by (SC descending, id
  * ascending).  Written as that sort.  cand: the chosen ids ascending;
- * last_out: the lowest level taken completely (the last chosen point's
- * SC-score plus one; Ns + 1 when R = 0).  Returns the number chosen. */
+ * last_out: L + 1, where L, the boundary level, is the SC-score of the last
+ * point chosen (Ns + 1 when R = 0).  The chosen points are every point with
+ * SC > L and the first R - #{SC > L} points of level L in id order, so
+ * level L itself may be taken whole or in part.  Returns the number chosen. */
 static int64_t select_fixed(const uint8_t *SC, int64_t n, int Ns, int64_t R, int32_t *last_out,
                             int32_t *cand)
 {

@@ -1097,33 +1097,29 @@ struct SelectArgs {
     const uint32_t *redo;    // null: query blockIdx.y; else the queue of ListArgs::redo
 };
 
-// Alg 5 scan from the level histogram (level 0 = n minus the others).
+// Alg 5's threshold (Section 4.3) from the level histogram (level 0 = n
+// minus the others).  With S(v) the number of points scoring at least v,
+// the threshold is the highest level at which the re-rank budget R is
+// exceeded: h[v] + S(v) > R as the algorithm prints its test (rule 0), or
+// S(v) > R as the text states it (rule 1); -1 when no level exceeds it.
 // Rule 2, the fixed budget (the R highest SC-scores, ties by lower id):
-// the boundary level L is the highest level whose points and those above
-// reach R; the result is L + 1, every point above L is a candidate, and
-// k_select_level adds the first points of level L in id order.
+// the boundary level L is the highest level with S(L) >= R; the result is
+// L + 1, every point above L is a candidate, and k_select_level adds the
+// first R - S(L + 1) points of level L in id order.
 __device__ int select_threshold(const uint32_t *h, int Ns, int64_t n, int64_t R, int rule) {
     int64_t above0 = 0;
     for (int v = 1; v <= Ns; v++) above0 += h[v];
-    if (rule == 2) {
-        int64_t above = 0;
-        for (int v = Ns; v >= 0; v--) {
-            const int64_t hv = v == 0 ? n - above0 : static_cast<int64_t>(h[v]);
-            if (above + hv >= R) return v + 1;
-            above += hv;
-        }
-        return 0;
-    }
-    int last = Ns;
-    int64_t cum = 0;
+    int64_t S = 0;  // S(v), built from the top level down
     for (int v = Ns; v >= 0; v--) {
         const int64_t hv = v == 0 ? n - above0 : static_cast<int64_t>(h[v]);
-        cum += hv;
-        const bool pass = rule == 1 ? (cum <= R) : (hv + cum <= R);
-        if (!pass) break;
-        last--;
+        S += hv;
+        if (rule == 2) {
+            if (S >= R) return v + 1;
+        } else if ((rule == 1 ? S : hv + S) > R) {
+            return v;
+        }
     }
-    return last;
+    return rule == 2 ? 0 : -1;
 }
 
 __device__ __forceinline__ void dump_threshold(int32_t *dump_last, int64_t *dump_hist, int q, int Ns,
@@ -1547,14 +1543,17 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
     uint32_t *tq = la.toff ? la.toff + static_cast<int64_t>(q) * (la.T + 1) : nullptr;
     uint32_t *h = hist + static_cast<int64_t>(q) * (Ns + 1);
     if (threadIdx.x == 0) {
-        int last = Ns;
-        int64_t cum = 0;
+        // the highest listed level (>= lv) exceeding the budget, as in
+        // select_threshold; lv - 1 when none does (the threshold is lower)
+        int last = lv - 1;
+        int64_t S = 0;
         for (int v = Ns; v >= lv; v--) {
             const int64_t hv = h[v];
-            cum += hv;
-            const bool pass = la.rule == 1 ? (cum <= la.R) : (hv + cum <= la.R);
-            if (!pass) break;
-            last--;
+            S += hv;
+            if ((la.rule == 1 ? S : hv + S) > la.R) {
+                last = v;
+                break;
+            }
         }
         if (la.dump_last || la.dump_hist)
             // stage dumps: the histogram is complete here; the threshold is

@@ -17,8 +17,11 @@ available.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import math
+import os
+import threading
 from typing import Dict, Optional, Tuple
 
 import numpy as np
@@ -133,29 +136,59 @@ def _mixture_params(rng, recipe: str, d: int):
     raise ValueError(f"unknown recipe {recipe!r}")
 
 
-def _draw_rows(rng, recipe: str, p, m: int, d: int) -> np.ndarray:
+def _draw_rows(rng, recipe: str, p, m: int, d: int, work=None) -> np.ndarray:
+    """``m`` rows of a recipe from one stream.  ``work``: optional pair of
+    float64 ``(>= m, d)`` scratch arrays, reused across chunks (the values
+    are the same with or without them)."""
     if recipe == "aniso":
         z = rng.standard_normal((m, d)) * p["sqrt_lam"][None, :]
         x = z @ p["rot"].T + p["offset"][None, :]
         return np.maximum(x, 0.0).astype(np.float32)
     comp = rng.choice(len(p["weights"]), size=m, p=p["weights"])
-    x = p["means"][comp] + rng.standard_normal((m, d)) * p["sigma"][comp][:, None]
+    if work is None:
+        work = (np.empty((m, d)), np.empty((m, d)))
+    x, g = work[0][:m], work[1][:m]
+    np.take(p["means"], comp, axis=0, out=x)
+    rng.standard_normal(out=g)
+    g *= p["sigma"][comp][:, None]
+    x += g                                  # means + noise * sigma
     if recipe == "gmm_iso" or recipe == "zipf":
-        x = np.maximum(x, 0.0)
+        np.maximum(x, 0.0, out=x)
     elif recipe == "gmm_int":
-        x = np.clip(np.rint(x), 0.0, 255.0)
+        np.rint(x, out=x)
+        np.clip(x, 0.0, 255.0, out=x)
     elif recipe == "sphere":
         x /= np.linalg.norm(x, axis=1, keepdims=True)
     return x.astype(np.float32)
 
 
 def _draw(seed: int, recipe: str, p, m: int, d: int) -> np.ndarray:
+    """Rows ``[0, m)``: chunk ``c`` comes from the ``c``-th spawned stream,
+    so chunks can be drawn on several threads in any order."""
     out = np.empty((m, d), dtype=np.float32)
     nchunk = (m + CHUNK - 1) // CHUNK
-    for ci, rng in enumerate(_streams(seed, max(nchunk, 1))):
+    streams = _streams(seed, max(nchunk, 1))
+    local = threading.local()
+
+    def job(ci):
         lo, hi = ci * CHUNK, min(m, (ci + 1) * CHUNK)
-        if lo < hi:
-            out[lo:hi] = _draw_rows(rng, recipe, p, hi - lo, d)
+        if lo >= hi:
+            return
+        if recipe == "aniso":
+            out[lo:hi] = _draw_rows(streams[ci], recipe, p, hi - lo, d)
+            return
+        if getattr(local, "work", None) is None:
+            local.work = (np.empty((CHUNK, d)), np.empty((CHUNK, d)))
+        out[lo:hi] = _draw_rows(streams[ci], recipe, p, hi - lo, d, local.work)
+
+    # the anisotropic recipe's product already runs on the BLAS threads
+    workers = 1 if recipe == "aniso" else max(1, min(16, os.cpu_count() or 1, nchunk))
+    if workers == 1:
+        for ci in range(nchunk):
+            job(ci)
+    else:
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(job, range(nchunk)))
     return out
 
 

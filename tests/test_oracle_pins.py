@@ -232,6 +232,83 @@ def test_kmeans_ties_go_to_lower_centroid_and_empty_cluster_reseeded():
     assert a2.tolist() == [0, 0, 1]
 
 
+def _kmeans_2d_rows():
+    # Rows of a 10 x 5 matrix whose columns 2 and 3 are the half (off = 2,
+    # h = 2, ld = 5); the other columns hold values that would pull every
+    # result far away if they were read.  Training rows are 0, 2, 3, 5, 6, 8:
+    # positions 0..5 are (0,0) (3,0) (6,0) (10,0) (6,6) (50,50); rows 1, 4,
+    # 7, 9 are not in the sample.
+    pts = [(0, 0), (100, 100), (3, 0), (6, 0), (-50, -50), (10, 0), (6, 6), (5, 5), (50, 50), (4, 0)]
+    T = np.zeros((10, 5), np.float32)
+    for i, (a, b) in enumerate(pts):
+        T[i] = (1000 + i, -1000 - i, a, b, 7777)
+    return T, np.array([0, 2, 3, 5, 6, 8], np.int64)
+
+
+def test_kmeans_hand_case_with_column_offset_and_training_sample():
+    # Worked by hand (Alg 3's clustering step, Section 4.1), l = 3 > h = 2.
+    # Seeds: sample positions 0, 1, 5 -> (0,0), (3,0), (50,50).
+    # Step 1: (0,0) -> c0; (3,0) (6,0) (10,0) (6,6) -> c1 ((6,6): 72 vs 45);
+    #   (50,50) -> c2.  Means: c0 (0,0), c1 (25/4, 6/4), c2 (50,50).
+    # Step 2: (3,0) moves to c0 (9 vs 10.5625 + 2.25); the rest stay.
+    #   Means: c0 (1.5, 0), c1 (22/3, 2), c2 (50, 50).
+    # Final labels of all ten rows by nearest FP32 centroid:
+    #   after 1 step  (4,0) -> c1 (16 vs 5.0625 + 2.25), after 2 steps -> c0.
+    T, train = _kmeans_2d_rows()
+    init = np.array([0, 1, 5])
+    cent1, a1 = O.kmeans(T, 2, 2, 3, 1, init, train)
+    assert cent1.tolist() == [[0.0, 0.0], [6.25, 1.5], [50.0, 50.0]]
+    assert a1.tolist() == [0, 2, 0, 1, 0, 1, 1, 1, 2, 1]
+    cent2, a2 = O.kmeans(T, 2, 2, 3, 2, init, train)
+    assert cent2.tolist() == [[1.5, 0.0], [float(np.float32(22.0 / 3.0)), 2.0], [50.0, 50.0]]
+    assert a2.tolist() == [0, 2, 0, 1, 0, 1, 1, 1, 2, 0]
+    # a fixed point: a third step changes nothing
+    cent3, a3 = O.kmeans(T, 2, 2, 3, 3, init, train)
+    assert cent3.tolist() == cent2.tolist() and a3.tolist() == a2.tolist()
+
+
+@pytest.mark.parametrize("h,n,n_train", [(3, 200_000, 150_000), (8, 6_000, 2_500)])
+def test_kmeans_centroids_are_means_of_their_training_points(h, n, n_train):
+    # Well separated blobs, one seed in each: after the last Lloyd step every
+    # centroid is the FP64 mean of the training rows labelled with it (the
+    # labels cannot flip between the last step and the final pass), rounded
+    # to FP32.  The sample spans several of the oracle's 65536-row blocks in
+    # the first case; columns outside [off, off + h) hold other blobs.
+    rng = np.random.default_rng(100 + h)
+    l, ld, off = 7, h + 9, 5
+    means = rng.uniform(0, 20, (l, h)) + 40.0 * np.arange(l)[:, None]
+    lab = rng.integers(0, l, n)
+    T = rng.uniform(-1e4, 1e4, (n, ld)).astype(np.float32)
+    T[:, off:off + h] = (means[lab] + rng.normal(0, 0.5, (n, h))).astype(np.float32)
+    train = np.sort(rng.choice(n, n_train, replace=False)).astype(np.int64)
+    init = np.array([int(np.flatnonzero(lab[train] == c)[0]) for c in range(l)])
+    cent, assign = O.kmeans(T, off, h, l, 3, init, train)
+    assert np.array_equal(assign, lab)
+    X = T[train, off:off + h].astype(np.float64)
+    for c in range(l):
+        want = X[lab[train] == c].mean(axis=0).astype(np.float32)
+        np.testing.assert_array_max_ulp(cent[c], want, maxulp=1)
+
+
+def test_recall_at_k_hand_case_with_ties_and_padding():
+    # One-dimensional base 0, 1, 1, 2, 4 (rows 0..4); query 1 has squared
+    # distances 1, 0, 0, 1, 9 and query 3 has 9, 4, 4, 1, 1.
+    X = np.array([[0], [1], [1], [2], [4]], np.float32)
+    Q = np.array([[1], [3]], np.float32)
+    gi, gd = O.bruteforce(X, Q, 3)
+    assert gi.tolist() == [[1, 2, 0], [3, 4, 1]] and gd[:, 2].tolist() == [1.0, 4.0]
+    # k = 3: the third neighbour of query 1 is at distance 1, shared by rows
+    # 0 and 3, so either counts; for query 3 rows 1 and 2 tie at 4.
+    ids = np.array([[2, 1, 3], [4, 2, -1]])
+    assert O.recall_at_k(ids, gd, X, Q, 3) == pytest.approx(5 / 6)   # 3 + 2 hits
+    ids = np.array([[0, 4, -1], [-1, -1, -1]])
+    assert O.recall_at_k(ids, gd, X, Q, 3) == pytest.approx(1 / 6)   # row 0 only
+    # k = 1 reads the first column only, against each query's nearest distance
+    gi1, gd1 = O.bruteforce(X, Q, 1)
+    ids = np.array([[2, 4, 4], [4, 0, 0]])
+    assert O.recall_at_k(ids, gd1, X, Q, 1) == pytest.approx(1.0)
+
+
 def test_kmeans_final_assignment_is_nearest(tiny_index):
     info, X = tiny_index["info"], tiny_index["X"]
     T = O.transform(X[:3000], info["mean32"], info["B32"])
@@ -284,7 +361,35 @@ def test_alg4_hand_cases(case):
     assert got == case["retrieved"]
 
 
-def test_alg4_heap_equals_sorted_closed_form_on_random_grids():
+def _activation_walk(D1, i1, D2, i2, sizes, A):
+    """Section 4.2's retrieval mechanics, simulated independently of the
+    oracle: a priority queue holds one (key, row, column) entry per active
+    row; taking a row's cell offers that row's next column, and taking the
+    first cell of row r activates row r + 1.  Cells come out until the
+    retrieved total reaches A."""
+    import heapq
+    l = len(D1)
+    key = lambda r, c: np.float32(D1[i1[r]]) + np.float32(D2[i2[c]])  # noqa: E731
+    queue = [(key(0, 0), 0, 0)]
+    out, got = [], 0
+    while queue:
+        _, r, c = heapq.heappop(queue)
+        cell = int(i1[r]) * l + int(i2[c])
+        out.append(cell)
+        got += int(sizes[cell])
+        if got >= A:
+            break
+        if c + 1 < l:
+            heapq.heappush(queue, (key(r, c + 1), r, c + 1))
+        if c == 0 and r + 1 < l:
+            heapq.heappush(queue, (key(r + 1, 0), r + 1, 0))
+    return out, got
+
+
+def test_alg4_oracle_equals_activation_walk_on_random_grids():
+    # The oracle takes the cells in their sorted order (key, row, column); an
+    # independent simulation of the activation queue must give the same list,
+    # including under ties of the keys and FP32 rounding collisions.
     rng = np.random.default_rng(11)
     for trial in range(3000):
         l = int(rng.integers(1, 9))
@@ -303,8 +408,8 @@ def test_alg4_heap_equals_sorted_closed_form_on_random_grids():
         A = int(rng.integers(1, sizes.sum() + 1))
         i1, i2 = O.argsort(D1), O.argsort(D2)
         c1, g1 = O.probe(D1, i1, D2, i2, sizes, A)
-        c2, g2 = O.probe(D1, i1, D2, i2, sizes, A, closed_form=True)
-        assert c1.tolist() == c2.tolist() and g1 == g2, trial
+        c2, g2 = _activation_walk(D1, i1, D2, i2, sizes, A)
+        assert c1.tolist() == c2 and g1 == g2, trial
 
 
 def test_alg4_stops_at_first_prefix_reaching_budget():
@@ -341,6 +446,32 @@ def test_alg5_hand_cases(case, rule):
     assert hist.tolist() == case["hist"]
     assert last == case[rule]["last"]
     assert cand.tolist() == case[rule]["cand"]
+
+
+def _level_scan(hist, Ns, R, rule):
+    """Section 4.3's scan restated: levels are visited from Ns down with a
+    running total that includes the visited level; the visited levels that
+    keep within the budget each lower the threshold from Ns by one, and the
+    first level that does not ends the visit."""
+    import itertools
+    totals = list(itertools.accumulate(int(hist[v]) for v in range(Ns, -1, -1)))
+    counts = [int(hist[v]) for v in range(Ns, -1, -1)]
+    within = (t <= R if rule == O.RULE_PROSE else c + t <= R for c, t in zip(counts, totals))
+    return Ns - sum(1 for _ in itertools.takewhile(bool, within))
+
+
+def test_alg5_threshold_equals_level_scan():
+    # The oracle states the threshold as the highest level exceeding the
+    # budget; the scan of Section 4.3 must give the same level, -1 included.
+    rng = np.random.default_rng(17)
+    for trial in range(2000):
+        Ns = int(rng.integers(0, 17))
+        hist = rng.integers(0, 6, Ns + 1)
+        if trial % 4 == 0:
+            hist[rng.integers(0, Ns + 1)] = 0
+        R = int(rng.integers(0, 3 * int(hist.sum()) + 2))
+        for rule in (O.RULE_PRINTED, O.RULE_PROSE):
+            assert O.threshold(hist, Ns, R, rule) == _level_scan(hist, Ns, R, rule), (trial, rule)
 
 
 def test_alg5_candidate_count_bounds():
@@ -404,11 +535,10 @@ def test_query_stage_invariants(tiny_index):
                 sizes = offs[j, 1:] - offs[j, :-1]
                 assert r["retrieved"][j] == sizes[cells].sum() >= A
                 assert sizes[cells[:-1]].sum() < A
-                # closed form of Alg 4 on the dumped distances
+                # the activation walk of Section 4.2 on the dumped distances
                 D1, D2 = r["cdist"][j, 0], r["cdist"][j, 1]
-                c2, _ = O.probe(D1, r["corder"][j, 0], D2, r["corder"][j, 1], sizes, A,
-                                closed_form=True)
-                assert c2.tolist() == cells.tolist()
+                c2, _ = _activation_walk(D1, r["corder"][j, 0], D2, r["corder"][j, 1], sizes, A)
+                assert c2 == cells.tolist()
             # SC recomputed by brute force from the probed cell lists
             want = np.zeros(idx.n, np.int64)
             for j in range(idx.Ns):
