@@ -213,6 +213,36 @@ int tc_search_batched(tc_index *index, const float *queries, int64_t nq, const d
                       const int32_t *k, int32_t k_max, double beta, int64_t *ids, float *dists,
                       void *stream);
 
+/* Size in bytes of the static device array that tc_search_noalloc takes its
+ * scratch from; the library holds one per GPU it runs on (256 MiB). */
+#define TC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/*
+ * tc_search for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Arguments, errors and results as for tc_search.  It calls no allocating
+ * routine.  Every per-batch buffer (transformed queries, probed cells and
+ * their flattened rows, query order, level histograms, packed collision
+ * counts, candidates and their distances) is a view into one static device
+ * array of TC_NOALLOC_SCRATCH_BYTES, which the library looks up on each GPU
+ * when an index is first loaded or built there and holds until the process
+ * ends.  It runs the split count form with the FP32 re-rank and FP32
+ * centroid distances whatever TC_OPT_COUNT_MODE, TC_OPT_PRECISION,
+ * TC_OPT_CDIST_PRECISION, TC_OPT_GRAPH and TC_OPT_PROFILE say (the selection
+ * rule, the tile width and the launch shapes apply), so its results equal
+ * tc_search's with the default options.  Queries run in internal batches of
+ * as many as fit the array, about TC_NOALLOC_SCRATCH_BYTES / (8n + n*b/8 +
+ * 8*Ns*K) with b = 4 bits per count when Ns <= 15, else 8; with n = 1e6 and
+ * Ns = 8 that is 29 queries per batch.  TC_EINVAL, with nothing enqueued,
+ * when one query's scratch exceeds the array (n above about 28 million at
+ * Ns = 8) and for every argument tc_search rejects.  All calls on one GPU
+ * share that GPU's array and find there what the previous call left (each
+ * batch clears what must start at zero before use): calls that overlap on
+ * one GPU, from any index, thread or stream, race and corrupt each other.
+ */
+int tc_search_noalloc(tc_index *index, const float *queries, int64_t nq, int32_t k, double alpha,
+                      double beta, int64_t *ids, float *dists, void *stream);
+
 /*
  * Autotuner.  Times the search of `queries` (device, f32 [nq][d]) with the
  * given k, alpha and beta under candidate launch configurations -- LDS tile

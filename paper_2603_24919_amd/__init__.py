@@ -91,6 +91,7 @@ def load_library():
                                 C.POINTER(i32), C.POINTER(i32)]
     L.tc_set_option.argtypes = [vp, C.c_int, i64]
     L.tc_search.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, vp]
+    L.tc_search_noalloc.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, vp]
     L.tc_search_debug.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, vp, C.POINTER(_StageDump)]
     L.tc_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
     L.tc_profile_reset.argtypes = [vp]
@@ -109,7 +110,8 @@ def load_library():
     L.tc_build_index.argtypes = [vp, i64, i32, i32, i32, i32, i32, vp, vp, i64, C.c_uint64, vp, vp,
                                  C.c_int, C.POINTER(vp), vp]
     L.tc_save_index.argtypes = [vp, C.c_char_p]
-    for f in ("tc_load_index", "tc_index_info", "tc_set_option", "tc_search", "tc_search_debug",
+    for f in ("tc_load_index", "tc_index_info", "tc_set_option", "tc_search", "tc_search_noalloc",
+              "tc_search_debug",
               "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity", "tc_device_errors",
               "tc_search_batched", "tc_autotune", "tc_build_stats", "tc_build_eigen",
               "tc_build_allocate", "tc_build_transform", "tc_build_kmeans", "tc_build_imi",
@@ -294,6 +296,22 @@ def tc_search(index, queries, k: int, alpha: float, beta: float, ids=None, dists
     return tc_search_debug(index, queries, k, alpha, beta, None, ids, dists, stream)
 
 
+def tc_search_noalloc(index, queries, k: int, alpha: float, beta: float, ids, dists,
+                      stream=None) -> None:
+    """Enqueue the search with no device allocation (tc_search_noalloc) into
+    the caller's ``ids`` (CUDA int64 [nq, k]) and ``dists`` (float32)."""
+    import torch
+    nq = int(queries.shape[0])
+    dev = queries.device
+    if queries.dtype != torch.float32 or not queries.is_cuda or not queries.is_contiguous():
+        raise ValueError("queries must be a contiguous float32 CUDA tensor")
+    _check_tensor(ids, torch.int64, (nq, k), dev, "ids")
+    _check_tensor(dists, torch.float32, (nq, k), dev, "dists")
+    _check(load_library().tc_search_noalloc(index, queries.data_ptr(), nq, int(k), float(alpha),
+                                            float(beta), ids.data_ptr(), dists.data_ptr(),
+                                            _stream_handle(stream, dev)))
+
+
 def tc_search_debug(index, queries, k: int, alpha: float, beta: float, dump=None, ids=None,
                     dists=None, stream=None):
     """tc_search plus per-stage outputs into the CUDA tensors of the ``dump``
@@ -423,6 +441,9 @@ class Index:
 
     def search(self, queries, k: int, alpha: float, beta: float, **kw):
         return tc_search(self.handle, queries, k, alpha, beta, **kw)
+
+    def search_noalloc(self, queries, k: int, alpha: float, beta: float, ids, dists, **kw):
+        return tc_search_noalloc(self.handle, queries, k, alpha, beta, ids, dists, **kw)
 
     def search_batched(self, queries, alpha, k, k_max: int, beta: float, **kw):
         return tc_search_batched(self.handle, queries, alpha, k, k_max, beta, **kw)

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -39,6 +40,36 @@ int hip_fail(hipError_t e, const char *what) {
         hipError_t e_ = (call);                    \
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
+
+}  // namespace
+
+// Scratch of tc_search_noalloc: a file-scope device array, one copy per GPU,
+// held from the library's load to the end of the process.  Its name is not a
+// device address in host code: each device's copy is looked up once with
+// hipGetSymbolAddress (noalloc_setup) and only that pointer is used.
+static __device__ __align__(256) unsigned char scratch[TC_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_ptr;  // device ordinal -> its copy of scratch
+
+// Looks up the current device's copy of the scratch array (once per device).
+int noalloc_setup(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return TC_OK;
+    void *ptr = nullptr;
+    TC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "looking up the static scratch array");
+    if (!ptr) return fail(TC_EDEVICE, "the static scratch array has no device address");
+    g_scratch_ptr[device] = static_cast<unsigned char *>(ptr);
+    return TC_OK;
+}
+
+unsigned char *noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
 
 // FNV-1a, 64-bit (offset basis 14695981039346656037, prime 1099511628211).
 struct Fnv {
@@ -549,6 +580,8 @@ int install(tc_index *x, int device, const std::vector<float> &mean, const std::
     if (device < 0 || device >= ndev) return fail(TC_EINVAL, "no such HIP device");
     x->device = device;
     DeviceGuard g(device);
+    int rc = noalloc_setup(device);
+    if (rc) return rc;
     hipDeviceProp_t prop;
     TC_HIP(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
     x->max_lds = static_cast<int>(prop.sharedMemPerBlock);
@@ -557,7 +590,6 @@ int install(tc_index *x, int device, const std::vector<float> &mean, const std::
     TC_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device),
            "hipDeviceGetAttribute");
     x->coop = coop != 0;
-    int rc;
     if ((rc = upload(&x->mean, mean, "mean"))) return rc;
     x->mean_host = mean;
     if ((rc = upload(&x->B, B, "transform"))) return rc;
@@ -684,12 +716,82 @@ struct Call {
     int64_t *ids = nullptr;
     float *dists = nullptr;
     const tc_stage_dump *dump = nullptr;
+    // tc_search_noalloc: the split count form, FP32 re-rank and centroid
+    // distances, no timing events, whatever the index's options; scratch
+    // from `scratch` instead of the index's buffers
+    bool plain = false;
+    const struct Scratch *scratch = nullptr;
 };
+
+// Per-batch scratch of a call, for Qb queries: the index's own buffers, or
+// views into the library's static device array (tc_search_noalloc, which
+// sets only what the plain path uses and leaves the rest null).
+struct Scratch {
+    int64_t Qb = 0;
+    float *qt = nullptr;
+    int32_t *cells = nullptr, *ncells = nullptr;
+    int64_t *retrieved = nullptr;
+    uint32_t *hist = nullptr, *cand_count = nullptr;
+    int32_t *cand = nullptr;
+    float *cand_dist = nullptr;
+    uint32_t *sc = nullptr;
+    int32_t *perm = nullptr, *flat = nullptr;
+    uint32_t *ftot = nullptr;
+    // used by the other forms only
+    uint32_t *lvl = nullptr, *tcount = nullptr, *toff = nullptr, *tlev = nullptr, *arrive = nullptr;
+    int64_t *Aq = nullptr;
+    int32_t *kq = nullptr;
+    float *lb = nullptr;
+    uint32_t *rk_count = nullptr, *exact = nullptr, *qinfo = nullptr;
+    int64_t *tau_ids = nullptr;
+    float *tau_d = nullptr, *qn = nullptr, *qsc = nullptr, *cd = nullptr;
+};
+
+Scratch own_scratch(const tc_index *x) {
+    Scratch S;
+    S.Qb = x->Qb;
+    S.qt = x->qt;
+    S.cells = x->cells;
+    S.ncells = x->ncells;
+    S.retrieved = x->retrieved;
+    S.hist = x->hist;
+    S.cand_count = x->cand_count;
+    S.cand = x->cand;
+    S.cand_dist = x->cand_dist;
+    S.sc = x->sc;
+    S.perm = x->perm;
+    S.flat = x->flat;
+    S.ftot = x->ftot;
+    S.lvl = x->lvl;
+    S.tcount = x->tcount;
+    S.toff = x->toff;
+    S.tlev = x->tlev;
+    S.arrive = x->arrive;
+    S.Aq = x->Aq;
+    S.kq = x->kq;
+    S.lb = x->lb;
+    S.rk_count = x->rk_count;
+    S.exact = x->exact;
+    S.qinfo = x->qinfo;
+    S.tau_ids = x->tau_ids;
+    S.tau_d = x->tau_d;
+    S.qn = x->qn;
+    S.qsc = x->qsc;
+    S.cd = x->cd;
+    return S;
+}
 
 // The launch sequence of a call, batch after batch, on stream st.  Nothing
 // here waits on the host, so it can also be captured into a graph.
 int enqueue(tc_index *x, const Call &c, hipStream_t st) {
     const tc_stage_dump *dump = c.dump;
+    const Scratch S = c.scratch ? *c.scratch : own_scratch(x);
+    const int precision = c.plain ? int(TC_FP32) : x->precision;
+    const int cdist = c.plain ? int(TC_CDIST_FP32) : x->cdist;
+    const int count_mode = c.plain ? int(TC_COUNT_SPLIT) : x->count_mode;
+    auto rec = [&](int kern, hipStream_t s_, bool begin) {
+        if (!c.plain) record(x, kern, s_, begin);
+    };
     // budgets in IEEE double (Alg 4 stop test, Alg 5 budget)
     double a = std::ceil(c.alpha * double(x->n));
     if (a < 1.0) a = 1.0;
@@ -706,170 +808,170 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
     // lock-step rounds (10.2 vs 17.3 ms per 10k-query step at n = 1M)
     // the fixed-budget rule needs the packed counts of the split form
     const bool fixed = x->rule == TC_RULE_FIXED;
-    const bool fused = x->count_mode == TC_COUNT_FUSED && !fixed;
-    const bool list = x->count_mode == TC_COUNT_LIST && !fixed;
-    for (int64_t b0 = 0; b0 < c.nq; b0 += x->Qb) {
-        const int nb = static_cast<int>(std::min<int64_t>(x->Qb, c.nq - b0));
+    const bool fused = count_mode == TC_COUNT_FUSED && !fixed;
+    const bool list = count_mode == TC_COUNT_LIST && !fixed;
+    for (int64_t b0 = 0; b0 < c.nq; b0 += S.Qb) {
+        const int nb = static_cast<int>(std::min<int64_t>(S.Qb, c.nq - b0));
         const float *Qb = c.Q + b0 * x->d;
         int64_t *ids = c.ids + b0 * k_max;
         float *dists = c.dists + b0 * k_max;
         const int64_t *Aq = nullptr;
         const int32_t *kq = nullptr;
         if (c.alpha_dev) {
-            TC_HIP(taco::launch_budgets(c.alpha_dev + b0, c.kq_dev + b0, nb, x->n, k_max, x->Aq, x->kq,
+            TC_HIP(taco::launch_budgets(c.alpha_dev + b0, c.kq_dev + b0, nb, x->n, k_max, S.Aq, S.kq,
                                         x->err, st),
                    "budget kernel");
-            Aq = x->Aq;
-            kq = x->kq;
+            Aq = S.Aq;
+            kq = S.kq;
         }
-        TC_HIP(taco::launch_fill_u32(x->hist, int64_t(nb) * (x->Ns + 1), 0u, st), "clearing histograms");
-        TC_HIP(taco::launch_fill_u32(x->cand_count, x->Qb + 2, 0u, st), "clearing candidate counts");
+        TC_HIP(taco::launch_fill_u32(S.hist, int64_t(nb) * (x->Ns + 1), 0u, st), "clearing histograms");
+        TC_HIP(taco::launch_fill_u32(S.cand_count, S.Qb + 2, 0u, st), "clearing candidate counts");
 
-        record(x, K_TRANSFORM, st, true);
-        TC_HIP(taco::launch_transform(Qb, nb, x->d, x->mean, x->B, x->M, x->qt, st), "transform kernel");
-        record(x, K_TRANSFORM, st, false);
+        rec(K_TRANSFORM, st, true);
+        TC_HIP(taco::launch_transform(Qb, nb, x->d, x->mean, x->B, x->M, S.qt, st), "transform kernel");
+        rec(K_TRANSFORM, st, false);
 
         float *dcd = dump && dump->cdist ? dump->cdist + b0 * x->Ns * 2 * x->l : nullptr;
         int32_t *dco = dump && dump->corder ? dump->corder + b0 * x->Ns * 2 * x->l : nullptr;
         const float *pre = nullptr;
-        if (x->cdist != TC_CDIST_FP32) {
-            record(x, K_CDIST, st, true);
-            TC_HIP(taco::launch_cdist_mfma(x->qt, nb, x->M, x->Ns, x->s, x->h1, x->h2, x->l, x->Kp,
-                                           x->cdist == TC_CDIST_FP8, x->cT, x->cnorm, x->csc, x->qn,
-                                           x->qsc, x->cd, st),
+        if (cdist != TC_CDIST_FP32) {
+            rec(K_CDIST, st, true);
+            TC_HIP(taco::launch_cdist_mfma(S.qt, nb, x->M, x->Ns, x->s, x->h1, x->h2, x->l, x->Kp,
+                                           cdist == TC_CDIST_FP8, x->cT, x->cnorm, x->csc, S.qn,
+                                           S.qsc, S.cd, st),
                    "centroid distance kernel");
-            record(x, K_CDIST, st, false);
-            pre = x->cd;
+            rec(K_CDIST, st, false);
+            pre = S.cd;
         }
-        record(x, K_PROBE, st, true);
-        TC_HIP(taco::launch_probe(x->qt, nb, x->Ns, x->M, x->s, x->h1, x->h2, x->l, x->K, x->C1,
-                                  x->C2, x->offs, A, Aq, x->cells, x->ncells, x->retrieved, dcd, dco,
+        rec(K_PROBE, st, true);
+        TC_HIP(taco::launch_probe(S.qt, nb, x->Ns, x->M, x->s, x->h1, x->h2, x->l, x->K, x->C1,
+                                  x->C2, x->offs, A, Aq, S.cells, S.ncells, S.retrieved, dcd, dco,
                                   pre, x->probe_qpw, st),
                "probe kernel");
-        record(x, K_PROBE, st, false);
+        rec(K_PROBE, st, false);
 
         // the order in which the count and re-rank take the queries (any order
         // gives the same results)
         const bool order = x->K <= 4096;
-        if (order) TC_HIP(taco::launch_query_order(x->cells, nb, x->Ns, x->K, x->perm, st), "query order kernel");
-        TC_HIP(taco::launch_flatten_cells(x->cells, x->ncells, nb, x->Ns, x->K, x->flat, x->ftot, st),
+        if (order) TC_HIP(taco::launch_query_order(S.cells, nb, x->Ns, x->K, S.perm, st), "query order kernel");
+        TC_HIP(taco::launch_flatten_cells(S.cells, S.ncells, nb, x->Ns, x->K, S.flat, S.ftot, st),
                "probed cell list kernel");
-        taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids_enc, x->off2d, x->flat,
-                             x->ftot, order ? x->perm : nullptr};
-        taco::SelectLaunch sl{x->hist, R, x->rule, cap, x->cand, x->cand_count,
+        taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids_enc, x->off2d, S.flat,
+                             S.ftot, order ? S.perm : nullptr};
+        taco::SelectLaunch sl{S.hist, R, x->rule, cap, S.cand, S.cand_count,
                               dump && dump->sc ? dump->sc + b0 * x->n : nullptr,
                               dump && dump->last ? dump->last + b0 : nullptr,
                               dump && dump->hist ? dump->hist + b0 * (x->Ns + 1) : nullptr};
         if (fused) {
-            TC_HIP(taco::launch_fill_u32(x->arrive, nb, 0u, st), "clearing tile arrivals");
-            record(x, K_FUSED, st, true);
-            TC_HIP(taco::launch_count_select(cl, sl, std::min(x->fused_groups, nb), x->arrive, x->err,
+            TC_HIP(taco::launch_fill_u32(S.arrive, nb, 0u, st), "clearing tile arrivals");
+            rec(K_FUSED, st, true);
+            TC_HIP(taco::launch_count_select(cl, sl, std::min(x->fused_groups, nb), S.arrive, x->err,
                                              1u << 24, st),
                    "fused count/select kernel");
-            record(x, K_FUSED, st, false);
+            rec(K_FUSED, st, false);
         } else if (list) {
-            uint32_t *redo = x->cand_count + x->Qb;
+            uint32_t *redo = S.cand_count + S.Qb;
             const bool dsc = dump && dump->sc;
             const bool dh = dump && (dump->hist || dump->last);
             // the lists sit in the distance slots, free until the re-rank
-            const taco::ListLaunch ll{x->list_level, x->lvl, cap, reinterpret_cast<uint32_t *>(x->cand_dist),
-                                      x->cand, x->cand_count, x->tcount, redo, 64, R, x->rule, dh,
-                                      sl.dump_last, sl.dump_hist, x->toff, x->tlev};
-            record(x, K_COUNT, st, true);
-            TC_HIP(taco::launch_count(cl, x->hist, dsc ? x->sc : nullptr, 1, &ll, st), "count kernel (list)");
-            record(x, K_COUNT, st, false);
-            record(x, K_SELECT, st, true);
-            TC_HIP(taco::launch_list_select(cl, ll, x->hist, st), "list select kernel");
-            TC_HIP(taco::launch_count(cl, x->hist, x->sc, 2, &ll, st), "recount kernel");
+            const taco::ListLaunch ll{x->list_level, S.lvl, cap, reinterpret_cast<uint32_t *>(S.cand_dist),
+                                      S.cand, S.cand_count, S.tcount, redo, 64, R, x->rule, dh,
+                                      sl.dump_last, sl.dump_hist, S.toff, S.tlev};
+            rec(K_COUNT, st, true);
+            TC_HIP(taco::launch_count(cl, S.hist, dsc ? S.sc : nullptr, 1, &ll, st), "count kernel (list)");
+            rec(K_COUNT, st, false);
+            rec(K_SELECT, st, true);
+            TC_HIP(taco::launch_list_select(cl, ll, S.hist, st), "list select kernel");
+            TC_HIP(taco::launch_count(cl, S.hist, S.sc, 2, &ll, st), "recount kernel");
             taco::SelectLaunch sr = sl;
             sr.dump_sc = nullptr;
             sr.dump_last = nullptr;
             sr.dump_hist = nullptr;
             sr.redo = redo;
             sr.redo_groups = 128;
-            TC_HIP(taco::launch_select(cl, sr, x->sc, st), "select kernel (queued)");
-            record(x, K_SELECT, st, false);
+            TC_HIP(taco::launch_select(cl, sr, S.sc, st), "select kernel (queued)");
+            rec(K_SELECT, st, false);
             if (dsc)
-                TC_HIP(taco::launch_unpack_counts(x->sc, nb, x->T, x->W, x->bits, x->n, dump->sc + b0 * x->n, st),
+                TC_HIP(taco::launch_unpack_counts(S.sc, nb, x->T, x->W, x->bits, x->n, dump->sc + b0 * x->n, st),
                        "dump sc");
         } else {
-            record(x, K_COUNT, st, true);
-            TC_HIP(taco::launch_count(cl, x->hist, x->sc, 0, nullptr, st), "count kernel");
-            record(x, K_COUNT, st, false);
-            record(x, K_SELECT, st, true);
-            TC_HIP(taco::launch_select(cl, sl, x->sc, st), "select kernel");
-            if (fixed) TC_HIP(taco::launch_select_level(cl, sl, x->sc, st), "boundary-level select kernel");
-            record(x, K_SELECT, st, false);
+            rec(K_COUNT, st, true);
+            TC_HIP(taco::launch_count(cl, S.hist, S.sc, 0, nullptr, st), "count kernel");
+            rec(K_COUNT, st, false);
+            rec(K_SELECT, st, true);
+            TC_HIP(taco::launch_select(cl, sl, S.sc, st), "select kernel");
+            if (fixed) TC_HIP(taco::launch_select_level(cl, sl, S.sc, st), "boundary-level select kernel");
+            rec(K_SELECT, st, false);
         }
 
-        if (x->precision != TC_FP32) {
+        if (precision != TC_FP32) {
             // bounds from the BF16 or 8-bit rows, the k-th smallest upper bound,
             // then the FP32 path's arithmetic on every row that can still make the top k
-            record(x, K_RERANK, st, true);
-            if (x->precision == TC_BF16)
-                TC_HIP(taco::launch_rerank16(Qb, nb, x->d, x->mu, x->base16, x->rowerr, x->cand,
-                                             x->cand_count, cap, x->cand_dist, x->lb, rr_blocks, st),
+            rec(K_RERANK, st, true);
+            if (precision == TC_BF16)
+                TC_HIP(taco::launch_rerank16(Qb, nb, x->d, x->mu, x->base16, x->rowerr, S.cand,
+                                             S.cand_count, cap, S.cand_dist, S.lb, rr_blocks, st),
                        "BF16 rerank kernel");
             else {
                 // exact form: plain rows, 16 | d <= 256
                 const bool ex = x->u8_plain && x->d % 16 == 0 && x->d <= 256;
-                if (ex) TC_HIP(taco::launch_qbytes(Qb, nb, x->d, x->qinfo, st), "query bytes kernel");
-                TC_HIP(taco::launch_rerank8(Qb, nb, x->d, x->base8, x->rmeta, x->u8_plain, x->cand,
-                                            x->cand_count, cap, x->cand_dist, x->lb, x->exact,
-                                            ex ? x->qinfo : nullptr, list ? x->toff : nullptr, x->T,
-                                            order ? x->perm : nullptr, rr_blocks, st),
+                if (ex) TC_HIP(taco::launch_qbytes(Qb, nb, x->d, S.qinfo, st), "query bytes kernel");
+                TC_HIP(taco::launch_rerank8(Qb, nb, x->d, x->base8, x->rmeta, x->u8_plain, S.cand,
+                                            S.cand_count, cap, S.cand_dist, S.lb, S.exact,
+                                            ex ? S.qinfo : nullptr, list ? S.toff : nullptr, x->T,
+                                            order ? S.perm : nullptr, rr_blocks, st),
                        "8-bit rerank kernel");
             }
-            record(x, K_RERANK, st, false);
-            record(x, K_TOPK, st, true);
-            TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, kq, k_max,
-                                     x->tau_ids, x->tau_d, st),
+            rec(K_RERANK, st, false);
+            rec(K_TOPK, st, true);
+            TC_HIP(taco::launch_topk(S.cand, S.cand_dist, S.cand_count, cap, nb, k, kq, k_max,
+                                     S.tau_ids, S.tau_d, st),
                    "bound top-k kernel");
-            record(x, K_TOPK, st, false);
-            record(x, K_RECHECK, st, true);
-            TC_HIP(taco::launch_recheck_topk(Qb, nb, x->d, x->base, x->cand, x->cand_count, x->lb, cap,
-                                             x->tau_d, k, kq, k_max, reinterpret_cast<int32_t *>(x->lb),
-                                             x->cand_dist, x->rk_count,
-                                             ids, dists, x->precision == TC_U8 ? x->exact : nullptr, x->tau_ids,
+            rec(K_TOPK, st, false);
+            rec(K_RECHECK, st, true);
+            TC_HIP(taco::launch_recheck_topk(Qb, nb, x->d, x->base, S.cand, S.cand_count, S.lb, cap,
+                                             S.tau_d, k, kq, k_max, reinterpret_cast<int32_t *>(S.lb),
+                                             S.cand_dist, S.rk_count,
+                                             ids, dists, precision == TC_U8 ? S.exact : nullptr, S.tau_ids,
                                              st),
                    "re-check and top-k kernel");
-            record(x, K_RECHECK, st, false);
+            rec(K_RECHECK, st, false);
             if (dump && dump->nrecheck)
-                TC_HIP(taco::launch_u32_to_i64(x->rk_count, dump->nrecheck + b0, nb, st), "dump nrecheck");
+                TC_HIP(taco::launch_u32_to_i64(S.rk_count, dump->nrecheck + b0, nb, st), "dump nrecheck");
         } else {
-            record(x, K_RERANK, st, true);
-            TC_HIP(taco::launch_rerank(Qb, nb, x->d, x->base, x->cand, x->cand_count, cap,
-                                       x->cand_dist, rr_blocks, st),
+            rec(K_RERANK, st, true);
+            TC_HIP(taco::launch_rerank(Qb, nb, x->d, x->base, S.cand, S.cand_count, cap,
+                                       S.cand_dist, rr_blocks, st),
                    "rerank kernel");
-            record(x, K_RERANK, st, false);
+            rec(K_RERANK, st, false);
 
-            record(x, K_TOPK, st, true);
-            TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, kq, k_max, ids,
+            rec(K_TOPK, st, true);
+            TC_HIP(taco::launch_topk(S.cand, S.cand_dist, S.cand_count, cap, nb, k, kq, k_max, ids,
                                      dists, st),
                    "top-k kernel");
-            record(x, K_TOPK, st, false);
+            rec(K_TOPK, st, false);
         }
 
         if (dump) {
             const hipMemcpyKind dd = hipMemcpyDeviceToDevice;
             if (dump->qt)
-                TC_HIP(hipMemcpyAsync(dump->qt + b0 * x->M, x->qt, sizeof(float) * nb * x->M, dd, st), "dump qt");
+                TC_HIP(hipMemcpyAsync(dump->qt + b0 * x->M, S.qt, sizeof(float) * nb * x->M, dd, st), "dump qt");
             if (dump->cells)
-                TC_HIP(hipMemcpyAsync(dump->cells + b0 * x->Ns * x->K, x->cells,
+                TC_HIP(hipMemcpyAsync(dump->cells + b0 * x->Ns * x->K, S.cells,
                                       sizeof(int32_t) * size_t(nb) * x->Ns * x->K, dd, st), "dump cells");
             if (dump->ncells)
-                TC_HIP(hipMemcpyAsync(dump->ncells + b0 * x->Ns, x->ncells, sizeof(int32_t) * nb * x->Ns, dd, st),
+                TC_HIP(hipMemcpyAsync(dump->ncells + b0 * x->Ns, S.ncells, sizeof(int32_t) * nb * x->Ns, dd, st),
                        "dump ncells");
             if (dump->retrieved)
-                TC_HIP(hipMemcpyAsync(dump->retrieved + b0 * x->Ns, x->retrieved,
+                TC_HIP(hipMemcpyAsync(dump->retrieved + b0 * x->Ns, S.retrieved,
                                       sizeof(int64_t) * nb * x->Ns, dd, st), "dump retrieved");
             if (dump->ncand)
-                TC_HIP(taco::launch_u32_to_i64(x->cand_count, dump->ncand + b0, nb, st), "dump ncand");
+                TC_HIP(taco::launch_u32_to_i64(S.cand_count, dump->ncand + b0, nb, st), "dump ncand");
             if (dump->cand)
-                TC_HIP(hipMemcpyAsync(dump->cand + b0 * x->n, x->cand, sizeof(int32_t) * size_t(nb) * x->n, dd, st),
+                TC_HIP(hipMemcpyAsync(dump->cand + b0 * x->n, S.cand, sizeof(int32_t) * size_t(nb) * x->n, dd, st),
                        "dump cand");
-            if (dump->cand_dist && x->precision == TC_FP32)
-                TC_HIP(hipMemcpyAsync(dump->cand_dist + b0 * x->n, x->cand_dist,
+            if (dump->cand_dist && precision == TC_FP32)
+                TC_HIP(hipMemcpyAsync(dump->cand_dist + b0 * x->n, S.cand_dist,
                                       sizeof(float) * size_t(nb) * x->n, dd, st), "dump cand_dist");
         }
     }
@@ -1091,6 +1193,70 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
 int tc_search(tc_index *x, const float *queries, int64_t nq, int32_t k, double alpha, double beta,
               int64_t *ids, float *dists, void *stream) {
     return search(x, queries, nq, k, alpha, beta, ids, dists, stream, nullptr);
+}
+
+int tc_search_noalloc(tc_index *x, const float *queries, int64_t nq, int32_t k, double alpha, double beta,
+                      int64_t *ids, float *dists, void *stream) {
+    if (!x) return fail(TC_EINVAL, "index is NULL");
+    if (nq < 0) return fail(TC_EINVAL, "nq < 0");
+    if (nq == 0) return TC_OK;
+    if (!queries || !ids || !dists) return fail(TC_EINVAL, "queries, ids and dists must be non-NULL");
+    if (k < 1 || int64_t(k) > x->n || k > 1024) return fail(TC_EINVAL, "k must be in [1, min(n, 1024)]");
+    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(TC_EINVAL, "alpha must be in (0, 1]");
+    if (!(beta >= 0.0 && beta <= 1.0)) return fail(TC_EINVAL, "beta must be in [0, 1]");
+    unsigned char *base = noalloc_scratch(x->device);
+    if (!base) return fail(TC_EDEVICE, "the static scratch array was not set up on this device");
+    // per-query bytes of every buffer the plain path touches, each rounded up
+    // to the array's 256-byte alignment once per buffer
+    const int64_t NsK = int64_t(x->Ns) * x->K;
+    const int64_t packed = int64_t(x->T) * (int64_t(x->W) * x->bits / 32);  // u32 words
+    auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
+    auto need = [&](int64_t qb) {
+        return up(4 * qb * x->M) + 2 * up(4 * qb * NsK) + up(4 * qb * x->Ns) + up(8 * qb * x->Ns) +
+               up(4 * qb * (x->Ns + 1)) + up(4 * (2 * qb + 2)) + up(4 * qb) + up(4 * qb) +
+               2 * up(4 * qb * x->n) + up(4 * qb * packed);
+    };
+    const int64_t cap = static_cast<int64_t>(TC_NOALLOC_SCRATCH_BYTES);
+    if (need(1) > cap)
+        return fail(TC_EINVAL, "tc_search_noalloc: one query needs " + std::to_string(need(1)) +
+                                   " bytes of scratch, more than the " + std::to_string(cap) +
+                                   "-byte static array (the index has too many points); use tc_search");
+    int64_t qb = std::min<int64_t>(nq, cap / need(1));
+    while (qb > 1 && need(qb) > cap) qb--;
+    Scratch S;
+    S.Qb = qb;
+    int64_t at = 0;
+    auto take = [&](int64_t bytes) {
+        unsigned char *p = base + at;
+        at += up(bytes);
+        return p;
+    };
+    S.qt = reinterpret_cast<float *>(take(4 * qb * x->M));
+    S.cells = reinterpret_cast<int32_t *>(take(4 * qb * NsK));
+    S.flat = reinterpret_cast<int32_t *>(take(4 * qb * NsK));
+    S.ncells = reinterpret_cast<int32_t *>(take(4 * qb * x->Ns));
+    S.retrieved = reinterpret_cast<int64_t *>(take(8 * qb * x->Ns));
+    S.hist = reinterpret_cast<uint32_t *>(take(4 * qb * (x->Ns + 1)));
+    S.cand_count = reinterpret_cast<uint32_t *>(take(4 * (2 * qb + 2)));
+    S.perm = reinterpret_cast<int32_t *>(take(4 * qb));
+    S.ftot = reinterpret_cast<uint32_t *>(take(4 * qb));
+    S.cand = reinterpret_cast<int32_t *>(take(4 * qb * x->n));
+    S.cand_dist = reinterpret_cast<float *>(take(4 * qb * x->n));
+    S.sc = reinterpret_cast<uint32_t *>(take(4 * qb * packed));
+    if (at > cap) return fail(TC_EINVAL, "tc_search_noalloc: scratch plan exceeds the static array");
+    Call c;
+    c.Q = queries;
+    c.nq = nq;
+    c.k = k;
+    c.k_max = k;
+    c.alpha = alpha;
+    c.beta = beta;
+    c.ids = ids;
+    c.dists = dists;
+    c.plain = true;
+    c.scratch = &S;
+    DeviceGuard g(x->device);
+    return enqueue(x, c, static_cast<hipStream_t>(stream));
 }
 
 int tc_search_batched(tc_index *x, const float *queries, int64_t nq, const double *alpha,
