@@ -50,19 +50,26 @@ enum tc_status {
     TC_EDEVICE = -5  /* HIP runtime error                                     */
 };
 
-/* Readings of Alg 5's stopping test (Section 4.3).  Scanning SC levels from
- * Ns down with a running total `cum` that includes the current level's count
- * c_j, a level "passes" and lowers last_collision by one when
- *   TC_RULE_PRINTED: c_j <= beta*n - cum   (as the algorithm prints it), or
- *   TC_RULE_PROSE:   cum <= beta*n         (as the text describes it);
- * the first failing level ends the scan.  Candidates are the points whose
- * SC-score is >= last_collision (every point when it drops to -1).
+/* Readings of Alg 5's stopping test (Section 4.3).  With S(v) the number of
+ * points whose SC-score is at least v, the threshold last_collision is the
+ * highest level v at which the re-rank budget floor(beta*n) is exceeded
+ * (-1 when no level exceeds it), where "exceeded" is
+ *   TC_RULE_PRINTED: c_v + S(v) > beta*n   (the test as the algorithm prints
+ *                    it, c_v the points at level v), or
+ *   TC_RULE_PROSE:   S(v) > beta*n         (as the text describes it).
+ * Candidates are the points whose SC-score is >= last_collision (every point
+ * when it is -1).
  *   TC_RULE_FIXED:   not Alg 5 but the fixed budget it is contrasted with in
  *                    Section 4.3 (SuCo's selection): exactly the floor(beta*n)
- *                    points of highest SC-score, ties by the lower id.  The
- *                    reported threshold is the lowest level taken completely.
- *                    Searches with this rule use the split count form
- *                    (TC_COUNT_SPLIT) whatever TC_OPT_COUNT_MODE says. */
+ *                    points of highest SC-score, ties by the lower id.  With
+ *                    L the boundary level (the highest level with S(L) >=
+ *                    floor(beta*n)), the candidates are every point with
+ *                    SC > L and the first floor(beta*n) - S(L + 1) points of
+ *                    level L in id order, and the reported threshold is
+ *                    L + 1 (Ns + 1 when beta*n < 1), whether or not level L
+ *                    is taken whole.  Searches with this rule use the split
+ *                    count form (TC_COUNT_SPLIT) whatever TC_OPT_COUNT_MODE
+ *                    says. */
 enum tc_select_rule { TC_RULE_PRINTED = 0, TC_RULE_PROSE = 1, TC_RULE_FIXED = 2 };
 
 /* Options for tc_set_option. */

@@ -140,14 +140,17 @@ def _draw_rows(rng, recipe: str, p, m: int, d: int, work=None) -> np.ndarray:
     """``m`` rows of a recipe from one stream.  ``work``: optional pair of
     float64 ``(>= m, d)`` scratch arrays, reused across chunks (the values
     are the same with or without them)."""
-    if recipe == "aniso":
-        z = rng.standard_normal((m, d)) * p["sqrt_lam"][None, :]
-        x = z @ p["rot"].T + p["offset"][None, :]
-        return np.maximum(x, 0.0).astype(np.float32)
-    comp = rng.choice(len(p["weights"]), size=m, p=p["weights"])
     if work is None:
         work = (np.empty((m, d)), np.empty((m, d)))
     x, g = work[0][:m], work[1][:m]
+    if recipe == "aniso":
+        rng.standard_normal(out=g)
+        g *= p["sqrt_lam"][None, :]
+        np.matmul(g, p["rot"].T, out=x)          # rotated, then offset and clipped
+        x += p["offset"][None, :]
+        np.maximum(x, 0.0, out=x)
+        return x.astype(np.float32)
+    comp = rng.choice(len(p["weights"]), size=m, p=p["weights"])
     np.take(p["means"], comp, axis=0, out=x)
     rng.standard_normal(out=g)
     g *= p["sigma"][comp][:, None]
@@ -173,9 +176,6 @@ def _draw(seed: int, recipe: str, p, m: int, d: int) -> np.ndarray:
     def job(ci):
         lo, hi = ci * CHUNK, min(m, (ci + 1) * CHUNK)
         if lo >= hi:
-            return
-        if recipe == "aniso":
-            out[lo:hi] = _draw_rows(streams[ci], recipe, p, hi - lo, d)
             return
         if getattr(local, "work", None) is None:
             local.work = (np.empty((CHUNK, d)), np.empty((CHUNK, d)))
