@@ -8,7 +8,8 @@ inputs come from ``synthdata`` (random draws only).
 What lives where:
   * ``taco_oracle.c`` (loaded here through ctypes): the FP32 canonical
     transform and half distances, k-means (Alg 3's clustering step), the
-    index file writer/reader, Scalable Dynamic Activation (Alg 4) as the
+    index file writer/reader, SC-Linear (the index-free baseline of Section
+    2.3), Scalable Dynamic Activation (Alg 4) as the
     cell order it produces, Query-aware Candidates Selection (Alg 5) as the
     highest level that exceeds the re-rank budget, the k-ANNS query
     (Alg 6), and FP64 brute-force k-NN (Definition 2).
@@ -101,6 +102,12 @@ def lib():
         L.orc_max_threads.restype = C.c_int
         L.orc_bruteforce.argtypes = [_f32p, C.c_int64, C.c_int, _f32p, C.c_int64, C.c_int,
                                      _i64p, _f64p]
+        L.orc_sclinear.argtypes = [C.c_void_p, _f32p, _f32p, C.c_double, C.c_double, C.c_int, _i64p,
+                                   _f32p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]
+        L.orc_sclinear.restype = C.c_int
+        L.orc_sclinear_batch.argtypes = [C.c_void_p, _f32p, _f32p, C.c_int64, C.c_double, C.c_double,
+                                         C.c_int, C.c_int, _i64p, C.c_void_p]
+        L.orc_sclinear_batch.restype = C.c_int
         _lib_handle = L
     return _lib_handle
 
@@ -431,6 +438,37 @@ class OracleIndex:
             out["cells"] = [out["cells"][j, :out["ncells"][j]].copy() for j in range(self.Ns)]
         return out
 
+    def transformed_base(self) -> np.ndarray:
+        """Every base row transformed with the canonical chain (n x M)."""
+        return transform(self.base(), self.mean(), self.B())
+
+    def sclinear(self, T: np.ndarray, q: np.ndarray, alpha: float, beta: float, k: int):
+        """SC-Linear on one query (see orc_sclinear); ``T`` from
+        transformed_base().  Returns dict(ids, d32, sc, cand)."""
+        q = np.ascontiguousarray(q, np.float32).reshape(self.d)
+        ids = np.empty(k, np.int64)
+        d32 = np.empty(k, np.float32)
+        sc = np.empty(self.n, np.uint8)
+        cand = np.empty(self.n, np.int32)
+        nc = C.c_int64(0)
+        rc = lib().orc_sclinear(self._h, np.ascontiguousarray(T, np.float32), q, float(alpha), float(beta),
+                                int(k), ids, d32, sc.ctypes.data, cand.ctypes.data, C.byref(nc))
+        if rc != 0:
+            raise ValueError(f"orc_sclinear rejected its arguments ({rc})")
+        return dict(ids=ids, d32=d32, sc=sc, cand=cand[:nc.value].copy())
+
+    def sclinear_batch(self, T: np.ndarray, Q: np.ndarray, alpha: float, beta: float, k: int,
+                       nthreads: int = 0):
+        """SC-Linear on many queries (parallel over queries): ids (nq, k), d32."""
+        Q = np.ascontiguousarray(Q, np.float32).reshape(-1, self.d)
+        ids = np.empty((Q.shape[0], k), np.int64)
+        d32 = np.empty((Q.shape[0], k), np.float32)
+        rc = lib().orc_sclinear_batch(self._h, np.ascontiguousarray(T, np.float32), Q, Q.shape[0],
+                                      float(alpha), float(beta), int(k), int(nthreads), ids, d32.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"orc_sclinear_batch rejected its arguments ({rc})")
+        return ids, d32
+
     def query_batch(self, Q: np.ndarray, alpha, beta: float, k: int, rule: int = RULE_PRINTED,
                     nthreads: int = 0, with_dists: bool = False):
         """Alg 6 on many queries (parallel over queries).  ``alpha`` is a
@@ -452,6 +490,19 @@ class OracleIndex:
         if rc != 0:
             raise ValueError(f"orc_query_batch rejected its arguments ({rc})")
         return (ids, d32, d64) if with_dists else ids
+
+
+def write_index(path: str, mean32, B32, C1, C2, offsets, ids, base, s: int, l: int, seed: int = 0):
+    """Write an index file from its parts (the layout the builder writes)."""
+    base = np.ascontiguousarray(base, np.float32)
+    n, d = base.shape
+    Ns = offsets.shape[0]
+    rc = lib().orc_write_index(path.encode(), n, d, Ns, s, l, seed, np.ascontiguousarray(mean32, np.float32),
+                               np.ascontiguousarray(B32, np.float32), np.ascontiguousarray(C1, np.float32),
+                               np.ascontiguousarray(C2, np.float32), np.ascontiguousarray(offsets, np.uint64),
+                               np.ascontiguousarray(ids, np.uint32), base.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"orc_write_index failed ({rc})")
 
 
 def recall_at_k(ids: np.ndarray, gt_d64: np.ndarray, X: np.ndarray, Q: np.ndarray, k: int) -> float:

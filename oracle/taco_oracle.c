@@ -762,6 +762,121 @@ int orc_max_threads(void)
 }
 
 /* ------------------------------------------------------------------------- */
+/* SC-Linear (Section 2.3; Definitions 5 and 6): the index-free baseline.      */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    float dist;
+    int32_t id;
+} sdist;
+
+static int sdcmp(const void *pa, const void *pb)
+{
+    const sdist *a = (const sdist *)pa, *b = (const sdist *)pb;
+    if (a->dist != b->dist) return a->dist < b->dist ? -1 : 1;
+    return (a->id > b->id) - (a->id < b->id);
+}
+
+/*
+ * SC-Linear for one query.  Subspace j is the j-th block of s columns of the
+ * transformed space (the index's own subspaces): the query and every base
+ * point are transformed with the canonical chain (T holds the base, n x M),
+ * and their squared distance in subspace j is the canonical half-distance
+ * chain over the block's s coordinates.  A point collides with the query in
+ * subspace j when it is among the A = ceil(alpha*n) nearest there (Definition
+ * 5), nearest meaning ascending (distance, id); its SC-score counts those
+ * subspaces (Definition 6).  The candidates are the R = floor(beta*n) points
+ * of highest SC-score, ties by the lower id (the selection SC-Linear makes,
+ * Section 2.3); they are re-ranked by the FP32 distance in the original
+ * space and the k smallest (distance, id) returned, padded with -1 / +inf.
+ * Written as the definitions: a full sort per subspace, a full sort of the
+ * scores.  sc_out (n, may be NULL) receives the SC-scores; cand_out (n, may
+ * be NULL) the candidates in ascending id and ncand_out their number.
+ */
+int orc_sclinear(const orc_index *x, const float *T, const float *q, double alpha, double beta, int k,
+                 int64_t *ids, float *d32, uint8_t *sc_out, int32_t *cand_out, int64_t *ncand_out)
+{
+    if (check_args(x, alpha, beta, k, ORC_RULE_FIXED)) return ORC_EINVAL;
+    const int d = x->d, M = x->M, Ns = x->Ns, s = x->s;
+    const int64_t n = x->n;
+    const int64_t A = budget_A(alpha, n), R = budget_R(beta, n);
+    float *qt = (float *)malloc(sizeof(float) * (size_t)M);
+    sdist *all = (sdist *)malloc(sizeof(sdist) * (size_t)n);
+    uint8_t *sc = (uint8_t *)calloc((size_t)n, 1);
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    rres *res = (rres *)malloc(sizeof(rres) * (size_t)n);
+    int rc = ORC_ENOMEM;
+    if (!qt || !all || !sc || !cand || !res) goto out;
+    for (int m = 0; m < M; m++) qt[m] = 0.0f;
+    for (int t = 0; t < d; t++) {
+        float e = q[t] - x->mean[t];
+        for (int m = 0; m < M; m++) qt[m] = fmaf(x->B[(size_t)t * M + m], e, qt[m]);
+    }
+    /* collisions: the A nearest points of every subspace */
+    for (int j = 0; j < Ns; j++) {
+        for (int64_t i = 0; i < n; i++) {
+            const float *r = T + (size_t)i * M + (size_t)j * s;
+            float acc = 0.0f;
+            for (int c = 0; c < s; c++) {
+                float u = qt[j * s + c] - r[c];
+                acc = fmaf(u, u, acc);
+            }
+            all[i].dist = acc;
+            all[i].id = (int32_t)i;
+        }
+        qsort(all, (size_t)n, sizeof(sdist), sdcmp);
+        for (int64_t z = 0; z < A; z++) sc[all[z].id]++;
+    }
+    /* candidates: the R highest SC-scores, ties by the lower id */
+    int32_t last = 0;
+    int64_t nc = select_fixed(sc, n, Ns, R, &last, cand);
+    if (nc < 0) goto out;
+    /* refinement in the original space */
+    for (int64_t i = 0; i < nc; i++) {
+        double unused;
+        row_dist(q, x->base + (size_t)cand[i] * d, d, &res[i].key, &unused);
+        res[i].id = cand[i];
+        res[i].d64 = unused;
+    }
+    qsort(res, (size_t)nc, sizeof(rres), rcmp);
+    for (int i = 0; i < k; i++) {
+        ids[i] = i < nc ? res[i].id : -1;
+        if (d32) d32[i] = i < nc ? res[i].key : INFINITY;
+    }
+    if (sc_out) memcpy(sc_out, sc, (size_t)n);
+    if (cand_out) memcpy(cand_out, cand, sizeof(int32_t) * (size_t)nc);
+    if (ncand_out) *ncand_out = nc;
+    rc = ORC_OK;
+out:
+    free(qt); free(all); free(sc); free(cand); free(res);
+    return rc;
+}
+
+/* SC-Linear for a batch of queries, in parallel over queries on `nthreads`
+ * threads (<= 0: the OpenMP default).  Outputs nq x k. */
+int orc_sclinear_batch(const orc_index *x, const float *T, const float *Q, int64_t nq, double alpha,
+                       double beta, int k, int nthreads, int64_t *ids, float *d32)
+{
+    if (check_args(x, alpha, beta, k, ORC_RULE_FIXED)) return ORC_EINVAL;
+    int err = ORC_OK;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#else
+    nthreads = 1;
+#endif
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int64_t i = 0; i < nq; i++) {
+        int rc = orc_sclinear(x, T, Q + (size_t)i * x->d, alpha, beta, k, ids + (size_t)i * k,
+                              d32 ? d32 + (size_t)i * k : NULL, NULL, NULL, NULL);
+        if (rc) {
+#pragma omp critical
+            err = rc;
+        }
+    }
+    return err;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Ground truth: exact k-NN by brute force in FP64 (Definition 2).             */
 /* ------------------------------------------------------------------------- */
 

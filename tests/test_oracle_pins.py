@@ -678,3 +678,84 @@ def test_fixed_budget_properties(seed):
         k = int(np.count_nonzero(chosen & (sc == L)))
         assert np.array_equal(np.flatnonzero(chosen & (sc == L)), at[:k])
         assert last == L + 1
+
+
+# ---------------------------------------------------------------------------
+# SC-Linear (Section 2.3, Definitions 5 and 6): the index-free baseline
+# ---------------------------------------------------------------------------
+
+def _hand_index(tmp_path):
+    g = _gold("sclinear.json")
+    X = np.array(g["points"], np.float32)
+    n, d = X.shape
+    path = str(tmp_path / "hand.tcx")
+    O.write_index(path, np.zeros(d, np.float32), np.eye(d, dtype=np.float32),
+                  np.zeros((2, 1, 1), np.float32), np.zeros((2, 1, 1), np.float32),
+                  np.array([[0, n], [0, n]], np.uint64), np.tile(np.arange(n, dtype=np.uint32), (2, 1)),
+                  X, s=2, l=1)
+    return g, X, O.OracleIndex(path)
+
+
+def test_sclinear_hand_cases(tmp_path):
+    g, X, idx = _hand_index(tmp_path)
+    T = idx.transformed_base()
+    assert np.array_equal(T, X)                      # the identity transform
+    q = np.array(g["query"], np.float32)
+    for c in g["cases"]:
+        r = idx.sclinear(T, q, c["alpha"], c["beta"], c["k"])
+        assert r["sc"].tolist() == c["sc"], c["why"]
+        assert r["cand"].tolist() == c["cand"], c["why"]
+        assert r["ids"].tolist() == c["ids"], c["why"]
+        want = [np.inf if v is None else v for v in c["d32"]]
+        assert r["d32"].tolist() == want, c["why"]
+    idx.close()
+
+
+def test_sclinear_invariants(tiny_index):
+    # each subspace contributes exactly A collisions; every score is at most
+    # Ns; beta = 1 re-ranks every point (exact k-NN); alpha = 1 makes every
+    # score Ns, so the candidates are the R lowest ids.
+    idx, Q, X = tiny_index["idx"], tiny_index["Q"], tiny_index["X"]
+    T = idx.transformed_base()
+    n, Ns = idx.n, idx.Ns
+    for qi, alpha, beta in ((0, 0.05, 0.005), (7, 0.01, 0.02), (31, 0.2, 0.001)):
+        r = idx.sclinear(T, Q[qi], alpha, beta, 10)
+        assert int(r["sc"].astype(np.int64).sum()) == Ns * O.budget_A(alpha, n)
+        assert r["sc"].max() <= Ns and r["cand"].size == O.budget_R(beta, n)
+        # the candidates hold the highest scores: none left out scores more
+        out = np.setdiff1d(np.arange(n), r["cand"])
+        assert r["sc"][out].max() <= r["sc"][r["cand"]].min()
+    gi, gd = O.bruteforce(X, Q[:5], 10)
+    ids, d32 = idx.sclinear_batch(T, Q[:5], 0.03, 1.0, 10)
+    assert np.array_equal(ids, gi)
+    np.testing.assert_allclose(d32, gd, rtol=1e-5)
+    r = idx.sclinear(T, Q[3], 1.0, 0.003, 10)
+    assert np.all(r["sc"] == Ns) and r["cand"].tolist() == list(range(O.budget_R(0.003, n)))
+    # one query alone and in a batch on several threads agree
+    ids1, _ = idx.sclinear_batch(T, Q[:8], 0.05, 0.005, 10, nthreads=3)
+    for i in range(8):
+        assert idx.sclinear(T, Q[i], 0.05, 0.005, 10)["ids"].tolist() == ids1[i].tolist()
+
+
+def test_sclinear_collisions_are_the_nearest_in_each_subspace(tmp_path):
+    # One subspace (Ns = 1) covering the whole identity-transformed space:
+    # the collisions are the A nearest points, so with beta such that R = A
+    # the candidates are exactly the A nearest by (distance, id) (ties are
+    # made frequent by integer coordinates).
+    rng = np.random.default_rng(31)
+    X = rng.integers(0, 5, (300, 4)).astype(np.float32)
+    path = str(tmp_path / "one.tcx")
+    O.write_index(path, np.zeros(4, np.float32), np.eye(4, dtype=np.float32),
+                  np.zeros((1, 1, 2), np.float32), np.zeros((1, 1, 2), np.float32),
+                  np.array([[0, 300]], np.uint64), np.arange(300, dtype=np.uint32)[None, :], X, s=4, l=1)
+    idx = O.OracleIndex(path)
+    T = idx.transformed_base()
+    for trial in range(20):
+        q = rng.integers(0, 5, 4).astype(np.float32) + np.float32(0.5) * (trial % 2)
+        A = int(rng.integers(1, 300))
+        alpha = A / 300.0
+        r = idx.sclinear(T, q, alpha, alpha, 5)
+        d = ((X.astype(np.float64) - q) ** 2).sum(1)
+        want = np.sort(np.lexsort((np.arange(300), d))[:O.budget_A(alpha, 300)])
+        assert r["sc"].sum() == want.size and np.array_equal(np.flatnonzero(r["sc"]), want)
+    idx.close()
