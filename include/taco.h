@@ -98,8 +98,11 @@ enum tc_option {
     TC_OPT_RERANK_BLOCKS = 10, /* re-rank workgroups per query, [1, 1024]; default 32 */
     TC_OPT_CDIST_PRECISION = 11, /* tc_cdist_precision of the half-subspace centroid
                                distances that order the probe; default TC_CDIST_FP32 */
-    TC_OPT_LIST_LEVEL = 12  /* list level of TC_COUNT_LIST: 1..Ns fixes it; 0 (the
+    TC_OPT_LIST_LEVEL = 12, /* list level of TC_COUNT_LIST: 1..Ns fixes it; 0 (the
                                default) adapts it on the device from batch to batch */
+    TC_OPT_TUNE_PRECISION = 13 /* 1 (default): the autotuners also choose the re-rank
+                               precision among TC_FP32, TC_BF16 and TC_U8; 0: they
+                               keep the current TC_OPT_PRECISION                     */
 };
 
 /* How collision counting and candidate selection are launched.
@@ -115,10 +118,23 @@ enum tc_option {
  *                   query's tiles wait for each other's histogram and
  *                   select straight from LDS.  Needs all tiles of a query
  *                   resident at once (n up to ~64 Mi ids on MI355X).
+ *   TC_COUNT_CODES: point-major counting: every point's Ns cell codes
+ *                   (16-bit, rows of 8 or 16, built on first use) are tested against
+ *                   bitmaps of each query's probed cells held in LDS, 16
+ *                   queries per pass over the codes; packed counts and the
+ *                   histogram then go to the split form's selection.  Its
+ *                   cost is n*Ns bitmap reads per query whatever alpha: the
+ *                   form for large collision ratios.
  *   TC_COUNT_AUTO:  the split launches (measured faster on MI355X for
  *                   uniform budgets).
  * Results are identical. */
-enum tc_count_mode { TC_COUNT_AUTO = 0, TC_COUNT_SPLIT = 1, TC_COUNT_FUSED = 2, TC_COUNT_LIST = 3 };
+enum tc_count_mode {
+    TC_COUNT_AUTO = 0,
+    TC_COUNT_SPLIT = 1,
+    TC_COUNT_FUSED = 2,
+    TC_COUNT_LIST = 3,
+    TC_COUNT_CODES = 4
+};
 
 /* Arithmetic of the re-rank step.
  *   TC_FP32: FP32 squared distances from the FP32 base rows.
@@ -253,17 +269,32 @@ int tc_search_noalloc(tc_index *index, const float *queries, int64_t nq, int32_t
 /*
  * Autotuner.  Times the search of `queries` (device, f32 [nq][d]) with the
  * given k, alpha and beta under candidate launch configurations -- LDS tile
- * width (ids per counting tile), split or fused counting, queries per probe
- * workgroup, re-rank workgroups per query, re-rank precision -- by coordinate
- * descent (1 warm-up + 3 timed runs each, HIP events on `stream`), and leaves
- * the fastest applied.  All candidates give identical results.  With a
- * cache_path (host string, may be NULL) a matching entry (same GPU, index
- * shape, nq, k, alpha, beta) is applied without measuring, and a new result
- * is appended as one JSON object per line.  `report` (host, may be NULL)
- * receives a text summary, truncated to report_len.  Synchronous.
+ * width (ids per counting tile), split, fused or list counting, queries per
+ * probe workgroup, re-rank workgroups per query and, unless
+ * TC_OPT_TUNE_PRECISION is 0, re-rank precision -- by coordinate descent
+ * (1 warm-up + 3 timed runs each, HIP events on `stream`), and leaves the
+ * fastest applied.  All candidates give identical results.  With a
+ * cache_path (host string, may be NULL) an entry with the same key is
+ * applied without measuring; the key holds the GPU, the index's shape, seed
+ * and a hash of its centroids and cell sizes, the selection rule, the
+ * centroid-distance form, the list level, whether precision is tuned, and
+ * the call's nq, k, alpha and beta.  An entry that no longer applies is
+ * measured again.  A new result is appended as one JSON object per line.
+ * `report` (host, may be NULL) receives a text summary, truncated to
+ * report_len.  Synchronous.
  */
 int tc_autotune(tc_index *index, const float *queries, int64_t nq, int32_t k, double alpha,
                 double beta, void *stream, const char *cache_path, char *report, size_t report_len);
+
+/*
+ * The autotuner for tc_search_batched: the same candidates and cache, timed
+ * on tc_search_batched(index, queries, nq, alpha, k, k_max, beta, ...) with
+ * the caller's per-query budgets (device arrays as there).  The cache key
+ * holds nq, k_max, beta and a hash of the alpha and k arrays.  Synchronous.
+ */
+int tc_autotune_batched(tc_index *index, const float *queries, int64_t nq, const double *alpha,
+                        const int32_t *k, int32_t k_max, double beta, void *stream,
+                        const char *cache_path, char *report, size_t report_len);
 
 /*
  * Per-stage outputs of tc_search, for parity checks.  Every member is a
@@ -293,6 +324,25 @@ typedef struct tc_stage_dump {
 int tc_search_debug(tc_index *index, const float *queries, int64_t nq, int32_t k, double alpha,
                     double beta, int64_t *ids, float *dists, void *stream,
                     const tc_stage_dump *dump);
+
+/*
+ * SC-Linear, the index-free baseline of the subspace-collision framework
+ * (Section 2.3; Definitions 5 and 6), on the index's transformed subspaces:
+ * a point collides with a query in subspace j when it is among the
+ * A = ceil(alpha*n) nearest points there, nearest by (squared distance over
+ * the subspace's s columns of the transformed vectors, canonical FP32 chain;
+ * id), and its SC-score counts those subspaces.  The candidates are the
+ * floor(beta*n) points of highest SC-score, ties by the lower id (the
+ * TC_RULE_FIXED selection), re-ranked by FP32 squared L2 in the original
+ * space.  Arguments and outputs as for tc_search; `dump` (host, may be NULL)
+ * receives sc, hist, last, ncand and cand when set (other members ignored).
+ * The first call builds the transformed base (n x Ns*s FP32, synchronous)
+ * and 4 GiB of per-batch distances.  Every point's distance is computed in
+ * every subspace, so the cost grows with n whatever alpha and beta.
+ * TC_EINVAL for Ns*s > 2048.
+ */
+int tc_search_sclinear(tc_index *index, const float *queries, int64_t nq, int32_t k, double alpha,
+                       double beta, int64_t *ids, float *dists, void *stream, const tc_stage_dump *dump);
 
 /*
  * Kernel timing, recorded while TC_OPT_PROFILE is 1.  Waits for the recorded

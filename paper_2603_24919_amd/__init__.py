@@ -20,9 +20,11 @@ __all__ = [
     "TC_RULE_PRINTED", "TC_RULE_PROSE", "TC_RULE_FIXED", "TC_OPT_SELECT_RULE", "TC_OPT_MAX_BATCH",
     "TC_OPT_TILE_IDS", "TC_OPT_PROFILE", "TC_OPT_SCRATCH_BYTES", "TC_OPT_PRECISION",
     "TC_FP32", "TC_BF16", "TC_OPT_COUNT_MODE", "TC_COUNT_AUTO", "TC_COUNT_SPLIT",
-    "TC_COUNT_FUSED", "TC_COUNT_LIST", "TC_OPT_LIST_LEVEL", "TC_OPT_GRAPH", "TC_OPT_PROBE_QPW", "TC_OPT_RERANK_BLOCKS", "KERNELS",
+    "TC_COUNT_FUSED", "TC_COUNT_LIST", "TC_COUNT_CODES", "TC_OPT_LIST_LEVEL", "TC_OPT_GRAPH", "TC_OPT_PROBE_QPW", "TC_OPT_RERANK_BLOCKS", "KERNELS",
     "TC_OPT_CDIST_PRECISION", "TC_CDIST_FP32", "TC_CDIST_BF16", "TC_CDIST_FP8", "TC_U8",
-    "tc_device_errors", "tc_search_batched", "tc_autotune",
+    "tc_device_errors", "tc_search_batched", "tc_autotune", "tc_autotune_batched", "tc_search_noalloc",
+    "tc_search_sclinear",
+    "TC_OPT_TUNE_PRECISION",
     "TacoError", "TacoLibraryMissing", "lib_path", "load_library",
     "tc_load_index", "tc_free_index", "tc_index_info", "tc_set_option", "tc_search",
     "tc_search_debug", "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity",
@@ -35,8 +37,9 @@ TC_OPT_SELECT_RULE, TC_OPT_MAX_BATCH, TC_OPT_TILE_IDS, TC_OPT_PROFILE, TC_OPT_SC
 TC_OPT_PRECISION = 6
 TC_FP32, TC_BF16, TC_U8 = 0, 1, 2
 TC_OPT_COUNT_MODE = 7
-TC_COUNT_AUTO, TC_COUNT_SPLIT, TC_COUNT_FUSED, TC_COUNT_LIST = 0, 1, 2, 3
+TC_COUNT_AUTO, TC_COUNT_SPLIT, TC_COUNT_FUSED, TC_COUNT_LIST, TC_COUNT_CODES = 0, 1, 2, 3, 4
 TC_OPT_LIST_LEVEL = 12
+TC_OPT_TUNE_PRECISION = 13
 TC_OPT_GRAPH, TC_OPT_PROBE_QPW, TC_OPT_RERANK_BLOCKS = 8, 9, 10
 TC_OPT_CDIST_PRECISION = 11
 TC_CDIST_FP32, TC_CDIST_BF16, TC_CDIST_FP8 = 0, 1, 2
@@ -92,6 +95,7 @@ def load_library():
     L.tc_set_option.argtypes = [vp, C.c_int, i64]
     L.tc_search.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, vp]
     L.tc_search_noalloc.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, vp]
+    L.tc_search_sclinear.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, vp, C.POINTER(_StageDump)]
     L.tc_search_debug.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, vp, C.POINTER(_StageDump)]
     L.tc_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
     L.tc_profile_reset.argtypes = [vp]
@@ -99,6 +103,8 @@ def load_library():
     L.tc_device_errors.argtypes = [vp, C.POINTER(C.c_uint32)]
     L.tc_search_batched.argtypes = [vp, vp, i64, vp, vp, i32, dbl, vp, vp, vp]
     L.tc_autotune.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, C.c_char_p, C.c_char_p, C.c_size_t]
+    L.tc_autotune_batched.argtypes = [vp, vp, i64, vp, vp, i32, dbl, vp, C.c_char_p, C.c_char_p,
+                                      C.c_size_t]
     L.tc_last_error.restype = C.c_char_p
     L.tc_last_error.argtypes = []
     L.tc_build_stats.argtypes = [vp, i64, i32, vp, vp, vp]
@@ -111,9 +117,10 @@ def load_library():
                                  C.c_int, C.POINTER(vp), vp]
     L.tc_save_index.argtypes = [vp, C.c_char_p]
     for f in ("tc_load_index", "tc_index_info", "tc_set_option", "tc_search", "tc_search_noalloc",
+              "tc_search_sclinear",
               "tc_search_debug",
               "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity", "tc_device_errors",
-              "tc_search_batched", "tc_autotune", "tc_build_stats", "tc_build_eigen",
+              "tc_search_batched", "tc_autotune", "tc_autotune_batched", "tc_build_stats", "tc_build_eigen",
               "tc_build_allocate", "tc_build_transform", "tc_build_kmeans", "tc_build_imi",
               "tc_build_index", "tc_save_index"):
         getattr(L, f).restype = C.c_int
@@ -346,6 +353,34 @@ def tc_search_debug(index, queries, k: int, alpha: float, beta: float, dump=None
     return ids, dists
 
 
+def tc_search_sclinear(index, queries, k: int, alpha: float, beta: float, dump=None, ids=None,
+                       dists=None, stream=None):
+    """SC-Linear (the index-free baseline) on ``queries``; ``dump`` as for
+    tc_search_debug (sc, hist, last, ncand, cand are written).  Returns
+    ``(ids, dists)``."""
+    import torch
+    nq = int(queries.shape[0])
+    dev = queries.device
+    if queries.dtype != torch.float32 or not queries.is_cuda or not queries.is_contiguous():
+        raise ValueError("queries must be a contiguous float32 CUDA tensor")
+    if ids is None:
+        ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    if dists is None:
+        dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    _check_tensor(ids, torch.int64, (nq, k), dev, "ids")
+    _check_tensor(dists, torch.float32, (nq, k), dev, "dists")
+    sd = None
+    if dump is not None:
+        unknown = set(dump) - set(DUMP_FIELDS)
+        if unknown:
+            raise ValueError(f"unknown dump fields {sorted(unknown)}")
+        sd = _StageDump(*[_ptr(dump.get(f)) for f in DUMP_FIELDS])
+    _check(load_library().tc_search_sclinear(index, queries.data_ptr(), nq, int(k), float(alpha), float(beta),
+                                             ids.data_ptr(), dists.data_ptr(), _stream_handle(stream, dev),
+                                             None if sd is None else C.byref(sd)))
+    return ids, dists
+
+
 def tc_search_batched(index, queries, alpha, k, k_max: int, beta: float, ids=None, dists=None,
                       stream=None):
     """Per-query budgets: ``alpha`` (CUDA float64 [nq]) and ``k`` (CUDA int32
@@ -375,6 +410,24 @@ def tc_autotune(index, queries, k: int, alpha: float, beta: float, cache_path=No
     _check(load_library().tc_autotune(
         index, queries.data_ptr(), int(queries.shape[0]), int(k), float(alpha), float(beta),
         _stream_handle(stream, queries.device), None if cache_path is None else os.fsencode(cache_path),
+        buf, len(buf)))
+    return buf.value.decode()
+
+
+def tc_autotune_batched(index, queries, alpha, k, k_max: int, beta: float, cache_path=None,
+                        stream=None) -> str:
+    """Tune the launch configuration of tc_search_batched on this batch and
+    its per-query budgets (CUDA float64 ``alpha`` [nq], int32 ``k`` [nq]);
+    returns the report."""
+    import torch
+    nq = int(queries.shape[0])
+    dev = queries.device
+    _check_tensor(alpha, torch.float64, (nq,), dev, "alpha")
+    _check_tensor(k, torch.int32, (nq,), dev, "k")
+    buf = C.create_string_buffer(8192)
+    _check(load_library().tc_autotune_batched(
+        index, queries.data_ptr(), nq, alpha.data_ptr(), k.data_ptr(), int(k_max), float(beta),
+        _stream_handle(stream, dev), None if cache_path is None else os.fsencode(cache_path),
         buf, len(buf)))
     return buf.value.decode()
 
@@ -442,6 +495,9 @@ class Index:
     def search(self, queries, k: int, alpha: float, beta: float, **kw):
         return tc_search(self.handle, queries, k, alpha, beta, **kw)
 
+    def search_sclinear(self, queries, k: int, alpha: float, beta: float, dump=None, **kw):
+        return tc_search_sclinear(self.handle, queries, k, alpha, beta, dump, **kw)
+
     def search_noalloc(self, queries, k: int, alpha: float, beta: float, ids, dists, **kw):
         return tc_search_noalloc(self.handle, queries, k, alpha, beta, ids, dists, **kw)
 
@@ -450,6 +506,11 @@ class Index:
 
     def autotune(self, queries, k: int, alpha: float, beta: float, cache_path=None, **kw) -> str:
         return tc_autotune(self.handle, queries, k, alpha, beta, cache_path=cache_path, **kw)
+
+    def autotune_batched(self, queries, alpha, k, k_max: int, beta: float, cache_path=None,
+                         **kw) -> str:
+        return tc_autotune_batched(self.handle, queries, alpha, k, k_max, beta,
+                                   cache_path=cache_path, **kw)
 
     def search_debug(self, queries, k: int, alpha: float, beta: float, dump, **kw):
         return tc_search_debug(self.handle, queries, k, alpha, beta, dump, **kw)

@@ -102,7 +102,10 @@ hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint
 size_t fused_lds_bytes(int W, int bits);
 hipError_t fused_max_blocks(int W, int bits, int Ns, int *blocks_per_cu);
 hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int NG, uint32_t *arrive,
-                               uint32_t *err, uint32_t spin_limit, hipStream_t st);
+                               uint32_t *err, uint32_t spin_limit, uint32_t *queue, const int32_t *order,
+                               hipStream_t st);
+// queries by descending work (sum of retrieved over subspaces), into perm
+hipError_t launch_cost_order(const int64_t *retrieved, int nq, int Ns, int32_t *perm, hipStream_t st);
 int rerank_lanes_per_row(int d);
 hipError_t launch_rerank(const float *Q, int nq, int d, const float *base, const int32_t *cand,
                          const uint32_t *cand_count, int64_t cap, float *cand_dist, int blocks_per_q,
@@ -143,5 +146,27 @@ hipError_t launch_prep_bf16(const float *base, int64_t n, int d, const float *mu
 hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32_t *cand_count,
                        int64_t cap, int nq, int k, const int32_t *kq, int k_max, int64_t *ids,
                        float *dists, hipStream_t st);
+
+// SC-Linear: per-subspace distances D [nq][Ns][n] of every point (canonical
+// FP32 chain on the transformed base T [n][M]), the A-th smallest
+// (distance, id) key of each (query, subspace), and the packed SC-scores
+// with their level histogram (levels >= 1 added into hist).
+hipError_t launch_sub_dist(const float *T, int64_t n, int M, int Ns, int s, const float *qt, int nq, float *D,
+                           hipStream_t st);
+hipError_t launch_sub_select(const float *D, int64_t n, int Ns, int nq, int64_t A, uint64_t *thr, hipStream_t st);
+hipError_t launch_sub_count(const float *D, int64_t n, int Ns, int nq, const uint64_t *thr, int T, int W, int bits,
+                            uint32_t *sc, uint32_t *hist, hipStream_t st);
+
+// Point-major counting (TC_COUNT_CODES): codes [n][code_stride(Ns)] u16 of
+// every point's cell per subspace (built once from the IMI), then per batch
+// the probed-cell bitmaps bm [nq][Ns][ceil(K/32)] and the packed counts and
+// level histogram of the split form.
+int code_stride(int Ns);
+size_t codes_lds_bytes(int Ns, int K);
+hipError_t launch_build_codes(const uint32_t *ids, const uint32_t *offs, int Ns, int K, int64_t n, uint16_t *codes,
+                              hipStream_t st);
+hipError_t launch_count_codes(const uint16_t *codes, const int32_t *cells, const int32_t *ncells, int nq, int Ns,
+                              int K, int64_t n, int T, int W, int bits, uint32_t *bm, uint32_t *sc, uint32_t *hist,
+                              int num_cu, hipStream_t st);
 
 }  // namespace taco

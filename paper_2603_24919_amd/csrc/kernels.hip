@@ -26,6 +26,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace taco {
@@ -679,6 +681,37 @@ __global__ __launch_bounds__(ORD_BLOCK) void k_query_order(const int32_t *__rest
     }
     for (int q = static_cast<int>(threadIdx.x) + KPT * ORD_BLOCK; q < nq; q += ORD_BLOCK)
         perm[atomicAdd(&bins[key(q)], 1u)] = q;
+}
+
+// Queries by descending work: the sum over subspaces of the points each
+// probed (the count's walk), in 64 buckets of its binary logarithm, bucket
+// by bucket from the largest (a counting sort; the order inside a bucket is
+// arbitrary).  The fused count hands queries out in this order when budgets
+// differ per query, so the longest ones start first.  grid 1, block
+// ORD_BLOCK.
+__global__ __launch_bounds__(ORD_BLOCK) void k_cost_order(const int64_t *__restrict__ retrieved, int nq, int Ns,
+                                                          int32_t *__restrict__ perm) {
+    __shared__ uint32_t bins[64];
+    if (threadIdx.x < 64) bins[threadIdx.x] = 0u;
+    __syncthreads();
+    auto key = [&](int q) {
+        int64_t r = 0;
+        for (int j = 0; j < Ns; j++) r += retrieved[static_cast<int64_t>(q) * Ns + j];
+        const int lg = r > 0 ? 63 - __clzll(static_cast<unsigned long long>(r)) : 0;
+        return 63 - lg;  // larger work, smaller key
+    };
+    for (int q = threadIdx.x; q < nq; q += ORD_BLOCK) atomicAdd(&bins[key(q)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0u;
+        for (int b = 0; b < 64; b++) {
+            const uint32_t c = bins[b];
+            bins[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nq; q += ORD_BLOCK) perm[atomicAdd(&bins[key(q)], 1u)] = q;
 }
 
 // ---------------------------------------------------------------------------
@@ -1677,15 +1710,18 @@ __global__ void k_unpack_counts(const uint32_t *__restrict__ sc, int64_t words_q
 
 // ---------------------------------------------------------------------------
 // count + select fused in one cooperative, persistent launch.  The grid is
-// exactly as large as the GPU can hold at once (cooperative launch), split
-// into NG groups of T workgroups; workgroup t of group g serves tile t of
-// queries g, g + NG, ...  After counting its tile and adding the tile's level
-// counts to hist[q], a workgroup arrives on arrive[q] and waits until all T
-// tiles of q have arrived.  Every member of a group is resident and works
-// through the same queries in the same order, so the wait ends; it is also
-// bounded (spin_limit polls), setting *err and going on if ever exceeded.
-// Then the threshold comes from the complete histogram and candidates are
-// compacted straight from LDS: no packed counts go to HBM.
+// exactly as large as the GPU can hold at once (cooperative launch): NG
+// workgroups per tile.  A workgroup of tile t takes its next query from an
+// atomic work queue, the tile's own counter into the query order (queries
+// of larger budgets first when budgets differ per query, so the longest
+// work starts early and the tail is short).  After counting its tile and
+// adding the tile's level counts to hist[q], it arrives on arrive[q] and
+// waits until all T tiles of q have arrived.  Every tile hands out the same
+// order, and every workgroup is resident, so the earliest unfinished query
+// always has each of its tiles counted or being counted and the wait ends;
+// it is also bounded (spin_limit polls), setting *err and going on if ever
+// exceeded.  Then the threshold comes from the complete histogram and
+// candidates are compacted straight from LDS: no packed counts go to HBM.
 // ---------------------------------------------------------------------------
 
 struct FuseArgs {
@@ -1694,6 +1730,8 @@ struct FuseArgs {
     uint32_t *arrive;     // [nq], zero before the launch
     uint32_t *err;        // set to 1 if a wait timed out
     uint32_t spin_limit;
+    uint32_t *queue;      // [T] per-tile dequeue counters, zero before the launch
+    const int32_t *order; // [nq] the order queries are handed out in, or null (0, 1, ...)
 };
 
 template <int BITS, bool HI>
@@ -1708,12 +1746,20 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
     // CT_FSTAGE slots per wavefront
     constexpr int CT_FSTAGE = 2 * CT_CHUNK / CT_WAVES >= 128 ? 128 : 64;
     static_assert(CT_FSTAGE * CT_WAVES <= 2 * CT_CHUNK, "staging must fit the slice table");
-    const int t = blockIdx.x % a.T, g = blockIdx.x / a.T;
+    __shared__ int s_q;
+    const int t = blockIdx.x % a.T;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int words = a.W / PER_WORD;
     const int64_t tile_lo = static_cast<int64_t>(t) * a.W;
     const int tile_n = static_cast<int>(min<int64_t>(a.W, a.n - tile_lo));
-    for (int q = g; q < f.nq; q += f.NG) {
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t i = atomicAdd(&f.queue[t], 1u);
+            s_q = i < static_cast<uint32_t>(f.nq) ? (f.order ? f.order[i] : static_cast<int>(i)) : -1;
+        }
+        __syncthreads();
+        const int q = s_q;
+        if (q < 0) break;
         if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
         count_tile<BITS, HI>(a, q, t, L, hsum);
         __syncthreads();
@@ -2904,12 +2950,18 @@ hipError_t fused_max_blocks(int W, int bits, int Ns, int *blocks_per_cu) {
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, CT_BLOCK, bytes);
 }
 
+hipError_t launch_cost_order(const int64_t *retrieved, int nq, int Ns, int32_t *perm, hipStream_t st) {
+    k_cost_order<<<1, ORD_BLOCK, 0, st>>>(retrieved, nq, Ns, perm);
+    return hipGetLastError();
+}
+
 hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int NG, uint32_t *arrive,
-                               uint32_t *err, uint32_t spin_limit, hipStream_t st) {
+                               uint32_t *err, uint32_t spin_limit, uint32_t *queue, const int32_t *order,
+                               hipStream_t st) {
     CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.flat, c.ftot, c.perm};
     SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
                   s.dump_hist, nullptr};
-    FuseArgs f{c.nq, NG, const_cast<uint32_t *>(s.hist), arrive, err, spin_limit};
+    FuseArgs f{c.nq, NG, const_cast<uint32_t *>(s.hist), arrive, err, spin_limit, queue, order};
     void *args[] = {&a, &sa, &f};
     const void *k = count_select_kernel(c.bits, c.Ns);
     return hipLaunchCooperativeKernel(k, dim3(static_cast<unsigned>(NG) * c.T), dim3(CT_BLOCK), args,
@@ -3047,6 +3099,382 @@ hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32
                        int64_t cap, int nq, int k, const int32_t *kq, int k_max, int64_t *ids,
                        float *dists, hipStream_t st) {
     k_topk<<<nq, BLOCK, 0, st>>>(cand, cand_dist, cand_count, cap, k, kq, k_max, ids, dists);
+    return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// SC-Linear (Section 2.3; Definitions 5 and 6): exact collisions, no index.
+// A point collides with the query in subspace j when its key (distance bits
+// << 32 | id) is among the A smallest of that subspace; distances use the
+// canonical FP32 chain over the subspace's columns of the transformed base.
+// ---------------------------------------------------------------------------
+
+// D[q][j][i] = sum_c fmaf(u, u) with u = qt[q][j*s+c] - T[i][j*s+c], c
+// ascending (T row-major [n][M]).  grid (ceil(n/256), ceil(nq/SD_Q)), block
+// 256: one point per thread, SD_Q queries per block from LDS.
+constexpr int SD_Q = 8;
+
+__global__ __launch_bounds__(256) void k_sub_dist(const float *__restrict__ T, int64_t n, int M, int Ns, int s,
+                                                  const float *__restrict__ qt, int nq, float *__restrict__ D) {
+    extern __shared__ float sq[];  // [SD_Q][M]
+    const int q0 = blockIdx.y * SD_Q;
+    const int nqb = min(SD_Q, nq - q0);
+    for (int i = threadIdx.x; i < nqb * M; i += blockDim.x) sq[i] = qt[static_cast<int64_t>(q0) * M + i];
+    __syncthreads();
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float *row = T + i * M;
+    for (int j = 0; j < Ns; j++) {
+        float acc[SD_Q];
+#pragma unroll
+        for (int b = 0; b < SD_Q; b++) acc[b] = 0.0f;
+        for (int c = 0; c < s; c++) {
+            const float x = row[j * s + c];
+#pragma unroll
+            for (int b = 0; b < SD_Q; b++) {
+                const float u = sq[b * M + j * s + c] - x;
+                acc[b] = fmaf(u, u, acc[b]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < SD_Q; b++)
+            if (b < nqb) D[(static_cast<int64_t>(q0 + b) * Ns + j) * n + i] = acc[b];
+    }
+}
+
+// Adds one to bin `b` of the LDS histogram for every active lane, one LDS
+// add per distinct bin of the wavefront: lanes holding the first active
+// lane's bin are folded into a single add (distances share their top bits,
+// so most lanes of a pass agree).
+__device__ __forceinline__ void wave_hist_add(uint32_t *hist, uint32_t b, bool active) {
+    uint64_t pend = __ballot(active);
+    while (pend) {
+        const int lead = __ffsll(static_cast<unsigned long long>(pend)) - 1;
+        const uint32_t lb = static_cast<uint32_t>(__shfl(static_cast<int>(b), lead, WAVE));
+        const uint64_t same = __ballot(active && b == lb) & pend;
+        if ((threadIdx.x % WAVE) == lead) atomicAdd(&hist[lb], static_cast<uint32_t>(__popcll(same)));
+        pend &= ~same;
+    }
+}
+
+// The A-th smallest key (distance bits << 32 | id) of each (query,
+// subspace): an MSB-first radix select on the distance bits, 8 bits per pass
+// over the keys whose higher bits match the digits chosen so far, then the
+// r-th smallest id among the keys with that distance, by a pass in id
+// order with workgroup prefix counts.  grid (Ns, nq), block SS_BLOCK.
+constexpr int SS_BLOCK = 1024;
+
+__global__ __launch_bounds__(SS_BLOCK) void k_sub_select(const float *__restrict__ D, int64_t n, int Ns, int64_t A,
+                                                         uint64_t *__restrict__ thr) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_digit, s_rank, s_wsum[SS_BLOCK / WAVE];
+    __shared__ uint32_t s_id;
+    const int j = blockIdx.x, q = blockIdx.y;
+    const uint32_t *key = reinterpret_cast<const uint32_t *>(D + (static_cast<int64_t>(q) * Ns + j) * n);
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    uint32_t prefix = 0u, pmask = 0u;
+    uint32_t rank = static_cast<uint32_t>(A);  // 1-based rank among the keys matching the prefix
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int b = tid; b < 256; b += SS_BLOCK) hist[b] = 0u;
+        __syncthreads();
+        for (int64_t i0 = 0; i0 < n; i0 += SS_BLOCK) {
+            const int64_t i = i0 + tid;
+            const uint32_t k = i < n ? key[i] : 0u;
+            const bool in = i < n && (k & pmask) == prefix;
+            wave_hist_add(hist, (k >> shift) & 0xffu, in);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t cum = 0u, d = 0u;
+            for (; d < 255u; d++) {
+                if (cum + hist[d] >= rank) break;
+                cum += hist[d];
+            }
+            s_digit = d;
+            s_rank = rank - cum;
+        }
+        __syncthreads();
+        prefix |= s_digit << shift;
+        pmask |= 0xffu << shift;
+        rank = s_rank;
+        __syncthreads();
+    }
+    // the rank-th id (ascending) among the keys equal to `prefix`
+    uint32_t seen = 0u;
+    if (tid == 0) s_id = 0xffffffffu;
+    __syncthreads();
+    for (int64_t i0 = 0; i0 < n; i0 += SS_BLOCK) {
+        const int64_t i = i0 + tid;
+        const uint32_t f = (i < n && key[i] == prefix) ? 1u : 0u;
+        const uint32_t incl = wave_incl_scan_u32(f, lane);
+        if (lane == WAVE - 1) s_wsum[wv] = incl;
+        __syncthreads();
+        uint32_t before = seen;
+        for (int w = 0; w < wv; w++) before += s_wsum[w];
+        if (f && before + incl == rank) s_id = static_cast<uint32_t>(i);
+        uint32_t tot = 0u;
+        for (int w = 0; w < SS_BLOCK / WAVE; w++) tot += s_wsum[w];
+        seen += tot;
+        __syncthreads();
+        if (s_id != 0xffffffffu) break;
+    }
+    if (tid == 0) thr[static_cast<int64_t>(q) * Ns + j] = (static_cast<uint64_t>(prefix) << 32) | s_id;
+}
+
+// SC-scores from the thresholds, packed BITS per id (ids past n score 0),
+// and the level histogram (levels >= 1, atomically into hist[q]).  grid
+// (ceil(words / 256), nq), block 256: one 32-bit word of counts per thread.
+template <int BITS>
+__global__ __launch_bounds__(256) void k_sub_count(const float *__restrict__ D, int64_t n, int Ns,
+                                                   const uint64_t *__restrict__ thr, int64_t words,
+                                                   uint32_t *__restrict__ sc, uint32_t *__restrict__ hist) {
+    constexpr int PER_WORD = 32 / BITS;
+    __shared__ uint32_t lh[17];
+    const int q = blockIdx.y;
+    if (threadIdx.x <= 16) lh[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (w < words) {
+        uint32_t word = 0u;
+        for (int b = 0; b < PER_WORD; b++) {
+            const int64_t id = w * PER_WORD + b;
+            if (id >= n) break;
+            uint32_t c = 0u;
+            for (int j = 0; j < Ns; j++) {
+                const uint32_t kb = __float_as_uint(D[(static_cast<int64_t>(q) * Ns + j) * n + id]);
+                const uint64_t key = (static_cast<uint64_t>(kb) << 32) | static_cast<uint64_t>(id);
+                c += key <= thr[static_cast<int64_t>(q) * Ns + j] ? 1u : 0u;
+            }
+            word |= c << (BITS * b);
+            if (c) atomicAdd(&lh[c], 1u);
+        }
+        sc[static_cast<int64_t>(q) * words + w] = word;
+    }
+    __syncthreads();
+    if (threadIdx.x >= 1 && threadIdx.x <= Ns && lh[threadIdx.x])
+        atomicAdd(&hist[static_cast<int64_t>(q) * (Ns + 1) + threadIdx.x], lh[threadIdx.x]);
+}
+
+hipError_t launch_sub_dist(const float *T, int64_t n, int M, int Ns, int s, const float *qt, int nq, float *D,
+                           hipStream_t st) {
+    dim3 grid(static_cast<unsigned>((n + 255) / 256), static_cast<unsigned>((nq + SD_Q - 1) / SD_Q));
+    k_sub_dist<<<grid, 256, sizeof(float) * SD_Q * M, st>>>(T, n, M, Ns, s, qt, nq, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_select(const float *D, int64_t n, int Ns, int nq, int64_t A, uint64_t *thr, hipStream_t st) {
+    k_sub_select<<<dim3(Ns, nq), SS_BLOCK, 0, st>>>(D, n, Ns, A, thr);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_count(const float *D, int64_t n, int Ns, int nq, const uint64_t *thr, int T, int W, int bits,
+                            uint32_t *sc, uint32_t *hist, hipStream_t st) {
+    const int64_t words = static_cast<int64_t>(T) * W * bits / 32;
+    dim3 grid(static_cast<unsigned>((words + 255) / 256), static_cast<unsigned>(nq));
+    if (bits == 4)
+        k_sub_count<4><<<grid, 256, 0, st>>>(D, n, Ns, thr, words, sc, hist);
+    else
+        k_sub_count<8><<<grid, 256, 0, st>>>(D, n, Ns, thr, words, sc, hist);
+    return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Point-major counting ("code scan", TC_COUNT_CODES).  Instead of walking the
+// probed cells' id lists, every point's Ns cell codes are tested against
+// bitmaps of each query's probed cells held in LDS, for CC_G queries per
+// pass over the codes.  The work is n * Ns bitmap reads per query whatever
+// the budget, against sum_j R_j increments for the list walk: the form for
+// large collision ratios.  Output as k_count's split form: packed counts and
+// the level histogram (levels >= 1).
+// ---------------------------------------------------------------------------
+
+// codes[i][j] (row stride cs u16) = the cell of point i in subspace j; rows
+// padded past Ns with 0.  grid over the Ns*n list entries, block 256.
+__global__ void k_build_codes(const uint32_t *__restrict__ ids, const uint32_t *__restrict__ offs, int Ns, int K,
+                              int64_t n, int cs, uint16_t *__restrict__ codes) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= static_cast<int64_t>(Ns) * n) return;
+    const int j = static_cast<int>(e / n);
+    const uint32_t p = static_cast<uint32_t>(e - static_cast<int64_t>(j) * n);
+    const uint32_t *o = offs + static_cast<int64_t>(j) * (K + 1);
+    int lo = 0, hi = K;  // the cell c with o[c] <= p < o[c+1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (o[mid] <= p)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    codes[static_cast<int64_t>(ids[e]) * cs + j] = static_cast<uint16_t>(lo);
+}
+
+// bm[q][j][KW] = bit c set when query q probed cell c of subspace j.  grid
+// nq, block 256, LDS Ns*KW words.
+__global__ __launch_bounds__(256) void k_cell_bitmap(const int32_t *__restrict__ cells,
+                                                     const int32_t *__restrict__ ncells, int Ns, int K, int KW,
+                                                     uint32_t *__restrict__ bm) {
+    extern __shared__ uint32_t b[];
+    const int q = blockIdx.x;
+    for (int i = threadIdx.x; i < Ns * KW; i += blockDim.x) b[i] = 0u;
+    __syncthreads();
+    for (int j = 0; j < Ns; j++) {
+        const int nc = ncells[static_cast<int64_t>(q) * Ns + j];
+        const int32_t *cj = cells + (static_cast<int64_t>(q) * Ns + j) * K;
+        for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+            const int c = cj[i];
+            atomicOr(&b[j * KW + (c >> 5)], 1u << (c & 31));
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < Ns * KW; i += blockDim.x) bm[static_cast<int64_t>(q) * Ns * KW + i] = b[i];
+}
+
+constexpr int CC_G = 16;     // queries per pass over the codes
+constexpr int CC_PTS = 8;    // points per thread and chunk (one nibble word, two byte words)
+
+// Adds the per-lane level counts of `lo` (byte c: points of count c < 8),
+// `hi` (byte c - 8: 8 <= c < 16) and `top` (count 16) of the wavefront to
+// h[1..Ns].  Each byte is at most CC_PTS; the 16-bit sums cannot carry.
+__device__ __forceinline__ void code_hist_fold(uint64_t lo, uint64_t hi, uint32_t top, int Ns, uint32_t *h,
+                                               int lane) {
+    uint64_t xs[2] = {lo, hi};
+#pragma unroll
+    for (int part = 0; part < 2; part++) {
+        if (part == 1 && Ns < 8) break;
+        const uint64_t x = xs[part];
+        if (!__any(x != 0ull)) continue;
+        const uint64_t ev = x & 0x00FF00FF00FF00FFull, od = (x >> 8) & 0x00FF00FF00FF00FFull;
+        const uint32_t s0 = wave_sum_u32(static_cast<uint32_t>(ev)), s1 = wave_sum_u32(static_cast<uint32_t>(ev >> 32));
+        const uint32_t s2 = wave_sum_u32(static_cast<uint32_t>(od)), s3 = wave_sum_u32(static_cast<uint32_t>(od >> 32));
+        if (lane == 0) {
+            const uint32_t v[8] = {s0 & 0xffffu, s2 & 0xffffu, s0 >> 16, s2 >> 16,
+                                   s1 & 0xffffu, s3 & 0xffffu, s1 >> 16, s3 >> 16};
+#pragma unroll
+            for (int c = 0; c < 8; c++) {
+                const int lv = part * 8 + c;
+                if (lv >= 1 && lv <= Ns && v[c]) atomicAdd(&h[lv], v[c]);
+            }
+        }
+    }
+    if (Ns >= 16) {
+        const uint32_t t = wave_sum_u32(top);
+        if (lane == 0 && t) atomicAdd(&h[16], t);
+    }
+}
+
+// grid (chunk workers, ceil(nq / CC_G)), block 256; LDS: the group's bitmaps
+// (CC_G * Ns * KW words) and its histograms (CC_G * 17 words).  Each thread
+// takes CC_PTS consecutive points per chunk, keeps their codes in registers
+// and, query by query, sums the Ns bitmap bits of each point.
+template <int BITS, int CS>
+__global__ __launch_bounds__(256) void k_count_codes(const uint16_t *__restrict__ codes, int64_t n, int Ns, int KW,
+                                                     const uint32_t *__restrict__ bm, int nq, int64_t words,
+                                                     uint32_t *__restrict__ sc, uint32_t *__restrict__ hist) {
+    constexpr int PER_WORD = 32 / BITS;
+    constexpr int WPT = CC_PTS / PER_WORD;  // output words per thread and chunk
+    extern __shared__ uint32_t lds[];
+    const int q0 = blockIdx.y * CC_G;
+    const int G = min(CC_G, nq - q0);
+    uint32_t *bl = lds;                         // [CC_G][Ns][KW]
+    uint32_t *hl = lds + CC_G * Ns * KW;        // [CC_G][17]
+    for (int i = threadIdx.x; i < G * Ns * KW; i += blockDim.x) bl[i] = bm[static_cast<int64_t>(q0) * Ns * KW + i];
+    for (int i = threadIdx.x; i < CC_G * 17; i += blockDim.x) hl[i] = 0u;
+    __syncthreads();
+    const int lane = threadIdx.x % WAVE;
+    const int64_t chunk = static_cast<int64_t>(blockDim.x) * CC_PTS;
+    for (int64_t c0 = static_cast<int64_t>(blockIdx.x) * chunk; c0 < n; c0 += static_cast<int64_t>(gridDim.x) * chunk) {
+        const int64_t p0 = c0 + static_cast<int64_t>(threadIdx.x) * CC_PTS;
+        // the codes of this thread's points (CS/8 16-byte loads per point)
+        uint4 cw[CC_PTS][CS / 8];
+#pragma unroll
+        for (int p = 0; p < CC_PTS; p++)
+#pragma unroll
+            for (int v = 0; v < CS / 8; v++)
+                cw[p][v] = p0 + p < n ? reinterpret_cast<const uint4 *>(codes + (p0 + p) * CS)[v]
+                                      : make_uint4(0u, 0u, 0u, 0u);
+        for (int g = 0; g < G; g++) {
+            const uint32_t *bg = bl + g * Ns * KW;
+            uint32_t out[WPT] = {};
+            uint64_t lo = 0ull, hi = 0ull;
+            uint32_t top = 0u;
+#pragma unroll
+            for (int p = 0; p < CC_PTS; p++) {
+                uint32_t c = 0u;
+#pragma unroll
+                for (int j = 0; j < CS; j++) {
+                    if (j < Ns) {
+                        const uint4 v4 = cw[p][j / 8];
+                        const uint32_t w32 = (j % 8) < 2 ? v4.x : (j % 8) < 4 ? v4.y : (j % 8) < 6 ? v4.z : v4.w;
+                        const uint32_t code = (j % 2) ? (w32 >> 16) : (w32 & 0xffffu);
+                        c += (bg[j * KW + (code >> 5)] >> (code & 31u)) & 1u;
+                    }
+                }
+                if (p0 + p >= n) c = 0u;
+                out[p / PER_WORD] |= c << (BITS * (p % PER_WORD));
+                const uint64_t inc = 1ull << ((c & 7u) << 3);
+                if (c < 8u)
+                    lo += c ? inc : 0ull;
+                else if (c < 16u)
+                    hi += inc;
+                else
+                    top += 1u;
+            }
+            const int64_t w0 = p0 / PER_WORD;
+#pragma unroll
+            for (int u = 0; u < WPT; u++)
+                if (w0 + u < words) sc[static_cast<int64_t>(q0 + g) * words + w0 + u] = out[u];
+            code_hist_fold(lo, hi, top, Ns, hl + g * 17, lane);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < G * 17; i += blockDim.x) {
+        const int g = i / 17, v = i % 17;
+        if (v >= 1 && v <= Ns && hl[i]) atomicAdd(&hist[static_cast<int64_t>(q0 + g) * (Ns + 1) + v], hl[i]);
+    }
+}
+
+int code_stride(int Ns) { return Ns <= 8 ? 8 : 16; }
+
+hipError_t launch_build_codes(const uint32_t *ids, const uint32_t *offs, int Ns, int K, int64_t n, uint16_t *codes,
+                              hipStream_t st) {
+    const int64_t e = static_cast<int64_t>(Ns) * n;
+    hipError_t r = hipMemsetAsync(codes, 0, sizeof(uint16_t) * static_cast<size_t>(n) * code_stride(Ns), st);
+    if (r != hipSuccess) return r;
+    k_build_codes<<<static_cast<unsigned>((e + 255) / 256), 256, 0, st>>>(ids, offs, Ns, K, n, code_stride(Ns), codes);
+    return hipGetLastError();
+}
+
+size_t codes_lds_bytes(int Ns, int K) {
+    const int KW = (K + 31) / 32;
+    return sizeof(uint32_t) * (static_cast<size_t>(CC_G) * Ns * KW + CC_G * 17);
+}
+
+hipError_t launch_count_codes(const uint16_t *codes, const int32_t *cells, const int32_t *ncells, int nq, int Ns,
+                              int K, int64_t n, int T, int W, int bits, uint32_t *bm, uint32_t *sc, uint32_t *hist,
+                              int num_cu, hipStream_t st) {
+    const int KW = (K + 31) / 32;
+    k_cell_bitmap<<<nq, 256, sizeof(uint32_t) * Ns * KW, st>>>(cells, ncells, Ns, K, KW, bm);
+    hipError_t r = hipGetLastError();
+    if (r != hipSuccess) return r;
+    const int64_t words = static_cast<int64_t>(T) * W * bits / 32;
+    const int64_t chunks = (n + 256 * CC_PTS - 1) / (256 * CC_PTS);
+    const int groups = (nq + CC_G - 1) / CC_G;
+    // enough workgroups to fill the GPU a few times over, each taking whole
+    // chunks of points (every query group re-reads the codes)
+    int64_t gx = (int64_t(num_cu) * 8 + groups - 1) / groups;
+    gx = std::max<int64_t>(1, std::min<int64_t>(gx, chunks));
+    dim3 grid(static_cast<unsigned>(gx), static_cast<unsigned>(groups));
+    const size_t lds = codes_lds_bytes(Ns, K);
+    if (bits == 4) {
+        if (code_stride(Ns) == 8)
+            k_count_codes<4, 8><<<grid, 256, lds, st>>>(codes, n, Ns, KW, bm, nq, words, sc, hist);
+        else
+            k_count_codes<4, 16><<<grid, 256, lds, st>>>(codes, n, Ns, KW, bm, nq, words, sc, hist);
+    } else {
+        k_count_codes<8, 16><<<grid, 256, lds, st>>>(codes, n, Ns, KW, bm, nq, words, sc, hist);
+    }
     return hipGetLastError();
 }
 

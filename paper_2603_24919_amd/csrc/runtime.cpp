@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -125,6 +126,8 @@ struct GraphKey {
 struct tc_index {
     int device = 0;
     uint64_t seed = 0;  // build seed recorded in the index file
+    uint64_t ident = 0; // FNV-1a of the centroids and cell offsets (autotune cache key)
+    bool tune_precision = true;  // TC_OPT_TUNE_PRECISION
     int64_t n = 0;
     int d = 0, Ns = 0, s = 0, h1 = 0, h2 = 0, l = 0, M = 0, K = 0;
     // index on the device
@@ -143,6 +146,9 @@ struct tc_index {
     uint32_t *lvl = nullptr;     // adaptive list level, on the device
     uint32_t *err = nullptr;     // device error word of the fused kernel
     uint32_t *arrive = nullptr;  // [Qb] tile arrivals per query
+    uint32_t *qctr = nullptr;    // [T] per-tile work-queue counters of the fused count
+    uint16_t *codes = nullptr;   // [n][code_stride] cell of every point per subspace (TC_COUNT_CODES)
+    uint32_t *bm = nullptr;      // [Qb][Ns][ceil(K/32)] probed-cell bitmaps (TC_COUNT_CODES)
     int64_t *Aq = nullptr;       // [Qb] per-query collision budgets (batched calls)
     int32_t *kq = nullptr;       // [Qb] per-query k, clamped
     int probe_qpw = 4;           // queries (wavefronts) per probe workgroup
@@ -198,6 +204,11 @@ struct tc_index {
     int cT_form = TC_CDIST_FP32; // form cT currently holds
     std::vector<float> C1h, C2h; // host copies of the centroids
     float *qn = nullptr, *qsc = nullptr, *cd = nullptr;  // per-batch scratch
+    // SC-Linear (built on first use): transformed base [n][M], subspace
+    // distances [scQ][Ns][n] and per-(query, subspace) thresholds
+    float *sct = nullptr, *scD = nullptr;
+    uint64_t *scthr = nullptr;
+    int64_t scQ = 0;
     // profiling
     std::vector<Timing> pending;
     double total_ms[K_COUNT_] = {0};
@@ -230,6 +241,10 @@ void free_scratch(tc_index *x) {
     (void)hipFree(x->sc);
     (void)hipFree(x->arrive);
     x->arrive = nullptr;
+    (void)hipFree(x->qctr);
+    x->qctr = nullptr;
+    (void)hipFree(x->bm);
+    x->bm = nullptr;
     (void)hipFree(x->lb);
     (void)hipFree(x->rk_count);
     (void)hipFree(x->tau_ids);
@@ -320,6 +335,8 @@ int alloc_scratch(tc_index *x) {
         TC_HIP(hipMemcpy(x->lvl, &l0, sizeof(l0), hipMemcpyHostToDevice), "list level");
     }
     if ((rc = dmalloc(&x->arrive, size_t(qb), "tile arrivals"))) return rc;
+    if ((rc = dmalloc(&x->qctr, size_t(x->T), "work-queue counters"))) return rc;
+    if ((rc = dmalloc(&x->bm, size_t(qb) * x->Ns * ((x->K + 31) / 32), "probed-cell bitmaps"))) return rc;
     if ((rc = dmalloc(&x->Aq, size_t(qb), "per-query budgets"))) return rc;
     if ((rc = dmalloc(&x->kq, size_t(qb), "per-query k"))) return rc;
     if ((rc = dmalloc(&x->cand, size_t(qb) * x->n, "candidates"))) return rc;
@@ -433,6 +450,10 @@ void free_all(tc_index *x) {
     (void)hipFree(x->csc);
     (void)hipFree(x->base8);
     (void)hipFree(x->rmeta);
+    (void)hipFree(x->codes);
+    (void)hipFree(x->sct);
+    (void)hipFree(x->scD);
+    (void)hipFree(x->scthr);
     for (auto &t : x->pending) {
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
@@ -574,6 +595,13 @@ int install(tc_index *x, int device, const std::vector<float> &mean, const std::
             }
         }
         for (size_t c = 0; c <= K; c++) offs[j * (K + 1) + c] = static_cast<uint32_t>(o[c]);
+    }
+    {
+        Fnv f;
+        f.add(C1.data(), C1.size() * sizeof(float));
+        f.add(C2.data(), C2.size() * sizeof(float));
+        f.add(off64.data(), off64.size() * sizeof(uint64_t));
+        x->ident = f.h;
     }
     int ndev = 0;
     TC_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
@@ -739,6 +767,7 @@ struct Scratch {
     uint32_t *ftot = nullptr;
     // used by the other forms only
     uint32_t *lvl = nullptr, *tcount = nullptr, *toff = nullptr, *tlev = nullptr, *arrive = nullptr;
+    uint32_t *qctr = nullptr, *bm = nullptr;
     int64_t *Aq = nullptr;
     int32_t *kq = nullptr;
     float *lb = nullptr;
@@ -767,6 +796,8 @@ Scratch own_scratch(const tc_index *x) {
     S.toff = x->toff;
     S.tlev = x->tlev;
     S.arrive = x->arrive;
+    S.qctr = x->qctr;
+    S.bm = x->bm;
     S.Aq = x->Aq;
     S.kq = x->kq;
     S.lb = x->lb;
@@ -810,6 +841,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
     const bool fixed = x->rule == TC_RULE_FIXED;
     const bool fused = count_mode == TC_COUNT_FUSED && !fixed;
     const bool list = count_mode == TC_COUNT_LIST && !fixed;
+    const bool codes = count_mode == TC_COUNT_CODES;
     for (int64_t b0 = 0; b0 < c.nq; b0 += S.Qb) {
         const int nb = static_cast<int>(std::min<int64_t>(S.Qb, c.nq - b0));
         const float *Qb = c.Q + b0 * x->d;
@@ -854,8 +886,9 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
         // gives the same results)
         const bool order = x->K <= 4096;
         if (order) TC_HIP(taco::launch_query_order(S.cells, nb, x->Ns, x->K, S.perm, st), "query order kernel");
-        TC_HIP(taco::launch_flatten_cells(S.cells, S.ncells, nb, x->Ns, x->K, S.flat, S.ftot, st),
-               "probed cell list kernel");
+        if (!codes)
+            TC_HIP(taco::launch_flatten_cells(S.cells, S.ncells, nb, x->Ns, x->K, S.flat, S.ftot, st),
+                   "probed cell list kernel");
         taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids_enc, x->off2d, S.flat,
                              S.ftot, order ? S.perm : nullptr};
         taco::SelectLaunch sl{S.hist, R, x->rule, cap, S.cand, S.cand_count,
@@ -864,9 +897,12 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                               dump && dump->hist ? dump->hist + b0 * (x->Ns + 1) : nullptr};
         if (fused) {
             TC_HIP(taco::launch_fill_u32(S.arrive, nb, 0u, st), "clearing tile arrivals");
+            TC_HIP(taco::launch_fill_u32(S.qctr, x->T, 0u, st), "clearing the work queue");
+            // per-query budgets: hand the largest walks out first
+            if (Aq) TC_HIP(taco::launch_cost_order(S.retrieved, nb, x->Ns, S.perm, st), "cost order kernel");
             rec(K_FUSED, st, true);
             TC_HIP(taco::launch_count_select(cl, sl, std::min(x->fused_groups, nb), S.arrive, x->err,
-                                             1u << 24, st),
+                                             1u << 24, S.qctr, (Aq || order) ? S.perm : nullptr, st),
                    "fused count/select kernel");
             rec(K_FUSED, st, false);
         } else if (list) {
@@ -896,7 +932,12 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                        "dump sc");
         } else {
             rec(K_COUNT, st, true);
-            TC_HIP(taco::launch_count(cl, S.hist, S.sc, 0, nullptr, st), "count kernel");
+            if (codes)
+                TC_HIP(taco::launch_count_codes(x->codes, S.cells, S.ncells, nb, x->Ns, x->K, x->n, x->T, x->W,
+                                                x->bits, S.bm, S.sc, S.hist, x->num_cu, st),
+                       "point-major count kernels");
+            else
+                TC_HIP(taco::launch_count(cl, S.hist, S.sc, 0, nullptr, st), "count kernel");
             rec(K_COUNT, st, false);
             rec(K_SELECT, st, true);
             TC_HIP(taco::launch_select(cl, sl, S.sc, st), "select kernel");
@@ -1155,8 +1196,20 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
         return TC_OK;
     case TC_OPT_COUNT_MODE:
         if (value != TC_COUNT_AUTO && value != TC_COUNT_SPLIT && value != TC_COUNT_FUSED &&
-            value != TC_COUNT_LIST)
+            value != TC_COUNT_LIST && value != TC_COUNT_CODES)
             return fail(TC_EINVAL, "unknown count mode");
+        if (value == TC_COUNT_CODES) {
+            if (taco::codes_lds_bytes(x->Ns, x->K) > size_t(x->max_lds))
+                return fail(TC_EINVAL, "the probed-cell bitmaps of the point-major form do not fit the LDS");
+            if (!x->codes) {
+                TC_HIP(hipDeviceSynchronize(), "synchronizing before building the cell codes");
+                int rc = dmalloc(&x->codes, size_t(x->n) * taco::code_stride(x->Ns), "cell codes");
+                if (rc) return rc;
+                TC_HIP(taco::launch_build_codes(x->ids, x->offs, x->Ns, x->K, x->n, x->codes, nullptr),
+                       "building the cell codes");
+                TC_HIP(hipDeviceSynchronize(), "building the cell codes");
+            }
+        }
         if (value == TC_COUNT_FUSED && x->fused_groups <= 0)
             return fail(TC_EINVAL, "the fused count/select kernel is unavailable for this index");
         if (value == TC_COUNT_LIST && x->n > (int64_t(1) << taco::list_shift(x->Ns)))
@@ -1184,6 +1237,10 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
     case TC_OPT_PROFILE:
         if (value != 0 && value != 1) return fail(TC_EINVAL, "profile must be 0 or 1");
         x->profile = value != 0;
+        return TC_OK;
+    case TC_OPT_TUNE_PRECISION:
+        if (value != 0 && value != 1) return fail(TC_EINVAL, "tune precision must be 0 or 1");
+        x->tune_precision = value != 0;
         return TC_OK;
     default:
         return fail(TC_EINVAL, "unknown option");
@@ -1323,14 +1380,18 @@ struct TuneConfig {
     int W, mode, qpw, rr, precision;
 };
 
-std::string tune_key(const tc_index *x, int64_t nq, int k, double alpha, double beta) {
+// Cache key of a tuning: the GPU, the index (shape, seed, content hash), the
+// options that change which kernels run, and the call (`call`).
+std::string tune_key(const tc_index *x, const std::string &call) {
     hipDeviceProp_t prop;
     std::string dev = hipGetDeviceProperties(&prop, x->device) == hipSuccess ? prop.gcnArchName : "gpu";
     for (auto &ch : dev)
         if (ch == ' ' || ch == '\t' || ch == '"') ch = '_';
     std::ostringstream os;
     os << dev << "|cu" << x->num_cu << "|n" << x->n << "|d" << x->d << "|Ns" << x->Ns << "|s" << x->s << "|l"
-       << x->l << "|nq" << nq << "|k" << k << "|a" << alpha << "|b" << beta;
+       << x->l << "|seed" << std::hex << x->seed << "|id" << x->ident << std::dec << "|rule" << x->rule
+       << "|cdist" << x->cdist << "|lvl" << x->list_level << "|tp"
+       << (x->tune_precision ? -1 : x->precision) << "|" << call;
     return os.str();
 }
 
@@ -1343,19 +1404,11 @@ int apply_config(tc_index *x, const TuneConfig &c) {
     return tc_set_option(x, TC_OPT_RERANK_BLOCKS, c.rr);
 }
 
-}  // namespace
-
-extern "C" {
-
-int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double alpha, double beta,
-                void *stream, const char *cache_path, char *report, size_t report_len) {
-    if (!x || !queries || nq < 1) return fail(TC_EINVAL, "index and a non-empty query batch are required");
-    if (k < 1 || int64_t(k) > x->n || k > 1024) return fail(TC_EINVAL, "k must be in [1, min(n, 1024)]");
-    if (!(alpha > 0.0 && alpha <= 1.0) || !(beta >= 0.0 && beta <= 1.0))
-        return fail(TC_EINVAL, "alpha must be in (0, 1] and beta in [0, 1]");
-    DeviceGuard g(x->device);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const std::string key = tune_key(x, nq, k, alpha, beta);
+// Coordinate descent over the launch configurations for the call `once`
+// (one search on stream st): tile width x count mode, then probe queries per
+// workgroup, re-rank precision (if tuned), then re-rank workgroups per query.
+int tune(tc_index *x, const std::string &key, const std::function<int()> &once, hipStream_t st,
+         const char *cache_path, char *report, size_t report_len) {
     std::ostringstream rep;
     auto finish = [&](int rc) {
         if (report && report_len) {
@@ -1375,34 +1428,32 @@ int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double
             TuneConfig c{};
             if (sscanf(line.c_str() + line.find("\"W\""), "\"W\": %d, \"mode\": %d, \"qpw\": %d, \"rr\": %d, \"precision\": %d",
                        &c.W, &c.mode, &c.qpw, &c.rr, &c.precision) == 5) {
-                int rc = apply_config(x, c);
-                rep << "cached " << key << " W=" << c.W << " mode=" << c.mode << " qpw=" << c.qpw
-                    << " rr=" << c.rr << " precision=" << c.precision << "\n";
-                return finish(rc);
+                if (apply_config(x, c) == TC_OK) {
+                    rep << "cached " << key << " W=" << c.W << " mode=" << c.mode << " qpw=" << c.qpw
+                        << " rr=" << c.rr << " precision=" << c.precision << "\n";
+                    return finish(TC_OK);
+                }
+                rep << "cached entry no longer applies (" << g_err << "); measuring\n";
+                break;
             }
         }
     }
-    int64_t *ids = nullptr;
-    float *dists = nullptr;
-    int rc;
-    if ((rc = dmalloc(&ids, size_t(nq) * k, "autotune ids"))) return finish(rc);
-    if ((rc = dmalloc(&dists, size_t(nq) * k, "autotune dists"))) {
-        (void)hipFree(ids);
-        return finish(rc);
-    }
     hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+    TC_HIP(hipEventCreate(&e0), "autotune timing");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return finish(fail(TC_EDEVICE, "autotune timing"));
+    }
     const bool graph = x->use_graph, prof = x->profile;
     x->use_graph = false;
     x->profile = false;
     auto measure = [&](const TuneConfig &c, double *ms) -> int {
         int r = apply_config(x, c);
         if (r) return r;
-        if ((r = search(x, queries, nq, k, alpha, beta, ids, dists, st, nullptr))) return r;
+        if ((r = once())) return r;
         TC_HIP(hipEventRecord(e0, st), "autotune timing");
         for (int i = 0; i < 3; i++)
-            if ((r = search(x, queries, nq, k, alpha, beta, ids, dists, st, nullptr))) return r;
+            if ((r = once())) return r;
         TC_HIP(hipEventRecord(e1, st), "autotune timing");
         TC_HIP(hipEventSynchronize(e1), "autotune timing");
         float f = 0.0f;
@@ -1412,11 +1463,10 @@ int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double
             << " precision=" << c.precision << " ms=" << *ms << "\n";
         return TC_OK;
     };
+    int rc = TC_OK;
     TuneConfig best{x->W, x->count_mode == TC_COUNT_AUTO ? TC_COUNT_SPLIT : x->count_mode, x->probe_qpw,
                     x->rr_blocks, x->precision};
     double best_ms = 1e30;
-    // coordinate descent: tile width x count mode, then probe queries per
-    // workgroup, re-rank precision, then re-rank workgroups per query
     std::vector<int> Ws = x->bits == 4 ? std::vector<int>{65536, 131072, 262144}
                                        : std::vector<int>{32768, 65536, 131072};
     for (int W : Ws) {
@@ -1430,10 +1480,18 @@ int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double
                 if ((rc = tc_set_option(x, TC_OPT_TILE_IDS, W))) goto done;
                 if (x->fused_groups <= 0) continue;
             }
+            if (mode == TC_COUNT_LIST && x->n > (int64_t(1) << taco::list_shift(x->Ns))) continue;
             double ms;
             if ((rc = measure(c, &ms))) goto done;
             if (ms < best_ms) best_ms = ms, best = c;
         }
+    }
+    if (taco::codes_lds_bytes(x->Ns, x->K) <= size_t(x->max_lds)) {
+        TuneConfig c = best;
+        c.mode = TC_COUNT_CODES;
+        double ms;
+        if ((rc = measure(c, &ms))) goto done;
+        if (ms < best_ms) best_ms = ms, best = c;
     }
     for (int qpw : {1, 2, 4, 8, 16}) {
         TuneConfig c = best;
@@ -1442,12 +1500,14 @@ int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double
         if ((rc = measure(c, &ms))) goto done;
         if (ms < best_ms) best_ms = ms, best = c;
     }
-    for (int p : {TC_FP32, TC_BF16, TC_U8}) {
-        TuneConfig c = best;
-        c.precision = p;
-        double ms;
-        if ((rc = measure(c, &ms))) goto done;
-        if (ms < best_ms) best_ms = ms, best = c;
+    if (x->tune_precision) {
+        for (int p : {TC_FP32, TC_BF16, TC_U8}) {
+            TuneConfig c = best;
+            c.precision = p;
+            double ms;
+            if ((rc = measure(c, &ms))) goto done;
+            if (ms < best_ms) best_ms = ms, best = c;
+        }
     }
     for (int rr : {8, 16, 32, 64}) {
         TuneConfig c = best;
@@ -1470,9 +1530,74 @@ done:
     x->profile = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    return finish(rc);
+}
+
+}  // namespace
+
+extern "C" {
+
+int tc_autotune(tc_index *x, const float *queries, int64_t nq, int32_t k, double alpha, double beta,
+                void *stream, const char *cache_path, char *report, size_t report_len) {
+    if (!x || !queries || nq < 1) return fail(TC_EINVAL, "index and a non-empty query batch are required");
+    if (k < 1 || int64_t(k) > x->n || k > 1024) return fail(TC_EINVAL, "k must be in [1, min(n, 1024)]");
+    if (!(alpha > 0.0 && alpha <= 1.0) || !(beta >= 0.0 && beta <= 1.0))
+        return fail(TC_EINVAL, "alpha must be in (0, 1] and beta in [0, 1]");
+    DeviceGuard g(x->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::ostringstream call;
+    call << "nq" << nq << "|k" << k << "|a" << alpha << "|b" << beta;
+    int64_t *ids = nullptr;
+    float *dists = nullptr;
+    int rc;
+    if ((rc = dmalloc(&ids, size_t(nq) * k, "autotune ids"))) return rc;
+    if ((rc = dmalloc(&dists, size_t(nq) * k, "autotune dists"))) {
+        (void)hipFree(ids);
+        return rc;
+    }
+    rc = tune(x, tune_key(x, call.str()),
+              [&]() { return search(x, queries, nq, k, alpha, beta, ids, dists, st, nullptr); }, st,
+              cache_path, report, report_len);
     (void)hipFree(ids);
     (void)hipFree(dists);
-    return finish(rc);
+    return rc;
+}
+
+int tc_autotune_batched(tc_index *x, const float *queries, int64_t nq, const double *alpha, const int32_t *k,
+                        int32_t k_max, double beta, void *stream, const char *cache_path, char *report,
+                        size_t report_len) {
+    if (!x || !queries || !alpha || !k || nq < 1)
+        return fail(TC_EINVAL, "index, a non-empty query batch and its budgets are required");
+    if (k_max < 1 || int64_t(k_max) > x->n || k_max > 1024)
+        return fail(TC_EINVAL, "k_max must be in [1, min(n, 1024)]");
+    if (!(beta >= 0.0 && beta <= 1.0)) return fail(TC_EINVAL, "beta must be in [0, 1]");
+    DeviceGuard g(x->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the budgets enter the key through a hash of their bytes
+    std::vector<double> ah(nq);
+    std::vector<int32_t> kh(nq);
+    TC_HIP(hipMemcpyAsync(ah.data(), alpha, sizeof(double) * nq, hipMemcpyDeviceToHost, st), "reading alpha");
+    TC_HIP(hipMemcpyAsync(kh.data(), k, sizeof(int32_t) * nq, hipMemcpyDeviceToHost, st), "reading k");
+    TC_HIP(hipStreamSynchronize(st), "reading the budgets");
+    Fnv f;
+    f.add(ah.data(), ah.size() * sizeof(double));
+    f.add(kh.data(), kh.size() * sizeof(int32_t));
+    std::ostringstream call;
+    call << "batched|nq" << nq << "|kmax" << k_max << "|b" << beta << "|budgets" << std::hex << f.h;
+    int64_t *ids = nullptr;
+    float *dists = nullptr;
+    int rc;
+    if ((rc = dmalloc(&ids, size_t(nq) * k_max, "autotune ids"))) return rc;
+    if ((rc = dmalloc(&dists, size_t(nq) * k_max, "autotune dists"))) {
+        (void)hipFree(ids);
+        return rc;
+    }
+    rc = tune(x, tune_key(x, call.str()),
+              [&]() { return tc_search_batched(x, queries, nq, alpha, k, k_max, beta, ids, dists, st); }, st,
+              cache_path, report, report_len);
+    (void)hipFree(ids);
+    (void)hipFree(dists);
+    return rc;
 }
 
 int tc_device_errors(tc_index *x, uint32_t *flags) {
@@ -1776,6 +1901,76 @@ int save(const tc_index *x, const char *path) {
     return ok ? TC_OK : fail(TC_EIO, std::string("cannot write index file ") + path);
 }
 
+// SC-Linear (Section 2.3): exact per-subspace collisions over every point,
+// then the fixed-budget selection, the FP32 re-rank and the top-k.
+int sclinear(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, double beta, int64_t *ids,
+             float *dists, hipStream_t st, const tc_stage_dump *dump) {
+    if (!x) return fail(TC_EINVAL, "index is NULL");
+    if (nq < 0) return fail(TC_EINVAL, "nq < 0");
+    if (nq == 0) return TC_OK;
+    if (!Q || !ids || !dists) return fail(TC_EINVAL, "queries, ids and dists must be non-NULL");
+    if (k < 1 || int64_t(k) > x->n || k > 1024) return fail(TC_EINVAL, "k must be in [1, min(n, 1024)]");
+    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(TC_EINVAL, "alpha must be in (0, 1]");
+    if (!(beta >= 0.0 && beta <= 1.0)) return fail(TC_EINVAL, "beta must be in [0, 1]");
+    if (size_t(x->M) * 8 * sizeof(float) > 65536) return fail(TC_EINVAL, "SC-Linear needs Ns*s <= 2048");
+    DeviceGuard g(x->device);
+    int rc;
+    const int64_t n = x->n;
+    if (!x->sct) {
+        if ((rc = dmalloc(&x->sct, size_t(n) * x->M, "SC-Linear transformed base"))) return rc;
+        TC_HIP(transform_rows(x->base, n, x->d, x->mean, x->B, x->M, x->sct, nullptr), "transforming the base");
+        TC_HIP(hipDeviceSynchronize(), "transforming the base");
+    }
+    // distances of up to 4 GiB per batch, at most the index's batch size
+    const int64_t per_q = int64_t(x->Ns) * n * 4;
+    const int64_t want = std::max<int64_t>(1, std::min<int64_t>(x->Qb, (int64_t(4) << 30) / per_q));
+    if (x->scQ != want) {
+        (void)hipFree(x->scD);
+        (void)hipFree(x->scthr);
+        x->scD = nullptr;
+        x->scthr = nullptr;
+        x->scQ = 0;
+        if ((rc = dmalloc(&x->scD, size_t(want) * x->Ns * n, "SC-Linear distances"))) return rc;
+        if ((rc = dmalloc(&x->scthr, size_t(want) * x->Ns, "SC-Linear thresholds"))) return rc;
+        x->scQ = want;
+    }
+    double a = std::ceil(alpha * double(n)), r = std::floor(beta * double(n));
+    a = std::min(std::max(a, 1.0), double(n));
+    r = std::min(std::max(r, 0.0), double(n));
+    const int64_t A = static_cast<int64_t>(a), R = static_cast<int64_t>(r);
+    for (int64_t b0 = 0; b0 < nq; b0 += x->scQ) {
+        const int nb = static_cast<int>(std::min<int64_t>(x->scQ, nq - b0));
+        TC_HIP(taco::launch_fill_u32(x->hist, int64_t(nb) * (x->Ns + 1), 0u, st), "clearing histograms");
+        TC_HIP(taco::launch_fill_u32(x->cand_count, x->Qb + 2, 0u, st), "clearing candidate counts");
+        TC_HIP(taco::launch_transform(Q + b0 * x->d, nb, x->d, x->mean, x->B, x->M, x->qt, st), "transform kernel");
+        TC_HIP(taco::launch_sub_dist(x->sct, n, x->M, x->Ns, x->s, x->qt, nb, x->scD, st), "subspace distances");
+        TC_HIP(taco::launch_sub_select(x->scD, n, x->Ns, nb, A, x->scthr, st), "subspace selection");
+        TC_HIP(taco::launch_sub_count(x->scD, n, x->Ns, nb, x->scthr, x->T, x->W, x->bits, x->sc, x->hist, st),
+               "SC-Linear counts");
+        taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, n, x->ids_enc, x->off2d, x->flat, x->ftot,
+                             nullptr};
+        taco::SelectLaunch sl{x->hist, R, TC_RULE_FIXED, n, x->cand, x->cand_count,
+                              dump && dump->sc ? dump->sc + b0 * n : nullptr,
+                              dump && dump->last ? dump->last + b0 : nullptr,
+                              dump && dump->hist ? dump->hist + b0 * (x->Ns + 1) : nullptr};
+        TC_HIP(taco::launch_select(cl, sl, x->sc, st), "select kernel");
+        TC_HIP(taco::launch_select_level(cl, sl, x->sc, st), "boundary-level select kernel");
+        TC_HIP(taco::launch_rerank(Q + b0 * x->d, nb, x->d, x->base, x->cand, x->cand_count, n, x->cand_dist,
+                                   x->rr_blocks, st),
+               "rerank kernel");
+        TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, n, nb, k, nullptr, k, ids + b0 * k,
+                                 dists + b0 * k, st),
+               "top-k kernel");
+        if (dump && dump->ncand)
+            TC_HIP(taco::launch_u32_to_i64(x->cand_count, dump->ncand + b0, nb, st), "dump ncand");
+        if (dump && dump->cand)
+            TC_HIP(hipMemcpyAsync(dump->cand + b0 * n, x->cand, sizeof(int32_t) * size_t(nb) * n,
+                                  hipMemcpyDeviceToDevice, st),
+                   "dump cand");
+    }
+    return TC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1877,6 +2072,11 @@ int tc_build_index(const float *base, int64_t n, int32_t d, int32_t Ns, int32_t 
     *out = x;
     g_err.clear();
     return TC_OK;
+}
+
+int tc_search_sclinear(tc_index *x, const float *queries, int64_t nq, int32_t k, double alpha, double beta,
+                       int64_t *ids, float *dists, void *stream, const tc_stage_dump *dump) {
+    return sclinear(x, queries, nq, k, alpha, beta, ids, dists, static_cast<hipStream_t>(stream), dump);
 }
 
 int tc_save_index(const tc_index *x, const char *path) {

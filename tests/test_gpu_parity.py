@@ -251,14 +251,15 @@ def test_u8_integer_queries_and_others_equal_fp32(taco_mod):
               f"others {nr[n_int:].mean():.1f} of {g8['ncand'][n_int:].mean():.0f}", flush=True)
 
 
-@pytest.mark.parametrize("mode", ["split", "fused", "list"])
+@pytest.mark.parametrize("mode", ["split", "fused", "list", "codes"])
 def test_count_modes_all_stages(taco_mod, tiny, mode):
-    """The split (count, then select), fused (one cooperative launch) and
-    list (ids at or above the list level listed while counting) paths all
-    match the oracle stage by stage, also with several tiles per query and
-    several batches."""
+    """The split (count, then select), fused (one cooperative launch), list
+    (ids at or above the list level listed while counting) and point-major
+    (cell codes against probed-cell bitmaps) paths all match the oracle
+    stage by stage, also with several tiles per query and several batches."""
     t = taco_mod
-    m = {"split": t.TC_COUNT_SPLIT, "fused": t.TC_COUNT_FUSED, "list": t.TC_COUNT_LIST}[mode]
+    m = {"split": t.TC_COUNT_SPLIT, "fused": t.TC_COUNT_FUSED, "list": t.TC_COUNT_LIST,
+         "codes": t.TC_COUNT_CODES}[mode]
     print(f"[tiny] count mode {mode}", flush=True)
     for opts in (((t.TC_OPT_COUNT_MODE, m),),
                  ((t.TC_OPT_TILE_IDS, 4096), (t.TC_OPT_COUNT_MODE, m), (t.TC_OPT_MAX_BATCH, 13))):
@@ -511,6 +512,84 @@ def test_autotune_keeps_results_and_caches(taco_mod, tiny, tmp_path):
     assert torch.equal(ids2, ref_ids) and torch.equal(d2, ref_d)
     idx.close()
     idx2.close()
+
+
+@pytest.mark.parametrize("w", scaled_workloads(), ids=lambda w: w.name)
+def test_codes_and_fused_modes_workload_shapes(taco_mod, w):
+    """The point-major count (Ns = 8 and 16, up to 4,096 cells) and the
+    fused count with its work queue match the split form bit for bit on the
+    workload shapes, with uniform and per-query budgets and the fixed-budget
+    rule."""
+    import torch
+    t = taco_mod
+    X, Q = synthdata.base_and_queries(w)
+    path = workload_index(w, X)
+    q = torch.from_numpy(Q).cuda()
+    alpha, k = _batched_inputs(w, Q.shape[0])
+    ad, kd = torch.from_numpy(alpha).cuda(), torch.from_numpy(k).cuda()
+    ref = None
+    for mode in (t.TC_COUNT_SPLIT, t.TC_COUNT_CODES, t.TC_COUNT_FUSED):
+        idx = t.Index(path, 0)
+        try:
+            idx.set_option(t.TC_OPT_COUNT_MODE, mode)
+        except t.TacoError:
+            idx.close()
+            assert mode == t.TC_COUNT_FUSED
+            continue
+        out = []
+        for rule in (t.TC_RULE_PRINTED, t.TC_RULE_FIXED):
+            idx.set_option(t.TC_OPT_SELECT_RULE, rule)
+            i1, d1 = idx.search(q, 10, 0.03, 0.005)
+            i2, d2 = idx.search_batched(q, ad, kd, 100, 0.005)
+            torch.cuda.synchronize()
+            out += [i1.cpu().numpy(), d1.cpu().numpy().view(np.uint32), i2.cpu().numpy(),
+                    d2.cpu().numpy().view(np.uint32)]
+        assert idx.device_errors() == 0
+        idx.close()
+        print(f"[{w.name}] mode {mode}", flush=True)
+        if ref is None:
+            ref = out
+        else:
+            for a, b in zip(out, ref):
+                assert np.array_equal(a, b), (w.name, mode)
+
+
+def test_autotune_key_separates_forms_and_batched_tuner(taco_mod, tiny, tmp_path):
+    """The tuning cache keys on the options that change which kernels run:
+    another selection rule or centroid-distance form measures afresh instead
+    of reusing the entry.  The batched tuner keeps tc_search_batched's
+    results and caches under its budgets' hash; with TC_OPT_TUNE_PRECISION
+    = 0 the re-rank precision stays as set."""
+    import torch
+    t = taco_mod
+    cache = str(tmp_path / "tune.jsonl")
+    q = torch.from_numpy(tiny["Q"]).cuda()
+    idx = t.Index(tiny["path"], 0)
+    assert "best" in idx.autotune(q, 10, 0.05, 0.005, cache_path=cache)
+    idx.set_option(t.TC_OPT_SELECT_RULE, t.TC_RULE_PROSE)
+    assert "best" in idx.autotune(q, 10, 0.05, 0.005, cache_path=cache)
+    idx.set_option(t.TC_OPT_CDIST_PRECISION, t.TC_CDIST_FP8)
+    assert "best" in idx.autotune(q, 10, 0.05, 0.005, cache_path=cache)
+    assert idx.autotune(q, 10, 0.05, 0.005, cache_path=cache).startswith("cached")
+    idx.close()
+    assert len(open(cache).read().strip().splitlines()) == 3
+    alpha_h, k_h = _batched_inputs(tiny["w"], q.shape[0])
+    alpha, k = torch.from_numpy(alpha_h).cuda(), torch.from_numpy(k_h).cuda()
+    ref = t.Index(tiny["path"], 0)
+    r_ids, r_d = ref.search_batched(q, alpha, k, 100, 0.005)
+    torch.cuda.synchronize()
+    ref.close()
+    idx = t.Index(tiny["path"], 0)
+    idx.set_option(t.TC_OPT_PRECISION, t.TC_BF16)
+    idx.set_option(t.TC_OPT_TUNE_PRECISION, 0)
+    rep = idx.autotune_batched(q, alpha, k, 100, 0.005, cache_path=cache)
+    print(rep, flush=True)
+    assert "best" in rep and all("precision=1" in ln for ln in rep.strip().splitlines())
+    ids, d = idx.search_batched(q, alpha, k, 100, 0.005)
+    torch.cuda.synchronize()
+    assert torch.equal(ids, r_ids) and torch.equal(d, r_d)
+    assert idx.autotune_batched(q, alpha, k, 100, 0.005, cache_path=cache).startswith("cached")
+    idx.close()
 
 
 # ---------------------------------------------------------------------------
