@@ -60,7 +60,7 @@ DEFAULT_WORKLOAD = "sphere-10m-d96"
 METRIC = "QPS at recall@10=0.95 on 1 MI355X; BF16/FP8+batched vs FP32 plain"
 RECALL_TARGET = 0.95
 HBM_PEAK_GBS = 8000.0
-KERNELS = ("transform", "cdist", "probe", "count", "select", "rerank", "topk", "recheck", "count_select")
+KERNELS = ("transform", "cdist", "probe", "count", "select", "rerank", "topk", "recheck", "count_select", "stream")
 
 # Per workload: the (alpha, beta) sweep, the paths run, the one the value is
 # read from, and the oracle's sweep points (a bounded sample near the target).
@@ -464,7 +464,7 @@ def kernel_rates(kern, alg, steps):
         v["alg_GBps"] = None if (b is None or v["ms_total"] <= 0) else (b * steps) / (v["ms_total"] * 1e-3) / 1e9
 
 
-def run_point(taco, torch, idx, pname, run, stream, args, w, nq, recall_fn, alg_fn, tuned_cfg):
+def run_point(taco, torch, idx, pname, run, stream, args, w, nq, recall_fn, alg_fn, tuned_cfg, beta, k_max):
     """One sweep point of one path: an eager timed run with per-kernel
     events, then for the tuned paths (already tuned: `tuned_cfg` is their
     configuration) the graph replay rate; recall from the results of the
@@ -485,7 +485,7 @@ def run_point(taco, torch, idx, pname, run, stream, args, w, nq, recall_fn, alg_
     kernel_rates(kern, alg, args.steps)
     qps = nq * args.steps / (ms * 1e-3)
     point.update(qps=qps, recall=rec, ms_per_step=ms / args.steps, kernels=kern, per_query=avg,
-                 increments_per_step=incr, batches_per_step=-(-nq // idx.batch_capacity()),
+                 increments_per_step=incr, batches_per_step=-(-nq // idx.batch_capacity(beta, k_max)),
                  rerank_precision=real_prec, cdist=cd)
     if tuned:
         idx.set_option(taco.TC_OPT_GRAPH, 1)
@@ -534,6 +534,34 @@ def roofline_of(workload, op, path_name):
         # the count kernel's own limiter: one LDS increment per probed id
         r["count_increments_per_s"] = op["increments_per_step"] / (c["ms_total"] / op["steps"] * 1e-3)
     return r
+
+
+def sclinear_leg(taco, torch, path, qd, Q, X, gt, S, w, op, stream, m):
+    """SC-Linear (the index-free baseline of Section 2.3) on the GPU at the
+    operating point's alpha and beta, over the first m queries: one warm-up
+    call, then one timed call (HIP events); recall on those with ground
+    truth.  The paper's Table 2 reports the TaCo / SC-Linear query-time
+    ratio the same way."""
+    m = min(m, qd.shape[0])
+    idx = taco.Index(path, 0)
+    q = qd[:m]
+    ids = torch.empty((m, w.k), dtype=torch.int64, device=qd.device)
+    dists = torch.empty((m, w.k), dtype=torch.float32, device=qd.device)
+    a, b = op["alpha"], op["beta"]
+    idx.search_sclinear(q, w.k, a, b, ids=ids, dists=dists, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    idx.search_sclinear(q, w.k, a, b, ids=ids, dists=dists, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    Sm = min(S, m)
+    rec = recall_at_k(ids[:Sm].cpu().numpy(), gt[w.k][:Sm], X, Q[:Sm], w.k)
+    idx.close()
+    return dict(qps=m / (ms * 1e-3), ms=ms, recall=rec, alpha=a, beta=b, queries=m,
+                note="exact per-subspace collisions over all n points, the floor(beta*n) highest "
+                     "SC-scores, FP32 re-rank; one call over the queries")
 
 
 def strip_point(p):
@@ -615,7 +643,7 @@ def main_uniform(args, taco, torch, w, plan, dev):
                 taco, torch, idx, pname,
                 lambda: idx.search(qd, w.k, a, b, ids=ids, dists=dists, stream=stream), stream, args, w, w.nq,
                 lambda: recall_at_k(ids[:S].cpu().numpy(), gt[w.k], X, Q[:S], w.k),
-                lambda prec: algorithmic_bytes(idx, qd, w, a, b, prec), tuned_cfg)
+                lambda prec: algorithmic_bytes(idx, qd, w, a, b, prec), tuned_cfg, b, w.k)
             p.update(alpha=a, beta=b, steps=args.steps)
             sweep.append(p)
             log(f"a={a} b={b} " + describe(pname, p) +
@@ -629,6 +657,14 @@ def main_uniform(args, taco, torch, w, plan, dev):
     op = operating_point(sweep)
     roofline = roofline_of(w.name, op, main_path)
     fp32_value = qps_at_recall(results["fp32"]) if "fp32" in results else None
+
+    sclinear = None
+    if not args.skip_sclinear:
+        sclinear = sclinear_leg(taco, torch, path, qd, Q, X, gt, S, w, op, stream, args.sclinear_queries)
+        sclinear["taco_qps_same_point"] = op["qps"]
+        sclinear["taco_path"] = main_path
+        sclinear["taco_speedup"] = op["qps"] / sclinear["qps"]
+        log("SC-Linear: " + json.dumps(sclinear))
 
     precision = None
     if not args.skip_precision_report:
@@ -679,7 +715,7 @@ def main_uniform(args, taco, torch, w, plan, dev):
         speedup_vs_fp32_plain=None if not (value and fp32_value) else value / fp32_value,
         paths={pn: dict(value=qps_at_recall(sw), points=[strip_point(p) for p in sw])
                for pn, sw in results.items()},
-        roofline=roofline, cpu_baseline=cpu, precision=precision, index_build=build)
+        roofline=roofline, cpu_baseline=cpu, precision=precision, index_build=build, sclinear=sclinear)
     return line
 
 
@@ -727,7 +763,7 @@ def main_batched(args, taco, torch, w, plan, dev):
                 taco, torch, idx, pname,
                 lambda: idx.search_batched(qd, ad, kd, k_max, b, ids=ids, dists=dists, stream=stream),
                 stream, args, w, w.nq, rec_fn,
-                lambda prec: algorithmic_bytes(idx, qd, w, None, b, prec, ad, kd, k_max), tuned_cfg)
+                lambda prec: algorithmic_bytes(idx, qd, w, None, b, prec, ad, kd, k_max), tuned_cfg, b, k_max)
             p.update(alpha=None, beta=b, steps=args.steps)
             sweep.append(p)
             log(f"b={b} " + describe(pname, p) +
@@ -797,9 +833,12 @@ def main_batched(args, taco, torch, w, plan, dev):
 # rocprofv3 summaries (run after a profiled bench; they read only its output)
 # ---------------------------------------------------------------------------
 
-_SHORT = (("k_count_select", "count_select"), ("k_list_select", "list_select"), ("k_select_level", "select_level"), ("k_select", "select"),
+_SHORT = (("k_count_select", "count_select"), ("k_count_codes", "count_codes"), ("k_cell_bitmap", "cell_bitmap"),
+          ("k_build_codes", "build_codes"), ("k_cost_order", "cost_order"), ("k_sub_dist", "sub_dist"),
+          ("k_sub_select", "sub_select"), ("k_sub_count", "sub_count"), ("k_list_select", "list_select"), ("k_select_level", "select_level"), ("k_select", "select"),
           ("k_rerank16", "rerank"), ("k_rerank8", "rerank"), ("k_rerank", "rerank"),
-          ("k_recheck_topk", "recheck"), ("k_topk", "topk"), ("k_probe", "probe"),
+          ("k_recheck_topk", "recheck"), ("k_stream_topk", "stream"), ("k_topk_queued", "stream"),
+          ("k_topk", "topk"), ("k_probe", "probe"),
           ("k_transform", "transform"), ("k_cdist_mfma", "cdist"), ("k_qstats", "cdist"),
           ("k_prep_cent", "prep_cent"), ("k_prep_bf16", "prep_bf16"), ("k_prep_u8", "prep_u8"), ("k_qbytes", "qbytes"),
           ("k_query_order", "query_order"), ("k_flatten_cells", "flatten"),
@@ -961,6 +1000,8 @@ def main():
                          "tuned, bf16, fp8; batched for zipf-1m-d256")
     ap.add_argument("--skip-precision-report", action="store_true")
     ap.add_argument("--skip-build", action="store_true", help="omit the GPU index-build leg")
+    ap.add_argument("--skip-sclinear", action="store_true", help="omit the SC-Linear leg")
+    ap.add_argument("--sclinear-queries", type=int, default=1000)
     ap.add_argument("--build-only", action="store_true",
                     help="run only the GPU index-build leg (and the oracle's build time unless "
                          "--skip-cpu-baseline); prints its own JSON line")

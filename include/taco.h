@@ -76,16 +76,20 @@ enum tc_select_rule { TC_RULE_PRINTED = 0, TC_RULE_PROSE = 1, TC_RULE_FIXED = 2 
 enum tc_option {
     TC_OPT_SELECT_RULE = 1, /* tc_select_rule; default TC_RULE_PRINTED                 */
     TC_OPT_MAX_BATCH = 2,   /* max queries per internal batch (>= 1); scratch is
-                               re-sized to fit; default: what 64 GiB of candidate
-                               scratch allows, at most 8192                          */
+                               re-sized to fit; default: what TC_OPT_SCRATCH_BYTES
+                               allows, at most 8192                                  */
     TC_OPT_TILE_IDS = 3,    /* ids per LDS counting tile: a multiple of 1024 whose
                                packed counts (4 bits per id when Ns <= 15, else 8)
                                fit the GPU's LDS per workgroup; default 64 KB of
                                counts (131072 ids as nibbles, 65536 as bytes)        */
     TC_OPT_PROFILE = 4,     /* 1: time every kernel launch with HIP events on the
                                search stream (read with tc_kernel_time); 0: off      */
-    TC_OPT_SCRATCH_BYTES = 5, /* candidate-scratch budget in bytes used to pick the
-                               batch size (>= 8*n); default 64 GiB                   */
+    TC_OPT_SCRATCH_BYTES = 5, /* scratch budget in bytes that picks the batch size
+                               Qb: per query n*b/8 bytes of packed counts (b = 4
+                               bits when Ns <= 15, else 8), 8*Ns*K of probed
+                               cells and 8*S bytes of candidate slots (12*S with
+                               a TC_BF16 or TC_U8 re-rank), S from
+                               TC_OPT_CANDIDATE_SLOTS; default 64 GiB                */
     TC_OPT_PRECISION = 6,   /* tc_precision of the re-rank; default TC_FP32         */
     TC_OPT_COUNT_MODE = 7,  /* tc_count_mode; default TC_COUNT_AUTO                  */
     TC_OPT_GRAPH = 8,       /* 1: capture each call's launch sequence into a HIP
@@ -100,9 +104,24 @@ enum tc_option {
                                distances that order the probe; default TC_CDIST_FP32 */
     TC_OPT_LIST_LEVEL = 12, /* list level of TC_COUNT_LIST: 1..Ns fixes it; 0 (the
                                default) adapts it on the device from batch to batch */
-    TC_OPT_TUNE_PRECISION = 13 /* 1 (default): the autotuners also choose the re-rank
+    TC_OPT_TUNE_PRECISION = 13, /* 1 (default): the autotuners also choose the re-rank
                                precision among TC_FP32, TC_BF16 and TC_U8; 0: they
                                keep the current TC_OPT_PRECISION                     */
+    TC_OPT_COUNT_QPW = 14,  /* queries each counting workgroup takes in turn for its
+                               tile (split and list forms): 1, 2, 4, 8, 16 or 32;
+                               default 1.  More means fewer, longer-lived workgroups
+                               where each tile holds few ids (large n, small alpha) */
+    TC_OPT_CANDIDATE_SLOTS = 15 /* candidate slots per query S that the batch size is
+                               planned for (>= 0; 0, the default: max(65536, n/128));
+                               at most n.  Alg 5 keeps the whole threshold level,
+                               so |C| is near R = floor(beta*n) but can reach n: a
+                               call gives each query cap = min(n, max(S, 4R,
+                               32*k_max)) slots from the pool of max(Qb*S, n) and
+                               runs min(Qb, pool / cap) queries per batch
+                               (tc_batch_capacity); a query with more than cap
+                               candidates takes a streamed FP32 re-rank and top-k
+                               over its collision counts instead (same results;
+                               kernel time "stream")                                 */
 };
 
 /* How collision counting and candidate selection are launched.
@@ -254,11 +273,12 @@ int tc_search_batched(tc_index *index, const float *queries, int64_t nq, const d
  * TC_OPT_CDIST_PRECISION, TC_OPT_GRAPH and TC_OPT_PROFILE say (the selection
  * rule, the tile width and the launch shapes apply), so its results equal
  * tc_search's with the default options.  Queries run in internal batches of
- * as many as fit the array, about TC_NOALLOC_SCRATCH_BYTES / (8n + n*b/8 +
- * 8*Ns*K) with b = 4 bits per count when Ns <= 15, else 8; with n = 1e6 and
- * Ns = 8 that is 29 queries per batch.  TC_EINVAL, with nothing enqueued,
- * when one query's scratch exceeds the array (n above about 28 million at
- * Ns = 8) and for every argument tc_search rejects.  All calls on one GPU
+ * as many as fit the array, about TC_NOALLOC_SCRATCH_BYTES / (8*max(R, 1) +
+ * n*b/8 + 8*Ns*K) with R = floor(beta*n) candidate slots per query and b = 4
+ * bits per count when Ns <= 15, else 8; with n = 1e6, Ns = 8, K = 4096 and
+ * beta = 0.01 that is 318 queries per batch.  TC_EINVAL, with nothing
+ * enqueued, when one query's scratch exceeds the array (a large n or beta)
+ * and for every argument tc_search rejects.  All calls on one GPU
  * share that GPU's array and find there what the previous call left (each
  * batch clears what must start at zero before use): calls that overlap on
  * one GPU, from any index, thread or stream, race and corrupt each other.
@@ -347,8 +367,9 @@ int tc_search_sclinear(tc_index *index, const float *queries, int64_t nq, int32_
 /*
  * Kernel timing, recorded while TC_OPT_PROFILE is 1.  Waits for the recorded
  * events, then reports for `kernel` -- one of "transform", "probe", "count",
- * "select", "rerank", "topk", "recheck", "count_select", "graph", "cdist" -- the summed duration in
- * milliseconds and the
+ * "select", "rerank", "topk", "recheck", "count_select", "graph", "cdist",
+ * "stream" (the streamed top-k of queries with more candidates than slots;
+ * see TC_OPT_CANDIDATE_SLOTS) -- the summed duration in milliseconds and the
  * number of launches since the last tc_profile_reset.  Host outputs.
  */
 int tc_kernel_time(tc_index *index, const char *kernel, double *total_ms, int64_t *launches);
@@ -362,8 +383,11 @@ int tc_profile_reset(tc_index *index);
  * search are then invalid).  Used by the tests; 0 in normal operation. */
 int tc_device_errors(tc_index *index, uint32_t *flags);
 
-/* Queries processed per internal batch with the current options (host out). */
-int tc_batch_capacity(const tc_index *index, int64_t *queries_per_batch);
+/* Queries processed per internal batch by a call with re-rank ratio beta
+ * (0 <= beta <= 1) and k_max results per query under the current options
+ * (host out); see TC_OPT_CANDIDATE_SLOTS.  TC_EINVAL for a NULL argument,
+ * beta outside [0, 1] or k_max outside [1, min(n, 1024)]. */
+int tc_batch_capacity(const tc_index *index, double beta, int32_t k_max, int64_t *queries_per_batch);
 
 /* Message for the calling thread's last failed call ("" if none). */
 const char *tc_last_error(void);

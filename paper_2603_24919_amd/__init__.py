@@ -24,7 +24,7 @@ __all__ = [
     "TC_OPT_CDIST_PRECISION", "TC_CDIST_FP32", "TC_CDIST_BF16", "TC_CDIST_FP8", "TC_U8",
     "tc_device_errors", "tc_search_batched", "tc_autotune", "tc_autotune_batched", "tc_search_noalloc",
     "tc_search_sclinear",
-    "TC_OPT_TUNE_PRECISION",
+    "TC_OPT_TUNE_PRECISION", "TC_OPT_COUNT_QPW", "TC_OPT_CANDIDATE_SLOTS",
     "TacoError", "TacoLibraryMissing", "lib_path", "load_library",
     "tc_load_index", "tc_free_index", "tc_index_info", "tc_set_option", "tc_search",
     "tc_search_debug", "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity",
@@ -40,11 +40,13 @@ TC_OPT_COUNT_MODE = 7
 TC_COUNT_AUTO, TC_COUNT_SPLIT, TC_COUNT_FUSED, TC_COUNT_LIST, TC_COUNT_CODES = 0, 1, 2, 3, 4
 TC_OPT_LIST_LEVEL = 12
 TC_OPT_TUNE_PRECISION = 13
+TC_OPT_COUNT_QPW = 14
+TC_OPT_CANDIDATE_SLOTS = 15
 TC_OPT_GRAPH, TC_OPT_PROBE_QPW, TC_OPT_RERANK_BLOCKS = 8, 9, 10
 TC_OPT_CDIST_PRECISION = 11
 TC_CDIST_FP32, TC_CDIST_BF16, TC_CDIST_FP8 = 0, 1, 2
 KERNELS = ("transform", "probe", "count", "select", "rerank", "topk", "recheck", "count_select",
-           "graph", "cdist")
+           "graph", "cdist", "stream")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libtaco_hip.so"
@@ -99,7 +101,7 @@ def load_library():
     L.tc_search_debug.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, vp, vp, C.POINTER(_StageDump)]
     L.tc_kernel_time.argtypes = [vp, C.c_char_p, C.POINTER(dbl), C.POINTER(i64)]
     L.tc_profile_reset.argtypes = [vp]
-    L.tc_batch_capacity.argtypes = [vp, C.POINTER(i64)]
+    L.tc_batch_capacity.argtypes = [vp, dbl, i32, C.POINTER(i64)]
     L.tc_device_errors.argtypes = [vp, C.POINTER(C.c_uint32)]
     L.tc_search_batched.argtypes = [vp, vp, i64, vp, vp, i32, dbl, vp, vp, vp]
     L.tc_autotune.argtypes = [vp, vp, i64, i32, dbl, dbl, vp, C.c_char_p, C.c_char_p, C.c_size_t]
@@ -448,9 +450,11 @@ def tc_device_errors(index) -> int:
     return v.value
 
 
-def tc_batch_capacity(index) -> int:
+def tc_batch_capacity(index, beta: float, k_max: int) -> int:
+    """Queries per internal batch of a call with re-rank ratio beta and
+    k_max results per query."""
     v = C.c_int64()
-    _check(load_library().tc_batch_capacity(index, C.byref(v)))
+    _check(load_library().tc_batch_capacity(index, float(beta), int(k_max), C.byref(v)))
     return v.value
 
 
@@ -535,8 +539,8 @@ class Index:
     def profile_reset(self):
         tc_profile_reset(self.handle)
 
-    def batch_capacity(self) -> int:
-        return tc_batch_capacity(self.handle)
+    def batch_capacity(self, beta: float, k_max: int) -> int:
+        return tc_batch_capacity(self.handle, beta, k_max)
 
     def device_errors(self) -> int:
         return tc_device_errors(self.handle)

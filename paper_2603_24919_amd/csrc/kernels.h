@@ -17,6 +17,7 @@ struct CountLaunch {
     const int32_t *flat;    // [nq][Ns*K] probed cells as rows j*K + cell (launch_flatten_cells)
     const uint32_t *ftot;   // [nq] number of probed cells
     const int32_t *perm = nullptr;  // [nq] order in which the count takes the queries, or null
+    int qpw = 1;                    // queries per count workgroup (split and list forms)
 };
 
 struct SelectLaunch {
@@ -31,6 +32,8 @@ struct SelectLaunch {
     int64_t *dump_hist;
     const uint32_t *redo = nullptr;  // select the queued queries of a list selection
     int redo_groups = 0;             // workgroups over them (grid y)
+    uint32_t *ovf = nullptr;         // [0] queries with more candidates than cap, [1 + i] the
+                                     // queue (for launch_stream_topk); null only for the fixed rule
 };
 
 // List selection (count form 1): ids with count >= the list level are listed
@@ -41,8 +44,9 @@ struct SelectLaunch {
 struct ListLaunch {
     int fixed;          // list level if > 0, else the adaptive level in *level
     uint32_t *level;    // device word
-    int64_t cap;
-    uint32_t *list;     // [nq][cap] listed words (count << shift | id) in per-tile ranges
+    int64_t cap;        // candidate slots per query
+    int64_t lcap;       // list slots per tile
+    uint32_t *list;     // [nq][T][lcap] listed words (count << shift | id), tile after tile
     int32_t *cand;
     uint32_t *count;
     uint32_t *tcount;   // [nq][T] entries listed per tile
@@ -101,9 +105,11 @@ hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint
                          hipStream_t st);
 size_t fused_lds_bytes(int W, int bits);
 hipError_t fused_max_blocks(int W, int bits, int Ns, int *blocks_per_cu);
+// sc: [nq][T][W*bits/32] words; receives the packed counts of the queries
+// whose candidates outgrow s.cap
 hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int NG, uint32_t *arrive,
                                uint32_t *err, uint32_t spin_limit, uint32_t *queue, const int32_t *order,
-                               hipStream_t st);
+                               uint32_t *sc, hipStream_t st);
 // queries by descending work (sum of retrieved over subspaces), into perm
 hipError_t launch_cost_order(const int64_t *retrieved, int nq, int Ns, int32_t *perm, hipStream_t st);
 int rerank_lanes_per_row(int d);
@@ -146,6 +152,19 @@ hipError_t launch_prep_bf16(const float *base, int64_t n, int d, const float *mu
 hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32_t *cand_count,
                        int64_t cap, int nq, int k, const int32_t *kq, int k_max, int64_t *ids,
                        float *dists, hipStream_t st);
+// Workgroups (id ranges) per query of launch_stream_topk; each leaves up to
+// k_max keys in the query's candidate slots, so cap >= STREAM_SPLIT * k_max.
+constexpr int STREAM_SPLIT = 32;
+// The queued queries of ovf (at most nq): FP32 re-rank and top-k of the ids
+// whose packed count in sc reaches Alg 5's threshold (from hist, R, rule),
+// into ids/dists [q][k_max], replacing what the top-k wrote for them; their
+// candidate slots (cand, cand_dist at stride cap, count 0 before) hold the
+// partial top-k lists.  hipErrorInvalidValue if cap < STREAM_SPLIT * k_max.
+hipError_t launch_stream_topk(const float *Q, int nq, int d, const float *base, const uint32_t *sc, int T, int W,
+                              int bits, const uint32_t *hist, int Ns, int64_t n, int64_t R, int rule,
+                              const uint32_t *ovf, int k, const int32_t *kq, int k_max, int64_t cap, int32_t *cand,
+                              float *cand_dist, uint32_t *cand_count, int64_t *ids, float *dists,
+                              hipStream_t st);
 
 // SC-Linear: per-subspace distances D [nq][Ns][n] of every point (canonical
 // FP32 chain on the transformed base T [n][M]), the A-th smallest

@@ -758,6 +758,8 @@ struct CountArgs {
     const int32_t *flat;     // [nq][Ns*K] probed cells as index rows j*K + cell (k_flatten_cells)
     const uint32_t *ftot;    // [nq] probed cells in all subspaces
     const int32_t *perm;     // [nq] query of each grid row (k_query_order), or null
+    int nq;                  // queries of the launch
+    int qpw;                 // queries per workgroup: grid row y takes rows y*qpw .. y*qpw+qpw-1
 };
 
 // LDS carve-up of k_count (dynamic part).  dl and sb are adjacent (the
@@ -957,7 +959,7 @@ __device__ __forceinline__ void walk_bump(const CountLds &L, const uint4 (&id)[C
 // the tile's "count >= v" totals to hsum[v] (hsum zeroed by the caller
 // before; complete after the caller's next barrier).
 template <int BITS, bool HI, bool TR = true>
-__device__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, uint32_t *hsum) {
+__device__ __forceinline__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, uint32_t *hsum) {
     const int vec = a.W * BITS / 128;  // 16-byte words of counts
     for (int i = threadIdx.x; i < vec; i += CT_BLOCK) reinterpret_cast<uint4 *>(L.cnt)[i] = make_uint4(0u, 0u, 0u, 0u);
     // (the counts are cleared before the barriers ahead of the walk)
@@ -1121,14 +1123,30 @@ struct SelectArgs {
     const uint32_t *hist;    // [nq][Ns+1], levels >= 1 filled by k_count
     int64_t R;               // floor(beta*n)
     int rule;                // 0 printed, 1 prose
-    int64_t cap;             // candidate slots per query (= n)
+    int64_t cap;             // candidate slots per query
     int32_t *cand;           // [nq][cap]
     uint32_t *cand_count;    // [nq]
     uint8_t *dump_sc;        // [nq][n] or null
     int32_t *dump_last;      // [nq] or null
     int64_t *dump_hist;      // [nq][Ns+1] or null
     const uint32_t *redo;    // null: query blockIdx.y; else the queue of ListArgs::redo
+    uint32_t *ovf;           // [0] queries whose candidates outgrow cap, [1 + i] the queue
 };
+
+// Ids scoring at least `last` (every id when last <= 0).
+__device__ __forceinline__ int64_t count_at_least(const uint32_t *h, int Ns, int64_t n, int last) {
+    if (last <= 0) return n;
+    int64_t c = 0;
+    for (int v = last; v <= Ns; v++) c += h[v];
+    return c;
+}
+
+// Alg 5 keeps the whole threshold level, so |C| = S(last) can exceed R and
+// the call's cap slots: such a query is queued for k_stream_topk, which
+// needs no slots.  The fixed-budget rule takes exactly min(R, ...) <= cap.
+__device__ __forceinline__ bool outgrows(const SelectArgs &sa, const uint32_t *h, int Ns, int64_t n, int last) {
+    return sa.rule != 2 && count_at_least(h, Ns, n, last) > sa.cap;
+}
 
 // Alg 5's threshold (Section 4.3) from the level histogram (level 0 = n
 // minus the others).  With S(v) the number of points scoring at least v,
@@ -1167,19 +1185,21 @@ __device__ __forceinline__ void dump_threshold(int32_t *dump_last, int64_t *dump
 }
 
 // List selection.  With a list level Lv, counting also lists every id of
-// the tile whose count reaches Lv in the tile's own range of the query's
-// list slots, [tW, tW + its entries) (a tile lists at most its own ids, so
-// the range stays below n), as one word count << shift | id (shift = 31 -
+// the tile whose count reaches Lv in the tile's own lcap slots of the
+// query's list (the query's packed-count row, idle in this form: lcap =
+// W*BITS/32 words per tile), as one word count << shift | id (shift = 31 -
 // bit width of Ns; the loader's bound Ns*n < 2^30 leaves room for both),
-// the number of its entries in tcount[q][t], and adds the levels of the
-// listed ids to hist[q] (exact for every level >= Lv).  Alg 5's threshold `last` follows from
-// the level histogram alone, in a launch of its own once every tile is
-// counted: when last >= Lv the candidates are exactly the listed ids with
-// count >= last (filtered in place); queries with last < Lv are queued,
-// counted again with their packed counts stored (CT_REDO) and take the
-// streaming selection.  The level is fixed, or adapted on the device
-// from batch to batch: down when more than 1/16 of a batch was queued, up
-// when at least 63/64 of it had last > Lv.  Results never depend on it.
+// the number of such ids in tcount[q][t] (also past lcap), and adds the
+// levels of the listed ids to hist[q] (exact for every level >= Lv).
+// Alg 5's threshold `last` follows from the level histogram alone, in a
+// launch of its own once every tile is counted: when last >= Lv and no
+// tile's list overflowed, the candidates are exactly the listed ids with
+// count >= last; other queries are queued, counted again with their packed
+// counts stored (CT_REDO) and take the streaming selection.  The level is
+// fixed, or adapted on the device from batch to batch: up when more than
+// 1/16 of a batch overflowed a tile's list, else down when more than 1/16
+// was queued for last < Lv, up when at least 63/64 had last > Lv.  Results
+// never depend on it.
 enum CountForm { CT_STORE = 0, CT_LIST = 1, CT_REDO = 2 };
 
 struct ListArgs {
@@ -1187,13 +1207,15 @@ struct ListArgs {
     uint32_t *level;    // adaptive level, kept on the device across batches
     int shift;          // a listed word is count << shift | id
     int nq;             // queries in the batch
-    int64_t cap;        // slots per query
-    uint32_t *list;     // [nq][cap] the lists
+    int64_t cap;        // candidate slots per query (>= floor(beta*n) or n)
+    int64_t lcap;       // list slots per tile
+    uint32_t *list;     // [nq][T][lcap] the lists, tile after tile
     int32_t *cand;      // [nq][cap] the candidates
     uint32_t *count;    // [nq] candidate counts
-    uint32_t *tcount;   // [nq][T] entries listed by each tile
+    uint32_t *tcount;   // [nq][T] ids with count >= the list level in each tile
     int T, W;           // tiles per query, ids per tile
-    uint32_t *redo;     // [0] queued queries, [1] queries with last > level, [2 + i] the queue
+    uint32_t *redo;     // [0] queued queries, [1] queries with last > level, [2] queued
+                        // because a tile's list overflowed, [3 + i] the queue
     int64_t R;          // floor(beta*n)
     int rule;           // Alg 5 reading
     int redo_hist;      // the recount adds the queued queries' level counts
@@ -1221,8 +1243,10 @@ __device__ __forceinline__ uint32_t flag_counts(uint32_t w, uint32_t lv) {
                     : (h & ((t + (16u - lv) * 0x11111111u) & 0x88888888u));
 }
 
-// Lists the tile's ids with count >= lv in the tile's range of the query's
-// list, and tallies their levels in lsum.  Each thread tests the 16 packed
+// Lists the tile's ids with count >= lv in the tile's lcap slots of the
+// query's list, and tallies their levels in lsum; tcount receives how many
+// there are, also when more than lcap (then only the first lcap are stored
+// and the selection queues the query for the recount).  Each thread tests the 16 packed
 // words it owns per pass (four
 // 16-byte words), keeping only the number of flagged ids and a 16-bit mask
 // of the words holding any; a prefix sum over the workgroup places them (no
@@ -1236,8 +1260,9 @@ __device__ __forceinline__ void list_tile(const ListArgs &la, const uint32_t *cn
     constexpr uint32_t CMASK = (1u << BITS) - 1u;
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     const u32x4 *c4v = reinterpret_cast<const u32x4 *>(cnt);
-    uint32_t *dst = la.list + static_cast<int64_t>(q) * la.cap;
+    uint32_t *dst = la.list + (static_cast<int64_t>(q) * la.T + t) * la.lcap;
     const uint32_t base = static_cast<uint32_t>(t) * static_cast<uint32_t>(W);
+    const uint32_t lim = static_cast<uint32_t>(la.lcap);
     uint32_t run = 0u;  // entries of this tile placed so far
     for (int i0 = 0; i0 < vec; i0 += 4 * CT_BLOCK) {
         uint32_t c = 0u, nz = 0u;
@@ -1261,7 +1286,7 @@ __device__ __forceinline__ void list_tile(const ListArgs &la, const uint32_t *cn
         // its offset, the sum of all the pass's total
         const uint32_t xt = lane < CT_WAVES ? wsum[lane] : 0u;
         const uint32_t before = wave_sum_u32(lane < wave ? xt : 0u), tot = wave_sum_u32(xt);
-        uint32_t j = base + run + before + inc - c;
+        uint32_t j = run + before + inc - c;
         run += tot;
         while (nz != 0u) {
             const int x = __builtin_ctz(nz);
@@ -1276,7 +1301,8 @@ __device__ __forceinline__ void list_tile(const ListArgs &la, const uint32_t *cn
                 mm &= mm - 1u;
                 const uint32_t cv = (wv >> (BITS * sub)) & CMASK;
                 atomicAdd(&lsum[cv], 1u);
-                dst[j++] = (cv << la.shift) | (id0 + static_cast<uint32_t>(sub));
+                if (j < lim) dst[j] = (cv << la.shift) | (id0 + static_cast<uint32_t>(sub));
+                j++;
             } while (mm != 0u);
         }
         if (i0 + 4 * CT_BLOCK < vec) __syncthreads();  // wsum is rewritten by the next pass
@@ -1293,7 +1319,7 @@ __device__ __forceinline__ void list_tile(const ListArgs &la, const uint32_t *cn
 // when sc is given.  CT_REDO: for each queued query, stores the packed
 // counts and, with la.redo_hist, adds its level counts; workgroup (0, 0)
 // also moves the adaptive level.
-template <int BITS, bool HI, int MODE, bool TR>
+template <int BITS, bool HI, int MODE, bool TR, bool MULTI>
 __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__restrict__ hist,
                                                    uint4 *__restrict__ sc, ListArgs la) {
     // no static LDS: the packed counts start at address 0, so an increment's
@@ -1306,16 +1332,22 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
     const int vec = a.W * BITS / 128;  // 16-byte words per tile
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
     const u32x4 *c4v = reinterpret_cast<const u32x4 *>(L.cnt);
-    uint32_t nrun = 1u, f0 = 0u, fstep = 1u;
+    // MULTI: a.qpw queries per workgroup, one after the other (fewer,
+    // longer-lived workgroups where tiles hold few ids each); otherwise one
+    uint32_t nrun = MULTI ? static_cast<uint32_t>(a.qpw) : 1u, f0 = 0u, fstep = 1u;
     if (MODE == CT_REDO) {
         nrun = la.redo[0];
         f0 = blockIdx.y;
         fstep = gridDim.y;
         if (la.fixed == 0 && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
-            const uint32_t lv = *la.level, nf = la.redo[0], na = la.redo[1];
+            const uint32_t lv = *la.level, nf = la.redo[0], na = la.redo[1], no = la.redo[2];
             const uint32_t nq = static_cast<uint32_t>(la.nq);
             uint32_t nl = lv;
-            if (nf * 16u > nq && lv > 1u)
+            // lists overflowing: list fewer ids; thresholds below the level:
+            // list more; almost all thresholds above it: list fewer
+            if (no * 16u > nq && lv < static_cast<uint32_t>(a.Ns))
+                nl = lv + 1u;
+            else if ((nf - no) * 16u > nq && lv > 1u)
                 nl = lv - 1u;
             else if (na * 64u >= nq * 63u && lv < static_cast<uint32_t>(a.Ns))
                 nl = lv + 1u;
@@ -1323,8 +1355,10 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
         }
     }
     for (uint32_t f = f0; f < nrun; f += fstep) {
-        const int q = MODE == CT_REDO ? static_cast<int>(la.redo[2 + f])
-                                      : (a.perm ? a.perm[blockIdx.y] : static_cast<int>(blockIdx.y));
+        const int row = MULTI ? static_cast<int>(blockIdx.y) * a.qpw + static_cast<int>(f)
+                              : static_cast<int>(blockIdx.y);
+        if (MULTI && row >= a.nq) break;
+        const int q = MODE == CT_REDO ? static_cast<int>(la.redo[3 + f]) : (a.perm ? a.perm[row] : row);
         if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
         if (MODE == CT_LIST && threadIdx.x < 17) lsum[threadIdx.x] = 0u;
         count_tile<BITS, HI, TR>(a, q, t, L, hsum);
@@ -1352,7 +1386,7 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
                     atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], c);
             }
         }
-        if (MODE == CT_REDO) __syncthreads();
+        if (MODE == CT_REDO || MULTI) __syncthreads();  // the next query clears the counts and sums read above
     }
 }
 
@@ -1381,7 +1415,7 @@ __global__ __launch_bounds__(SEL_BLOCK) void k_select(SelectArgs sa, int Ns, int
     }
     const uint32_t nrun = sa.redo[0];
     for (uint32_t f = blockIdx.y; f < nrun; f += gridDim.y)
-        select_query<BITS>(sa, Ns, n, words4, sc, static_cast<int>(sa.redo[2 + f]), stage_all);
+        select_query<BITS>(sa, Ns, n, words4, sc, static_cast<int>(sa.redo[3 + f]), stage_all);
 }
 
 template <int BITS>
@@ -1391,7 +1425,12 @@ __device__ __forceinline__ void select_query(const SelectArgs &sa, int Ns, int64
     constexpr int PER_VEC = 128 / BITS;   // ids per 16-byte word
     const uint32_t *h = sa.hist + static_cast<int64_t>(q) * (Ns + 1);
     const int last = select_threshold(h, Ns, n, sa.R, sa.rule);
-    if (blockIdx.x == 0 && threadIdx.x == 0) dump_threshold(sa.dump_last, sa.dump_hist, q, Ns, n, h, last);
+    const bool over = outgrows(sa, h, Ns, n, last);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        dump_threshold(sa.dump_last, sa.dump_hist, q, Ns, n, h, last);
+        if (over) sa.ovf[1 + atomicAdd(&sa.ovf[0], 1u)] = static_cast<uint32_t>(q);
+    }
+    if (over && !sa.dump_sc) return;  // (with stage dumps the pass still dumps the counts)
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     int32_t *cq = sa.cand + static_cast<int64_t>(q) * sa.cap;
     uint32_t *stage = stage_all + wave * CT_STAGE;
@@ -1430,7 +1469,7 @@ __device__ __forceinline__ void select_query(const SelectArgs &sa, int Ns, int64
 #pragma unroll
             for (int c = 0; c < 4; c++) {
                 ge_masks<BITS>(wv[c], lv, m[2 * c], m[2 * c + 1]);
-                if (!in) m[2 * c] = m[2 * c + 1] = 0u;
+                if (!in || over) m[2 * c] = m[2 * c + 1] = 0u;
             }
             if (in && id0 + PER_VEC > n) {
                 // the last word of the last tile: ids past n are padding
@@ -1547,9 +1586,10 @@ __global__ __launch_bounds__(SL_BLOCK) void k_select_level(SelectArgs sa, int Ns
 // Alg 5 on a query's lists: the threshold from the histogram's levels >=
 // the list level, scanned from the top (where this scan stops, the full
 // scan stops; if it passes the list level, last < it), then either the
-// queue (last < list level; with redo_hist its histogram row is cleared for
-// the recount) or the candidates: the listed ids with count >= last, moved
-// from the tiles' list ranges to the candidate slots.  Each wavefront takes
+// queue (last < list level, or a tile listed more ids than its lcap slots;
+// with redo_hist its histogram row is cleared for the recount) or the
+// candidates: the listed ids with count >= last, moved from the tiles' list
+// ranges to the candidate slots.  Each wavefront takes
 // whole tiles.  With toff and tlev (and at most LS_TMAX tiles) the
 // candidates are grouped by tile, in list order inside a tile: each tile's
 // count is the sum of its listed ids' levels >= last (tlev, from the count
@@ -1567,7 +1607,7 @@ constexpr uint32_t TOFF_NONE = 0xffffffffu;
 __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t *__restrict__ hist, int Ns,
                                                           int64_t n) {
     __shared__ int s_last;
-    __shared__ uint32_t s_out;
+    __shared__ uint32_t s_out, s_over;
     __shared__ uint32_t s_tc[LS_TMAX + 1];
     const int q = blockIdx.x;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -1575,11 +1615,20 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
     const bool grouped = la.toff != nullptr && la.tlev != nullptr && la.T <= LS_TMAX;
     uint32_t *tq = la.toff ? la.toff + static_cast<int64_t>(q) * (la.T + 1) : nullptr;
     uint32_t *h = hist + static_cast<int64_t>(q) * (Ns + 1);
+    if (threadIdx.x == 0) s_over = 0u;
+    __syncthreads();
+    {
+        uint32_t over = 0u;
+        for (int t = threadIdx.x; t < la.T; t += LS_BLOCK)
+            over |= la.tcount[static_cast<int64_t>(q) * la.T + t] > static_cast<uint64_t>(la.lcap) ? 1u : 0u;
+        if (over) s_over = 1u;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         // the highest listed level (>= lv) exceeding the budget, as in
         // select_threshold; lv - 1 when none does (the threshold is lower)
         int last = lv - 1;
-        int64_t S = 0;
+        int64_t S = 0;  // S(last) at the break
         for (int v = Ns; v >= lv; v--) {
             const int64_t hv = h[v];
             S += hv;
@@ -1592,23 +1641,28 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
             // stage dumps: the histogram is complete here; the threshold is
             // the full scan's (equal to last whenever last >= lv)
             dump_threshold(la.dump_last, la.dump_hist, q, Ns, n, h, select_threshold(h, Ns, n, la.R, la.rule));
-        if (tq && (last < lv || !grouped)) tq[0] = TOFF_NONE;
-        if (last < lv) {
+        if (last > lv) atomicAdd(&la.redo[1], 1u);
+        // a tile's list overflowed, or more candidates than slots (the
+        // recount's selection queues those for k_stream_topk)
+        const bool lover = last >= lv && s_over != 0u;
+        const bool over = lover || (last >= lv && S > la.cap);
+        if (lover) atomicAdd(&la.redo[2], 1u);  // (moves the adaptive level up)
+        if (last < lv || over) {
             const uint32_t f = atomicAdd(&la.redo[0], 1u);
-            la.redo[2 + f] = static_cast<uint32_t>(q);
+            la.redo[3 + f] = static_cast<uint32_t>(q);
             la.count[q] = 0u;
             if (la.redo_hist)
                 for (int v = 1; v <= Ns; v++) h[v] = 0u;
-        } else if (last > lv) {
-            atomicAdd(&la.redo[1], 1u);
+            last = -1;  // queued
         }
+        if (tq && (last < lv || !grouped)) tq[0] = TOFF_NONE;
         s_last = last;
         s_out = 0u;
     }
     __syncthreads();
     const int last = s_last;
     if (last < lv) return;
-    const uint32_t *ls = la.list + static_cast<int64_t>(q) * la.cap;
+    const uint32_t *ls = la.list + static_cast<int64_t>(q) * la.T * la.lcap;
     int32_t *cq = la.cand + static_cast<int64_t>(q) * la.cap;
     const uint32_t idmask = (1u << la.shift) - 1u, lu = static_cast<uint32_t>(last);
     const uint64_t below = lanes_below(lane);
@@ -1638,7 +1692,7 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
         // pass 2: each tile's candidates from its first slot, in list order
         for (int t = wave; t < la.T; t += LS_BLOCK / WAVE) {
             const uint32_t nt = la.tcount[static_cast<int64_t>(q) * la.T + t];
-            const uint32_t *et = ls + static_cast<int64_t>(t) * la.W;
+            const uint32_t *et = ls + static_cast<int64_t>(t) * la.lcap;
             uint32_t base = s_tc[t];
             for (uint32_t b0 = 0; b0 < nt; b0 += WAVE * LS_UNROLL) {
                 uint32_t v[LS_UNROLL];
@@ -1661,7 +1715,7 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
     }
     for (int t = wave; t < la.T; t += LS_BLOCK / WAVE) {
         const uint32_t nt = la.tcount[static_cast<int64_t>(q) * la.T + t];
-        const uint32_t *et = ls + static_cast<int64_t>(t) * la.W;
+        const uint32_t *et = ls + static_cast<int64_t>(t) * la.lcap;
         for (uint32_t b0 = 0; b0 < nt; b0 += WAVE * LS_UNROLL) {
             uint32_t v[LS_UNROLL];
 #pragma unroll
@@ -1732,6 +1786,7 @@ struct FuseArgs {
     uint32_t spin_limit;
     uint32_t *queue;      // [T] per-tile dequeue counters, zero before the launch
     const int32_t *order; // [nq] the order queries are handed out in, or null (0, 1, ...)
+    uint4 *sc;            // [nq][T][W*BITS/128] packed counts of queries that outgrow cap
 };
 
 template <int BITS, bool HI>
@@ -1741,7 +1796,7 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
     const CountLds L = carve<BITS>(lds_raw, a.W);
     __shared__ uint32_t hsum[18];
     __shared__ uint32_t hq[17];
-    __shared__ int s_last;
+    __shared__ int s_last, s_over;
     // candidate staging reuses the slice table (idle during compaction):
     // CT_FSTAGE slots per wavefront
     constexpr int CT_FSTAGE = 2 * CT_CHUNK / CT_WAVES >= 128 ? 128 : 64;
@@ -1784,7 +1839,9 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
             for (int v = 1; v <= a.Ns; v++)
                 hq[v] = __hip_atomic_load(&hg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_last = select_threshold(hq, a.Ns, a.n, sa.R, sa.rule);
+            s_over = outgrows(sa, hq, a.Ns, a.n, s_last) ? 1 : 0;
             if (t == 0) {
+                if (s_over) sa.ovf[1 + atomicAdd(&sa.ovf[0], 1u)] = static_cast<uint32_t>(q);
                 if (sa.dump_last) sa.dump_last[q] = s_last;
                 if (sa.dump_hist) {
                     int64_t above0 = 0;
@@ -1797,6 +1854,17 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
         }
         __syncthreads();
         const int last = s_last;
+        const bool over = s_over != 0;
+        if (over) {
+            // the tile's counts go to HBM for k_stream_topk
+            const int vec = a.W * BITS / 128;
+            uint4 *dst = f.sc + (static_cast<int64_t>(q) * a.T + t) * vec;
+            for (int i = threadIdx.x; i < vec; i += CT_BLOCK) dst[i] = reinterpret_cast<const uint4 *>(L.cnt)[i];
+            if (!sa.dump_sc) {
+                __syncthreads();  // the next query's counting rewrites L.cnt
+                continue;
+            }
+        }
         const uint32_t lv = static_cast<uint32_t>(last > 0 ? last : 0);
         int32_t *cq = sa.cand + static_cast<int64_t>(q) * sa.cap;
         uint32_t *stage = L.dl + wave * CT_FSTAGE;
@@ -1815,7 +1883,7 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
             }
             uint32_t m[2];
             ge_masks<BITS>(w, lv, m[0], m[1]);
-            if (!in) m[0] = m[1] = 0u;
+            if (!in || over) m[0] = m[1] = 0u;
             if (in && i * PER_WORD + PER_WORD > tile_n) {
                 // ids past n in the last tile are padding
                 for (int i2 = 0; i2 < 2; i2++)
@@ -2620,6 +2688,164 @@ __global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
                 cand_count[q], kq ? kq[q] : k_all, k_max, ids_out, d_out);
 }
 
+// ---------------------------------------------------------------------------
+// Queries whose candidate set outgrows the call's slots (Alg 5 keeps the
+// whole threshold level, so |C| = S(last) can exceed R): the FP32 re-rank
+// straight from the packed counts, and the top-k in two steps, with no more
+// than ST_SPLIT * k_max slots per query (which the call's cap leaves).  The
+// ids of each queued query are split into ST_SPLIT ranges, one workgroup
+// each.  A workgroup scans its range ST_WORDS count words at a time, lists
+// the chunk's candidates (count >= last, id < n) in LDS, computes their
+// distances with the re-rank's lane groups (row_partial32 and group_sum: the
+// bits of k_rerank and k_recheck_topk), and keeps every key (distance bits,
+// id) below the running k-th smallest in a buffer that a bitonic sort cuts
+// back to k keys whenever it holds more than TOPK_MAX.  Its k smallest go to
+// the query's candidate slots (positions reserved on cand_count[q]); the
+// top-k of those (k_topk_queued) replaces the query's results, written
+// before from its empty candidate list.  grid (ST_SPLIT, any), block BLOCK,
+// dynamic LDS d floats; ovf: [0] queued queries, [1 + i] the queue.
+// ---------------------------------------------------------------------------
+constexpr int ST_SPLIT = STREAM_SPLIT; // workgroups (id ranges) per queued query
+constexpr int ST_WORDS = BLOCK;        // 32-bit count words per chunk, one per thread
+constexpr int ST_LIST = BLOCK * 8;     // candidates per chunk, at most
+constexpr int ST_BUF = 4096;           // >= TOPK_MAX + ST_LIST, a power of two
+static_assert(TOPK_MAX + ST_LIST <= ST_BUF, "the key buffer must hold a cut plus a chunk");
+
+// Ascending bitonic sort of a[0, P) in LDS, P a power of two; every thread
+// of the workgroup calls it.
+__device__ __forceinline__ void lds_bitonic_u64(uint64_t *a, int P) {
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P; i += BLOCK) {
+                const int pj = i ^ stride;
+                if (pj > i) {
+                    const bool up = (i & size) == 0;
+                    const uint64_t x = a[i], y = a[pj];
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[pj] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Sorts the nb keys of buf (padding to a power of two with ~0) and keeps
+// the first min(nb, k); returns how many are kept.
+__device__ __forceinline__ uint32_t cut_keys(uint64_t *buf, uint32_t nb, int k) {
+    int P = 1;
+    while (P < static_cast<int>(nb)) P <<= 1;
+    for (int i = static_cast<int>(nb) + threadIdx.x; i < P; i += BLOCK) buf[i] = ~0ull;
+    __syncthreads();
+    lds_bitonic_u64(buf, P);
+    return min(nb, static_cast<uint32_t>(k));
+}
+
+template <int LPR, bool VEC4, int BITS>
+__global__ __launch_bounds__(BLOCK) void k_stream_topk(const float *__restrict__ Q, int d,
+                                                       const float *__restrict__ base,
+                                                       const uint32_t *__restrict__ sc, int64_t row_words,
+                                                       const uint32_t *__restrict__ hist, int Ns, int64_t n,
+                                                       int64_t R, int rule, const uint32_t *__restrict__ ovf,
+                                                       int k_all, const int32_t *__restrict__ kq, int64_t cap,
+                                                       int32_t *__restrict__ cand, float *__restrict__ cand_dist,
+                                                       uint32_t *__restrict__ cand_count) {
+    extern __shared__ float qs[];
+    __shared__ uint32_t list[ST_LIST];
+    __shared__ uint64_t buf[ST_BUF];
+    __shared__ uint32_t s_nl, s_nb, s_at;
+    __shared__ int s_last;
+    constexpr int PER_WORD = 32 / BITS;
+    constexpr uint32_t CMASK = (1u << BITS) - 1u;
+    constexpr int RPW = WAVE / LPR;  // rows per wavefront per step
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int sub = lane / LPR, li = lane % LPR;
+    const int64_t nwords = (n + PER_WORD - 1) / PER_WORD;
+    const int64_t span = (nwords + gridDim.x - 1) / gridDim.x;
+    const int64_t w_lo = static_cast<int64_t>(blockIdx.x) * span;
+    const int64_t w_hi = min(nwords, w_lo + span);
+    const uint32_t nov = ovf[0];
+    for (uint32_t f = blockIdx.y; f < nov; f += gridDim.y) {
+        const int q = static_cast<int>(ovf[1 + f]);
+        const int k = kq ? kq[q] : k_all;
+        for (int t = threadIdx.x; t < d; t += BLOCK) qs[t] = Q[static_cast<int64_t>(q) * d + t];
+        if (threadIdx.x == 0) {
+            s_last = select_threshold(hist + static_cast<int64_t>(q) * (Ns + 1), Ns, n, R, rule);
+            s_nb = 0u;
+        }
+        __syncthreads();
+        const uint32_t lv = static_cast<uint32_t>(s_last > 0 ? s_last : 0);  // level 0: every id
+        const uint32_t *row = sc + static_cast<int64_t>(q) * row_words;
+        uint64_t bound = ~0ull;  // the k-th smallest key kept so far (after a cut)
+        for (int64_t g0 = w_lo; g0 < w_hi; g0 += ST_WORDS) {
+            if (threadIdx.x == 0) s_nl = 0u;
+            __syncthreads();
+            const int64_t g = g0 + threadIdx.x;
+            if (g < w_hi) {
+                const uint32_t w = row[g];
+#pragma unroll
+                for (int j = 0; j < PER_WORD; j++) {
+                    const int64_t id = g * PER_WORD + j;
+                    if (id < n && ((w >> (BITS * j)) & CMASK) >= lv)
+                        list[atomicAdd(&s_nl, 1u)] = static_cast<uint32_t>(id);
+                }
+            }
+            __syncthreads();
+            const uint32_t nl = s_nl;
+            // every lane of a row group runs the same iterations (group_sum)
+            for (uint32_t i0 = static_cast<uint32_t>(wave * RPW); i0 < nl; i0 += WAVES * RPW) {
+                const uint32_t i = i0 + static_cast<uint32_t>(sub);
+                const bool ok = i < nl;
+                const int64_t id = ok ? static_cast<int64_t>(list[i]) : 0;
+                const float acc = group_sum<LPR>(row_partial32<LPR, VEC4>(qs, base + id * d, d, li));
+                if (ok && li == 0) {
+                    const uint64_t key = (static_cast<uint64_t>(__float_as_uint(acc)) << 32) |
+                                         static_cast<uint32_t>(id);
+                    if (key < bound) buf[atomicAdd(&s_nb, 1u)] = key;
+                }
+            }
+            __syncthreads();
+            const uint32_t nb = s_nb;
+            if (nb > static_cast<uint32_t>(TOPK_MAX)) {
+                const uint32_t kept = cut_keys(buf, nb, k);
+                bound = kept == static_cast<uint32_t>(k) ? buf[k - 1] : ~0ull;
+                __syncthreads();
+                if (threadIdx.x == 0) s_nb = kept;
+            }
+        }
+        __syncthreads();
+        const uint32_t m = cut_keys(buf, s_nb, k);
+        if (threadIdx.x == 0) s_at = m ? atomicAdd(&cand_count[q], m) : 0u;
+        __syncthreads();
+        int32_t *cq = cand + static_cast<int64_t>(q) * cap + s_at;
+        float *dq = cand_dist + static_cast<int64_t>(q) * cap + s_at;
+        for (uint32_t i = threadIdx.x; i < m; i += BLOCK) {
+            cq[i] = static_cast<int32_t>(static_cast<uint32_t>(buf[i] & 0xffffffffu));
+            dq[i] = __uint_as_float(static_cast<uint32_t>(buf[i] >> 32));
+        }
+        __syncthreads();  // qs, buf, s_nb and s_at are rewritten for the next query
+    }
+}
+
+// The top-k of the queued queries of ovf from their candidate slots (the
+// workgroups' partial top-k of k_stream_topk).  grid (any), block 256.
+__global__ __launch_bounds__(256) void k_topk_queued(const int32_t *__restrict__ cand,
+                                                     const float *__restrict__ cand_dist,
+                                                     const uint32_t *__restrict__ cand_count, int64_t cap,
+                                                     const uint32_t *__restrict__ ovf, int k_all,
+                                                     const int32_t *__restrict__ kq, int k_max,
+                                                     int64_t *__restrict__ ids_out, float *__restrict__ d_out) {
+    const uint32_t nov = ovf[0];
+    for (uint32_t f = blockIdx.x; f < nov; f += gridDim.x) {
+        const int q = static_cast<int>(ovf[1 + f]);
+        topk_select(q, cand + static_cast<int64_t>(q) * cap, cand_dist + static_cast<int64_t>(q) * cap,
+                    cand_count[q], kq ? kq[q] : k_all, k_max, ids_out, d_out);
+        __syncthreads();  // topk_select's shared state is reused for the next query
+    }
+}
+
 // FP32 re-check of the rows whose lower bound reaches the query's tau (the
 // k-th smallest upper bound), then the top-k of those rows, one workgroup per
 // query.  Chunks of RC_CHUNK candidates are tested (eight loads per thread in
@@ -2812,19 +3038,22 @@ size_t count_lds_bytes(int W, int bits) { return count_lds_size(W, bits); }
 
 // Instances: nibble counts up to 8 levels (Ns <= 8), nibbles with up to
 // 15, bytes (Ns = 16).
-template <int MODE, bool TR>
+template <int MODE, bool TR, bool MULTI>
 static const void *count_kernel_form(int bits, int Ns) {
-    if (bits == 8) return reinterpret_cast<const void *>(k_count<8, true, MODE, TR>);
-    return Ns > 8 ? reinterpret_cast<const void *>(k_count<4, true, MODE, TR>)
-                  : reinterpret_cast<const void *>(k_count<4, false, MODE, TR>);
+    if (bits == 8) return reinterpret_cast<const void *>(k_count<8, true, MODE, TR, MULTI>);
+    return Ns > 8 ? reinterpret_cast<const void *>(k_count<4, true, MODE, TR, MULTI>)
+                  : reinterpret_cast<const void *>(k_count<4, false, MODE, TR, MULTI>);
 }
 
-// form 3: the list form with the level transitions
+// form 3: the list form with the level transitions; 4 and 5: the list and
+// store forms taking several queries per workgroup
 static const void *count_kernel(int bits, int Ns, int form) {
-    if (form == CT_LIST) return count_kernel_form<CT_LIST, false>(bits, Ns);
-    if (form == 3) return count_kernel_form<CT_LIST, true>(bits, Ns);
-    if (form == CT_REDO) return count_kernel_form<CT_REDO, true>(bits, Ns);
-    return count_kernel_form<CT_STORE, true>(bits, Ns);
+    if (form == CT_LIST) return count_kernel_form<CT_LIST, false, false>(bits, Ns);
+    if (form == 3) return count_kernel_form<CT_LIST, true, false>(bits, Ns);
+    if (form == 4) return count_kernel_form<CT_LIST, false, true>(bits, Ns);
+    if (form == 5) return count_kernel_form<CT_STORE, true, true>(bits, Ns);
+    if (form == CT_REDO) return count_kernel_form<CT_REDO, true, false>(bits, Ns);
+    return count_kernel_form<CT_STORE, true, false>(bits, Ns);
 }
 
 static const void *count_select_kernel(int bits, int Ns) {
@@ -2835,7 +3064,7 @@ static const void *count_select_kernel(int bits, int Ns) {
 
 hipError_t prepare_count_kernels(int W, int bits, int Ns) {
     const int bytes = static_cast<int>(count_lds_size(W, bits));
-    for (int form : {0, 1, 2, 3}) {
+    for (int form : {0, 1, 2, 3, 4, 5}) {
         hipError_t e = hipFuncSetAttribute(count_kernel(bits, Ns, form),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -2853,7 +3082,8 @@ static ListArgs list_args(const CountLaunch &c, const ListLaunch *l) {
     ListArgs la{};
     la.nq = c.nq;
     if (l)
-        la = ListArgs{l->fixed, l->level, list_shift(c.Ns), c.nq, l->cap, l->list, l->cand, l->count, l->tcount,
+        la = ListArgs{l->fixed, l->level, list_shift(c.Ns), c.nq, l->cap, l->lcap, l->list, l->cand, l->count,
+                      l->tcount,
                       c.T, c.W, l->redo, l->R, l->rule, l->trans ? 0 : 1, l->dump_last, l->dump_hist,
                       l->toff, l->tlev};
     return la;
@@ -2867,28 +3097,38 @@ hipError_t launch_list_select(const CountLaunch &c, const ListLaunch &l, uint32_
 hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, int form, const ListLaunch *l,
                         hipStream_t st) {
     if (form != CT_STORE && !l) return hipErrorInvalidValue;
-    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.flat, c.ftot, c.perm};
+    // several queries per workgroup for the list and split forms (not with
+    // the list form's level transitions, a stage-dump variant)
+    const int qpw = (form == CT_REDO || (form == CT_LIST && l->trans)) ? 1 : std::max(1, c.qpw);
+    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.flat, c.ftot, c.perm, c.nq, qpw};
     const ListArgs la = list_args(c, l);
-    dim3 grid(c.T, form == CT_REDO ? l->redo_groups : c.nq);
+    dim3 grid(c.T, form == CT_REDO ? l->redo_groups : (c.nq + qpw - 1) / qpw);
     uint4 *s4 = reinterpret_cast<uint4 *>(sc);
     const size_t lds = count_lds_size(c.W, c.bits);
-#define TACO_COUNT(MODE, TR)                                                        \
-    do {                                                                            \
-        if (c.bits == 8)                                                            \
-            k_count<8, true, MODE, TR><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la);  \
-        else if (c.Ns > 8)                                                          \
-            k_count<4, true, MODE, TR><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la);  \
-        else                                                                        \
-            k_count<4, false, MODE, TR><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la); \
+#define TACO_COUNT(MODE, TR, MULTI)                                                        \
+    do {                                                                                \
+        if (c.bits == 8)                                                                \
+            k_count<8, true, MODE, TR, MULTI><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la);  \
+        else if (c.Ns > 8)                                                              \
+            k_count<4, true, MODE, TR, MULTI><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la);  \
+        else                                                                            \
+            k_count<4, false, MODE, TR, MULTI><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la); \
     } while (0)
+    // several queries per workgroup: instances of their own, so that the
+    // one-query forms keep their registers
+    const bool multi = qpw > 1;
     if (form == CT_LIST && l->trans)
-        TACO_COUNT(CT_LIST, true);
+        TACO_COUNT(CT_LIST, true, false);
+    else if (form == CT_LIST && multi)
+        TACO_COUNT(CT_LIST, false, true);
     else if (form == CT_LIST)
-        TACO_COUNT(CT_LIST, false);
+        TACO_COUNT(CT_LIST, false, false);
     else if (form == CT_REDO)
-        TACO_COUNT(CT_REDO, true);
+        TACO_COUNT(CT_REDO, true, false);
+    else if (multi)
+        TACO_COUNT(CT_STORE, true, true);
     else
-        TACO_COUNT(CT_STORE, true);
+        TACO_COUNT(CT_STORE, true, false);
 #undef TACO_COUNT
     return hipGetLastError();
 }
@@ -2921,7 +3161,7 @@ hipError_t launch_select_level(const CountLaunch &c, const SelectLaunch &s, cons
 hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
                          hipStream_t st) {
     SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
-                  s.dump_hist, s.redo};
+                  s.dump_hist, s.redo, s.ovf};
     const int64_t words4 = static_cast<int64_t>(c.T) * c.W * c.bits / 128;
     // about 16 sixteen-byte words per thread; the few queued queries of a
     // list selection get four (one pass of SEL_UNROLL loads)
@@ -2939,7 +3179,7 @@ hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint
 }
 
 size_t fused_lds_bytes(int W, int bits) {
-    return count_lds_size(W, bits) + (18 + 17 + 1) * sizeof(uint32_t);
+    return count_lds_size(W, bits) + (18 + 17 + 3) * sizeof(uint32_t);
 }
 
 hipError_t fused_max_blocks(int W, int bits, int Ns, int *blocks_per_cu) {
@@ -2957,11 +3197,12 @@ hipError_t launch_cost_order(const int64_t *retrieved, int nq, int Ns, int32_t *
 
 hipError_t launch_count_select(const CountLaunch &c, const SelectLaunch &s, int NG, uint32_t *arrive,
                                uint32_t *err, uint32_t spin_limit, uint32_t *queue, const int32_t *order,
-                               hipStream_t st) {
-    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.flat, c.ftot, c.perm};
+                               uint32_t *sc, hipStream_t st) {
+    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.flat, c.ftot, c.perm, c.nq, 1};
     SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, s.dump_sc, s.dump_last,
-                  s.dump_hist, nullptr};
-    FuseArgs f{c.nq, NG, const_cast<uint32_t *>(s.hist), arrive, err, spin_limit, queue, order};
+                  s.dump_hist, nullptr, s.ovf};
+    FuseArgs f{c.nq, NG, const_cast<uint32_t *>(s.hist), arrive, err, spin_limit, queue, order,
+               reinterpret_cast<uint4 *>(sc)};
     void *args[] = {&a, &sa, &f};
     const void *k = count_select_kernel(c.bits, c.Ns);
     return hipLaunchCooperativeKernel(k, dim3(static_cast<unsigned>(NG) * c.T), dim3(CT_BLOCK), args,
@@ -3099,6 +3340,47 @@ hipError_t launch_topk(const int32_t *cand, const float *cand_dist, const uint32
                        int64_t cap, int nq, int k, const int32_t *kq, int k_max, int64_t *ids,
                        float *dists, hipStream_t st) {
     k_topk<<<nq, BLOCK, 0, st>>>(cand, cand_dist, cand_count, cap, k, kq, k_max, ids, dists);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_topk(const float *Q, int nq, int d, const float *base, const uint32_t *sc, int T, int W,
+                              int bits, const uint32_t *hist, int Ns, int64_t n, int64_t R, int rule,
+                              const uint32_t *ovf, int k, const int32_t *kq, int k_max, int64_t cap, int32_t *cand,
+                              float *cand_dist, uint32_t *cand_count, int64_t *ids, float *dists,
+                              hipStream_t st) {
+    if (static_cast<int64_t>(ST_SPLIT) * k_max > cap) return hipErrorInvalidValue;
+    // ST_SPLIT workgroups per queued query, up to 32 queries at a time (each
+    // group of them takes queued queries in turn; none when nothing is queued)
+    const dim3 grid(ST_SPLIT, static_cast<unsigned>(std::max(1, std::min(nq, 32))));
+    const int64_t row_words = static_cast<int64_t>(T) * W * bits / 32;
+    const size_t lds = sizeof(float) * static_cast<size_t>(d);
+#define TACO_ST(L, V)                                                                                    \
+    do {                                                                                                 \
+        if (bits == 4)                                                                                   \
+            k_stream_topk<L, V, 4><<<grid, BLOCK, lds, st>>>(Q, d, base, sc, row_words, hist, Ns, n, R,  \
+                                                            rule, ovf, k, kq, cap, cand, cand_dist,      \
+                                                            cand_count);                                 \
+        else                                                                                             \
+            k_stream_topk<L, V, 8><<<grid, BLOCK, lds, st>>>(Q, d, base, sc, row_words, hist, Ns, n, R,  \
+                                                            rule, ovf, k, kq, cap, cand, cand_dist,      \
+                                                            cand_count);                                 \
+    } while (0)
+    if (d % 4 != 0) {
+        TACO_ST(64, false);
+    } else {
+        switch (rerank_lanes_per_row(d)) {
+        case 4: TACO_ST(4, true); break;
+        case 8: TACO_ST(8, true); break;
+        case 16: TACO_ST(16, true); break;
+        case 32: TACO_ST(32, true); break;
+        default: TACO_ST(64, true); break;
+        }
+    }
+#undef TACO_ST
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_topk_queued<<<static_cast<unsigned>(std::max(1, std::min(nq, 256))), BLOCK, 0, st>>>(
+        cand, cand_dist, cand_count, cap, ovf, k, kq, k_max, ids, dists);
     return hipGetLastError();
 }
 

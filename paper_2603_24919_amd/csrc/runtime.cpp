@@ -98,10 +98,10 @@ struct Reader {
 };
 
 const char *kKernelNames[] = {"transform", "probe", "count", "select", "rerank", "topk", "recheck",
-                              "count_select", "graph", "cdist"};
+                              "count_select", "graph", "cdist", "stream"};
 enum Kern {
     K_TRANSFORM = 0, K_PROBE, K_COUNT, K_SELECT, K_RERANK, K_TOPK, K_RECHECK, K_FUSED, K_GRAPH, K_CDIST,
-    K_COUNT_
+    K_STREAM, K_COUNT_
 };
 
 struct Timing {
@@ -116,8 +116,8 @@ struct GraphKey {
     int64_t nq;
     int k, k_max;
     uint64_t alpha_bits, beta_bits;
-    int precision, count_mode, W, qpw, rule, rr_blocks, cdist, list_level;
-    int64_t Qb;
+    int precision, count_mode, W, qpw, rule, rr_blocks, cdist, list_level, count_qpw;
+    int64_t Qb, pool, slots;
     bool operator==(const GraphKey &o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 
@@ -152,6 +152,7 @@ struct tc_index {
     int64_t *Aq = nullptr;       // [Qb] per-query collision budgets (batched calls)
     int32_t *kq = nullptr;       // [Qb] per-query k, clamped
     int probe_qpw = 4;           // queries (wavefronts) per probe workgroup
+    int count_qpw = 1;           // queries per counting workgroup
     int rr_blocks = 32;          // re-rank workgroups per query
     // graph capture of whole calls
     bool use_graph = false;
@@ -164,9 +165,12 @@ struct tc_index {
     int rule = TC_RULE_PRINTED;
     int64_t max_batch = 0;  // 0: automatic
     int64_t scratch_budget = int64_t(64) << 30;
+    int64_t cand_slots = 0;  // TC_OPT_CANDIDATE_SLOTS (0: automatic)
     bool profile = false;
-    // scratch for one batch of Qb queries
+    // scratch for one batch of Qb queries; pool: candidate slots (cand,
+    // cand_dist, lb), shared by the batch's queries at a call's stride
     int64_t Qb = 0;
+    int64_t pool = 0;
     float *qt = nullptr;
     int32_t *cells = nullptr, *ncells = nullptr;
     int64_t *retrieved = nullptr;
@@ -297,32 +301,62 @@ int dmalloc(T **p, size_t count, const char *what) {
     return TC_OK;
 }
 
-// Candidate slots are n per query (|C| can reach n): ids and distances, and
-// in the bounded re-ranks the lower bounds (which also hold the re-checked
-// ids), plus the packed counts; the batch size follows from the scratch
-// budget.
-int64_t batch_for(const tc_index *x) {
-    int64_t per_q = 8 * x->n + int64_t(x->T) * x->W * x->bits / 8;
-    if (x->precision != TC_FP32) per_q += 4 * x->n;
+// Alg 5's budget R = floor(beta*n), in IEEE double, clamped to [0, n].
+int64_t budget_R(int64_t n, double beta) {
+    double r = std::floor(beta * double(n));
+    if (r < 0.0) r = 0.0;
+    if (r > double(n)) r = double(n);
+    return static_cast<int64_t>(r);
+}
+
+// Candidate slots per query of a call with budget R.  Alg 5 keeps the whole
+// threshold level, so |C| is about R but can reach R + that level's size
+// (up to n); slots for max(slots, 4R) of them, and a query with more is
+// queued for the streamed top-k, whose partial lists need STREAM_SPLIT *
+// k_max of them (the fixed-budget rule takes exactly min(R, ...)).
+int64_t call_cap(int64_t n, int64_t R, int64_t slots, int k_max) {
+    return std::min<int64_t>(
+        n, std::max<int64_t>(std::max<int64_t>(slots, 4 * R), int64_t(taco::STREAM_SPLIT) * k_max));
+}
+
+// Candidate slots per query the batch size is planned for.
+int64_t plan_slots(const tc_index *x) {
+    const int64_t s = x->cand_slots > 0 ? x->cand_slots : std::max<int64_t>(65536, x->n / 128);
+    return std::min<int64_t>(s, x->n);
+}
+
+// Per query: the packed counts (which the list form also uses for its
+// lists), the probed cells, and plan_slots() candidate slots (ids and
+// distances, and in the bounded re-ranks the lower bounds, which also hold
+// the re-checked ids).  The batch size follows from the scratch budget; the
+// pool holds at least n slots, so that any beta runs (one query per batch
+// at worst).
+int64_t batch_for(const tc_index *x, int64_t *pool) {
+    const int64_t slots = plan_slots(x);
+    int64_t per_q = int64_t(x->T) * x->W * x->bits / 8 + 8 * int64_t(x->Ns) * x->K + 8 * slots;
+    if (x->precision != TC_FP32) per_q += 4 * slots;
     int64_t qb = x->scratch_budget / per_q;
     int64_t cap = x->max_batch > 0 ? x->max_batch : 8192;
     if (qb > cap) qb = cap;
     if (qb < 1) qb = 1;
+    *pool = std::max<int64_t>(qb * slots, x->n);
     return qb;
 }
 
 int alloc_scratch(tc_index *x) {
     free_scratch(x);
-    const int64_t qb = batch_for(x);
+    int64_t pool = 0;
+    const int64_t qb = batch_for(x, &pool);
     int rc;
     if ((rc = dmalloc(&x->qt, size_t(qb) * x->M, "transformed queries"))) return rc;
     if ((rc = dmalloc(&x->cells, size_t(qb) * x->Ns * x->K, "probed cells"))) return rc;
     if ((rc = dmalloc(&x->ncells, size_t(qb) * x->Ns, "probe lengths"))) return rc;
     if ((rc = dmalloc(&x->retrieved, size_t(qb) * x->Ns, "retrieved counts"))) return rc;
     if ((rc = dmalloc(&x->hist, size_t(qb) * (x->Ns + 1), "level histograms"))) return rc;
-    // candidate counts [qb], then for the list selection the queue's header
-    // (queued, above the level) and the queue [qb]
-    if ((rc = dmalloc(&x->cand_count, size_t(2 * qb + 2), "candidate counts"))) return rc;
+    // candidate counts [qb]; for the list selection the queue's header
+    // (queued, above the level, overflowed lists) and the queue [qb]; the
+    // queue of queries with more candidates than slots: length, queue [qb]
+    if ((rc = dmalloc(&x->cand_count, size_t(3 * qb + 4), "candidate counts"))) return rc;
     if ((rc = dmalloc(&x->lvl, 1, "list level"))) return rc;
     if ((rc = dmalloc(&x->tcount, size_t(qb) * x->T, "per-tile list lengths"))) return rc;
     if ((rc = dmalloc(&x->toff, size_t(qb) * (x->T + 1), "per-tile candidate offsets"))) return rc;
@@ -339,15 +373,15 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->bm, size_t(qb) * x->Ns * ((x->K + 31) / 32), "probed-cell bitmaps"))) return rc;
     if ((rc = dmalloc(&x->Aq, size_t(qb), "per-query budgets"))) return rc;
     if ((rc = dmalloc(&x->kq, size_t(qb), "per-query k"))) return rc;
-    if ((rc = dmalloc(&x->cand, size_t(qb) * x->n, "candidates"))) return rc;
-    if ((rc = dmalloc(&x->cand_dist, size_t(qb) * x->n, "candidate distances"))) return rc;
+    if ((rc = dmalloc(&x->cand, size_t(pool), "candidates"))) return rc;
+    if ((rc = dmalloc(&x->cand_dist, size_t(pool), "candidate distances"))) return rc;
     if ((rc = dmalloc(&x->sc, size_t(qb) * x->T * (size_t(x->W) * x->bits / 32), "packed counts")))
         return rc;
     if ((rc = dmalloc(&x->qn, size_t(qb) * x->Ns * 2, "query half norms"))) return rc;
     if ((rc = dmalloc(&x->qsc, size_t(qb) * x->Ns, "query scales"))) return rc;
     if ((rc = dmalloc(&x->cd, size_t(qb) * x->Ns * 2 * x->l, "centroid distances"))) return rc;
     if (x->precision != TC_FP32) {
-        if ((rc = dmalloc(&x->lb, size_t(qb) * x->n, "distance lower bounds"))) return rc;
+        if ((rc = dmalloc(&x->lb, size_t(pool), "distance lower bounds"))) return rc;
         if ((rc = dmalloc(&x->rk_count, size_t(qb), "re-check counts"))) return rc;
         if ((rc = dmalloc(&x->tau_ids, size_t(qb) * 1024, "bound top-k ids"))) return rc;
         if ((rc = dmalloc(&x->exact, size_t(qb), "exact-bound flags"))) return rc;
@@ -355,6 +389,7 @@ int alloc_scratch(tc_index *x) {
         if ((rc = dmalloc(&x->tau_d, size_t(qb) * 1024, "bound top-k"))) return rc;
     }
     x->Qb = qb;
+    x->pool = pool;
     return TC_OK;
 }
 
@@ -756,6 +791,7 @@ struct Call {
 // sets only what the plain path uses and leaves the rest null).
 struct Scratch {
     int64_t Qb = 0;
+    int64_t pool = 0;  // candidate slots of cand, cand_dist (and lb)
     float *qt = nullptr;
     int32_t *cells = nullptr, *ncells = nullptr;
     int64_t *retrieved = nullptr;
@@ -779,6 +815,7 @@ struct Scratch {
 Scratch own_scratch(const tc_index *x) {
     Scratch S;
     S.Qb = x->Qb;
+    S.pool = x->pool;
     S.qt = x->qt;
     S.cells = x->cells;
     S.ncells = x->ncells;
@@ -827,11 +864,14 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
     double a = std::ceil(c.alpha * double(x->n));
     if (a < 1.0) a = 1.0;
     if (a > double(x->n)) a = double(x->n);
-    double r = std::floor(c.beta * double(x->n));
-    if (r < 0.0) r = 0.0;
-    if (r > double(x->n)) r = double(x->n);
-    const int64_t A = static_cast<int64_t>(a), R = static_cast<int64_t>(r);
-    const int64_t cap = x->n;
+    const int64_t A = static_cast<int64_t>(a), R = budget_R(x->n, c.beta);
+    // candidate slots per query (all n with stage dumps, which hold every
+    // candidate), and the queries per batch they leave
+    const int64_t cap = dump ? x->n : call_cap(x->n, R, c.scratch ? S.pool / S.Qb : plan_slots(x), c.k_max);
+    const int64_t Qc = std::min<int64_t>(S.Qb, S.pool / cap);
+    // queries with more candidates than cap (none possible when cap = n)
+    const bool stream = cap < x->n && x->rule != TC_RULE_FIXED;
+    uint32_t *ovf = S.cand_count + 2 * S.Qb + 3;
     const int rr_blocks = x->rr_blocks;
     const int k = c.k, k_max = c.k_max;
     // AUTO takes the split launches: on MI355X the ~T*nq independent
@@ -842,8 +882,8 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
     const bool fused = count_mode == TC_COUNT_FUSED && !fixed;
     const bool list = count_mode == TC_COUNT_LIST && !fixed;
     const bool codes = count_mode == TC_COUNT_CODES;
-    for (int64_t b0 = 0; b0 < c.nq; b0 += S.Qb) {
-        const int nb = static_cast<int>(std::min<int64_t>(S.Qb, c.nq - b0));
+    for (int64_t b0 = 0; b0 < c.nq; b0 += Qc) {
+        const int nb = static_cast<int>(std::min<int64_t>(Qc, c.nq - b0));
         const float *Qb = c.Q + b0 * x->d;
         int64_t *ids = c.ids + b0 * k_max;
         float *dists = c.dists + b0 * k_max;
@@ -857,7 +897,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             kq = S.kq;
         }
         TC_HIP(taco::launch_fill_u32(S.hist, int64_t(nb) * (x->Ns + 1), 0u, st), "clearing histograms");
-        TC_HIP(taco::launch_fill_u32(S.cand_count, S.Qb + 2, 0u, st), "clearing candidate counts");
+        TC_HIP(taco::launch_fill_u32(S.cand_count, 2 * S.Qb + 4, 0u, st), "clearing candidate counts");
 
         rec(K_TRANSFORM, st, true);
         TC_HIP(taco::launch_transform(Qb, nb, x->d, x->mean, x->B, x->M, S.qt, st), "transform kernel");
@@ -890,11 +930,12 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             TC_HIP(taco::launch_flatten_cells(S.cells, S.ncells, nb, x->Ns, x->K, S.flat, S.ftot, st),
                    "probed cell list kernel");
         taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids_enc, x->off2d, S.flat,
-                             S.ftot, order ? S.perm : nullptr};
+                             S.ftot, order ? S.perm : nullptr, c.plain ? 1 : x->count_qpw};
         taco::SelectLaunch sl{S.hist, R, x->rule, cap, S.cand, S.cand_count,
                               dump && dump->sc ? dump->sc + b0 * x->n : nullptr,
                               dump && dump->last ? dump->last + b0 : nullptr,
                               dump && dump->hist ? dump->hist + b0 * (x->Ns + 1) : nullptr};
+        sl.ovf = ovf;
         if (fused) {
             TC_HIP(taco::launch_fill_u32(S.arrive, nb, 0u, st), "clearing tile arrivals");
             TC_HIP(taco::launch_fill_u32(S.qctr, x->T, 0u, st), "clearing the work queue");
@@ -902,19 +943,20 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             if (Aq) TC_HIP(taco::launch_cost_order(S.retrieved, nb, x->Ns, S.perm, st), "cost order kernel");
             rec(K_FUSED, st, true);
             TC_HIP(taco::launch_count_select(cl, sl, std::min(x->fused_groups, nb), S.arrive, x->err,
-                                             1u << 24, S.qctr, (Aq || order) ? S.perm : nullptr, st),
+                                             1u << 24, S.qctr, (Aq || order) ? S.perm : nullptr, S.sc, st),
                    "fused count/select kernel");
             rec(K_FUSED, st, false);
         } else if (list) {
             uint32_t *redo = S.cand_count + S.Qb;
             const bool dsc = dump && dump->sc;
             const bool dh = dump && (dump->hist || dump->last);
-            // the lists sit in the distance slots, free until the re-rank
-            const taco::ListLaunch ll{x->list_level, S.lvl, cap, reinterpret_cast<uint32_t *>(S.cand_dist),
+            // the lists sit in the packed-count rows, which the list form
+            // fills only for the queued queries, after their lists are read
+            const taco::ListLaunch ll{x->list_level, S.lvl, cap, int64_t(x->W) * x->bits / 32, S.sc,
                                       S.cand, S.cand_count, S.tcount, redo, 64, R, x->rule, dh,
                                       sl.dump_last, sl.dump_hist, S.toff, S.tlev};
             rec(K_COUNT, st, true);
-            TC_HIP(taco::launch_count(cl, S.hist, dsc ? S.sc : nullptr, 1, &ll, st), "count kernel (list)");
+            TC_HIP(taco::launch_count(cl, S.hist, nullptr, 1, &ll, st), "count kernel (list)");
             rec(K_COUNT, st, false);
             rec(K_SELECT, st, true);
             TC_HIP(taco::launch_list_select(cl, ll, S.hist, st), "list select kernel");
@@ -927,9 +969,13 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             sr.redo_groups = 128;
             TC_HIP(taco::launch_select(cl, sr, S.sc, st), "select kernel (queued)");
             rec(K_SELECT, st, false);
-            if (dsc)
+            if (dsc) {
+                // stage dumps: every query's packed counts, over the lists
+                // (the level counts it adds go to the spent histograms)
+                TC_HIP(taco::launch_count(cl, S.hist, S.sc, 0, nullptr, st), "count kernel (dump)");
                 TC_HIP(taco::launch_unpack_counts(S.sc, nb, x->T, x->W, x->bits, x->n, dump->sc + b0 * x->n, st),
                        "dump sc");
+            }
         } else {
             rec(K_COUNT, st, true);
             if (codes)
@@ -992,6 +1038,14 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                    "top-k kernel");
             rec(K_TOPK, st, false);
         }
+        if (stream) {
+            rec(K_STREAM, st, true);
+            TC_HIP(taco::launch_stream_topk(Qb, nb, x->d, x->base, S.sc, x->T, x->W, x->bits, S.hist, x->Ns, x->n,
+                                            R, x->rule, ovf, k, kq, k_max, cap, S.cand, S.cand_dist,
+                                            S.cand_count, ids, dists, st),
+                   "streamed top-k kernels");
+            rec(K_STREAM, st, false);
+        }
 
         if (dump) {
             const hipMemcpyKind dd = hipMemcpyDeviceToDevice;
@@ -1008,12 +1062,15 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                                       sizeof(int64_t) * nb * x->Ns, dd, st), "dump retrieved");
             if (dump->ncand)
                 TC_HIP(taco::launch_u32_to_i64(S.cand_count, dump->ncand + b0, nb, st), "dump ncand");
+            // candidates at the call's stride cap, dumped at stride n
             if (dump->cand)
-                TC_HIP(hipMemcpyAsync(dump->cand + b0 * x->n, S.cand, sizeof(int32_t) * size_t(nb) * x->n, dd, st),
+                TC_HIP(hipMemcpy2DAsync(dump->cand + b0 * x->n, sizeof(int32_t) * size_t(x->n), S.cand,
+                                        sizeof(int32_t) * size_t(cap), sizeof(int32_t) * size_t(cap), nb, dd, st),
                        "dump cand");
             if (dump->cand_dist && precision == TC_FP32)
-                TC_HIP(hipMemcpyAsync(dump->cand_dist + b0 * x->n, S.cand_dist,
-                                      sizeof(float) * size_t(nb) * x->n, dd, st), "dump cand_dist");
+                TC_HIP(hipMemcpy2DAsync(dump->cand_dist + b0 * x->n, sizeof(float) * size_t(x->n), S.cand_dist,
+                                        sizeof(float) * size_t(cap), sizeof(float) * size_t(cap), nb, dd, st),
+                       "dump cand_dist");
         }
     }
     return TC_OK;
@@ -1046,7 +1103,10 @@ int run(tc_index *x, const Call &c, void *stream) {
     key.rr_blocks = x->rr_blocks;
     key.cdist = x->cdist;
     key.list_level = x->list_level;
+    key.count_qpw = x->count_qpw;
     key.Qb = x->Qb;
+    key.pool = x->pool;
+    key.slots = plan_slots(x);
     if (!x->graph_exec || !(key == x->graph_key)) {
         drop_graph(x);
         if (!x->cap_stream)
@@ -1159,9 +1219,14 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
         x->max_batch = value;
         return alloc_scratch(x);
     case TC_OPT_SCRATCH_BYTES:
-        if (value < 8 * x->n) return fail(TC_EINVAL, "scratch budget below one query (8*n bytes)");
+        if (value < 1) return fail(TC_EINVAL, "scratch budget must be >= 1 byte");
         TC_HIP(hipDeviceSynchronize(), "synchronizing before re-sizing scratch");
         x->scratch_budget = value;
+        return alloc_scratch(x);
+    case TC_OPT_CANDIDATE_SLOTS:
+        if (value < 0) return fail(TC_EINVAL, "candidate slots must be >= 0 (0: automatic)");
+        TC_HIP(hipDeviceSynchronize(), "synchronizing before re-sizing scratch");
+        x->cand_slots = value;
         return alloc_scratch(x);
     case TC_OPT_TILE_IDS:
         if (value < 1024 || value % 1024 != 0 || value > (int64_t(1) << 20) ||
@@ -1242,6 +1307,11 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
         if (value != 0 && value != 1) return fail(TC_EINVAL, "tune precision must be 0 or 1");
         x->tune_precision = value != 0;
         return TC_OK;
+    case TC_OPT_COUNT_QPW:
+        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16 && value != 32)
+            return fail(TC_EINVAL, "queries per counting workgroup must be 1, 2, 4, 8, 16 or 32");
+        x->count_qpw = static_cast<int>(value);
+        return TC_OK;
     default:
         return fail(TC_EINVAL, "unknown option");
     }
@@ -1267,21 +1337,24 @@ int tc_search_noalloc(tc_index *x, const float *queries, int64_t nq, int32_t k, 
     // to the array's 256-byte alignment once per buffer
     const int64_t NsK = int64_t(x->Ns) * x->K;
     const int64_t packed = int64_t(x->T) * (int64_t(x->W) * x->bits / 32);  // u32 words
+    // candidate slots per query (queries with more take the streamed top-k)
+    const int64_t cap = call_cap(x->n, budget_R(x->n, beta), std::min<int64_t>(plan_slots(x), 16384), k);
     auto up = [](int64_t b) { return (b + 255) & ~int64_t(255); };
     auto need = [&](int64_t qb) {
         return up(4 * qb * x->M) + 2 * up(4 * qb * NsK) + up(4 * qb * x->Ns) + up(8 * qb * x->Ns) +
-               up(4 * qb * (x->Ns + 1)) + up(4 * (2 * qb + 2)) + up(4 * qb) + up(4 * qb) +
-               2 * up(4 * qb * x->n) + up(4 * qb * packed);
+               up(4 * qb * (x->Ns + 1)) + up(4 * (3 * qb + 4)) + up(4 * qb) + up(4 * qb) +
+               2 * up(4 * qb * cap) + up(4 * qb * packed);
     };
-    const int64_t cap = static_cast<int64_t>(TC_NOALLOC_SCRATCH_BYTES);
-    if (need(1) > cap)
+    const int64_t limit = static_cast<int64_t>(TC_NOALLOC_SCRATCH_BYTES);
+    if (need(1) > limit)
         return fail(TC_EINVAL, "tc_search_noalloc: one query needs " + std::to_string(need(1)) +
-                                   " bytes of scratch, more than the " + std::to_string(cap) +
-                                   "-byte static array (the index has too many points); use tc_search");
-    int64_t qb = std::min<int64_t>(nq, cap / need(1));
-    while (qb > 1 && need(qb) > cap) qb--;
+                                   " bytes of scratch, more than the " + std::to_string(limit) +
+                                   "-byte static array (too many points or too large a beta); use tc_search");
+    int64_t qb = std::min<int64_t>(nq, limit / need(1));
+    while (qb > 1 && need(qb) > limit) qb--;
     Scratch S;
     S.Qb = qb;
+    S.pool = qb * cap;
     int64_t at = 0;
     auto take = [&](int64_t bytes) {
         unsigned char *p = base + at;
@@ -1294,13 +1367,13 @@ int tc_search_noalloc(tc_index *x, const float *queries, int64_t nq, int32_t k, 
     S.ncells = reinterpret_cast<int32_t *>(take(4 * qb * x->Ns));
     S.retrieved = reinterpret_cast<int64_t *>(take(8 * qb * x->Ns));
     S.hist = reinterpret_cast<uint32_t *>(take(4 * qb * (x->Ns + 1)));
-    S.cand_count = reinterpret_cast<uint32_t *>(take(4 * (2 * qb + 2)));
+    S.cand_count = reinterpret_cast<uint32_t *>(take(4 * (3 * qb + 4)));
     S.perm = reinterpret_cast<int32_t *>(take(4 * qb));
     S.ftot = reinterpret_cast<uint32_t *>(take(4 * qb));
-    S.cand = reinterpret_cast<int32_t *>(take(4 * qb * x->n));
-    S.cand_dist = reinterpret_cast<float *>(take(4 * qb * x->n));
+    S.cand = reinterpret_cast<int32_t *>(take(4 * qb * cap));
+    S.cand_dist = reinterpret_cast<float *>(take(4 * qb * cap));
     S.sc = reinterpret_cast<uint32_t *>(take(4 * qb * packed));
-    if (at > cap) return fail(TC_EINVAL, "tc_search_noalloc: scratch plan exceeds the static array");
+    if (at > limit) return fail(TC_EINVAL, "tc_search_noalloc: scratch plan exceeds the static array");
     Call c;
     c.Q = queries;
     c.nq = nq;
@@ -1377,7 +1450,7 @@ int tc_profile_reset(tc_index *x) {
 namespace {
 
 struct TuneConfig {
-    int W, mode, qpw, rr, precision;
+    int W, mode, qpw, rr, precision, cqpw;
 };
 
 // Cache key of a tuning: the GPU, the index (shape, seed, content hash), the
@@ -1401,6 +1474,7 @@ int apply_config(tc_index *x, const TuneConfig &c) {
     if (c.precision != x->precision && (rc = tc_set_option(x, TC_OPT_PRECISION, c.precision))) return rc;
     if ((rc = tc_set_option(x, TC_OPT_COUNT_MODE, c.mode))) return rc;
     if ((rc = tc_set_option(x, TC_OPT_PROBE_QPW, c.qpw))) return rc;
+    if ((rc = tc_set_option(x, TC_OPT_COUNT_QPW, c.cqpw))) return rc;
     return tc_set_option(x, TC_OPT_RERANK_BLOCKS, c.rr);
 }
 
@@ -1426,11 +1500,12 @@ int tune(tc_index *x, const std::string &key, const std::function<int()> &once, 
         while (std::getline(in, line)) {
             if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
             TuneConfig c{};
-            if (sscanf(line.c_str() + line.find("\"W\""), "\"W\": %d, \"mode\": %d, \"qpw\": %d, \"rr\": %d, \"precision\": %d",
-                       &c.W, &c.mode, &c.qpw, &c.rr, &c.precision) == 5) {
+            if (sscanf(line.c_str() + line.find("\"W\""),
+                       "\"W\": %d, \"mode\": %d, \"qpw\": %d, \"rr\": %d, \"precision\": %d, \"cqpw\": %d",
+                       &c.W, &c.mode, &c.qpw, &c.rr, &c.precision, &c.cqpw) == 6) {
                 if (apply_config(x, c) == TC_OK) {
                     rep << "cached " << key << " W=" << c.W << " mode=" << c.mode << " qpw=" << c.qpw
-                        << " rr=" << c.rr << " precision=" << c.precision << "\n";
+                        << " rr=" << c.rr << " precision=" << c.precision << " cqpw=" << c.cqpw << "\n";
                     return finish(TC_OK);
                 }
                 rep << "cached entry no longer applies (" << g_err << "); measuring\n";
@@ -1460,12 +1535,12 @@ int tune(tc_index *x, const std::string &key, const std::function<int()> &once, 
         TC_HIP(hipEventElapsedTime(&f, e0, e1), "autotune timing");
         *ms = f / 3.0;
         rep << "W=" << c.W << " mode=" << c.mode << " qpw=" << c.qpw << " rr=" << c.rr
-            << " precision=" << c.precision << " ms=" << *ms << "\n";
+            << " precision=" << c.precision << " cqpw=" << c.cqpw << " ms=" << *ms << "\n";
         return TC_OK;
     };
     int rc = TC_OK;
     TuneConfig best{x->W, x->count_mode == TC_COUNT_AUTO ? TC_COUNT_SPLIT : x->count_mode, x->probe_qpw,
-                    x->rr_blocks, x->precision};
+                    x->rr_blocks, x->precision, x->count_qpw};
     double best_ms = 1e30;
     std::vector<int> Ws = x->bits == 4 ? std::vector<int>{65536, 131072, 262144}
                                        : std::vector<int>{32768, 65536, 131072};
@@ -1493,6 +1568,15 @@ int tune(tc_index *x, const std::string &key, const std::function<int()> &once, 
         if ((rc = measure(c, &ms))) goto done;
         if (ms < best_ms) best_ms = ms, best = c;
     }
+    if (best.mode == TC_COUNT_SPLIT || best.mode == TC_COUNT_LIST) {
+        for (int cq : {2, 4, 8, 16}) {
+            TuneConfig c = best;
+            c.cqpw = cq;
+            double ms;
+            if ((rc = measure(c, &ms))) goto done;
+            if (ms < best_ms) best_ms = ms, best = c;
+        }
+    }
     for (int qpw : {1, 2, 4, 8, 16}) {
         TuneConfig c = best;
         c.qpw = qpw;
@@ -1518,12 +1602,12 @@ int tune(tc_index *x, const std::string &key, const std::function<int()> &once, 
     }
     rc = apply_config(x, best);
     rep << "best W=" << best.W << " mode=" << best.mode << " qpw=" << best.qpw << " rr=" << best.rr
-        << " precision=" << best.precision << " ms=" << best_ms << "\n";
+        << " precision=" << best.precision << " cqpw=" << best.cqpw << " ms=" << best_ms << "\n";
     if (rc == TC_OK && cache_path) {
         std::ofstream out(cache_path, std::ios::app);
         out << "{\"key\": \"" << key << "\", \"W\": " << best.W << ", \"mode\": " << best.mode
             << ", \"qpw\": " << best.qpw << ", \"rr\": " << best.rr << ", \"precision\": " << best.precision
-            << ", \"ms\": " << best_ms << "}\n";
+            << ", \"cqpw\": " << best.cqpw << ", \"ms\": " << best_ms << "}\n";
     }
 done:
     x->use_graph = graph;
@@ -1609,9 +1693,11 @@ int tc_device_errors(tc_index *x, uint32_t *flags) {
     return TC_OK;
 }
 
-int tc_batch_capacity(const tc_index *x, int64_t *qpb) {
+int tc_batch_capacity(const tc_index *x, double beta, int32_t k_max, int64_t *qpb) {
     if (!x || !qpb) return fail(TC_EINVAL, "index and output must be non-NULL");
-    *qpb = x->Qb;
+    if (!(beta >= 0.0 && beta <= 1.0)) return fail(TC_EINVAL, "beta must be in [0, 1]");
+    if (k_max < 1 || int64_t(k_max) > x->n || k_max > 1024) return fail(TC_EINVAL, "k must be in [1, min(n, 1024)]");
+    *qpb = std::min<int64_t>(x->Qb, x->pool / call_cap(x->n, budget_R(x->n, beta), plan_slots(x), k_max));
     return TC_OK;
 }
 
@@ -1934,14 +2020,16 @@ int sclinear(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, d
         if ((rc = dmalloc(&x->scthr, size_t(want) * x->Ns, "SC-Linear thresholds"))) return rc;
         x->scQ = want;
     }
-    double a = std::ceil(alpha * double(n)), r = std::floor(beta * double(n));
+    double a = std::ceil(alpha * double(n));
     a = std::min(std::max(a, 1.0), double(n));
-    r = std::min(std::max(r, 0.0), double(n));
-    const int64_t A = static_cast<int64_t>(a), R = static_cast<int64_t>(r);
-    for (int64_t b0 = 0; b0 < nq; b0 += x->scQ) {
-        const int nb = static_cast<int>(std::min<int64_t>(x->scQ, nq - b0));
+    const int64_t A = static_cast<int64_t>(a), R = budget_R(n, beta);
+    // the fixed-budget rule selects min(R, ...) candidates (all n with dumps)
+    const int64_t cap = dump ? n : std::max<int64_t>(R, 1);
+    const int64_t Qc = std::min<int64_t>(x->scQ, x->pool / cap);
+    for (int64_t b0 = 0; b0 < nq; b0 += Qc) {
+        const int nb = static_cast<int>(std::min<int64_t>(Qc, nq - b0));
         TC_HIP(taco::launch_fill_u32(x->hist, int64_t(nb) * (x->Ns + 1), 0u, st), "clearing histograms");
-        TC_HIP(taco::launch_fill_u32(x->cand_count, x->Qb + 2, 0u, st), "clearing candidate counts");
+        TC_HIP(taco::launch_fill_u32(x->cand_count, 2 * x->Qb + 4, 0u, st), "clearing candidate counts");
         TC_HIP(taco::launch_transform(Q + b0 * x->d, nb, x->d, x->mean, x->B, x->M, x->qt, st), "transform kernel");
         TC_HIP(taco::launch_sub_dist(x->sct, n, x->M, x->Ns, x->s, x->qt, nb, x->scD, st), "subspace distances");
         TC_HIP(taco::launch_sub_select(x->scD, n, x->Ns, nb, A, x->scthr, st), "subspace selection");
@@ -1949,23 +2037,24 @@ int sclinear(tc_index *x, const float *Q, int64_t nq, int32_t k, double alpha, d
                "SC-Linear counts");
         taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, n, x->ids_enc, x->off2d, x->flat, x->ftot,
                              nullptr};
-        taco::SelectLaunch sl{x->hist, R, TC_RULE_FIXED, n, x->cand, x->cand_count,
+        taco::SelectLaunch sl{x->hist, R, TC_RULE_FIXED, cap, x->cand, x->cand_count,
                               dump && dump->sc ? dump->sc + b0 * n : nullptr,
                               dump && dump->last ? dump->last + b0 : nullptr,
                               dump && dump->hist ? dump->hist + b0 * (x->Ns + 1) : nullptr};
         TC_HIP(taco::launch_select(cl, sl, x->sc, st), "select kernel");
         TC_HIP(taco::launch_select_level(cl, sl, x->sc, st), "boundary-level select kernel");
-        TC_HIP(taco::launch_rerank(Q + b0 * x->d, nb, x->d, x->base, x->cand, x->cand_count, n, x->cand_dist,
+        TC_HIP(taco::launch_rerank(Q + b0 * x->d, nb, x->d, x->base, x->cand, x->cand_count, cap, x->cand_dist,
                                    x->rr_blocks, st),
                "rerank kernel");
-        TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, n, nb, k, nullptr, k, ids + b0 * k,
+        TC_HIP(taco::launch_topk(x->cand, x->cand_dist, x->cand_count, cap, nb, k, nullptr, k, ids + b0 * k,
                                  dists + b0 * k, st),
                "top-k kernel");
         if (dump && dump->ncand)
             TC_HIP(taco::launch_u32_to_i64(x->cand_count, dump->ncand + b0, nb, st), "dump ncand");
         if (dump && dump->cand)
-            TC_HIP(hipMemcpyAsync(dump->cand + b0 * n, x->cand, sizeof(int32_t) * size_t(nb) * n,
-                                  hipMemcpyDeviceToDevice, st),
+            TC_HIP(hipMemcpy2DAsync(dump->cand + b0 * n, sizeof(int32_t) * size_t(n), x->cand,
+                                    sizeof(int32_t) * size_t(cap), sizeof(int32_t) * size_t(cap), nb,
+                                    hipMemcpyDeviceToDevice, st),
                    "dump cand");
     }
     return TC_OK;

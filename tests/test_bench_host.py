@@ -33,10 +33,15 @@ def test_short_kernel_names():
     assert f("void taco::k_rerank16<16, true>(float const*)") == "rerank"
     assert f("void taco::k_rerank<16, true>(float const*)") == "rerank"
     assert f("void taco::k_recheck_topk<16, true>(float const*)") == "recheck"
+    assert f("void taco::k_stream_topk<16, true, 4>(float const*, int)") == "stream"
+    assert f("taco::k_topk_queued(int const*, float const*)") == "stream"
+    assert f("taco::k_topk(int const*, float const*)") == "topk"
     assert f("void taco::k_rerank8<8, true, true>(float const*)") == "rerank"
     assert f("void taco::k_cdist_mfma<true>(float const*)") == "cdist"
     assert f("void taco::bld::(anonymous namespace)::k_km_assign<8>(taco::bld::KmArgs, int)") == "build_km_assign"
     assert f("taco::bld::(anonymous namespace)::k_jacobi(double const*, int, int)") == "build_jacobi"
+    assert f("void taco::k_count_codes<4, 8>(unsigned short const*, long)") == "count_codes"
+    assert f("taco::k_sub_select(float const*, long, int, long, unsigned long*)") == "sub_select"
     assert f("__amd_rocclr_copyBuffer") is None
 
 

@@ -267,6 +267,21 @@ def test_count_modes_all_stages(taco_mod, tiny, mode):
                  options=opts)
 
 
+@pytest.mark.parametrize("cqpw", [2, 4, 32])
+@pytest.mark.parametrize("mode", ["split", "list"])
+def test_count_queries_per_workgroup_all_stages(taco_mod, tiny, mode, cqpw):
+    """Counting workgroups that take several queries of their tile in turn
+    (the last one partly empty) match the oracle stage by stage."""
+    t = taco_mod
+    m = {"split": t.TC_COUNT_SPLIT, "list": t.TC_COUNT_LIST}[mode]
+    print(f"[tiny] count mode {mode}, {cqpw} queries per workgroup", flush=True)
+    for opts in (((t.TC_OPT_COUNT_MODE, m), (t.TC_OPT_COUNT_QPW, cqpw)),
+                 ((t.TC_OPT_TILE_IDS, 4096), (t.TC_OPT_COUNT_MODE, m), (t.TC_OPT_COUNT_QPW, cqpw),
+                  (t.TC_OPT_MAX_BATCH, 13))):
+        _run_all(t, tiny["path"], tiny["oidx"], tiny["Q"], 10, 0.05, 0.005, 0, f"tiny {mode} cqpw={cqpw}",
+                 options=opts)
+
+
 @pytest.mark.parametrize("qpw", [1, 2, 8, 16])
 def test_probe_widths_all_stages(taco_mod, tiny, qpw):
     """Every probe workgroup width (queries per workgroup) matches the oracle
