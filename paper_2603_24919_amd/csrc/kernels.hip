@@ -776,6 +776,7 @@ struct CountLds {
     uint32_t *wsum;   // [2 * CT_WAVES] per-wavefront totals of the prefix sums
     uint32_t *hsum;   // [18] the tile's "count >= v" totals
     uint32_t *lsum;   // [17] levels of the listed ids
+    uint32_t *lcnt;   // [1] ids listed by the re-walk (count_tile's XL form)
 };
 
 static_assert(2 * CT_WT <= CT_CHUNK + 1, "the start bitmap must fit its region");
@@ -784,7 +785,7 @@ static_assert(CT_CHUNK % 2 == 0, "the start bitmap is read in 64-bit words");
 __host__ __device__ constexpr size_t count_lds_size(int W, int bits) {
     return static_cast<size_t>(W) * bits / 8 + CT_DUMMY * 4 + static_cast<size_t>(CT_CHUNK) * 4 +
            static_cast<size_t>(CT_CHUNK + 1) * 4 + static_cast<size_t>(CT_WT) * 2 +
-           2 * CT_WAVES * 4 + (18 + 17) * 4;
+           2 * CT_WAVES * 4 + (18 + 17 + 1) * 4;
 }
 
 template <int BITS>
@@ -797,6 +798,7 @@ __device__ __forceinline__ CountLds carve(unsigned char *lds, int W) {
     c.wsum = reinterpret_cast<uint32_t *>(c.wt + CT_WT);
     c.hsum = c.wsum + 2 * CT_WAVES;
     c.lsum = c.hsum + 18;
+    c.lcnt = c.lsum + 17;
     return c;
 }
 
@@ -955,14 +957,70 @@ __device__ __forceinline__ void walk_bump(const CountLds &L, const uint4 (&id)[C
     }
 }
 
+// The re-walk of a sparse tile: for each id of the walk once more, an
+// atomic AND takes its count and clears it, so only an id's first visit sees
+// its final count c; ids with c >= lv are listed as c << shift | id (tile
+// base id0), their positions reserved on L.lcnt one wavefront at a time
+// (only the first lcap are stored) and their levels tallied in L.lsum.
+template <int BITS>
+__device__ __forceinline__ void walk_take(const CountLds &L, const uint4 (&id)[CT_UNROLL], uint32_t lim,
+                                          uint32_t lv, uint32_t *dst, uint32_t lcap, int shift, uint32_t id0,
+                                          int lane) {
+    constexpr uint32_t CMASK = (1u << BITS) - 1u;
+    const uint64_t below = lanes_below(lane);
+#pragma unroll
+    for (int u = 0; u < CT_UNROLL; u++) {
+        const uint32_t e4[4] = {id[u].x, id[u].y, id[u].z, id[u].w};
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const uint32_t enc = e4[j];
+            uint32_t c = 0u;
+            if (enc < lim) {  // pads and the guard value lie at or above lim
+                const uint32_t sh = enc & 31u;
+                uint32_t *w = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(L.cnt) + (enc >> 5));
+                c = (atomicAnd(w, ~(CMASK << sh)) >> sh) & CMASK;
+            }
+            const bool emit = c >= lv && c != 0u;
+            const uint64_t m = __ballot(emit);
+            if (m != 0ull) {
+                const int leader = __ffsll(static_cast<long long>(m)) - 1;
+                uint32_t at = 0u;
+                if (lane == leader) at = atomicAdd(L.lcnt, static_cast<uint32_t>(__popcll(m)));
+                at = static_cast<uint32_t>(__shfl(static_cast<int>(at), leader, WAVE));
+                if (emit) {
+                    const uint32_t pos = at + static_cast<uint32_t>(__popcll(m & below));
+                    atomicAdd(&L.lsum[c], 1u);
+                    const uint32_t tid = ((enc >> 5) * 8u + (enc & 31u)) / BITS;  // id within the tile
+                    if (pos < lcap) dst[pos] = (c << shift) | (id0 + tid);
+                }
+            }
+        }
+    }
+}
+
+// Re-walk (XL) only where it reads fewer words than the full scan of the
+// tile's counts: positions (groups of four ids) * RW_DENSITY <= 16-byte words.
+constexpr uint32_t RW_DENSITY = 4;
+
 // Counts the collisions of tile t of query q into L.cnt and, with TR, adds
 // the tile's "count >= v" totals to hsum[v] (hsum zeroed by the caller
-// before; complete after the caller's next barrier).
-template <int BITS, bool HI, bool TR = true>
-__device__ __forceinline__ void count_tile(const CountArgs &a, int q, int t, const CountLds &L, uint32_t *hsum) {
+// before; complete after the caller's next barrier).  clear: zero the counts
+// first (else they are zero already).  XL with xl_dst: when the walk is one
+// chunk and one segment and sparse (RW_DENSITY), also lists the ids with
+// count >= lv into xl_dst (walk_take; L.lcnt receives their number, L.lsum
+// their levels, lsum zeroed by the caller) and leaves every count zero;
+// returns whether it did.
+template <int BITS, bool HI, bool TR = true, bool XL = false>
+__device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, const CountLds &L, uint32_t *hsum,
+                                           uint32_t *xl_dst = nullptr, uint32_t xl_cap = 0u, int xl_shift = 0,
+                                           uint32_t lv = 0u, bool clear = true) {
     const int vec = a.W * BITS / 128;  // 16-byte words of counts
-    for (int i = threadIdx.x; i < vec; i += CT_BLOCK) reinterpret_cast<uint4 *>(L.cnt)[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (clear)
+        for (int i = threadIdx.x; i < vec; i += CT_BLOCK)
+            reinterpret_cast<uint4 *>(L.cnt)[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (XL && threadIdx.x == 0) *L.lcnt = 0u;
     // (the counts are cleared before the barriers ahead of the walk)
+    bool rw = XL && xl_dst != nullptr;
     const int totalP = static_cast<int>(a.ftot[q]);
     const int32_t *fq = a.flat + static_cast<int64_t>(q) * a.Ns * a.K;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -996,6 +1054,9 @@ __device__ __forceinline__ void count_tile(const CountArgs &a, int q, int t, con
         const uint32_t tne = wave_sum_u32(x1), tpos = wave_sum_u32(x2);
         const uint32_t ci = bne + ine - ne, p0 = bpos + ipos - len;
         if (len > 0u) L.dl[ci] = st - p0;
+        if (XL)
+            rw = rw && c0 == 0 && totalP <= CT_CHUNK && tpos <= static_cast<uint32_t>(CT_WT * WAVE) &&
+                 tpos * RW_DENSITY <= static_cast<uint32_t>(vec);
         __syncthreads();
         for (uint32_t seg = 0; seg < tpos; seg += CT_WT * WAVE) {
             const uint32_t seg_end = min(tpos, seg + static_cast<uint32_t>(CT_WT * WAVE));
@@ -1046,9 +1107,20 @@ __device__ __forceinline__ void count_tile(const CountArgs &a, int q, int t, con
                 walk_bump<BITS, HI, true, TR>(L, id, lim, tr);
             }
             __syncthreads();
+            if (XL && rw) {
+                // the only segment: list the tile's ids with count >= lv and
+                // clear every count the walk raised
+                const uint32_t id0 = static_cast<uint32_t>(t) * static_cast<uint32_t>(a.W);
+                for (uint32_t wr = static_cast<uint32_t>(wave); wr < nwin; wr += STRIDE) {
+                    walk_load<true>(a, L, seg, seg_end, nwin, tne, wr, lane, id);
+                    walk_take<BITS>(L, id, lim, lv, xl_dst, xl_cap, xl_shift, id0, lane);
+                }
+                __syncthreads();
+            }
         }
     }
     if (TR) trans_flush<HI>(tr, hsum, lane);
+    return rw;
 }
 
 // Output of the staged lists: slot j of the query's list receives the
@@ -1354,6 +1426,12 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
             if (nl != lv) *la.level = nl;
         }
     }
+    // the list form lists sparse tiles during a re-walk that also clears the
+    // counts (then the next query of this workgroup skips the clear); with
+    // the packed counts stored (stage dumps) it scans instead
+    constexpr bool XL = MODE == CT_LIST;
+    const bool xl = XL && sc == nullptr;
+    bool clean = false;
     for (uint32_t f = f0; f < nrun; f += fstep) {
         const int row = MULTI ? static_cast<int>(blockIdx.y) * a.qpw + static_cast<int>(f)
                               : static_cast<int>(blockIdx.y);
@@ -1361,7 +1439,10 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
         const int q = MODE == CT_REDO ? static_cast<int>(la.redo[3 + f]) : (a.perm ? a.perm[row] : row);
         if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
         if (MODE == CT_LIST && threadIdx.x < 17) lsum[threadIdx.x] = 0u;
-        count_tile<BITS, HI, TR>(a, q, t, L, hsum);
+        uint32_t *xl_dst = xl ? la.list + (static_cast<int64_t>(q) * la.T + t) * la.lcap : nullptr;
+        const bool listed = count_tile<BITS, HI, TR, XL>(a, q, t, L, hsum, xl_dst, static_cast<uint32_t>(la.lcap),
+                                                         la.shift, XL ? list_level(la) : 0u, !clean);
+        clean = listed;
         __syncthreads();
 
         // Level histogram of the tile: hsum[v] = ids with count >= v, so level v
@@ -1376,7 +1457,12 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
             for (int i = threadIdx.x; i < vec; i += CT_BLOCK) __builtin_nontemporal_store(c4v[i], &dstv[i]);
         }
         if (MODE == CT_LIST) {
-            list_tile<BITS, HI>(la, L.cnt, L.wsum, lsum, vec, q, t, a.W, list_level(la), threadIdx.x / WAVE, lane);
+            if (listed) {
+                if (threadIdx.x == 0) la.tcount[static_cast<int64_t>(q) * la.T + t] = *L.lcnt;
+            } else {
+                list_tile<BITS, HI>(la, L.cnt, L.wsum, lsum, vec, q, t, a.W, list_level(la), threadIdx.x / WAVE,
+                                    lane);
+            }
             __syncthreads();
             if (threadIdx.x <= static_cast<unsigned>(a.Ns)) {
                 const uint32_t c = lsum[threadIdx.x];
