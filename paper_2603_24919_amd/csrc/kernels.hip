@@ -1040,24 +1040,46 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
         }
         // compacted index and first position of each non-empty slice
         const uint32_t ne = len > 0u ? 1u : 0u;
-        const uint32_t ine = wave_incl_scan_u32(ne, lane), ipos = wave_incl_scan_u32(len, lane);
-        if (lane == WAVE - 1) {
-            L.wsum[wave] = ine;
-            L.wsum[CT_WAVES + wave] = ipos;
+        uint32_t ci, p0, tne, tpos;
+        if (nsl <= WAVE) {
+            // every slice in wavefront 0: its scans alone, the totals through LDS
+            uint32_t ine = 0u, ipos = 0u;
+            if (wave == 0) {
+                ine = wave_incl_scan_u32(ne, lane);
+                ipos = wave_incl_scan_u32(len, lane);
+                if (len > 0u) L.dl[ine - ne] = st - (ipos - len);
+                if (lane == WAVE - 1) {
+                    L.wsum[0] = ine;
+                    L.wsum[1] = ipos;
+                }
+            }
+            ci = ine - ne;
+            p0 = ipos - len;
+            __syncthreads();
+            tne = L.wsum[0];
+            tpos = L.wsum[1];
+        } else {
+            const uint32_t ine = wave_incl_scan_u32(ne, lane), ipos = wave_incl_scan_u32(len, lane);
+            if (lane == WAVE - 1) {
+                L.wsum[wave] = ine;
+                L.wsum[CT_WAVES + wave] = ipos;
+            }
+            __syncthreads();
+            // lane w holds wavefront w's totals; sums over the lanes below this
+            // wavefront's index give its offsets, over all lanes the chunk's totals
+            const uint32_t x1 = lane < CT_WAVES ? L.wsum[lane] : 0u;
+            const uint32_t x2 = lane < CT_WAVES ? L.wsum[CT_WAVES + lane] : 0u;
+            const uint32_t bne = wave_sum_u32(lane < wave ? x1 : 0u), bpos = wave_sum_u32(lane < wave ? x2 : 0u);
+            tne = wave_sum_u32(x1);
+            tpos = wave_sum_u32(x2);
+            ci = bne + ine - ne;
+            p0 = bpos + ipos - len;
+            if (len > 0u) L.dl[ci] = st - p0;
+            __syncthreads();
         }
-        __syncthreads();
-        // lane w holds wavefront w's totals; sums over the lanes below this
-        // wavefront's index give its offsets, over all lanes the chunk's totals
-        const uint32_t x1 = lane < CT_WAVES ? L.wsum[lane] : 0u;
-        const uint32_t x2 = lane < CT_WAVES ? L.wsum[CT_WAVES + lane] : 0u;
-        const uint32_t bne = wave_sum_u32(lane < wave ? x1 : 0u), bpos = wave_sum_u32(lane < wave ? x2 : 0u);
-        const uint32_t tne = wave_sum_u32(x1), tpos = wave_sum_u32(x2);
-        const uint32_t ci = bne + ine - ne, p0 = bpos + ipos - len;
-        if (len > 0u) L.dl[ci] = st - p0;
         if (XL)
             rw = rw && c0 == 0 && totalP <= CT_CHUNK && tpos <= static_cast<uint32_t>(CT_WT * WAVE) &&
                  tpos * RW_DENSITY <= static_cast<uint32_t>(vec);
-        __syncthreads();
         for (uint32_t seg = 0; seg < tpos; seg += CT_WT * WAVE) {
             const uint32_t seg_end = min(tpos, seg + static_cast<uint32_t>(CT_WT * WAVE));
             for (int i = threadIdx.x; i < 2 * CT_WT; i += CT_BLOCK) L.sb[i] = 0u;
@@ -1269,9 +1291,9 @@ __device__ __forceinline__ void dump_threshold(int32_t *dump_last, int64_t *dump
 // count >= last; other queries are queued, counted again with their packed
 // counts stored (CT_REDO) and take the streaming selection.  The level is
 // fixed, or adapted on the device from batch to batch: up when more than
-// 1/16 of a batch overflowed a tile's list, else down when more than 1/16
-// was queued for last < Lv, up when at least 63/64 had last > Lv.  Results
-// never depend on it.
+// 1/16 of a batch overflowed a tile's list, else down when more than 1/64
+// was queued for last < Lv, up when at least 255/256 had last > Lv.
+// Results never depend on it.
 enum CountForm { CT_STORE = 0, CT_LIST = 1, CT_REDO = 2 };
 
 struct ListArgs {
@@ -1416,12 +1438,13 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
             const uint32_t nq = static_cast<uint32_t>(la.nq);
             uint32_t nl = lv;
             // lists overflowing: list fewer ids; thresholds below the level:
-            // list more; almost all thresholds above it: list fewer
+            // list more (a recount costs far more than longer lists); almost
+            // all thresholds above it: list fewer
             if (no * 16u > nq && lv < static_cast<uint32_t>(a.Ns))
                 nl = lv + 1u;
-            else if ((nf - no) * 16u > nq && lv > 1u)
+            else if ((nf - no) * 64u > nq && lv > 1u)
                 nl = lv - 1u;
-            else if (na * 64u >= nq * 63u && lv < static_cast<uint32_t>(a.Ns))
+            else if (na * 256u >= nq * 255u && lv < static_cast<uint32_t>(a.Ns))
                 nl = lv + 1u;
             if (nl != lv) *la.level = nl;
         }
