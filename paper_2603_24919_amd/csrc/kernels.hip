@@ -1147,10 +1147,22 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
 
 // Output of the staged lists: slot j of the query's list receives the
 // staged value v (the id itself in the candidate lists).
+// Candidate slot writer.  The positions come from an atomic counter; the
+// selection decides from the level histogram that |C| <= cap, but a count
+// the histogram disagrees with (the fused kernel after a timed-out wait,
+// which sets the error word) must not write past the query's cap slots.
 struct CandOut {
     int32_t *cq;
-    __device__ __forceinline__ void operator()(uint32_t j, uint32_t v) const { cq[j] = static_cast<int32_t>(v); }
+    uint32_t cap;
+    __device__ __forceinline__ void operator()(uint32_t j, uint32_t v) const {
+        if (j < cap) cq[j] = static_cast<int32_t>(v);
+    }
 };
+
+// A query's candidate count as the later kernels read it: at most its slots.
+__device__ __forceinline__ int64_t cand_n(const uint32_t *cand_count, int q, int64_t cap) {
+    return min(static_cast<int64_t>(cand_count[q]), cap);
+}
 
 // Move a wavefront's staged entries to the query's list: one atomic to
 // reserve the range, then coalesced stores.
@@ -1595,10 +1607,10 @@ __device__ __forceinline__ void select_query(const SelectArgs &sa, int Ns, int64
                 [&](int i, int b) {
                     return static_cast<uint32_t>(id0 + (i / 2) * PER_WORD + (BITS == 8 ? b : 2 * b + (i % 2)));
                 },
-                stage, scount, counter, CandOut{cq}, lane);
+                stage, scount, counter, CandOut{cq, static_cast<uint32_t>(sa.cap)}, lane);
         }
     }
-    if (__any(scount != 0u)) flush_stage(stage, scount, counter, CandOut{cq}, lane);
+    if (__any(scount != 0u)) flush_stage(stage, scount, counter, CandOut{cq, static_cast<uint32_t>(sa.cap)}, lane);
 }
 
 // Fixed-budget rule, second part: after k_select has listed the points
@@ -1813,7 +1825,8 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
 #pragma unroll
                 for (int u = 0; u < LS_UNROLL; u++) {
                     const uint64_t m = __ballot(v[u] != 0u && (v[u] >> la.shift) >= lu);
-                    if ((m >> lane) & 1u) cq[base + __popcll(m & below)] = static_cast<int32_t>(v[u] & idmask);
+                    const uint32_t j = base + static_cast<uint32_t>(__popcll(m & below));
+                    if (((m >> lane) & 1u) && j < static_cast<uint32_t>(la.cap)) cq[j] = static_cast<int32_t>(v[u] & idmask);
                     base += static_cast<uint32_t>(__popcll(m));
                 }
             }
@@ -1846,7 +1859,8 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
             base = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(base));
 #pragma unroll
             for (int u = 0; u < LS_UNROLL; u++) {
-                if ((m[u] >> lane) & 1u) cq[base + __popcll(m[u] & below)] = static_cast<int32_t>(v[u] & idmask);
+                const uint32_t j = base + static_cast<uint32_t>(__popcll(m[u] & below));
+                if (((m[u] >> lane) & 1u) && j < static_cast<uint32_t>(la.cap)) cq[j] = static_cast<int32_t>(v[u] & idmask);
                 base += static_cast<uint32_t>(__popcll(m[u]));
             }
         }
@@ -2004,9 +2018,10 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count_select(CountArgs a, Selec
                 [&](int i2, int b) {
                     return static_cast<uint32_t>(tile_lo + i * PER_WORD + (BITS == 8 ? b : 2 * b + i2));
                 },
-                stage, scount, sa.cand_count + q, CandOut{cq}, lane);
+                stage, scount, sa.cand_count + q, CandOut{cq, static_cast<uint32_t>(sa.cap)}, lane);
         }
-        if (__any(scount != 0u)) flush_stage(stage, scount, sa.cand_count + q, CandOut{cq}, lane);
+        if (__any(scount != 0u))
+            flush_stage(stage, scount, sa.cand_count + q, CandOut{cq, static_cast<uint32_t>(sa.cap)}, lane);
         __syncthreads();
     }
 }
@@ -2089,7 +2104,7 @@ __global__ __launch_bounds__(256) void k_rerank(const float *__restrict__ Q, int
     const int q = blockIdx.y;
     for (int t = threadIdx.x; t < d; t += BLOCK) qs[t] = Q[static_cast<int64_t>(q) * d + t];
     __syncthreads();
-    const int64_t nc = cand_count[q];
+    const int64_t nc = cand_n(cand_count, q, cap);
     constexpr int RPW = WAVE / LPR;  // rows per wavefront per step
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int sub = lane / LPR, li = lane % LPR;
@@ -2196,7 +2211,7 @@ __global__ __launch_bounds__(256) void k_rerank16(const float *__restrict__ Q, i
     for (int w = 0; w < WAVES; w++) rq2 += rq_part[w];
     // ||q - mu||, inflated for the FP32 roundings of q - mu and of the sum
     const float rq = sqrtf(rq2) * (1.0f + (d + 8) * 0x1p-23f);
-    const int64_t nc = cand_count[q];
+    const int64_t nc = cand_n(cand_count, q, cap);
     constexpr int RPW = WAVE / LPR;
     const int sub = lane / LPR, li = lane % LPR;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVES * RPW;
@@ -2323,7 +2338,7 @@ __global__ __launch_bounds__(256, PLAIN ? 8 : 1) void k_rerank8(const float *__r
     __shared__ float rq_part[WAVES];
     const int q = perm ? perm[blockIdx.y] : static_cast<int>(blockIdx.y), chunk = blockIdx.x;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int64_t nc = cand_count[q];
+    const int64_t nc = cand_n(cand_count, q, cap);
     constexpr int RPW = WAVE / LPR;
     const int sub = lane / LPR, li = lane % LPR;
     const int64_t stride = static_cast<int64_t>(gridDim.x) * WAVES * RPW;
@@ -2794,7 +2809,7 @@ __global__ __launch_bounds__(256) void k_topk(const int32_t *__restrict__ cand,
                                               float *__restrict__ d_out) {
     const int q = blockIdx.x;
     topk_select(q, cand + static_cast<int64_t>(q) * cap, cand_dist + static_cast<int64_t>(q) * cap,
-                cand_count[q], kq ? kq[q] : k_all, k_max, ids_out, d_out);
+                cand_n(cand_count, q, cap), kq ? kq[q] : k_all, k_max, ids_out, d_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -2930,7 +2945,7 @@ __global__ __launch_bounds__(BLOCK) void k_stream_topk(const float *__restrict__
         __syncthreads();
         int32_t *cq = cand + static_cast<int64_t>(q) * cap + s_at;
         float *dq = cand_dist + static_cast<int64_t>(q) * cap + s_at;
-        for (uint32_t i = threadIdx.x; i < m; i += BLOCK) {
+        for (uint32_t i = threadIdx.x; i < m && s_at + i < cap; i += BLOCK) {
             cq[i] = static_cast<int32_t>(static_cast<uint32_t>(buf[i] & 0xffffffffu));
             dq[i] = __uint_as_float(static_cast<uint32_t>(buf[i] >> 32));
         }
@@ -2950,7 +2965,7 @@ __global__ __launch_bounds__(256) void k_topk_queued(const int32_t *__restrict__
     for (uint32_t f = blockIdx.x; f < nov; f += gridDim.x) {
         const int q = static_cast<int>(ovf[1 + f]);
         topk_select(q, cand + static_cast<int64_t>(q) * cap, cand_dist + static_cast<int64_t>(q) * cap,
-                    cand_count[q], kq ? kq[q] : k_all, k_max, ids_out, d_out);
+                    cand_n(cand_count, q, cap), kq ? kq[q] : k_all, k_max, ids_out, d_out);
         __syncthreads();  // topk_select's shared state is reused for the next query
     }
 }
@@ -2993,7 +3008,7 @@ __global__ __launch_bounds__(256) void k_recheck_topk(const float *__restrict__ 
         return;
     }
     for (int t = threadIdx.x; t < d; t += BLOCK) qs[t] = Q[static_cast<int64_t>(q) * d + t];
-    const int64_t nc = cand_count[q];
+    const int64_t nc = cand_n(cand_count, q, cap);
     const int k = kq ? kq[q] : k_all;
     const float tau = tau_d[static_cast<int64_t>(q) * k_max + (k - 1)];  // +inf when |C| < k
     constexpr int RPW = WAVE / LPR;

@@ -455,12 +455,14 @@ int build_tiles(tc_index *x) {
     if (e != hipSuccess) return fail(TC_EDEVICE, std::string("encoding the id lists: ") + hipGetErrorString(e));
     TC_HIP(taco::prepare_count_kernels(x->W, x->bits, x->Ns), "setting LDS size of the count kernels");
     TC_HIP(hipDeviceSynchronize(), "building tile offsets");
-    // How many groups of T co-resident workgroups the fused kernel can keep.
+    // How many groups of T co-resident workgroups the fused kernel can keep:
+    // three quarters of what the occupancy figures allow, so that a few
+    // workgroup slots taken by anything else cannot leave its waits short
     x->fused_groups = 0;
     if (x->coop && taco::fused_lds_bytes(x->W, x->bits) <= size_t(x->max_lds)) {
         int per_cu = 0;
         TC_HIP(taco::fused_max_blocks(x->W, x->bits, x->Ns, &per_cu), "occupancy of the fused kernel");
-        x->fused_groups = per_cu * x->num_cu / x->T;
+        x->fused_groups = per_cu * x->num_cu * 3 / 4 / x->T;
     }
     return TC_OK;
 }
