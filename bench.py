@@ -883,19 +883,43 @@ def summarize_stats(stats_csv, bench_json, out_md, command):
                                      "from top_kernels order by total_duration desc")]
     else:
         rows = list(csv.DictReader(open(stats_csv)))
+    # per-dispatch durations (the kernel_trace.csv beside kernel_stats.csv):
+    # each library kernel's launches of its largest grid, the full batches
+    # the timed steps run (the other launches are sample batches)
+    full = {}
+    trace = stats_csv.replace("kernel_stats.csv", "kernel_trace.csv")
+    if trace != stats_csv and os.path.exists(trace):
+        per = {}
+        for r in csv.DictReader(open(trace)):
+            short = short_kernel_name(r["Kernel_Name"])
+            if not short:
+                continue
+            grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            per.setdefault((r["Kernel_Name"], short), {}).setdefault(grid, []).append(dur)
+        for (name, short), by_grid in per.items():
+            g = max(by_grid)
+            v = by_grid[g]
+            full[name] = (len(v), sum(v) / len(v))
     out = [f"# rocprofv3 kernel statistics: {line['config']['workload']}, alpha={op.get('alpha')}, "
            f"beta={op.get('beta')}, {op['path']} path", "", "Command (from the repository root, TMPDIR=/tmp):", "",
            "```", command, "```", "",
            f"Tuned configuration: {line['config'].get('tuned_config')}", "",
-           "rocprofv3 averages cover every launch of the process (tuning, warm-up, the timed "
-           "steps, the stage-count pass); the bench column is the HIP-event average over the "
-           "eager timed steps only.", "",
-           "| kernel | calls | rocprof avg (us) | bench avg (us) | rocprof total (ms) | % |",
-           "|---|---|---|---|---|---|"]
+           "The first rocprofv3 columns cover every launch of the process (warm-up, the "
+           "timed steps of every sweep point, graph replays, the sample batches of the "
+           "stage-count and error passes); the full-batch columns take, from the per-dispatch "
+           "trace, each kernel's launches at its largest grid, i.e. the full batches of the "
+           "steps; the bench column is the HIP-event average over the eager timed steps of the "
+           "operating point.", "",
+           "| kernel | calls | rocprof avg (us) | full-batch calls | full-batch avg (us) | bench avg (us) "
+           "| rocprof total (ms) | % |",
+           "|---|---|---|---|---|---|---|---|"]
     for r in rows:
         short = short_kernel_name(r["Name"])
         b = ev.get(short, {}).get("ms_per_launch") if short else None
+        fc, fa = full.get(r["Name"], (None, None))
         out.append(f"| {short or r['Name'][:40]} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{'' if fc is None else fc} | {'' if fa is None else f'{fa:.1f}'} | "
                    f"{'' if b is None else f'{b * 1e3:.1f}'} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                    f"{float(r['Percentage']):.1f} |")
     if any(short_kernel_name(r["Name"]) in ("list_select", "recount") for r in rows):
@@ -937,13 +961,16 @@ def summarize_build_stats(stats_csv, line, out_md, command):
 
 
 def _counter_means(csv_path, counter):
+    """Per library kernel, the mean of `counter` over its dispatches at its
+    largest grid (the full batches of the timed steps; sample batches run
+    smaller grids), and every copy dispatch's value."""
     import csv
     per = {}
     copies = []
     if csv_path.endswith(".db"):
         import sqlite3
         con = sqlite3.connect(csv_path)
-        src = [dict(Kernel_Name=r[0], Counter_Name=r[1], Counter_Value=r[2]) for r in
+        src = [dict(Kernel_Name=r[0], Counter_Name=r[1], Counter_Value=r[2], Grid_Size=0) for r in
                con.execute("select kernel_name, counter_name, value from counters_collection")]
     else:
         src = csv.DictReader(open(csv_path))
@@ -956,8 +983,12 @@ def _counter_means(csv_path, counter):
             continue
         short = short_kernel_name(r["Kernel_Name"])
         if short:
-            per.setdefault(short, []).append(v)
-    return {k: (sum(v) / len(v), len(v)) for k, v in per.items()}, copies
+            per.setdefault(short, {}).setdefault(int(r.get("Grid_Size") or 0), []).append(v)
+    out = {}
+    for k, by_grid in per.items():
+        v = by_grid[max(by_grid)]
+        out[k] = (sum(v) / len(v), len(v))
+    return out, copies
 
 
 def summarize_traffic(fetch_csv, write_csv, bench_json, out_json, command, copy_bytes=1 << 30):
@@ -983,6 +1014,46 @@ def summarize_traffic(fetch_csv, write_csv, bench_json, out_json, command, copy_
                copy_fetch_KiB=max(fc) if fc else None, copy_write_KiB=max(wc) if wc else None,
                command=command, kernels=kern)
     json.dump(rec, open(out_json, "w"), indent=1)
+
+
+def summarize_counters(csv_paths, out_md, command):
+    """Markdown table of rocprofv3 --pmc counters per library kernel: the
+    mean over its full-batch dispatches (largest grid), with the derived
+    shares a 256-CU, 8-XCD MI355X gives them (GRBM_GUI_ACTIVE and the SQ
+    counters are summed over the XCDs)."""
+    import csv
+    per = {}
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            short = short_kernel_name(r["Kernel_Name"])
+            if not short:
+                continue
+            key = (short, r["Kernel_Name"].split("(")[0].replace("void ", "")[:48])
+            per.setdefault(key, {}).setdefault(int(r["Grid_Size"]), {}).setdefault(
+                r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    counters = sorted({c for bg in per.values() for g in bg.values() for c in g})
+    out = ["# rocprofv3 counters per kernel (full-batch dispatches)", "",
+           "Commands (from the repository root, TMPDIR=/tmp):", "", "```", command, "```", "",
+           "Means over each kernel's dispatches at its largest grid.  Derived: cycles = "
+           "GRBM_GUI_ACTIVE / 8 (per XCD); VALU issue = SQ_INSTS_VALU / (256 CUs x cycles), one "
+           "wave64 VALU instruction per cycle per CU being the peak; waits = SQ_WAIT_INST_ANY / "
+           "SQ_WAVE_CYCLES; MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / SQ_BUSY_CU_CYCLES.", "",
+           "| kernel | dispatches | " + " | ".join(counters) + " | VALU issue | waits | MFMA busy |",
+           "|---|---|" + "---|" * (len(counters) + 3)]
+    for (short, name), bg in sorted(per.items(), key=lambda kv: -max(
+            v[0] if v else 0 for v in [kv[1][max(kv[1])].get("GRBM_GUI_ACTIVE", [0])])):
+        g = bg[max(bg)]
+        m = {c: sum(v) / len(v) for c, v in g.items()}
+        n = max(len(v) for v in g.values())
+        cyc = m.get("GRBM_GUI_ACTIVE", 0) / 8
+        valu = f"{m['SQ_INSTS_VALU'] / (256 * cyc):.2f}" if cyc and "SQ_INSTS_VALU" in m else ""
+        wait = (f"{m['SQ_WAIT_INST_ANY'] / m['SQ_WAVE_CYCLES']:.2f}"
+                if m.get("SQ_WAVE_CYCLES") and "SQ_WAIT_INST_ANY" in m else "")
+        mf = (f"{m['SQ_VALU_MFMA_BUSY_CYCLES'] / m['SQ_BUSY_CU_CYCLES']:.4f}"
+              if m.get("SQ_BUSY_CU_CYCLES") and "SQ_VALU_MFMA_BUSY_CYCLES" in m else "")
+        out.append(f"| {short} ({name}) | {n} | " + " | ".join(
+            f"{m[c]:.4g}" if c in m else "" for c in counters) + f" | {valu} | {wait} | {mf} |")
+    open(out_md, "w").write("\n".join(out) + "\n")
 
 
 def main():
@@ -1014,6 +1085,7 @@ def main():
                     help="first copy 1 GiB device-to-device (a known-size kernel for counter scaling)")
     ap.add_argument("--summarize-stats", nargs=2, metavar=("KERNEL_STATS_CSV", "BENCH_JSON"))
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"))
+    ap.add_argument("--summarize-counters", nargs="+", metavar="PMC_CSV")
     ap.add_argument("--summary-out")
     ap.add_argument("--summary-command", default="")
     args = ap.parse_args()
@@ -1022,6 +1094,9 @@ def main():
         return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic, args.summary_out, args.summary_command)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.summary_out, args.summary_command)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
