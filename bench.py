@@ -68,7 +68,7 @@ PLANS = {
     "sphere-10m-d96": dict(
         sweep=[(0.002, b) for b in (0.0001, 0.0002, 0.00025, 0.0003)], tune_at=(0.002, 0.0002),
         paths=("fp32", "fp32_tuned", "bf16", "fp8"), main="fp8",
-        cpu_points=[(0.002, b) for b in (0.0002, 0.00025, 0.0003)], cpu_sample=2000),
+        cpu_points=[(0.002, b) for b in (0.0002, 0.00025, 0.0003)], cpu_sample=4000),
     "gmm-int-1m-d128": dict(
         sweep=[(0.05, b) for b in (0.0001, 0.0002, 0.0005, 0.001, 0.005)], tune_at=(0.05, 0.0005),
         paths=("fp32", "tuned", "bf16", "fp8"), main="fp8",
