@@ -223,11 +223,12 @@ def recall_of(ids, gt, X, Qs, k, k_q=None):
     if k_q is None:
         return recall_at_k(ids, gt[k], X, Qs, k)
     big, one = k_q >= 10, k_q == 1
+    m = len(k_q)  # the ground truth may cover more queries than this sample
     tot = 0.0
     if big.any():
-        tot += recall_at_k(ids[big], gt[10][big], X, Qs[big], 10) * big.sum()
+        tot += recall_at_k(ids[big], gt[10][:m][big], X, Qs[big], 10) * big.sum()
     if one.any():
-        tot += recall_at_k(ids[one], gt[1][one], X, Qs[one], 1) * one.sum()
+        tot += recall_at_k(ids[one], gt[1][:m][one], X, Qs[one], 1) * one.sum()
     return tot / float(big.sum() + one.sum())
 
 

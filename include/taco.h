@@ -88,8 +88,8 @@ enum tc_option {
                                Qb: per query n*b/8 bytes of packed counts (b = 4
                                bits when Ns <= 15, else 8), 8*Ns*K of probed
                                cells and 8*S bytes of candidate slots (12*S with
-                               a TC_BF16 or TC_U8 re-rank), S from
-                               TC_OPT_CANDIDATE_SLOTS; default 64 GiB                */
+                               a TC_BF16 or TC_U8 re-rank), S as
+                               TC_OPT_CANDIDATE_SLOTS says; default 64 GiB          */
     TC_OPT_PRECISION = 6,   /* tc_precision of the re-rank; default TC_FP32         */
     TC_OPT_COUNT_MODE = 7,  /* tc_count_mode; default TC_COUNT_AUTO                  */
     TC_OPT_GRAPH = 8,       /* 1: capture each call's launch sequence into a HIP
@@ -112,9 +112,12 @@ enum tc_option {
                                default 1.  More means fewer, longer-lived workgroups
                                where each tile holds few ids (large n, small alpha) */
     TC_OPT_CANDIDATE_SLOTS = 15 /* candidate slots per query S that the batch size is
-                               planned for (>= 0; 0, the default: max(65536, n/128));
-                               at most n.  Alg 5 keeps the whole threshold level,
-                               so |C| is near R = floor(beta*n) but can reach n: a
+                               planned for (>= 0, at most n).  0, the default: Qb
+                               is planned with S = min(n, 65536), then S takes
+                               what the budget leaves after Qb queries' counts
+                               and cells (at most n).  Alg 5 keeps the whole
+                               threshold level, so |C| is near R = floor(beta*n)
+                               but can reach n: a
                                call gives each query cap = min(n, max(S, 4R,
                                32*k_max)) slots from the pool of max(Qb*S, n) and
                                runs min(Qb, pool / cap) queries per batch

@@ -171,6 +171,7 @@ struct tc_index {
     // cand_dist, lb), shared by the batch's queries at a call's stride
     int64_t Qb = 0;
     int64_t pool = 0;
+    int64_t slots = 0;  // candidate slots per query the batches are planned for
     float *qt = nullptr;
     int32_t *cells = nullptr, *ncells = nullptr;
     int64_t *retrieved = nullptr;
@@ -319,34 +320,39 @@ int64_t call_cap(int64_t n, int64_t R, int64_t slots, int k_max) {
         n, std::max<int64_t>(std::max<int64_t>(slots, 4 * R), int64_t(taco::STREAM_SPLIT) * k_max));
 }
 
-// Candidate slots per query the batch size is planned for.
-int64_t plan_slots(const tc_index *x) {
-    const int64_t s = x->cand_slots > 0 ? x->cand_slots : std::max<int64_t>(65536, x->n / 128);
-    return std::min<int64_t>(s, x->n);
-}
+// Candidate slots per query of the allocated scratch (set by alloc_scratch).
+int64_t plan_slots(const tc_index *x) { return x->slots; }
 
-// Per query: the packed counts (which the list form also uses for its
-// lists), the probed cells, and plan_slots() candidate slots (ids and
+// The scratch plan: per query, the packed counts (which the list form also
+// uses for its lists), the probed cells and `slots` candidate slots (ids and
 // distances, and in the bounded re-ranks the lower bounds, which also hold
-// the re-checked ids).  The batch size follows from the scratch budget; the
-// pool holds at least n slots, so that any beta runs (one query per batch
-// at worst).
-int64_t batch_for(const tc_index *x, int64_t *pool) {
-    const int64_t slots = plan_slots(x);
-    int64_t per_q = int64_t(x->T) * x->W * x->bits / 8 + 8 * int64_t(x->Ns) * x->K + 8 * slots;
-    if (x->precision != TC_FP32) per_q += 4 * slots;
-    int64_t qb = x->scratch_budget / per_q;
-    int64_t cap = x->max_batch > 0 ? x->max_batch : 8192;
+// the re-checked ids).  With TC_OPT_CANDIDATE_SLOTS = S, slots = min(S, n)
+// and Qb follows from the budget.  Automatically, Qb follows from the budget
+// with min(n, 65536) slots per query, and the slots then take what the
+// budget leaves (at most n): a query streams only when its candidates
+// outgrow all of that.  The pool holds at least n slots, so that any beta
+// runs (one query per batch at worst).
+int64_t batch_for(const tc_index *x, int64_t *pool, int64_t *slots) {
+    const int64_t fixed = int64_t(x->T) * x->W * x->bits / 8 + 8 * int64_t(x->Ns) * x->K;
+    const int64_t bps = x->precision != TC_FP32 ? 12 : 8;  // bytes per candidate slot
+    int64_t s = x->cand_slots > 0 ? std::min<int64_t>(x->cand_slots, x->n) : std::min<int64_t>(x->n, 65536);
+    int64_t qb = x->scratch_budget / (fixed + bps * s);
+    const int64_t cap = x->max_batch > 0 ? x->max_batch : 8192;
     if (qb > cap) qb = cap;
     if (qb < 1) qb = 1;
-    *pool = std::max<int64_t>(qb * slots, x->n);
+    if (x->cand_slots <= 0) {
+        const int64_t left = x->scratch_budget - qb * fixed;
+        if (left > 0) s = std::max<int64_t>(s, std::min<int64_t>(x->n, left / (bps * qb)));
+    }
+    *slots = s;
+    *pool = std::max<int64_t>(qb * s, x->n);
     return qb;
 }
 
 int alloc_scratch(tc_index *x) {
     free_scratch(x);
-    int64_t pool = 0;
-    const int64_t qb = batch_for(x, &pool);
+    int64_t pool = 0, slots = 0;
+    const int64_t qb = batch_for(x, &pool, &slots);
     int rc;
     if ((rc = dmalloc(&x->qt, size_t(qb) * x->M, "transformed queries"))) return rc;
     if ((rc = dmalloc(&x->cells, size_t(qb) * x->Ns * x->K, "probed cells"))) return rc;
@@ -390,6 +396,7 @@ int alloc_scratch(tc_index *x) {
     }
     x->Qb = qb;
     x->pool = pool;
+    x->slots = slots;
     return TC_OK;
 }
 

@@ -19,6 +19,25 @@ def test_qps_at_recall_frontier():
     assert bench.qps_at_recall([dict(recall=0.5, qps=1.0)], 0.95) is None
 
 
+def test_recall_of_per_query_k_on_a_sample_shorter_than_the_ground_truth():
+    """The oracle's single-thread sample covers fewer queries than the
+    ground truth: recall is read on the sample's rows only."""
+    import numpy as np
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((40, 3)).astype(np.float32)
+    Q = rng.standard_normal((9, 3)).astype(np.float32)
+    d = ((Q[:, None, :].astype(np.float64) - X[None].astype(np.float64)) ** 2).sum(2)
+    order = np.argsort(d, axis=1)
+    gt = {10: np.sort(d, 1)[:, 9], 1: np.sort(d, 1)[:, 0]}
+    k_q = np.array([10, 1, 10, 1, 10], np.int32)  # a 5-query sample of the 9
+    ids = np.full((5, 10), -1, np.int64)
+    for i in range(5):
+        ids[i, :k_q[i]] = order[i, :k_q[i]]
+    assert bench.recall_of(ids, gt, X, Q[:5], 10, k_q) == pytest.approx(1.0)
+    ids[0, 0] = order[0, 20]  # one miss among the three recall@10 queries
+    assert bench.recall_of(ids, gt, X, Q[:5], 10, k_q) == pytest.approx((1.0 - 1.0 / 30) * 3 / 5 + 2 / 5)
+
+
 def test_short_kernel_names():
     f = bench.short_kernel_name
     assert f("void taco::k_count_select<4>(taco::FuseArgs)") == "count_select"
