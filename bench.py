@@ -78,8 +78,8 @@ PLANS = {
         paths=("fp32", "fp32_tuned", "bf16"), main="bf16",
         cpu_points=[(0.2, b) for b in (0.02, 0.05)], cpu_sample=400),
     "zipf-1m-d256": dict(
-        betas=(0.005, 0.01, 0.02, 0.05), tune_beta=0.01, paths=("fp32", "batched"), main="batched",
-        per_query_sample=2000, cpu_sample=2000),
+        betas=(0.005, 0.01, 0.02, 0.05, 0.15), tune_beta=0.01, paths=("fp32", "batched"), main="batched",
+        per_query_sample=2000, cpu_points=[(None, b) for b in (0.02, 0.15)], cpu_sample=2000),
 }
 
 # path -> (centroid-distance form, re-rank precision or None to let the

@@ -77,7 +77,9 @@ enum tc_option {
     TC_OPT_SELECT_RULE = 1, /* tc_select_rule; default TC_RULE_PRINTED                 */
     TC_OPT_MAX_BATCH = 2,   /* max queries per internal batch (>= 1); scratch is
                                re-sized to fit; default: what TC_OPT_SCRATCH_BYTES
-                               allows, at most 8192                                  */
+                               allows, at most 8192.  With automatic candidate
+                               slots the batch stops at 16384 queries and the
+                               rest of the budget goes to slots                      */
     TC_OPT_TILE_IDS = 3,    /* ids per LDS counting tile: a multiple of 1024 whose
                                packed counts (4 bits per id when Ns <= 15, else 8)
                                fit the GPU's LDS per workgroup; default 64 KB of
@@ -113,12 +115,12 @@ enum tc_option {
                                where each tile holds few ids (large n, small alpha) */
     TC_OPT_CANDIDATE_SLOTS = 15 /* candidate slots per query S that the batch size is
                                planned for (>= 0, at most n).  0, the default: Qb
-                               is planned with S = min(n, 65536), then S takes
-                               what the budget leaves after Qb queries' counts
-                               and cells (at most n).  Alg 5 keeps the whole
-                               threshold level, so |C| is near R = floor(beta*n)
-                               but can reach n: a
-                               call gives each query cap = min(n, max(S, 4R,
+                               is planned with S = min(n, 65536) (and at most
+                               16384 queries), then S takes what the budget
+                               leaves after Qb queries' counts and cells (at
+                               most n).  Alg 5 keeps the whole threshold level,
+                               so |C| is near R = floor(beta*n) but can reach n:
+                               a call gives each query cap = min(n, max(S, 8R,
                                32*k_max)) slots from the pool of max(Qb*S, n) and
                                runs min(Qb, pool / cap) queries per batch
                                (tc_batch_capacity); a query with more than cap

@@ -312,12 +312,17 @@ int64_t budget_R(int64_t n, double beta) {
 
 // Candidate slots per query of a call with budget R.  Alg 5 keeps the whole
 // threshold level, so |C| is about R but can reach R + that level's size
-// (up to n); slots for max(slots, 4R) of them, and a query with more is
-// queued for the streamed top-k, whose partial lists need STREAM_SPLIT *
-// k_max of them (the fixed-budget rule takes exactly min(R, ...)).
+// (up to n); slots for max(slots, CAP_PER_R * R) of them, and a query with
+// more is queued for the streamed top-k, whose partial lists need
+// STREAM_SPLIT * k_max of them (the fixed-budget rule takes exactly
+// min(R, ...)).  On mixtures with Zipf-skewed cells, one query in twenty
+// has |C| above 4R at beta = 0.02 and about one in three hundred above 6R;
+// the streamed path reads FP32 rows (four times the bytes of U8 codes), so
+// the extra slots, which only shrink the batch, are the cheaper side.
+constexpr int64_t CAP_PER_R = 8;
 int64_t call_cap(int64_t n, int64_t R, int64_t slots, int k_max) {
     return std::min<int64_t>(
-        n, std::max<int64_t>(std::max<int64_t>(slots, 4 * R), int64_t(taco::STREAM_SPLIT) * k_max));
+        n, std::max<int64_t>(std::max<int64_t>(slots, CAP_PER_R * R), int64_t(taco::STREAM_SPLIT) * k_max));
 }
 
 // Candidate slots per query of the allocated scratch (set by alloc_scratch).
@@ -328,16 +333,21 @@ int64_t plan_slots(const tc_index *x) { return x->slots; }
 // distances, and in the bounded re-ranks the lower bounds, which also hold
 // the re-checked ids).  With TC_OPT_CANDIDATE_SLOTS = S, slots = min(S, n)
 // and Qb follows from the budget.  Automatically, Qb follows from the budget
-// with min(n, 65536) slots per query, and the slots then take what the
-// budget leaves (at most n): a query streams only when its candidates
-// outgrow all of that.  The pool holds at least n slots, so that any beta
-// runs (one query per batch at worst).
+// with min(n, 65536) slots per query, up to QB_FILL queries, and the slots
+// then take what the budget leaves (at most n): a query streams only when
+// its candidates outgrow all of that.  QB_FILL queries already give each
+// launch tens of thousands of workgroups, so a larger batch saves next to
+// nothing while fewer slots send more queries to the streamed path.  The
+// pool holds at least n slots, so that any beta runs (one query per batch
+// at worst).
 int64_t batch_for(const tc_index *x, int64_t *pool, int64_t *slots) {
     const int64_t fixed = int64_t(x->T) * x->W * x->bits / 8 + 8 * int64_t(x->Ns) * x->K;
     const int64_t bps = x->precision != TC_FP32 ? 12 : 8;  // bytes per candidate slot
     int64_t s = x->cand_slots > 0 ? std::min<int64_t>(x->cand_slots, x->n) : std::min<int64_t>(x->n, 65536);
     int64_t qb = x->scratch_budget / (fixed + bps * s);
-    const int64_t cap = x->max_batch > 0 ? x->max_batch : 8192;
+    constexpr int64_t QB_FILL = 16384;
+    int64_t cap = x->max_batch > 0 ? x->max_batch : 8192;
+    if (x->cand_slots <= 0 && cap > QB_FILL) cap = QB_FILL;
     if (qb > cap) qb = cap;
     if (qb < 1) qb = 1;
     if (x->cand_slots <= 0) {

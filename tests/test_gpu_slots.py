@@ -2,7 +2,7 @@
 
 Alg 5 (Section 4.3) keeps the whole threshold level, so a query's candidate
 set |C| = S(last) is about R = floor(beta*n) but can reach n.  A call gives
-each query max(S, 4R, 32*k_max) slots (S = TC_OPT_CANDIDATE_SLOTS); a query
+each query max(S, 8R, 32*k_max) slots (S = TC_OPT_CANDIDATE_SLOTS); a query
 with more candidates skips the slots and takes the streamed FP32 re-rank and
 top-k over its packed counts.  Its results must be bit-identical to the full-slot
 path (cap = n, which the oracle parity tests cover) in every count form,
@@ -79,7 +79,7 @@ def _ncand(taco, path, Q, k, alpha, beta, rule):
 
 def _cap(n, beta, slots, k_max=10):
     R = int(np.floor(beta * n))
-    return min(n, max(slots, 4 * R, 32 * k_max))
+    return min(n, max(slots, 8 * R, 32 * k_max))
 
 
 def _same(a, b, label):
@@ -88,7 +88,7 @@ def _same(a, b, label):
 
 
 @pytest.mark.parametrize("rule", [0, 1])
-@pytest.mark.parametrize("alpha,beta", [(0.2, 0.001), (0.3, 0.0005), (0.01, 0.02)])
+@pytest.mark.parametrize("alpha,beta", [(0.2, 0.001), (0.3, 0.0005), (0.003, 0.005)])
 def test_streamed_topk_equals_full_slots(taco_mod, tiny, rule, alpha, beta):
     t = taco_mod
     Q, path, n = tiny["Q"], tiny["path"], tiny["w"].n
@@ -164,10 +164,10 @@ def test_batched_and_noalloc_stream(taco_mod, tiny):
     t = taco_mod
     Q, path, n = tiny["Q"], tiny["path"], tiny["w"].n
     nq = Q.shape[0]
-    nc = _ncand(t, path, Q, 10, 0.01, 0.02, 0)
-    assert np.any(nc > _cap(n, 0.02, SMALL)), "these settings should overflow some queries"
+    nc = _ncand(t, path, Q, 10, 0.003, 0.005, 0)
+    assert np.any(nc > _cap(n, 0.005, SMALL)), "these settings should overflow some queries"
     rng = np.random.default_rng(5)
-    alpha = np.exp(rng.uniform(np.log(0.005), np.log(0.05), nq))
+    alpha = np.exp(rng.uniform(np.log(0.003), np.log(0.05), nq))
     kk = rng.choice(np.array([1, 10], dtype=np.int32), nq).astype(np.int32)
     q = torch.from_numpy(Q).cuda()
     out = {}
@@ -176,10 +176,10 @@ def test_batched_and_noalloc_stream(taco_mod, tiny):
         try:
             idx.set_option(t.TC_OPT_CANDIDATE_SLOTS, slots)
             ids, d = idx.search_batched(q, torch.from_numpy(alpha).cuda(), torch.from_numpy(kk).cuda(),
-                                        10, 0.02)
+                                        10, 0.005)
             nids = torch.empty((nq, 10), dtype=torch.int64, device="cuda")
             nd = torch.empty((nq, 10), dtype=torch.float32, device="cuda")
-            idx.search_noalloc(q, 10, 0.01, 0.02, nids, nd)
+            idx.search_noalloc(q, 10, 0.003, 0.005, nids, nd)
             torch.cuda.synchronize()
             assert idx.device_errors() == 0
             out[slots] = (ids.cpu().numpy(), d.cpu().numpy(), nids.cpu().numpy(), nd.cpu().numpy())
@@ -188,7 +188,7 @@ def test_batched_and_noalloc_stream(taco_mod, tiny):
     a, b = out[n], out[SMALL]
     _same(a[:2], b[:2], "batched")
     _same(a[2:], b[2:], "noalloc")
-    ref = _search(t, path, Q, 10, 0.01, 0.02, ((t.TC_OPT_CANDIDATE_SLOTS, n),))
+    ref = _search(t, path, Q, 10, 0.003, 0.005, ((t.TC_OPT_CANDIDATE_SLOTS, n),))
     _same(ref, a[2:], "noalloc vs search")
 
 
