@@ -12,7 +12,7 @@ struct CountLaunch {
     const uint32_t *ids;    // the id lists in 4-id groups, every (subspace, cell, tile)
                             // slice padded to whole groups, encoded for the tile width
                             // by launch_encode_ids
-    const uint32_t *off2d;  // [Ns][K][T][2] first and end group of each tile's slice of each
+    const uint32_t *off2d;  // [T][Ns][K][2] first and end group of each tile's slice of each
                             // cell; slices are laid out tile by tile
     const int32_t *flat;    // [nq][Ns*K] probed cells as rows j*K + cell (launch_flatten_cells)
     const uint32_t *ftot;   // [nq] number of probed cells

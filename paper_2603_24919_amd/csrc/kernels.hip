@@ -172,7 +172,7 @@ __global__ void k_build_off2d(const uint32_t *ids, const uint32_t *offs, int Ns,
 // The id lists as the count walk reads them for tile width W.  Every slice
 // (subspace j, cell c, tile t) of the lists is laid out on its own, padded
 // to a whole number of 4-id groups: its first and end group are
-// pad[((j*K + c)*T + t)*2 + {0, 1}] (the host lays the slices out tile by
+// pad[((t*Ns + j)*K + c)*2 + {0, 1}] (the host lays the slices out tile by
 // tile), its ids those of the unpadded positions raw[(j*K + c)*(T+1) + t]
 // up to [.. + t + 1] of k_build_off2d.  An id's tile-local position
 // loc = id mod W becomes (byte offset of its packed word) << 5 | (its bit
@@ -191,7 +191,7 @@ __global__ void k_encode_ids(const uint32_t *__restrict__ ids, const uint32_t *_
     const uint32_t lane = threadIdx.x % WAVE;
     const int64_t jc = sl / T;
     const int t = static_cast<int>(sl % T), j = static_cast<int>(jc / K);
-    const int64_t b = jc * (T + 1) + t, bp = (jc * T + t) * 2;
+    const int64_t b = jc * (T + 1) + t, bp = (static_cast<int64_t>(t) * Ns * K + jc) * 2;
     const uint32_t lo = raw[b], len = raw[b + 1] - lo;
     const uint32_t g0 = pad[bp], m = (pad[bp + 1] - g0) * 4u;
     const uint32_t *src = ids + static_cast<int64_t>(j) * n + lo;
@@ -754,12 +754,13 @@ struct CountArgs {
     int Ns, K, T, W;
     int64_t n;
     const uint32_t *ids;     // padded 4-id groups encoded for the tile width (see k_encode_ids)
-    const uint32_t *off2d;   // [Ns][K][T][2] first and end group of each slice in ids
+    const uint32_t *off2d;   // [T][Ns][K][2] first and end group of each slice in ids
     const int32_t *flat;     // [nq][Ns*K] probed cells as index rows j*K + cell (k_flatten_cells)
     const uint32_t *ftot;    // [nq] probed cells in all subspaces
     const int32_t *perm;     // [nq] query of each grid row (k_query_order), or null
     int nq;                  // queries of the launch
     int qpw;                 // queries per workgroup: grid row y takes rows y*qpw .. y*qpw+qpw-1
+    int xper;                // > 0: one-dimensional grid of 8*xper workgroups in XCD order
 };
 
 // LDS carve-up of k_count (dynamic part).  dl and sb are adjacent (the
@@ -1034,7 +1035,7 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
         uint32_t len = 0u, st = 0u;
         if (static_cast<int>(threadIdx.x) < nsl) {
             const int64_t row = fq[c0 + static_cast<int>(threadIdx.x)];
-            const uint2 se = reinterpret_cast<const uint2 *>(a.off2d)[row * a.T + t];
+            const uint2 se = reinterpret_cast<const uint2 *>(a.off2d)[static_cast<int64_t>(t) * a.Ns * a.K + row];
             st = se.x;
             len = se.y - se.x;
         }
@@ -1433,7 +1434,20 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const CountLds L = carve<BITS>(lds_raw, a.W);
     uint32_t *hsum = L.hsum, *lsum = L.lsum;
-    const int t = blockIdx.x;
+    // (tile t, query row group gy).  In XCD order (a.xper > 0) the T x G units
+    // are numbered tile-major and cut into 8 runs of xper, one per XCD: the
+    // dispatcher deals consecutive workgroups to the 8 XCDs in turn, so
+    // workgroup b runs on XCD b % 8 and takes unit (b % 8)*xper + b/8.  The
+    // workgroups an XCD holds at once then share one or two tiles, whose
+    // lists and slice table stay in that XCD's L2.
+    int t = static_cast<int>(blockIdx.x), gy = static_cast<int>(blockIdx.y);
+    if (MODE != CT_REDO && a.xper > 0) {
+        const uint32_t groups = static_cast<uint32_t>(MULTI ? (a.nq + a.qpw - 1) / a.qpw : a.nq);
+        const uint32_t u = (blockIdx.x % 8u) * static_cast<uint32_t>(a.xper) + blockIdx.x / 8u;
+        if (u >= groups * static_cast<uint32_t>(a.T)) return;  // the padding of the last run
+        t = static_cast<int>(u / groups);
+        gy = static_cast<int>(u % groups);
+    }
     const int lane = threadIdx.x % WAVE;
     const int vec = a.W * BITS / 128;  // 16-byte words per tile
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -1468,8 +1482,7 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
     const bool xl = XL && sc == nullptr;
     bool clean = false;
     for (uint32_t f = f0; f < nrun; f += fstep) {
-        const int row = MULTI ? static_cast<int>(blockIdx.y) * a.qpw + static_cast<int>(f)
-                              : static_cast<int>(blockIdx.y);
+        const int row = MULTI ? gy * a.qpw + static_cast<int>(f) : gy;
         if (MULTI && row >= a.nq) break;
         const int q = MODE == CT_REDO ? static_cast<int>(la.redo[3 + f]) : (a.perm ? a.perm[row] : row);
         if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
@@ -3224,9 +3237,15 @@ hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, int 
     // several queries per workgroup for the list and split forms (not with
     // the list form's level transitions, a stage-dump variant)
     const int qpw = (form == CT_REDO || (form == CT_LIST && l->trans)) ? 1 : std::max(1, c.qpw);
-    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.flat, c.ftot, c.perm, c.nq, qpw};
+    CountArgs a{c.Ns, c.K, c.T, c.W, c.n, c.ids, c.off2d, c.flat, c.ftot, c.perm, c.nq, qpw, 0};
     const ListArgs la = list_args(c, l);
     dim3 grid(c.T, form == CT_REDO ? l->redo_groups : (c.nq + qpw - 1) / qpw);
+    if (form != CT_REDO) {
+        // XCD order (k_count): T x groups units in 8 runs
+        const int64_t units = static_cast<int64_t>(c.T) * ((c.nq + qpw - 1) / qpw);
+        a.xper = static_cast<int>((units + 7) / 8);
+        grid = dim3(static_cast<unsigned>(8 * a.xper), 1);
+    }
     uint4 *s4 = reinterpret_cast<uint4 *>(sc);
     const size_t lds = count_lds_size(c.W, c.bits);
 #define TACO_COUNT(MODE, TR, MULTI)                                                        \

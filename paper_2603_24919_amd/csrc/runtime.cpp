@@ -428,9 +428,10 @@ int build_tiles(tc_index *x) {
         (void)hipFree(raw);
         return fail(TC_EDEVICE, std::string("building tile offsets: ") + hipGetErrorString(e));
     }
-    // (first, end) group of every slice, laid out tile by tile: the
-    // workgroups of one tile, which the grid places on one XCD, then read
-    // one contiguous part of the lists
+    // (first, end) group of every slice, laid out tile by tile, and the
+    // table itself tile-major ([T][Ns][K]): the workgroups of one tile, which
+    // the count grid places on one XCD, then read one contiguous part of the
+    // lists and of the table
     const size_t slices = size_t(x->Ns) * x->K;
     std::vector<uint32_t> pr(slices * x->T * 2);
     uint64_t groups = 0;
@@ -438,7 +439,7 @@ int build_tiles(tc_index *x) {
         for (size_t jc = 0; jc < slices; jc++) {
             const size_t c = jc * (size_t(x->T) + 1);
             const uint32_t len = h[c + t + 1] - h[c + t];
-            const size_t e = (jc * x->T + t) * 2;
+            const size_t e = (size_t(t) * slices + jc) * 2;
             pr[e] = static_cast<uint32_t>(groups);
             groups += (len + 3u) / 4u;
             pr[e + 1] = static_cast<uint32_t>(groups);
