@@ -815,22 +815,34 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// The packed-count word at byte offset off of the counts.  ZB: the kernel
+// has no static LDS, so the dynamic region, and the counts with it, start at
+// LDS address 0 and the offset is the address itself (one add less per
+// increment; prepare_count_kernels checks that k_count has none).
+template <bool ZB>
+__device__ __forceinline__ lds_u32 *count_word(uint32_t *cnt, uint32_t off) {
+    if (ZB) return (lds_u32 *)static_cast<uintptr_t>(off);
+    return (lds_u32 *)(reinterpret_cast<unsigned char *>(cnt) + off);  // an address-space cast
+}
+
 // Adds one to the packed count of an id given in its encoded form (byte
 // offset of its packed word << 5 | its bit position in the word); returns
 // the count it held before.
-template <int BITS>
+template <int BITS, bool ZB = false>
 __device__ __forceinline__ uint32_t bump(uint32_t *cnt, uint32_t enc) {
     const uint32_t sh = enc & 31u;
-    uint32_t *w = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(cnt) + (enc >> 5));
-    const uint32_t old = atomicAdd(w, 1u << sh);
+    const uint32_t old = __hip_atomic_fetch_add(count_word<ZB>(cnt, enc >> 5), 1u << sh, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
     return (old >> sh) & ((1u << BITS) - 1u);
 }
 
 // The same increment when the old count is not needed.
-template <int BITS>
+template <int BITS, bool ZB = false>
 __device__ __forceinline__ void bump_add(uint32_t *cnt, uint32_t enc) {
-    uint32_t *w = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(cnt) + (enc >> 5));
-    atomicAdd(w, 1u << (enc & 31u));
+    __hip_atomic_fetch_add(count_word<ZB>(cnt, enc >> 5), 1u << (enc & 31u), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Level transitions seen by one lane.  Byte c of lo (c < 8) or of hi (c >=
@@ -934,26 +946,26 @@ __device__ __forceinline__ void walk_load(const CountArgs &a, const CountLds &L,
 // The LDS increments of one round (groups of 0xffffffff skipped when
 // GUARD); TR: the old counts feed the level transitions, except those of
 // the pads (codes at or above lim, the dummy words).
-template <int BITS, bool HI, bool TR>
+template <int BITS, bool HI, bool TR, bool ZB>
 __device__ __forceinline__ void bump_one(const CountLds &L, uint32_t enc, uint32_t lim, Trans<HI> &tr) {
     if (TR) {
-        const uint32_t old = bump<BITS>(L.cnt, enc);
+        const uint32_t old = bump<BITS, ZB>(L.cnt, enc);
         if (enc < lim) tr.add(old);
     } else {
-        bump_add<BITS>(L.cnt, enc);
+        bump_add<BITS, ZB>(L.cnt, enc);
     }
 }
 
-template <int BITS, bool HI, bool GUARD, bool TR>
+template <int BITS, bool HI, bool GUARD, bool TR, bool ZB>
 __device__ __forceinline__ void walk_bump(const CountLds &L, const uint4 (&id)[CT_UNROLL], uint32_t lim,
                                           Trans<HI> &tr) {
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) {
         if (!GUARD || id[u].x != 0xffffffffu) {
-            bump_one<BITS, HI, TR>(L, id[u].x, lim, tr);
-            bump_one<BITS, HI, TR>(L, id[u].y, lim, tr);
-            bump_one<BITS, HI, TR>(L, id[u].z, lim, tr);
-            bump_one<BITS, HI, TR>(L, id[u].w, lim, tr);
+            bump_one<BITS, HI, TR, ZB>(L, id[u].x, lim, tr);
+            bump_one<BITS, HI, TR, ZB>(L, id[u].y, lim, tr);
+            bump_one<BITS, HI, TR, ZB>(L, id[u].z, lim, tr);
+            bump_one<BITS, HI, TR, ZB>(L, id[u].w, lim, tr);
         }
     }
 }
@@ -963,7 +975,7 @@ __device__ __forceinline__ void walk_bump(const CountLds &L, const uint4 (&id)[C
 // its final count c; ids with c >= lv are listed as c << shift | id (tile
 // base id0), their positions reserved on L.lcnt one wavefront at a time
 // (only the first lcap are stored) and their levels tallied in L.lsum.
-template <int BITS>
+template <int BITS, bool ZB>
 __device__ __forceinline__ void walk_take(const CountLds &L, const uint4 (&id)[CT_UNROLL], uint32_t lim,
                                           uint32_t lv, uint32_t *dst, uint32_t lcap, int shift, uint32_t id0,
                                           int lane) {
@@ -978,8 +990,10 @@ __device__ __forceinline__ void walk_take(const CountLds &L, const uint4 (&id)[C
             uint32_t c = 0u;
             if (enc < lim) {  // pads and the guard value lie at or above lim
                 const uint32_t sh = enc & 31u;
-                uint32_t *w = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(L.cnt) + (enc >> 5));
-                c = (atomicAnd(w, ~(CMASK << sh)) >> sh) & CMASK;
+                c = (__hip_atomic_fetch_and(count_word<ZB>(L.cnt, enc >> 5), ~(CMASK << sh), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_WORKGROUP) >>
+                     sh) &
+                    CMASK;
             }
             const bool emit = c >= lv && c != 0u;
             const uint64_t m = __ballot(emit);
@@ -1011,7 +1025,7 @@ constexpr uint32_t RW_DENSITY = 4;
 // count >= lv into xl_dst (walk_take; L.lcnt receives their number, L.lsum
 // their levels, lsum zeroed by the caller) and leaves every count zero;
 // returns whether it did.
-template <int BITS, bool HI, bool TR = true, bool XL = false>
+template <int BITS, bool HI, bool TR = true, bool XL = false, bool ZB = false>
 __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, const CountLds &L, uint32_t *hsum,
                                            uint32_t *xl_dst = nullptr, uint32_t xl_cap = 0u, int xl_shift = 0,
                                            uint32_t lv = 0u, bool clear = true) {
@@ -1098,24 +1112,33 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
             const uint32_t nfull = (seg_end - seg) / WAVE;  // windows with all 64 positions in range
             constexpr uint32_t STRIDE = CT_WAVES * CT_UNROLL, SPAN = (CT_UNROLL - 1) * CT_WAVES;
             // rounds whose windows all lie in [0, nfull): software-pipelined,
-            // the next round's ids are in flight during this round's increments
+            // the next round's ids are in flight during this round's
+            // increments; two buffers take turns (no copies between rounds)
             uint32_t w0 = static_cast<uint32_t>(wave);
-            uint4 id[CT_UNROLL];
+            uint4 id[CT_UNROLL], id2[CT_UNROLL];
             bool have = w0 + SPAN < nfull;
             if (have) walk_load<false>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
             while (have) {
-                const uint32_t wn = w0 + STRIDE;
-                const bool nhave = wn + SPAN < nfull;
-                uint4 nid[CT_UNROLL];
-                if (nhave) walk_load<false>(a, L, seg, seg_end, nwin, tne, wn, lane, nid);
+                uint32_t wn = w0 + STRIDE;
+                bool nhave = wn + SPAN < nfull;
+                if (nhave) walk_load<false>(a, L, seg, seg_end, nwin, tne, wn, lane, id2);
                 if (TR && held > 255 - PER_ROUND) {
                     trans_flush<HI>(tr, hsum, lane);
                     held = 0;
                 }
                 held += PER_ROUND;
-                walk_bump<BITS, HI, false, TR>(L, id, lim, tr);
-#pragma unroll
-                for (int u = 0; u < CT_UNROLL; u++) id[u] = nid[u];
+                walk_bump<BITS, HI, false, TR, ZB>(L, id, lim, tr);
+                w0 = wn;
+                if (!nhave) break;
+                wn = w0 + STRIDE;
+                nhave = wn + SPAN < nfull;
+                if (nhave) walk_load<false>(a, L, seg, seg_end, nwin, tne, wn, lane, id);
+                if (TR && held > 255 - PER_ROUND) {
+                    trans_flush<HI>(tr, hsum, lane);
+                    held = 0;
+                }
+                held += PER_ROUND;
+                walk_bump<BITS, HI, false, TR, ZB>(L, id2, lim, tr);
                 w0 = wn;
                 have = nhave;
             }
@@ -1127,7 +1150,7 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
                 }
                 held += PER_ROUND;
                 walk_load<true>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
-                walk_bump<BITS, HI, true, TR>(L, id, lim, tr);
+                walk_bump<BITS, HI, true, TR, ZB>(L, id, lim, tr);
             }
             __syncthreads();
             if (XL && rw) {
@@ -1136,7 +1159,7 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
                 const uint32_t id0 = static_cast<uint32_t>(t) * static_cast<uint32_t>(a.W);
                 for (uint32_t wr = static_cast<uint32_t>(wave); wr < nwin; wr += STRIDE) {
                     walk_load<true>(a, L, seg, seg_end, nwin, tne, wr, lane, id);
-                    walk_take<BITS>(L, id, lim, lv, xl_dst, xl_cap, xl_shift, id0, lane);
+                    walk_take<BITS, ZB>(L, id, lim, lv, xl_dst, xl_cap, xl_shift, id0, lane);
                 }
                 __syncthreads();
             }
@@ -1488,8 +1511,9 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
         if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
         if (MODE == CT_LIST && threadIdx.x < 17) lsum[threadIdx.x] = 0u;
         uint32_t *xl_dst = xl ? la.list + (static_cast<int64_t>(q) * la.T + t) * la.lcap : nullptr;
-        const bool listed = count_tile<BITS, HI, TR, XL>(a, q, t, L, hsum, xl_dst, static_cast<uint32_t>(la.lcap),
-                                                         la.shift, XL ? list_level(la) : 0u, !clean);
+        const bool listed = count_tile<BITS, HI, TR, XL, true>(a, q, t, L, hsum, xl_dst,
+                                                               static_cast<uint32_t>(la.lcap), la.shift,
+                                                               XL ? list_level(la) : 0u, !clean);
         clean = listed;
         __syncthreads();
 
@@ -3202,9 +3226,13 @@ static const void *count_select_kernel(int bits, int Ns) {
 hipError_t prepare_count_kernels(int W, int bits, int Ns) {
     const int bytes = static_cast<int>(count_lds_size(W, bits));
     for (int form : {0, 1, 2, 3, 4, 5}) {
-        hipError_t e = hipFuncSetAttribute(count_kernel(bits, Ns, form),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        const void *k = count_kernel(bits, Ns, form);
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
+        // k_count addresses its counts from LDS address 0 (count_word<true>)
+        hipFuncAttributes fa{};
+        if ((e = hipFuncGetAttributes(&fa, k)) != hipSuccess) return e;
+        if (fa.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
     }
     return hipSuccess;
 }
