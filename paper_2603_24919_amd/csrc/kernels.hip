@@ -973,41 +973,51 @@ __device__ __forceinline__ void walk_bump(const CountLds &L, const uint4 (&id)[C
 // The re-walk of a sparse tile: for each id of the walk once more, an
 // atomic AND takes its count and clears it, so only an id's first visit sees
 // its final count c; ids with c >= lv are listed as c << shift | id (tile
-// base id0), their positions reserved on L.lcnt one wavefront at a time
-// (only the first lcap are stored) and their levels tallied in L.lsum.
+// base id0) and their levels tallied in L.lsum.  Per window, the four ANDs
+// of a lane are issued before any result is used, so their LDS round trips
+// overlap (a pad ANDs all ones into a dummy word of its lane: no change; the
+// round's windows at or past nwin, all empty, take none), and one
+// reservation on L.lcnt per wavefront places the window's listed ids in lane
+// order (only the first lcap are stored).  Every lane of the wavefront calls
+// it (wr is the round's first window).
 template <int BITS, bool ZB>
 __device__ __forceinline__ void walk_take(const CountLds &L, const uint4 (&id)[CT_UNROLL], uint32_t lim,
                                           uint32_t lv, uint32_t *dst, uint32_t lcap, int shift, uint32_t id0,
-                                          int lane) {
+                                          int lane, uint32_t wr, uint32_t nwin) {
     constexpr uint32_t CMASK = (1u << BITS) - 1u;
-    const uint64_t below = lanes_below(lane);
+    const uint32_t dummy = (lim >> 5) + 4u * static_cast<uint32_t>(lane % static_cast<int>(CT_DUMMY));
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) {
-        const uint32_t e4[4] = {id[u].x, id[u].y, id[u].z, id[u].w};
+        if (wr + static_cast<uint32_t>(u * CT_WAVES) >= nwin) break;  // uniform over the wavefront
+        const uint32_t e[4] = {id[u].x, id[u].y, id[u].z, id[u].w};
+        uint32_t c[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-            const uint32_t enc = e4[j];
-            uint32_t c = 0u;
-            if (enc < lim) {  // pads and the guard value lie at or above lim
-                const uint32_t sh = enc & 31u;
-                c = (__hip_atomic_fetch_and(count_word<ZB>(L.cnt, enc >> 5), ~(CMASK << sh), __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_WORKGROUP) >>
-                     sh) &
-                    CMASK;
-            }
-            const bool emit = c >= lv && c != 0u;
-            const uint64_t m = __ballot(emit);
-            if (m != 0ull) {
-                const int leader = __ffsll(static_cast<long long>(m)) - 1;
-                uint32_t at = 0u;
-                if (lane == leader) at = atomicAdd(L.lcnt, static_cast<uint32_t>(__popcll(m)));
-                at = static_cast<uint32_t>(__shfl(static_cast<int>(at), leader, WAVE));
-                if (emit) {
-                    const uint32_t pos = at + static_cast<uint32_t>(__popcll(m & below));
-                    atomicAdd(&L.lsum[c], 1u);
-                    const uint32_t tid = ((enc >> 5) * 8u + (enc & 31u)) / BITS;  // id within the tile
-                    if (pos < lcap) dst[pos] = (c << shift) | (id0 + tid);
-                }
+            const bool real = e[j] < lim;  // pads and the guard value lie at or above lim
+            const uint32_t off = real ? (e[j] >> 5) : dummy;
+            const uint32_t keep = real ? ~(CMASK << (e[j] & 31u)) : 0xffffffffu;
+            c[j] = __hip_atomic_fetch_and(count_word<ZB>(L.cnt, off), keep, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        uint32_t ne = 0u;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            c[j] = e[j] < lim ? (c[j] >> (e[j] & 31u)) & CMASK : 0u;
+            ne += (c[j] >= lv && c[j] != 0u) ? 1u : 0u;
+        }
+        const uint32_t inc = wave_incl_scan_u32(ne, lane);
+        const uint32_t tot = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(inc), WAVE - 1));
+        if (tot == 0u) continue;
+        uint32_t at = 0u;
+        if (lane == 0) at = atomicAdd(L.lcnt, tot);
+        uint32_t pos = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(at))) + inc - ne;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            if (c[j] >= lv && c[j] != 0u) {
+                atomicAdd(&L.lsum[c[j]], 1u);
+                const uint32_t tid = ((e[j] >> 5) * 8u + (e[j] & 31u)) / BITS;  // id within the tile
+                if (pos < lcap) dst[pos] = (c[j] << shift) | (id0 + tid);
+                pos++;
             }
         }
     }
@@ -1159,7 +1169,7 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
                 const uint32_t id0 = static_cast<uint32_t>(t) * static_cast<uint32_t>(a.W);
                 for (uint32_t wr = static_cast<uint32_t>(wave); wr < nwin; wr += STRIDE) {
                     walk_load<true>(a, L, seg, seg_end, nwin, tne, wr, lane, id);
-                    walk_take<BITS, ZB>(L, id, lim, lv, xl_dst, xl_cap, xl_shift, id0, lane);
+                    walk_take<BITS, ZB>(L, id, lim, lv, xl_dst, xl_cap, xl_shift, id0, lane, wr, nwin);
                 }
                 __syncthreads();
             }
