@@ -1055,6 +1055,10 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
     const uint32_t lim = (static_cast<uint32_t>(a.W) * BITS / 8u) << 5;  // first pad code
     for (int c0 = 0; c0 < totalP; c0 += CT_CHUNK) {
         const int nsl = min(CT_CHUNK, totalP - c0);
+        // the start bitmap of the chunk's first segment, cleared ahead of the
+        // slice barriers below (its last reader, the previous walk, ended at
+        // a barrier)
+        for (int i = threadIdx.x; i < 2 * CT_WT; i += CT_BLOCK) L.sb[i] = 0u;
         // this thread's slice
         uint32_t len = 0u, st = 0u;
         if (static_cast<int>(threadIdx.x) < nsl) {
@@ -1107,8 +1111,10 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
                  tpos * RW_DENSITY <= static_cast<uint32_t>(vec);
         for (uint32_t seg = 0; seg < tpos; seg += CT_WT * WAVE) {
             const uint32_t seg_end = min(tpos, seg + static_cast<uint32_t>(CT_WT * WAVE));
-            for (int i = threadIdx.x; i < 2 * CT_WT; i += CT_BLOCK) L.sb[i] = 0u;
-            __syncthreads();
+            if (seg != 0u) {  // (the first segment's bitmap was cleared before the slice barriers)
+                for (int i = threadIdx.x; i < 2 * CT_WT; i += CT_BLOCK) L.sb[i] = 0u;
+                __syncthreads();
+            }
             // window table and start bitmap of this segment: every window
             // start (a multiple of 64) lies in exactly one non-empty slice
             if (len > 0u) {
@@ -1525,7 +1531,9 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
                                                                static_cast<uint32_t>(la.lcap), la.shift,
                                                                XL ? list_level(la) : 0u, !clean);
         clean = listed;
-        __syncthreads();
+        // count_tile ends at a barrier after its last LDS count access; the
+        // level transitions (TR) add to hsum after it
+        if (TR || !listed) __syncthreads();
 
         // Level histogram of the tile: hsum[v] = ids with count >= v, so level v
         // holds hsum[v] - hsum[v+1].  Ids past n hold 0 and count nowhere.
@@ -1545,7 +1553,8 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
                 list_tile<BITS, HI>(la, L.cnt, L.wsum, lsum, vec, q, t, a.W, list_level(la), threadIdx.x / WAVE,
                                     lane);
             }
-            __syncthreads();
+            // a re-walk's level tallies are complete at count_tile's last barrier
+            if (!listed) __syncthreads();
             if (threadIdx.x <= static_cast<unsigned>(a.Ns)) {
                 const uint32_t c = lsum[threadIdx.x];
                 if (la.tlev) la.tlev[(static_cast<int64_t>(q) * a.T + t) * (a.Ns + 1) + threadIdx.x] = c;
@@ -1554,7 +1563,12 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
                     atomicAdd(&hist[static_cast<int64_t>(q) * (a.Ns + 1) + threadIdx.x], c);
             }
         }
-        if (MODE == CT_REDO || MULTI) __syncthreads();  // the next query clears the counts and sums read above
+        // the next query clears the counts and sums read above.  After a
+        // re-walk (counts left zero) without transitions, nothing read here
+        // is written before the next query's own barriers: lcnt and lsum[v]
+        // are cleared by the threads that read them, the rest by count_tile
+        // ahead of its barriers
+        if (MODE == CT_REDO || (MULTI && (TR || !listed))) __syncthreads();
     }
 }
 
