@@ -74,11 +74,11 @@ PLANS = {
         paths=("fp32", "tuned", "bf16", "fp8"), main="fp8",
         cpu_points=[(0.05, b) for b in (0.0001, 0.0002, 0.0005, 0.001)], cpu_sample=4000),
     "aniso-1m-d960": dict(
-        sweep=[(a, b) for a in (0.1, 0.2, 0.3) for b in (0.01, 0.02, 0.05)], tune_at=(0.2, 0.02),
+        sweep=[(a, b) for a in (0.1, 0.2, 0.3) for b in (0.01, 0.02, 0.05)], tune_at=(0.2, 0.05),
         paths=("fp32", "fp32_tuned", "bf16"), main="bf16",
         cpu_points=[(0.2, b) for b in (0.02, 0.05)], cpu_sample=400),
     "zipf-1m-d256": dict(
-        betas=(0.005, 0.01, 0.02, 0.05, 0.15), tune_beta=0.01, paths=("fp32", "batched"), main="batched",
+        betas=(0.005, 0.01, 0.02, 0.05, 0.15), tune_beta=0.05, paths=("fp32", "batched"), main="batched",
         per_query_sample=2000, cpu_points=[(None, b) for b in (0.02, 0.15)], cpu_sample=2000),
 }
 
