@@ -1589,7 +1589,7 @@ int tune(tc_index *x, const std::string &key, const std::function<int()> &once, 
         if (ms < best_ms) best_ms = ms, best = c;
     }
     if (best.mode == TC_COUNT_SPLIT || best.mode == TC_COUNT_LIST) {
-        for (int cq : {2, 4, 8, 16}) {
+        for (int cq : {2, 4, 8, 16, 32}) {
             TuneConfig c = best;
             c.cqpw = cq;
             double ms;
