@@ -80,12 +80,13 @@ hipError_t launch_probe(const float *qt, int nq, int Ns, int M, int s, int h1, i
 // Reduced-precision centroid distances: the block-diagonal centroid matrix
 // (transposed, Kp = M rounded up to 32 columns; bf16 or e4m3 with per-
 // subspace scales csc) and its FP32 norms, then per batch the distances
-// cd[nq][Ns][2][l] (qn [nq][Ns][2], qsc [nq][Ns] are scratch).
+// cd[nq][Ns][2][l] (qn [nq][Ns][2], qsc [nq][Ns] and the operand rows qa [nq][Kp] (bytes for
+// FP8, 16-bit values for BF16) are scratch).
 hipError_t launch_prep_centroids(const float *C1, const float *C2, int Ns, int s, int h1, int h2, int l,
                                  int Kp, bool fp8, const float *csc, void *cT, float *cnorm, hipStream_t st);
 hipError_t launch_cdist_mfma(const float *qt, int nq, int M, int Ns, int s, int h1, int h2, int l, int Kp,
                              bool fp8, const void *cT, const float *cnorm, const float *csc, float *qn,
-                             float *qsc, float *cd, hipStream_t st);
+                             float *qsc, void *qa, float *cd, hipStream_t st);
 hipError_t launch_budgets(const double *alpha, const int32_t *kq, int nq, int64_t n, int k_max,
                           int64_t *A, int32_t *kc, uint32_t *err, hipStream_t st);
 hipError_t prepare_count_kernels(int W, int bits, int Ns);

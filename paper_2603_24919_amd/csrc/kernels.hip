@@ -297,10 +297,13 @@ __device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) {
 
 // Per (query, subspace): the two half norms |x_h|^2 (one fma per term,
 // ascending) and the FP8 query scale max|x| / 240 (1 when the half values
-// are all zero).  grid ceil(nq*Ns/256), block 256.
+// are all zero); and the query's operand row of the contraction, qa[q][k]
+// for k < Kp (zero from M on): e4m3 of x / scale (FP8) or the BF16 of x.
+// grid ceil(nq*Ns/256), block 256.
+template <bool FP8>
 __global__ __launch_bounds__(256) void k_qstats(const float *__restrict__ qt, int nq, int Ns, int M,
-                                                int s, int h1, float *__restrict__ qn,
-                                                float *__restrict__ qsc) {
+                                                int s, int h1, int Kp, float *__restrict__ qn,
+                                                float *__restrict__ qsc, void *__restrict__ qa) {
     const int64_t t = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (t >= static_cast<int64_t>(nq) * Ns) return;
     const int64_t q = t / Ns;
@@ -317,7 +320,16 @@ __global__ __launch_bounds__(256) void k_qstats(const float *__restrict__ qt, in
     }
     qn[t * 2] = n1;
     qn[t * 2 + 1] = n2;
-    qsc[t] = mx > 0.0f ? mx / FP8_RANGE : 1.0f;
+    const float sc = mx > 0.0f ? mx / FP8_RANGE : 1.0f;
+    qsc[t] = sc;
+    const int k_end = j == Ns - 1 ? Kp : (j + 1) * s;  // the last subspace also writes the zero tail
+    for (int k = j * s; k < k_end; k++) {
+        const float v = k < M ? qt[q * M + k] : 0.0f;
+        if (FP8)
+            reinterpret_cast<uint8_t *>(qa)[q * Kp + k] = static_cast<uint8_t>(fp8x4(v / sc, 0.0f, 0.0f, 0.0f));
+        else
+            reinterpret_cast<uint16_t *>(qa)[q * Kp + k] = bf16_rne(v);
+    }
 }
 
 // Column col = (j*2 + h)*l + c of the block-diagonal centroid matrix, stored
@@ -368,7 +380,8 @@ __global__ __launch_bounds__(256) void k_cdist_mfma(const float *__restrict__ qt
                                                     int s, int h1, int h2, int l, int Kp,
                                                     const void *__restrict__ cT, const float *__restrict__ cnorm,
                                                     const float *__restrict__ csc, const float *__restrict__ qn,
-                                                    const float *__restrict__ qsc, float *__restrict__ cd) {
+                                                    const float *__restrict__ qsc, const void *__restrict__ qa,
+                                                    float *__restrict__ cd) {
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int ncol = Ns * 2 * l;
     const int n0 = (blockIdx.x * 4 + wave) * 16;
@@ -380,25 +393,17 @@ __global__ __launch_bounds__(256) void k_cdist_mfma(const float *__restrict__ qt
     const int k_lo = (jf * s + (hf ? h1 : 0)) / 32 * 32;
     const int k_hi = min(Kp, (jl * s + (hl ? s : h1) + 31) / 32 * 32);
     const int r = lane % 16, kq8 = 8 * (lane / 16);
-    const int qa = q0 + r;                     // this lane's query row of A
+    const int qrow = q0 + r;                   // this lane's query row of A
     const int colb = min(n0 + r, ncol - 1);    // this lane's column of B
     f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
     for (int k0 = k_lo; k0 < k_hi; k0 += 32) {
         const int kb = k0 + kq8;
-        float a[8];
-#pragma unroll
-        for (int e = 0; e < 8; e++) a[e] = (qa < nq && kb + e < M) ? qt[static_cast<int64_t>(qa) * M + kb + e] : 0.0f;
+        // A: this lane's 8 operand values of its query row (k_qstats: each
+        // value already scaled by its own (query, subspace) factor in FP8)
         if (FP8) {
-            // the A values of this lane lie in subspaces (kb)/s .. (kb+7)/s;
-            // each is scaled by its own (query, subspace) factor
-            float sa[8];
-#pragma unroll
-            for (int e = 0; e < 8; e++) {
-                const int jj = min((kb + e) / s, Ns - 1);
-                sa[e] = a[e] / (qa < nq ? qsc[static_cast<int64_t>(qa) * Ns + jj] : 1.0f);
-            }
-            const uint32_t lo = fp8x4(sa[0], sa[1], sa[2], sa[3]), hi = fp8x4(sa[4], sa[5], sa[6], sa[7]);
-            const long av = static_cast<long>((static_cast<uint64_t>(hi) << 32) | lo);
+            const long av = qrow < nq ? *reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(qa) +
+                                                                       static_cast<int64_t>(qrow) * Kp + kb)
+                                      : 0l;
             const long bv = *reinterpret_cast<const long *>(reinterpret_cast<const uint8_t *>(cT) +
                                                             static_cast<int64_t>(colb) * Kp + kb);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
@@ -406,10 +411,10 @@ __global__ __launch_bounds__(256) void k_cdist_mfma(const float *__restrict__ qt
             bf16x8_t av, bv;
             const uint16_t *bp = reinterpret_cast<const uint16_t *>(cT) + static_cast<int64_t>(colb) * Kp + kb;
             const uint4 braw = *reinterpret_cast<const uint4 *>(bp);
-            uint16_t ab[8];
-#pragma unroll
-            for (int e = 0; e < 8; e++) ab[e] = bf16_rne(a[e]);
-            __builtin_memcpy(&av, ab, 16);
+            const uint4 araw = qrow < nq ? *reinterpret_cast<const uint4 *>(reinterpret_cast<const uint16_t *>(qa) +
+                                                                           static_cast<int64_t>(qrow) * Kp + kb)
+                                         : make_uint4(0u, 0u, 0u, 0u);
+            __builtin_memcpy(&av, &araw, 16);
             __builtin_memcpy(&bv, &braw, 16);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
         }
@@ -3200,16 +3205,20 @@ hipError_t launch_prep_centroids(const float *C1, const float *C2, int Ns, int s
 
 hipError_t launch_cdist_mfma(const float *qt, int nq, int M, int Ns, int s, int h1, int h2, int l, int Kp,
                              bool fp8, const void *cT, const float *cnorm, const float *csc, float *qn,
-                             float *qsc, float *cd, hipStream_t st) {
+                             float *qsc, void *qa, float *cd, hipStream_t st) {
     if (nq <= 0) return hipSuccess;
     const int64_t pairs = static_cast<int64_t>(nq) * Ns;
-    k_qstats<<<static_cast<unsigned>((pairs + 255) / 256), 256, 0, st>>>(qt, nq, Ns, M, s, h1, qn, qsc);
+    const unsigned qblocks = static_cast<unsigned>((pairs + 255) / 256);
+    if (fp8)
+        k_qstats<true><<<qblocks, 256, 0, st>>>(qt, nq, Ns, M, s, h1, Kp, qn, qsc, qa);
+    else
+        k_qstats<false><<<qblocks, 256, 0, st>>>(qt, nq, Ns, M, s, h1, Kp, qn, qsc, qa);
     const int ncol = Ns * 2 * l;
     dim3 grid((ncol + 63) / 64, (nq + 15) / 16);
     if (fp8)
-        k_cdist_mfma<true><<<grid, 256, 0, st>>>(qt, nq, M, Ns, s, h1, h2, l, Kp, cT, cnorm, csc, qn, qsc, cd);
+        k_cdist_mfma<true><<<grid, 256, 0, st>>>(qt, nq, M, Ns, s, h1, h2, l, Kp, cT, cnorm, csc, qn, qsc, qa, cd);
     else
-        k_cdist_mfma<false><<<grid, 256, 0, st>>>(qt, nq, M, Ns, s, h1, h2, l, Kp, cT, cnorm, csc, qn, qsc, cd);
+        k_cdist_mfma<false><<<grid, 256, 0, st>>>(qt, nq, M, Ns, s, h1, h2, l, Kp, cT, cnorm, csc, qn, qsc, qa, cd);
     return hipGetLastError();
 }
 

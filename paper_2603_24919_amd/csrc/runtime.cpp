@@ -209,6 +209,7 @@ struct tc_index {
     int cT_form = TC_CDIST_FP32; // form cT currently holds
     std::vector<float> C1h, C2h; // host copies of the centroids
     float *qn = nullptr, *qsc = nullptr, *cd = nullptr;  // per-batch scratch
+    uint16_t *qa = nullptr;  // [Qb][M rounded up to 32] contraction operand rows (BF16, or e4m3 bytes)
     // SC-Linear (built on first use): transformed base [n][M], subspace
     // distances [scQ][Ns][n] and per-(query, subspace) thresholds
     float *sct = nullptr, *scD = nullptr;
@@ -260,6 +261,7 @@ void free_scratch(tc_index *x) {
     (void)hipFree(x->tau_d);
     (void)hipFree(x->qn);
     (void)hipFree(x->qsc);
+    (void)hipFree(x->qa);
     (void)hipFree(x->cd);
     (void)hipFree(x->lvl);
     x->lvl = nullptr;
@@ -276,6 +278,7 @@ void free_scratch(tc_index *x) {
     (void)hipFree(x->ftot);
     x->ftot = nullptr;
     x->qn = x->qsc = x->cd = nullptr;
+    x->qa = nullptr;
     x->sc = nullptr;
     x->lb = nullptr;
     x->rk_count = nullptr;
@@ -396,6 +399,7 @@ int alloc_scratch(tc_index *x) {
     if ((rc = dmalloc(&x->qn, size_t(qb) * x->Ns * 2, "query half norms"))) return rc;
     if ((rc = dmalloc(&x->qsc, size_t(qb) * x->Ns, "query scales"))) return rc;
     if ((rc = dmalloc(&x->cd, size_t(qb) * x->Ns * 2 * x->l, "centroid distances"))) return rc;
+    if ((rc = dmalloc(&x->qa, size_t(qb) * ((x->M + 31) / 32 * 32), "query operand rows"))) return rc;
     if (x->precision != TC_FP32) {
         if ((rc = dmalloc(&x->lb, size_t(pool), "distance lower bounds"))) return rc;
         if ((rc = dmalloc(&x->rk_count, size_t(qb), "re-check counts"))) return rc;
@@ -830,6 +834,7 @@ struct Scratch {
     uint32_t *rk_count = nullptr, *exact = nullptr, *qinfo = nullptr;
     int64_t *tau_ids = nullptr;
     float *tau_d = nullptr, *qn = nullptr, *qsc = nullptr, *cd = nullptr;
+    uint16_t *qa = nullptr;
 };
 
 Scratch own_scratch(const tc_index *x) {
@@ -866,6 +871,7 @@ Scratch own_scratch(const tc_index *x) {
     S.qn = x->qn;
     S.qsc = x->qsc;
     S.cd = x->cd;
+    S.qa = x->qa;
     return S;
 }
 
@@ -930,7 +936,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             rec(K_CDIST, st, true);
             TC_HIP(taco::launch_cdist_mfma(S.qt, nb, x->M, x->Ns, x->s, x->h1, x->h2, x->l, x->Kp,
                                            cdist == TC_CDIST_FP8, x->cT, x->cnorm, x->csc, S.qn,
-                                           S.qsc, S.cd, st),
+                                           S.qsc, S.qa, S.cd, st),
                    "centroid distance kernel");
             rec(K_CDIST, st, false);
             pre = S.cd;
