@@ -113,7 +113,7 @@ enum tc_option {
                                tile (split and list forms): 1, 2, 4, 8, 16 or 32;
                                default 1.  More means fewer, longer-lived workgroups
                                where each tile holds few ids (large n, small alpha) */
-    TC_OPT_CANDIDATE_SLOTS = 15 /* candidate slots per query S that the batch size is
+    TC_OPT_CANDIDATE_SLOTS = 15, /* candidate slots per query S that the batch size is
                                planned for (>= 0, at most n).  0, the default: Qb
                                is planned with S = min(n, 65536) (and at most
                                16384 queries), then S takes what the budget
@@ -127,6 +127,11 @@ enum tc_option {
                                candidates takes a streamed FP32 re-rank and top-k
                                over its collision counts instead (same results;
                                kernel time "stream")                                 */
+    TC_OPT_COUNT_BLOCK = 16 /* threads per counting workgroup of the split and list
+                               forms: 1024 (the default; sixteen wavefronts, 64
+                               registers each) or 768 (twelve, 80 registers):
+                               fewer, roomier wavefronts pay where each tile holds
+                               few ids.  Results do not depend on it             */
 };
 
 /* How collision counting and candidate selection are launched.

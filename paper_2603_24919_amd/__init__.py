@@ -24,7 +24,7 @@ __all__ = [
     "TC_OPT_CDIST_PRECISION", "TC_CDIST_FP32", "TC_CDIST_BF16", "TC_CDIST_FP8", "TC_U8",
     "tc_device_errors", "tc_search_batched", "tc_autotune", "tc_autotune_batched", "tc_search_noalloc",
     "tc_search_sclinear",
-    "TC_OPT_TUNE_PRECISION", "TC_OPT_COUNT_QPW", "TC_OPT_CANDIDATE_SLOTS",
+    "TC_OPT_TUNE_PRECISION", "TC_OPT_COUNT_QPW", "TC_OPT_CANDIDATE_SLOTS", "TC_OPT_COUNT_BLOCK",
     "TacoError", "TacoLibraryMissing", "lib_path", "load_library",
     "tc_load_index", "tc_free_index", "tc_index_info", "tc_set_option", "tc_search",
     "tc_search_debug", "tc_kernel_time", "tc_profile_reset", "tc_batch_capacity",
@@ -42,6 +42,7 @@ TC_OPT_LIST_LEVEL = 12
 TC_OPT_TUNE_PRECISION = 13
 TC_OPT_COUNT_QPW = 14
 TC_OPT_CANDIDATE_SLOTS = 15
+TC_OPT_COUNT_BLOCK = 16
 TC_OPT_GRAPH, TC_OPT_PROBE_QPW, TC_OPT_RERANK_BLOCKS = 8, 9, 10
 TC_OPT_CDIST_PRECISION = 11
 TC_CDIST_FP32, TC_CDIST_BF16, TC_CDIST_FP8 = 0, 1, 2

@@ -18,6 +18,7 @@ struct CountLaunch {
     const uint32_t *ftot;   // [nq] number of probed cells
     const int32_t *perm = nullptr;  // [nq] order in which the count takes the queries, or null
     int qpw = 1;                    // queries per count workgroup (split and list forms)
+    int nt = 1024;                  // threads per count workgroup: 768 or 1024 (not the fused form)
 };
 
 struct SelectLaunch {

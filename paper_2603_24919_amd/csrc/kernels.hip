@@ -748,11 +748,14 @@ __global__ __launch_bounds__(ORD_BLOCK) void k_cost_order(const int64_t *__restr
 #ifndef TACO_CT_UNROLL
 #define TACO_CT_UNROLL 2
 #endif
-constexpr int CT_BLOCK = TACO_CT_BLOCK;
+constexpr int CT_BLOCK = TACO_CT_BLOCK;         // threads of the fused kernel's workgroups and the
+                                                // default of k_count's (its NT: 768 or 1024)
 constexpr int CT_UNROLL = TACO_CT_UNROLL;       // windows (groups per lane) in flight per wavefront
 constexpr int CT_WAVES = CT_BLOCK / WAVE;
 constexpr int CT_CHUNK = CT_BLOCK;              // slices staged at a time, one per thread
-constexpr int CT_WT = 512;                      // windows per position segment
+constexpr int CT_WT = CT_BLOCK / 2;             // windows per position segment
+// Functions templated on the workgroup size NT shadow these four with
+// NT, NT / WAVE, NT and NT / 2.
 constexpr int CT_STAGE = 256;                   // per-wavefront candidate staging slots
 
 struct CountArgs {
@@ -773,7 +776,7 @@ struct CountArgs {
 struct CountLds {
     uint32_t *cnt;    // W*BITS/32 words of packed counts, then CT_DUMMY words that
                       // the pads of the id lists increment
-    uint32_t *dl;     // [CT_CHUNK] start (group of ids) minus first position, per
+    uint32_t *dl;     // [CT_CHUNK] (NT) start (group of ids) minus first position, per
                       // non-empty slice: position p of the slice is group dl + p
     uint32_t *sb;     // [2 * CT_WT] of a region of CT_CHUNK + 1 words: bit p - 1 of
                       // the segment is set when a non-empty slice starts at position
@@ -788,14 +791,16 @@ struct CountLds {
 static_assert(2 * CT_WT <= CT_CHUNK + 1, "the start bitmap must fit its region");
 static_assert(CT_CHUNK % 2 == 0, "the start bitmap is read in 64-bit words");
 
-__host__ __device__ constexpr size_t count_lds_size(int W, int bits) {
-    return static_cast<size_t>(W) * bits / 8 + CT_DUMMY * 4 + static_cast<size_t>(CT_CHUNK) * 4 +
-           static_cast<size_t>(CT_CHUNK + 1) * 4 + static_cast<size_t>(CT_WT) * 2 +
-           2 * CT_WAVES * 4 + (18 + 17 + 1) * 4;
+// Dynamic LDS of the count kernels with workgroups of nt threads.
+__host__ __device__ constexpr size_t count_lds_size(int W, int bits, int nt = CT_BLOCK) {
+    return static_cast<size_t>(W) * bits / 8 + CT_DUMMY * 4 + static_cast<size_t>(nt) * 4 +
+           static_cast<size_t>(nt + 1) * 4 + static_cast<size_t>(nt / 2) * 2 + 2 * (nt / WAVE) * 4 +
+           (18 + 17 + 1) * 4;
 }
 
-template <int BITS>
+template <int BITS, int NT = CT_BLOCK>
 __device__ __forceinline__ CountLds carve(unsigned char *lds, int W) {
+    constexpr int CT_WAVES = NT / WAVE, CT_CHUNK = NT, CT_WT = NT / 2;
     CountLds c;
     c.cnt = reinterpret_cast<uint32_t *>(lds);
     c.dl = c.cnt + W / (32 / BITS) + CT_DUMMY;
@@ -916,10 +921,11 @@ __device__ __forceinline__ void ge_masks(uint32_t w, uint32_t v, uint32_t &m0, u
 // at or before the lane's: the bits below the lane in the window's 64-bit
 // word of the start bitmap (stored one position down), one masked count.  GUARD: some windows or positions of
 // the round lie past the segment; otherwise no lane needs a bounds test.
-template <bool GUARD>
+template <bool GUARD, int NT = CT_BLOCK>
 __device__ __forceinline__ void walk_load(const CountArgs &a, const CountLds &L, uint32_t seg,
                                           uint32_t seg_end, uint32_t nwin, uint32_t tne, uint32_t w0,
                                           int lane, uint4 (&id)[CT_UNROLL]) {
+    constexpr int CT_WAVES = NT / WAVE;
     uint32_t e[CT_UNROLL];
 #pragma unroll
     for (int u = 0; u < CT_UNROLL; u++) {
@@ -985,10 +991,11 @@ __device__ __forceinline__ void walk_bump(const CountLds &L, const uint4 (&id)[C
 // reservation on L.lcnt per wavefront places the window's listed ids in lane
 // order (only the first lcap are stored).  Every lane of the wavefront calls
 // it (wr is the round's first window).
-template <int BITS, bool ZB>
+template <int BITS, bool ZB, int NT = CT_BLOCK>
 __device__ __forceinline__ void walk_take(const CountLds &L, const uint4 (&id)[CT_UNROLL], uint32_t lim,
                                           uint32_t lv, uint32_t *dst, uint32_t lcap, int shift, uint32_t id0,
                                           int lane, uint32_t wr, uint32_t nwin) {
+    constexpr int CT_WAVES = NT / WAVE;
     constexpr uint32_t CMASK = (1u << BITS) - 1u;
     const uint32_t dummy = (lim >> 5) + 4u * static_cast<uint32_t>(lane % static_cast<int>(CT_DUMMY));
 #pragma unroll
@@ -1040,10 +1047,12 @@ constexpr uint32_t RW_DENSITY = 4;
 // count >= lv into xl_dst (walk_take; L.lcnt receives their number, L.lsum
 // their levels, lsum zeroed by the caller) and leaves every count zero;
 // returns whether it did.
-template <int BITS, bool HI, bool TR = true, bool XL = false, bool ZB = false>
+template <int BITS, bool HI, bool TR = true, bool XL = false, bool ZB = false, int NT = CT_BLOCK>
 __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, const CountLds &L, uint32_t *hsum,
                                            uint32_t *xl_dst = nullptr, uint32_t xl_cap = 0u, int xl_shift = 0,
                                            uint32_t lv = 0u, bool clear = true) {
+    constexpr int CT_BLOCK = NT, CT_WAVES = NT / WAVE, CT_CHUNK = NT, CT_WT = NT / 2;
+    static_assert(2 * CT_WT <= CT_CHUNK + 1 && CT_CHUNK % 2 == 0, "the start bitmap must fit its region");
     const int vec = a.W * BITS / 128;  // 16-byte words of counts
     if (clear)
         for (int i = threadIdx.x; i < vec; i += CT_BLOCK)
@@ -1138,11 +1147,11 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
             uint32_t w0 = static_cast<uint32_t>(wave);
             uint4 id[CT_UNROLL], id2[CT_UNROLL];
             bool have = w0 + SPAN < nfull;
-            if (have) walk_load<false>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
+            if (have) walk_load<false, NT>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
             while (have) {
                 uint32_t wn = w0 + STRIDE;
                 bool nhave = wn + SPAN < nfull;
-                if (nhave) walk_load<false>(a, L, seg, seg_end, nwin, tne, wn, lane, id2);
+                if (nhave) walk_load<false, NT>(a, L, seg, seg_end, nwin, tne, wn, lane, id2);
                 if (TR && held > 255 - PER_ROUND) {
                     trans_flush<HI>(tr, hsum, lane);
                     held = 0;
@@ -1153,7 +1162,7 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
                 if (!nhave) break;
                 wn = w0 + STRIDE;
                 nhave = wn + SPAN < nfull;
-                if (nhave) walk_load<false>(a, L, seg, seg_end, nwin, tne, wn, lane, id);
+                if (nhave) walk_load<false, NT>(a, L, seg, seg_end, nwin, tne, wn, lane, id);
                 if (TR && held > 255 - PER_ROUND) {
                     trans_flush<HI>(tr, hsum, lane);
                     held = 0;
@@ -1170,7 +1179,7 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
                     held = 0;
                 }
                 held += PER_ROUND;
-                walk_load<true>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
+                walk_load<true, NT>(a, L, seg, seg_end, nwin, tne, w0, lane, id);
                 walk_bump<BITS, HI, true, TR, ZB>(L, id, lim, tr);
             }
             __syncthreads();
@@ -1179,8 +1188,8 @@ __device__ __forceinline__ bool count_tile(const CountArgs &a, int q, int t, con
                 // clear every count the walk raised
                 const uint32_t id0 = static_cast<uint32_t>(t) * static_cast<uint32_t>(a.W);
                 for (uint32_t wr = static_cast<uint32_t>(wave); wr < nwin; wr += STRIDE) {
-                    walk_load<true>(a, L, seg, seg_end, nwin, tne, wr, lane, id);
-                    walk_take<BITS, ZB>(L, id, lim, lv, xl_dst, xl_cap, xl_shift, id0, lane, wr, nwin);
+                    walk_load<true, NT>(a, L, seg, seg_end, nwin, tne, wr, lane, id);
+                    walk_take<BITS, ZB, NT>(L, id, lim, lv, xl_dst, xl_cap, xl_shift, id0, lane, wr, nwin);
                 }
                 __syncthreads();
             }
@@ -1404,9 +1413,10 @@ __device__ __forceinline__ uint32_t flag_counts(uint32_t w, uint32_t lv) {
 // atomics: the T tiles of a query write disjoint ranges), and only the
 // flagged words are read again from LDS to extract their ids.  Ids past n
 // hold 0 and lv >= 1, so none is listed.  wsum: CT_WAVES words of LDS.
-template <int BITS, bool HI>
+template <int BITS, bool HI, int NT = CT_BLOCK>
 __device__ __forceinline__ void list_tile(const ListArgs &la, const uint32_t *cnt, uint32_t *wsum, uint32_t *lsum,
                                           int vec, int q, int t, int W, uint32_t lv, int wave, int lane) {
+    constexpr int CT_BLOCK = NT, CT_WAVES = NT / WAVE;
     constexpr int PER_WORD = 32 / BITS;
     constexpr uint32_t CMASK = (1u << BITS) - 1u;
     typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -1470,13 +1480,16 @@ __device__ __forceinline__ void list_tile(const ListArgs &la, const uint32_t *cn
 // when sc is given.  CT_REDO: for each queued query, stores the packed
 // counts and, with la.redo_hist, adds its level counts; workgroup (0, 0)
 // also moves the adaptive level.
-template <int BITS, bool HI, int MODE, bool TR, bool MULTI>
-__global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__restrict__ hist,
-                                                   uint4 *__restrict__ sc, ListArgs la) {
+// NT threads per workgroup: 1024 (eight waves per SIMD, 64 VGPRs) or 768
+// (six, 80 VGPRs: room for the re-walk to keep the walk's groups).
+template <int BITS, bool HI, int MODE, bool TR, bool MULTI, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 768 ? 6 : 8))) void k_count(
+    CountArgs a, uint32_t *__restrict__ hist, uint4 *__restrict__ sc, ListArgs la) {
+    constexpr int CT_BLOCK = NT;
     // no static LDS: the packed counts start at address 0, so an increment's
     // byte offset is its address
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const CountLds L = carve<BITS>(lds_raw, a.W);
+    const CountLds L = carve<BITS, NT>(lds_raw, a.W);
     uint32_t *hsum = L.hsum, *lsum = L.lsum;
     // (tile t, query row group gy).  In XCD order (a.xper > 0) the T x G units
     // are numbered tile-major and cut into 8 runs of xper, one per XCD: the
@@ -1532,9 +1545,9 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
         if (threadIdx.x < 18) hsum[threadIdx.x] = 0u;
         if (MODE == CT_LIST && threadIdx.x < 17) lsum[threadIdx.x] = 0u;
         uint32_t *xl_dst = xl ? la.list + (static_cast<int64_t>(q) * la.T + t) * la.lcap : nullptr;
-        const bool listed = count_tile<BITS, HI, TR, XL, true>(a, q, t, L, hsum, xl_dst,
-                                                               static_cast<uint32_t>(la.lcap), la.shift,
-                                                               XL ? list_level(la) : 0u, !clean);
+        const bool listed = count_tile<BITS, HI, TR, XL, true, NT>(a, q, t, L, hsum, xl_dst,
+                                                                   static_cast<uint32_t>(la.lcap), la.shift,
+                                                                   XL ? list_level(la) : 0u, !clean);
         clean = listed;
         // count_tile ends at a barrier after its last LDS count access; the
         // level transitions (TR) add to hsum after it
@@ -1555,8 +1568,8 @@ __global__ __launch_bounds__(CT_BLOCK, 8) void k_count(CountArgs a, uint32_t *__
             if (listed) {
                 if (threadIdx.x == 0) la.tcount[static_cast<int64_t>(q) * la.T + t] = *L.lcnt;
             } else {
-                list_tile<BITS, HI>(la, L.cnt, L.wsum, lsum, vec, q, t, a.W, list_level(la), threadIdx.x / WAVE,
-                                    lane);
+                list_tile<BITS, HI, NT>(la, L.cnt, L.wsum, lsum, vec, q, t, a.W, list_level(la),
+                                        threadIdx.x / WAVE, lane);
             }
             // a re-walk's level tallies are complete at count_tile's last barrier
             if (!listed) __syncthreads();
@@ -3232,22 +3245,27 @@ size_t count_lds_bytes(int W, int bits) { return count_lds_size(W, bits); }
 
 // Instances: nibble counts up to 8 levels (Ns <= 8), nibbles with up to
 // 15, bytes (Ns = 16).
-template <int MODE, bool TR, bool MULTI>
+template <int MODE, bool TR, bool MULTI, int NT>
 static const void *count_kernel_form(int bits, int Ns) {
-    if (bits == 8) return reinterpret_cast<const void *>(k_count<8, true, MODE, TR, MULTI>);
-    return Ns > 8 ? reinterpret_cast<const void *>(k_count<4, true, MODE, TR, MULTI>)
-                  : reinterpret_cast<const void *>(k_count<4, false, MODE, TR, MULTI>);
+    if (bits == 8) return reinterpret_cast<const void *>(k_count<8, true, MODE, TR, MULTI, NT>);
+    return Ns > 8 ? reinterpret_cast<const void *>(k_count<4, true, MODE, TR, MULTI, NT>)
+                  : reinterpret_cast<const void *>(k_count<4, false, MODE, TR, MULTI, NT>);
 }
 
 // form 3: the list form with the level transitions; 4 and 5: the list and
 // store forms taking several queries per workgroup
-static const void *count_kernel(int bits, int Ns, int form) {
-    if (form == CT_LIST) return count_kernel_form<CT_LIST, false, false>(bits, Ns);
-    if (form == 3) return count_kernel_form<CT_LIST, true, false>(bits, Ns);
-    if (form == 4) return count_kernel_form<CT_LIST, false, true>(bits, Ns);
-    if (form == 5) return count_kernel_form<CT_STORE, true, true>(bits, Ns);
-    if (form == CT_REDO) return count_kernel_form<CT_REDO, true, false>(bits, Ns);
-    return count_kernel_form<CT_STORE, true, false>(bits, Ns);
+template <int NT>
+static const void *count_kernel_nt(int bits, int Ns, int form) {
+    if (form == CT_LIST) return count_kernel_form<CT_LIST, false, false, NT>(bits, Ns);
+    if (form == 3) return count_kernel_form<CT_LIST, true, false, NT>(bits, Ns);
+    if (form == 4) return count_kernel_form<CT_LIST, false, true, NT>(bits, Ns);
+    if (form == 5) return count_kernel_form<CT_STORE, true, true, NT>(bits, Ns);
+    if (form == CT_REDO) return count_kernel_form<CT_REDO, true, false, NT>(bits, Ns);
+    return count_kernel_form<CT_STORE, true, false, NT>(bits, Ns);
+}
+
+static const void *count_kernel(int bits, int Ns, int form, int nt) {
+    return nt == 768 ? count_kernel_nt<768>(bits, Ns, form) : count_kernel_nt<1024>(bits, Ns, form);
 }
 
 static const void *count_select_kernel(int bits, int Ns) {
@@ -3257,15 +3275,17 @@ static const void *count_select_kernel(int bits, int Ns) {
 }
 
 hipError_t prepare_count_kernels(int W, int bits, int Ns) {
-    const int bytes = static_cast<int>(count_lds_size(W, bits));
-    for (int form : {0, 1, 2, 3, 4, 5}) {
-        const void *k = count_kernel(bits, Ns, form);
-        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-        if (e != hipSuccess) return e;
-        // k_count addresses its counts from LDS address 0 (count_word<true>)
-        hipFuncAttributes fa{};
-        if ((e = hipFuncGetAttributes(&fa, k)) != hipSuccess) return e;
-        if (fa.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
+    for (int nt : {768, 1024}) {
+        const int bytes = static_cast<int>(count_lds_size(W, bits, nt));
+        for (int form : {0, 1, 2, 3, 4, 5}) {
+            const void *k = count_kernel(bits, Ns, form, nt);
+            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            if (e != hipSuccess) return e;
+            // k_count addresses its counts from LDS address 0 (count_word<true>)
+            hipFuncAttributes fa{};
+            if ((e = hipFuncGetAttributes(&fa, k)) != hipSuccess) return e;
+            if (fa.sharedSizeBytes != 0) return hipErrorInvalidDeviceFunction;
+        }
     }
     return hipSuccess;
 }
@@ -3308,15 +3328,23 @@ hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, int 
         grid = dim3(static_cast<unsigned>(8 * a.xper), 1);
     }
     uint4 *s4 = reinterpret_cast<uint4 *>(sc);
-    const size_t lds = count_lds_size(c.W, c.bits);
-#define TACO_COUNT(MODE, TR, MULTI)                                                        \
-    do {                                                                                \
-        if (c.bits == 8)                                                                \
-            k_count<8, true, MODE, TR, MULTI><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la);  \
-        else if (c.Ns > 8)                                                              \
-            k_count<4, true, MODE, TR, MULTI><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la);  \
-        else                                                                            \
-            k_count<4, false, MODE, TR, MULTI><<<grid, CT_BLOCK, lds, st>>>(a, hist, s4, la); \
+    if (c.nt != 768 && c.nt != 1024) return hipErrorInvalidValue;
+    const size_t lds = count_lds_size(c.W, c.bits, c.nt);
+#define TACO_COUNT_NT(MODE, TR, MULTI, NT)                                                     \
+    do {                                                                                    \
+        if (c.bits == 8)                                                                    \
+            k_count<8, true, MODE, TR, MULTI, NT><<<grid, NT, lds, st>>>(a, hist, s4, la);  \
+        else if (c.Ns > 8)                                                                  \
+            k_count<4, true, MODE, TR, MULTI, NT><<<grid, NT, lds, st>>>(a, hist, s4, la);  \
+        else                                                                                \
+            k_count<4, false, MODE, TR, MULTI, NT><<<grid, NT, lds, st>>>(a, hist, s4, la); \
+    } while (0)
+#define TACO_COUNT(MODE, TR, MULTI)                 \
+    do {                                            \
+        if (c.nt == 768)                            \
+            TACO_COUNT_NT(MODE, TR, MULTI, 768);    \
+        else                                        \
+            TACO_COUNT_NT(MODE, TR, MULTI, 1024);   \
     } while (0)
     // several queries per workgroup: instances of their own, so that the
     // one-query forms keep their registers
@@ -3334,6 +3362,7 @@ hipError_t launch_count(const CountLaunch &c, uint32_t *hist, uint32_t *sc, int 
     else
         TACO_COUNT(CT_STORE, true, false);
 #undef TACO_COUNT
+#undef TACO_COUNT_NT
     return hipGetLastError();
 }
 

@@ -116,7 +116,7 @@ struct GraphKey {
     int64_t nq;
     int k, k_max;
     uint64_t alpha_bits, beta_bits;
-    int precision, count_mode, W, qpw, rule, rr_blocks, cdist, list_level, count_qpw;
+    int precision, count_mode, W, qpw, rule, rr_blocks, cdist, list_level, count_qpw, count_nt;
     int64_t Qb, pool, slots;
     bool operator==(const GraphKey &o) const { return memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
@@ -153,6 +153,7 @@ struct tc_index {
     int32_t *kq = nullptr;       // [Qb] per-query k, clamped
     int probe_qpw = 4;           // queries (wavefronts) per probe workgroup
     int count_qpw = 1;           // queries per counting workgroup
+    int count_nt = 1024;         // threads per counting workgroup (768 or 1024)
     int rr_blocks = 32;          // re-rank workgroups per query
     // graph capture of whole calls
     bool use_graph = false;
@@ -957,6 +958,7 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
                    "probed cell list kernel");
         taco::CountLaunch cl{nb, x->Ns, x->K, x->T, x->W, x->bits, x->n, x->ids_enc, x->off2d, S.flat,
                              S.ftot, order ? S.perm : nullptr, c.plain ? 1 : x->count_qpw};
+        cl.nt = c.plain ? 1024 : x->count_nt;
         taco::SelectLaunch sl{S.hist, R, x->rule, cap, S.cand, S.cand_count,
                               dump && dump->sc ? dump->sc + b0 * x->n : nullptr,
                               dump && dump->last ? dump->last + b0 : nullptr,
@@ -1130,6 +1132,7 @@ int run(tc_index *x, const Call &c, void *stream) {
     key.cdist = x->cdist;
     key.list_level = x->list_level;
     key.count_qpw = x->count_qpw;
+    key.count_nt = x->count_nt;
     key.Qb = x->Qb;
     key.pool = x->pool;
     key.slots = plan_slots(x);
@@ -1338,6 +1341,11 @@ int tc_set_option(tc_index *x, int option, int64_t value) {
             return fail(TC_EINVAL, "queries per counting workgroup must be 1, 2, 4, 8, 16 or 32");
         x->count_qpw = static_cast<int>(value);
         return TC_OK;
+    case TC_OPT_COUNT_BLOCK:
+        if (value != 768 && value != 1024)
+            return fail(TC_EINVAL, "threads per counting workgroup must be 768 or 1024");
+        x->count_nt = static_cast<int>(value);
+        return TC_OK;
     default:
         return fail(TC_EINVAL, "unknown option");
     }
@@ -1476,7 +1484,7 @@ int tc_profile_reset(tc_index *x) {
 namespace {
 
 struct TuneConfig {
-    int W, mode, qpw, rr, precision, cqpw;
+    int W, mode, qpw, rr, precision, cqpw, nt;
 };
 
 // Cache key of a tuning: the GPU, the index (shape, seed, content hash), the
@@ -1501,6 +1509,7 @@ int apply_config(tc_index *x, const TuneConfig &c) {
     if ((rc = tc_set_option(x, TC_OPT_COUNT_MODE, c.mode))) return rc;
     if ((rc = tc_set_option(x, TC_OPT_PROBE_QPW, c.qpw))) return rc;
     if ((rc = tc_set_option(x, TC_OPT_COUNT_QPW, c.cqpw))) return rc;
+    if ((rc = tc_set_option(x, TC_OPT_COUNT_BLOCK, c.nt))) return rc;
     return tc_set_option(x, TC_OPT_RERANK_BLOCKS, c.rr);
 }
 
@@ -1526,12 +1535,15 @@ int tune(tc_index *x, const std::string &key, const std::function<int()> &once, 
         while (std::getline(in, line)) {
             if (line.find("\"key\": \"" + key + "\"") == std::string::npos) continue;
             TuneConfig c{};
+            c.nt = 1024;  // (entries written before the workgroup size was tuned have none)
             if (sscanf(line.c_str() + line.find("\"W\""),
-                       "\"W\": %d, \"mode\": %d, \"qpw\": %d, \"rr\": %d, \"precision\": %d, \"cqpw\": %d",
-                       &c.W, &c.mode, &c.qpw, &c.rr, &c.precision, &c.cqpw) == 6) {
+                       "\"W\": %d, \"mode\": %d, \"qpw\": %d, \"rr\": %d, \"precision\": %d, \"cqpw\": %d, "
+                       "\"nt\": %d",
+                       &c.W, &c.mode, &c.qpw, &c.rr, &c.precision, &c.cqpw, &c.nt) >= 6) {
                 if (apply_config(x, c) == TC_OK) {
                     rep << "cached " << key << " W=" << c.W << " mode=" << c.mode << " qpw=" << c.qpw
-                        << " rr=" << c.rr << " precision=" << c.precision << " cqpw=" << c.cqpw << "\n";
+                        << " rr=" << c.rr << " precision=" << c.precision << " cqpw=" << c.cqpw << " nt=" << c.nt
+                        << "\n";
                     return finish(TC_OK);
                 }
                 rep << "cached entry no longer applies (" << g_err << "); measuring\n";
@@ -1561,12 +1573,12 @@ int tune(tc_index *x, const std::string &key, const std::function<int()> &once, 
         TC_HIP(hipEventElapsedTime(&f, e0, e1), "autotune timing");
         *ms = f / 3.0;
         rep << "W=" << c.W << " mode=" << c.mode << " qpw=" << c.qpw << " rr=" << c.rr
-            << " precision=" << c.precision << " cqpw=" << c.cqpw << " ms=" << *ms << "\n";
+            << " precision=" << c.precision << " cqpw=" << c.cqpw << " nt=" << c.nt << " ms=" << *ms << "\n";
         return TC_OK;
     };
     int rc = TC_OK;
     TuneConfig best{x->W, x->count_mode == TC_COUNT_AUTO ? TC_COUNT_SPLIT : x->count_mode, x->probe_qpw,
-                    x->rr_blocks, x->precision, x->count_qpw};
+                    x->rr_blocks, x->precision, x->count_qpw, x->count_nt};
     double best_ms = 1e30;
     std::vector<int> Ws = x->bits == 4 ? std::vector<int>{65536, 131072, 262144}
                                        : std::vector<int>{32768, 65536, 131072};
@@ -1602,6 +1614,12 @@ int tune(tc_index *x, const std::string &key, const std::function<int()> &once, 
             if ((rc = measure(c, &ms))) goto done;
             if (ms < best_ms) best_ms = ms, best = c;
         }
+        // the other workgroup size (more registers per wavefront, fewer wavefronts)
+        TuneConfig c = best;
+        c.nt = best.nt == 768 ? 1024 : 768;
+        double ms;
+        if ((rc = measure(c, &ms))) goto done;
+        if (ms < best_ms) best_ms = ms, best = c;
     }
     for (int qpw : {1, 2, 4, 8, 16}) {
         TuneConfig c = best;
@@ -1628,12 +1646,13 @@ int tune(tc_index *x, const std::string &key, const std::function<int()> &once, 
     }
     rc = apply_config(x, best);
     rep << "best W=" << best.W << " mode=" << best.mode << " qpw=" << best.qpw << " rr=" << best.rr
-        << " precision=" << best.precision << " cqpw=" << best.cqpw << " ms=" << best_ms << "\n";
+        << " precision=" << best.precision << " cqpw=" << best.cqpw << " nt=" << best.nt << " ms=" << best_ms
+        << "\n";
     if (rc == TC_OK && cache_path) {
         std::ofstream out(cache_path, std::ios::app);
         out << "{\"key\": \"" << key << "\", \"W\": " << best.W << ", \"mode\": " << best.mode
             << ", \"qpw\": " << best.qpw << ", \"rr\": " << best.rr << ", \"precision\": " << best.precision
-            << ", \"cqpw\": " << best.cqpw << ", \"ms\": " << best_ms << "}\n";
+            << ", \"cqpw\": " << best.cqpw << ", \"nt\": " << best.nt << ", \"ms\": " << best_ms << "}\n";
     }
 done:
     x->use_graph = graph;

@@ -282,6 +282,56 @@ def test_count_queries_per_workgroup_all_stages(taco_mod, tiny, mode, cqpw):
                  options=opts)
 
 
+@pytest.mark.parametrize("mode", ["split", "list"])
+def test_count_workgroup_768_all_stages(taco_mod, tiny, mode):
+    """768-thread counting workgroups (TC_OPT_COUNT_BLOCK) match the oracle
+    stage by stage: whole tiles and 4096-id tiles with a ragged tail, one and
+    several queries per workgroup, batches with a ragged end."""
+    t = taco_mod
+    m = {"split": t.TC_COUNT_SPLIT, "list": t.TC_COUNT_LIST}[mode]
+    print(f"[tiny] count mode {mode}, 768-thread workgroups", flush=True)
+    for opts in (((t.TC_OPT_COUNT_MODE, m), (t.TC_OPT_COUNT_BLOCK, 768)),
+                 ((t.TC_OPT_TILE_IDS, 4096), (t.TC_OPT_COUNT_MODE, m), (t.TC_OPT_COUNT_BLOCK, 768),
+                  (t.TC_OPT_COUNT_QPW, 4), (t.TC_OPT_MAX_BATCH, 13))):
+        _run_all(t, tiny["path"], tiny["oidx"], tiny["Q"], 10, 0.05, 0.005, 0, f"tiny {mode} nt=768",
+                 options=opts)
+
+
+def test_count_workgroup_sizes_same_results(taco_mod, tiny):
+    """Without stage dumps (the re-walk listing, the multi-query forms), both
+    workgroup sizes give bit-identical results in every split and list
+    configuration, at list levels the re-walk and the scan both serve."""
+    import torch
+    t = taco_mod
+    q = torch.from_numpy(tiny["Q"]).cuda()
+
+    def run(opts):
+        idx = t.Index(tiny["path"], 0)
+        try:
+            for opt, val in opts:
+                idx.set_option(opt, val)
+            ids, d = idx.search(q, 10, 0.05, 0.005)
+            torch.cuda.synchronize()
+            assert idx.device_errors() == 0
+            return ids.cpu().numpy(), d.cpu().numpy().view(np.uint32)
+        finally:
+            idx.close()
+
+    for mode in (t.TC_COUNT_SPLIT, t.TC_COUNT_LIST):
+        for tile in (131072, 4096):
+            for cqpw in (1, 8):
+                for level in (0, 1, 3):
+                    base = ((t.TC_OPT_COUNT_MODE, mode), (t.TC_OPT_TILE_IDS, tile),
+                            (t.TC_OPT_COUNT_QPW, cqpw), (t.TC_OPT_LIST_LEVEL, level))
+                    a = run(base + ((t.TC_OPT_COUNT_BLOCK, 1024),))
+                    b = run(base + ((t.TC_OPT_COUNT_BLOCK, 768),))
+                    lab = f"mode {mode} tile {tile} cqpw {cqpw} level {level}"
+                    assert np.array_equal(a[0], b[0]), f"{lab}: ids differ"
+                    assert np.array_equal(a[1], b[1]), f"{lab}: distance bits differ"
+    with pytest.raises(Exception):
+        run(((t.TC_OPT_COUNT_BLOCK, 512),))
+
+
 @pytest.mark.parametrize("qpw", [1, 2, 8, 16])
 def test_probe_widths_all_stages(taco_mod, tiny, qpw):
     """Every probe workgroup width (queries per workgroup) matches the oracle
