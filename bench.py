@@ -308,11 +308,20 @@ def qps_at_recall(points, target=RECALL_TARGET):
     return best
 
 
+def code_text(src):
+    """C++ source without its comments and with runs of whitespace folded:
+    what the compiler sees, so that a comment edit keeps the hash."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def source_hash():
     h = hashlib.sha256()
     for f in ("kernels.hip", "kernels.h", "runtime.cpp"):
-        with open(os.path.join(ROOT, "paper_2603_24919_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2603_24919_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

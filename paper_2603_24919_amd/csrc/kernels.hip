@@ -1481,7 +1481,7 @@ __device__ __forceinline__ void list_tile(const ListArgs &la, const uint32_t *cn
 // counts and, with la.redo_hist, adds its level counts; workgroup (0, 0)
 // also moves the adaptive level.
 // NT threads per workgroup: 1024 (eight waves per SIMD, 64 VGPRs) or 768
-// (six, 80 VGPRs: room for the re-walk to keep the walk's groups).
+// (six, 80 VGPRs: the multi-query list form then spills nothing).
 template <int BITS, bool HI, int MODE, bool TR, bool MULTI, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT == 768 ? 6 : 8))) void k_count(
     CountArgs a, uint32_t *__restrict__ hist, uint4 *__restrict__ sc, ListArgs la) {
