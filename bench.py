@@ -325,21 +325,38 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary of this workload, if it was taken on the current kernel
-    sources (else None)."""
-    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
-    if not os.path.exists(p):
-        return None
+def launch_config(tuned):
+    """The launch configuration in a tuner report line ("... W=131072 mode=3
+    qpw=8 rr=8 precision=1 cqpw=32 nt=768 ..."): those fields as a dict."""
+    import re
+    return {k: int(v) for k, v in re.findall(r"\b(W|mode|qpw|rr|precision|cqpw|nt)=(\d+)", tuned or "")}
+
+
+def traffic_records(path):
+    """The records of a traffic summary file (one per launch configuration)."""
+    if not os.path.exists(path):
+        return []
     try:
-        rec = json.load(open(p))
+        doc = json.load(open(path))
     except ValueError:
-        return None
-    if rec.get("source_hash") != source_hash() or rec.get("workload") != workload:
-        return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+        return []
+    return doc.get("records", [doc] if "kernels" in doc else [])
+
+
+def traffic_from_profiles(workload, kernel, tuned=None):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload: the record taken on the current kernel sources
+    with the same launch configuration as the run's (`tuned`, its tuner
+    report), else None."""
+    want = launch_config(tuned)
+    for rec in traffic_records(os.path.join(ROOT, "profiles", f"traffic_{workload}.json")):
+        if rec.get("source_hash") != source_hash() or rec.get("workload") != workload:
+            continue
+        if launch_config(rec.get("tuned_config")) != want:
+            continue
+        k = rec.get("kernels", {}).get(kernel)
+        return None if k is None else k.get("hbm_bytes_per_launch")
+    return None
 
 
 def algorithmic_bytes(idx, q, w, alpha, beta, precision, alpha_dev=None, k_dev=None, k_max=None):
@@ -531,7 +548,7 @@ def roofline_of(workload, op, path_name):
     dom = max(op["kernels"], key=lambda k_: op["kernels"][k_]["ms_total"])
     dk = op["kernels"][dom]
     achieved = dk["alg_GBps"]
-    traffic = traffic_from_profiles(workload, dom)
+    traffic = traffic_from_profiles(workload, dom, op.get("config"))
     r = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
              frac=None if achieved is None else achieved / HBM_PEAK_GBS, traffic=traffic,
              alg_bytes_per_launch=dk["alg_bytes_per_launch"], ms_per_launch=dk["ms_per_launch"],
@@ -1023,7 +1040,12 @@ def summarize_traffic(fetch_csv, write_csv, bench_json, out_json, command, copy_
                fetch_scale=f_scale, write_scale=w_scale,
                copy_fetch_KiB=max(fc) if fc else None, copy_write_KiB=max(wc) if wc else None,
                command=command, kernels=kern)
-    json.dump(rec, open(out_json, "w"), indent=1)
+    # one record per launch configuration: a summary of another
+    # configuration on the same sources is kept beside this one
+    keep = [r for r in traffic_records(out_json)
+            if r.get("workload") == rec["workload"] and r.get("source_hash") == rec["source_hash"]
+            and launch_config(r.get("tuned_config")) != launch_config(rec["tuned_config"])]
+    json.dump(dict(workload=rec["workload"], records=keep + [rec]), open(out_json, "w"), indent=1)
 
 
 def summarize_counters(csv_paths, out_md, command):

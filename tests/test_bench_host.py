@@ -86,10 +86,37 @@ def test_summarize_traffic_scales_by_copy(tmp_path):
     out = tmp_path / "t.json"
     bench.summarize_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "b.json"),
                             str(out), "cmd")
-    rec = json.loads(out.read_text())
+    rec = json.loads(out.read_text())["records"][0]
     # the copy's fetch read half its size: fetch counts are doubled
     assert rec["fetch_scale"] == pytest.approx(2.0)
     assert rec["write_scale"] == pytest.approx(1.0)
     c = rec["kernels"]["count"]
     assert c["dispatches"] == 2
     assert c["hbm_bytes_per_launch"] == pytest.approx(200.0 * 1024 * 2 + 50.0 * 1024)
+
+
+def test_traffic_is_matched_to_the_launch_configuration(tmp_path, monkeypatch):
+    """A traffic record serves only runs with its own launch configuration
+    and sources; summaries of two configurations sit side by side."""
+    kib = 1 << 20
+    _write_pmc(tmp_path / "f.csv", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", kib / 2),
+                                                 ("void taco::k_count<4>(taco::CountArgs)", 10.0)])
+    _write_pmc(tmp_path / "w.csv", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", kib),
+                                                 ("void taco::k_count<4>(taco::CountArgs)", 1.0)])
+    (tmp_path / "profiles").mkdir()
+    out = tmp_path / "profiles" / "traffic_w.json"
+    for W in (131072, 262144):
+        line = dict(config=dict(workload="w", path="fp8",
+                                tuned_config=f"best W={W} mode=3 qpw=8 rr=8 precision=1 cqpw=32 nt=768 ms=7.7"))
+        (tmp_path / "b.json").write_text(json.dumps(line) + "\n")
+        bench.summarize_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(tmp_path / "b.json"),
+                                str(out), "cmd")
+    assert len(json.loads(out.read_text())["records"]) == 2
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "source_hash", lambda: json.loads(out.read_text())["records"][0]["source_hash"])
+    run = "cached key W=262144 mode=3 qpw=8 rr=8 precision=1 cqpw=32 nt=768 (tuned at alpha=0.002)"
+    assert bench.traffic_from_profiles("w", "count", run) == pytest.approx(10.0 * 1024 * 2 + 1024)
+    assert bench.traffic_from_profiles("w", "count", run.replace("nt=768", "nt=1024")) is None
+    assert bench.traffic_from_profiles("w", "count", None) is None
+    monkeypatch.setattr(bench, "source_hash", lambda: "other")
+    assert bench.traffic_from_profiles("w", "count", run) is None
