@@ -343,16 +343,27 @@ def traffic_records(path):
     return doc.get("records", [doc] if "kernels" in doc else [])
 
 
+# The launch settings each kernel's own work depends on (the others change
+# only which kernels run beside it); kernels not listed need all of them.
+TRAFFIC_KEYS = {
+    "count": ("W", "mode", "nt", "cqpw"), "count_select": ("W", "mode", "nt", "cqpw"),
+    "rerank": ("W", "mode", "precision", "rr"), "recheck": ("W", "mode", "precision", "rr"),
+}
+
+
 def traffic_from_profiles(workload, kernel, tuned=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary of this workload: the record taken on the current kernel sources
-    with the same launch configuration as the run's (`tuned`, its tuner
-    report), else None."""
-    want = launch_config(tuned)
+    whose launch configuration agrees with the run's (`tuned`, its tuner
+    report) in every setting the kernel depends on, else None."""
+    keys = TRAFFIC_KEYS.get(kernel, ("W", "mode", "qpw", "rr", "precision", "cqpw", "nt"))
+    run = launch_config(tuned)
+    want = {k: run.get(k) for k in keys}
     for rec in traffic_records(os.path.join(ROOT, "profiles", f"traffic_{workload}.json")):
         if rec.get("source_hash") != source_hash() or rec.get("workload") != workload:
             continue
-        if launch_config(rec.get("tuned_config")) != want:
+        have = launch_config(rec.get("tuned_config"))
+        if not run or {k: have.get(k) for k in keys} != want:
             continue
         k = rec.get("kernels", {}).get(kernel)
         return None if k is None else k.get("hbm_bytes_per_launch")

@@ -100,9 +100,11 @@ def test_traffic_is_matched_to_the_launch_configuration(tmp_path, monkeypatch):
     and sources; summaries of two configurations sit side by side."""
     kib = 1 << 20
     _write_pmc(tmp_path / "f.csv", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", kib / 2),
-                                                 ("void taco::k_count<4>(taco::CountArgs)", 10.0)])
+                                                 ("void taco::k_count<4>(taco::CountArgs)", 10.0),
+                                                 ("void taco::k_probe<4>(float const*)", 3.0)])
     _write_pmc(tmp_path / "w.csv", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", kib),
-                                                 ("void taco::k_count<4>(taco::CountArgs)", 1.0)])
+                                                 ("void taco::k_count<4>(taco::CountArgs)", 1.0),
+                                                 ("void taco::k_probe<4>(float const*)", 1.0)])
     (tmp_path / "profiles").mkdir()
     out = tmp_path / "profiles" / "traffic_w.json"
     for W in (131072, 262144):
@@ -118,5 +120,11 @@ def test_traffic_is_matched_to_the_launch_configuration(tmp_path, monkeypatch):
     assert bench.traffic_from_profiles("w", "count", run) == pytest.approx(10.0 * 1024 * 2 + 1024)
     assert bench.traffic_from_profiles("w", "count", run.replace("nt=768", "nt=1024")) is None
     assert bench.traffic_from_profiles("w", "count", None) is None
+    # the count's traffic does not depend on the probe or re-rank settings;
+    # other kernels need the whole configuration to agree
+    other = run.replace("qpw=8", "qpw=16").replace("rr=8", "rr=32")
+    assert bench.traffic_from_profiles("w", "count", other) == pytest.approx(10.0 * 1024 * 2 + 1024)
+    assert bench.traffic_from_profiles("w", "probe", other) is None
+    assert bench.traffic_from_profiles("w", "probe", run) == pytest.approx(3.0 * 1024 * 2 + 1024)
     monkeypatch.setattr(bench, "source_hash", lambda: "other")
     assert bench.traffic_from_profiles("w", "count", run) is None
