@@ -67,9 +67,9 @@ enum tc_status {
  *                    SC > L and the first floor(beta*n) - S(L + 1) points of
  *                    level L in id order, and the reported threshold is
  *                    L + 1 (Ns + 1 when beta*n < 1), whether or not level L
- *                    is taken whole.  Searches with this rule use the split
- *                    count form (TC_COUNT_SPLIT) whatever TC_OPT_COUNT_MODE
- *                    says. */
+ *                    is taken whole.  The rule runs on the split and list
+ *                    count forms; TC_COUNT_FUSED takes the split form's
+ *                    launches with it. */
 enum tc_select_rule { TC_RULE_PRINTED = 0, TC_RULE_PROSE = 1, TC_RULE_FIXED = 2 };
 
 /* Options for tc_set_option. */
@@ -140,7 +140,8 @@ enum tc_option {
  *   TC_COUNT_LIST:  the count launch lists the ids whose count reaches the
  *                   list level instead of storing the counts; whenever Alg
  *                   5's threshold is at or above that level (known from the
- *                   histogram), the candidates are filtered from the list.
+ *                   histogram), the candidates are filtered from the list
+ *                   (under TC_RULE_FIXED: whenever the boundary level is).
  *                   Queries whose threshold falls below it are counted again
  *                   and selected as in TC_COUNT_SPLIT.
  *   TC_COUNT_FUSED: one cooperative, persistent launch; the workgroups of a

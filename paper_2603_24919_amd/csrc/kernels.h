@@ -100,7 +100,8 @@ hipError_t launch_unpack_counts(const uint32_t *sc, int nq, int T, int W, int bi
 hipError_t launch_list_select(const CountLaunch &c, const ListLaunch &l, uint32_t *hist, hipStream_t st);
 int list_shift(int Ns);
 // Fixed-budget rule (rule 2), after launch_select: the first points of the
-// boundary level in id order, and the final candidate counts.
+// boundary level in id order, and the final candidate counts (with s.redo,
+// of the queued queries of a list selection only).
 hipError_t launch_select_level(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
                                hipStream_t st);
 hipError_t launch_select(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,

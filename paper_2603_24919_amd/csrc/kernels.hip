@@ -1697,17 +1697,17 @@ __device__ __forceinline__ void select_query(const SelectArgs &sa, int Ns, int64
 // level L in id order (ids below n), and set the candidate count.  One
 // workgroup per query walks the packed counts in id order, 256 words at a
 // time, ranking matches by a workgroup prefix sum; it stops once enough are
-// found.  grid nq, block SL_BLOCK.
+// found.  grid nq, block SL_BLOCK; with sa.redo, the queued queries of a
+// list selection instead (grid any).
 constexpr int SL_BLOCK = 256;
 
 template <int BITS>
-__global__ __launch_bounds__(SL_BLOCK) void k_select_level(SelectArgs sa, int Ns, int64_t n, int64_t words,
-                                                           const uint32_t *__restrict__ sc32) {
+__device__ __forceinline__ void select_level_query(const SelectArgs &sa, int Ns, int64_t n, int64_t words,
+                                                   const uint32_t *__restrict__ sc32, int q, uint32_t *wtot,
+                                                   uint32_t &base_s) {
     constexpr int PER_WORD = 32 / BITS;
     constexpr uint32_t MASK = (1u << BITS) - 1u;
-    __shared__ uint32_t wtot[SL_BLOCK / WAVE];
-    __shared__ uint32_t base_s;
-    const int q = blockIdx.x, tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
+    const int tid = threadIdx.x, lane = tid % WAVE, w = tid / WAVE;
     const uint32_t *h = sa.hist + static_cast<int64_t>(q) * (Ns + 1);
     int64_t above0 = 0;
     for (int v = 1; v <= Ns; v++) above0 += h[v];
@@ -1781,6 +1781,21 @@ __global__ __launch_bounds__(SL_BLOCK) void k_select_level(SelectArgs sa, int Ns
         const int64_t end = base + (taken < need ? taken : need);
         *counter = static_cast<uint32_t>(end < sa.cap ? end : sa.cap);
     }
+    __syncthreads();  // base_s is rewritten for the next query
+}
+
+template <int BITS>
+__global__ __launch_bounds__(SL_BLOCK) void k_select_level(SelectArgs sa, int Ns, int64_t n, int64_t words,
+                                                           const uint32_t *__restrict__ sc32) {
+    __shared__ uint32_t wtot[SL_BLOCK / WAVE];
+    __shared__ uint32_t base_s;
+    if (!sa.redo) {
+        select_level_query<BITS>(sa, Ns, n, words, sc32, blockIdx.x, wtot, base_s);
+        return;
+    }
+    const uint32_t nrun = sa.redo[0];
+    for (uint32_t f = blockIdx.x; f < nrun; f += gridDim.x)
+        select_level_query<BITS>(sa, Ns, n, words, sc32, static_cast<int>(sa.redo[3 + f]), wtot, base_s);
 }
 
 // Alg 5 on a query's lists: the threshold from the histogram's levels >=
@@ -1798,6 +1813,15 @@ __global__ __launch_bounds__(SL_BLOCK) void k_select_level(SelectArgs sa, int Ns
 // tile, i.e. of one id range, to workgroups on one XCD.  Without toff, or
 // with more tiles, a wavefront reserves its slots with one LDS add per 256
 // entries and toff[q][0] (if given) is TOFF_NONE, as for a queued query.
+// The fixed-budget rule (rule 2) takes the same scan to the boundary level
+// L, the highest listed level with S(L) >= R (queued when it lies below the
+// list level).  Its candidates are the listed ids above L and the first
+// need = R - S(L + 1) listed ids of level L in id order, i.e. those of
+// level L below an id bound tau.  Tiles are consecutive id ranges: the
+// tile where the running count of level-L entries reaches need holds tau,
+// which a binary search over that tile's ids finds (the number of its
+// level-L entries below a trial bound, counted by the workgroup).  These
+// candidates are never grouped by tile.
 // grid nq, block LS_BLOCK.
 constexpr int LS_BLOCK = 256;
 constexpr int LS_UNROLL = 4;
@@ -1806,13 +1830,15 @@ constexpr uint32_t TOFF_NONE = 0xffffffffu;
 
 __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t *__restrict__ hist, int Ns,
                                                           int64_t n) {
-    __shared__ int s_last;
-    __shared__ uint32_t s_out, s_over;
+    __shared__ int s_last, s_tile;
+    __shared__ uint32_t s_out, s_over, s_need, s_acc;
     __shared__ uint32_t s_tc[LS_TMAX + 1];
+    __shared__ uint32_t s_red[LS_BLOCK / WAVE];
     const int q = blockIdx.x;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int lv = static_cast<int>(list_level(la));
-    const bool grouped = la.toff != nullptr && la.tlev != nullptr && la.T <= LS_TMAX;
+    const bool fixed = la.rule == 2;
+    const bool grouped = !fixed && la.toff != nullptr && la.tlev != nullptr && la.T <= LS_TMAX;
     uint32_t *tq = la.toff ? la.toff + static_cast<int64_t>(q) * (la.T + 1) : nullptr;
     uint32_t *h = hist + static_cast<int64_t>(q) * (Ns + 1);
     if (threadIdx.x == 0) s_over = 0u;
@@ -1826,20 +1852,29 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
     __syncthreads();
     if (threadIdx.x == 0) {
         // the highest listed level (>= lv) exceeding the budget, as in
-        // select_threshold; lv - 1 when none does (the threshold is lower)
+        // select_threshold; lv - 1 when none does (the threshold is lower).
+        // Rule 2: the boundary level, with S(last) >= R
         int last = lv - 1;
         int64_t S = 0;  // S(last) at the break
+        uint32_t need = 0u;
         for (int v = Ns; v >= lv; v--) {
             const int64_t hv = h[v];
+            if (fixed && S + hv >= la.R) {
+                last = v;
+                need = static_cast<uint32_t>(la.R - S);
+                S = la.R;
+                break;
+            }
             S += hv;
-            if ((la.rule == 1 ? S : hv + S) > la.R) {
+            if (!fixed && (la.rule == 1 ? S : hv + S) > la.R) {
                 last = v;
                 break;
             }
         }
         if (la.dump_last || la.dump_hist)
             // stage dumps: the histogram is complete here; the threshold is
-            // the full scan's (equal to last whenever last >= lv)
+            // the full scan's (equal to last whenever last >= lv; rule 2
+            // reports the boundary level plus one)
             dump_threshold(la.dump_last, la.dump_hist, q, Ns, n, h, select_threshold(h, Ns, n, la.R, la.rule));
         if (last > lv) atomicAdd(&la.redo[1], 1u);
         // a tile's list overflowed, or more candidates than slots (the
@@ -1858,6 +1893,9 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
         if (tq && (last < lv || !grouped)) tq[0] = TOFF_NONE;
         s_last = last;
         s_out = 0u;
+        s_need = need;
+        s_tile = -1;
+        s_acc = 0u;
     }
     __syncthreads();
     const int last = s_last;
@@ -1866,6 +1904,73 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
     int32_t *cq = la.cand + static_cast<int64_t>(q) * la.cap;
     const uint32_t idmask = (1u << la.shift) - 1u, lu = static_cast<uint32_t>(last);
     const uint64_t below = lanes_below(lane);
+    // ids of level `last` are taken below tau (all of them for Alg 5)
+    uint32_t tau = 0xffffffffu;
+    if (fixed) {
+        const uint32_t need = s_need;
+        tau = 0u;  // R = 0: none
+        if (need > 0u) {
+            // the tile where the level-L entries reach need, LS_TMAX tiles a pass
+            for (int t0 = 0; t0 < la.T && s_tile < 0; t0 += LS_TMAX) {
+                const int tn = min(LS_TMAX, la.T - t0);
+                for (int t = t0 + wave; t < t0 + tn; t += LS_BLOCK / WAVE) {
+                    const uint32_t nt = min(la.tcount[static_cast<int64_t>(q) * la.T + t],
+                                            static_cast<uint32_t>(la.lcap));
+                    const uint32_t *et = ls + static_cast<int64_t>(t) * la.lcap;
+                    uint32_t c = 0u;
+                    for (uint32_t i = lane; i < nt; i += WAVE) c += (et[i] >> la.shift) == lu ? 1u : 0u;
+                    c = wave_sum_u32(c);
+                    if (lane == 0) s_tc[t - t0] = c;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    uint32_t acc = s_acc;
+                    for (int i = 0; i < tn; i++) {
+                        if (acc + s_tc[i] >= need) {
+                            s_tile = t0 + i;
+                            break;
+                        }
+                        acc += s_tc[i];
+                    }
+                    s_acc = acc;  // the entries of level L in the tiles before s_tile
+                }
+                __syncthreads();
+            }
+            const int tc = s_tile;
+            if (tc < 0) {
+                tau = 0xffffffffu;  // (fewer entries than the histogram says: take them all)
+            } else {
+                // the smallest bound with `want` entries below it: the level-L
+                // ids below it are the first `want` of the tile
+                const uint32_t want = need - s_acc;
+                const uint32_t nt = min(la.tcount[static_cast<int64_t>(q) * la.T + tc],
+                                        static_cast<uint32_t>(la.lcap));
+                const uint32_t *et = ls + static_cast<int64_t>(tc) * la.lcap;
+                uint32_t lo = static_cast<uint32_t>(tc) * static_cast<uint32_t>(la.W);
+                uint32_t hi = lo + static_cast<uint32_t>(la.W);  // below lo: none; below hi: >= want
+                while (hi - lo > 1u) {
+                    const uint32_t mid = lo + (hi - lo) / 2u;
+                    uint32_t c = 0u;
+                    for (uint32_t i = threadIdx.x; i < nt; i += LS_BLOCK) {
+                        const uint32_t v = et[i];
+                        c += ((v >> la.shift) == lu && (v & idmask) < mid) ? 1u : 0u;
+                    }
+                    c = wave_sum_u32(c);
+                    if (lane == 0) s_red[wave] = c;
+                    __syncthreads();
+                    uint32_t tot = 0u;
+#pragma unroll
+                    for (int i = 0; i < LS_BLOCK / WAVE; i++) tot += s_red[i];
+                    __syncthreads();  // s_red is rewritten by the next step
+                    if (tot >= want)
+                        hi = mid;
+                    else
+                        lo = mid;
+                }
+                tau = hi;
+            }
+        }
+    }
     if (grouped) {
         // candidates per tile: its listed ids at levels >= last
         for (int t = threadIdx.x; t < la.T; t += LS_BLOCK) {
@@ -1929,7 +2034,8 @@ __global__ __launch_bounds__(LS_BLOCK) void k_list_select(ListArgs la, uint32_t 
 #pragma unroll
             for (int u = 0; u < LS_UNROLL; u++) {
                 // listed words hold a count >= 1; 0 marks an empty slot
-                m[u] = __ballot(v[u] != 0u && (v[u] >> la.shift) >= lu);
+                const uint32_t lev = v[u] >> la.shift;
+                m[u] = __ballot(v[u] != 0u && (lev > lu || (lev == lu && (v[u] & idmask) < tau)));
                 tot += static_cast<uint32_t>(__popcll(m[u]));
             }
             if (tot == 0u) continue;
@@ -3382,12 +3488,14 @@ hipError_t launch_unpack_counts(const uint32_t *sc, int nq, int T, int W, int bi
 
 hipError_t launch_select_level(const CountLaunch &c, const SelectLaunch &s, const uint32_t *sc,
                                hipStream_t st) {
-    SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, nullptr, nullptr, nullptr, nullptr};
+    SelectArgs sa{s.hist, s.R, s.rule, s.cap, s.cand, s.cand_count, nullptr, nullptr, nullptr, s.redo, nullptr};
     const int64_t words = static_cast<int64_t>(c.T) * c.W * c.bits / 32;
+    const unsigned grid = static_cast<unsigned>(s.redo ? s.redo_groups : c.nq);
+    if (grid == 0u) return hipErrorInvalidValue;
     if (c.bits == 4)
-        k_select_level<4><<<c.nq, SL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words, sc);
+        k_select_level<4><<<grid, SL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words, sc);
     else
-        k_select_level<8><<<c.nq, SL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words, sc);
+        k_select_level<8><<<grid, SL_BLOCK, 0, st>>>(sa, c.Ns, c.n, words, sc);
     return hipGetLastError();
 }
 

@@ -904,10 +904,11 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
     // AUTO takes the split launches: on MI355X the ~T*nq independent
     // workgroups of the split form overlap better than the fused groups'
     // lock-step rounds (10.2 vs 17.3 ms per 10k-query step at n = 1M)
-    // the fixed-budget rule needs the packed counts of the split form
+    // the fixed-budget rule runs on the packed counts of the split form or
+    // on the lists (the fused form takes the split launches for it)
     const bool fixed = x->rule == TC_RULE_FIXED;
     const bool fused = count_mode == TC_COUNT_FUSED && !fixed;
-    const bool list = count_mode == TC_COUNT_LIST && !fixed;
+    const bool list = count_mode == TC_COUNT_LIST;
     const bool codes = count_mode == TC_COUNT_CODES;
     for (int64_t b0 = 0; b0 < c.nq; b0 += Qc) {
         const int nb = static_cast<int>(std::min<int64_t>(Qc, c.nq - b0));
@@ -996,6 +997,8 @@ int enqueue(tc_index *x, const Call &c, hipStream_t st) {
             sr.redo = redo;
             sr.redo_groups = 128;
             TC_HIP(taco::launch_select(cl, sr, S.sc, st), "select kernel (queued)");
+            if (fixed)
+                TC_HIP(taco::launch_select_level(cl, sr, S.sc, st), "boundary-level select kernel (queued)");
             rec(K_SELECT, st, false);
             if (dsc) {
                 // stage dumps: every query's packed counts, over the lists

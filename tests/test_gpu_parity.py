@@ -673,21 +673,48 @@ def test_tiny_fixed_budget_rule(taco_mod, tiny, alpha, beta):
              f"tiny fixed a={alpha} b={beta}")
 
 
-def test_fixed_budget_rule_takes_the_split_form(taco_mod, tiny):
-    """Whatever count form is asked for, the rule runs on the packed counts
-    (stage by stage against the oracle); the exact 8-bit re-rank and the
-    captured graph give the FP32 results bit for bit."""
+def _fixed_on_lists(t, path, oidx, Q, alpha, beta, label, options=()):
+    """The fixed-budget rule with the list form at list levels 1, 3 and Ns
+    (at Ns most queries' boundary level lies below the lists and they are
+    queued, counted again and selected on their packed counts): candidates
+    against the oracle, once with every stage dumped (the count launch then
+    adds every level count) and once with the candidates only (the lists'
+    own histogram, exact at the list level and above)."""
+    rule = ((t.TC_OPT_SELECT_RULE, t.TC_RULE_FIXED), (t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST))
+    for level in (1, 3, oidx.Ns):
+        opts = rule + tuple(options) + ((t.TC_OPT_LIST_LEVEL, level),)
+        print(f"[{label}] fixed budget on the lists, level {level}", flush=True)
+        _run_all(t, path, oidx, Q, 10, alpha, beta, 2, f"{label} lists lvl {level}", options=opts[1:])
+        idx = t.Index(path, 0)
+        try:
+            for opt, val in opts:
+                idx.set_option(opt, val)
+            g = gpu_search(idx, Q, 10, alpha, beta, ("ncand", "cand"))
+        finally:
+            idx.close()
+        for qi in range(Q.shape[0]):
+            compare_query(g, qi, oidx.query(Q[qi], alpha, beta, 10, rule=2), oidx.Ns, 10,
+                          f"{label} lists lvl {level} (candidates only)")
+
+
+def test_fixed_budget_rule_on_the_lists(taco_mod, tiny):
+    """The rule on the list form (the first ids of the boundary level found
+    on the lists), on the lists' queue, and in a captured graph, stage by
+    stage against the oracle; the exact 8-bit re-rank on the lists and the
+    graph give the split form's FP32 results bit for bit."""
     t = taco_mod
     rule = ((t.TC_OPT_SELECT_RULE, t.TC_RULE_FIXED),)
-    for opts in (((t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST),), ((t.TC_OPT_GRAPH, 1),)):
-        print(f"[tiny] fixed budget with {opts}", flush=True)
-        _run_all(t, tiny["path"], tiny["oidx"], tiny["Q"], 10, 0.05, 0.005, 2, f"tiny fixed {opts}",
-                 options=opts)
-    ref = _search_bits(t, tiny["path"], tiny["Q"], 0.05, rule)
-    got = _search_bits(t, tiny["path"], tiny["Q"], 0.05,
-                       rule + ((t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST), (t.TC_OPT_PRECISION, t.TC_U8)),
-                       calls=2, graph=True)
-    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+    _fixed_on_lists(t, tiny["path"], tiny["oidx"], tiny["Q"], 0.05, 0.005, "tiny")
+    print("[tiny] fixed budget in a graph", flush=True)
+    _run_all(t, tiny["path"], tiny["oidx"], tiny["Q"], 10, 0.05, 0.005, 2, "tiny fixed graph",
+             options=((t.TC_OPT_GRAPH, 1),))
+    ref = _search_bits(t, tiny["path"], tiny["Q"], 0.05, rule + ((t.TC_OPT_COUNT_MODE, t.TC_COUNT_SPLIT),))
+    for level in (0, 1, 3):
+        got = _search_bits(t, tiny["path"], tiny["Q"], 0.05,
+                           rule + ((t.TC_OPT_COUNT_MODE, t.TC_COUNT_LIST), (t.TC_OPT_LIST_LEVEL, level),
+                                   (t.TC_OPT_PRECISION, t.TC_U8)),
+                           calls=2, graph=True)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), level
 
 
 def test_fixed_budget_rule_many_tiles(taco_mod):
@@ -699,3 +726,5 @@ def test_fixed_budget_rule_many_tiles(taco_mod):
     for beta in (0.005, 0.05):
         _run_all(taco_mod, path, oidx, Q, 10, 0.05, beta, 2, f"140k fixed b={beta}",
                  options=((taco_mod.TC_OPT_TILE_IDS, 8192),))
+    # 137 tiles of 1024 ids: the lists' tile counts are scanned 128 tiles at a time
+    _fixed_on_lists(taco_mod, path, oidx, Q, 0.05, 0.005, "140k", options=((taco_mod.TC_OPT_TILE_IDS, 1024),))
