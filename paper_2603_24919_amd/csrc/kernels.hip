@@ -1700,6 +1700,7 @@ __device__ __forceinline__ void select_query(const SelectArgs &sa, int Ns, int64
 // found.  grid nq, block SL_BLOCK; with sa.redo, the queued queries of a
 // list selection instead (grid any).
 constexpr int SL_BLOCK = 256;
+constexpr int SL_VEC = 4;  // 16-byte words per thread and round
 
 template <int BITS>
 __device__ __forceinline__ void select_level_query(const SelectArgs &sa, int Ns, int64_t n, int64_t words,
@@ -1729,32 +1730,34 @@ __device__ __forceinline__ void select_level_query(const SelectArgs &sa, int Ns,
     __syncthreads();
     const int64_t base = base_s;
     // words is a multiple of 4 (tiles hold a multiple of 1024 ids): each
-    // thread takes one 16-byte word, i.e. four 32-bit words, per round
+    // thread takes SL_VEC consecutive 16-byte words per round, so one
+    // workgroup prefix sum ranks SL_VEC * SL_BLOCK words in id order
     const uint4 *src = reinterpret_cast<const uint4 *>(sc32 + static_cast<int64_t>(q) * words);
     const int64_t words4 = words / 4;
     const uint32_t lv = static_cast<uint32_t>(L);
     int64_t taken = 0;
-    for (int64_t w0 = 0; w0 < words4 && taken < need; w0 += SL_BLOCK) {
-        const int64_t wi = w0 + tid;
-        uint32_t mb[4] = {0u, 0u, 0u, 0u};
-        if (wi < words4) {
-            const uint4 v4 = src[wi];
-            const uint32_t wv[4] = {v4.x, v4.y, v4.z, v4.w};
+    for (int64_t w0 = 0; w0 < words4 && taken < need; w0 += SL_VEC * SL_BLOCK) {
+        const int64_t wt = w0 + static_cast<int64_t>(tid) * SL_VEC;  // this thread's first word
+        uint4 v4[SL_VEC];
 #pragma unroll
-            for (int j = 0; j < 4; j++)
+        for (int u = 0; u < SL_VEC; u++) v4[u] = wt + u < words4 ? src[wt + u] : make_uint4(0u, 0u, 0u, 0u);
+        uint32_t mb[SL_VEC][4];
+        uint32_t cnt = 0u;
+#pragma unroll
+        for (int u = 0; u < SL_VEC; u++) {
+            const uint32_t wv[4] = {v4[u].x, v4[u].y, v4[u].z, v4[u].w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                mb[u][j] = 0u;
 #pragma unroll
                 for (int k = 0; k < PER_WORD; k++) {
-                    const int64_t id = (wi * 4 + j) * PER_WORD + k;
-                    if (id < n && ((wv[j] >> (BITS * k)) & MASK) == lv) mb[j] |= 1u << k;
+                    const int64_t id = ((wt + u) * 4 + j) * PER_WORD + k;
+                    if (wt + u < words4 && id < n && ((wv[j] >> (BITS * k)) & MASK) == lv) mb[u][j] |= 1u << k;
                 }
+                cnt += static_cast<uint32_t>(__popc(mb[u][j]));
+            }
         }
-        const uint32_t cnt = static_cast<uint32_t>(__popc(mb[0]) + __popc(mb[1]) + __popc(mb[2]) + __popc(mb[3]));
-        uint32_t incl = cnt;
-#pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o, WAVE);
-            if (lane >= o) incl += y;
-        }
+        const uint32_t incl = wave_incl_scan_u32(cnt, lane);
         if (lane == WAVE - 1) wtot[w] = incl;
         __syncthreads();
         uint32_t before = 0, total = 0;
@@ -1763,16 +1766,20 @@ __device__ __forceinline__ void select_level_query(const SelectArgs &sa, int Ns,
             total += wtot[i];
         }
         int64_t r = taken + before + incl - cnt;
+        if (cnt != 0u && r < need) {
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            uint32_t mbits = mb[j];
-            while (mbits) {
-                const int k = __ffs(mbits) - 1;
-                mbits &= mbits - 1u;
-                if (r < need && base + r < sa.cap)
-                    cq[base + r] = static_cast<int32_t>((wi * 4 + j) * PER_WORD + k);
-                r++;
-            }
+            for (int u = 0; u < SL_VEC; u++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    uint32_t mbits = mb[u][j];
+                    while (mbits) {
+                        const int k = __ffs(mbits) - 1;
+                        mbits &= mbits - 1u;
+                        if (r < need && base + r < sa.cap)
+                            cq[base + r] = static_cast<int32_t>(((wt + u) * 4 + j) * PER_WORD + k);
+                        r++;
+                    }
+                }
         }
         taken += total;
         __syncthreads();  // wtot is rewritten by the next round
