@@ -83,13 +83,17 @@ PLANS = {
 }
 
 # path -> (centroid-distance form, re-rank precision or None to let the
-# tuner choose an exact form, tuned/graph/one-batch)
+# tuner choose an exact form, tuned/graph/one-batch, selection rule)
 PATHS = {
-    "fp32": ("fp32", "fp32", False),
-    "fp32_tuned": ("fp32", "fp32", True),
-    "tuned": ("fp32", None, True),
-    "bf16": ("bf16", "bf16", True),
-    "fp8": ("fp8", "bf16", True),
+    "fp32": ("fp32", "fp32", False, "printed"),
+    "fp32_tuned": ("fp32", "fp32", True, "printed"),
+    "tuned": ("fp32", None, True, "printed"),
+    "bf16": ("bf16", "bf16", True, "printed"),
+    "fp8": ("fp8", "bf16", True, "printed"),
+    # the fixed budget of the floor(beta*n) highest SC-scores (SuCo's
+    # selection, contrasted with Alg 5 in Section 4.3) on the fp8 path's
+    # options; not in any plan's default paths
+    "fp8_fixed": ("fp8", "bf16", True, "fixed"),
 }
 
 
@@ -351,16 +355,20 @@ TRAFFIC_KEYS = {
 }
 
 
-def traffic_from_profiles(workload, kernel, tuned=None):
+def traffic_from_profiles(workload, kernel, tuned=None, path=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary of this workload: the record taken on the current kernel sources
-    whose launch configuration agrees with the run's (`tuned`, its tuner
-    report) in every setting the kernel depends on, else None."""
+    summary of this workload: the record taken on the current kernel sources,
+    on the same bench path (when `path` is given: its precision forms and
+    selection rule), whose launch configuration agrees with the run's
+    (`tuned`, its tuner report) in every setting the kernel depends on, else
+    None."""
     keys = TRAFFIC_KEYS.get(kernel, ("W", "mode", "qpw", "rr", "precision", "cqpw", "nt"))
     run = launch_config(tuned)
     want = {k: run.get(k) for k in keys}
     for rec in traffic_records(os.path.join(ROOT, "profiles", f"traffic_{workload}.json")):
         if rec.get("source_hash") != source_hash() or rec.get("workload") != workload:
+            continue
+        if path is not None and rec.get("path") != path:
             continue
         have = launch_config(rec.get("tuned_config"))
         if not run or {k: have.get(k) for k in keys} != want:
@@ -481,7 +489,8 @@ def configure_path(taco, torch, idx, pname, dev, nq):
     """Options of a path before tuning: its centroid-distance form, its
     re-rank precision (fixed unless the tuner chooses), and for the tuned
     paths one batch per step (scratch up to 60% of the free device memory)."""
-    cd, prec, tuned = PATHS[pname]
+    cd, prec, tuned, rule = PATHS[pname]
+    idx.set_option(taco.TC_OPT_SELECT_RULE, dict(printed=taco.TC_RULE_PRINTED, fixed=taco.TC_RULE_FIXED)[rule])
     idx.set_option(taco.TC_OPT_CDIST_PRECISION, dict(fp32=taco.TC_CDIST_FP32, bf16=taco.TC_CDIST_BF16,
                                                      fp8=taco.TC_CDIST_FP8)[cd])
     if prec is not None:
@@ -507,7 +516,7 @@ def run_point(taco, torch, idx, pname, run, stream, args, w, nq, recall_fn, alg_
     events, then for the tuned paths (already tuned: `tuned_cfg` is their
     configuration) the graph replay rate; recall from the results of the
     timed runs."""
-    cd, prec, tuned = PATHS.get(pname, ("fp32", None, True))
+    cd, prec, tuned = PATHS.get(pname, ("fp32", None, True, "printed"))[:3]
     t0 = time.time()
     point = {}
     if tuned:
@@ -559,7 +568,7 @@ def roofline_of(workload, op, path_name):
     dom = max(op["kernels"], key=lambda k_: op["kernels"][k_]["ms_total"])
     dk = op["kernels"][dom]
     achieved = dk["alg_GBps"]
-    traffic = traffic_from_profiles(workload, dom, op.get("config"))
+    traffic = traffic_from_profiles(workload, dom, op.get("config"), path_name)
     r = dict(bound="hbm", kernel=dom, achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
              frac=None if achieved is None else achieved / HBM_PEAK_GBS, traffic=traffic,
              alg_bytes_per_launch=dk["alg_bytes_per_launch"], ms_per_launch=dk["ms_per_launch"],
@@ -737,7 +746,8 @@ def main_uniform(args, taco, torch, w, plan, dev):
     if not args.skip_cpu_baseline:
         cpu = cpu_baseline_leg(path, X, Q, w, gt, plan, args)
 
-    dtype = dict(fp8="fp8+bf16", bf16="bf16", fp32="f32", fp32_tuned="f32").get(main_path, "f32")
+    dtype = dict(fp8="fp8+bf16", fp8_fixed="fp8+bf16", bf16="bf16", fp32="f32",
+                 fp32_tuned="f32").get(main_path, "f32")
     if main_path == "tuned":
         dtype = {"bf16": "bf16+f32", "u8": "u8+f32"}.get(op.get("rerank_precision"), "f32")
     line = dict(
@@ -1111,7 +1121,8 @@ def main():
     ap.add_argument("--beta", type=float, default=None, help="run only the sweep points with this beta")
     ap.add_argument("--paths", default=None,
                     help="comma list of paths (default: the workload's plan): fp32, fp32_tuned, "
-                         "tuned, bf16, fp8; batched for zipf-1m-d256")
+                         "tuned, bf16, fp8, fp8_fixed (the fixed-budget selection); batched for "
+                         "zipf-1m-d256")
     ap.add_argument("--skip-precision-report", action="store_true")
     ap.add_argument("--skip-build", action="store_true", help="omit the GPU index-build leg")
     ap.add_argument("--skip-sclinear", action="store_true", help="omit the SC-Linear leg")

@@ -126,5 +126,36 @@ def test_traffic_is_matched_to_the_launch_configuration(tmp_path, monkeypatch):
     assert bench.traffic_from_profiles("w", "count", other) == pytest.approx(10.0 * 1024 * 2 + 1024)
     assert bench.traffic_from_profiles("w", "probe", other) is None
     assert bench.traffic_from_profiles("w", "probe", run) == pytest.approx(3.0 * 1024 * 2 + 1024)
+    # a record serves only its own bench path (precision forms, selection rule)
+    assert bench.traffic_from_profiles("w", "count", run, "fp8") == pytest.approx(10.0 * 1024 * 2 + 1024)
+    assert bench.traffic_from_profiles("w", "count", run, "fp8_fixed") is None
     monkeypatch.setattr(bench, "source_hash", lambda: "other")
     assert bench.traffic_from_profiles("w", "count", run) is None
+
+
+def test_paths_set_their_selection_rule_and_forms():
+    """Each bench path sets its selection rule (fp8_fixed: the fixed budget
+    on the fp8 path's options) before tuning."""
+    import types
+    import paper_2603_24919_amd as taco
+
+    class FakeIndex:
+        def __init__(self):
+            self.opts = {}
+
+        def set_option(self, opt, val):
+            self.opts[opt] = val
+
+    fake_torch = types.SimpleNamespace(cuda=types.SimpleNamespace(mem_get_info=lambda dev: (10 << 30, 20 << 30)))
+    got = {}
+    for pname in ("fp32", "fp8", "fp8_fixed"):
+        idx = FakeIndex()
+        bench.configure_path(taco, fake_torch, idx, pname, None, 100)
+        got[pname] = idx.opts
+    assert got["fp32"][taco.TC_OPT_SELECT_RULE] == taco.TC_RULE_PRINTED
+    assert got["fp8"][taco.TC_OPT_SELECT_RULE] == taco.TC_RULE_PRINTED
+    assert got["fp8_fixed"][taco.TC_OPT_SELECT_RULE] == taco.TC_RULE_FIXED
+    same = {k: v for k, v in got["fp8"].items() if k != taco.TC_OPT_SELECT_RULE}
+    assert same == {k: v for k, v in got["fp8_fixed"].items() if k != taco.TC_OPT_SELECT_RULE}
+    assert got["fp8"][taco.TC_OPT_CDIST_PRECISION] == taco.TC_CDIST_FP8
+    assert got["fp8"][taco.TC_OPT_MAX_BATCH] == 100 and taco.TC_OPT_MAX_BATCH not in got["fp32"]
